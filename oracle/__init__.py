@@ -1,0 +1,354 @@
+"""FP64 CPU oracle of the LBM-based discrete particle step (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``.  The product library under
+``paper_1303_2653_amd/`` never imports, links or calls anything here, and the
+two share no code.
+
+The arithmetic lives in ``lbdps_oracle.c`` (plain C99, FP64, contraction off);
+this module only builds it, loads it and marshals numpy arrays.  Section,
+equation and reading references are in the C source next to each function.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbdps_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+PERIODIC, WALL, INLET, OUTLET = 0, 1, 2, 3
+BC_NAMES = {"periodic": PERIODIC, "wall": WALL, "inlet": INLET, "outlet": OUTLET}
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (FP64, -ffp-contract=off)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+               "-o", LIB + ".tmp", SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 4),
+        ("tau", ctypes.c_double),
+        ("rho_g", ctypes.c_double), ("rho_s", ctypes.c_double), ("d", ctypes.c_double),
+        ("e_pp", ctypes.c_double), ("e_pw", ctypes.c_double),
+        ("g", ctypes.c_double * 2), ("G", ctypes.c_double * 2),
+        ("drag_ratio_mode", ctypes.c_int32), ("u_gas_porosity", ctypes.c_int32),
+        ("omega_mode", ctypes.c_int32), ("pressure_sign", ctypes.c_int32),
+        ("omega_dense", ctypes.c_double),
+        ("cs_smag", ctypes.c_double),
+    ]
+
+
+class OrcOut(ctypes.Structure):
+    _fields_ = [
+        ("ncell", ctypes.c_void_p), ("vs", ctypes.c_void_p), ("rho", ctypes.c_void_p),
+        ("ugas", ctypes.c_void_p), ("fpg", ctypes.c_void_p), ("beta", ctypes.c_void_p),
+        ("fd", ctypes.c_void_p), ("pairs", ctypes.c_void_p),
+        ("pair_cap", ctypes.c_int64), ("npairs", ctypes.c_int64),
+        ("ncollisions", ctypes.c_int64), ("nwall", ctypes.c_int64),
+        ("nzero_den", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.POINTER(OrcParams)
+        vp = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.orc_feq.restype = ctypes.c_double
+        L.orc_feq.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_gamma.restype = ctypes.c_double
+        L.orc_gamma.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_omega_emms.restype = ctypes.c_double
+        L.orc_omega_emms.argtypes = [ctypes.c_double]
+        L.orc_cd0.restype = ctypes.c_double
+        L.orc_cd0.argtypes = [ctypes.c_double]
+        L.orc_beta.restype = ctypes.c_double
+        L.orc_beta.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_cell_props.argtypes = [P, i64, vp]
+        L.orc_collide_node.argtypes = [P, vp, i64, vp, vp, vp]
+        L.orc_stream.argtypes = [P, vp, vp, vp]
+        L.orc_stencil.argtypes = [P, ctypes.c_double, ctypes.c_double, vp, vp]
+        L.orc_interp.restype = ctypes.c_double
+        L.orc_interp.argtypes = [P, vp, ctypes.c_double, ctypes.c_double]
+        L.orc_grad_p.argtypes = [P, vp, vp]
+        L.orc_integrate.argtypes = [P, i64, vp, vp, vp, vp]
+        L.orc_contacts_brute.restype = ctypes.c_int
+        L.orc_contacts_brute.argtypes = [P, i64, vp, vp, i64, ctypes.POINTER(i64)]
+        L.orc_contacts_cells.restype = ctypes.c_int
+        L.orc_contacts_cells.argtypes = [P, i64, vp, vp, i64, ctypes.POINTER(i64)]
+        L.orc_contacts_f32.restype = ctypes.c_int
+        L.orc_contacts_f32.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_float, i64, vp, vp, ctypes.c_int32, vp, i64,
+                                       ctypes.POINTER(i64)]
+        L.orc_resolve.argtypes = [P, i64, vp, vp, vp, i64, ctypes.POINTER(i64)]
+        L.orc_walls.argtypes = [P, i64, vp, vp, ctypes.POINTER(i64)]
+        L.orc_step.restype = ctypes.c_int
+        L.orc_step.argtypes = [P, vp, vp, i64, vp, vp, ctypes.POINTER(OrcOut)]
+        L.orc_conservation.argtypes = [P, vp, i64, vp, vp]
+        L.orc_lattice.argtypes = [vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _bc_code(v):
+    return BC_NAMES[v] if isinstance(v, str) else int(v)
+
+
+def make_params(cfg: dict) -> OrcParams:
+    """Build the oracle's parameter struct from a workload dict (see ``synth``)."""
+    p = OrcParams()
+    p.nx, p.ny = int(cfg["nx"]), int(cfg["ny"])
+    for k, v in enumerate(cfg["bc"]):
+        p.bc[k] = _bc_code(v)
+    p.tau = float(cfg.get("tau", 0.6))
+    p.rho_g = float(cfg.get("rho_g", 1.0))
+    p.rho_s = float(cfg.get("rho_s", 788.5))
+    p.d = float(cfg.get("d", 0.5))
+    p.e_pp = float(cfg.get("e_pp", 0.9))
+    p.e_pw = float(cfg.get("e_pw", cfg.get("e_pp", 0.9)))
+    g = cfg.get("g", (0.0, 0.0))
+    G = cfg.get("G", (0.0, 0.0))
+    p.g[0], p.g[1] = float(g[0]), float(g[1])
+    p.G[0], p.G[1] = float(G[0]), float(G[1])
+    p.drag_ratio_mode = int(cfg.get("drag_ratio_mode", 0))
+    p.u_gas_porosity = int(cfg.get("u_gas_porosity", 0))
+    p.omega_mode = int(cfg.get("omega_mode", 0))
+    p.pressure_sign = int(cfg.get("pressure_sign", -1))
+    p.omega_dense = float(cfg.get("omega_dense", 1.0))
+    p.cs_smag = float(cfg.get("cs_smag", 0.0))
+    return p
+
+
+# ---------------------------------------------------------------- small pieces
+def lattice():
+    c = np.zeros((9, 2), np.int32)
+    w = np.zeros(9)
+    opp = np.zeros(9, np.int32)
+    lib().orc_lattice(_ptr(c), _ptr(w), _ptr(opp))
+    return c, w, opp
+
+
+def feq(i, rho, ux, uy):
+    return lib().orc_feq(int(i), float(rho), float(ux), float(uy))
+
+
+def gamma(eps_s, tau):
+    return lib().orc_gamma(float(eps_s), float(tau))
+
+
+def omega_emms(eps_g):
+    return lib().orc_omega_emms(float(eps_g))
+
+
+def cd0(re):
+    return lib().orc_cd0(float(re))
+
+
+def beta(p: OrcParams, eps_g, om, slip):
+    return lib().orc_beta(ctypes.byref(p), float(eps_g), float(om), float(slip))
+
+
+def cell_props(p: OrcParams, n: int):
+    out = np.zeros(6)
+    lib().orc_cell_props(ctypes.byref(p), int(n), _ptr(out))
+    return dict(eps_s2=out[0], eps_2=out[1], eps_s3=out[2], eps_g=out[3], gamma=out[4], omega=out[5])
+
+
+def collide_node(p: OrcParams, f, n, vs):
+    f = np.ascontiguousarray(f, np.float64)
+    vs = np.ascontiguousarray(vs, np.float64)
+    fs = np.zeros(9)
+    o = np.zeros(8)
+    lib().orc_collide_node(ctypes.byref(p), _ptr(f), int(n), _ptr(vs), _ptr(fs), _ptr(o))
+    return fs, dict(rho=o[0], ugas=o[1:3].copy(), fpg=o[3:5].copy(), beta=o[5], usup=o[6:8].copy())
+
+
+def stream(p: OrcParams, fstar, inlet_uy=None):
+    fstar = np.ascontiguousarray(fstar, np.float64)
+    out = np.zeros_like(fstar)
+    iu = None if inlet_uy is None else np.ascontiguousarray(inlet_uy, np.float64)
+    lib().orc_stream(ctypes.byref(p), _ptr(iu), _ptr(fstar), _ptr(out))
+    return out
+
+
+def stencil(p: OrcParams, px, py):
+    idx = np.zeros(4, np.int64)
+    wt = np.zeros(4)
+    lib().orc_stencil(ctypes.byref(p), float(px), float(py), _ptr(idx), _ptr(wt))
+    return idx, wt
+
+
+def interp(p: OrcParams, q, px, py):
+    q = np.ascontiguousarray(q, np.float64).reshape(-1)
+    return lib().orc_interp(ctypes.byref(p), _ptr(q), float(px), float(py))
+
+
+def grad_p(p: OrcParams, pres):
+    pres = np.ascontiguousarray(pres, np.float64).reshape(-1)
+    g = np.zeros((pres.size, 2))
+    lib().orc_grad_p(ctypes.byref(p), _ptr(pres), _ptr(g))
+    return g
+
+
+def integrate(p: OrcParams, pos, vel, fd, gpk):
+    pos = np.ascontiguousarray(pos, np.float64).copy()
+    vel = np.ascontiguousarray(vel, np.float64).copy()
+    fd = np.ascontiguousarray(fd, np.float64)
+    gpk = np.ascontiguousarray(gpk, np.float64)
+    lib().orc_integrate(ctypes.byref(p), len(pos), _ptr(pos), _ptr(vel), _ptr(fd), _ptr(gpk))
+    return pos, vel
+
+
+def contacts(p: OrcParams, pos, brute=False, cap=None):
+    pos = np.ascontiguousarray(pos, np.float64)
+    n = len(pos)
+    cap = cap if cap is not None else max(16, 32 * n)
+    pairs = np.zeros((cap, 2), np.int32)
+    m = ctypes.c_int64(0)
+    fn = lib().orc_contacts_brute if brute else lib().orc_contacts_cells
+    rc = fn(ctypes.byref(p), n, _ptr(pos), _ptr(pairs), cap, ctypes.byref(m))
+    if rc != 0:
+        raise RuntimeError(f"oracle contacts failed rc={rc}")
+    return pairs[: m.value].copy()
+
+
+def contacts_f32(nx, ny, per_x, per_y, d, cell, off, brute=False, cap=None):
+    cell = np.ascontiguousarray(cell, np.int32)
+    off = np.ascontiguousarray(off, np.float32)
+    n = len(cell)
+    cap = cap if cap is not None else max(16, 32 * n)
+    pairs = np.zeros((cap, 2), np.int32)
+    m = ctypes.c_int64(0)
+    rc = lib().orc_contacts_f32(int(nx), int(ny), int(per_x), int(per_y), float(np.float32(d)), n,
+                                _ptr(cell), _ptr(off), int(bool(brute)), _ptr(pairs), cap,
+                                ctypes.byref(m))
+    if rc != 0:
+        raise RuntimeError(f"oracle contacts_f32 failed rc={rc}")
+    return pairs[: m.value].copy()
+
+
+def resolve(p: OrcParams, pos, vel, pairs):
+    pos = np.ascontiguousarray(pos, np.float64)
+    vel = np.ascontiguousarray(vel, np.float64).copy()
+    pairs = np.ascontiguousarray(pairs, np.int32)
+    nc = ctypes.c_int64(0)
+    lib().orc_resolve(ctypes.byref(p), len(pos), _ptr(pos), _ptr(vel), _ptr(pairs), len(pairs),
+                      ctypes.byref(nc))
+    return vel, nc.value
+
+
+def walls(p: OrcParams, pos, vel):
+    pos = np.ascontiguousarray(pos, np.float64)
+    vel = np.ascontiguousarray(vel, np.float64).copy()
+    nw = ctypes.c_int64(0)
+    lib().orc_walls(ctypes.byref(p), len(pos), _ptr(pos), _ptr(vel), ctypes.byref(nw))
+    return vel, nw.value
+
+
+def conservation(p: OrcParams, f, vel):
+    f = np.ascontiguousarray(f, np.float64)
+    vel = np.ascontiguousarray(vel, np.float64)
+    out = np.zeros(5)
+    lib().orc_conservation(ctypes.byref(p), _ptr(f), len(vel), _ptr(vel), _ptr(out))
+    return out
+
+
+def equilibrium_state(nx, ny, rho=1.0, ux=0.0, uy=0.0):
+    """f = f^eq(rho, u) on every node, [9][ny][nx] (R33 initial state)."""
+    f = np.empty((9, ny, nx))
+    for i in range(9):
+        f[i] = feq(i, rho, ux, uy)
+    return f
+
+
+# ---------------------------------------------------------------- the step
+@dataclass
+class StepOut:
+    ncell: np.ndarray
+    vs: np.ndarray
+    rho: np.ndarray
+    ugas: np.ndarray
+    fpg: np.ndarray
+    beta: np.ndarray
+    fd: np.ndarray
+    pairs: np.ndarray
+    ncollisions: int
+    nwall: int
+    nzero_den: int
+
+
+class Sim:
+    """Holds an oracle state (f, pos, vel) and advances it with orc_step."""
+
+    def __init__(self, cfg: dict, f=None, pos=None, vel=None):
+        self.cfg = cfg
+        self.p = make_params(cfg)
+        nx, ny = self.p.nx, self.p.ny
+        self.inlet_uy = None
+        if cfg.get("inlet_uy") is not None:
+            self.inlet_uy = np.ascontiguousarray(cfg["inlet_uy"], np.float64)
+        self.f = equilibrium_state(nx, ny) if f is None else np.array(f, np.float64, copy=True)
+        pos = cfg["pos"] if pos is None else pos
+        vel = cfg["vel"] if vel is None else vel
+        self.pos = np.array(pos, np.float64, copy=True).reshape(-1, 2)
+        self.vel = np.array(vel, np.float64, copy=True).reshape(-1, 2)
+        self.nstep = 0
+
+    def step(self, record=False, pair_cap=None):
+        nx, ny = self.p.nx, self.p.ny
+        C = nx * ny
+        n = len(self.pos)
+        o = OrcOut()
+        bufs = {}
+        if record:
+            bufs = dict(ncell=np.zeros(C, np.int32), vs=np.zeros((C, 2)), rho=np.zeros(C),
+                        ugas=np.zeros((C, 2)), fpg=np.zeros((C, 2)), beta=np.zeros(C),
+                        fd=np.zeros((max(n, 1), 2)))
+            cap = pair_cap if pair_cap is not None else max(16, 32 * n)
+            bufs["pairs"] = np.zeros((cap, 2), np.int32)
+            for k, v in bufs.items():
+                setattr(o, k, v.ctypes.data)
+            o.pair_cap = cap
+        rc = lib().orc_step(ctypes.byref(self.p), _ptr(self.inlet_uy), _ptr(self.f), n,
+                            _ptr(self.pos), _ptr(self.vel), ctypes.byref(o))
+        if rc != 0:
+            raise RuntimeError(f"oracle step failed rc={rc}")
+        self.nstep += 1
+        if not record:
+            return None
+        return StepOut(ncell=bufs["ncell"].reshape(ny, nx), vs=bufs["vs"].reshape(ny, nx, 2),
+                       rho=bufs["rho"].reshape(ny, nx), ugas=bufs["ugas"].reshape(ny, nx, 2),
+                       fpg=bufs["fpg"].reshape(ny, nx, 2), beta=bufs["beta"].reshape(ny, nx),
+                       fd=bufs["fd"][:n].copy(), pairs=bufs["pairs"][: o.npairs].copy(),
+                       ncollisions=o.ncollisions, nwall=o.nwall, nzero_den=o.nzero_den)
+
+    def run(self, nsteps):
+        for _ in range(nsteps):
+            self.step()
+
+    def conservation(self):
+        return conservation(self.p, self.f, self.vel)

@@ -1,0 +1,185 @@
+"""Seeded synthetic inputs for the LBM discrete-particle workloads.
+
+This module holds random-number generation and workload recipes only (lattice
+sizes, boundary faces, parameters and initial particle positions).  It carries
+none of the simulation method's arithmetic.  Both the FP64 oracle runs and the
+GPU runs take their inputs from here, so they start from the same state.
+
+Random numbers: splitmix64 (Steele, Lea & Flood, OOPSLA 2014), output k of a
+stream with seed s is mix(s + (k+1) * 0x9E3779B97F4A7C15); a uniform double is
+(x >> 11) * 2^-53.  Draws are consumed in particle-index order, x then y.
+
+The workloads borrow the shapes of the paper's two experiments (bubble
+injection, Table 1; riser, Table 2) at the sizes of the benchmark plan.  No
+dataset is involved.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, count: int, offset: int = 0) -> np.ndarray:
+    """Outputs offset .. offset+count-1 of the splitmix64 stream for ``seed``."""
+    k = np.arange(offset + 1, offset + count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + k * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform(seed: int, count: int, offset: int = 0) -> np.ndarray:
+    """Uniform doubles in [0, 1) from splitmix64."""
+    return (splitmix64(seed, count, offset) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+# Physical defaults shared by every workload (lattice units): tau = 0.6,
+# gas density 1, solid density 788.5 (Tables 1-2, dimensionless column),
+# restitution 0.9 (Tables 1-2), particle diameter 0.5 cells.
+DEFAULTS = dict(tau=0.6, rho_g=1.0, rho_s=788.5, d=0.5, e_pp=0.9, e_pw=0.9,
+                drag_ratio_mode=0, u_gas_porosity=0, omega_mode=0, pressure_sign=-1,
+                omega_dense=1.0, cs_smag=0.0, G=(0.0, 0.0))
+
+DISC = math.pi * 0.25 / 4.0  # area of a d = 0.5 disc, used only to size seeding bands
+
+
+def _cfg(name, nx, ny, bc, pos, steps, **kw):
+    c = dict(DEFAULTS)
+    c.update(kw)
+    c.update(name=name, nx=nx, ny=ny, bc=list(bc), steps=steps,
+             pos=np.ascontiguousarray(pos, np.float64),
+             vel=np.ascontiguousarray(kw.get("vel", np.zeros_like(pos)), np.float64))
+    return c
+
+
+def cell_order(pos: np.ndarray, nx: int) -> np.ndarray:
+    """Permutation that numbers particles in row-major cell order of their
+    position (ties by draw order): the numbering a spatially sorted injector
+    would give."""
+    key = np.floor(pos[:, 1]).astype(np.int64) * nx + np.floor(pos[:, 0]).astype(np.int64)
+    return np.argsort(key, kind="stable")
+
+
+def bubble_small(seed: int = 1) -> dict:
+    """64x256 bed, x periodic, inflow u = 0.01 at the bottom, zero-gradient
+    outlet at the top, 2000 spheres (d = 0.5) seeded uniformly in a bottom band
+    whose 2-D solid area fraction is 0.35 (band height N pi d^2/(4 0.35 nx) =
+    17.53 rows), zero velocity, gravity 1e-5, 100 steps.  FP64."""
+    nx, ny, n, phi, r = 64, 256, 2000, 0.35, 0.25
+    band = n * DISC / (phi * nx)
+    u = uniform(seed, 2 * n).reshape(n, 2)
+    pos = np.empty((n, 2))
+    pos[:, 0] = nx * u[:, 0]
+    pos[:, 1] = r + (band - 2 * r) * u[:, 1]
+    return _cfg("bubble-64x256-2k-fp64", nx, ny, ["periodic", "periodic", "inlet", "outlet"], pos, 100,
+                inlet_uy=np.full(nx, 0.01), g=(0.0, -1e-5), precision="fp64")
+
+
+def bubble(seed: int = 2, v_mf: float = 0.005) -> dict:
+    """Bubble-injection shape: 256x1024 bed, 200 000 spheres on a jittered
+    square lattice (365 columns, 548 rows, the last row holding 345) filling a
+    bottom band of 2-D solid fraction 0.4 (383.5 rows), jitter uniform +-0.09
+    per axis so no two spheres touch at t = 0.  Inflow v_mf = 0.005 everywhere
+    except 3 v_mf on the 8 central columns x in [124, 132).  Gravity 4.35e-7,
+    which balances the bed's weight against the drag at v_mf (cell force balance
+    at solid fraction 0.4).  2000 steps, FP32."""
+    nx, ny, n, phi = 256, 1024, 200_000, 0.4
+    band = n * DISC / (phi * nx)
+    ncol = 365
+    nrow = -(-n // ncol)
+    dx, dy = nx / ncol, band / nrow
+    k = np.arange(n)
+    col, row = k % ncol, k // ncol
+    jit = (uniform(seed, 2 * n).reshape(n, 2) * 2.0 - 1.0) * 0.09
+    pos = np.empty((n, 2))
+    pos[:, 0] = (col + 0.5) * dx + jit[:, 0]
+    pos[:, 1] = (row + 0.5) * dy + jit[:, 1]
+    inlet = np.full(nx, v_mf)
+    inlet[124:132] = 3.0 * v_mf
+    return _cfg("bubble-256x1024-200k-fp32", nx, ny, ["periodic", "periodic", "inlet", "outlet"], pos, 2000,
+                inlet_uy=inlet, g=(0.0, -4.35e-7), precision="fp32")
+
+
+# Riser shape: a body force on the gas balances the particles' weight.  With
+# m = 788.5 pi 0.5^3/6 = 51.607, g_eff = (1 - 1/788.5) 2.82e-7 and 0.95367
+# particles per cell, N m g_eff / C = 1.38614e-5 per cell.
+RISER_G = (0.0, -2.82e-7)
+RISER_BODY = (0.0, 1.38614e-5)
+
+
+def riser(nx: int = 512, ny: int = 4096, n: int = 2_000_000, seed: int = 3, sort_ids: bool = True,
+          precision: str = "fp32") -> dict:
+    """Riser shape: y periodic, x walls, n spheres uniform in
+    x in [r, nx - r), y in [0, ny), zero velocity, gas driven upward by a body
+    force, particle gravity 2.82e-7.  Default 512x4096 with 2 000 000 spheres
+    (0.954 per cell).  sort_ids numbers particles in cell order."""
+    r = 0.25
+    u = uniform(seed, 2 * n).reshape(n, 2)
+    pos = np.empty((n, 2))
+    pos[:, 0] = r + (nx - 2 * r) * u[:, 0]
+    pos[:, 1] = ny * u[:, 1]
+    if sort_ids:
+        pos = pos[cell_order(pos, nx)]
+    return _cfg(f"riser-{nx}x{ny}-{n}-{precision}", nx, ny, ["wall", "wall", "periodic", "periodic"], pos,
+                5000, inlet_uy=None, g=RISER_G, G=RISER_BODY, precision=precision)
+
+
+def riser_crop(seed: int = 3, precision: str = "fp32") -> dict:
+    """64x512 bed at the riser's density: 31 250 spheres."""
+    return riser(64, 512, 31_250, seed, True, precision)
+
+
+def riser_large(seed: int = 3) -> dict:
+    """2048x8192 bed (16.8 M cells) at the riser's density: 16 000 000 spheres."""
+    return riser(2048, 8192, 16_000_000, seed, True, "fp32")
+
+
+def beds(count: int = 64, seed0: int = 1000) -> list:
+    """Batch of uneven beds: bed b draws s, phi from seed seed0 + b; nx =
+    round(64 4^s), ny = 4 nx, 2-D solid fraction phi = 0.05 + 0.35 u, particle
+    count clip(round(phi nx ny / 2 / (pi d^2/4)), 2000, 200000) seeded
+    uniformly in a bottom band of that fraction; boundaries as bubble_small."""
+    out = []
+    for b in range(count):
+        s, uphi = uniform(seed0 + b, 2)
+        nx = int(round(64 * 4.0 ** s))
+        ny = 4 * nx
+        phi = 0.05 + 0.35 * uphi
+        n = int(np.clip(round(phi * nx * ny / 2 / DISC), 2000, 200_000))
+        band = min(n * DISC / (phi * nx), ny - 1.0)
+        u = uniform(seed0 + b, 2 * n, offset=2).reshape(n, 2)
+        pos = np.empty((n, 2))
+        pos[:, 0] = nx * u[:, 0]
+        pos[:, 1] = 0.25 + (band - 0.5) * u[:, 1]
+        pos = pos[cell_order(pos, nx)]
+        out.append(_cfg(f"bed{b}-{nx}x{ny}-{n}", nx, ny, ["periodic", "periodic", "inlet", "outlet"], pos, 200,
+                        inlet_uy=np.full(nx, 0.01), g=(0.0, -1e-5), precision="fp16"))
+    return out
+
+
+def tiny(nx: int = 16, ny: int = 24, n: int = 60, seed: int = 7, bc=("periodic", "periodic", "inlet", "outlet"),
+         band: float | None = None, vel_scale: float = 0.0, **kw) -> dict:
+    """Small random bed for unit and parity tests: n spheres uniform in
+    [0, nx) x [r, band - r) (band defaults to ny), velocities uniform in
+    +-vel_scale."""
+    r = 0.5 * kw.get("d", DEFAULTS["d"])
+    band = ny if band is None else band
+    u = uniform(seed, 4 * n).reshape(n, 4)
+    pos = np.empty((n, 2))
+    xlo = 0.0 if bc[0] == "periodic" else r
+    xhi = nx if bc[0] == "periodic" else nx - r
+    pos[:, 0] = xlo + (xhi - xlo) * u[:, 0]
+    ylo = 0.0 if bc[2] == "periodic" else r
+    yhi = band if bc[2] == "periodic" else band - r
+    pos[:, 1] = ylo + (yhi - ylo) * u[:, 1]
+    vel = (u[:, 2:4] * 2.0 - 1.0) * vel_scale
+    inlet = kw.pop("inlet_uy", np.full(nx, 0.01) if "inlet" in bc else None)
+    kw.setdefault("g", (0.0, -1e-5))
+    return _cfg(f"tiny-{nx}x{ny}-{n}", nx, ny, list(bc), pos, 10, vel=vel, inlet_uy=inlet, **kw)
