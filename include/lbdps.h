@@ -1,0 +1,199 @@
+/*
+ * lbdps.h - C ABI of the MI355X (gfx950) library for the lattice-Boltzmann-based
+ * discrete particle simulation of gas-solid fluidization (Wang, Zhang, Wang, Ge
+ * & Li, Chem. Eng. Sci.).
+ *
+ * One library call advances the coupled method of Sec. 2.4 (the seven-step
+ * procedure): particle statistics per cell (Eqs. 8, 10, 11), the modified
+ * lattice Boltzmann collision and streaming (Eqs. 7, 9, 23-25), EMMS drag with
+ * bilinear grid-to-particle interpolation and the Newton-third-law correction
+ * (Eqs. 19-22, 26-28), integration of the particle equation of motion (Eq. 16)
+ * and the time-driven hard-sphere collisions (Eqs. 17-18).
+ *
+ * Conventions
+ *  - Lattice units: cell size h = 1, time step dt = 1 (Sec. 2.1).
+ *  - Every function returns lbdps_status (0 = OK, < 0 = error).  Nothing throws
+ *    or aborts across the ABI.  lbdps_last_error() returns a thread-local
+ *    message for the last failure on the calling thread.
+ *  - Pointers named d_* are device pointers (HIP device memory of the GPU the
+ *    context was created on); h_* are host pointers.  The library never
+ *    allocates device memory: the caller passes one workspace buffer of
+ *    lbdps_workspace_bytes() bytes that must outlive the context.  Host-side
+ *    context memory is allocated by lbdps_create and freed by lbdps_destroy.
+ *    No pointer passed in is kept after a call returns, except the workspace.
+ *  - Boundary layouts are canonical FP64 whatever the internal precision:
+ *    populations f as [9][ny][nx] (direction-major, D2Q9 numbering below),
+ *    node fields as [ny][nx] (vectors [ny][nx][2]), particles as [n][2] in
+ *    particle-index order.  Internal layouts are private.
+ *  - D2Q9 numbering: 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1)
+ *    6:(-1,1) 7:(-1,-1) 8:(1,-1); weights 4/9, 1/9 (1-4), 1/36 (5-8).
+ *  - Work is enqueued on the stream given to lbdps_create (a hipStream_t passed
+ *    as void*).  lbdps_step returns without waiting.  The lbdps_get_*,
+ *    lbdps_conservation and lbdps_counters calls enqueue their copies on the
+ *    same stream and wait for it; device-side errors latched since the last
+ *    such call are returned by them.
+ *  - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef LBDPS_H
+#define LBDPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBDPS_OK = 0,
+  LBDPS_E_INVALID = -1,     /* a parameter or input value is out of range      */
+  LBDPS_E_SHAPE = -2,       /* a size does not match the context or workspace   */
+  LBDPS_E_DEVICE = -3,      /* a HIP runtime call failed                        */
+  LBDPS_E_UNSUPPORTED = -4, /* valid for the method, not supported by this build */
+  LBDPS_E_NONFINITE = -5,   /* a NaN or infinity appeared in the state           */
+  LBDPS_E_CAPACITY = -6,    /* a particle has more contacts than LBDPS_MAX_CONTACTS */
+  LBDPS_E_STALL = -7        /* collision resolution exceeded its bounded wait    */
+} lbdps_status;
+
+/* Storage and arithmetic precision of a context. */
+typedef enum {
+  LBDPS_FP64 = 0,            /* FP64 storage and arithmetic                      */
+  LBDPS_FP32 = 1,            /* FP32 storage and arithmetic                      */
+  LBDPS_FP32_STORE_FP16 = 2, /* populations stored as FP16 deviations f_i - w_i, FP32 arithmetic */
+  LBDPS_FP32_STORE_BF16 = 3  /* populations stored as BF16 deviations f_i - w_i, FP32 arithmetic */
+} lbdps_precision;
+
+/* Boundary type of a lattice face.  x faces take PERIODIC or WALL; y faces take
+ * any.  PERIODIC must be set on both faces of an axis.  Particles see a wall on
+ * every non-periodic face. */
+typedef enum {
+  LBDPS_BC_PERIODIC = 0,
+  LBDPS_BC_WALL = 1,  /* halfway bounce-back for the gas; particle walls           */
+  LBDPS_BC_INLET = 2, /* incoming populations set to f^eq(1, (0, u_in(x)))         */
+  LBDPS_BC_OUTLET = 3 /* incoming populations copied from the boundary row         */
+} lbdps_bc;
+
+/* Contacts recorded per particle; a particle with more is an LBDPS_E_CAPACITY error. */
+#define LBDPS_MAX_CONTACTS 32
+
+typedef struct {
+  int32_t nx, ny;            /* lattice size, nx, ny >= 3, nx * ny < 2^31            */
+  int32_t bc[4];             /* lbdps_bc of faces x-, x+, y-, y+                       */
+  double tau;                /* relaxation time, tau = 3 nu + 1/2 (Eq. 3), > 0.5      */
+  double rho_g;              /* gas density in the drag laws (Eqs. 19, 22), > 0       */
+  double rho_s;              /* solid density, > 0; particle mass rho_s pi d^3/6      */
+  double d_p;                /* particle diameter in cells, 0 < d_p < 1               */
+  double e_pp;               /* particle-particle restitution e of Eqs. 17-18, [0, 1]  */
+  double e_pw;               /* particle-wall restitution, [0, 1]                      */
+  double g[2];               /* gravity on particles; the (1 - rho_g/rho_s) factor of
+                                Sec. 3 is applied by the library                       */
+  double body_force[2];      /* force per cell on the gas (drives periodic beds)      */
+  int32_t drag_ratio_mode;   /* Eq. 28: 0 signed ratio F_pg/F_pre (default), 1 ratio of
+                                absolute values as printed                              */
+  int32_t u_gas_porosity;    /* superficial -> actual gas velocity (after Eq. 24):
+                                0 divide by eps_2d (default), 1 by the 3-D voidage, 2 none */
+  int32_t omega_mode;        /* 0 EMMS correction of Eq. 20 (default), 1 omega = 1 (Eq. 6) */
+  int32_t pressure_force_sign; /* sign s of the s V_p grad p term of Eq. 16: -1 (default), 0, +1 */
+  double omega_dense;        /* omega used where eps_g <= 0.74 (Eq. 20 undefined), default 1 */
+  double cs_smag;            /* Smagorinsky constant of Eqs. 12-15; 0 = plain BGK (only 0 supported) */
+  int32_t precision;         /* lbdps_precision                                        */
+  int32_t diagnostics;       /* 1: each step also records per-cell n, v_s and per-particle
+                                drag for lbdps_get_fields / lbdps_get_particles          */
+} lbdps_params;
+
+typedef struct lbdps_ctx lbdps_ctx;
+
+/* Check parameters without touching any device.  max_particles >= 0. */
+lbdps_status lbdps_validate_params(const lbdps_params *p, int64_t max_particles);
+
+/* Workspace size for a context holding up to max_particles particles.  Device-free. */
+lbdps_status lbdps_workspace_bytes(const lbdps_params *p, int64_t max_particles, size_t *bytes);
+
+/*
+ * Create a context on the current HIP device.  d_workspace: device buffer of at
+ * least lbdps_workspace_bytes() bytes, 256-byte aligned.  h_inlet_uy: host array
+ * of nx inlet velocities (y component) used by INLET faces, or NULL for zero.
+ * stream: hipStream_t for all work of this context (NULL = default stream).
+ * The state starts as f = f^eq(1, 0) and no particles.
+ */
+lbdps_status lbdps_create(const lbdps_params *p, int64_t max_particles, void *d_workspace, size_t bytes,
+                          const double *h_inlet_uy, void *stream, lbdps_ctx **out);
+
+/*
+ * Replace the state.  d_f: device [9][ny][nx] FP64 pre-collision populations,
+ * or NULL for f^eq(1, 0) everywhere.  d_pos, d_vel: device [n][2] FP64 particle
+ * centres in [0, nx) x [0, ny) and velocities, particle index order (the index
+ * orders the collisions, Eqs. 17-18).  n <= max_particles.  Positions outside
+ * the domain are reported as LBDPS_E_INVALID by the next synchronising call.
+ * In reduced precisions values are rounded to the internal representation.
+ */
+lbdps_status lbdps_set_state(lbdps_ctx *ctx, const double *d_f, const double *d_pos, const double *d_vel,
+                             int64_t n);
+
+/* Enqueue nsteps coupled time steps (Sec. 2.4, steps 2-6 each).  Asynchronous. */
+lbdps_status lbdps_step(lbdps_ctx *ctx, int32_t nsteps);
+
+/*
+ * Enqueue the hard-sphere stage alone on the current state: contact detection
+ * at the present positions and binary plus wall collisions (Eqs. 17-18).  This is
+ * the last stage of every step; exposed for stage-by-stage checks.  Asynchronous.
+ */
+lbdps_status lbdps_collide_particles(lbdps_ctx *ctx);
+
+/*
+ * Node fields of the most recent step, device FP64 [ny][nx] (vectors [ny][nx][2]):
+ * density rho (Eq. 5), actual gas velocity (Eq. 24 and the note after it),
+ * force on the gas F_p->g (Eq. 25), drag coefficient beta (Eq. 19).  With
+ * diagnostics on, also the particle count n_tot (int32) and mean solid
+ * velocity v_s (Eq. 8) per cell used by that step.  Any pointer may be NULL.
+ * Synchronises the stream.
+ */
+lbdps_status lbdps_get_fields(lbdps_ctx *ctx, double *d_rho, double *d_ugas, double *d_fpg, double *d_beta,
+                              int32_t *d_ncell, double *d_vs);
+
+/*
+ * Particle state in index order, device FP64 [n][2]: positions, velocities, and
+ * (diagnostics on) the corrected drag of the most recent step (Eq. 28); d_cell
+ * receives the int32 [n][2] cell of each particle.  Any pointer may be NULL.
+ * Synchronises the stream.
+ */
+lbdps_status lbdps_get_particles(lbdps_ctx *ctx, double *d_pos, double *d_vel, double *d_fd, int32_t *d_cell);
+
+/*
+ * Contact pairs (i, j), i < j by particle index, of the most recent hard-sphere
+ * stage, in lexicographic order, device int32 [cap][2].  *n_out receives the
+ * number of pairs (also when it exceeds cap; then only cap are written).
+ * Synchronises the stream.
+ */
+lbdps_status lbdps_get_pairs(lbdps_ctx *ctx, int32_t *d_pairs, int64_t cap, int64_t *n_out);
+
+/* Checkpoint: FP64 populations [9][ny][nx], positions and velocities [n][2]
+ * (index order) and the step counter.  Any pointer may be NULL.  Synchronises. */
+lbdps_status lbdps_get_state(lbdps_ctx *ctx, double *d_f, double *d_pos, double *d_vel, int64_t *h_step);
+
+/*
+ * FP64 conservation sums over the current state, fixed-order reductions:
+ * h_out[0] = sum of f (mass), h_out[1..2] = sum c_i f_i (gas momentum),
+ * h_out[3..4] = sum m v (particle momentum), h_out[5] = 1 if any value is not
+ * finite, else 0.  Returns LBDPS_E_NONFINITE in that case.  Synchronises.
+ */
+lbdps_status lbdps_conservation(lbdps_ctx *ctx, double h_out[6]);
+
+/*
+ * Event counts of the most recent hard-sphere stage: h_out[0] contact pairs,
+ * h_out[1] pairs that collided, h_out[2] particle-wall collisions, h_out[3]
+ * (diagnostics on) cell components with a zero Eq. 28 denominator in the most
+ * recent drag.  Synchronises.
+ */
+lbdps_status lbdps_counters(lbdps_ctx *ctx, int64_t h_out[4]);
+
+/* Release the host context (the workspace stays the caller's). */
+lbdps_status lbdps_destroy(lbdps_ctx *ctx);
+
+const char *lbdps_status_str(lbdps_status s);
+const char *lbdps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBDPS_H */

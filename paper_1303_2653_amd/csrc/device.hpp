@@ -1,0 +1,131 @@
+// Device-side building blocks for gfx950: precision traits, D2Q9 constants,
+// kernel argument structs.  Wave64 throughout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbdps {
+
+constexpr int Q = 9;
+constexpr int KMAX = 32;      // contacts stored per particle
+constexpr int BLOCK = 256;    // threads per workgroup (4 waves)
+constexpr int LUT_W = 12;     // columns of the per-count table
+
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INLET = 2, BC_OUTLET = 3 };
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16DEV = 2, PREC_BF16DEV = 3 };
+// Error flag slots (int32 each).
+enum { FLAG_DOMAIN = 0, FLAG_CAPACITY = 1, FLAG_STALL = 2, FLAG_COUNT = 8 };
+// Columns of the per-count table (built on the host in FP64).
+enum {
+  L_ES3 = 0,  // 3-D solid fraction eps_s,3d (Eq. 11)
+  L_UDIV,     // divisor turning the superficial into the actual gas velocity
+  L_OMG,      // omega * gamma (Eqs. 9, 20, 23)
+  L_RELAX,    // (1 - gamma) / tau (Eq. 23)
+  L_A,        // dilute low-Re drag prefactor 18 (1-eg) omega mu / d^2
+  L_BRE,      // eg * rho_g  (Re_p = eg rho_g |u-v| d / mu, Eq. 22)
+  L_H,        // 0.75 (1-eg) eg rho_g  (dilute, Re_p >= 1000)
+  L_OM,       // omega (Eq. 20)
+  L_D1,       // Ergun viscous term 150 (1-eg)^2 mu / (eg d^2)
+  L_D2,       // Ergun inertial prefactor 1.75 (1-eg) rho_g
+  L_DILUTE    // 1 if eg > 0.74
+};
+
+// D2Q9, numbering 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1).
+__host__ __device__ constexpr int cx_of(int i) {
+  return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int cy_of(int i) {
+  return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+__host__ __device__ constexpr int opp9(int i) {
+  return i == 0 ? 0 : i == 1 ? 3 : i == 2 ? 4 : i == 3 ? 1 : i == 4 ? 2 : i == 5 ? 7 : i == 6 ? 8 : i == 7 ? 5 : 6;
+}
+template <class T>
+__host__ __device__ constexpr T wgt(int i) {
+  return i == 0 ? T(4.0 / 9.0) : (i <= 4 ? T(1.0 / 9.0) : T(1.0 / 36.0));
+}
+
+// bf16 <-> fp32 with round-to-nearest-even.
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Precision modes: T = arithmetic type, S = population storage type.  In the
+// deviation modes a population is stored as f_i - w_i.  In FP64 particle
+// positions are global coordinates; otherwise a cell index plus an offset in
+// [0, 1) (so FP32 keeps its resolution on tall lattices).
+template <int P> struct Prec;
+template <> struct Prec<PREC_FP64> {
+  using T = double;
+  using S = double;
+  static constexpr bool global_pos = true;
+};
+template <> struct Prec<PREC_FP32> {
+  using T = float;
+  using S = float;
+  static constexpr bool global_pos = false;
+};
+template <> struct Prec<PREC_FP16DEV> {
+  using T = float;
+  using S = _Float16;
+  static constexpr bool global_pos = false;
+};
+template <> struct Prec<PREC_BF16DEV> {
+  using T = float;
+  using S = uint16_t;
+  static constexpr bool global_pos = false;
+};
+
+template <int P>
+__device__ __forceinline__ typename Prec<P>::T load_pop(const typename Prec<P>::S *f, size_t idx, int i) {
+  using T = typename Prec<P>::T;
+  if constexpr (P == PREC_FP64 || P == PREC_FP32) {
+    return f[idx];
+  } else if constexpr (P == PREC_FP16DEV) {
+    return wgt<T>(i) + (T)f[idx];
+  } else {
+    return wgt<T>(i) + bf16_to_f32(f[idx]);
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void store_pop(typename Prec<P>::S *f, size_t idx, int i, typename Prec<P>::T v) {
+  if constexpr (P == PREC_FP64 || P == PREC_FP32) {
+    f[idx] = v;
+  } else if constexpr (P == PREC_FP16DEV) {
+    f[idx] = (_Float16)(v - wgt<float>(i));
+  } else {
+    f[idx] = f32_to_bf16(v - wgt<float>(i));
+  }
+}
+
+// Scalar constants of a context, in the arithmetic type.
+template <class T> struct Consts {
+  int nx, ny, C, nlut;
+  int per_x, per_y, bc_ylo, bc_yhi;
+  int drag_abs;
+  int npart;
+  T tau, d, mu, vp, m, msum, one_e, e_pw, r;
+  T geff[2], fp, halfG[2], src[Q];
+  unsigned spin_limit;
+};
+
+// Particle storage (structure of arrays, one "slot" per particle).
+template <class T> struct Parts {
+  int32_t *key;  // cell index y * nx + x
+  int32_t *pid;  // particle index (orders the collisions)
+  T *px, *py;    // global position (FP64) or offset in the cell (reduced precisions)
+  T *vx, *vy;
+};
+
+// Node fields written by the collision, read by the particle stage.
+template <class T> struct Fields {
+  T *rho, *ugx, *ugy, *beta, *fpgx, *fpgy;
+};
+
+}  // namespace lbdps

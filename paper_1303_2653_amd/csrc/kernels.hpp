@@ -1,0 +1,1042 @@
+// HIP kernels of one coupled step (gfx950, wave64).  Citations name the
+// equation or section of Wang, Zhang, Wang, Ge & Li, "Lattice Boltzmann based
+// discrete simulation for gas-solid fluidization" that each piece computes.
+//
+// Arithmetic order: in FP64 every expression is written in the order the
+// method's reference formulation evaluates it, and the library is compiled
+// with contraction off, so FP64 results agree with an FP64 evaluation of the
+// same formulas to the last bit except where pow() is involved.
+#pragma once
+
+#include "device.hpp"
+
+namespace lbdps {
+
+// ------------------------------------------------------------------ helpers
+template <class T>
+__device__ __forceinline__ T feq(int i, T rho, T ux, T uy) {
+  // Eq. 4 with c_s^2 = 1/3.
+  T cu = (T)cx_of(i) * ux + (T)cy_of(i) * uy;
+  T uu = ux * ux + uy * uy;
+  return wgt<T>(i) * rho * ((T)1.0 + (T)3.0 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
+}
+
+__device__ __forceinline__ int wrap_i(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Node index for interpolation and gradients: wrap on periodic axes, clamp
+// otherwise (node (i, j) sits at the cell centre (i + 1/2, j + 1/2)).
+__device__ __forceinline__ int node_idx(int i, int n, int per) {
+  if (per) return ((i % n) + n) % n;
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+template <int P> struct Pos {
+  using T = typename Prec<P>::T;
+  static constexpr bool G = Prec<P>::global_pos;
+
+  // Minimum-image separation a - b.
+  __device__ static void sep(const Consts<T> &k, int ka, T xa, T ya, int kb, T xb, T yb, T &dx, T &dy) {
+    if constexpr (G) {
+      T x = xa - xb, y = ya - yb;
+      if (k.per_x) {
+        if (x > (T)0.5 * (T)k.nx)
+          x -= (T)k.nx;
+        else if (x < -(T)0.5 * (T)k.nx)
+          x += (T)k.nx;
+      }
+      if (k.per_y) {
+        if (y > (T)0.5 * (T)k.ny)
+          y -= (T)k.ny;
+        else if (y < -(T)0.5 * (T)k.ny)
+          y += (T)k.ny;
+      }
+      dx = x;
+      dy = y;
+    } else {
+      int dcx = ka % k.nx - kb % k.nx, dcy = ka / k.nx - kb / k.nx;
+      if (k.per_x) {
+        if (dcx > k.nx / 2)
+          dcx -= k.nx;
+        else if (dcx < -(k.nx / 2))
+          dcx += k.nx;
+      }
+      if (k.per_y) {
+        if (dcy > k.ny / 2)
+          dcy -= k.ny;
+        else if (dcy < -(k.ny / 2))
+          dcy += k.ny;
+      }
+      T ox = xa - xb, oy = ya - yb;
+      dx = (T)dcx + ox;
+      dy = (T)dcy + oy;
+    }
+  }
+
+  // Bilinear stencil origin (i0, j0) and fractions (tx, ty) for s = P - (1/2, 1/2).
+  __device__ static void stencil(const Consts<T> &k, int key, T x, T y, int &i0, int &j0, T &tx, T &ty) {
+    if constexpr (G) {
+      T sx = x - (T)0.5, sy = y - (T)0.5;
+      T fx = floor(sx), fy = floor(sy);
+      tx = sx - fx;
+      ty = sy - fy;
+      i0 = (int)fx;
+      j0 = (int)fy;
+    } else {
+      int cx = key % k.nx, cy = key / k.nx;
+      if (x >= (T)0.5) {
+        i0 = cx;
+        tx = x - (T)0.5;
+      } else {
+        i0 = cx - 1;
+        tx = x + (T)0.5;
+      }
+      if (y >= (T)0.5) {
+        j0 = cy;
+        ty = y - (T)0.5;
+      } else {
+        j0 = cy - 1;
+        ty = y + (T)0.5;
+      }
+    }
+  }
+
+  // Move by v (P <- P + v), then periodic wrap or wall mirror.  Returns the new
+  // cell key, or -1 if the result is not a valid cell (NaN, or a jump across
+  // the whole domain).
+  __device__ static int move(const Consts<T> &k, int key, T &x, T &y, T vx, T vy) {
+    if constexpr (G) {
+      T X = x + vx, Y = y + vy;
+      X = k.per_x ? wrap_c(X, (T)k.nx) : mirror_c(X, (T)k.nx);
+      Y = k.per_y ? wrap_c(Y, (T)k.ny) : mirror_c(Y, (T)k.ny);
+      x = X;
+      y = Y;
+      T fx = floor(X), fy = floor(Y);
+      if (!(fx >= (T)0 && fx < (T)k.nx && fy >= (T)0 && fy < (T)k.ny)) return -1;
+      return (int)fy * k.nx + (int)fx;
+    } else {
+      int cx = key % k.nx, cy = key / k.nx;
+      T ox = x + vx, oy = y + vy;
+      renorm(ox, cx);
+      renorm(oy, cy);
+      if (!axis(cx, ox, k.nx, k.per_x) || !axis(cy, oy, k.ny, k.per_y)) return -1;
+      x = ox;
+      y = oy;
+      return cy * k.nx + cx;
+    }
+  }
+
+  __device__ static T wrap_c(T x, T L) {
+    if (x >= L) {
+      x -= L;
+    } else if (x < (T)0) {
+      x += L;
+      if (x >= L) x = (T)0;
+    }
+    return x;
+  }
+  __device__ static T mirror_c(T x, T L) {
+    if (x < (T)0) x = -x;
+    if (x >= L) x = (T)2 * L - x;
+    if (x >= L) x = nextafter(L, (T)0);
+    return x;
+  }
+  // Offset in [0, 1) after adding a displacement; carries into the cell index.
+  __device__ static void renorm(T &o, int &c) {
+    if (o >= (T)1 || o < (T)0) {
+      T fl = floor(o);
+      o -= fl;
+      c += (int)fl;
+      if (o >= (T)1) {
+        o = (T)0;
+        c += 1;
+      }
+    }
+  }
+  // Periodic wrap or wall mirror of a (cell, offset) coordinate.
+  __device__ static bool axis(int &c, T &o, int n, int per) {
+    if (c >= 0 && c < n) return true;
+    if (per) {
+      c = ((c % n) + n) % n;
+      return true;
+    }
+    if (c < 0) {  // mirror at 0: -(c + o) = (-c - 1) + (1 - o)
+      c = -c - 1;
+      o = (T)1 - o;
+    } else {  // mirror at n: 2n - (c + o) = (2n - c - 1) + (1 - o)
+      c = 2 * n - c - 1;
+      o = (T)1 - o;
+    }
+    if (o >= (T)1) {
+      o = (T)0;
+      c += 1;
+    }
+    if (c >= n) {
+      c = n - 1;
+      o = (T)0.99999994f;
+    }
+    return c >= 0 && c < n;
+  }
+
+  // Global coordinate along x / y as FP64 (exact for both representations).
+  __device__ static double gx(const Consts<T> &k, int key, T x) {
+    if constexpr (G) return (double)x;
+    else return (double)(key % k.nx) + (double)x;
+  }
+  __device__ static double gy(const Consts<T> &k, int key, T y) {
+    if constexpr (G) return (double)y;
+    else return (double)(key / k.nx) + (double)y;
+  }
+
+  // Particle-wall collisions on non-periodic axes (walls as infinitely heavy
+  // particles, Sec. 2.2): within r of a wall and moving into it, v_n -> -e_w v_n.
+  // Faces in the order x-, x+, y-, y+.
+  __device__ static int walls(const Consts<T> &k, int key, T x, T y, T &vx, T &vy) {
+    int hits = 0;
+    bool lx, rx, ly, ry;
+    if constexpr (G) {
+      lx = x <= k.r;
+      rx = (T)k.nx - x <= k.r;
+      ly = y <= k.r;
+      ry = (T)k.ny - y <= k.r;
+    } else {
+      int cx = key % k.nx, cy = key / k.nx;
+      lx = cx == 0 && x <= k.r;
+      rx = cx == k.nx - 1 && (T)1 - x <= k.r;
+      ly = cy == 0 && y <= k.r;
+      ry = cy == k.ny - 1 && (T)1 - y <= k.r;
+    }
+    if (!k.per_x) {
+      if (lx && vx < (T)0) {
+        vx = -k.e_pw * vx;
+        ++hits;
+      }
+      if (rx && vx > (T)0) {
+        vx = -k.e_pw * vx;
+        ++hits;
+      }
+    }
+    if (!k.per_y) {
+      if (ly && vy < (T)0) {
+        vy = -k.e_pw * vy;
+        ++hits;
+      }
+      if (ry && vy > (T)0) {
+        vy = -k.e_pw * vy;
+        ++hits;
+      }
+    }
+    return hits;
+  }
+};
+
+// Block-wide sum of a 64-bit integer (BLOCK threads), result valid in thread 0.
+__device__ __forceinline__ long long block_sum_ll(long long v, long long *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  long long t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < BLOCK / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+// ------------------------------------------------------------------ A2 + A3: deposition fused into collide-stream
+// One thread per cell.  Reads the cell's particle segment (sorted by cell, then
+// particle index) to form n_tot and v_s (Eq. 8), the nine pre-collision
+// populations, collides with Eq. 23 (solid term Eq. 7, weights Eqs. 9-11, 20),
+// writes rho, the actual gas velocity (Eq. 24 and note), F_p->g (Eq. 25) and
+// beta (Eqs. 19, 21, 22), and pushes the post-collision populations to their
+// neighbours with the boundary rules (bounce-back, equilibrium inlet,
+// zero-gradient outlet).
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__restrict__ fsrc,
+                                                   typename Prec<P>::S *__restrict__ fdst,
+                                                   Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs,
+                                                   const typename Prec<P>::T *__restrict__ pvx,
+                                                   const typename Prec<P>::T *__restrict__ pvy,
+                                                   const typename Prec<P>::T *__restrict__ lut,
+                                                   const typename Prec<P>::T *__restrict__ inlet,
+                                                   Consts<typename Prec<P>::T> k, int32_t *dg_n,
+                                                   typename Prec<P>::T *dg_vsx, typename Prec<P>::T *dg_vsy) {
+  using T = typename Prec<P>::T;
+  const int c = blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= k.C) return;
+  const int x = c % k.nx, y = c / k.nx;
+  const size_t C = (size_t)k.C;
+
+  T f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = load_pop<P>(fsrc, i * C + c, i);
+
+  // Eq. 8: n_tot and v_s, summed in ascending particle index.
+  const int a0 = cs[c], a1 = cs[c + 1];
+  const int n = a1 - a0;
+  T sx = (T)0, sy = (T)0;
+  for (int s = a0; s < a1; ++s) {
+    sx += pvx[s];
+    sy += pvy[s];
+  }
+  T vsx = (T)0, vsy = (T)0;
+  if (n > 0) {
+    vsx = sx / (T)n;
+    vsy = sy / (T)n;
+  }
+  const T *L = lut + (size_t)min(n, k.nlut - 1) * LUT_W;
+
+  T rho = (T)0, jx = (T)0, jy = (T)0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) rho += f[i];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) jx += (T)cx_of(i) * f[i];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) jy += (T)cy_of(i) * f[i];
+  const T ux = jx / rho, uy = jy / rho;
+  T fu[Q], oms[Q], fs[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) fu[i] = feq<T>(i, rho, ux, uy);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) oms[i] = f[opp9(i)] - f[i] + feq<T>(i, rho, vsx, vsy) - fu[opp9(i)];
+  const T omg = L[L_OMG], relax = L[L_RELAX];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) fs[i] = f[i] - relax * (f[i] - fu[i]) + omg * oms[i] + k.src[i];
+  T ssx = (T)0, ssy = (T)0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ssx += (T)cx_of(i) * oms[i];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ssy += (T)cy_of(i) * oms[i];
+  const T fpx = omg * ssx, fpy = omg * ssy;
+  const T usx = (jx + (T)0.5 * fpx + k.halfG[0]) / rho;
+  const T usy = (jy + (T)0.5 * fpy + k.halfG[1]) / rho;
+  const T ugx = usx / L[L_UDIV], ugy = usy / L[L_UDIV];
+  const T ddx = ugx - vsx, ddy = ugy - vsy;
+  const T slip = sqrt(ddx * ddx + ddy * ddy);
+  T beta;
+  if (L[L_DILUTE] != (T)0) {
+    const T re = L[L_BRE] * slip * k.d / k.mu;
+    if (re < (T)1000)
+      beta = L[L_A] * ((T)1.0 + (T)0.15 * pow(re, (T)0.687));
+    else
+      beta = L[L_H] * slip * (T)0.44 * L[L_OM] / k.d;
+  } else {
+    beta = L[L_D1] + L[L_D2] * slip / k.d;
+  }
+  fl.rho[c] = rho;
+  fl.ugx[c] = ugx;
+  fl.ugy[c] = ugy;
+  fl.beta[c] = beta;
+  fl.fpgx[c] = fpx;
+  fl.fpgy[c] = fpy;
+  if (dg_n) {
+    dg_n[c] = n;
+    dg_vsx[c] = vsx;
+    dg_vsy[c] = vsy;
+  }
+
+  // Streaming, push form.  An x wall takes precedence at corners.
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int tx = x + cx_of(i), ty = y + cy_of(i);
+    if (tx < 0 || tx >= k.nx) {
+      if (!k.per_x) {  // halfway bounce-back: returns as the opposite population
+        store_pop<P>(fdst, opp9(i) * C + c, opp9(i), fs[i]);
+        continue;
+      }
+      tx = wrap_i(tx, k.nx);
+    }
+    if (ty < 0 || ty >= k.ny) {
+      const int face = ty < 0 ? k.bc_ylo : k.bc_yhi;
+      if (face == BC_PERIODIC) {
+        ty = wrap_i(ty, k.ny);
+      } else if (face == BC_WALL) {
+        store_pop<P>(fdst, opp9(i) * C + c, opp9(i), fs[i]);
+        continue;
+      } else {
+        continue;  // leaves through an inlet or outlet face
+      }
+    }
+    store_pop<P>(fdst, i * C + (size_t)ty * k.nx + tx, i, fs[i]);
+  }
+  // Populations entering through an inlet or outlet face.
+  if ((y == 0 && k.bc_ylo >= BC_INLET) || (y == k.ny - 1 && k.bc_yhi >= BC_INLET)) {
+    const int face = y == 0 ? k.bc_ylo : k.bc_yhi;
+    const int dir = y == 0 ? 1 : -1;  // c_y of the entering populations
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (cy_of(i) != dir) continue;
+      if (face == BC_INLET) {
+        // f_i(x) = f^eq_i(1, (0, u_in(x))) unless its source lies beyond an x wall
+        const int sxn = x - cx_of(i);
+        if ((sxn < 0 || sxn >= k.nx) && !k.per_x) continue;
+        store_pop<P>(fdst, i * C + c, i, feq<T>(i, (T)1.0, (T)0.0, inlet[x]));
+      } else {
+        // zero gradient: this boundary node also feeds its own row
+        int tx = x + cx_of(i);
+        if (tx < 0 || tx >= k.nx) {
+          if (!k.per_x) continue;
+          tx = wrap_i(tx, k.nx);
+        }
+        store_pop<P>(fdst, i * C + (size_t)y * k.nx + tx, i, fs[i]);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ A4 + A5: drag and integration, fused with binning
+// One thread per cell, looping over its particles (ascending index).  Pass 1
+// interpolates u_gas, the solid fraction, beta and grad p at each particle
+// (bilinear, Sec. 2.3 after Eq. 26), forms the pre-estimated drag (Eq. 26) and
+// the cell sum (Eq. 27).  Pass 2 distributes F_p->g with Eq. 28, integrates
+// Eq. 16 (symplectic Euler), moves, wraps or mirrors, and counts the particle
+// into its new cell for the next binning.
+template <int P> struct Interp {
+  using T = typename Prec<P>::T;
+  T ux, uy, es, beta, gpx, gpy;
+
+  __device__ static T pnode(const T *rho, int i, int j, const Consts<T> &k) {
+    return rho[(size_t)j * k.nx + i] / (T)3.0;
+  }
+
+  __device__ void at(const Consts<T> &k, const Fields<T> &fl, const int32_t *cs, const T *lut, int key, T x, T y) {
+    int i0, j0;
+    T tx, ty;
+    Pos<P>::stencil(k, key, x, y, i0, j0, tx, ty);
+    const int ia = node_idx(i0, k.nx, k.per_x), ib = node_idx(i0 + 1, k.nx, k.per_x);
+    const int ja = node_idx(j0, k.ny, k.per_y), jb = node_idx(j0 + 1, k.ny, k.per_y);
+    const int ii[4] = {ia, ib, ia, ib}, jj[4] = {ja, ja, jb, jb};
+    const T w[4] = {((T)1.0 - tx) * ((T)1.0 - ty), tx * ((T)1.0 - ty), ((T)1.0 - tx) * ty, tx * ty};
+    T q[6][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const size_t c = (size_t)jj[m] * k.nx + ii[m];
+      q[0][m] = fl.ugx[c];
+      q[1][m] = fl.ugy[c];
+      const int nn = cs[c + 1] - cs[c];
+      q[2][m] = lut[(size_t)min(nn, k.nlut - 1) * LUT_W + L_ES3];
+      q[3][m] = fl.beta[c];
+      // node pressure gradient, central differences of p = rho / 3 with the
+      // boundary value as ghost beyond a non-periodic face
+      const int ie = node_idx(ii[m] + 1, k.nx, k.per_x), iw = node_idx(ii[m] - 1, k.nx, k.per_x);
+      const int jn = node_idx(jj[m] + 1, k.ny, k.per_y), js = node_idx(jj[m] - 1, k.ny, k.per_y);
+      q[4][m] = (pnode(fl.rho, ie, jj[m], k) - pnode(fl.rho, iw, jj[m], k)) * (T)0.5;
+      q[5][m] = (pnode(fl.rho, ii[m], jn, k) - pnode(fl.rho, ii[m], js, k)) * (T)0.5;
+    }
+    T r[6];
+#pragma unroll
+    for (int v = 0; v < 6; ++v) r[v] = w[0] * q[v][0] + w[1] * q[v][1] + w[2] * q[v][2] + w[3] * q[v][3];
+    ux = r[0];
+    uy = r[1];
+    es = r[2];
+    beta = r[3];
+    gpx = r[4];
+    gpy = r[5];
+  }
+};
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
+                                                const int32_t *__restrict__ cs,
+                                                const typename Prec<P>::T *__restrict__ lut,
+                                                Consts<typename Prec<P>::T> k, int32_t *__restrict__ count,
+                                                int32_t *__restrict__ rank, int32_t *flags,
+                                                typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy,
+                                                long long *zero_part) {
+  using T = typename Prec<P>::T;
+  __shared__ long long sh[BLOCK / 64];
+  const int c = blockIdx.x * BLOCK + threadIdx.x;
+  long long nzero = 0;
+  if (c < k.C) {
+    const int a0 = cs[c], a1 = cs[c + 1];
+    const int n = a1 - a0;
+    if (n > 0) {
+      const T fgx = fl.fpgx[c], fgy = fl.fpgy[c];
+      T Sx = (T)0, Sy = (T)0;
+      for (int s = a0; s < a1; ++s) {
+        Interp<P> I;
+        I.at(k, fl, cs, lut, pt.key[s], pt.px[s], pt.py[s]);
+        Sx += k.vp * I.beta / I.es * (I.ux - pt.vx[s]);
+        Sy += k.vp * I.beta / I.es * (I.uy - pt.vy[s]);
+      }
+      nzero = (Sx == (T)0) + (Sy == (T)0);
+      for (int s = a0; s < a1; ++s) {
+        Interp<P> I;
+        const int key = pt.key[s];
+        T x = pt.px[s], y = pt.py[s], vx = pt.vx[s], vy = pt.vy[s];
+        I.at(k, fl, cs, lut, key, x, y);
+        const T prx = k.vp * I.beta / I.es * (I.ux - vx);
+        const T pry = k.vp * I.beta / I.es * (I.uy - vy);
+        T fdx, fdy;
+        if (Sx == (T)0)
+          fdx = -fgx / (T)n;
+        else if (k.drag_abs)
+          fdx = fabs(fgx) / fabs(Sx) * prx;
+        else
+          fdx = -fgx * prx / Sx;
+        if (Sy == (T)0)
+          fdy = -fgy / (T)n;
+        else if (k.drag_abs)
+          fdy = fabs(fgy) / fabs(Sy) * pry;
+        else
+          fdy = -fgy * pry / Sy;
+        // Eq. 16: v <- v + g_eff + (F_d + s V_p grad p) / m;  P <- P + v
+        const T ax = k.geff[0] + (fdx + k.fp * I.gpx) / k.m;
+        const T ay = k.geff[1] + (fdy + k.fp * I.gpy) / k.m;
+        vx = vx + ax;
+        vy = vy + ay;
+        int nk = Pos<P>::move(k, key, x, y, vx, vy);
+        if (nk < 0) {
+          atomicOr(&flags[FLAG_DOMAIN], 1);
+          nk = key;
+        }
+        pt.key[s] = nk;
+        pt.px[s] = x;
+        pt.py[s] = y;
+        pt.vx[s] = vx;
+        pt.vy[s] = vy;
+        rank[s] = atomicAdd(&count[nk], 1);
+        if (dg_fdx) {
+          const int id = pt.pid[s];
+          dg_fdx[id] = fdx;
+          dg_fdy[id] = fdy;
+        }
+      }
+    }
+  }
+  if (zero_part) {
+    const long long t = block_sum_ll(nzero, sh);
+    if (threadIdx.x == 0) zero_part[blockIdx.x] = t;
+  }
+}
+
+// ------------------------------------------------------------------ A1: binning (counting sort by cell, then particle index)
+// Count particles per cell (slot within the cell from the atomic counter).
+__global__ __launch_bounds__(BLOCK) void k_bin(const int32_t *__restrict__ key, int n, int32_t *__restrict__ count,
+                                               int32_t *__restrict__ rank) {
+  const int s = blockIdx.x * BLOCK + threadIdx.x;
+  if (s < n) rank[s] = atomicAdd(&count[key[s]], 1);
+}
+
+// perm[cell_start[key] + rank] = slot.
+__global__ __launch_bounds__(BLOCK) void k_scatter(const int32_t *__restrict__ key, const int32_t *__restrict__ rank,
+                                                   const int32_t *__restrict__ cs, int n, int32_t *__restrict__ perm) {
+  const int s = blockIdx.x * BLOCK + threadIdx.x;
+  if (s < n) perm[cs[key[s]] + rank[s]] = s;
+}
+
+// One thread per cell: order the cell's segment by particle index (the atomic
+// counter leaves it in arrival order), then gather the particle records into
+// the new storage so each cell's particles are contiguous and ascending.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_sortgather(const int32_t *__restrict__ cs, int32_t *__restrict__ perm,
+                                                      Parts<T> src, Parts<T> dst, int32_t *__restrict__ slot, int C) {
+  const int c = blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= C) return;
+  const int a0 = cs[c], a1 = cs[c + 1];
+  for (int i = a0 + 1; i < a1; ++i) {
+    const int v = perm[i];
+    const int kv = src.pid[v];
+    int j = i - 1;
+    while (j >= a0 && src.pid[perm[j]] > kv) {
+      perm[j + 1] = perm[j];
+      --j;
+    }
+    perm[j + 1] = v;
+  }
+  for (int s = a0; s < a1; ++s) {
+    const int o = perm[s];
+    const int id = src.pid[o];
+    dst.key[s] = src.key[o];
+    dst.pid[s] = id;
+    dst.px[s] = src.px[o];
+    dst.py[s] = src.py[o];
+    dst.vx[s] = src.vx[o];
+    dst.vy[s] = src.vy[o];
+    slot[id] = s;
+  }
+}
+
+// ------------------------------------------------------------------ A6: contact detection
+// One thread per particle slot.  Candidates come from the 3x3 cells around the
+// particle (d < 1 cell); a contact is a centre distance <= d (Sec. 2.2), with
+// the periodic minimum image.  Each particle keeps its full neighbour list
+// sorted by particle index, as 64-bit entries (index << 32 | slot).
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
+                                                    Consts<typename Prec<P>::T> k, long long *__restrict__ adj,
+                                                    int32_t *__restrict__ deg, int32_t *__restrict__ done,
+                                                    int32_t *ticket, int32_t *flags, long long *pair_part) {
+  using T = typename Prec<P>::T;
+  __shared__ long long sh[BLOCK / 64];
+  const int s = blockIdx.x * BLOCK + threadIdx.x;
+  long long fwd = 0;
+  if (s == 0) *ticket = 0;
+  if (s < k.npart) {
+    const int key = pt.key[s];
+    const int id = pt.pid[s];
+    const T x = pt.px[s], y = pt.py[s];
+    const int cx = key % k.nx, cy = key / k.nx;
+    const T dd = k.d * k.d;
+    long long *row = adj + (size_t)s * KMAX;
+    int cnt = 0;
+    bool over = false;
+    for (int oy = -1; oy <= 1; ++oy) {
+      int yy = cy + oy;
+      if (yy < 0 || yy >= k.ny) {
+        if (!k.per_y) continue;
+        yy = wrap_i(yy, k.ny);
+      }
+      for (int ox = -1; ox <= 1; ++ox) {
+        int xx = cx + ox;
+        if (xx < 0 || xx >= k.nx) {
+          if (!k.per_x) continue;
+          xx = wrap_i(xx, k.nx);
+        }
+        const int nc = yy * k.nx + xx;
+        const int t0 = cs[nc], t1 = cs[nc + 1];
+        for (int t = t0; t < t1; ++t) {
+          if (t == s) continue;
+          T dx, dy;
+          Pos<P>::sep(k, key, x, y, pt.key[t], pt.px[t], pt.py[t], dx, dy);
+          if (dx * dx + dy * dy <= dd) {
+            const int tid = pt.pid[t];
+            if (tid > id) ++fwd;
+            if (cnt == KMAX) {
+              over = true;
+              continue;
+            }
+            const long long e = ((long long)tid << 32) | (unsigned)t;
+            int j = cnt;
+            while (j > 0 && row[j - 1] > e) {
+              row[j] = row[j - 1];
+              --j;
+            }
+            row[j] = e;
+            ++cnt;
+          }
+        }
+      }
+    }
+    if (over) atomicOr(&flags[FLAG_CAPACITY], 1);
+    deg[s] = cnt;
+    done[s] = 0;
+  }
+  const long long t = block_sum_ll(fwd, sh);
+  if (threadIdx.x == 0) pair_part[blockIdx.x] = t;
+}
+
+// ------------------------------------------------------------------ A7: collision resolution (Eqs. 17-18) and walls
+// Sequential semantics: pairs (i, j), i < j, processed in lexicographic order,
+// each with the current velocities.  A pair touches only its two particles, so
+// the result is fixed by the order of each particle's own pairs.  Each
+// particle's pairs in that order are exactly its neighbours by ascending index;
+// done[s] counts how many of them are finished.  The owner of a pair is its
+// lower-index particle; it fires the pair once both particles have finished
+// all earlier pairs.  Every wait is for a lexicographically earlier pair, whose
+// owner has a lower particle index; workgroups take particle ranges in the
+// order they start (atomic ticket), so the owner of the earliest unfinished
+// pair is always running and the sweep always progresses.  Waits are bounded
+// by spin_limit polls; exceeding it latches FLAG_STALL and the wave exits.
+// Position of particle index g in the neighbour list of slot t: the number of
+// neighbours of t with a lower index (bounded by the list length).
+__device__ __forceinline__ int row_position(const long long *adj, const int32_t *deg, int t, int g) {
+  const long long *rt = adj + (size_t)t * KMAX;
+  const int n = min(deg[t], KMAX);
+  int b = 0;
+  while (b < n && (int)(rt[b] >> 32) < g) ++b;
+  return b;
+}
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
+                                                   const long long *__restrict__ adj, const int32_t *__restrict__ deg,
+                                                   int32_t *done, int32_t *ticket, Consts<typename Prec<P>::T> k,
+                                                   int32_t *flags, long long *coll_part, long long *wall_part) {
+  using T = typename Prec<P>::T;
+  __shared__ int s_ticket;
+  __shared__ long long sh[BLOCK / 64];
+  if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1);
+  __syncthreads();
+  const int g = s_ticket * BLOCK + threadIdx.x;  // particle index owned by this lane
+  int state = 2;                                  // 0: pair pending, 1: waiting for all pairs, 2: finished
+  int s = 0, dg = 0, a = 0, t = 0, b = 0;
+  long long ncoll = 0, nwall = 0;
+  const long long *row = nullptr;
+  if (g < k.npart) {
+    s = slot[g];
+    dg = deg[s];
+    row = adj + (size_t)s * KMAX;
+    while (a < dg && (int)(row[a] >> 32) < g) ++a;
+    state = a < dg ? 0 : 1;
+    if (state == 0) {
+      t = (int)(row[a] & 0xffffffffll);
+      b = row_position(adj, deg, t, g);
+    }
+  }
+  unsigned spins = 0;
+  while (__any(state != 2)) {
+    if (state == 0) {
+      const int ds = __hip_atomic_load(&done[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int dt = __hip_atomic_load(&done[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (ds == a && dt == b) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        T dx, dy;
+        Pos<P>::sep(k, pt.key[s], pt.px[s], pt.py[s], pt.key[t], pt.px[t], pt.py[t], dx, dy);
+        T vix = pt.vx[s], viy = pt.vy[s], vjx = pt.vx[t], vjy = pt.vy[t];
+        const T dvx = vix - vjx, dvy = viy - vjy;
+        const T dot = dvx * dx + dvy * dy;
+        if (dot < (T)0) {
+          const T r2 = dx * dx + dy * dy;
+          const T q0 = k.one_e * dot / r2;
+          const T ci = q0 * k.m / k.msum;
+          const T cj = q0 * k.m / k.msum;
+          pt.vx[s] = vix - ci * dx;
+          pt.vy[s] = viy - ci * dy;
+          pt.vx[t] = vjx + cj * dx;
+          pt.vy[t] = vjy + cj * dy;
+          ++ncoll;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&done[t], b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&done[s], a + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ++a;
+        if (a < dg) {
+          t = (int)(row[a] & 0xffffffffll);
+          b = row_position(adj, deg, t, g);
+        } else {
+          state = 1;
+        }
+      }
+    } else if (state == 1) {
+      const int ds = __hip_atomic_load(&done[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (ds == dg) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        T vx = pt.vx[s], vy = pt.vy[s];
+        const int h = Pos<P>::walls(k, pt.key[s], pt.px[s], pt.py[s], vx, vy);
+        if (h) {
+          pt.vx[s] = vx;
+          pt.vy[s] = vy;
+          nwall += h;
+        }
+        state = 2;
+      }
+    }
+    if (state != 2) {
+      if (++spins > k.spin_limit) {
+        atomicOr(&flags[FLAG_STALL], 1);
+        state = 2;
+      } else {
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+  }
+  const long long tc = block_sum_ll(ncoll, sh);
+  const long long tw = block_sum_ll(nwall, sh);
+  if (threadIdx.x == 0) {
+    coll_part[blockIdx.x] = tc;
+    wall_part[blockIdx.x] = tw;
+  }
+}
+
+// ------------------------------------------------------------------ exclusive scan of int32 (three passes)
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
+
+__device__ __forceinline__ int block_excl_scan(int v, int *sh, int &total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) sh[wv] = inc;
+  __syncthreads();
+  int base = 0;
+  total = 0;
+  for (int w = 0; w < BLOCK / 64; ++w) {
+    if (w < wv) base += sh[w];
+    total += sh[w];
+  }
+  __syncthreads();
+  return base + inc - v;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int32_t *__restrict__ in, long long n,
+                                                       int32_t *__restrict__ part) {
+  __shared__ int sh[BLOCK / 64];
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  int v = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j)
+    if (base + j < n) v += in[base + j];
+  int total;
+  block_excl_scan(v, sh, total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// Single workgroup: exclusive scan of the tile totals; writes the grand total to *total_out.
+__global__ __launch_bounds__(BLOCK) void k_scan_top(int32_t *__restrict__ part, int ntiles, int32_t *total_out) {
+  __shared__ int sh[BLOCK / 64];
+  int carry = 0;
+  for (int base = 0; base < ntiles; base += BLOCK) {
+    const int i = base + threadIdx.x;
+    const int v = i < ntiles ? part[i] : 0;
+    int total;
+    const int ex = block_excl_scan(v, sh, total);
+    if (i < ntiles) part[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_apply(int32_t *__restrict__ in, long long n,
+                                                      const int32_t *__restrict__ part, int32_t *__restrict__ out,
+                                                      int zero_in) {
+  __shared__ int sh[BLOCK / 64];
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    v[j] = base + j < n ? in[base + j] : 0;
+    sum += v[j];
+  }
+  int total;
+  int run = part[blockIdx.x] + block_excl_scan(sum, sh, total);
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j)
+    if (base + j < n) {
+      out[base + j] = run;
+      run += v[j];
+      if (zero_in) in[base + j] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ FP64 conservation sums (fixed-order reductions)
+__device__ __forceinline__ double block_sum_d(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < BLOCK / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_cons_cells(const typename Prec<P>::S *__restrict__ f, int C,
+                                                      double *__restrict__ part, int32_t *nonfinite) {
+  __shared__ double sh[BLOCK / 64];
+  double m = 0.0, px = 0.0, py = 0.0;
+  int bad = 0;
+  for (int c = blockIdx.x * BLOCK + threadIdx.x; c < C; c += gridDim.x * BLOCK) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double v = (double)load_pop<P>(f, (size_t)i * C + c, i);
+      bad |= !isfinite(v);
+      m += v;
+      px += (double)cx_of(i) * v;
+      py += (double)cy_of(i) * v;
+    }
+  }
+  if (bad) atomicOr(nonfinite, 1);
+  const double a = block_sum_d(m, sh), b = block_sum_d(px, sh), c2 = block_sum_d(py, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 3 + 0] = a;
+    part[blockIdx.x * 3 + 1] = b;
+    part[blockIdx.x * 3 + 2] = c2;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_cons_parts(const T *__restrict__ vx, const T *__restrict__ vy, int n,
+                                                      double mass, double *__restrict__ part, int32_t *nonfinite) {
+  __shared__ double sh[BLOCK / 64];
+  double qx = 0.0, qy = 0.0;
+  int bad = 0;
+  for (int s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
+    const double a = (double)vx[s], b = (double)vy[s];
+    bad |= !isfinite(a) || !isfinite(b);
+    qx += mass * a;
+    qy += mass * b;
+  }
+  if (bad) atomicOr(nonfinite, 1);
+  const double a = block_sum_d(qx, sh), b = block_sum_d(qy, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 2 + 0] = a;
+    part[blockIdx.x * 2 + 1] = b;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cons_final(const double *__restrict__ pc, int nbc,
+                                                      const double *__restrict__ pp, int nbp, const int32_t *nonfinite,
+                                                      double *out) {
+  __shared__ double sh[BLOCK / 64];
+  double v[5] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nbc; b += BLOCK)
+    for (int j = 0; j < 3; ++j) v[j] += pc[b * 3 + j];
+  for (int b = threadIdx.x; b < nbp; b += BLOCK)
+    for (int j = 0; j < 2; ++j) v[3 + j] += pp[b * 2 + j];
+  for (int j = 0; j < 5; ++j) {
+    const double t = block_sum_d(v[j], sh);
+    if (threadIdx.x == 0) out[j] = t;
+  }
+  if (threadIdx.x == 0) out[5] = *nonfinite ? 1.0 : 0.0;
+}
+
+// ------------------------------------------------------------------ layout conversion (canonical FP64 <-> internal)
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_set_f(const double *__restrict__ fin, typename Prec<P>::S *__restrict__ f,
+                                                 int C) {
+  const long long e = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= (long long)Q * C) return;
+  const int i = (int)(e / C);
+  using T = typename Prec<P>::T;
+  const T v = fin ? (T)fin[e] : wgt<T>(i);
+  store_pop<P>(f, (size_t)e, i, v);
+}
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_get_f(const typename Prec<P>::S *__restrict__ f, double *__restrict__ out,
+                                                 int C) {
+  const long long e = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= (long long)Q * C) return;
+  out[e] = (double)load_pop<P>(f, (size_t)e, (int)(e / C));
+}
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_set_parts(const double *__restrict__ pos, const double *__restrict__ vel,
+                                                     int n, Parts<typename Prec<P>::T> pt, int32_t *__restrict__ slot,
+                                                     Consts<typename Prec<P>::T> k, int32_t *flags) {
+  using T = typename Prec<P>::T;
+  const int s = blockIdx.x * BLOCK + threadIdx.x;
+  if (s >= n) return;
+  double X = pos[2 * s], Y = pos[2 * s + 1];
+  double fx = floor(X), fy = floor(Y);
+  if (!(fx >= 0.0 && fx < k.nx && fy >= 0.0 && fy < k.ny)) {
+    atomicOr(&flags[FLAG_DOMAIN], 1);
+    X = 0.5;
+    Y = 0.5;
+    fx = 0.0;
+    fy = 0.0;
+  }
+  int cx = (int)fx, cy = (int)fy;
+  if constexpr (Prec<P>::global_pos) {
+    pt.px[s] = (T)X;
+    pt.py[s] = (T)Y;
+  } else {
+    T ox = (T)(X - fx), oy = (T)(Y - fy);
+    if (ox >= (T)1) {  // rounding of the offset reached 1: carry
+      ox = (T)0;
+      cx += 1;
+      if (cx >= k.nx) {
+        if (k.per_x) cx = 0;
+        else {
+          cx = k.nx - 1;
+          ox = (T)0.99999994f;
+        }
+      }
+    }
+    if (oy >= (T)1) {
+      oy = (T)0;
+      cy += 1;
+      if (cy >= k.ny) {
+        if (k.per_y) cy = 0;
+        else {
+          cy = k.ny - 1;
+          oy = (T)0.99999994f;
+        }
+      }
+    }
+    pt.px[s] = ox;
+    pt.py[s] = oy;
+  }
+  pt.key[s] = cy * k.nx + cx;
+  pt.pid[s] = s;
+  pt.vx[s] = (T)vel[2 * s];
+  pt.vy[s] = (T)vel[2 * s + 1];
+  slot[s] = s;
+}
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_get_parts(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
+                                                     int n, Consts<typename Prec<P>::T> k, double *pos, double *vel,
+                                                     int32_t *cell, const typename Prec<P>::T *fdx,
+                                                     const typename Prec<P>::T *fdy, double *fd) {
+  const int g = blockIdx.x * BLOCK + threadIdx.x;
+  if (g >= n) return;
+  const int s = slot[g];
+  const int key = pt.key[s];
+  if (pos) {
+    pos[2 * g] = Pos<P>::gx(k, key, pt.px[s]);
+    pos[2 * g + 1] = Pos<P>::gy(k, key, pt.py[s]);
+  }
+  if (vel) {
+    vel[2 * g] = (double)pt.vx[s];
+    vel[2 * g + 1] = (double)pt.vy[s];
+  }
+  if (cell) {
+    cell[2 * g] = key % k.nx;
+    cell[2 * g + 1] = key / k.nx;
+  }
+  if (fd) {
+    fd[2 * g] = (double)fdx[g];
+    fd[2 * g + 1] = (double)fdy[g];
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_get_field(const T *__restrict__ a, const T *__restrict__ b, int C,
+                                                     double *out) {
+  const int c = blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= C) return;
+  if (b) {
+    out[2 * c] = (double)a[c];
+    out[2 * c + 1] = (double)b[c];
+  } else {
+    out[c] = (double)a[c];
+  }
+}
+
+// Forward contacts (higher index) per particle index, then the pair list.
+__global__ __launch_bounds__(BLOCK) void k_pairs_count(const int32_t *__restrict__ slot,
+                                                       const long long *__restrict__ adj,
+                                                       const int32_t *__restrict__ deg, int n, int32_t *cnt) {
+  const int g = blockIdx.x * BLOCK + threadIdx.x;
+  if (g >= n) return;
+  const int s = slot[g];
+  const long long *row = adj + (size_t)s * KMAX;
+  int c = 0;
+  for (int a = 0; a < deg[s]; ++a) c += (int)(row[a] >> 32) > g;
+  cnt[g] = c;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_pairs_write(const int32_t *__restrict__ slot,
+                                                       const long long *__restrict__ adj,
+                                                       const int32_t *__restrict__ deg, int n,
+                                                       const int32_t *__restrict__ off, int32_t *pairs, long long cap) {
+  const int g = blockIdx.x * BLOCK + threadIdx.x;
+  if (g >= n) return;
+  const int s = slot[g];
+  const long long *row = adj + (size_t)s * KMAX;
+  long long o = off[g];
+  for (int a = 0; a < deg[s]; ++a) {
+    const int j = (int)(row[a] >> 32);
+    if (j > g) {
+      if (o < cap) {
+        pairs[2 * o] = g;
+        pairs[2 * o + 1] = j;
+      }
+      ++o;
+    }
+  }
+}
+
+__global__ void k_fill_i32(int32_t *p, long long n, int32_t v) {
+  const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace lbdps

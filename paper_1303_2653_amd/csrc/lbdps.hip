@@ -1,0 +1,681 @@
+// Host runtime and C ABI of the lbdps library (see include/lbdps.h).
+// Builds the per-count drag/porosity table in FP64, carves the caller's
+// workspace, and enqueues the kernels of kernels.hpp on the context's stream.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lbdps.h"
+
+using namespace lbdps;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbdps_status fail(lbdps_status s, const std::string &m) {
+  g_err = m;
+  return s;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int NB_CONS = 512;  // workgroups of the conservation reductions
+
+int nblocks(long long n) { return (int)((n + BLOCK - 1) / BLOCK); }
+
+size_t pop_bytes(int prec) { return prec == PREC_FP64 ? 8 : (prec == PREC_FP32 ? 4 : 2); }
+size_t real_bytes(int prec) { return prec == PREC_FP64 ? 8 : 4; }
+
+// Number of rows of the per-count table: every count from the first one whose
+// 2-D solid fraction reaches the packing limit on shares that row.
+int lut_rows(double d) {
+  const double disc = kPi * d * d / 4.0;
+  const double cap = kPi / (2.0 * std::sqrt(3.0));
+  return (int)std::floor(cap / disc) + 2;
+}
+
+// Eq. 20 (EMMS correction), breakpoints in the lower branch.
+double omega_emms(double eg) {
+  if (eg <= 0.82) {
+    const double t = eg - 0.7463;
+    return 0.0214 / (4.0 * t * t + 0.0044) - 0.5760;
+  }
+  if (eg <= 0.97) {
+    const double t = eg - 0.7789;
+    return 0.0038 / (4.0 * t * t + 0.0040) - 0.0101;
+  }
+  return 32.8295 * eg - 31.8295;
+}
+
+double gas_mu(const lbdps_params &p) { return p.rho_g * ((p.tau - 0.5) / 3.0); }
+
+// Per-count table in FP64 (columns L_* of device.hpp): porosities (Eqs. 10, 11,
+// clamped at the densest disc packing), gamma (Eq. 9), omega (Eq. 20) and the
+// count-dependent factors of the drag laws (Eqs. 19, 21, 22).
+std::vector<double> build_lut(const lbdps_params &p) {
+  const int rows = lut_rows(p.d_p);
+  std::vector<double> L((size_t)rows * LUT_W, 0.0);
+  const double d = p.d_p;
+  const double disc = kPi * d * d / 4.0;
+  const double cap = kPi / (2.0 * std::sqrt(3.0));
+  const double coeff = std::sqrt(2.0) / std::sqrt(kPi * std::sqrt(3.0));
+  const double mu = gas_mu(p);
+  for (int n = 0; n < rows; ++n) {
+    double es2 = (double)n * disc;
+    if (es2 > cap) es2 = cap;
+    const double e2 = 1.0 - es2;
+    const double es3 = coeff * std::pow(es2, 1.5);
+    const double eg = 1.0 - es3;
+    double om;
+    if (p.omega_mode == 1)
+      om = 1.0;
+    else if (eg > 0.74)
+      om = omega_emms(eg);
+    else
+      om = p.omega_dense;
+    const double gam = es2 * (p.tau - 0.5) / ((1.0 - es2) + (p.tau - 0.5));
+    double *r = &L[(size_t)n * LUT_W];
+    r[L_ES3] = es3;
+    r[L_UDIV] = p.u_gas_porosity == 0 ? e2 : (p.u_gas_porosity == 1 ? eg : 1.0);
+    r[L_OMG] = om * gam;
+    r[L_RELAX] = (1.0 - gam) / p.tau;
+    r[L_A] = 18.0 * (1.0 - eg) * om * mu / (d * d);
+    r[L_BRE] = eg * p.rho_g;
+    r[L_H] = 0.75 * (1.0 - eg) * eg * p.rho_g;
+    r[L_OM] = om;
+    r[L_D1] = 150.0 * (1.0 - eg) * (1.0 - eg) * mu / (eg * d * d);
+    r[L_D2] = 1.75 * (1.0 - eg) * p.rho_g;
+    r[L_DILUTE] = eg > 0.74 ? 1.0 : 0.0;
+  }
+  return L;
+}
+
+struct DConsts {  // FP64 master copy of the kernel constants
+  double tau, d, mu, vp, m, msum, one_e, e_pw, r, geff[2], fp, halfG[2], src[Q];
+};
+
+DConsts make_dconsts(const lbdps_params &p) {
+  DConsts c{};
+  c.tau = p.tau;
+  c.d = p.d_p;
+  c.mu = gas_mu(p);
+  c.vp = kPi * p.d_p * p.d_p * p.d_p / 6.0;
+  c.m = p.rho_s * c.vp;
+  c.msum = c.m + c.m;
+  c.one_e = 1.0 + p.e_pp;
+  c.e_pw = p.e_pw;
+  c.r = 0.5 * p.d_p;
+  c.geff[0] = (1.0 - p.rho_g / p.rho_s) * p.g[0];
+  c.geff[1] = (1.0 - p.rho_g / p.rho_s) * p.g[1];
+  c.fp = (double)p.pressure_force_sign * c.vp;
+  c.halfG[0] = 0.5 * p.body_force[0];
+  c.halfG[1] = 0.5 * p.body_force[1];
+  for (int i = 0; i < Q; ++i)
+    c.src[i] = 3.0 * wgt<double>(i) * (cx_of(i) * p.body_force[0] + cy_of(i) * p.body_force[1]);
+  return c;
+}
+
+// Workspace layout: every buffer 256-byte aligned.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <class X> X *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    X *p = base ? reinterpret_cast<X *>(base + off) : nullptr;
+    off += (count > 0 ? count : 1) * sizeof(X);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct lbdps_ctx {
+  lbdps_params p{};
+  int prec = 0, nx = 0, ny = 0, C = 0, nlut = 0;
+  long long nmax = 0, n = 0;
+  hipStream_t stream = nullptr;
+  int cf = 0, cp = 0;
+  bool bins_valid = false;
+  long long step = 0;
+  DConsts dc{};
+  // device buffers (carved from the workspace)
+  void *f[2]{};
+  void *fld[6]{};  // rho, ugx, ugy, beta, fpgx, fpgy
+  int32_t *count = nullptr, *cs = nullptr, *spart = nullptr;
+  int32_t *key[2]{}, *pid[2]{};
+  void *px[2]{}, *py[2]{}, *vx[2]{}, *vy[2]{};
+  int32_t *rank = nullptr, *perm = nullptr, *slot = nullptr, *deg = nullptr, *done = nullptr;
+  int32_t *ticket = nullptr, *flags = nullptr, *nonfinite = nullptr;
+  long long *adj = nullptr;
+  void *lut = nullptr, *inlet = nullptr;
+  long long *pair_part = nullptr, *coll_part = nullptr, *wall_part = nullptr, *zero_part = nullptr;
+  double *cons_pc = nullptr, *cons_pp = nullptr, *cons_out = nullptr;
+  int32_t *dg_n = nullptr;
+  void *dg_vsx = nullptr, *dg_vsy = nullptr, *dg_fdx = nullptr, *dg_fdy = nullptr;
+};
+
+namespace {
+
+size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
+  Carver cv{base};
+  const size_t C = (size_t)p.nx * p.ny;
+  const size_t N = (size_t)nmax;
+  const size_t sS = pop_bytes(p.precision), sT = real_bytes(p.precision);
+  const size_t tiles = (std::max(C + 1, N + 1) + SCAN_TILE - 1) / SCAN_TILE + 1;
+  auto raw = [&](size_t bytes) { return cv.take<char>(bytes); };
+  char *f0 = raw(Q * C * sS), *f1 = raw(Q * C * sS);
+  char *fl[6];
+  for (auto &q : fl) q = raw(C * sT);
+  int32_t *count = cv.take<int32_t>(C), *cs = cv.take<int32_t>(C + 1), *spart = cv.take<int32_t>(tiles);
+  int32_t *key[2], *pid[2];
+  char *px[2], *py[2], *vx[2], *vy[2];
+  for (int b = 0; b < 2; ++b) {
+    key[b] = cv.take<int32_t>(N);
+    pid[b] = cv.take<int32_t>(N);
+    px[b] = raw(N * sT);
+    py[b] = raw(N * sT);
+    vx[b] = raw(N * sT);
+    vy[b] = raw(N * sT);
+  }
+  int32_t *rank = cv.take<int32_t>(N + 1), *perm = cv.take<int32_t>(N + 1), *slot = cv.take<int32_t>(N);
+  int32_t *deg = cv.take<int32_t>(N), *done = cv.take<int32_t>(N);
+  long long *adj = cv.take<long long>(N * KMAX);
+  int32_t *ticket = cv.take<int32_t>(4), *flags = cv.take<int32_t>(FLAG_COUNT), *nonfinite = cv.take<int32_t>(4);
+  char *lut = raw((size_t)lut_rows(p.d_p) * LUT_W * sT), *inlet = raw((size_t)p.nx * sT);
+  const size_t nbN = (size_t)nblocks((long long)N), nbC = (size_t)nblocks((long long)C);
+  long long *pair_part = cv.take<long long>(nbN), *coll_part = cv.take<long long>(nbN);
+  long long *wall_part = cv.take<long long>(nbN), *zero_part = cv.take<long long>(nbC);
+  double *pc = cv.take<double>(NB_CONS * 3), *pp = cv.take<double>(NB_CONS * 2), *co = cv.take<double>(8);
+  int32_t *dg_n = nullptr;
+  char *dvx = nullptr, *dvy = nullptr, *dfx = nullptr, *dfy = nullptr;
+  if (p.diagnostics) {
+    dg_n = cv.take<int32_t>(C);
+    dvx = raw(C * sT);
+    dvy = raw(C * sT);
+    dfx = raw(N * sT);
+    dfy = raw(N * sT);
+  }
+  if (x) {
+    x->f[0] = f0;
+    x->f[1] = f1;
+    for (int i = 0; i < 6; ++i) x->fld[i] = fl[i];
+    x->count = count;
+    x->cs = cs;
+    x->spart = spart;
+    for (int b = 0; b < 2; ++b) {
+      x->key[b] = key[b];
+      x->pid[b] = pid[b];
+      x->px[b] = px[b];
+      x->py[b] = py[b];
+      x->vx[b] = vx[b];
+      x->vy[b] = vy[b];
+    }
+    x->rank = rank;
+    x->perm = perm;
+    x->slot = slot;
+    x->deg = deg;
+    x->done = done;
+    x->adj = adj;
+    x->ticket = ticket;
+    x->flags = flags;
+    x->nonfinite = nonfinite;
+    x->lut = lut;
+    x->inlet = inlet;
+    x->pair_part = pair_part;
+    x->coll_part = coll_part;
+    x->wall_part = wall_part;
+    x->zero_part = zero_part;
+    x->cons_pc = pc;
+    x->cons_pp = pp;
+    x->cons_out = co;
+    x->dg_n = dg_n;
+    x->dg_vsx = dvx;
+    x->dg_vsy = dvy;
+    x->dg_fdx = dfx;
+    x->dg_fdy = dfy;
+  }
+  return cv.off + 256;
+}
+
+lbdps_status check_hip(hipError_t e, const char *what) {
+  if (e == hipSuccess) return LBDPS_OK;
+  return fail(LBDPS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+lbdps_status launch_status(const char *what) { return check_hip(hipGetLastError(), what); }
+
+template <int P> struct Impl {
+  using T = typename Prec<P>::T;
+  using S = typename Prec<P>::S;
+
+  static Consts<T> consts(const lbdps_ctx *x) {
+    Consts<T> k{};
+    const DConsts &d = x->dc;
+    k.nx = x->nx;
+    k.ny = x->ny;
+    k.C = x->C;
+    k.nlut = x->nlut;
+    k.per_x = x->p.bc[0] == BC_PERIODIC;
+    k.per_y = x->p.bc[2] == BC_PERIODIC;
+    k.bc_ylo = x->p.bc[2];
+    k.bc_yhi = x->p.bc[3];
+    k.drag_abs = x->p.drag_ratio_mode == 1;
+    k.npart = (int)x->n;
+    k.tau = (T)d.tau;
+    k.d = (T)d.d;
+    k.mu = (T)d.mu;
+    k.vp = (T)d.vp;
+    k.m = (T)d.m;
+    k.msum = (T)d.msum;
+    k.one_e = (T)d.one_e;
+    k.e_pw = (T)d.e_pw;
+    k.r = (T)d.r;
+    for (int a = 0; a < 2; ++a) {
+      k.geff[a] = (T)d.geff[a];
+      k.halfG[a] = (T)d.halfG[a];
+    }
+    k.fp = (T)d.fp;
+    for (int i = 0; i < Q; ++i) k.src[i] = (T)d.src[i];
+    k.spin_limit = 1u << 22;
+    return k;
+  }
+  static Parts<T> parts(const lbdps_ctx *x, int b) {
+    return Parts<T>{x->key[b], x->pid[b], (T *)x->px[b], (T *)x->py[b], (T *)x->vx[b], (T *)x->vy[b]};
+  }
+  static Fields<T> fields(const lbdps_ctx *x) {
+    return Fields<T>{(T *)x->fld[0], (T *)x->fld[1], (T *)x->fld[2], (T *)x->fld[3], (T *)x->fld[4], (T *)x->fld[5]};
+  }
+
+  static void scan(lbdps_ctx *x, int32_t *in, long long n, int32_t *out, int zero_in) {
+    const int tiles = (int)((n + SCAN_TILE - 1) / SCAN_TILE) + (n == 0);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(BLOCK), 0, x->stream, in, n, x->spart);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, x->stream, x->spart, tiles, out + n);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(BLOCK), 0, x->stream, in, n, x->spart, out, zero_in);
+  }
+
+  // Counting sort of the particle storage by (cell, particle index); the
+  // per-cell counts must already be in x->count with slots in x->rank.
+  static void sort_counted(lbdps_ctx *x) {
+    scan(x, x->count, x->C, x->cs, 1);
+    const int N = (int)x->n;
+    if (N == 0) return;
+    hipLaunchKernelGGL(k_scatter, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->key[x->cp], x->rank, x->cs, N,
+                       x->perm);
+    hipLaunchKernelGGL(k_sortgather<T>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, x->cs, x->perm,
+                       parts(x, x->cp), parts(x, 1 - x->cp), x->slot, x->C);
+    x->cp = 1 - x->cp;
+  }
+
+  static void rebin(lbdps_ctx *x) {
+    const int N = (int)x->n;
+    if (N > 0)
+      hipLaunchKernelGGL(k_bin, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->key[x->cp], N, x->count, x->rank);
+    sort_counted(x);
+    x->bins_valid = true;
+  }
+
+  static void hard_spheres(lbdps_ctx *x) {
+    const int N = (int)x->n;
+    if (N == 0) return;
+    const Consts<T> k = consts(x);
+    hipLaunchKernelGGL(k_contacts<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->cs, k, x->adj,
+                       x->deg, x->done, x->ticket, x->flags, x->pair_part);
+    hipLaunchKernelGGL(k_resolve<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot, x->adj,
+                       x->deg, x->done, x->ticket, k, x->flags, x->coll_part, x->wall_part);
+  }
+
+  static lbdps_status step(lbdps_ctx *x, int nsteps) {
+    const Consts<T> k = consts(x);
+    const bool dg = x->p.diagnostics != 0;
+    for (int it = 0; it < nsteps; ++it) {
+      if (!x->bins_valid) rebin(x);
+      hipLaunchKernelGGL(k_collide<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, (const S *)x->f[x->cf],
+                         (S *)x->f[1 - x->cf], fields(x), x->cs, (const T *)x->vx[x->cp], (const T *)x->vy[x->cp],
+                         (const T *)x->lut, (const T *)x->inlet, k, dg ? x->dg_n : nullptr,
+                         dg ? (T *)x->dg_vsx : nullptr, dg ? (T *)x->dg_vsy : nullptr);
+      if (x->n > 0) {
+        hipLaunchKernelGGL(k_drag<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x),
+                           x->cs, (const T *)x->lut, k, x->count, x->rank, x->flags, dg ? (T *)x->dg_fdx : nullptr,
+                           dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr);
+        sort_counted(x);
+        hard_spheres(x);
+      }
+      x->cf = 1 - x->cf;
+      x->step += 1;
+    }
+    return launch_status("lbdps_step");
+  }
+
+  static lbdps_status collide_particles(lbdps_ctx *x) {
+    if (!x->bins_valid) rebin(x);
+    hard_spheres(x);
+    return launch_status("lbdps_collide_particles");
+  }
+
+  static lbdps_status set_state(lbdps_ctx *x, const double *d_f, const double *d_pos, const double *d_vel,
+                                long long n) {
+    const long long e = (long long)Q * x->C;
+    hipLaunchKernelGGL(k_set_f<P>, dim3((unsigned)((e + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, x->stream, d_f,
+                       (S *)x->f[x->cf], x->C);
+    x->n = n;
+    const Consts<T> k = consts(x);
+    if (n > 0)
+      hipLaunchKernelGGL(k_set_parts<P>, dim3(nblocks(n)), dim3(BLOCK), 0, x->stream, d_pos, d_vel, (int)n,
+                         parts(x, x->cp), x->slot, k, x->flags);
+    x->bins_valid = false;
+    x->step = 0;
+    if (x->p.diagnostics) {
+      hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, x->dg_n, (long long)x->C, 0);
+    }
+    return launch_status("lbdps_set_state");
+  }
+
+  static void get_particles(lbdps_ctx *x, double *pos, double *vel, double *fd, int32_t *cell) {
+    if (x->n == 0) return;
+    const Consts<T> k = consts(x);
+    hipLaunchKernelGGL(k_get_parts<P>, dim3(nblocks(x->n)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot,
+                       (int)x->n, k, pos, vel, cell, (const T *)x->dg_fdx, (const T *)x->dg_fdy,
+                       x->p.diagnostics ? fd : nullptr);
+  }
+
+  static void get_field2(lbdps_ctx *x, const void *a, const void *b, double *out) {
+    hipLaunchKernelGGL(k_get_field<T>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, (const T *)a, (const T *)b,
+                       x->C, out);
+  }
+
+  static void get_f(lbdps_ctx *x, double *out) {
+    const long long e = (long long)Q * x->C;
+    hipLaunchKernelGGL(k_get_f<P>, dim3((unsigned)((e + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, x->stream,
+                       (const S *)x->f[x->cf], out, x->C);
+  }
+
+  static void conservation(lbdps_ctx *x) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, x->nonfinite, 1ll, 0);
+    hipLaunchKernelGGL(k_cons_cells<P>, dim3(NB_CONS), dim3(BLOCK), 0, x->stream, (const S *)x->f[x->cf], x->C,
+                       x->cons_pc, x->nonfinite);
+    hipLaunchKernelGGL(k_cons_parts<T>, dim3(NB_CONS), dim3(BLOCK), 0, x->stream, (const T *)x->vx[x->cp],
+                       (const T *)x->vy[x->cp], (int)x->n, x->dc.m, x->cons_pp, x->nonfinite);
+    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(BLOCK), 0, x->stream, x->cons_pc, NB_CONS, x->cons_pp, NB_CONS,
+                       x->nonfinite, x->cons_out);
+  }
+};
+
+template <class F> lbdps_status dispatch(lbdps_ctx *x, F &&fn) {
+  switch (x->prec) {
+    case PREC_FP64: return fn(Impl<PREC_FP64>{});
+    case PREC_FP32: return fn(Impl<PREC_FP32>{});
+    case PREC_FP16DEV: return fn(Impl<PREC_FP16DEV>{});
+    case PREC_BF16DEV: return fn(Impl<PREC_BF16DEV>{});
+  }
+  return fail(LBDPS_E_INVALID, "unknown precision");
+}
+
+// Wait for the stream and report device-side errors latched since the last sync.
+lbdps_status sync_and_check(lbdps_ctx *x, const char *what) {
+  lbdps_status st = check_hip(hipStreamSynchronize(x->stream), what);
+  if (st != LBDPS_OK) return st;
+  int32_t fl[FLAG_COUNT];
+  st = check_hip(hipMemcpy(fl, x->flags, sizeof(fl), hipMemcpyDeviceToHost), what);
+  if (st != LBDPS_OK) return st;
+  bool any = false;
+  for (int i = 0; i < FLAG_COUNT; ++i) any |= fl[i] != 0;
+  if (!any) return LBDPS_OK;
+  // clear the latched flags, then report the first error
+  const int32_t zero[FLAG_COUNT] = {0};
+  check_hip(hipMemcpy(x->flags, zero, sizeof(zero), hipMemcpyHostToDevice), what);
+  const int32_t *had = fl;
+  if (had[FLAG_DOMAIN]) return fail(LBDPS_E_INVALID, std::string(what) + ": a particle left the domain or was placed outside it");
+  if (had[FLAG_CAPACITY])
+    return fail(LBDPS_E_CAPACITY, std::string(what) + ": a particle had more than LBDPS_MAX_CONTACTS contacts");
+  if (had[FLAG_STALL]) return fail(LBDPS_E_STALL, std::string(what) + ": collision resolution exceeded its wait bound");
+  return fail(LBDPS_E_DEVICE, std::string(what) + ": unknown device flag");
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+extern "C" {
+
+const char *lbdps_status_str(lbdps_status s) {
+  switch (s) {
+    case LBDPS_OK: return "ok";
+    case LBDPS_E_INVALID: return "invalid argument";
+    case LBDPS_E_SHAPE: return "shape mismatch";
+    case LBDPS_E_DEVICE: return "device error";
+    case LBDPS_E_UNSUPPORTED: return "unsupported";
+    case LBDPS_E_NONFINITE: return "non-finite value in state";
+    case LBDPS_E_CAPACITY: return "capacity exceeded";
+    case LBDPS_E_STALL: return "collision resolution stalled";
+  }
+  return "unknown status";
+}
+
+const char *lbdps_last_error(void) { return g_err.c_str(); }
+
+lbdps_status lbdps_validate_params(const lbdps_params *p, int64_t max_particles) {
+  if (!p) return fail(LBDPS_E_INVALID, "params is NULL");
+  if (p->nx < 3 || p->ny < 3) return fail(LBDPS_E_SHAPE, "nx and ny must be >= 3");
+  if ((long long)p->nx * p->ny >= 0x7fffffffll) return fail(LBDPS_E_SHAPE, "nx * ny must be < 2^31 - 1");
+  for (int i = 0; i < 4; ++i)
+    if (p->bc[i] < 0 || p->bc[i] > 3) return fail(LBDPS_E_INVALID, "bc values must be 0..3");
+  if (p->bc[0] > 1 || p->bc[1] > 1) return fail(LBDPS_E_INVALID, "x faces must be PERIODIC or WALL");
+  if ((p->bc[0] == 0) != (p->bc[1] == 0)) return fail(LBDPS_E_INVALID, "PERIODIC must be set on both x faces");
+  if ((p->bc[2] == 0) != (p->bc[3] == 0)) return fail(LBDPS_E_INVALID, "PERIODIC must be set on both y faces");
+  if (!(is_fin(p->tau) && p->tau > 0.5)) return fail(LBDPS_E_INVALID, "tau must be > 0.5");
+  if (!(is_fin(p->rho_g) && p->rho_g > 0)) return fail(LBDPS_E_INVALID, "rho_g must be > 0");
+  if (!(is_fin(p->rho_s) && p->rho_s > 0)) return fail(LBDPS_E_INVALID, "rho_s must be > 0");
+  if (!(is_fin(p->d_p) && p->d_p >= 0.02 && p->d_p < 1.0)) return fail(LBDPS_E_INVALID, "d_p must be in [0.02, 1)");
+  if (!(p->e_pp >= 0 && p->e_pp <= 1)) return fail(LBDPS_E_INVALID, "e_pp must be in [0, 1]");
+  if (!(p->e_pw >= 0 && p->e_pw <= 1)) return fail(LBDPS_E_INVALID, "e_pw must be in [0, 1]");
+  for (int a = 0; a < 2; ++a)
+    if (!is_fin(p->g[a]) || !is_fin(p->body_force[a])) return fail(LBDPS_E_INVALID, "g and body_force must be finite");
+  if (p->drag_ratio_mode < 0 || p->drag_ratio_mode > 1) return fail(LBDPS_E_INVALID, "drag_ratio_mode must be 0 or 1");
+  if (p->u_gas_porosity < 0 || p->u_gas_porosity > 2) return fail(LBDPS_E_INVALID, "u_gas_porosity must be 0..2");
+  if (p->omega_mode < 0 || p->omega_mode > 1) return fail(LBDPS_E_INVALID, "omega_mode must be 0 or 1");
+  if (p->pressure_force_sign < -1 || p->pressure_force_sign > 1)
+    return fail(LBDPS_E_INVALID, "pressure_force_sign must be -1, 0 or 1");
+  if (!is_fin(p->omega_dense)) return fail(LBDPS_E_INVALID, "omega_dense must be finite");
+  if (!is_fin(p->cs_smag) || p->cs_smag < 0) return fail(LBDPS_E_INVALID, "cs_smag must be >= 0");
+  if (p->cs_smag != 0.0) return fail(LBDPS_E_UNSUPPORTED, "Smagorinsky LES (cs_smag > 0) is not supported");
+  if (p->precision < 0 || p->precision > 3) return fail(LBDPS_E_INVALID, "precision must be 0..3");
+  if (p->diagnostics < 0 || p->diagnostics > 1) return fail(LBDPS_E_INVALID, "diagnostics must be 0 or 1");
+  if (max_particles < 0 || max_particles > 0x7fffffffll)
+    return fail(LBDPS_E_SHAPE, "max_particles must be in [0, 2^31 - 1]");
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_workspace_bytes(const lbdps_params *p, int64_t max_particles, size_t *bytes) {
+  lbdps_status st = lbdps_validate_params(p, max_particles);
+  if (st != LBDPS_OK) return st;
+  if (!bytes) return fail(LBDPS_E_INVALID, "bytes is NULL");
+  *bytes = carve(*p, max_particles, nullptr, nullptr);
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_create(const lbdps_params *p, int64_t max_particles, void *d_workspace, size_t bytes,
+                          const double *h_inlet_uy, void *stream, lbdps_ctx **out) {
+  if (!out) return fail(LBDPS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  lbdps_status st = lbdps_validate_params(p, max_particles);
+  if (st != LBDPS_OK) return st;
+  const size_t need = carve(*p, max_particles, nullptr, nullptr);
+  if (!d_workspace) return fail(LBDPS_E_INVALID, "workspace is NULL");
+  if (bytes < need) return fail(LBDPS_E_SHAPE, "workspace too small: need " + std::to_string(need) + " bytes");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(LBDPS_E_INVALID, "workspace must be 256-byte aligned");
+  lbdps_ctx *x = new (std::nothrow) lbdps_ctx();
+  if (!x) return fail(LBDPS_E_DEVICE, "host allocation failed");
+  x->p = *p;
+  x->prec = p->precision;
+  x->nx = p->nx;
+  x->ny = p->ny;
+  x->C = p->nx * p->ny;
+  x->nmax = max_particles;
+  x->nlut = lut_rows(p->d_p);
+  x->stream = (hipStream_t)stream;
+  x->dc = make_dconsts(*p);
+  carve(*p, max_particles, (char *)d_workspace, x);
+
+  // per-count table and inlet profile, converted to the arithmetic type
+  std::vector<double> lut = build_lut(*p);
+  std::vector<double> inl(p->nx, 0.0);
+  if (h_inlet_uy)
+    for (int i = 0; i < p->nx; ++i) inl[i] = h_inlet_uy[i];
+  auto upload = [&](void *dst, const std::vector<double> &v) -> lbdps_status {
+    if (x->prec == PREC_FP64) return check_hip(hipMemcpy(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice), "upload");
+    std::vector<float> f(v.begin(), v.end());
+    return check_hip(hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice), "upload");
+  };
+  if ((st = upload(x->lut, lut)) != LBDPS_OK || (st = upload(x->inlet, inl)) != LBDPS_OK) {
+    delete x;
+    return st;
+  }
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, x->count, (long long)x->C, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, x->flags, (long long)FLAG_COUNT, 0);
+  st = dispatch(x, [&](auto impl) { return decltype(impl)::set_state(x, nullptr, nullptr, nullptr, 0); });
+  if (st == LBDPS_OK) st = check_hip(hipStreamSynchronize(x->stream), "lbdps_create");
+  if (st != LBDPS_OK) {
+    delete x;
+    return st;
+  }
+  *out = x;
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_set_state(lbdps_ctx *x, const double *d_f, const double *d_pos, const double *d_vel, int64_t n) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (n < 0 || n > x->nmax) return fail(LBDPS_E_SHAPE, "n must be in [0, max_particles]");
+  if (n > 0 && (!d_pos || !d_vel)) return fail(LBDPS_E_INVALID, "positions and velocities are required when n > 0");
+  return dispatch(x, [&](auto impl) { return decltype(impl)::set_state(x, d_f, d_pos, d_vel, n); });
+}
+
+lbdps_status lbdps_step(lbdps_ctx *x, int32_t nsteps) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (nsteps < 0) return fail(LBDPS_E_INVALID, "nsteps must be >= 0");
+  return dispatch(x, [&](auto impl) { return decltype(impl)::step(x, nsteps); });
+}
+
+lbdps_status lbdps_collide_particles(lbdps_ctx *x) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  return dispatch(x, [&](auto impl) { return decltype(impl)::collide_particles(x); });
+}
+
+lbdps_status lbdps_get_fields(lbdps_ctx *x, double *d_rho, double *d_ugas, double *d_fpg, double *d_beta,
+                              int32_t *d_ncell, double *d_vs) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if ((d_ncell || d_vs) && !x->p.diagnostics) return fail(LBDPS_E_INVALID, "n_tot and v_s need diagnostics on");
+  lbdps_status st = dispatch(x, [&](auto impl) {
+    using I = decltype(impl);
+    if (d_rho) I::get_field2(x, x->fld[0], nullptr, d_rho);
+    if (d_ugas) I::get_field2(x, x->fld[1], x->fld[2], d_ugas);
+    if (d_fpg) I::get_field2(x, x->fld[4], x->fld[5], d_fpg);
+    if (d_beta) I::get_field2(x, x->fld[3], nullptr, d_beta);
+    if (d_vs) I::get_field2(x, x->dg_vsx, x->dg_vsy, d_vs);
+    return launch_status("lbdps_get_fields");
+  });
+  if (st != LBDPS_OK) return st;
+  if (d_ncell) {
+    st = check_hip(hipMemcpyAsync(d_ncell, x->dg_n, (size_t)x->C * 4, hipMemcpyDeviceToDevice, x->stream),
+                   "lbdps_get_fields");
+    if (st != LBDPS_OK) return st;
+  }
+  return sync_and_check(x, "lbdps_get_fields");
+}
+
+lbdps_status lbdps_get_particles(lbdps_ctx *x, double *d_pos, double *d_vel, double *d_fd, int32_t *d_cell) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (d_fd && !x->p.diagnostics) return fail(LBDPS_E_INVALID, "drag output needs diagnostics on");
+  lbdps_status st = dispatch(x, [&](auto impl) {
+    decltype(impl)::get_particles(x, d_pos, d_vel, d_fd, d_cell);
+    return launch_status("lbdps_get_particles");
+  });
+  if (st != LBDPS_OK) return st;
+  return sync_and_check(x, "lbdps_get_particles");
+}
+
+lbdps_status lbdps_get_pairs(lbdps_ctx *x, int32_t *d_pairs, int64_t cap, int64_t *n_out) {
+  if (!x || !n_out) return fail(LBDPS_E_INVALID, "ctx or n_out is NULL");
+  if (cap < 0 || (cap > 0 && !d_pairs)) return fail(LBDPS_E_INVALID, "bad pair buffer");
+  const int N = (int)x->n;
+  *n_out = 0;
+  if (N == 0) return sync_and_check(x, "lbdps_get_pairs");
+  // rank and perm are free between steps: counts, then offsets
+  hipLaunchKernelGGL(k_pairs_count, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->slot, x->adj, x->deg, N, x->rank);
+  dispatch(x, [&](auto impl) {
+    decltype(impl)::scan(x, x->rank, N, x->perm, 0);
+    return LBDPS_OK;
+  });
+  hipLaunchKernelGGL(k_pairs_write, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->slot, x->adj, x->deg, N, x->perm,
+                     d_pairs, (long long)cap);
+  lbdps_status st = launch_status("lbdps_get_pairs");
+  if (st != LBDPS_OK) return st;
+  int32_t total = 0;
+  st = check_hip(hipMemcpyAsync(&total, x->perm + N, 4, hipMemcpyDeviceToHost, x->stream), "lbdps_get_pairs");
+  if (st != LBDPS_OK) return st;
+  st = sync_and_check(x, "lbdps_get_pairs");
+  *n_out = total;
+  return st;
+}
+
+lbdps_status lbdps_get_state(lbdps_ctx *x, double *d_f, double *d_pos, double *d_vel, int64_t *h_step) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  lbdps_status st = dispatch(x, [&](auto impl) {
+    using I = decltype(impl);
+    if (d_f) I::get_f(x, d_f);
+    I::get_particles(x, d_pos, d_vel, nullptr, nullptr);
+    return launch_status("lbdps_get_state");
+  });
+  if (st != LBDPS_OK) return st;
+  if (h_step) *h_step = x->step;
+  return sync_and_check(x, "lbdps_get_state");
+}
+
+lbdps_status lbdps_conservation(lbdps_ctx *x, double h_out[6]) {
+  if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
+  lbdps_status st = dispatch(x, [&](auto impl) {
+    decltype(impl)::conservation(x);
+    return launch_status("lbdps_conservation");
+  });
+  if (st != LBDPS_OK) return st;
+  st = check_hip(hipMemcpyAsync(h_out, x->cons_out, 6 * sizeof(double), hipMemcpyDeviceToHost, x->stream),
+                 "lbdps_conservation");
+  if (st != LBDPS_OK) return st;
+  st = sync_and_check(x, "lbdps_conservation");
+  if (st != LBDPS_OK) return st;
+  if (h_out[5] != 0.0) return fail(LBDPS_E_NONFINITE, "non-finite value in populations or velocities");
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_counters(lbdps_ctx *x, int64_t h_out[4]) {
+  if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
+  lbdps_status st = sync_and_check(x, "lbdps_counters");
+  if (st != LBDPS_OK) return st;
+  const int nbN = nblocks(x->n), nbC = nblocks(x->C);
+  std::vector<long long> buf((size_t)std::max(nbN, nbC));
+  long long *src[3] = {x->pair_part, x->coll_part, x->wall_part};
+  for (int j = 0; j < 4; ++j) h_out[j] = 0;
+  if (x->n > 0)
+    for (int j = 0; j < 3; ++j) {
+      st = check_hip(hipMemcpy(buf.data(), src[j], (size_t)nbN * 8, hipMemcpyDeviceToHost), "lbdps_counters");
+      if (st != LBDPS_OK) return st;
+      for (int b = 0; b < nbN; ++b) h_out[j] += buf[b];
+    }
+  if (x->p.diagnostics && x->n > 0) {
+    st = check_hip(hipMemcpy(buf.data(), x->zero_part, (size_t)nbC * 8, hipMemcpyDeviceToHost), "lbdps_counters");
+    if (st != LBDPS_OK) return st;
+    for (int b = 0; b < nbC; ++b) h_out[3] += buf[b];
+  }
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_destroy(lbdps_ctx *x) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  delete x;
+  return LBDPS_OK;
+}
+
+}  // extern "C"

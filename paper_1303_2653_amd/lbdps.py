@@ -1,0 +1,245 @@
+"""Python binding of the lbdps C ABI (include/lbdps.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+library ``liblbdps.so`` built next to this file.  PyTorch supplies device
+memory (the workspace and the canonical FP64 in/out buffers) and the stream.
+If the library has not been built, importing the binding raises ImportError:
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbdps.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lbdps.h")
+
+LBDPS_OK, LBDPS_E_INVALID, LBDPS_E_SHAPE, LBDPS_E_DEVICE = 0, -1, -2, -3
+LBDPS_E_UNSUPPORTED, LBDPS_E_NONFINITE, LBDPS_E_CAPACITY, LBDPS_E_STALL = -4, -5, -6, -7
+LBDPS_FP64, LBDPS_FP32, LBDPS_FP32_STORE_FP16, LBDPS_FP32_STORE_BF16 = 0, 1, 2, 3
+LBDPS_BC_PERIODIC, LBDPS_BC_WALL, LBDPS_BC_INLET, LBDPS_BC_OUTLET = 0, 1, 2, 3
+LBDPS_MAX_CONTACTS = 32
+
+PRECISIONS = {"fp64": LBDPS_FP64, "fp32": LBDPS_FP32, "fp16": LBDPS_FP32_STORE_FP16, "bf16": LBDPS_FP32_STORE_BF16}
+BCS = {"periodic": LBDPS_BC_PERIODIC, "wall": LBDPS_BC_WALL, "inlet": LBDPS_BC_INLET, "outlet": LBDPS_BC_OUTLET}
+
+c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class lbdps_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", c_i32), ("ny", c_i32), ("bc", c_i32 * 4),
+        ("tau", c_dbl), ("rho_g", c_dbl), ("rho_s", c_dbl), ("d_p", c_dbl),
+        ("e_pp", c_dbl), ("e_pw", c_dbl), ("g", c_dbl * 2), ("body_force", c_dbl * 2),
+        ("drag_ratio_mode", c_i32), ("u_gas_porosity", c_i32), ("omega_mode", c_i32),
+        ("pressure_force_sign", c_i32), ("omega_dense", c_dbl), ("cs_smag", c_dbl),
+        ("precision", c_i32), ("diagnostics", c_i32),
+    ]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.POINTER(lbdps_params)
+_SIGS = {
+    "lbdps_validate_params": (c_i32, [_P, c_i64]),
+    "lbdps_workspace_bytes": (c_i32, [_P, c_i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbdps_create": (c_i32, [_P, c_i64, c_vp, ctypes.c_size_t, c_vp, c_vp, ctypes.POINTER(c_vp)]),
+    "lbdps_set_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64]),
+    "lbdps_step": (c_i32, [c_vp, c_i32]),
+    "lbdps_collide_particles": (c_i32, [c_vp]),
+    "lbdps_get_fields": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lbdps_get_particles": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lbdps_get_pairs": (c_i32, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]),
+    "lbdps_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64)]),
+    "lbdps_conservation": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
+    "lbdps_counters": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
+    "lbdps_destroy": (c_i32, [c_vp]),
+    "lbdps_status_str": (ctypes.c_char_p, [c_i32]),
+    "lbdps_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype, _fn.argtypes = _res, _args
+    globals()[_name] = _fn
+
+
+def header_functions(path: str = HEADER) -> list:
+    """Names of the functions declared in include/lbdps.h."""
+    text = open(path).read()
+    decl = r"^\s*(?:lbdps_status|const\s+char\s*\*)\s*(lbdps_[a-z_]+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
+
+
+class LbdpsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lbdps_last_error().decode() or lbdps_status_str(status).decode()
+        super().__init__(f"{where}: {lbdps_status_str(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def check(status: int, where: str = "lbdps"):
+    if status != LBDPS_OK:
+        raise LbdpsError(status, where)
+
+
+def make_params(cfg: dict, precision=None, diagnostics: bool = False) -> lbdps_params:
+    """Parameter struct from a workload dict (keys as produced by ``synth``)."""
+    p = lbdps_params()
+    p.nx, p.ny = int(cfg["nx"]), int(cfg["ny"])
+    for k, v in enumerate(cfg["bc"]):
+        p.bc[k] = BCS[v] if isinstance(v, str) else int(v)
+    p.tau = float(cfg.get("tau", 0.6))
+    p.rho_g = float(cfg.get("rho_g", 1.0))
+    p.rho_s = float(cfg.get("rho_s", 788.5))
+    p.d_p = float(cfg.get("d", 0.5))
+    p.e_pp = float(cfg.get("e_pp", 0.9))
+    p.e_pw = float(cfg.get("e_pw", cfg.get("e_pp", 0.9)))
+    g, G = cfg.get("g", (0.0, 0.0)), cfg.get("G", (0.0, 0.0))
+    p.g[0], p.g[1] = float(g[0]), float(g[1])
+    p.body_force[0], p.body_force[1] = float(G[0]), float(G[1])
+    p.drag_ratio_mode = int(cfg.get("drag_ratio_mode", 0))
+    p.u_gas_porosity = int(cfg.get("u_gas_porosity", 0))
+    p.omega_mode = int(cfg.get("omega_mode", 0))
+    p.pressure_force_sign = int(cfg.get("pressure_sign", -1))
+    p.omega_dense = float(cfg.get("omega_dense", 1.0))
+    p.cs_smag = float(cfg.get("cs_smag", 0.0))
+    prec = precision if precision is not None else cfg.get("precision", "fp32")
+    p.precision = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    p.diagnostics = int(bool(diagnostics))
+    return p
+
+
+def workspace_bytes(params: lbdps_params, max_particles: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(lbdps_workspace_bytes(ctypes.byref(params), int(max_particles), ctypes.byref(out)), "workspace_bytes")
+    return out.value
+
+
+class Sim:
+    """One context on the current HIP device (torch "cuda" device)."""
+
+    def __init__(self, cfg: dict, precision=None, diagnostics: bool = False, max_particles=None, stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.params = make_params(cfg, precision, diagnostics)
+        pos = np.asarray(cfg["pos"], np.float64).reshape(-1, 2)
+        self.n = len(pos)
+        self.nmax = int(max_particles if max_particles is not None else self.n)
+        self.nx, self.ny = self.params.nx, self.params.ny
+        nbytes = workspace_bytes(self.params, self.nmax)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        inlet = cfg.get("inlet_uy")
+        inlet_arr = None if inlet is None else np.ascontiguousarray(inlet, np.float64)
+        ctx = c_vp()
+        check(lbdps_create(ctypes.byref(self.params), self.nmax, self.ws.data_ptr(), nbytes,
+                           None if inlet_arr is None else inlet_arr.ctypes.data_as(c_vp),
+                           self.stream.cuda_stream, ctypes.byref(ctx)), "lbdps_create")
+        self.ctx = ctx
+        self.set_state(None, pos, cfg.get("vel", np.zeros_like(pos)))
+
+    def _dev(self, a, dtype=None):
+        t = self.torch
+        return t.as_tensor(np.ascontiguousarray(a), dtype=dtype or t.float64).to("cuda").contiguous()
+
+    def set_state(self, f, pos, vel):
+        t = self.torch
+        pos = self._dev(np.asarray(pos, np.float64).reshape(-1, 2))
+        vel = self._dev(np.asarray(vel, np.float64).reshape(-1, 2))
+        fd = None if f is None else self._dev(np.asarray(f, np.float64).reshape(9, self.ny, self.nx))
+        self.n = pos.shape[0]
+        with t.cuda.stream(self.stream):
+            check(lbdps_set_state(self.ctx, None if fd is None else fd.data_ptr(), pos.data_ptr(),
+                                  vel.data_ptr(), self.n), "lbdps_set_state")
+        self.stream.synchronize()
+
+    def step(self, nsteps: int = 1):
+        check(lbdps_step(self.ctx, int(nsteps)), "lbdps_step")
+
+    def collide_particles(self):
+        check(lbdps_collide_particles(self.ctx), "lbdps_collide_particles")
+
+    def fields(self):
+        t = self.torch
+        C = self.nx * self.ny
+        rho = t.empty(C, dtype=t.float64, device="cuda")
+        ug = t.empty(C, 2, dtype=t.float64, device="cuda")
+        fpg = t.empty(C, 2, dtype=t.float64, device="cuda")
+        beta = t.empty(C, dtype=t.float64, device="cuda")
+        diag = bool(self.params.diagnostics)
+        ncell = t.empty(C, dtype=t.int32, device="cuda") if diag else None
+        vs = t.empty(C, 2, dtype=t.float64, device="cuda") if diag else None
+        check(lbdps_get_fields(self.ctx, rho.data_ptr(), ug.data_ptr(), fpg.data_ptr(), beta.data_ptr(),
+                               ncell.data_ptr() if diag else None, vs.data_ptr() if diag else None),
+              "lbdps_get_fields")
+        sh = (self.ny, self.nx)
+        out = dict(rho=rho.cpu().numpy().reshape(sh), ugas=ug.cpu().numpy().reshape(*sh, 2),
+                   fpg=fpg.cpu().numpy().reshape(*sh, 2), beta=beta.cpu().numpy().reshape(sh))
+        if diag:
+            out["ncell"] = ncell.cpu().numpy().reshape(sh)
+            out["vs"] = vs.cpu().numpy().reshape(*sh, 2)
+        return out
+
+    def particles(self):
+        t = self.torch
+        n = max(self.n, 1)
+        pos = t.empty(n, 2, dtype=t.float64, device="cuda")
+        vel = t.empty(n, 2, dtype=t.float64, device="cuda")
+        cell = t.empty(n, 2, dtype=t.int32, device="cuda")
+        diag = bool(self.params.diagnostics)
+        fd = t.empty(n, 2, dtype=t.float64, device="cuda") if diag else None
+        check(lbdps_get_particles(self.ctx, pos.data_ptr(), vel.data_ptr(), fd.data_ptr() if diag else None,
+                                  cell.data_ptr()), "lbdps_get_particles")
+        out = dict(pos=pos.cpu().numpy()[: self.n], vel=vel.cpu().numpy()[: self.n],
+                   cell=cell.cpu().numpy()[: self.n])
+        if diag:
+            out["fd"] = fd.cpu().numpy()[: self.n]
+        return out
+
+    def pairs(self, cap=None):
+        t = self.torch
+        cap = int(cap if cap is not None else max(16, LBDPS_MAX_CONTACTS * self.n // 2 + 16))
+        buf = t.empty(cap, 2, dtype=t.int32, device="cuda")
+        m = c_i64(0)
+        check(lbdps_get_pairs(self.ctx, buf.data_ptr(), cap, ctypes.byref(m)), "lbdps_get_pairs")
+        return buf[: min(m.value, cap)].cpu().numpy(), m.value
+
+    def state(self):
+        t = self.torch
+        n = max(self.n, 1)
+        f = t.empty(9, self.ny, self.nx, dtype=t.float64, device="cuda")
+        pos = t.empty(n, 2, dtype=t.float64, device="cuda")
+        vel = t.empty(n, 2, dtype=t.float64, device="cuda")
+        st = c_i64(0)
+        check(lbdps_get_state(self.ctx, f.data_ptr(), pos.data_ptr(), vel.data_ptr(), ctypes.byref(st)),
+              "lbdps_get_state")
+        return f.cpu().numpy(), pos.cpu().numpy()[: self.n], vel.cpu().numpy()[: self.n], st.value
+
+    def conservation(self):
+        out = (c_dbl * 6)()
+        check(lbdps_conservation(self.ctx, out), "lbdps_conservation")
+        return np.array(out[:])
+
+    def counters(self):
+        out = (c_i64 * 4)()
+        check(lbdps_counters(self.ctx, out), "lbdps_counters")
+        return dict(pairs=out[0], collisions=out[1], walls=out[2], zero_den=out[3])
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.stream.synchronize()
+            lbdps_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

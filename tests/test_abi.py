@@ -1,0 +1,92 @@
+"""C ABI contract checks that need no GPU: the library loads, exports every
+function include/lbdps.h declares, and validates parameters and sizes the
+workspace without touching a device."""
+import ctypes
+
+import pytest
+
+import synth
+
+L = pytest.importorskip("paper_1303_2653_amd.lbdps", reason="HIP library not built")
+
+
+def test_exports_every_declared_symbol():
+    names = L.header_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layout_matches_header():
+    # offsets of the C struct on x86-64 / LP64 (natural alignment)
+    assert L.lbdps_params.tau.offset == 24
+    assert L.lbdps_params.g.offset == 72
+    assert L.lbdps_params.drag_ratio_mode.offset == 104
+    assert L.lbdps_params.omega_dense.offset == 120
+    assert L.lbdps_params.precision.offset == 136
+    assert ctypes.sizeof(L.lbdps_params) == 144
+
+
+def _status(p, nmax=10):
+    return L.lbdps_validate_params(ctypes.byref(p), nmax)
+
+
+def test_validation_accepts_workloads():
+    for cfg in (synth.bubble_small(), synth.bubble(), synth.riser_crop()):
+        p = L.make_params(cfg)
+        assert _status(p, len(cfg["pos"])) == L.LBDPS_OK, L.lbdps_last_error()
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("nx", 2, L.LBDPS_E_SHAPE), ("ny", 0, L.LBDPS_E_SHAPE), ("tau", 0.5, L.LBDPS_E_INVALID),
+    ("tau", float("nan"), L.LBDPS_E_INVALID), ("d_p", 1.0, L.LBDPS_E_INVALID), ("d_p", 0.0, L.LBDPS_E_INVALID),
+    ("e_pp", 1.5, L.LBDPS_E_INVALID), ("e_pw", -0.1, L.LBDPS_E_INVALID), ("rho_s", 0.0, L.LBDPS_E_INVALID),
+    ("precision", 7, L.LBDPS_E_INVALID), ("pressure_force_sign", 2, L.LBDPS_E_INVALID),
+    ("cs_smag", 0.1, L.LBDPS_E_UNSUPPORTED), ("drag_ratio_mode", 3, L.LBDPS_E_INVALID),
+])
+def test_validation_rejects(field, value, code):
+    p = L.make_params(synth.bubble_small())
+    setattr(p, field, value)
+    assert _status(p) == code
+    assert L.lbdps_last_error()
+
+
+def test_validation_rejects_bad_faces():
+    p = L.make_params(synth.bubble_small())
+    p.bc[0] = L.LBDPS_BC_INLET
+    assert _status(p) == L.LBDPS_E_INVALID
+    p = L.make_params(synth.bubble_small())
+    p.bc[2] = L.LBDPS_BC_PERIODIC  # y- periodic with y+ outlet
+    assert _status(p) == L.LBDPS_E_INVALID
+    p = L.make_params(synth.bubble_small())
+    assert _status(p, -1) == L.LBDPS_E_SHAPE
+    assert L.lbdps_validate_params(None, 0) == L.LBDPS_E_INVALID
+
+
+def test_workspace_bytes_scale():
+    p = L.make_params(synth.bubble())
+    b0 = L.workspace_bytes(p, 0)
+    b1 = L.workspace_bytes(p, 200_000)
+    C = 256 * 1024
+    assert b0 > 2 * 9 * C * 4  # two population buffers
+    # per particle: 2 x 24-byte records, 5 int32 work arrays, 32 contact slots of 8 bytes
+    assert b1 - b0 >= 200_000 * (48 + 20 + 256)
+    p.precision = L.LBDPS_FP32_STORE_FP16
+    assert L.workspace_bytes(p, 0) < b0
+    p.diagnostics = 1
+    assert L.workspace_bytes(p, 0) > L.workspace_bytes(L.make_params(synth.bubble(), "fp16"), 0)
+
+
+def test_create_rejects_small_workspace_before_device():
+    p = L.make_params(synth.bubble_small())
+    ctx = ctypes.c_void_p()
+    st = L.lbdps_create(ctypes.byref(p), 10, ctypes.c_void_p(256), 16, None, None, ctypes.byref(ctx))
+    assert st == L.LBDPS_E_SHAPE and not ctx.value
+    st = L.lbdps_create(ctypes.byref(p), 10, None, 1 << 30, None, None, ctypes.byref(ctx))
+    assert st == L.LBDPS_E_INVALID
+
+
+def test_status_strings():
+    for s in range(-7, 1):
+        assert L.lbdps_status_str(s)

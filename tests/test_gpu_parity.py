@@ -1,0 +1,237 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances (norm-wise, max|x - ref| / max(max|ref|, floor)):
+  FP64 mode: 1e-12 after a fixed number of free-running steps;
+  FP32 mode: 1e-5 after one step from the same (FP32-representable) state.
+Integer outputs (cell counts, contact pairs) are compared bit for bit; in
+FP32 the contact predicate is evaluated in single precision on both sides.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+L = pytest.importorskip("paper_1303_2653_amd.lbdps")
+import oracle  # noqa: E402
+
+
+def rel(a, b, floor=0.0):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    scale = max(np.abs(b).max() if b.size else 0.0, floor)
+    if scale == 0.0:
+        return float(np.abs(a).max()) if a.size else 0.0
+    return float(np.abs(a - b).max() / scale)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def compare_step(gpu, ref_out, ref, tol, fields=True, what=""):
+    f, pos, vel, _ = gpu.state()
+    errs = dict(f=rel(f, ref.f, 1.0), pos=rel(pos, ref.pos, 1.0), vel=rel(vel, ref.vel))
+    if fields:
+        fl = gpu.fields()
+        errs.update(rho=rel(fl["rho"], ref_out.rho, 1.0), ugas=rel(fl["ugas"], ref_out.ugas),
+                    fpg=rel(fl["fpg"], ref_out.fpg), beta=rel(fl["beta"], ref_out.beta))
+        if "ncell" in fl:
+            assert (fl["ncell"] == ref_out.ncell).all(), f"{what}: cell counts differ"
+            errs["vs"] = rel(fl["vs"], ref_out.vs)
+            pf = gpu.particles()
+            errs["fd"] = rel(pf["fd"], ref_out.fd)
+    say(what, {k: f"{v:.2e}" for k, v in errs.items()})
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"{what}: beyond {tol}: {bad}"
+    return errs
+
+
+# ---------------------------------------------------------------- FP64 free run
+TINY_CASES = {
+    "inlet-outlet": dict(bc=("periodic", "periodic", "inlet", "outlet"), band=10.0),
+    "closed-box": dict(bc=("wall",) * 4, band=12.0, g=(2e-5, -1e-5)),
+    "riser-walls": dict(bc=("wall", "wall", "periodic", "periodic"), G=(0.0, 2e-5), g=(0.0, -3e-5)),
+    "periodic": dict(bc=("periodic",) * 4, g=(0.0, 0.0), G=(1e-5, 0.0)),
+    "inlet-walls": dict(bc=("wall", "wall", "inlet", "outlet"), band=14.0),
+    "abs-ratio": dict(bc=("periodic", "periodic", "wall", "wall"), drag_ratio_mode=1, pressure_sign=1,
+                      u_gas_porosity=1),
+    "omega1": dict(bc=("periodic", "periodic", "inlet", "outlet"), omega_mode=1, u_gas_porosity=2),
+}
+
+
+@pytest.mark.parametrize("case", sorted(TINY_CASES))
+def test_fp64_free_run_small(case):
+    kw = dict(TINY_CASES[case])
+    cfg = synth.tiny(nx=19, ny=23, n=260, seed=31, vel_scale=2e-3, **kw)
+    say("case", case)
+    gpu = L.Sim(cfg, precision="fp64", diagnostics=True)
+    ref = oracle.Sim(cfg)
+    for k in range(1, 21):
+        gpu.step(1)
+        o = ref.step(record=True)
+        if k in (1, 2, 5, 20):
+            compare_step(gpu, o, ref, 1e-12, what=f"{case} step {k}")
+            pairs, m = gpu.pairs()
+            assert m == len(o.pairs) and (pairs == o.pairs).all(), f"{case} step {k}: pairs differ"
+    c = gpu.counters()
+    assert c["pairs"] == len(o.pairs)
+    assert c["collisions"] == o.ncollisions and c["walls"] == o.nwall
+
+
+def test_fp64_bubble_small_100_steps():
+    """64x256 bed, 2000 spheres, 100 coupled steps, FP64: every field and
+    particle state within 1e-12 of the oracle, pair lists identical."""
+    cfg = synth.bubble_small()
+    gpu = L.Sim(cfg, precision="fp64", diagnostics=True)
+    ref = oracle.Sim(cfg)
+    for k in range(1, 101):
+        gpu.step(1)
+        o = ref.step(record=(k in (1, 10, 50, 100)))
+        if o is not None:
+            compare_step(gpu, o, ref, 1e-12, what=f"bubble_small step {k}")
+            pairs, m = gpu.pairs()
+            assert m == len(o.pairs) and (pairs == o.pairs).all()
+            c = gpu.counters()
+            assert c["collisions"] == o.ncollisions
+
+
+def test_fp64_multi_step_call_equals_single_steps():
+    """lbdps_step(k) equals k calls of lbdps_step(1), bit for bit, and a
+    checkpoint (get_state / set_state) in the middle changes nothing."""
+    cfg = synth.tiny(nx=17, ny=20, n=200, seed=5, vel_scale=3e-3, bc=("periodic", "periodic", "wall", "wall"))
+    a = L.Sim(cfg, precision="fp64")
+    a.step(12)
+    b = L.Sim(cfg, precision="fp64")
+    for _ in range(6):
+        b.step(1)
+    f, pos, vel, st = b.state()
+    assert st == 6
+    b.set_state(f, pos, vel)
+    b.step(6)
+    fa, pa, va, _ = a.state()
+    fb, pb, vb, _ = b.state()
+    assert (fa == fb).all() and (pa == pb).all() and (va == vb).all()
+
+
+def test_determinism_fp32():
+    cfg = synth.tiny(nx=40, ny=60, n=1500, seed=9, vel_scale=5e-3, band=30.0)
+    out = []
+    for _ in range(2):
+        s = L.Sim(cfg, precision="fp32")
+        s.step(15)
+        out.append(s.state())
+    for x, y in zip(out[0][:3], out[1][:3]):
+        assert (x == y).all()
+
+
+# ---------------------------------------------------------------- hard-sphere stage alone
+def test_fp64_collision_stage_exact():
+    """Contacts and Eqs. 17-18 on the dense 2000-particle bed with random
+    velocities: pair list and post-collision velocities bit-identical to the
+    oracle's sequential lexicographic sweep followed by the wall pass."""
+    cfg = synth.bubble_small()
+    rng = np.random.default_rng(4)
+    vel = (rng.random(cfg["pos"].shape) - 0.5) * 1e-2
+    gpu = L.Sim(dict(cfg, vel=vel), precision="fp64")
+    gpu.collide_particles()
+    pairs, m = gpu.pairs()
+    p = oracle.make_params(cfg)
+    ref_pairs = oracle.contacts(p, cfg["pos"])
+    assert m == len(ref_pairs) and (pairs == ref_pairs).all()
+    v1, nc = oracle.resolve(p, cfg["pos"], vel, ref_pairs)
+    v1, nw = oracle.walls(p, cfg["pos"], v1)
+    st = gpu.particles()
+    assert (st["vel"] == v1).all(), rel(st["vel"], v1)
+    c = gpu.counters()
+    assert c["collisions"] == nc and c["walls"] == nw
+
+
+def test_fp32_contacts_exact_single_precision():
+    """Contact pairs in FP32 mode equal the oracle's single-precision predicate
+    on the same cell + offset state, bit for bit, including the periodic wrap."""
+    rng = np.random.default_rng(12)
+    nx, ny, n = 48, 40, 5000
+    cell = np.stack([rng.integers(0, nx, n), rng.integers(0, ny, n)], 1).astype(np.int32)
+    off = rng.random((n, 2)).astype(np.float32)
+    pos = cell.astype(np.float64) + off.astype(np.float64)
+    cfg = synth.tiny(nx=nx, ny=ny, n=n, bc=("periodic", "periodic", "wall", "wall"))
+    cfg["pos"] = pos
+    gpu = L.Sim(cfg, precision="fp32")
+    gpu.collide_particles()
+    pairs, m = gpu.pairs()
+    ref = oracle.contacts_f32(nx, ny, 1, 0, 0.5, cell, off)
+    assert m == len(ref) and (pairs == ref).all()
+    st = gpu.particles()
+    assert (st["cell"] == cell).all()
+
+
+# ---------------------------------------------------------------- FP32 lockstep at full size
+@pytest.mark.parametrize("name", ["bubble", "riser_crop"])
+def test_fp32_one_step_full_size(name):
+    """One coupled step in FP32 at the workload's full size from a shared
+    FP32-representable state, against the FP64 oracle step from the same state:
+    fields and particle state within 1e-5 (norm-wise)."""
+    cfg = getattr(synth, name)()
+    say("workload", cfg["name"])
+    warm = L.Sim(cfg, precision="fp32")
+    warm.step(20)  # develop flow and velocities on the GPU, then hand the state to both sides
+    f, pos, vel, _ = warm.state()
+    del warm
+    gpu = L.Sim(cfg, precision="fp32", diagnostics=True)
+    gpu.set_state(f, pos, vel)
+    gpu.step(1)
+    ref = oracle.Sim(cfg, f=f, pos=pos, vel=vel)
+    o = ref.step(record=True)
+    compare_step(gpu, o, ref, 1e-5, what=f"{name} fp32 one step")
+    pairs, m = gpu.pairs()
+    a, b = set(map(tuple, pairs.tolist())), set(map(tuple, o.pairs.tolist()))
+    diff = a ^ b
+    say("pairs", m, len(o.pairs), "differing", len(diff))
+    P = gpu.particles()["pos"]
+    for i, j in list(diff)[:1000]:
+        dx, dy = P[i] - P[j]
+        if cfg["bc"][0] == "periodic":
+            dx -= cfg["nx"] * round(dx / cfg["nx"])
+        if cfg["bc"][2] == "periodic":
+            dy -= cfg["ny"] * round(dy / cfg["ny"])
+        assert abs(math.hypot(dx, dy) - cfg["d"]) < 1e-5, "pair sets differ away from a tie"
+
+
+# ---------------------------------------------------------------- conservation
+def test_conservation_sums_fp64():
+    """FP64 conservation reductions on the GPU equal the oracle's sums (to
+    roundoff) and show the periodic bed's gas + particle momentum conserved."""
+    cfg = synth.tiny(nx=30, ny=30, n=500, seed=2, bc=("periodic",) * 4, vel_scale=2e-3, g=(0.0, 0.0),
+                     pressure_sign=0)
+    gpu = L.Sim(cfg, precision="fp64")
+    ref = oracle.Sim(cfg)
+    c0 = gpu.conservation()
+    assert np.allclose(c0[:5], ref.conservation(), rtol=1e-13, atol=1e-15) and c0[5] == 0
+    gpu.step(30)
+    ref.run(30)
+    c1 = gpu.conservation()
+    assert np.allclose(c1[:5], ref.conservation(), rtol=1e-12, atol=1e-14)
+    assert abs(c1[0] - c0[0]) < 1e-12 * c0[0]
+    tot0, tot1 = c0[1:3] + c0[3:5], c1[1:3] + c1[3:5]
+    assert np.abs(tot1 - tot0).max() < 1e-12 * max(np.abs(c1[3:5]).max(), 1e-30)
+
+
+def test_error_particle_outside_domain():
+    cfg = synth.tiny(nx=10, ny=10, n=20, seed=1)
+    gpu = L.Sim(cfg, precision="fp64")
+    pos = cfg["pos"].copy()
+    pos[3] = (10.5, 2.0)
+    gpu_bad = L.Sim(dict(cfg), precision="fp64")
+    with pytest.raises(L.LbdpsError) as e:
+        gpu_bad.set_state(None, pos, cfg["vel"])
+        gpu_bad.conservation()
+    assert e.value.status == L.LBDPS_E_INVALID
+    gpu.step(2)
+    gpu.conservation()  # the healthy context is unaffected
