@@ -58,7 +58,7 @@ typedef enum {
 /* Storage and arithmetic precision of a context. */
 typedef enum {
   LBDPS_FP64 = 0,            /* FP64 storage and arithmetic                      */
-  LBDPS_FP32 = 1,            /* FP32 storage and arithmetic                      */
+  LBDPS_FP32 = 1,            /* populations stored as FP32 deviations f_i - w_i, FP32 arithmetic */
   LBDPS_FP32_STORE_FP16 = 2, /* populations stored as FP16 deviations f_i - w_i, FP32 arithmetic */
   LBDPS_FP32_STORE_BF16 = 3  /* populations stored as BF16 deviations f_i - w_i, FP32 arithmetic */
 } lbdps_precision;

@@ -55,7 +55,8 @@ class OrcOut(ctypes.Structure):
     _fields_ = [
         ("ncell", ctypes.c_void_p), ("vs", ctypes.c_void_p), ("rho", ctypes.c_void_p),
         ("ugas", ctypes.c_void_p), ("fpg", ctypes.c_void_p), ("beta", ctypes.c_void_p),
-        ("fd", ctypes.c_void_p), ("pairs", ctypes.c_void_p),
+        ("fd", ctypes.c_void_p), ("fpre", ctypes.c_void_p), ("upart", ctypes.c_void_p),
+        ("pairs", ctypes.c_void_p),
         ("pair_cap", ctypes.c_int64), ("npairs", ctypes.c_int64),
         ("ncollisions", ctypes.c_int64), ("nwall", ctypes.c_int64),
         ("nzero_den", ctypes.c_int64),
@@ -295,6 +296,8 @@ class StepOut:
     fpg: np.ndarray
     beta: np.ndarray
     fd: np.ndarray
+    fpre: np.ndarray
+    upart: np.ndarray
     pairs: np.ndarray
     ncollisions: int
     nwall: int
@@ -327,7 +330,8 @@ class Sim:
         if record:
             bufs = dict(ncell=np.zeros(C, np.int32), vs=np.zeros((C, 2)), rho=np.zeros(C),
                         ugas=np.zeros((C, 2)), fpg=np.zeros((C, 2)), beta=np.zeros(C),
-                        fd=np.zeros((max(n, 1), 2)))
+                        fd=np.zeros((max(n, 1), 2)), fpre=np.zeros((max(n, 1), 2)),
+                        upart=np.zeros((max(n, 1), 2)))
             cap = pair_cap if pair_cap is not None else max(16, 32 * n)
             bufs["pairs"] = np.zeros((cap, 2), np.int32)
             for k, v in bufs.items():
@@ -343,7 +347,8 @@ class Sim:
         return StepOut(ncell=bufs["ncell"].reshape(ny, nx), vs=bufs["vs"].reshape(ny, nx, 2),
                        rho=bufs["rho"].reshape(ny, nx), ugas=bufs["ugas"].reshape(ny, nx, 2),
                        fpg=bufs["fpg"].reshape(ny, nx, 2), beta=bufs["beta"].reshape(ny, nx),
-                       fd=bufs["fd"][:n].copy(), pairs=bufs["pairs"][: o.npairs].copy(),
+                       fd=bufs["fd"][:n].copy(), fpre=bufs["fpre"][:n].copy(),
+                       upart=bufs["upart"][:n].copy(), pairs=bufs["pairs"][: o.npairs].copy(),
                        ncollisions=o.ncollisions, nwall=o.nwall, nzero_den=o.nzero_den)
 
     def run(self, nsteps):

@@ -62,6 +62,8 @@ typedef struct {
   double *fpg;    /* [C][2] force of the particles on the gas (Eq. 25) */
   double *beta;   /* [C]    EMMS drag coefficient at the node (Eq. 19) */
   double *fd;     /* [N][2] corrected drag on each particle (Eq. 28) */
+  double *fpre;   /* [N][2] pre-estimated drag (Eq. 26) */
+  double *upart;  /* [N][2] gas velocity interpolated at the particle */
   int32_t *pairs; /* [cap][2] contact pairs after the move, lexicographic */
   int64_t pair_cap;
   int64_t npairs;      /* out */
@@ -759,6 +761,10 @@ int orc_step(const orc_params *p, const double *inlet_uy, double *f, int64_t np,
     double px = pos[2 * k], py = pos[2 * k + 1];
     double uk_x = orc_interp(p, ugx, px, py);
     double uk_y = orc_interp(p, ugy, px, py);
+    if (out && out->upart) {
+      out->upart[2 * k] = uk_x;
+      out->upart[2 * k + 1] = uk_y;
+    }
     double ek = orc_interp(p, es3, px, py); /* solid fraction 1 - eps_k (R13) */
     double bk = orc_interp(p, beta, px, py);
     gpk[2 * k] = orc_interp(p, gx, px, py);
@@ -813,6 +819,7 @@ int orc_step(const orc_params *p, const double *inlet_uy, double *f, int64_t np,
     if (out->fpg) memcpy(out->fpg, fpg, (size_t)(2 * C) * sizeof(double));
     if (out->beta) memcpy(out->beta, beta, (size_t)C * sizeof(double));
     if (out->fd && np > 0) memcpy(out->fd, fd, NP * 2 * sizeof(double));
+    if (out->fpre && np > 0) memcpy(out->fpre, fpre, NP * 2 * sizeof(double));
     out->npairs = npairs;
     out->ncollisions = ncoll;
     out->nwall = nwall;

@@ -81,27 +81,35 @@ template <> struct Prec<PREC_BF16DEV> {
   static constexpr bool global_pos = false;
 };
 
+// Stored population value: f_i itself in FP64; in the reduced precisions the
+// deviation g_i = f_i - w_i from the lattice weight, so that moments of
+// populations close to the weights keep their digits in single precision.
+template <int P> constexpr bool kDev = P != PREC_FP64;
+
 template <int P>
-__device__ __forceinline__ typename Prec<P>::T load_pop(const typename Prec<P>::S *f, size_t idx, int i) {
-  using T = typename Prec<P>::T;
-  if constexpr (P == PREC_FP64 || P == PREC_FP32) {
-    return f[idx];
-  } else if constexpr (P == PREC_FP16DEV) {
-    return wgt<T>(i) + (T)f[idx];
-  } else {
-    return wgt<T>(i) + bf16_to_f32(f[idx]);
-  }
+__device__ __forceinline__ typename Prec<P>::T load_v(const typename Prec<P>::S *f, size_t idx) {
+  if constexpr (P == PREC_FP64 || P == PREC_FP32) return f[idx];
+  else if constexpr (P == PREC_FP16DEV) return (float)f[idx];
+  else return bf16_to_f32(f[idx]);
 }
 
 template <int P>
-__device__ __forceinline__ void store_pop(typename Prec<P>::S *f, size_t idx, int i, typename Prec<P>::T v) {
-  if constexpr (P == PREC_FP64 || P == PREC_FP32) {
-    f[idx] = v;
-  } else if constexpr (P == PREC_FP16DEV) {
-    f[idx] = (_Float16)(v - wgt<float>(i));
-  } else {
-    f[idx] = f32_to_bf16(v - wgt<float>(i));
-  }
+__device__ __forceinline__ void store_v(typename Prec<P>::S *f, size_t idx, typename Prec<P>::T v) {
+  if constexpr (P == PREC_FP64 || P == PREC_FP32) f[idx] = v;
+  else if constexpr (P == PREC_FP16DEV) f[idx] = (_Float16)v;  // round to nearest even
+  else f[idx] = f32_to_bf16(v);
+}
+
+// Population i as FP64 f_i (canonical value).
+template <int P> __device__ __forceinline__ double to_f64(const typename Prec<P>::S *f, size_t idx, int i) {
+  if constexpr (kDev<P>) return wgt<double>(i) + (double)load_v<P>(f, idx);
+  else return (double)f[idx];
+}
+
+template <int P> __device__ __forceinline__ void from_f64(typename Prec<P>::S *f, size_t idx, int i, double v) {
+  using T = typename Prec<P>::T;
+  if constexpr (kDev<P>) store_v<P>(f, idx, (T)(v - wgt<double>(i)));
+  else f[idx] = v;
 }
 
 // Scalar constants of a context, in the arithmetic type.

@@ -21,6 +21,21 @@ __device__ __forceinline__ T feq(int i, T rho, T ux, T uy) {
   return wgt<T>(i) * rho * ((T)1.0 + (T)3.0 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
 }
 
+// Equilibrium in the stored form: f^eq_i (FP64), or f^eq_i - w_i =
+// w_i ((rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)) in the deviation modes.
+template <int P>
+__device__ __forceinline__ typename Prec<P>::T feq_v(int i, typename Prec<P>::T rho, typename Prec<P>::T rho1,
+                                                     typename Prec<P>::T ux, typename Prec<P>::T uy) {
+  using T = typename Prec<P>::T;
+  if constexpr (kDev<P>) {
+    T cu = (T)cx_of(i) * ux + (T)cy_of(i) * uy;
+    T uu = ux * ux + uy * uy;
+    return wgt<T>(i) * (rho1 + rho * ((T)3.0 * cu + (T)4.5 * cu * cu - (T)1.5 * uu));
+  } else {
+    return feq<T>(i, rho, ux, uy);
+  }
+}
+
 __device__ __forceinline__ int wrap_i(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // Node index for interpolation and gradients: wrap on periodic axes, clamp
@@ -266,9 +281,9 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
   const int x = c % k.nx, y = c / k.nx;
   const size_t C = (size_t)k.C;
 
-  T f[Q];
+  T f[Q];  // f_i (FP64) or g_i = f_i - w_i
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = load_pop<P>(fsrc, i * C + c, i);
+  for (int i = 0; i < Q; ++i) f[i] = load_v<P>(fsrc, i * C + c);
 
   // Eq. 8: n_tot and v_s, summed in ascending particle index.
   const int a0 = cs[c], a1 = cs[c + 1];
@@ -285,9 +300,15 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
   }
   const T *L = lut + (size_t)min(n, k.nlut - 1) * LUT_W;
 
-  T rho = (T)0, jx = (T)0, jy = (T)0;
+  T rho = (T)0, rho1 = (T)0, jx = (T)0, jy = (T)0;
+  if constexpr (kDev<P>) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) rho += f[i];
+    for (int i = 0; i < Q; ++i) rho1 += f[i];
+    rho = (T)1.0 + rho1;
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) rho += f[i];
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) jx += (T)cx_of(i) * f[i];
 #pragma unroll
@@ -295,9 +316,10 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
   const T ux = jx / rho, uy = jy / rho;
   T fu[Q], oms[Q], fs[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) fu[i] = feq<T>(i, rho, ux, uy);
+  for (int i = 0; i < Q; ++i) fu[i] = feq_v<P>(i, rho, rho1, ux, uy);
+  // Eq. 7 (the weights cancel between f_-i and f_i, so the same form holds for deviations)
 #pragma unroll
-  for (int i = 0; i < Q; ++i) oms[i] = f[opp9(i)] - f[i] + feq<T>(i, rho, vsx, vsy) - fu[opp9(i)];
+  for (int i = 0; i < Q; ++i) oms[i] = f[opp9(i)] - f[i] + feq_v<P>(i, rho, rho1, vsx, vsy) - fu[opp9(i)];
   const T omg = L[L_OMG], relax = L[L_RELAX];
 #pragma unroll
   for (int i = 0; i < Q; ++i) fs[i] = f[i] - relax * (f[i] - fu[i]) + omg * oms[i] + k.src[i];
@@ -322,7 +344,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
   } else {
     beta = L[L_D1] + L[L_D2] * slip / k.d;
   }
-  fl.rho[c] = rho;
+  fl.rho[c] = kDev<P> ? rho1 : rho;  // the deviation modes keep rho - 1
   fl.ugx[c] = ugx;
   fl.ugy[c] = ugy;
   fl.beta[c] = beta;
@@ -340,7 +362,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
     int tx = x + cx_of(i), ty = y + cy_of(i);
     if (tx < 0 || tx >= k.nx) {
       if (!k.per_x) {  // halfway bounce-back: returns as the opposite population
-        store_pop<P>(fdst, opp9(i) * C + c, opp9(i), fs[i]);
+        store_v<P>(fdst, opp9(i) * C + c, fs[i]);
         continue;
       }
       tx = wrap_i(tx, k.nx);
@@ -350,13 +372,13 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
       if (face == BC_PERIODIC) {
         ty = wrap_i(ty, k.ny);
       } else if (face == BC_WALL) {
-        store_pop<P>(fdst, opp9(i) * C + c, opp9(i), fs[i]);
+        store_v<P>(fdst, opp9(i) * C + c, fs[i]);
         continue;
       } else {
         continue;  // leaves through an inlet or outlet face
       }
     }
-    store_pop<P>(fdst, i * C + (size_t)ty * k.nx + tx, i, fs[i]);
+    store_v<P>(fdst, i * C + (size_t)ty * k.nx + tx, fs[i]);
   }
   // Populations entering through an inlet or outlet face.
   if ((y == 0 && k.bc_ylo >= BC_INLET) || (y == k.ny - 1 && k.bc_yhi >= BC_INLET)) {
@@ -369,7 +391,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
         // f_i(x) = f^eq_i(1, (0, u_in(x))) unless its source lies beyond an x wall
         const int sxn = x - cx_of(i);
         if ((sxn < 0 || sxn >= k.nx) && !k.per_x) continue;
-        store_pop<P>(fdst, i * C + c, i, feq<T>(i, (T)1.0, (T)0.0, inlet[x]));
+        store_v<P>(fdst, i * C + c, feq_v<P>(i, (T)1.0, (T)0.0, (T)0.0, inlet[x]));
       } else {
         // zero gradient: this boundary node also feeds its own row
         int tx = x + cx_of(i);
@@ -377,7 +399,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
           if (!k.per_x) continue;
           tx = wrap_i(tx, k.nx);
         }
-        store_pop<P>(fdst, i * C + (size_t)y * k.nx + tx, i, fs[i]);
+        store_v<P>(fdst, i * C + (size_t)y * k.nx + tx, fs[i]);
       }
     }
   }
@@ -834,7 +856,7 @@ __global__ __launch_bounds__(BLOCK) void k_cons_cells(const typename Prec<P>::S 
   for (int c = blockIdx.x * BLOCK + threadIdx.x; c < C; c += gridDim.x * BLOCK) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const double v = (double)load_pop<P>(f, (size_t)i * C + c, i);
+      const double v = to_f64<P>(f, (size_t)i * C + c, i);
       bad |= !isfinite(v);
       m += v;
       px += (double)cx_of(i) * v;
@@ -893,9 +915,7 @@ __global__ __launch_bounds__(BLOCK) void k_set_f(const double *__restrict__ fin,
   const long long e = (long long)blockIdx.x * BLOCK + threadIdx.x;
   if (e >= (long long)Q * C) return;
   const int i = (int)(e / C);
-  using T = typename Prec<P>::T;
-  const T v = fin ? (T)fin[e] : wgt<T>(i);
-  store_pop<P>(f, (size_t)e, i, v);
+  from_f64<P>(f, (size_t)e, i, fin ? fin[e] : wgt<double>(i));
 }
 
 template <int P>
@@ -903,7 +923,7 @@ __global__ __launch_bounds__(BLOCK) void k_get_f(const typename Prec<P>::S *__re
                                                  int C) {
   const long long e = (long long)blockIdx.x * BLOCK + threadIdx.x;
   if (e >= (long long)Q * C) return;
-  out[e] = (double)load_pop<P>(f, (size_t)e, (int)(e / C));
+  out[e] = to_f64<P>(f, (size_t)e, (int)(e / C));
 }
 
 template <int P>
@@ -989,14 +1009,14 @@ __global__ __launch_bounds__(BLOCK) void k_get_parts(Parts<typename Prec<P>::T> 
 
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_get_field(const T *__restrict__ a, const T *__restrict__ b, int C,
-                                                     double *out) {
+                                                     double *out, double add) {
   const int c = blockIdx.x * BLOCK + threadIdx.x;
   if (c >= C) return;
   if (b) {
     out[2 * c] = (double)a[c];
     out[2 * c + 1] = (double)b[c];
   } else {
-    out[c] = (double)a[c];
+    out[c] = add + (double)a[c];
   }
 }
 

@@ -382,9 +382,9 @@ template <int P> struct Impl {
                        x->p.diagnostics ? fd : nullptr);
   }
 
-  static void get_field2(lbdps_ctx *x, const void *a, const void *b, double *out) {
+  static void get_field2(lbdps_ctx *x, const void *a, const void *b, double *out, double add = 0.0) {
     hipLaunchKernelGGL(k_get_field<T>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, (const T *)a, (const T *)b,
-                       x->C, out);
+                       x->C, out, add);
   }
 
   static void get_f(lbdps_ctx *x, double *out) {
@@ -570,7 +570,7 @@ lbdps_status lbdps_get_fields(lbdps_ctx *x, double *d_rho, double *d_ugas, doubl
   if ((d_ncell || d_vs) && !x->p.diagnostics) return fail(LBDPS_E_INVALID, "n_tot and v_s need diagnostics on");
   lbdps_status st = dispatch(x, [&](auto impl) {
     using I = decltype(impl);
-    if (d_rho) I::get_field2(x, x->fld[0], nullptr, d_rho);
+    if (d_rho) I::get_field2(x, x->fld[0], nullptr, d_rho, x->prec == PREC_FP64 ? 0.0 : 1.0);
     if (d_ugas) I::get_field2(x, x->fld[1], x->fld[2], d_ugas);
     if (d_fpg) I::get_field2(x, x->fld[4], x->fld[5], d_fpg);
     if (d_beta) I::get_field2(x, x->fld[3], nullptr, d_beta);
