@@ -187,6 +187,31 @@ lbdps_status lbdps_conservation(lbdps_ctx *ctx, double h_out[6]);
  */
 lbdps_status lbdps_counters(lbdps_ctx *ctx, int64_t h_out[4]);
 
+/* Kernels of one step, for per-kernel timing. */
+typedef enum {
+  LBDPS_K_COLLIDE = 0,    /* deposition + collision + streaming                     */
+  LBDPS_K_DRAG = 1,       /* drag, integration, and the per-cell count of new cells  */
+  LBDPS_K_SCAN = 2,       /* prefix sum of the cell counts                           */
+  LBDPS_K_SCATTER = 3,    /* particle records -> their cell's slots                  */
+  LBDPS_K_CONTACTS = 4,   /* contact detection, wall collisions of contact-free particles */
+  LBDPS_K_RESOLVE = 5,    /* binary collisions, then the remaining wall collisions   */
+  LBDPS_K_COUNT = 6
+} lbdps_kernel;
+
+/*
+ * Bracket every later launch of the kernels in `mask` (bit k = lbdps_kernel k)
+ * with a pair of hipEvents on the context's stream; mask 0 stops.  For
+ * measurement only: the events add a little work to the stream.
+ */
+lbdps_status lbdps_time_kernels(lbdps_ctx *ctx, uint32_t mask);
+
+/*
+ * Wait for the stream, then return per kernel the summed event time in
+ * milliseconds (h_ms[LBDPS_K_COUNT]) and the number of timed launches
+ * (h_launches[LBDPS_K_COUNT]) since the previous call, and reset both.
+ */
+lbdps_status lbdps_kernel_times(lbdps_ctx *ctx, double *h_ms, int64_t *h_launches);
+
 /* Release the host context (the workspace stays the caller's). */
 lbdps_status lbdps_destroy(lbdps_ctx *ctx);
 

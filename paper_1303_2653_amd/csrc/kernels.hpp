@@ -87,8 +87,21 @@ template <int P> struct Pos {
     }
   }
 
-  // Bilinear stencil origin (i0, j0) and fractions (tx, ty) for s = P - (1/2, 1/2).
-  __device__ static void stencil(const Consts<T> &k, int key, T x, T y, int &i0, int &j0, T &tx, T &ty) {
+  // Separation a - b for b in the cell (ox, oy) away from a's cell (|ox|, |oy| <= 1
+  // after the periodic wrap, so the minimum-image cell difference is -ox, -oy).
+  __device__ static void sep_nb(const Consts<T> &k, int ox, int oy, T xa, T ya, T xb, T yb, T &dx, T &dy) {
+    if constexpr (G) {
+      sep(k, 0, xa, ya, 0, xb, yb, dx, dy);
+    } else {
+      T o1 = xa - xb, o2 = ya - yb;
+      dx = (T)(-ox) + o1;
+      dy = (T)(-oy) + o2;
+    }
+  }
+
+  // Bilinear stencil origin (i0, j0) and fractions (tx, ty) for s = P - (1/2, 1/2);
+  // (cx, cy) is the particle's cell.
+  __device__ static void stencil(const Consts<T> &k, int cx, int cy, T x, T y, int &i0, int &j0, T &tx, T &ty) {
     if constexpr (G) {
       T sx = x - (T)0.5, sy = y - (T)0.5;
       T fx = floor(sx), fy = floor(sy);
@@ -97,7 +110,6 @@ template <int P> struct Pos {
       i0 = (int)fx;
       j0 = (int)fy;
     } else {
-      int cx = key % k.nx, cy = key / k.nx;
       if (x >= (T)0.5) {
         i0 = cx;
         tx = x - (T)0.5;
@@ -118,7 +130,7 @@ template <int P> struct Pos {
   // Move by v (P <- P + v), then periodic wrap or wall mirror.  Returns the new
   // cell key, or -1 if the result is not a valid cell (NaN, or a jump across
   // the whole domain).
-  __device__ static int move(const Consts<T> &k, int key, T &x, T &y, T vx, T vy) {
+  __device__ static int move(const Consts<T> &k, int cx, int cy, T &x, T &y, T vx, T vy) {
     if constexpr (G) {
       T X = x + vx, Y = y + vy;
       X = k.per_x ? wrap_c(X, (T)k.nx) : mirror_c(X, (T)k.nx);
@@ -129,7 +141,6 @@ template <int P> struct Pos {
       if (!(fx >= (T)0 && fx < (T)k.nx && fy >= (T)0 && fy < (T)k.ny)) return -1;
       return (int)fy * k.nx + (int)fx;
     } else {
-      int cx = key % k.nx, cy = key / k.nx;
       T ox = x + vx, oy = y + vy;
       renorm(ox, cx);
       renorm(oy, cy);
@@ -205,7 +216,7 @@ template <int P> struct Pos {
   // Particle-wall collisions on non-periodic axes (walls as infinitely heavy
   // particles, Sec. 2.2): within r of a wall and moving into it, v_n -> -e_w v_n.
   // Faces in the order x-, x+, y-, y+.
-  __device__ static int walls(const Consts<T> &k, int key, T x, T y, T &vx, T &vy) {
+  __device__ static int walls(const Consts<T> &k, int cx, int cy, T x, T y, T &vx, T &vy) {
     int hits = 0;
     bool lx, rx, ly, ry;
     if constexpr (G) {
@@ -214,7 +225,6 @@ template <int P> struct Pos {
       ly = y <= k.r;
       ry = (T)k.ny - y <= k.r;
     } else {
-      int cx = key % k.nx, cy = key / k.nx;
       lx = cx == 0 && x <= k.r;
       rx = cx == k.nx - 1 && (T)1 - x <= k.r;
       ly = cy == 0 && y <= k.r;
@@ -244,6 +254,43 @@ template <int P> struct Pos {
   }
 };
 
+// Generic three-pass scan: SCAN_ITEMS per thread.
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
+// Cell-start scan: tiles of SCAN_TILE = 2^shift cells.  The per-tile particle
+// counts of the next binning are accumulated while the new cells are counted
+// (one atomic per workgroup and tile).
+struct TileSums {
+  int32_t *tile;
+  int ntiles, shift;
+  __device__ void add(int t, int v) const { atomicAdd(&tile[t], v); }
+};
+
+constexpr int SEG_REG = 4;                    // cell segments up to this length stay in registers
+constexpr int CONTACT_REG = 6;                // contacts per particle collected in registers first
+constexpr int RES_ITEMS = 8;                  // particle indices per lane and resolution chunk
+constexpr int RES_CHUNK = BLOCK * RES_ITEMS;  // particle indices per chunk
+
+// Block-wide exclusive scan of one int per thread; total = block sum.
+__device__ __forceinline__ int block_excl_scan(int v, int *sh, int &total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) sh[wv] = inc;
+  __syncthreads();
+  int base = 0;
+  total = 0;
+  for (int w = 0; w < BLOCK / 64; ++w) {
+    if (w < wv) base += sh[w];
+    total += sh[w];
+  }
+  __syncthreads();
+  return base + inc - v;
+}
+
 // Block-wide sum of a 64-bit integer (BLOCK threads), result valid in thread 0.
 __device__ __forceinline__ long long block_sum_ll(long long v, long long *sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -269,8 +316,7 @@ template <int P>
 __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__restrict__ fsrc,
                                                    typename Prec<P>::S *__restrict__ fdst,
                                                    Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs,
-                                                   const typename Prec<P>::T *__restrict__ pvx,
-                                                   const typename Prec<P>::T *__restrict__ pvy,
+                                                   Parts<typename Prec<P>::T> pt,
                                                    const typename Prec<P>::T *__restrict__ lut,
                                                    const typename Prec<P>::T *__restrict__ inlet,
                                                    Consts<typename Prec<P>::T> k, int32_t *dg_n,
@@ -285,13 +331,92 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
 #pragma unroll
   for (int i = 0; i < Q; ++i) f[i] = load_v<P>(fsrc, i * C + c);
 
-  // Eq. 8: n_tot and v_s, summed in ascending particle index.
+  // The binning leaves each cell's particles in arrival order: put the
+  // segment in ascending particle index (a segment already in order is only
+  // read).  Later stages of this step sum over the segment in that order.
+  // Up to SEG_REG particles are handled in registers, longer segments by an
+  // insertion sort of the records in memory.
   const int a0 = cs[c], a1 = cs[c + 1];
   const int n = a1 - a0;
   T sx = (T)0, sy = (T)0;
-  for (int s = a0; s < a1; ++s) {
-    sx += pvx[s];
-    sy += pvy[s];
+  if (n <= SEG_REG) {
+    int id[SEG_REG];
+    T px[SEG_REG], py[SEG_REG], vx[SEG_REG], vy[SEG_REG];
+#pragma unroll
+    for (int u = 0; u < SEG_REG; ++u)
+      if (u < n) {
+        id[u] = pt.pid[a0 + u];
+        px[u] = pt.px[a0 + u];
+        py[u] = pt.py[a0 + u];
+        vx[u] = pt.vx[a0 + u];
+        vy[u] = pt.vy[a0 + u];
+      }
+    bool moved = false;
+#pragma unroll
+    for (int pass = 0; pass < SEG_REG - 1; ++pass)
+#pragma unroll
+      for (int q = 0; q < SEG_REG - 1; ++q)
+        if (q + 1 < n && id[q] > id[q + 1]) {
+          int ti = id[q];
+          id[q] = id[q + 1];
+          id[q + 1] = ti;
+          T t0 = px[q];
+          px[q] = px[q + 1];
+          px[q + 1] = t0;
+          t0 = py[q];
+          py[q] = py[q + 1];
+          py[q + 1] = t0;
+          t0 = vx[q];
+          vx[q] = vx[q + 1];
+          vx[q + 1] = t0;
+          t0 = vy[q];
+          vy[q] = vy[q + 1];
+          vy[q + 1] = t0;
+          moved = true;
+        }
+    if (moved) {
+#pragma unroll
+      for (int u = 0; u < SEG_REG; ++u)
+        if (u < n) {
+          pt.pid[a0 + u] = id[u];
+          pt.px[a0 + u] = px[u];
+          pt.py[a0 + u] = py[u];
+          pt.vx[a0 + u] = vx[u];
+          pt.vy[a0 + u] = vy[u];
+        }
+    }
+    // Eq. 8: n_tot and v_s, summed in ascending particle index.
+#pragma unroll
+    for (int u = 0; u < SEG_REG; ++u)
+      if (u < n) {
+        sx += vx[u];
+        sy += vy[u];
+      }
+  } else {
+    for (int i = a0 + 1; i < a1; ++i) {
+      const int kv = pt.pid[i];
+      if (pt.pid[i - 1] <= kv) continue;
+      const T x0 = pt.px[i], y0 = pt.py[i], u0 = pt.vx[i], w0 = pt.vy[i];
+      int j = i - 1;
+      do {
+        pt.pid[j + 1] = pt.pid[j];
+        pt.px[j + 1] = pt.px[j];
+        pt.py[j + 1] = pt.py[j];
+        pt.vx[j + 1] = pt.vx[j];
+        pt.vy[j + 1] = pt.vy[j];
+        --j;
+      } while (j >= a0 && pt.pid[j] > kv);
+      pt.pid[j + 1] = kv;
+      pt.px[j + 1] = x0;
+      pt.py[j + 1] = y0;
+      pt.vx[j + 1] = u0;
+      pt.vy[j + 1] = w0;
+    }
+    // Eq. 8: n_tot and v_s, summed in ascending particle index.
+    for (int s = a0; s < a1; ++s) {
+      sx += pt.vx[s];
+      sy += pt.vy[s];
+    }
   }
   T vsx = (T)0, vsy = (T)0;
   if (n > 0) {
@@ -412,50 +537,59 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
 // the cell sum (Eq. 27).  Pass 2 distributes F_p->g with Eq. 28, integrates
 // Eq. 16 (symplectic Euler), moves, wraps or mirrors, and counts the particle
 // into its new cell for the next binning.
+// Node fields a workgroup's particles interpolate from, staged in LDS: the
+// workgroup covers a DTX x DTY tile of cells, and its particles' bilinear
+// stencils reach one node beyond it on every side.  Each slot holds the value
+// at the wrapped (periodic) or clamped (wall) node, and the node's pressure
+// gradient is formed from the node's own neighbours as in the global field.
+constexpr int DTX = 32, DTY = 8;
+constexpr int DSX = DTX + 2, DSY = DTY + 2, DSN = DSX * DSY;
+constexpr int HIST_MAX = 32;
+
+template <int P> struct DragTile {
+  using T = typename Prec<P>::T;
+  T ux[DSN], uy[DSN], es[DSN], beta[DSN], gpx[DSN], gpy[DSN];
+
+  __device__ void load(const Consts<T> &k, const Fields<T> &fl, const int32_t *cs, const T *lut, int tx0, int ty0) {
+    for (int q = threadIdx.x; q < DSN; q += BLOCK) {
+      const int i = node_idx(tx0 - 1 + q % DSX, k.nx, k.per_x);
+      const int j = node_idx(ty0 - 1 + q / DSX, k.ny, k.per_y);
+      const size_t c = (size_t)j * k.nx + i;
+      ux[q] = fl.ugx[c];
+      uy[q] = fl.ugy[c];
+      beta[q] = fl.beta[c];
+      es[q] = lut[(size_t)min(cs[c + 1] - cs[c], k.nlut - 1) * LUT_W + L_ES3];
+      // central differences of p = rho / 3, boundary value as the ghost beyond a wall
+      const int ie = node_idx(i + 1, k.nx, k.per_x), iw = node_idx(i - 1, k.nx, k.per_x);
+      const int jn = node_idx(j + 1, k.ny, k.per_y), js = node_idx(j - 1, k.ny, k.per_y);
+      gpx[q] = (fl.rho[(size_t)j * k.nx + ie] / (T)3.0 - fl.rho[(size_t)j * k.nx + iw] / (T)3.0) * (T)0.5;
+      gpy[q] = (fl.rho[(size_t)jn * k.nx + i] / (T)3.0 - fl.rho[(size_t)js * k.nx + i] / (T)3.0) * (T)0.5;
+    }
+  }
+};
+
+// Interpolated gas quantities at one particle (bilinear, Sec. 2.3 after Eq. 26).
 template <int P> struct Interp {
   using T = typename Prec<P>::T;
   T ux, uy, es, beta, gpx, gpy;
 
-  __device__ static T pnode(const T *rho, int i, int j, const Consts<T> &k) {
-    return rho[(size_t)j * k.nx + i] / (T)3.0;
-  }
-
-  __device__ void at(const Consts<T> &k, const Fields<T> &fl, const int32_t *cs, const T *lut, int key, T x, T y) {
+  __device__ void at(const Consts<T> &k, const DragTile<P> &D, int tx0, int ty0, int cx, int cy, T x, T y) {
     int i0, j0;
     T tx, ty;
-    Pos<P>::stencil(k, key, x, y, i0, j0, tx, ty);
-    const int ia = node_idx(i0, k.nx, k.per_x), ib = node_idx(i0 + 1, k.nx, k.per_x);
-    const int ja = node_idx(j0, k.ny, k.per_y), jb = node_idx(j0 + 1, k.ny, k.per_y);
-    const int ii[4] = {ia, ib, ia, ib}, jj[4] = {ja, ja, jb, jb};
+    Pos<P>::stencil(k, cx, cy, x, y, i0, j0, tx, ty);
+    const int q = (j0 - ty0 + 1) * DSX + (i0 - tx0 + 1);
+    const int qq[4] = {q, q + 1, q + DSX, q + DSX + 1};
     const T w[4] = {((T)1.0 - tx) * ((T)1.0 - ty), tx * ((T)1.0 - ty), ((T)1.0 - tx) * ty, tx * ty};
-    T q[6][4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const size_t c = (size_t)jj[m] * k.nx + ii[m];
-      q[0][m] = fl.ugx[c];
-      q[1][m] = fl.ugy[c];
-      const int nn = cs[c + 1] - cs[c];
-      q[2][m] = lut[(size_t)min(nn, k.nlut - 1) * LUT_W + L_ES3];
-      q[3][m] = fl.beta[c];
-      // node pressure gradient, central differences of p = rho / 3 with the
-      // boundary value as ghost beyond a non-periodic face
-      const int ie = node_idx(ii[m] + 1, k.nx, k.per_x), iw = node_idx(ii[m] - 1, k.nx, k.per_x);
-      const int jn = node_idx(jj[m] + 1, k.ny, k.per_y), js = node_idx(jj[m] - 1, k.ny, k.per_y);
-      q[4][m] = (pnode(fl.rho, ie, jj[m], k) - pnode(fl.rho, iw, jj[m], k)) * (T)0.5;
-      q[5][m] = (pnode(fl.rho, ii[m], jn, k) - pnode(fl.rho, ii[m], js, k)) * (T)0.5;
-    }
-    T r[6];
-#pragma unroll
-    for (int v = 0; v < 6; ++v) r[v] = w[0] * q[v][0] + w[1] * q[v][1] + w[2] * q[v][2] + w[3] * q[v][3];
-    ux = r[0];
-    uy = r[1];
-    es = r[2];
-    beta = r[3];
-    gpx = r[4];
-    gpy = r[5];
+    ux = w[0] * D.ux[qq[0]] + w[1] * D.ux[qq[1]] + w[2] * D.ux[qq[2]] + w[3] * D.ux[qq[3]];
+    uy = w[0] * D.uy[qq[0]] + w[1] * D.uy[qq[1]] + w[2] * D.uy[qq[2]] + w[3] * D.uy[qq[3]];
+    es = w[0] * D.es[qq[0]] + w[1] * D.es[qq[1]] + w[2] * D.es[qq[2]] + w[3] * D.es[qq[3]];
+    beta = w[0] * D.beta[qq[0]] + w[1] * D.beta[qq[1]] + w[2] * D.beta[qq[2]] + w[3] * D.beta[qq[3]];
+    gpx = w[0] * D.gpx[qq[0]] + w[1] * D.gpx[qq[1]] + w[2] * D.gpx[qq[2]] + w[3] * D.gpx[qq[3]];
+    gpy = w[0] * D.gpy[qq[0]] + w[1] * D.gpy[qq[1]] + w[2] * D.gpy[qq[2]] + w[3] * D.gpy[qq[3]];
   }
 };
 
+// Workgroup = one DTX x DTY tile of cells, one thread per cell.
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
                                                 const int32_t *__restrict__ cs,
@@ -463,31 +597,45 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
                                                 Consts<typename Prec<P>::T> k, int32_t *__restrict__ count,
                                                 int32_t *__restrict__ rank, int32_t *flags,
                                                 typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy,
-                                                long long *zero_part) {
+                                                long long *zero_part, TileSums ts) {
   using T = typename Prec<P>::T;
   __shared__ long long sh[BLOCK / 64];
-  const int c = blockIdx.x * BLOCK + threadIdx.x;
+  __shared__ int hist[HIST_MAX];
+  __shared__ DragTile<P> D;
+  __shared__ int s_occupied;
+  const int ntx = (k.nx + DTX - 1) / DTX;
+  const int tx0 = (blockIdx.x % ntx) * DTX, ty0 = (blockIdx.x / ntx) * DTY;
+  // a tile without particles has nothing to do (its rows' particle ranges are empty)
+  if (threadIdx.x == 0) s_occupied = 0;
+  __syncthreads();
+  if (threadIdx.x < DTY && ty0 + (int)threadIdx.x < k.ny) {
+    const int rb = (ty0 + (int)threadIdx.x) * k.nx;
+    if (cs[rb + min(tx0 + DTX, k.nx)] > cs[rb + tx0]) s_occupied = 1;
+  }
+  __syncthreads();
+  if (!s_occupied) {
+    if (zero_part && threadIdx.x == 0) zero_part[blockIdx.x] = 0;
+    return;
+  }
+  D.load(k, fl, cs, lut, tx0, ty0);
+  // scan tiles the new cells of this tile's particles can fall in (one cell
+  // move at most, periodic jumps go straight to the global counters)
+  const int klo = max(0, (ty0 - 1) * k.nx + tx0 - 1);
+  const int khi = min(k.C - 1, (ty0 + DTY) * k.nx + tx0 + DTX);
+  const int tlo = klo >> ts.shift, nh = (khi >> ts.shift) - tlo + 1;
+  if (threadIdx.x < HIST_MAX) hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int cx = tx0 + (int)threadIdx.x % DTX, cy = ty0 + (int)threadIdx.x / DTX;
+  const int c = cy * k.nx + cx;
   long long nzero = 0;
-  if (c < k.C) {
+  if (cx < k.nx && cy < k.ny) {
     const int a0 = cs[c], a1 = cs[c + 1];
     const int n = a1 - a0;
     if (n > 0) {
       const T fgx = fl.fpgx[c], fgy = fl.fpgy[c];
-      T Sx = (T)0, Sy = (T)0;
-      for (int s = a0; s < a1; ++s) {
-        Interp<P> I;
-        I.at(k, fl, cs, lut, pt.key[s], pt.px[s], pt.py[s]);
-        Sx += k.vp * I.beta / I.es * (I.ux - pt.vx[s]);
-        Sy += k.vp * I.beta / I.es * (I.uy - pt.vy[s]);
-      }
-      nzero = (Sx == (T)0) + (Sy == (T)0);
-      for (int s = a0; s < a1; ++s) {
-        Interp<P> I;
-        const int key = pt.key[s];
-        T x = pt.px[s], y = pt.py[s], vx = pt.vx[s], vy = pt.vy[s];
-        I.at(k, fl, cs, lut, key, x, y);
-        const T prx = k.vp * I.beta / I.es * (I.ux - vx);
-        const T pry = k.vp * I.beta / I.es * (I.uy - vy);
+      // Eq. 28 for one particle, then Eq. 16: v <- v + g_eff + (F_d + s V_p grad p) / m,
+      // P <- P + v, and the particle's new cell.
+      auto finish = [&](int s, T prx, T pry, T gpx, T gpy, T Sx, T Sy, T x, T y, T vx, T vy) -> int {
         T fdx, fdy;
         if (Sx == (T)0)
           fdx = -fgx / (T)n;
@@ -501,29 +649,91 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
           fdy = fabs(fgy) / fabs(Sy) * pry;
         else
           fdy = -fgy * pry / Sy;
-        // Eq. 16: v <- v + g_eff + (F_d + s V_p grad p) / m;  P <- P + v
-        const T ax = k.geff[0] + (fdx + k.fp * I.gpx) / k.m;
-        const T ay = k.geff[1] + (fdy + k.fp * I.gpy) / k.m;
+        const T ax = k.geff[0] + (fdx + k.fp * gpx) / k.m;
+        const T ay = k.geff[1] + (fdy + k.fp * gpy) / k.m;
         vx = vx + ax;
         vy = vy + ay;
-        int nk = Pos<P>::move(k, key, x, y, vx, vy);
+        int nk = Pos<P>::move(k, cx, cy, x, y, vx, vy);
         if (nk < 0) {
           atomicOr(&flags[FLAG_DOMAIN], 1);
-          nk = key;
+          nk = c;
         }
         pt.key[s] = nk;
         pt.px[s] = x;
         pt.py[s] = y;
         pt.vx[s] = vx;
         pt.vy[s] = vy;
-        rank[s] = atomicAdd(&count[nk], 1);
         if (dg_fdx) {
           const int id = pt.pid[s];
           dg_fdx[id] = fdx;
           dg_fdy[id] = fdy;
         }
+        return nk;
+      };
+      auto count_new = [&](int s, int nk) {
+        rank[s] = atomicAdd(&count[nk], 1);
+        const int dt = (nk >> ts.shift) - tlo;
+        if (nh <= HIST_MAX && dt >= 0 && dt < nh)
+          atomicAdd(&hist[dt], 1);
+        else
+          ts.add(nk >> ts.shift, 1);
+      };
+      if (n <= SEG_REG) {  // short segment: particle data and pre-drags in registers
+        T x[SEG_REG], y[SEG_REG], vx[SEG_REG], vy[SEG_REG];
+        T prx[SEG_REG], pry[SEG_REG], gpx[SEG_REG], gpy[SEG_REG];
+        int nk[SEG_REG];
+#pragma unroll
+        for (int u = 0; u < SEG_REG; ++u)
+          if (u < n) {
+            x[u] = pt.px[a0 + u];
+            y[u] = pt.py[a0 + u];
+            vx[u] = pt.vx[a0 + u];
+            vy[u] = pt.vy[a0 + u];
+          }
+        T Sx = (T)0, Sy = (T)0;
+#pragma unroll
+        for (int u = 0; u < SEG_REG; ++u)
+          if (u < n) {
+            Interp<P> I;
+            I.at(k, D, tx0, ty0, cx, cy, x[u], y[u]);
+            prx[u] = k.vp * I.beta / I.es * (I.ux - vx[u]);
+            pry[u] = k.vp * I.beta / I.es * (I.uy - vy[u]);
+            gpx[u] = I.gpx;
+            gpy[u] = I.gpy;
+            Sx += prx[u];
+            Sy += pry[u];
+          }
+        nzero = (Sx == (T)0) + (Sy == (T)0);
+#pragma unroll
+        for (int u = 0; u < SEG_REG; ++u)
+          if (u < n) nk[u] = finish(a0 + u, prx[u], pry[u], gpx[u], gpy[u], Sx, Sy, x[u], y[u], vx[u], vy[u]);
+#pragma unroll
+        for (int u = 0; u < SEG_REG; ++u)
+          if (u < n) count_new(a0 + u, nk[u]);
+      } else {
+        T Sx = (T)0, Sy = (T)0;
+        for (int s = a0; s < a1; ++s) {
+          Interp<P> I;
+          I.at(k, D, tx0, ty0, cx, cy, pt.px[s], pt.py[s]);
+          Sx += k.vp * I.beta / I.es * (I.ux - pt.vx[s]);
+          Sy += k.vp * I.beta / I.es * (I.uy - pt.vy[s]);
+        }
+        nzero = (Sx == (T)0) + (Sy == (T)0);
+        for (int s = a0; s < a1; ++s) {
+          Interp<P> I;
+          const T x = pt.px[s], y = pt.py[s], vx = pt.vx[s], vy = pt.vy[s];
+          I.at(k, D, tx0, ty0, cx, cy, x, y);
+          const T prx = k.vp * I.beta / I.es * (I.ux - vx);
+          const T pry = k.vp * I.beta / I.es * (I.uy - vy);
+          count_new(s, finish(s, prx, pry, I.gpx, I.gpy, Sx, Sy, x, y, vx, vy));
+        }
       }
     }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < min(nh, HIST_MAX)) {
+    const int h = hist[threadIdx.x];
+    if (h) ts.add(tlo + (int)threadIdx.x, h);
   }
   if (zero_part) {
     const long long t = block_sum_ll(nzero, sh);
@@ -539,112 +749,159 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const int32_t *__restrict__ key, 
   if (s < n) rank[s] = atomicAdd(&count[key[s]], 1);
 }
 
-// perm[cell_start[key] + rank] = slot.
-__global__ __launch_bounds__(BLOCK) void k_scatter(const int32_t *__restrict__ key, const int32_t *__restrict__ rank,
-                                                   const int32_t *__restrict__ cs, int n, int32_t *__restrict__ perm) {
-  const int s = blockIdx.x * BLOCK + threadIdx.x;
-  if (s < n) perm[cs[key[s]] + rank[s]] = s;
-}
-
-// One thread per cell: order the cell's segment by particle index (the atomic
-// counter leaves it in arrival order), then gather the particle records into
-// the new storage so each cell's particles are contiguous and ascending.
+// Move every particle record to its slot cell_start[key] + rank in the other
+// storage and record the slot of each particle index.  Clears the tile sums
+// for the next binning.
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_sortgather(const int32_t *__restrict__ cs, int32_t *__restrict__ perm,
-                                                      Parts<T> src, Parts<T> dst, int32_t *__restrict__ slot, int C) {
-  const int c = blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= C) return;
-  const int a0 = cs[c], a1 = cs[c + 1];
-  for (int i = a0 + 1; i < a1; ++i) {
-    const int v = perm[i];
-    const int kv = src.pid[v];
-    int j = i - 1;
-    while (j >= a0 && src.pid[perm[j]] > kv) {
-      perm[j + 1] = perm[j];
-      --j;
-    }
-    perm[j + 1] = v;
-  }
-  for (int s = a0; s < a1; ++s) {
-    const int o = perm[s];
-    const int id = src.pid[o];
-    dst.key[s] = src.key[o];
-    dst.pid[s] = id;
-    dst.px[s] = src.px[o];
-    dst.py[s] = src.py[o];
-    dst.vx[s] = src.vx[o];
-    dst.vy[s] = src.vy[o];
-    slot[id] = s;
-  }
+__global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, const int32_t *__restrict__ rank,
+                                                   const int32_t *__restrict__ cs, int n, int32_t *__restrict__ slot,
+                                                   TileSums ts) {
+  const int s = blockIdx.x * BLOCK + threadIdx.x;
+  for (int i = s; i < ts.ntiles; i += gridDim.x * BLOCK) ts.tile[i] = 0;
+  if (s >= n) return;
+  const int key = src.key[s];
+  const int d = cs[key] + rank[s];
+  const int id = src.pid[s];
+  dst.key[d] = key;
+  dst.pid[d] = id;
+  dst.px[d] = src.px[s];
+  dst.py[d] = src.py[s];
+  dst.vx[d] = src.vx[s];
+  dst.vy[d] = src.vy[s];
+  slot[id] = d;
 }
 
 // ------------------------------------------------------------------ A6: contact detection
 // One thread per particle slot.  Candidates come from the 3x3 cells around the
 // particle (d < 1 cell); a contact is a centre distance <= d (Sec. 2.2), with
-// the periodic minimum image.  Each particle keeps its full neighbour list
-// sorted by particle index, as 64-bit entries (index << 32 | slot).
+// the periodic minimum image.  Away from a periodic seam the three cells of a
+// neighbour row are one contiguous slot range, and a candidate's column offset
+// follows from the cell starts.  Each particle keeps its full neighbour list
+// sorted by particle index, as 64-bit entries (index << 32 | slot).  A particle
+// without contacts gets its wall collision here; the others get it after their
+// binary collisions.
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
                                                     Consts<typename Prec<P>::T> k, long long *__restrict__ adj,
                                                     int32_t *__restrict__ deg, int32_t *__restrict__ done,
-                                                    int32_t *ticket, int32_t *flags, long long *pair_part) {
+                                                    int32_t *ticket, int32_t *flags, long long *pair_part,
+                                                    long long *wall_part, int32_t *__restrict__ chunk_busy,
+                                                    int32_t *need_sweep) {
   using T = typename Prec<P>::T;
   __shared__ long long sh[BLOCK / 64];
   const int s = blockIdx.x * BLOCK + threadIdx.x;
-  long long fwd = 0;
-  if (s == 0) *ticket = 0;
+  long long fwd = 0, nwall = 0;
+  if (s == 0) {
+    *ticket = 0;
+    *need_sweep = 0;
+  }
   if (s < k.npart) {
     const int key = pt.key[s];
     const int id = pt.pid[s];
     const T x = pt.px[s], y = pt.py[s];
-    const int cx = key % k.nx, cy = key / k.nx;
+    const int cy = key / k.nx, cx = key - cy * k.nx;
     const T dd = k.d * k.d;
     long long *row = adj + (size_t)s * KMAX;
+    // Pass 1 keeps the first CONTACT_REG contacts sorted in registers (no
+    // stores while scanning, so candidate loads overlap); a particle with more
+    // contacts is scanned again and its list built in memory.
+    long long r[CONTACT_REG];
     int cnt = 0;
     bool over = false;
-    for (int oy = -1; oy <= 1; ++oy) {
-      int yy = cy + oy;
-      if (yy < 0 || yy >= k.ny) {
-        if (!k.per_y) continue;
-        yy = wrap_i(yy, k.ny);
-      }
-      for (int ox = -1; ox <= 1; ++ox) {
-        int xx = cx + ox;
-        if (xx < 0 || xx >= k.nx) {
-          if (!k.per_x) continue;
-          xx = wrap_i(xx, k.nx);
+    auto scan = [&](auto &&hit) {
+      const bool inner_x = cx >= 1 && cx + 1 < k.nx;
+      for (int oy = -1; oy <= 1; ++oy) {
+        int yy = cy + oy;
+        if (yy < 0 || yy >= k.ny) {
+          if (!k.per_y) continue;
+          yy = wrap_i(yy, k.ny);
         }
-        const int nc = yy * k.nx + xx;
-        const int t0 = cs[nc], t1 = cs[nc + 1];
-        for (int t = t0; t < t1; ++t) {
-          if (t == s) continue;
+        const int rb = yy * k.nx;
+        auto test = [&](int t, int ox) {
+          if (t == s) return;
           T dx, dy;
-          Pos<P>::sep(k, key, x, y, pt.key[t], pt.px[t], pt.py[t], dx, dy);
-          if (dx * dx + dy * dy <= dd) {
-            const int tid = pt.pid[t];
-            if (tid > id) ++fwd;
-            if (cnt == KMAX) {
-              over = true;
-              continue;
+          Pos<P>::sep_nb(k, ox, oy, x, y, pt.px[t], pt.py[t], dx, dy);
+          if (dx * dx + dy * dy <= dd) hit(t);
+        };
+        if (inner_x) {
+          const int c0 = rb + cx - 1;
+          const int e0 = cs[c0], e1 = cs[c0 + 1], e2 = cs[c0 + 2], e3 = cs[c0 + 3];
+#pragma unroll 4
+          for (int t = e0; t < e3; ++t) test(t, t < e1 ? -1 : (t < e2 ? 0 : 1));
+        } else {
+          for (int ox = -1; ox <= 1; ++ox) {
+            int xx = cx + ox;
+            if (xx < 0 || xx >= k.nx) {
+              if (!k.per_x) continue;
+              xx = wrap_i(xx, k.nx);
             }
-            const long long e = ((long long)tid << 32) | (unsigned)t;
-            int j = cnt;
-            while (j > 0 && row[j - 1] > e) {
-              row[j] = row[j - 1];
-              --j;
-            }
-            row[j] = e;
-            ++cnt;
+            const int c = rb + xx;
+            for (int t = cs[c]; t < cs[c + 1]; ++t) test(t, ox);
           }
         }
       }
+    };
+    scan([&](int t) {
+      const int tid = pt.pid[t];
+      if (tid > id) ++fwd;
+      if (cnt < CONTACT_REG) {
+        const long long e = ((long long)tid << 32) | (unsigned)t;
+        bool placed = false;
+#pragma unroll
+        for (int u = CONTACT_REG - 1; u >= 0; --u)
+          if (!placed && u <= cnt) {
+            if (u > 0 && r[u - 1] > e) {
+              r[u] = r[u - 1];
+            } else {
+              r[u] = e;
+              placed = true;
+            }
+          }
+      }
+      ++cnt;
+    });
+    if (cnt <= CONTACT_REG) {
+#pragma unroll
+      for (int u = 0; u < CONTACT_REG; ++u)
+        if (u < cnt) row[u] = r[u];
+    } else {
+      int m = 0;
+      scan([&](int t) {
+        if (m == KMAX) {
+          over = true;
+          return;
+        }
+        const long long e = ((long long)pt.pid[t] << 32) | (unsigned)t;
+        int j = m;
+        while (j > 0 && row[j - 1] > e) {
+          row[j] = row[j - 1];
+          --j;
+        }
+        row[j] = e;
+        ++m;
+      });
+      cnt = m;
     }
     if (over) atomicOr(&flags[FLAG_CAPACITY], 1);
     deg[s] = cnt;
     done[s] = 0;
+    if (cnt > 0) chunk_busy[id / RES_CHUNK] = 1;  // the resolution visits this chunk of indices
+    if (cnt == 0) {  // no binary collision: the wall pass can run now
+      T vx = pt.vx[s], vy = pt.vy[s];
+      const int h = Pos<P>::walls(k, cx, cy, x, y, vx, vy);
+      if (h) {
+        pt.vx[s] = vx;
+        pt.vy[s] = vy;
+        nwall += h;
+      }
+    }
   }
   const long long t = block_sum_ll(fwd, sh);
-  if (threadIdx.x == 0) pair_part[blockIdx.x] = t;
+  const long long tw = block_sum_ll(nwall, sh);
+  if (threadIdx.x == 0) {
+    pair_part[blockIdx.x] = t;
+    wall_part[blockIdx.x] = tw;
+  }
 }
 
 // ------------------------------------------------------------------ A7: collision resolution (Eqs. 17-18) and walls
@@ -659,96 +916,117 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
 // order they start (atomic ticket), so the owner of the earliest unfinished
 // pair is always running and the sweep always progresses.  Waits are bounded
 // by spin_limit polls; exceeding it latches FLAG_STALL and the wave exits.
-// Position of particle index g in the neighbour list of slot t: the number of
-// neighbours of t with a lower index (bounded by the list length).
-__device__ __forceinline__ int row_position(const long long *adj, const int32_t *deg, int t, int g) {
-  const long long *rt = adj + (size_t)t * KMAX;
-  const int n = min(deg[t], KMAX);
-  int b = 0;
-  while (b < n && (int)(rt[b] >> 32) < g) ++b;
-  return b;
+// Binary collision of slots s (lower particle index) and t, Eqs. 17-18 with the
+// current velocities; the pair collides only if (P_s - P_t).(v_s - v_t) < 0.
+template <int P>
+__device__ __forceinline__ bool pair_collide(const Consts<typename Prec<P>::T> &k, Parts<typename Prec<P>::T> &pt,
+                                             int s, int t) {
+  using T = typename Prec<P>::T;
+  T dx, dy;
+  Pos<P>::sep(k, pt.key[s], pt.px[s], pt.py[s], pt.key[t], pt.px[t], pt.py[t], dx, dy);
+  const T vix = pt.vx[s], viy = pt.vy[s], vjx = pt.vx[t], vjy = pt.vy[t];
+  const T dvx = vix - vjx, dvy = viy - vjy;
+  const T dot = dvx * dx + dvy * dy;
+  if (!(dot < (T)0)) return false;
+  const T r2 = dx * dx + dy * dy;
+  const T q0 = k.one_e * dot / r2;
+  const T ci = q0 * k.m / k.msum;
+  const T cj = q0 * k.m / k.msum;
+  pt.vx[s] = vix - ci * dx;
+  pt.vy[s] = viy - ci * dy;
+  pt.vx[t] = vjx + cj * dx;
+  pt.vy[t] = vjy + cj * dy;
+  return true;
 }
 
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
-                                                   const long long *__restrict__ adj, const int32_t *__restrict__ deg,
-                                                   int32_t *done, int32_t *ticket, Consts<typename Prec<P>::T> k,
-                                                   int32_t *flags, long long *coll_part, long long *wall_part) {
+__device__ __forceinline__ int wall_pass(const Consts<typename Prec<P>::T> &k, Parts<typename Prec<P>::T> &pt, int s) {
   using T = typename Prec<P>::T;
-  __shared__ int s_ticket;
-  __shared__ long long sh[BLOCK / 64];
-  if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1);
-  __syncthreads();
-  const int g = s_ticket * BLOCK + threadIdx.x;  // particle index owned by this lane
-  int state = 2;                                  // 0: pair pending, 1: waiting for all pairs, 2: finished
-  int s = 0, dg = 0, a = 0, t = 0, b = 0;
-  long long ncoll = 0, nwall = 0;
-  const long long *row = nullptr;
-  if (g < k.npart) {
-    s = slot[g];
-    dg = deg[s];
-    row = adj + (size_t)s * KMAX;
-    while (a < dg && (int)(row[a] >> 32) < g) ++a;
-    state = a < dg ? 0 : 1;
-    if (state == 0) {
-      t = (int)(row[a] & 0xffffffffll);
-      b = row_position(adj, deg, t, g);
-    }
+  T vx = pt.vx[s], vy = pt.vy[s];
+  const int key = pt.key[s];
+  const int h = Pos<P>::walls(k, key % k.nx, key / k.nx, pt.px[s], pt.py[s], vx, vy);
+  if (h) {
+    pt.vx[s] = vx;
+    pt.vy[s] = vy;
   }
-  unsigned spins = 0;
-  while (__any(state != 2)) {
-    if (state == 0) {
-      const int ds = __hip_atomic_load(&done[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int dt = __hip_atomic_load(&done[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (ds == a && dt == b) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        T dx, dy;
-        Pos<P>::sep(k, pt.key[s], pt.px[s], pt.py[s], pt.key[t], pt.px[t], pt.py[t], dx, dy);
-        T vix = pt.vx[s], viy = pt.vy[s], vjx = pt.vx[t], vjy = pt.vy[t];
-        const T dvx = vix - vjx, dvy = viy - vjy;
-        const T dot = dvx * dx + dvy * dy;
-        if (dot < (T)0) {
-          const T r2 = dx * dx + dy * dy;
-          const T q0 = k.one_e * dot / r2;
-          const T ci = q0 * k.m / k.msum;
-          const T cj = q0 * k.m / k.msum;
-          pt.vx[s] = vix - ci * dx;
-          pt.vy[s] = viy - ci * dy;
-          pt.vx[t] = vjx + cj * dx;
-          pt.vy[t] = vjy + cj * dy;
-          ++ncoll;
+  return h;
+}
+
+// Contact clusters (connected components of the contact graph) are independent:
+// a pair only touches its two particles, so resolving every cluster's pairs in
+// lexicographic order gives the sequential sweep's result bit for bit.  The
+// lane of a cluster's lowest-index particle gathers the cluster (breadth-first
+// over the neighbour lists, up to CLUSTER_MAX particles, in LDS), orders it by
+// index and applies the pairs in order, then the wall pass of each member, and
+// marks the members finished (done = number of contacts).  No lane waits for
+// another.  Larger clusters are left to the ordered sweep of k_resolve.  The
+// gathered cluster lives in the root's own CLUSTER_MAX-entry scratch row.
+constexpr int CLUSTER_MAX = 64;
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<P>::T> pt,
+                                                            const long long *__restrict__ adj,
+                                                            const int32_t *__restrict__ deg, int32_t *done,
+                                                            Consts<typename Prec<P>::T> k, int32_t *need_sweep,
+                                                            long long *coll_part, long long *wall_part,
+                                                            long long *__restrict__ scratch) {
+  __shared__ long long sh[BLOCK / 64];
+  const int s = blockIdx.x * BLOCK + threadIdx.x;
+  long long *q = scratch + (size_t)s * CLUSTER_MAX;
+  long long ncoll = 0, nwall = 0;
+  if (s < k.npart && deg[s] > 0) {
+    const int g = pt.pid[s];
+    if ((int)(adj[(size_t)s * KMAX] >> 32) > g) {  // no neighbour with a lower index
+      q[0] = ((long long)g << 32) | (unsigned)s;
+      int m = 1, head = 0;
+      bool root = true, over = false;
+      while (head < m && root && !over) {
+        const int u = (int)(q[head] & 0xffffffffll);
+        ++head;
+        const long long *ru = adj + (size_t)u * KMAX;
+        const int du = min(deg[u], KMAX);
+        if ((int)(ru[0] >> 32) < g) {
+          root = false;  // a lower index belongs to this cluster
+          break;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(&done[t], b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&done[s], a + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ++a;
-        if (a < dg) {
-          t = (int)(row[a] & 0xffffffffll);
-          b = row_position(adj, deg, t, g);
-        } else {
-          state = 1;
+        for (int a = 0; a < du; ++a) {
+          const long long e = ru[a];
+          bool seen = false;
+          for (int i = 0; i < m; ++i) seen |= q[i] == e;
+          if (seen) continue;
+          if (m == CLUSTER_MAX) {
+            over = true;
+            break;
+          }
+          q[m] = e;
+          ++m;
         }
       }
-    } else if (state == 1) {
-      const int ds = __hip_atomic_load(&done[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (ds == dg) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        T vx = pt.vx[s], vy = pt.vy[s];
-        const int h = Pos<P>::walls(k, pt.key[s], pt.px[s], pt.py[s], vx, vy);
-        if (h) {
-          pt.vx[s] = vx;
-          pt.vy[s] = vy;
-          nwall += h;
+      if (root && over) atomicOr(need_sweep, 1);
+      if (root && !over) {
+        for (int i = 1; i < m; ++i) {  // order the members by particle index
+          const long long e = q[i];
+          int j = i - 1;
+          while (j >= 0 && q[j] > e) {
+            q[j + 1] = q[j];
+            --j;
+          }
+          q[j + 1] = e;
         }
-        state = 2;
-      }
-    }
-    if (state != 2) {
-      if (++spins > k.spin_limit) {
-        atomicOr(&flags[FLAG_STALL], 1);
-        state = 2;
-      } else {
-        __builtin_amdgcn_s_sleep(1);
+        for (int i = 0; i < m; ++i) {  // pairs (u, w), u < w, in lexicographic order
+          const int u = (int)(q[i] & 0xffffffffll), gu = (int)(q[i] >> 32);
+          const long long *ru = adj + (size_t)u * KMAX;
+          const int du = min(deg[u], KMAX);
+          for (int a = 0; a < du; ++a) {
+            const long long e = ru[a];
+            if ((int)(e >> 32) > gu) ncoll += pair_collide<P>(k, pt, u, (int)(e & 0xffffffffll));
+          }
+        }
+        for (int i = 0; i < m; ++i) {
+          const int u = (int)(q[i] & 0xffffffffll);
+          nwall += wall_pass<P>(k, pt, u);
+          done[u] = deg[u];
+        }
       }
     }
   }
@@ -760,27 +1038,168 @@ __global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt
   }
 }
 
-// ------------------------------------------------------------------ exclusive scan of int32 (three passes)
-constexpr int SCAN_ITEMS = 8;
-constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
+// Position of particle index g in the neighbour list of slot t: the number of
+// neighbours of t with a lower index (bounded by the list length).
+__device__ __forceinline__ int row_position(const long long *adj, const int32_t *deg, int t, int g) {
+  const long long *rt = adj + (size_t)t * KMAX;
+  const int n = min(deg[t], KMAX);
+  int b = 0;
+  while (b < n && (int)(rt[b] >> 32) < g) ++b;
+  return b;
+}
 
-__device__ __forceinline__ int block_excl_scan(int v, int *sh, int &total) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int inc = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int u = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += u;
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
+                                                   const long long *__restrict__ adj, const int32_t *__restrict__ deg,
+                                                   int32_t *done, int32_t *ticket, Consts<typename Prec<P>::T> k,
+                                                   int32_t *flags, long long *coll_part, long long *wall_part,
+                                                   int32_t *__restrict__ chunk_busy, const int32_t *need_sweep) {
+  using T = typename Prec<P>::T;
+  __shared__ int s_ticket;
+  __shared__ long long sh[BLOCK / 64];
+  long long ncoll = 0, nwall = 0;
+  unsigned spins = 0;
+  // Chunks of RES_CHUNK particle indices are taken in increasing order from an
+  // atomic ticket; chunks that hold no particle with a contact are skipped.
+  const int nchunks = (k.npart + RES_CHUNK - 1) / RES_CHUNK;
+  if (!*need_sweep) {  // every cluster was resolved whole: only clear the chunk marks
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < nchunks; i += gridDim.x * BLOCK) chunk_busy[i] = 0;
+    if (threadIdx.x == 0) {
+      coll_part[blockIdx.x] = 0;
+      wall_part[blockIdx.x] = 0;
+    }
+    return;
   }
-  if (lane == 63) sh[wv] = inc;
-  __syncthreads();
-  int base = 0;
-  total = 0;
-  for (int w = 0; w < BLOCK / 64; ++w) {
-    if (w < wv) base += sh[w];
-    total += sh[w];
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int tk;
+      do {
+        tk = atomicAdd(ticket, 1);
+      } while (tk < nchunks && chunk_busy[tk] == 0);
+      s_ticket = tk;
+    }
+    __syncthreads();
+    const int tk = s_ticket;
+    __syncthreads();
+    if (tk >= nchunks) break;
+    if (threadIdx.x == 0) chunk_busy[tk] = 0;
+    // This lane owns particle indices base + j BLOCK, j = 0 .. RES_ITEMS-1, taken
+    // in increasing order; a later one is started only when the earlier is done.
+    const int base = tk * RES_CHUNK + (int)threadIdx.x;
+    int j = 0, g = base;
+    int state = 2;  // 0: pair pending, 1: waiting for all pairs, 2: finished
+    int s = 0, dg = 0, a = 0, t = 0, b = 0;
+    const long long *row = nullptr;
+    // Set up the next owned particle that has contacts (those without had
+    // their wall pass in the contact kernel).
+    auto next = [&]() {
+      for (; j < RES_ITEMS; ++j) {
+        g = base + j * BLOCK;
+        if (g >= k.npart) {
+          j = RES_ITEMS;
+          break;
+        }
+        s = slot[g];
+        dg = deg[s];
+        if (dg == 0 || done[s] == dg) continue;  // no contacts, or resolved with its cluster
+        row = adj + (size_t)s * KMAX;
+        a = 0;
+        while (a < dg && (int)(row[a] >> 32) < g) ++a;
+        if (a < dg) {
+          t = (int)(row[a] & 0xffffffffll);
+          b = row_position(adj, deg, t, g);
+          state = 0;
+        } else {
+          state = 1;
+        }
+        return;
+      }
+      state = 2;
+    };
+    next();
+    while (__any(state != 2)) {
+      bool progressed = false;
+      if (state == 0) {
+        const int ds = __hip_atomic_load(&done[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int dt = __hip_atomic_load(&done[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ds == a && dt == b) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          ncoll += pair_collide<P>(k, pt, s, t);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __hip_atomic_store(&done[t], b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&done[s], a + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ++a;
+          if (a < dg) {
+            t = (int)(row[a] & 0xffffffffll);
+            b = row_position(adj, deg, t, g);
+          } else {
+            state = 1;
+          }
+          progressed = true;
+        }
+      } else if (state == 1) {
+        const int ds = __hip_atomic_load(&done[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ds == dg) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          nwall += wall_pass<P>(k, pt, s);
+          ++j;
+          next();
+          progressed = true;
+        }
+      }
+      if (state != 2 && !progressed) {
+        if (++spins > k.spin_limit) {
+          atomicOr(&flags[FLAG_STALL], 1);
+          state = 2;
+          j = RES_ITEMS;
+        } else {
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
   }
-  __syncthreads();
-  return base + inc - v;
+  const long long tc = block_sum_ll(ncoll, sh);
+  const long long tw = block_sum_ll(nwall, sh);
+  if (threadIdx.x == 0) {
+    coll_part[blockIdx.x] = tc;
+    wall_part[blockIdx.x] = tw;
+  }
+}
+
+// ------------------------------------------------------------------ exclusive scan of int32
+
+
+// Cell starts in one pass: the tile sums were accumulated while counting, so
+// each workgroup adds the sums of all tiles before its own (a strided sum),
+// scans its SCAN_TILE counts, writes cell_start and clears the counts.
+__global__ __launch_bounds__(BLOCK) void k_scan_cells(int32_t *__restrict__ count, long long n, TileSums ts,
+                                                      int32_t *__restrict__ out) {
+  __shared__ int sh[BLOCK / 64];
+  const int b = blockIdx.x;
+  int v = 0;
+#pragma unroll 8
+  for (int i = threadIdx.x; i < b; i += BLOCK) v += ts.tile[i];
+  int base;
+  block_excl_scan(v, sh, base);
+  const long long e0 = (long long)b * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  int vals[SCAN_ITEMS];
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    vals[j] = e0 + j < n ? count[e0 + j] : 0;
+    sum += vals[j];
+  }
+  int total;
+  int run = base + block_excl_scan(sum, sh, total);
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j)
+    if (e0 + j < n) {
+      out[e0 + j] = run;
+      run += vals[j];
+      count[e0 + j] = 0;
+    }
+  if (b == gridDim.x - 1 && threadIdx.x == 0) out[n] = base + total;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int32_t *__restrict__ in, long long n,

@@ -119,6 +119,13 @@ DConsts make_dconsts(const lbdps_params &p) {
   return c;
 }
 
+// Cell-start scan tile: SCAN_TILE = 2^shift cells.
+int cell_tile_shift(size_t) {
+  int shift = 0;
+  while ((1 << shift) < SCAN_TILE) ++shift;
+  return shift;
+}
+
 // Workspace layout: every buffer 256-byte aligned.
 struct Carver {
   char *base;
@@ -152,10 +159,32 @@ struct lbdps_ctx {
   int32_t *ticket = nullptr, *flags = nullptr, *nonfinite = nullptr;
   long long *adj = nullptr;
   void *lut = nullptr, *inlet = nullptr;
-  long long *pair_part = nullptr, *coll_part = nullptr, *wall_part = nullptr, *zero_part = nullptr;
+  long long *pair_part = nullptr, *coll_part = nullptr, *wall_part = nullptr, *wall0_part = nullptr,
+            *zero_part = nullptr;
+  int32_t *tile_sum = nullptr, *chunk_busy = nullptr, *need_sweep = nullptr;
+  int tile_shift = 11;
+  long long *cluster_scratch = nullptr;
+  long long *collc_part = nullptr, *wallc_part = nullptr;
+  int ntiles = 0;
   double *cons_pc = nullptr, *cons_pp = nullptr, *cons_out = nullptr;
   int32_t *dg_n = nullptr;
   void *dg_vsx = nullptr, *dg_vsy = nullptr, *dg_fdx = nullptr, *dg_fdy = nullptr;
+  // per-kernel event timing
+  uint32_t timed = 0;
+  struct Mark {
+    hipEvent_t a, b;
+    int k;
+  };
+  std::vector<Mark> marks;
+  size_t nmarks = 0;
+  double ms[LBDPS_K_COUNT] = {0};
+  long long launches[LBDPS_K_COUNT] = {0};
+  ~lbdps_ctx() {
+    for (auto &m : marks) {
+      (void)hipEventDestroy(m.a);
+      (void)hipEventDestroy(m.b);
+    }
+  }
 };
 
 namespace {
@@ -187,8 +216,17 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   int32_t *ticket = cv.take<int32_t>(4), *flags = cv.take<int32_t>(FLAG_COUNT), *nonfinite = cv.take<int32_t>(4);
   char *lut = raw((size_t)lut_rows(p.d_p) * LUT_W * sT), *inlet = raw((size_t)p.nx * sT);
   const size_t nbN = (size_t)nblocks((long long)N), nbC = (size_t)nblocks((long long)C);
-  long long *pair_part = cv.take<long long>(nbN), *coll_part = cv.take<long long>(nbN);
-  long long *wall_part = cv.take<long long>(nbN), *zero_part = cv.take<long long>(nbC);
+  const size_t ntile2 = (size_t)((p.nx + DTX - 1) / DTX) * ((p.ny + DTY - 1) / DTY);
+  long long *pair_part = cv.take<long long>(std::max(nbN, ntile2)), *coll_part = cv.take<long long>(nbN);
+  const size_t ndrag = (size_t)((p.nx + DTX - 1) / DTX) * ((p.ny + DTY - 1) / DTY);
+  long long *wall_part = cv.take<long long>(nbN), *zero_part = cv.take<long long>(std::max(nbC, ndrag));
+  long long *wall0_part = cv.take<long long>(std::max(nbN, ntile2));
+  const int shift = cell_tile_shift(C);
+  const size_t ntiles = (C + ((size_t)1 << shift) - 1) >> shift;
+  int32_t *tile_sum = cv.take<int32_t>(ntiles + 1);
+  long long *cluster_scratch = cv.take<long long>(N * CLUSTER_MAX);
+  int32_t *chunk_busy = cv.take<int32_t>(N / RES_CHUNK + 1), *need_sweep = cv.take<int32_t>(4);
+  long long *collc_part = cv.take<long long>(nbN), *wallc_part = cv.take<long long>(nbN);
   double *pc = cv.take<double>(NB_CONS * 3), *pp = cv.take<double>(NB_CONS * 2), *co = cv.take<double>(8);
   int32_t *dg_n = nullptr;
   char *dvx = nullptr, *dvy = nullptr, *dfx = nullptr, *dfy = nullptr;
@@ -229,6 +267,15 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->coll_part = coll_part;
     x->wall_part = wall_part;
     x->zero_part = zero_part;
+    x->wall0_part = wall0_part;
+    x->tile_sum = tile_sum;
+    x->tile_shift = shift;
+    x->cluster_scratch = cluster_scratch;
+    x->chunk_busy = chunk_busy;
+    x->need_sweep = need_sweep;
+    x->collc_part = collc_part;
+    x->wallc_part = wallc_part;
+    x->ntiles = (int)ntiles;
     x->cons_pc = pc;
     x->cons_pp = pp;
     x->cons_out = co;
@@ -239,6 +286,23 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->dg_fdy = dfy;
   }
   return cv.off + 256;
+}
+
+// Start / stop the event bracket of kernel k if it is being timed.
+void tstart(lbdps_ctx *x, int k) {
+  if (!(x->timed >> k & 1u)) return;
+  if (x->nmarks == x->marks.size()) {
+    lbdps_ctx::Mark m{};
+    if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess) return;
+    x->marks.push_back(m);
+  }
+  x->marks[x->nmarks].k = k;
+  (void)hipEventRecord(x->marks[x->nmarks].a, x->stream);
+}
+void tstop(lbdps_ctx *x, int k) {
+  if (!(x->timed >> k & 1u) || x->nmarks >= x->marks.size() || x->marks[x->nmarks].k != k) return;
+  (void)hipEventRecord(x->marks[x->nmarks].b, x->stream);
+  x->nmarks += 1;
 }
 
 lbdps_status check_hip(hipError_t e, const char *what) {
@@ -297,16 +361,31 @@ template <int P> struct Impl {
     hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(BLOCK), 0, x->stream, in, n, x->spart, out, zero_in);
   }
 
-  // Counting sort of the particle storage by (cell, particle index); the
-  // per-cell counts must already be in x->count with slots in x->rank.
-  static void sort_counted(lbdps_ctx *x) {
-    scan(x, x->count, x->C, x->cs, 1);
+  static TileSums tiles(const lbdps_ctx *x) { return TileSums{x->tile_sum, x->ntiles, x->tile_shift}; }
+  static int drag_tiles(const lbdps_ctx *x) { return ((x->nx + DTX - 1) / DTX) * ((x->ny + DTY - 1) / DTY); }
+  // Workgroups of the resolution: they loop over chunks of particle indices.
+  static int resolve_blocks(const lbdps_ctx *x) {
+    const long long chunks = (x->n + RES_CHUNK - 1) / RES_CHUNK;
+    return (int)std::max(1ll, std::min(chunks, 512ll));
+  }
+
+  // Counting sort of the particle storage by cell: the per-cell counts are in
+  // x->count (slots in x->rank) and the tile sums in x->tile_sum; cell starts
+  // in one pass, then every record moves to its slot in the other storage.
+  // Each cell's segment is put in particle-index order by the next collision.
+  static void sort_counted(lbdps_ctx *x, bool tile_sums = true) {
+    tstart(x, LBDPS_K_SCAN);
+    if (tile_sums)
+      hipLaunchKernelGGL(k_scan_cells, dim3(x->ntiles), dim3(BLOCK), 0, x->stream, x->count, (long long)x->C,
+                         tiles(x), x->cs);
+    else
+      scan(x, x->count, x->C, x->cs, 1);
+    tstop(x, LBDPS_K_SCAN);
     const int N = (int)x->n;
-    if (N == 0) return;
-    hipLaunchKernelGGL(k_scatter, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->key[x->cp], x->rank, x->cs, N,
-                       x->perm);
-    hipLaunchKernelGGL(k_sortgather<T>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, x->cs, x->perm,
-                       parts(x, x->cp), parts(x, 1 - x->cp), x->slot, x->C);
+    tstart(x, LBDPS_K_SCATTER);
+    hipLaunchKernelGGL(k_scatter<T>, dim3(std::max(nblocks(N), 1)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
+                       parts(x, 1 - x->cp), x->rank, x->cs, N, x->slot, tiles(x));
+    tstop(x, LBDPS_K_SCATTER);
     x->cp = 1 - x->cp;
   }
 
@@ -314,7 +393,7 @@ template <int P> struct Impl {
     const int N = (int)x->n;
     if (N > 0)
       hipLaunchKernelGGL(k_bin, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->key[x->cp], N, x->count, x->rank);
-    sort_counted(x);
+    sort_counted(x, false);
     x->bins_valid = true;
   }
 
@@ -322,10 +401,18 @@ template <int P> struct Impl {
     const int N = (int)x->n;
     if (N == 0) return;
     const Consts<T> k = consts(x);
+    tstart(x, LBDPS_K_CONTACTS);
     hipLaunchKernelGGL(k_contacts<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->cs, k, x->adj,
-                       x->deg, x->done, x->ticket, x->flags, x->pair_part);
-    hipLaunchKernelGGL(k_resolve<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot, x->adj,
-                       x->deg, x->done, x->ticket, k, x->flags, x->coll_part, x->wall_part);
+                       x->deg, x->done, x->ticket, x->flags, x->pair_part, x->wall0_part, x->chunk_busy,
+                       x->need_sweep);
+    tstop(x, LBDPS_K_CONTACTS);
+    tstart(x, LBDPS_K_RESOLVE);
+    hipLaunchKernelGGL(k_resolve_clusters<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->adj,
+                       x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part, x->cluster_scratch);
+    hipLaunchKernelGGL(k_resolve<P>, dim3(resolve_blocks(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot, x->adj,
+                       x->deg, x->done, x->ticket, k, x->flags, x->coll_part, x->wall_part, x->chunk_busy,
+                       x->need_sweep);
+    tstop(x, LBDPS_K_RESOLVE);
   }
 
   static lbdps_status step(lbdps_ctx *x, int nsteps) {
@@ -333,14 +420,17 @@ template <int P> struct Impl {
     const bool dg = x->p.diagnostics != 0;
     for (int it = 0; it < nsteps; ++it) {
       if (!x->bins_valid) rebin(x);
+      tstart(x, LBDPS_K_COLLIDE);
       hipLaunchKernelGGL(k_collide<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, (const S *)x->f[x->cf],
-                         (S *)x->f[1 - x->cf], fields(x), x->cs, (const T *)x->vx[x->cp], (const T *)x->vy[x->cp],
-                         (const T *)x->lut, (const T *)x->inlet, k, dg ? x->dg_n : nullptr,
+                         (S *)x->f[1 - x->cf], fields(x), x->cs, parts(x, x->cp), (const T *)x->lut, (const T *)x->inlet, k, dg ? x->dg_n : nullptr,
                          dg ? (T *)x->dg_vsx : nullptr, dg ? (T *)x->dg_vsy : nullptr);
+      tstop(x, LBDPS_K_COLLIDE);
       if (x->n > 0) {
-        hipLaunchKernelGGL(k_drag<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x),
+        tstart(x, LBDPS_K_DRAG);
+        hipLaunchKernelGGL(k_drag<P>, dim3(drag_tiles(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x),
                            x->cs, (const T *)x->lut, k, x->count, x->rank, x->flags, dg ? (T *)x->dg_fdx : nullptr,
-                           dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr);
+                           dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x));
+        tstop(x, LBDPS_K_DRAG);
         sort_counted(x);
         hard_spheres(x);
       }
@@ -536,6 +626,10 @@ lbdps_status lbdps_create(const lbdps_params *p, int64_t max_particles, void *d_
   }
   hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, x->count, (long long)x->C, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, x->flags, (long long)FLAG_COUNT, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->nmax / RES_CHUNK + 1)), dim3(BLOCK), 0, x->stream, x->chunk_busy,
+                     (long long)(x->nmax / RES_CHUNK + 1), 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->ntiles + 1)), dim3(BLOCK), 0, x->stream, x->tile_sum,
+                     (long long)x->ntiles + 1, 0);
   st = dispatch(x, [&](auto impl) { return decltype(impl)::set_state(x, nullptr, nullptr, nullptr, 0); });
   if (st == LBDPS_OK) st = check_hip(hipStreamSynchronize(x->stream), "lbdps_create");
   if (st != LBDPS_OK) {
@@ -654,20 +748,53 @@ lbdps_status lbdps_counters(lbdps_ctx *x, int64_t h_out[4]) {
   if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
   lbdps_status st = sync_and_check(x, "lbdps_counters");
   if (st != LBDPS_OK) return st;
-  const int nbN = nblocks(x->n), nbC = nblocks(x->C);
-  std::vector<long long> buf((size_t)std::max(nbN, nbC));
-  long long *src[3] = {x->pair_part, x->coll_part, x->wall_part};
+  const int nbN = nblocks(x->n), nbC = Impl<PREC_FP32>::drag_tiles(x);
+  std::vector<long long> buf((size_t)std::max(nbN, nbC) + 1);
+  // contacts: one partial per workgroup of the contact kernel; collisions and
+  // wall hits of the resolution kernel: one per workgroup of that kernel
+  long long *src[6] = {x->pair_part, x->coll_part, x->wall_part, x->wall0_part, x->collc_part, x->wallc_part};
+  const int dst[6] = {0, 1, 2, 2, 1, 2};
+  const int nres = Impl<PREC_FP32>::resolve_blocks(x);
+  const int len[6] = {nbN, nres, nres, nbN, nbN, nbN};
   for (int j = 0; j < 4; ++j) h_out[j] = 0;
   if (x->n > 0)
-    for (int j = 0; j < 3; ++j) {
-      st = check_hip(hipMemcpy(buf.data(), src[j], (size_t)nbN * 8, hipMemcpyDeviceToHost), "lbdps_counters");
+    for (int j = 0; j < 6; ++j) {
+      st = check_hip(hipMemcpy(buf.data(), src[j], (size_t)len[j] * 8, hipMemcpyDeviceToHost), "lbdps_counters");
       if (st != LBDPS_OK) return st;
-      for (int b = 0; b < nbN; ++b) h_out[j] += buf[b];
+      for (int b = 0; b < len[j]; ++b) h_out[dst[j]] += buf[b];
     }
   if (x->p.diagnostics && x->n > 0) {
     st = check_hip(hipMemcpy(buf.data(), x->zero_part, (size_t)nbC * 8, hipMemcpyDeviceToHost), "lbdps_counters");
     if (st != LBDPS_OK) return st;
     for (int b = 0; b < nbC; ++b) h_out[3] += buf[b];
+  }
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_time_kernels(lbdps_ctx *x, uint32_t mask) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (mask >> LBDPS_K_COUNT) return fail(LBDPS_E_INVALID, "unknown kernel bit in mask");
+  x->timed = mask;
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_kernel_times(lbdps_ctx *x, double *h_ms, int64_t *h_launches) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  lbdps_status st = check_hip(hipStreamSynchronize(x->stream), "lbdps_kernel_times");
+  if (st != LBDPS_OK) return st;
+  double ms[LBDPS_K_COUNT] = {0};
+  long long cnt[LBDPS_K_COUNT] = {0};
+  for (size_t i = 0; i < x->nmarks; ++i) {
+    float t = 0.f;
+    st = check_hip(hipEventElapsedTime(&t, x->marks[i].a, x->marks[i].b), "lbdps_kernel_times");
+    if (st != LBDPS_OK) return st;
+    ms[x->marks[i].k] += t;
+    cnt[x->marks[i].k] += 1;
+  }
+  x->nmarks = 0;
+  for (int k = 0; k < LBDPS_K_COUNT; ++k) {
+    if (h_ms) h_ms[k] = ms[k];
+    if (h_launches) h_launches[k] = cnt[k];
   }
   return LBDPS_OK;
 }

@@ -23,6 +23,7 @@ LBDPS_E_UNSUPPORTED, LBDPS_E_NONFINITE, LBDPS_E_CAPACITY, LBDPS_E_STALL = -4, -5
 LBDPS_FP64, LBDPS_FP32, LBDPS_FP32_STORE_FP16, LBDPS_FP32_STORE_BF16 = 0, 1, 2, 3
 LBDPS_BC_PERIODIC, LBDPS_BC_WALL, LBDPS_BC_INLET, LBDPS_BC_OUTLET = 0, 1, 2, 3
 LBDPS_MAX_CONTACTS = 32
+KERNELS = ["collide", "drag", "scan", "scatter", "contacts", "resolve"]
 
 PRECISIONS = {"fp64": LBDPS_FP64, "fp32": LBDPS_FP32, "fp16": LBDPS_FP32_STORE_FP16, "bf16": LBDPS_FP32_STORE_BF16}
 BCS = {"periodic": LBDPS_BC_PERIODIC, "wall": LBDPS_BC_WALL, "inlet": LBDPS_BC_INLET, "outlet": LBDPS_BC_OUTLET}
@@ -59,6 +60,8 @@ _SIGS = {
     "lbdps_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64)]),
     "lbdps_conservation": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
     "lbdps_counters": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
+    "lbdps_time_kernels": (c_i32, [c_vp, ctypes.c_uint32]),
+    "lbdps_kernel_times": (c_i32, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
     "lbdps_destroy": (c_i32, [c_vp]),
     "lbdps_status_str": (ctypes.c_char_p, [c_i32]),
     "lbdps_last_error": (ctypes.c_char_p, []),
@@ -231,6 +234,18 @@ class Sim:
         out = (c_i64 * 4)()
         check(lbdps_counters(self.ctx, out), "lbdps_counters")
         return dict(pairs=out[0], collisions=out[1], walls=out[2], zero_den=out[3])
+
+    def time_kernels(self, names):
+        mask = 0
+        for n in names:
+            mask |= 1 << KERNELS.index(n)
+        check(lbdps_time_kernels(self.ctx, mask), "lbdps_time_kernels")
+
+    def kernel_times(self):
+        ms = (c_dbl * len(KERNELS))()
+        cnt = (c_i64 * len(KERNELS))()
+        check(lbdps_kernel_times(self.ctx, ms, cnt), "lbdps_kernel_times")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS)}
 
     def close(self):
         if getattr(self, "ctx", None):

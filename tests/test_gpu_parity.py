@@ -85,6 +85,40 @@ def test_fp64_free_run_small(case):
     assert c["collisions"] == o.ncollisions and c["walls"] == o.nwall
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_crowded_cells(prec):
+    """A crowded periodic box (about 6 particles per cell, up to a dozen, many
+    particles with more than 6 contacts) exercises the long-segment and
+    many-contact code paths.  FP64: 1e-12 against the oracle after 10 steps with
+    identical pair lists; FP32: identical pair lists at t = 0 (single-precision
+    predicate) and the first step's gas fields within 1e-5."""
+    cfg = synth.tiny(nx=9, ny=8, n=430, seed=17, bc=("periodic",) * 4, vel_scale=3e-3, g=(0.0, -2e-5))
+    p = oracle.make_params(cfg)
+    pairs0 = oracle.contacts(p, cfg["pos"])
+    deg = np.bincount(pairs0.ravel(), minlength=len(cfg["pos"]))
+    say("max per cell", np.bincount((np.floor(cfg["pos"][:, 1]) * 9 + np.floor(cfg["pos"][:, 0])).astype(int)).max(),
+        "max contacts", deg.max())
+    assert deg.max() > 6
+    gpu = L.Sim(cfg, precision=prec, diagnostics=True)
+    ref = oracle.Sim(cfg)
+    if prec == "fp64":
+        for k in range(1, 11):
+            gpu.step(1)
+            o = ref.step(record=True)
+            if k in (1, 10):
+                compare_step(gpu, o, ref, 1e-12, what=f"crowded step {k}")
+                pairs, m = gpu.pairs()
+                assert m == len(o.pairs) and (pairs == o.pairs).all()
+    else:
+        gpu.collide_particles()
+        pairs, m = gpu.pairs()
+        st = gpu.particles()
+        cell = np.floor(cfg["pos"]).astype(np.int32)
+        off = (cfg["pos"] - cell).astype(np.float32)
+        ref_pairs = oracle.contacts_f32(9, 8, 1, 1, 0.5, cell, off)
+        assert m == len(ref_pairs) and (pairs == ref_pairs).all()
+
+
 def test_fp64_bubble_small_100_steps():
     """64x256 bed, 2000 spheres, 100 coupled steps, FP64: every field and
     particle state within 1e-12 of the oracle, pair lists identical."""
@@ -151,6 +185,28 @@ def test_fp64_collision_stage_exact():
     assert (st["vel"] == v1).all(), rel(st["vel"], v1)
     c = gpu.counters()
     assert c["collisions"] == nc and c["walls"] == nw
+
+
+@pytest.mark.parametrize("name", ["riser_crop", "bubble_small"])
+def test_fp64_collision_stage_clusters(name):
+    """Hard-sphere stage on a whole bed with random velocities: contact clusters
+    small enough are resolved whole by one lane, larger ones by the ordered
+    sweep; either way the velocities equal the oracle's sequential
+    lexicographic sweep bit for bit."""
+    cfg = getattr(synth, name)()
+    rng = np.random.default_rng(21)
+    vel = (rng.random(cfg["pos"].shape) - 0.5) * 2e-2
+    gpu = L.Sim(dict(cfg, vel=vel), precision="fp64")
+    gpu.collide_particles()
+    p = oracle.make_params(cfg)
+    ref_pairs = oracle.contacts(p, cfg["pos"])
+    v1, nc = oracle.resolve(p, cfg["pos"], vel, ref_pairs)
+    v1, nw = oracle.walls(p, cfg["pos"], v1)
+    st = gpu.particles()
+    c = gpu.counters()
+    say(name, "pairs", len(ref_pairs), "collisions", nc, "walls", nw)
+    assert c["pairs"] == len(ref_pairs) and c["collisions"] == nc and c["walls"] == nw
+    assert (st["vel"] == v1).all(), rel(st["vel"], v1)
 
 
 def test_fp32_contacts_exact_single_precision():
