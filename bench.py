@@ -97,6 +97,92 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None):
     return out
 
 
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_2653_amd", "csrc", f) for f in ("kernels.hpp", "device.hpp")]
+KERNEL_KEYS = {"collide": "k_collide", "drag": "k_drag", "scan": "k_scan_cells", "scatter": "k_scatter",
+               "contacts": "k_contacts", "resolve": "k_resolve_clusters"}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM-side bytes per launch of `kernel` from the committed counter summary,
+    or None if there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    v = t.get("bytes_per_launch", {}).get(kernel)
+    return None if v is None else int(v)
+
+
+def summarize(args):
+    """Turn rocprofv3 CSV output into the short summaries kept under profiles/:
+    <label>.md (per-kernel duration statistics and counter bytes) and
+    traffic_<workload>.json (HBM-side bytes per launch, scaled by the copy probe)."""
+    import csv
+    import glob
+
+    def rows(d, pattern):
+        out = []
+        for f in glob.glob(os.path.join(d, "**", pattern), recursive=True):
+            with open(f) as fh:
+                out += list(csv.DictReader(fh))
+        return out
+
+    def short(name):
+        n = name.split("(")[0].split("<")[0].split("::")[-1]
+        return n
+
+    stats = rows(args.stats, "*kernel_stats.csv")
+    lines = [f"# rocprofv3 summary: {args.label}", "", "Command (run from /tmp, repository at $R):", "",
+             "```", args.command, "```", "", "| kernel | calls | mean us | min us | max us | share % |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"| {r['Name'].split('(')[0][:70]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+    traffic = {}
+    if args.fetch and args.write and args.copy_fetch and args.copy_write:
+        def per_kernel(d):
+            acc = {}
+            for r in rows(d, "*counter_collection.csv"):
+                acc.setdefault(short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]) * 1024.0)
+            return {k: sum(v) / len(v) for k, v in acc.items()}
+        fetch, write = per_kernel(args.fetch), per_kernel(args.write)
+        cf, cw = per_kernel(args.copy_fetch), per_kernel(args.copy_write)
+        copy_name = max(cf, key=lambda k: cf[k])  # the copy: the only probe kernel that reads
+        f_scale = args.copy_bytes / cf[copy_name]
+        w_scale = args.copy_bytes / cw[copy_name]
+        lines += ["", f"HBM-side bytes per launch: FETCH_SIZE x {f_scale:.3f} + WRITE_SIZE x {w_scale:.3f}; the factors "
+                  f"make a plain {args.copy_bytes} byte copy ({copy_name}) read and write exactly its size.", "",
+                  "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes per launch |", "|---|---:|---:|---:|"]
+        for key, kname in KERNEL_KEYS.items():
+            if kname in fetch and kname in write:
+                b = fetch[kname] * f_scale + write[kname] * w_scale
+                traffic[key] = int(b)
+                lines.append(f"| {kname} | {fetch[kname] / 1024:.1f} | {write[kname] / 1024:.1f} | {int(b)} |")
+        lines += ["", "Counter commands: the same program under `rocprofv3 --pmc FETCH_SIZE` and "
+                  "`rocprofv3 --pmc WRITE_SIZE` (one counter per run), and `bench.py --copy-probe "
+                  f"{args.copy_bytes}` under each for the scale factors."]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"{args.label}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    if traffic:
+        with open(os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json"), "w") as fh:
+            json.dump({"workload": args.workload, "kernel_source_hash": kernel_source_hash(),
+                       "bytes_per_launch": traffic, "fetch_scale": f_scale, "write_scale": w_scale}, fh, indent=1)
+    print("\n".join(lines))
+
+
 def cpu_baseline(cfg, seconds):
     import oracle
     sim = oracle.Sim(cfg)
@@ -124,15 +210,39 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
+    ap.add_argument("--summarize", action="store_true", help="write profiles/ summaries from rocprofv3 output")
+    ap.add_argument("--stats", help="directory of a rocprofv3 --kernel-trace --stats run")
+    ap.add_argument("--fetch", help="directory of the --pmc FETCH_SIZE run")
+    ap.add_argument("--write", help="directory of the --pmc WRITE_SIZE run")
+    ap.add_argument("--copy-fetch", help="directory of the copy probe under --pmc FETCH_SIZE")
+    ap.add_argument("--copy-write", help="directory of the copy probe under --pmc WRITE_SIZE")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--label", default="profile")
+    ap.add_argument("--command", default="")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_1303_2653_amd import lbdps as L
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}), flush=True)
+        return
+    from paper_1303_2653_amd import lbdps as L
+
     cfg = WORKLOADS[args.workload]()
     C, N = cfg["nx"] * cfg["ny"], len(cfg["pos"])
     r = run_gpu(cfg, args.precision, args.steps, args.warmup, torch, L)
@@ -144,6 +254,7 @@ def main():
     dom_bytes = algorithmic_bytes(dom, args.precision, C, N, r["pairs"])
     achieved = dom_bytes / (dom_us * 1e-6) / 1e9
     model = model_bytes_per_step(args.precision, C, N, r["pairs"])
+    traffic = measured_traffic(args.workload if args.precision == "fp32" else f"{args.workload}-{args.precision}", dom)
     line = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -165,7 +276,7 @@ def main():
         "contact_pairs": r["pairs"],
         "kernel_us": {k: round(v, 2) for k, v in r["breakdown_us"].items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3)},
     }
     if not args.no_variants and args.precision == "fp32":

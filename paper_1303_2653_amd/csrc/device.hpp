@@ -133,7 +133,7 @@ template <class T> struct Parts {
 
 // Node fields written by the collision, read by the particle stage.
 template <class T> struct Fields {
-  T *rho, *ugx, *ugy, *beta, *fpgx, *fpgy;
+  T *rho, *ugx, *ugy, *beta, *fpgx, *fpgy, *es;  // es: 3-D solid fraction of the node (Eq. 11)
 };
 
 }  // namespace lbdps

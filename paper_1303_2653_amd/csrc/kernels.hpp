@@ -266,6 +266,7 @@ struct TileSums {
   __device__ void add(int t, int v) const { atomicAdd(&tile[t], v); }
 };
 
+constexpr int LUT_ROWS_MAX = 64;              // per-count table rows staged in LDS
 constexpr int SEG_REG = 4;                    // cell segments up to this length stay in registers
 constexpr int CONTACT_REG = 6;                // contacts per particle collected in registers first
 constexpr int RES_ITEMS = 8;                  // particle indices per lane and resolution chunk
@@ -322,6 +323,9 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
                                                    Consts<typename Prec<P>::T> k, int32_t *dg_n,
                                                    typename Prec<P>::T *dg_vsx, typename Prec<P>::T *dg_vsy) {
   using T = typename Prec<P>::T;
+  __shared__ T sl[LUT_ROWS_MAX * LUT_W];  // the per-count table
+  for (int i = threadIdx.x; i < min(k.nlut, LUT_ROWS_MAX) * LUT_W; i += BLOCK) sl[i] = lut[i];
+  __syncthreads();
   const int c = blockIdx.x * BLOCK + threadIdx.x;
   if (c >= k.C) return;
   const int x = c % k.nx, y = c / k.nx;
@@ -423,7 +427,8 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
     vsx = sx / (T)n;
     vsy = sy / (T)n;
   }
-  const T *L = lut + (size_t)min(n, k.nlut - 1) * LUT_W;
+  const int row = min(n, k.nlut - 1);
+  const T *L = row < LUT_ROWS_MAX ? sl + row * LUT_W : lut + (size_t)row * LUT_W;
 
   T rho = (T)0, rho1 = (T)0, jx = (T)0, jy = (T)0;
   if constexpr (kDev<P>) {
@@ -475,6 +480,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
   fl.beta[c] = beta;
   fl.fpgx[c] = fpx;
   fl.fpgy[c] = fpy;
+  fl.es[c] = L[L_ES3];
   if (dg_n) {
     dg_n[c] = n;
     dg_vsx[c] = vsx;
@@ -550,7 +556,7 @@ template <int P> struct DragTile {
   using T = typename Prec<P>::T;
   T ux[DSN], uy[DSN], es[DSN], beta[DSN], gpx[DSN], gpy[DSN];
 
-  __device__ void load(const Consts<T> &k, const Fields<T> &fl, const int32_t *cs, const T *lut, int tx0, int ty0) {
+  __device__ void load(const Consts<T> &k, const Fields<T> &fl, int tx0, int ty0) {
     for (int q = threadIdx.x; q < DSN; q += BLOCK) {
       const int i = node_idx(tx0 - 1 + q % DSX, k.nx, k.per_x);
       const int j = node_idx(ty0 - 1 + q / DSX, k.ny, k.per_y);
@@ -558,7 +564,7 @@ template <int P> struct DragTile {
       ux[q] = fl.ugx[c];
       uy[q] = fl.ugy[c];
       beta[q] = fl.beta[c];
-      es[q] = lut[(size_t)min(cs[c + 1] - cs[c], k.nlut - 1) * LUT_W + L_ES3];
+      es[q] = fl.es[c];
       // central differences of p = rho / 3, boundary value as the ghost beyond a wall
       const int ie = node_idx(i + 1, k.nx, k.per_x), iw = node_idx(i - 1, k.nx, k.per_x);
       const int jn = node_idx(j + 1, k.ny, k.per_y), js = node_idx(j - 1, k.ny, k.per_y);
@@ -602,22 +608,29 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
   __shared__ long long sh[BLOCK / 64];
   __shared__ int hist[HIST_MAX];
   __shared__ DragTile<P> D;
-  __shared__ int s_occupied;
   const int ntx = (k.nx + DTX - 1) / DTX;
   const int tx0 = (blockIdx.x % ntx) * DTX, ty0 = (blockIdx.x / ntx) * DTY;
-  // a tile without particles has nothing to do (its rows' particle ranges are empty)
-  if (threadIdx.x == 0) s_occupied = 0;
-  __syncthreads();
-  if (threadIdx.x < DTY && ty0 + (int)threadIdx.x < k.ny) {
-    const int rb = (ty0 + (int)threadIdx.x) * k.nx;
-    if (cs[rb + min(tx0 + DTX, k.nx)] > cs[rb + tx0]) s_occupied = 1;
-  }
-  __syncthreads();
-  if (!s_occupied) {
+  const int cx = tx0 + (int)threadIdx.x % DTX, cy = ty0 + (int)threadIdx.x / DTX;
+  const int c = cy * k.nx + cx;
+  const bool inside = cx < k.nx && cy < k.ny;
+  const int a0 = inside ? cs[c] : 0, a1 = inside ? cs[c + 1] : 0;
+  const int n = a1 - a0;
+  // a tile without particles has nothing to do
+  if (!__syncthreads_or(n > 0)) {
     if (zero_part && threadIdx.x == 0) zero_part[blockIdx.x] = 0;
     return;
   }
-  D.load(k, fl, cs, lut, tx0, ty0);
+  // this thread's particles (short segments), loaded while the tile is staged
+  T px[SEG_REG], py[SEG_REG], pvx[SEG_REG], pvy[SEG_REG];
+#pragma unroll
+  for (int u = 0; u < SEG_REG; ++u)
+    if (u < n) {
+      px[u] = pt.px[a0 + u];
+      py[u] = pt.py[a0 + u];
+      pvx[u] = pt.vx[a0 + u];
+      pvy[u] = pt.vy[a0 + u];
+    }
+  D.load(k, fl, tx0, ty0);
   // scan tiles the new cells of this tile's particles can fall in (one cell
   // move at most, periodic jumps go straight to the global counters)
   const int klo = max(0, (ty0 - 1) * k.nx + tx0 - 1);
@@ -625,12 +638,8 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
   const int tlo = klo >> ts.shift, nh = (khi >> ts.shift) - tlo + 1;
   if (threadIdx.x < HIST_MAX) hist[threadIdx.x] = 0;
   __syncthreads();
-  const int cx = tx0 + (int)threadIdx.x % DTX, cy = ty0 + (int)threadIdx.x / DTX;
-  const int c = cy * k.nx + cx;
   long long nzero = 0;
-  if (cx < k.nx && cy < k.ny) {
-    const int a0 = cs[c], a1 = cs[c + 1];
-    const int n = a1 - a0;
+  if (inside) {
     if (n > 0) {
       const T fgx = fl.fpgx[c], fgy = fl.fpgy[c];
       // Eq. 28 for one particle, then Eq. 16: v <- v + g_eff + (F_d + s V_p grad p) / m,
@@ -679,17 +688,9 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
           ts.add(nk >> ts.shift, 1);
       };
       if (n <= SEG_REG) {  // short segment: particle data and pre-drags in registers
-        T x[SEG_REG], y[SEG_REG], vx[SEG_REG], vy[SEG_REG];
+        T *x = px, *y = py, *vx = pvx, *vy = pvy;
         T prx[SEG_REG], pry[SEG_REG], gpx[SEG_REG], gpy[SEG_REG];
         int nk[SEG_REG];
-#pragma unroll
-        for (int u = 0; u < SEG_REG; ++u)
-          if (u < n) {
-            x[u] = pt.px[a0 + u];
-            y[u] = pt.py[a0 + u];
-            vx[u] = pt.vx[a0 + u];
-            vy[u] = pt.vy[a0 + u];
-          }
         T Sx = (T)0, Sy = (T)0;
 #pragma unroll
         for (int u = 0; u < SEG_REG; ++u)
@@ -808,27 +809,54 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
     long long r[CONTACT_REG];
     int cnt = 0;
     bool over = false;
+    // candidate ranges: the three cells of each neighbour row are one slot
+    // range away from a periodic seam; the column offset of a candidate follows
+    // from the cell starts.  All starts are loaded first.
+    const bool inner_x = cx >= 1 && cx + 1 < k.nx;
+    int rlo[3], rm1[3], rm2[3], rhi[3];
+#pragma unroll
+    for (int rw = 0; rw < 3; ++rw) {
+      int yy = cy + rw - 1;
+      bool ok = true;
+      if (yy < 0 || yy >= k.ny) {
+        ok = k.per_y != 0;
+        yy = wrap_i(yy, k.ny);
+      }
+      const int c0 = yy * k.nx + cx - 1;
+      if (ok && inner_x) {
+        rlo[rw] = cs[c0];
+        rm1[rw] = cs[c0 + 1];
+        rm2[rw] = cs[c0 + 2];
+        rhi[rw] = cs[c0 + 3];
+      } else {  // a row beyond a wall (empty), or a seam column walked cell by cell below
+        rlo[rw] = rm1[rw] = rm2[rw] = rhi[rw] = 0;
+      }
+    }
     auto scan = [&](auto &&hit) {
-      const bool inner_x = cx >= 1 && cx + 1 < k.nx;
-      for (int oy = -1; oy <= 1; ++oy) {
-        int yy = cy + oy;
-        if (yy < 0 || yy >= k.ny) {
-          if (!k.per_y) continue;
-          yy = wrap_i(yy, k.ny);
-        }
-        const int rb = yy * k.nx;
-        auto test = [&](int t, int ox) {
-          if (t == s) return;
-          T dx, dy;
-          Pos<P>::sep_nb(k, ox, oy, x, y, pt.px[t], pt.py[t], dx, dy);
-          if (dx * dx + dy * dy <= dd) hit(t);
-        };
-        if (inner_x) {
-          const int c0 = rb + cx - 1;
-          const int e0 = cs[c0], e1 = cs[c0 + 1], e2 = cs[c0 + 2], e3 = cs[c0 + 3];
+      auto test = [&](int t, int ox, int oy) {
+        if (t == s) return;
+        T dx, dy;
+        Pos<P>::sep_nb(k, ox, oy, x, y, pt.px[t], pt.py[t], dx, dy);
+        if (dx * dx + dy * dy <= dd) hit(t);
+      };
+      if (inner_x) {
+        // one flattened pass over the three rows' ranges
+        const int n0 = rhi[0] - rlo[0], n1 = rhi[1] - rlo[1], n2 = rhi[2] - rlo[2];
+        const int tot = n0 + n1 + n2;
 #pragma unroll 4
-          for (int t = e0; t < e3; ++t) test(t, t < e1 ? -1 : (t < e2 ? 0 : 1));
-        } else {
+        for (int q = 0; q < tot; ++q) {
+          const int rw = q < n0 ? 0 : (q < n0 + n1 ? 1 : 2);
+          const int t = rlo[rw] + q - (rw == 0 ? 0 : (rw == 1 ? n0 : n0 + n1));
+          test(t, t < rm1[rw] ? -1 : (t < rm2[rw] ? 0 : 1), rw - 1);
+        }
+      } else {
+        for (int oy = -1; oy <= 1; ++oy) {
+          int yy = cy + oy;
+          if (yy < 0 || yy >= k.ny) {
+            if (!k.per_y) continue;
+            yy = wrap_i(yy, k.ny);
+          }
+          const int rb = yy * k.nx;
           for (int ox = -1; ox <= 1; ++ox) {
             int xx = cx + ox;
             if (xx < 0 || xx >= k.nx) {
@@ -836,7 +864,7 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
               xx = wrap_i(xx, k.nx);
             }
             const int c = rb + xx;
-            for (int t = cs[c]; t < cs[c + 1]; ++t) test(t, ox);
+            for (int t = cs[c]; t < cs[c + 1]; ++t) test(t, ox, oy);
           }
         }
       }

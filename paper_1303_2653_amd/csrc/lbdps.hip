@@ -151,7 +151,7 @@ struct lbdps_ctx {
   DConsts dc{};
   // device buffers (carved from the workspace)
   void *f[2]{};
-  void *fld[6]{};  // rho, ugx, ugy, beta, fpgx, fpgy
+  void *fld[7]{};  // rho, ugx, ugy, beta, fpgx, fpgy, es
   int32_t *count = nullptr, *cs = nullptr, *spart = nullptr;
   int32_t *key[2]{}, *pid[2]{};
   void *px[2]{}, *py[2]{}, *vx[2]{}, *vy[2]{};
@@ -197,7 +197,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   const size_t tiles = (std::max(C + 1, N + 1) + SCAN_TILE - 1) / SCAN_TILE + 1;
   auto raw = [&](size_t bytes) { return cv.take<char>(bytes); };
   char *f0 = raw(Q * C * sS), *f1 = raw(Q * C * sS);
-  char *fl[6];
+  char *fl[7];
   for (auto &q : fl) q = raw(C * sT);
   int32_t *count = cv.take<int32_t>(C), *cs = cv.take<int32_t>(C + 1), *spart = cv.take<int32_t>(tiles);
   int32_t *key[2], *pid[2];
@@ -240,7 +240,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   if (x) {
     x->f[0] = f0;
     x->f[1] = f1;
-    for (int i = 0; i < 6; ++i) x->fld[i] = fl[i];
+    for (int i = 0; i < 7; ++i) x->fld[i] = fl[i];
     x->count = count;
     x->cs = cs;
     x->spart = spart;
@@ -351,7 +351,8 @@ template <int P> struct Impl {
     return Parts<T>{x->key[b], x->pid[b], (T *)x->px[b], (T *)x->py[b], (T *)x->vx[b], (T *)x->vy[b]};
   }
   static Fields<T> fields(const lbdps_ctx *x) {
-    return Fields<T>{(T *)x->fld[0], (T *)x->fld[1], (T *)x->fld[2], (T *)x->fld[3], (T *)x->fld[4], (T *)x->fld[5]};
+    return Fields<T>{(T *)x->fld[0], (T *)x->fld[1], (T *)x->fld[2], (T *)x->fld[3],
+                     (T *)x->fld[4], (T *)x->fld[5], (T *)x->fld[6]};
   }
 
   static void scan(lbdps_ctx *x, int32_t *in, long long n, int32_t *out, int zero_in) {
