@@ -787,11 +787,14 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
                                                     int32_t *__restrict__ deg, int32_t *__restrict__ done,
                                                     int32_t *ticket, int32_t *flags, long long *pair_part,
                                                     long long *wall_part, int32_t *__restrict__ chunk_busy,
-                                                    int32_t *need_sweep) {
+                                                    int32_t *need_sweep, int32_t *__restrict__ roots,
+                                                    int32_t *__restrict__ rcount) {
   using T = typename Prec<P>::T;
   __shared__ long long sh[BLOCK / 64];
+  __shared__ int shi[BLOCK / 64];
   const int s = blockIdx.x * BLOCK + threadIdx.x;
   long long fwd = 0, nwall = 0;
+  bool cand = false;  // has contacts, all with higher indices: a possible cluster root
   if (s == 0) {
     *ticket = 0;
     *need_sweep = 0;
@@ -911,6 +914,7 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
       cnt = m;
     }
     if (over) atomicOr(&flags[FLAG_CAPACITY], 1);
+    if (cnt > 0) cand = (int)((cnt <= CONTACT_REG ? r[0] : row[0]) >> 32) > id;
     deg[s] = cnt;
     done[s] = 0;
     if (cnt > 0) chunk_busy[id / RES_CHUNK] = 1;  // the resolution visits this chunk of indices
@@ -924,11 +928,16 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
       }
     }
   }
+  // candidate roots of this workgroup, compacted to the front of its segment
+  int nc;
+  const int off = block_excl_scan(cand ? 1 : 0, shi, nc);
+  if (cand) roots[(size_t)blockIdx.x * BLOCK + off] = s;
   const long long t = block_sum_ll(fwd, sh);
   const long long tw = block_sum_ll(nwall, sh);
   if (threadIdx.x == 0) {
     pair_part[blockIdx.x] = t;
     wall_part[blockIdx.x] = tw;
+    rcount[blockIdx.x] = nc;
   }
 }
 
@@ -983,13 +992,91 @@ __device__ __forceinline__ int wall_pass(const Consts<typename Prec<P>::T> &k, P
 // Contact clusters (connected components of the contact graph) are independent:
 // a pair only touches its two particles, so resolving every cluster's pairs in
 // lexicographic order gives the sequential sweep's result bit for bit.  The
-// lane of a cluster's lowest-index particle gathers the cluster (breadth-first
-// over the neighbour lists, up to CLUSTER_MAX particles, in LDS), orders it by
-// index and applies the pairs in order, then the wall pass of each member, and
-// marks the members finished (done = number of contacts).  No lane waits for
-// another.  Larger clusters are left to the ordered sweep of k_resolve.  The
-// gathered cluster lives in the root's own CLUSTER_MAX-entry scratch row.
+// contact kernel lists, per workgroup, the particles whose neighbours all have
+// higher indices: every cluster's lowest index is among them.  A lane takes one
+// such candidate, gathers its cluster breadth-first and gives up as soon as it
+// meets a lower index (the cluster belongs to another candidate).  Otherwise it
+// orders the members by index, applies the pairs in order, runs the wall pass
+// of each member and marks them finished (done = number of contacts).  No lane
+// waits for another.
+//
+// The cluster is gathered into CL_LDS entries of LDS; a larger one is gathered
+// again into the lane's CLUSTER_MAX-entry row of global scratch, and a cluster
+// beyond that is left to the ordered sweep of k_resolve.  Each workgroup takes
+// the candidate lists of a run of contact-kernel workgroups and deals their
+// candidates out to its lanes densely, so lanes resolve several clusters each.
+constexpr int CL_LDS = 8;
 constexpr int CLUSTER_MAX = 64;
+constexpr int RC_GRID_MAX = 2048;  // resolution workgroups (each takes <= BLOCK candidate lists)
+
+struct LdsColumn {  // entry i of a lane's column of a [CL_LDS][BLOCK] LDS array
+  long long *p;
+  __device__ long long &operator[](int i) const { return p[i * BLOCK]; }
+};
+struct MemRow {
+  long long *p;
+  __device__ long long &operator[](int i) const { return p[i]; }
+};
+
+// Gathers the cluster of candidate slot s (index g) into q[0 .. m) as
+// (index << 32 | slot) and returns m; returns 0 if a member has a lower index
+// than g, and -1 if the cluster has more than cap members.
+template <class Row>
+__device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, const long long *__restrict__ adj,
+                                              const int32_t *__restrict__ deg) {
+  q[0] = ((long long)g << 32) | (unsigned)s;
+  int m = 1;
+  for (int head = 0; head < m; ++head) {
+    const int u = (int)(q[head] & 0xffffffffll);
+    const long long *ru = adj + (size_t)u * KMAX;
+    const int du = min(deg[u], KMAX);
+    // the first four entries are loaded together (a row has KMAX slots)
+    const long long e0 = ru[0], e1 = ru[1], e2 = ru[2], e3 = ru[3];
+    for (int a = 0; a < du; ++a) {
+      const long long e = a == 0 ? e0 : (a == 1 ? e1 : (a == 2 ? e2 : (a == 3 ? e3 : ru[a])));
+      if ((int)(e >> 32) < g) return 0;
+      bool seen = false;
+      for (int i = 0; i < m; ++i) seen |= q[i] == e;
+      if (seen) continue;
+      if (m == cap) return -1;
+      q[m] = e;
+      ++m;
+    }
+  }
+  return m;
+}
+
+// Orders the gathered members by index, applies the cluster's pairs in
+// lexicographic order, then each member's wall pass.
+template <int P, class Row>
+__device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typename Prec<P>::T> &k,
+                                                Parts<typename Prec<P>::T> &pt, const long long *__restrict__ adj,
+                                                const int32_t *__restrict__ deg, int32_t *done, long long &ncoll,
+                                                long long &nwall) {
+  for (int i = 1; i < m; ++i) {
+    const long long e = q[i];
+    int j = i - 1;
+    while (j >= 0 && q[j] > e) {
+      q[j + 1] = q[j];
+      --j;
+    }
+    q[j + 1] = e;
+  }
+  for (int i = 0; i < m; ++i) {  // pairs (u, w), u < w, in lexicographic order
+    const int u = (int)(q[i] & 0xffffffffll), gu = (int)(q[i] >> 32);
+    const long long *ru = adj + (size_t)u * KMAX;
+    const int du = min(deg[u], KMAX);
+    for (int a = 0; a < du; ++a) {
+      const long long e = ru[a];
+      if ((int)(e >> 32) > gu) ncoll += pair_collide<P>(k, pt, u, (int)(e & 0xffffffffll));
+    }
+  }
+  for (int i = 0; i < m; ++i) {
+    const int u = (int)(q[i] & 0xffffffffll);
+    nwall += wall_pass<P>(k, pt, u);
+    done[u] = deg[u];
+  }
+}
 
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<P>::T> pt,
@@ -997,65 +1084,42 @@ __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<
                                                             const int32_t *__restrict__ deg, int32_t *done,
                                                             Consts<typename Prec<P>::T> k, int32_t *need_sweep,
                                                             long long *coll_part, long long *wall_part,
-                                                            long long *__restrict__ scratch) {
+                                                            long long *__restrict__ scratch,
+                                                            const int32_t *__restrict__ roots,
+                                                            const int32_t *__restrict__ rcount, int nlists) {
   __shared__ long long sh[BLOCK / 64];
-  const int s = blockIdx.x * BLOCK + threadIdx.x;
-  long long *q = scratch + (size_t)s * CLUSTER_MAX;
+  __shared__ int shi[BLOCK / 64];
+  __shared__ int pre[BLOCK + 1];
+  __shared__ long long qs[CL_LDS * BLOCK];
+  // candidate lists [b0, b0 + nb) of the contact kernel's workgroups
+  const int per = (nlists + gridDim.x - 1) / gridDim.x;  // <= BLOCK (host grid choice)
+  const int b0 = blockIdx.x * per;
+  const int nb = max(0, min(nlists - b0, per));
+  int tot;
+  const int c = (int)threadIdx.x < nb ? rcount[b0 + threadIdx.x] : 0;
+  const int o = block_excl_scan(c, shi, tot);
+  if ((int)threadIdx.x < nb) pre[threadIdx.x] = o;
+  if (threadIdx.x == 0) pre[nb] = tot;
+  __syncthreads();
+  const LdsColumn ql{qs + threadIdx.x};
+  const MemRow qg{scratch + ((size_t)blockIdx.x * BLOCK + threadIdx.x) * CLUSTER_MAX};
   long long ncoll = 0, nwall = 0;
-  if (s < k.npart && deg[s] > 0) {
+  for (int f = threadIdx.x; f < tot; f += BLOCK) {
+    int lo = 0, hi = nb;  // list j with pre[j] <= f < pre[j + 1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pre[mid] <= f) lo = mid;
+      else hi = mid;
+    }
+    const int s = roots[(size_t)(b0 + lo) * BLOCK + (f - pre[lo])];
     const int g = pt.pid[s];
-    if ((int)(adj[(size_t)s * KMAX] >> 32) > g) {  // no neighbour with a lower index
-      q[0] = ((long long)g << 32) | (unsigned)s;
-      int m = 1, head = 0;
-      bool root = true, over = false;
-      while (head < m && root && !over) {
-        const int u = (int)(q[head] & 0xffffffffll);
-        ++head;
-        const long long *ru = adj + (size_t)u * KMAX;
-        const int du = min(deg[u], KMAX);
-        if ((int)(ru[0] >> 32) < g) {
-          root = false;  // a lower index belongs to this cluster
-          break;
-        }
-        for (int a = 0; a < du; ++a) {
-          const long long e = ru[a];
-          bool seen = false;
-          for (int i = 0; i < m; ++i) seen |= q[i] == e;
-          if (seen) continue;
-          if (m == CLUSTER_MAX) {
-            over = true;
-            break;
-          }
-          q[m] = e;
-          ++m;
-        }
-      }
-      if (root && over) atomicOr(need_sweep, 1);
-      if (root && !over) {
-        for (int i = 1; i < m; ++i) {  // order the members by particle index
-          const long long e = q[i];
-          int j = i - 1;
-          while (j >= 0 && q[j] > e) {
-            q[j + 1] = q[j];
-            --j;
-          }
-          q[j + 1] = e;
-        }
-        for (int i = 0; i < m; ++i) {  // pairs (u, w), u < w, in lexicographic order
-          const int u = (int)(q[i] & 0xffffffffll), gu = (int)(q[i] >> 32);
-          const long long *ru = adj + (size_t)u * KMAX;
-          const int du = min(deg[u], KMAX);
-          for (int a = 0; a < du; ++a) {
-            const long long e = ru[a];
-            if ((int)(e >> 32) > gu) ncoll += pair_collide<P>(k, pt, u, (int)(e & 0xffffffffll));
-          }
-        }
-        for (int i = 0; i < m; ++i) {
-          const int u = (int)(q[i] & 0xffffffffll);
-          nwall += wall_pass<P>(k, pt, u);
-          done[u] = deg[u];
-        }
-      }
+    int m = gather_cluster(ql, CL_LDS, s, g, adj, deg);
+    if (m > 0) {
+      resolve_cluster<P>(ql, m, k, pt, adj, deg, done, ncoll, nwall);
+    } else if (m < 0) {
+      m = gather_cluster(qg, CLUSTER_MAX, s, g, adj, deg);
+      if (m > 0) resolve_cluster<P>(qg, m, k, pt, adj, deg, done, ncoll, nwall);
+      else if (m < 0) atomicOr(need_sweep, 1);
     }
   }
   const long long tc = block_sum_ll(ncoll, sh);

@@ -26,6 +26,12 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int NB_CONS = 512;  // workgroups of the conservation reductions
 
 int nblocks(long long n) { return (int)((n + BLOCK - 1) / BLOCK); }
+// Workgroups of the cluster resolution: at most RC_GRID_MAX, and enough that
+// each takes at most BLOCK of the contact kernel's candidate lists.
+int cluster_blocks(long long n) {
+  const long long nl = std::max(1ll, (long long)nblocks(n));
+  return (int)std::max(std::min(nl, (long long)RC_GRID_MAX), (nl + BLOCK - 1) / BLOCK);
+}
 
 size_t pop_bytes(int prec) { return prec == PREC_FP64 ? 8 : (prec == PREC_FP32 ? 4 : 2); }
 size_t real_bytes(int prec) { return prec == PREC_FP64 ? 8 : 4; }
@@ -164,6 +170,7 @@ struct lbdps_ctx {
   int32_t *tile_sum = nullptr, *chunk_busy = nullptr, *need_sweep = nullptr;
   int tile_shift = 11;
   long long *cluster_scratch = nullptr;
+  int32_t *roots = nullptr, *rcount = nullptr;
   long long *collc_part = nullptr, *wallc_part = nullptr;
   int ntiles = 0;
   double *cons_pc = nullptr, *cons_pp = nullptr, *cons_out = nullptr;
@@ -224,7 +231,8 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   const int shift = cell_tile_shift(C);
   const size_t ntiles = (C + ((size_t)1 << shift) - 1) >> shift;
   int32_t *tile_sum = cv.take<int32_t>(ntiles + 1);
-  long long *cluster_scratch = cv.take<long long>(N * CLUSTER_MAX);
+  long long *cluster_scratch = cv.take<long long>((size_t)cluster_blocks((long long)N) * BLOCK * CLUSTER_MAX);
+  int32_t *roots = cv.take<int32_t>(nbN * BLOCK), *rcount = cv.take<int32_t>(nbN);
   int32_t *chunk_busy = cv.take<int32_t>(N / RES_CHUNK + 1), *need_sweep = cv.take<int32_t>(4);
   long long *collc_part = cv.take<long long>(nbN), *wallc_part = cv.take<long long>(nbN);
   double *pc = cv.take<double>(NB_CONS * 3), *pp = cv.take<double>(NB_CONS * 2), *co = cv.take<double>(8);
@@ -271,6 +279,8 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->tile_sum = tile_sum;
     x->tile_shift = shift;
     x->cluster_scratch = cluster_scratch;
+    x->roots = roots;
+    x->rcount = rcount;
     x->chunk_busy = chunk_busy;
     x->need_sweep = need_sweep;
     x->collc_part = collc_part;
@@ -405,11 +415,12 @@ template <int P> struct Impl {
     tstart(x, LBDPS_K_CONTACTS);
     hipLaunchKernelGGL(k_contacts<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->cs, k, x->adj,
                        x->deg, x->done, x->ticket, x->flags, x->pair_part, x->wall0_part, x->chunk_busy,
-                       x->need_sweep);
+                       x->need_sweep, x->roots, x->rcount);
     tstop(x, LBDPS_K_CONTACTS);
     tstart(x, LBDPS_K_RESOLVE);
-    hipLaunchKernelGGL(k_resolve_clusters<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->adj,
-                       x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part, x->cluster_scratch);
+    hipLaunchKernelGGL(k_resolve_clusters<P>, dim3(cluster_blocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
+                       x->adj, x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part, x->cluster_scratch,
+                       x->roots, x->rcount, nblocks(N));
     hipLaunchKernelGGL(k_resolve<P>, dim3(resolve_blocks(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot, x->adj,
                        x->deg, x->done, x->ticket, k, x->flags, x->coll_part, x->wall_part, x->chunk_busy,
                        x->need_sweep);
@@ -756,7 +767,8 @@ lbdps_status lbdps_counters(lbdps_ctx *x, int64_t h_out[4]) {
   long long *src[6] = {x->pair_part, x->coll_part, x->wall_part, x->wall0_part, x->collc_part, x->wallc_part};
   const int dst[6] = {0, 1, 2, 2, 1, 2};
   const int nres = Impl<PREC_FP32>::resolve_blocks(x);
-  const int len[6] = {nbN, nres, nres, nbN, nbN, nbN};
+  const int ncl = cluster_blocks(x->n);
+  const int len[6] = {nbN, nres, nres, nbN, ncl, ncl};
   for (int j = 0; j < 4; ++j) h_out[j] = 0;
   if (x->n > 0)
     for (int j = 0; j < 6; ++j) {

@@ -12,6 +12,7 @@ import math
 import numpy as np
 import pytest
 
+import storage_repr
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -276,9 +277,9 @@ def test_fp32_one_step_full_size(name):
     velocity to 1e-5 max|v| plus that bound over the particle mass."""
     cfg = getattr(synth, name)()
     say("workload", cfg["name"])
-    warm = L.Sim(cfg, precision="fp32")
-    warm.step(20)  # develop flow and velocities on the GPU, then hand the state to both sides
-    f, pos, vel, _ = warm.state()
+    warm = oracle.Sim(cfg)
+    warm.run(20)  # develop flow and velocities, then hand the FP32-held state to both sides
+    f, pos, vel = storage_repr.state(cfg, warm.f, warm.pos, warm.vel, "fp32")
     del warm
     gpu = L.Sim(cfg, precision="fp32", diagnostics=True)
     gpu.set_state(f, pos, vel)

@@ -1,0 +1,150 @@
+"""Precision pattern: the populations stored as FP16 or BF16 deviations from
+the lattice weights with FP32 arithmetic, and plain FP32, against the FP64
+oracle on the 64x512 riser crop (31 250 spheres, walls at x, periodic in y,
+gas driven by a body force).  All runs start from the state the library holds
+in its FP32-position modes: gas at rest in equilibrium (exact in every
+format), positions as cell + float32 offset, zero velocities.
+
+Two measures, printed as a table and written as JSON to $LBDPS_STUDY_OUT when
+that is set:
+- pointwise: norm-wise error max|x - ref| / max|ref| of the gas fields and the
+  populations, and the largest position error in cells (minimum image), after
+  10, 100 and 1000 free-running steps;
+- statistics: time averages over steps 1000-5000 sampled every 10 steps
+  (column solid fraction phi(x), mean gas u_y, mean particle v_y, mean slip)
+  against the oracle's values in tests/golden/precision_riser_crop_stats.json,
+  beside the FP64 library path's own distance from them: the collisions make
+  the particle system chaotic, so after a few hundred steps any rounding
+  difference, even the FP64 path's few-ulp one, decorrelates the trajectories
+  and only statistics remain comparable.
+
+The bounds asserted below are the stated errors of the precision pattern.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import storage_repr
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+L = pytest.importorskip("paper_1303_2653_amd.lbdps")
+import oracle  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+POINTS = (10, 100, 1000)
+STEPS, START, EVERY = 5000, 1000, 10
+PRECS = ("fp32", "fp16", "bf16")
+
+# stated pointwise bounds (gas fields and populations, norm-wise) at step 10
+BOUND10 = {"fp32": 1e-4, "fp16": 2e-2, "bf16": 2e-1}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def nrel(a, b, floor=0.0):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), floor))
+
+
+def pos_err(a, b, ny):
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    d[:, 1] = np.minimum(d[:, 1], ny - d[:, 1])  # periodic in y
+    return float(d.max())
+
+
+@pytest.fixture(scope="module")
+def crop():
+    cfg = synth.riser_crop()
+    f0, pos0, vel0 = storage_repr.state(cfg, oracle.equilibrium_state(cfg["nx"], cfg["ny"]), cfg["pos"],
+                                        cfg["vel"], "fp32")
+    sim = oracle.Sim(cfg, f=f0, pos=pos0, vel=vel0)
+    snaps = {}
+    for k in range(1, max(POINTS) + 1):
+        out = sim.step(record=k in POINTS)
+        if k in POINTS:
+            snaps[k] = dict(f=sim.f.copy(), pos=sim.pos.copy(), vel=sim.vel.copy(), rho=out.rho.copy(),
+                            ugas=out.ugas.copy(), fpg=out.fpg.copy(), beta=out.beta.copy())
+    say("oracle snapshots done")
+    with open(os.path.join(HERE, "golden", "precision_riser_crop_stats.json")) as fh:
+        stats = json.load(fh)
+    return cfg, (f0, pos0, vel0), snaps, stats
+
+
+def run(cfg, state, prec, snaps):
+    gpu = L.Sim(cfg, precision=prec)
+    gpu.set_state(*state)
+    point, done = {}, 0
+    acc_phi, acc_uy, acc_vy, ns = np.zeros(cfg["nx"]), 0.0, 0.0, 0
+    area = math.pi * cfg["d"] ** 2 / 4
+    for k in list(POINTS) + list(range(START, STEPS + 1, EVERY)):
+        if k <= done:
+            if k != done:
+                continue
+        else:
+            gpu.step(k - done)
+            done = k
+        need_fields = k in POINTS or (k >= START and (k - START) % EVERY == 0)
+        if not need_fields:
+            continue
+        fl = gpu.fields()
+        f, pos, vel, _ = gpu.state()
+        if k in POINTS and k not in point:
+            s = snaps[k]
+            point[k] = dict(f=nrel(f, s["f"], 1.0), rho=nrel(fl["rho"], s["rho"], 1.0), ugas=nrel(fl["ugas"], s["ugas"]),
+                            fpg=nrel(fl["fpg"], s["fpg"]), beta=nrel(fl["beta"], s["beta"]),
+                            pos_cells=pos_err(pos, s["pos"], cfg["ny"]), vel=nrel(vel, s["vel"]))
+        if k >= START and (k - START) % EVERY == 0:
+            col = np.bincount(np.floor(pos[:, 0]).astype(np.int64), minlength=cfg["nx"])[:cfg["nx"]]
+            acc_phi += col * area / cfg["ny"]
+            acc_uy += float(np.mean(fl["ugas"][:, 1]))
+            acc_vy += float(np.mean(vel[:, 1]))
+            ns += 1
+    stats = dict(phi_x=acc_phi / ns, mean_uy=acc_uy / ns, mean_vy=acc_vy / ns, mean_slip=(acc_uy - acc_vy) / ns,
+                 samples=ns)
+    assert np.isfinite(f).all() and np.isfinite(vel).all()
+    return point, stats
+
+
+def stat_errors(st, ref):
+    phi_ref = np.asarray(ref["phi_x"])
+    return dict(phi_x=float(np.abs(st["phi_x"] - phi_ref).max() / phi_ref.max()),
+                mean_uy=abs(st["mean_uy"] - ref["mean_uy"]) / abs(ref["mean_uy"]),
+                mean_vy=abs(st["mean_vy"] - ref["mean_vy"]) / max(abs(ref["mean_vy"]), 1e-30),
+                mean_slip=abs(st["mean_slip"] - ref["mean_slip"]) / abs(ref["mean_slip"]))
+
+
+def test_precision_pattern(crop):
+    cfg, state, snaps, ref = crop
+    assert ref["samples"] == (STEPS - START) // EVERY + 1
+    report = dict(workload=cfg["name"], points=list(POINTS), stats_window=[START, STEPS, EVERY], runs={})
+    for prec in ("fp64",) + PRECS:
+        st0 = state if prec != "fp64" else state  # the FP32-position state is exact in FP64
+        point, stats = run(cfg, st0, prec, snaps)
+        se = stat_errors(stats, ref)
+        report["runs"][prec] = dict(pointwise={str(k): v for k, v in point.items()}, stats_err=se,
+                                    stats={k: (v.tolist() if isinstance(v, np.ndarray) else v)
+                                           for k, v in stats.items() if k != "phi_x"})
+        say(prec, "stats err", {k: f"{v:.2e}" for k, v in se.items()})
+        for k, v in point.items():
+            say(prec, "step", k, {a: f"{b:.2e}" for a, b in v.items()})
+    out = os.environ.get("LBDPS_STUDY_OUT")
+    if out:
+        with open(out, "w") as fh:
+            json.dump(report, fh, indent=1)
+    for prec in PRECS:
+        p10 = report["runs"][prec]["pointwise"]["10"]
+        for key in ("f", "rho", "ugas", "fpg", "beta"):
+            assert p10[key] <= BOUND10[prec], (prec, key, p10[key])
+    for prec in ("fp64",) + PRECS:
+        se = report["runs"][prec]["stats_err"]
+        assert all(np.isfinite(v) for v in se.values())
