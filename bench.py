@@ -14,6 +14,12 @@ Prints ONE JSON line:
                     region), against the 8 TB/s HBM3E peak
   cpu_baseline      the FP64 oracle timed on the host on a bounded sample
   variants          the same workload with FP16 / BF16 population storage
+
+--workload beds: the batching pattern, 64 independent beds of uneven size
+(64x256 to 256x1024, 2 000 to 200 000 spheres) with FP16 population storage,
+advanced by one launch per phase for all beds and replayed from a captured
+hipGraph; compared with the same beds stepped one after another through the
+plain single-bed FP32 path.
 """
 from __future__ import annotations
 
@@ -35,6 +41,7 @@ WORKLOADS = {
     "riser": lambda: __import__("synth").riser(),
     "riser_crop": lambda: __import__("synth").riser_crop(),
     "riser_large": lambda: __import__("synth").riser_large(),
+    "beds": lambda: __import__("synth").beds(64),
 }
 SIZES = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4), "bf16": (2, 4)}  # (population, scalar) bytes
 
@@ -200,13 +207,106 @@ def cpu_baseline(cfg, seconds):
                        f"({dt:.1f} s); particle updates/s {len(cfg['pos']) * steps / dt:.3e}")
 
 
+def time_region(torch, stream, fn):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def run_beds(args, torch, L):
+    """The batching workload: one JSON line (see the module docstring)."""
+    cfgs = WORKLOADS["beds"]()
+    prec = args.precision if args.precision_given else "fp16"
+    Cs = [c["nx"] * c["ny"] for c in cfgs]
+    Ns = [len(c["pos"]) for c in cfgs]
+    K = args.steps + (args.steps & 1)  # graphs hold an even number of steps
+    batch = L.Batch(cfgs, precision=prec)
+    st = batch.stream
+    batch.step(args.warmup)
+    batch.sync()
+    batch.time_kernels(L.KERNELS)
+    batch.step(max(4, min(K, 20)))
+    bd = batch.kernel_times()
+    breakdown = {k: ms / max(n, 1) * 1e3 for k, (ms, n) in bd.items()}
+    dom = max(breakdown, key=lambda k: breakdown[k])
+    batch.time_kernels([dom])
+    ms_eager = time_region(torch, st, lambda: batch.step(K))
+    kt = batch.kernel_times()[dom]
+    batch.time_kernels([])
+    batch.capture(K)
+    batch.launch()  # first replay: uploads the graph
+    batch.sync()
+    ms_graph = time_region(torch, st, batch.launch)
+    batch.sync()
+    pairs = [b.counters()["pairs"] for b in batch.beds]
+    batch.close()
+    del batch
+    sims = [L.Sim(c, precision="fp32") for c in cfgs]
+    for sm in sims:
+        sm.step(2)
+
+    def sequential():
+        for sm in sims:
+            sm.step(K)
+
+    ms_seq = time_region(torch, torch.cuda.current_stream(), sequential)
+    for sm in sims:
+        sm.close()
+    s = ms_graph / 1e3
+    dom_us = kt[0] / max(kt[1], 1) * 1e3
+    dom_bytes = sum(algorithmic_bytes(dom, prec, C, N, pr) for C, N, pr in zip(Cs, Ns, pairs))
+    achieved = dom_bytes / (dom_us * 1e-6) / 1e9
+    model = sum(model_bytes_per_step(prec, C, N, pr) for C, N, pr in zip(Cs, Ns, pairs))
+    line = {
+        "metric": METRIC, "value": round(sum(Cs) * K / s / 1e6, 2), "unit": "MLUPS", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(ms_graph / K, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)", "bf16": "f32 (bf16 storage)"}[prec],
+        "data": "synthetic (seeded splitmix64 beds, recipe in DESIGN.md)",
+        "config": {"workload": f"beds-64-uneven-{prec}", "beds": len(cfgs), "cells": sum(Cs), "particles": sum(Ns),
+                   "precision": prec, "launch": "hipGraph of batched phases"},
+        "particle_updates_per_s": float(f"{sum(Ns) * K / s:.4e}"),
+        "model_bytes_per_step": int(model),
+        "model_bw_frac": round(model * K / s / 1e9 / HBM_PEAK_GBS, 4),
+        "contact_pairs": int(sum(pairs)),
+        "kernel_us": {k: round(v, 2) for k, v in breakdown.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3)},
+        "batched_eager_ms_per_step": round(ms_eager / K, 5),
+        "sequential_fp32_ms_per_step": round(ms_seq / K, 5),
+        "speedup_vs_sequential_fp32": round(ms_seq / ms_graph, 3),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t0, cells, n = time.perf_counter(), 0, 0
+        sims_o = []
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            if n < len(cfgs):
+                sims_o.append(oracle.Sim(cfgs[n]))
+            o = sims_o[n % len(cfgs)]
+            o.step()
+            cells += o.p.nx * o.p.ny
+            n += 1
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = dict(value=round(cells / dt / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
+                                    sample=f"first coupled step of beds 0..{min(n, len(cfgs)) - 1} in turn, FP64, "
+                                           f"single thread ({n} bed-steps, {dt:.1f} s)")
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="bubble", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=sorted(SIZES))
+    ap.add_argument("--precision", default=None, choices=sorted(SIZES))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -222,6 +322,9 @@ def main():
     ap.add_argument("--label", default="profile")
     ap.add_argument("--command", default="")
     args = ap.parse_args()
+    args.precision_given = args.precision is not None
+    if args.precision is None:
+        args.precision = "fp32"
     if args.summarize:
         summarize(args)
         return
@@ -243,6 +346,9 @@ def main():
         return
     from paper_1303_2653_amd import lbdps as L
 
+    if args.workload == "beds":
+        print(json.dumps(run_beds(args, torch, L)), flush=True)
+        return
     cfg = WORKLOADS[args.workload]()
     C, N = cfg["nx"] * cfg["ny"], len(cfg["pos"])
     r = run_gpu(cfg, args.precision, args.steps, args.warmup, torch, L)

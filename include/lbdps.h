@@ -212,8 +212,65 @@ lbdps_status lbdps_time_kernels(lbdps_ctx *ctx, uint32_t mask);
  */
 lbdps_status lbdps_kernel_times(lbdps_ctx *ctx, double *h_ms, int64_t *h_launches);
 
-/* Release the host context (the workspace stays the caller's). */
+/* Release the host context (the workspace stays the caller's).  A bed of a
+ * batch is released by lbdps_batch_destroy instead (LBDPS_E_INVALID here). */
 lbdps_status lbdps_destroy(lbdps_ctx *ctx);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent beds (uneven lattices and particle counts; each with its own
+ * parameters, boundary faces and inlet profile, one precision for all) advance
+ * together: each phase of the step of Sec. 2.4 is one launch for every bed.
+ * Every bed is an ordinary context (lbdps_batch_bed) for set_state and the
+ * get_* / conservation / counters calls; lbdps_step on it steps that bed alone.
+ * Beds do not record diagnostics.  A batch is not thread-safe.
+ */
+typedef struct lbdps_batch lbdps_batch;
+
+/* Workspace for a batch: two small launch tables, then each bed's workspace. */
+lbdps_status lbdps_batch_workspace_bytes(const lbdps_params *beds, int32_t nbeds, const int64_t *max_particles,
+                                         size_t *bytes);
+
+/*
+ * beds[nbeds], max_particles[nbeds]: as for lbdps_create, per bed.
+ * h_inlet_uy: NULL, or nbeds host pointers (each NULL or [nx] of that bed).
+ * d_workspace: caller-owned device memory of lbdps_batch_workspace_bytes,
+ * 256-byte aligned.  stream: hipStream_t for every launch of the batch; graph
+ * capture needs a stream other than the null stream.  Each bed starts as
+ * lbdps_create leaves a context (gas at rest, no particles).  Synchronises.
+ */
+lbdps_status lbdps_batch_create(const lbdps_params *beds, int32_t nbeds, const int64_t *max_particles,
+                                const double *const *h_inlet_uy, void *d_workspace, size_t bytes, void *stream,
+                                lbdps_batch **out);
+
+/* The context of bed `bed` (owned by the batch). */
+lbdps_status lbdps_batch_bed(lbdps_batch *batch, int32_t bed, lbdps_ctx **out);
+
+/* Enqueue nsteps steps of every bed: 7 launches per step for the whole batch.
+ * Results equal nsteps calls of lbdps_step on each bed, bit for bit. */
+lbdps_status lbdps_batch_step(lbdps_batch *batch, int32_t nsteps);
+
+/*
+ * Capture nsteps batched steps (even, >= 2) into a hipGraph on the batch's
+ * stream.  The graph holds the beds' particle counts and buffer parities of
+ * this moment: lbdps_batch_launch refuses to replay it once a bed has been
+ * changed otherwise (set_state, lbdps_step, lbdps_batch_step with an odd count).
+ */
+lbdps_status lbdps_batch_capture(lbdps_batch *batch, int32_t nsteps);
+
+/* Replay the captured graph: nsteps more steps of every bed. */
+lbdps_status lbdps_batch_launch(lbdps_batch *batch);
+
+/* Wait for the stream; report the first bed's latched device error. */
+lbdps_status lbdps_batch_sync(lbdps_batch *batch);
+
+/* As lbdps_time_kernels / lbdps_kernel_times, for the batched launches of
+ * lbdps_batch_step (each timed launch covers every bed; graph replays are not
+ * timed).  LBDPS_K_RESOLVE covers both resolution launches. */
+lbdps_status lbdps_batch_time_kernels(lbdps_batch *batch, uint32_t mask);
+lbdps_status lbdps_batch_kernel_times(lbdps_batch *batch, double *h_ms, int64_t *h_launches);
+
+/* Release the batch and its beds' contexts (the workspace stays the caller's). */
+lbdps_status lbdps_batch_destroy(lbdps_batch *batch);
 
 const char *lbdps_status_str(lbdps_status s);
 const char *lbdps_last_error(void);

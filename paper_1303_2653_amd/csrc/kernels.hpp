@@ -314,7 +314,7 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long *sh) {
 // neighbours with the boundary rules (bounce-back, equilibrium inlet,
 // zero-gradient outlet).
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__restrict__ fsrc,
+__device__ __forceinline__ void collide_body(const int bidx, const int gdim, const typename Prec<P>::S *__restrict__ fsrc,
                                                    typename Prec<P>::S *__restrict__ fdst,
                                                    Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs,
                                                    Parts<typename Prec<P>::T> pt,
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
   __shared__ T sl[LUT_ROWS_MAX * LUT_W];  // the per-count table
   for (int i = threadIdx.x; i < min(k.nlut, LUT_ROWS_MAX) * LUT_W; i += BLOCK) sl[i] = lut[i];
   __syncthreads();
-  const int c = blockIdx.x * BLOCK + threadIdx.x;
+  const int c = bidx * BLOCK + threadIdx.x;
   if (c >= k.C) return;
   const int x = c % k.nx, y = c / k.nx;
   const size_t C = (size_t)k.C;
@@ -535,6 +535,17 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
     }
   }
 }
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__restrict__ fsrc,
+                                                   typename Prec<P>::S *__restrict__ fdst,
+                                                   Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs,
+                                                   Parts<typename Prec<P>::T> pt,
+                                                   const typename Prec<P>::T *__restrict__ lut,
+                                                   const typename Prec<P>::T *__restrict__ inlet,
+                                                   Consts<typename Prec<P>::T> k, int32_t *dg_n,
+                                                   typename Prec<P>::T *dg_vsx, typename Prec<P>::T *dg_vsy) {
+  collide_body<P>(blockIdx.x, gridDim.x, fsrc, fdst, fl, cs, pt, lut, inlet, k, dg_n, dg_vsx, dg_vsy);
+}
 
 // ------------------------------------------------------------------ A4 + A5: drag and integration, fused with binning
 // One thread per cell, looping over its particles (ascending index).  Pass 1
@@ -597,7 +608,7 @@ template <int P> struct Interp {
 
 // Workgroup = one DTX x DTY tile of cells, one thread per cell.
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
+__device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
                                                 const int32_t *__restrict__ cs,
                                                 const typename Prec<P>::T *__restrict__ lut,
                                                 Consts<typename Prec<P>::T> k, int32_t *__restrict__ count,
@@ -609,7 +620,7 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
   __shared__ int hist[HIST_MAX];
   __shared__ DragTile<P> D;
   const int ntx = (k.nx + DTX - 1) / DTX;
-  const int tx0 = (blockIdx.x % ntx) * DTX, ty0 = (blockIdx.x / ntx) * DTY;
+  const int tx0 = (bidx % ntx) * DTX, ty0 = (bidx / ntx) * DTY;
   const int cx = tx0 + (int)threadIdx.x % DTX, cy = ty0 + (int)threadIdx.x / DTX;
   const int c = cy * k.nx + cx;
   const bool inside = cx < k.nx && cy < k.ny;
@@ -617,7 +628,7 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
   const int n = a1 - a0;
   // a tile without particles has nothing to do
   if (!__syncthreads_or(n > 0)) {
-    if (zero_part && threadIdx.x == 0) zero_part[blockIdx.x] = 0;
+    if (zero_part && threadIdx.x == 0) zero_part[bidx] = 0;
     return;
   }
   // this thread's particles (short segments), loaded while the tile is staged
@@ -738,8 +749,18 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
   }
   if (zero_part) {
     const long long t = block_sum_ll(nzero, sh);
-    if (threadIdx.x == 0) zero_part[blockIdx.x] = t;
+    if (threadIdx.x == 0) zero_part[bidx] = t;
   }
+}
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
+                                                const int32_t *__restrict__ cs,
+                                                const typename Prec<P>::T *__restrict__ lut,
+                                                Consts<typename Prec<P>::T> k, int32_t *__restrict__ count,
+                                                int32_t *__restrict__ rank, int32_t *flags,
+                                                typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy,
+                                                long long *zero_part, TileSums ts) {
+  drag_body<P>(blockIdx.x, gridDim.x, pt, fl, cs, lut, k, count, rank, flags, dg_fdx, dg_fdy, zero_part, ts);
 }
 
 // ------------------------------------------------------------------ A1: binning (counting sort by cell, then particle index)
@@ -754,11 +775,11 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const int32_t *__restrict__ key, 
 // storage and record the slot of each particle index.  Clears the tile sums
 // for the next binning.
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, const int32_t *__restrict__ rank,
+__device__ __forceinline__ void scatter_body(const int bidx, const int gdim, Parts<T> src, Parts<T> dst, const int32_t *__restrict__ rank,
                                                    const int32_t *__restrict__ cs, int n, int32_t *__restrict__ slot,
                                                    TileSums ts) {
-  const int s = blockIdx.x * BLOCK + threadIdx.x;
-  for (int i = s; i < ts.ntiles; i += gridDim.x * BLOCK) ts.tile[i] = 0;
+  const int s = bidx * BLOCK + threadIdx.x;
+  for (int i = s; i < ts.ntiles; i += gdim * BLOCK) ts.tile[i] = 0;
   if (s >= n) return;
   const int key = src.key[s];
   const int d = cs[key] + rank[s];
@@ -771,6 +792,12 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, c
   dst.vy[d] = src.vy[s];
   slot[id] = d;
 }
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, const int32_t *__restrict__ rank,
+                                                   const int32_t *__restrict__ cs, int n, int32_t *__restrict__ slot,
+                                                   TileSums ts) {
+  scatter_body<T>(blockIdx.x, gridDim.x, src, dst, rank, cs, n, slot, ts);
+}
 
 // ------------------------------------------------------------------ A6: contact detection
 // One thread per particle slot.  Candidates come from the 3x3 cells around the
@@ -782,7 +809,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, c
 // without contacts gets its wall collision here; the others get it after their
 // binary collisions.
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
+__device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
                                                     Consts<typename Prec<P>::T> k, long long *__restrict__ adj,
                                                     int32_t *__restrict__ deg, int32_t *__restrict__ done,
                                                     int32_t *ticket, int32_t *flags, long long *pair_part,
@@ -792,7 +819,7 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
   using T = typename Prec<P>::T;
   __shared__ long long sh[BLOCK / 64];
   __shared__ int shi[BLOCK / 64];
-  const int s = blockIdx.x * BLOCK + threadIdx.x;
+  const int s = bidx * BLOCK + threadIdx.x;
   long long fwd = 0, nwall = 0;
   bool cand = false;  // has contacts, all with higher indices: a possible cluster root
   if (s == 0) {
@@ -931,14 +958,24 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
   // candidate roots of this workgroup, compacted to the front of its segment
   int nc;
   const int off = block_excl_scan(cand ? 1 : 0, shi, nc);
-  if (cand) roots[(size_t)blockIdx.x * BLOCK + off] = s;
+  if (cand) roots[(size_t)bidx * BLOCK + off] = s;
   const long long t = block_sum_ll(fwd, sh);
   const long long tw = block_sum_ll(nwall, sh);
   if (threadIdx.x == 0) {
-    pair_part[blockIdx.x] = t;
-    wall_part[blockIdx.x] = tw;
-    rcount[blockIdx.x] = nc;
+    pair_part[bidx] = t;
+    wall_part[bidx] = tw;
+    rcount[bidx] = nc;
   }
+}
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
+                                                    Consts<typename Prec<P>::T> k, long long *__restrict__ adj,
+                                                    int32_t *__restrict__ deg, int32_t *__restrict__ done,
+                                                    int32_t *ticket, int32_t *flags, long long *pair_part,
+                                                    long long *wall_part, int32_t *__restrict__ chunk_busy,
+                                                    int32_t *need_sweep, int32_t *__restrict__ roots,
+                                                    int32_t *__restrict__ rcount) {
+  contacts_body<P>(blockIdx.x, gridDim.x, pt, cs, k, adj, deg, done, ticket, flags, pair_part, wall_part, chunk_busy, need_sweep, roots, rcount);
 }
 
 // ------------------------------------------------------------------ A7: collision resolution (Eqs. 17-18) and walls
@@ -1079,7 +1116,7 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typen
 }
 
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<P>::T> pt,
+__device__ __forceinline__ void resolve_clusters_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
                                                             const long long *__restrict__ adj,
                                                             const int32_t *__restrict__ deg, int32_t *done,
                                                             Consts<typename Prec<P>::T> k, int32_t *need_sweep,
@@ -1092,8 +1129,8 @@ __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<
   __shared__ int pre[BLOCK + 1];
   __shared__ long long qs[CL_LDS * BLOCK];
   // candidate lists [b0, b0 + nb) of the contact kernel's workgroups
-  const int per = (nlists + gridDim.x - 1) / gridDim.x;  // <= BLOCK (host grid choice)
-  const int b0 = blockIdx.x * per;
+  const int per = (nlists + gdim - 1) / gdim;  // <= BLOCK (host grid choice)
+  const int b0 = bidx * per;
   const int nb = max(0, min(nlists - b0, per));
   int tot;
   const int c = (int)threadIdx.x < nb ? rcount[b0 + threadIdx.x] : 0;
@@ -1102,7 +1139,7 @@ __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<
   if (threadIdx.x == 0) pre[nb] = tot;
   __syncthreads();
   const LdsColumn ql{qs + threadIdx.x};
-  const MemRow qg{scratch + ((size_t)blockIdx.x * BLOCK + threadIdx.x) * CLUSTER_MAX};
+  const MemRow qg{scratch + ((size_t)bidx * BLOCK + threadIdx.x) * CLUSTER_MAX};
   long long ncoll = 0, nwall = 0;
   for (int f = threadIdx.x; f < tot; f += BLOCK) {
     int lo = 0, hi = nb;  // list j with pre[j] <= f < pre[j + 1]
@@ -1125,9 +1162,20 @@ __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<
   const long long tc = block_sum_ll(ncoll, sh);
   const long long tw = block_sum_ll(nwall, sh);
   if (threadIdx.x == 0) {
-    coll_part[blockIdx.x] = tc;
-    wall_part[blockIdx.x] = tw;
+    coll_part[bidx] = tc;
+    wall_part[bidx] = tw;
   }
+}
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<P>::T> pt,
+                                                            const long long *__restrict__ adj,
+                                                            const int32_t *__restrict__ deg, int32_t *done,
+                                                            Consts<typename Prec<P>::T> k, int32_t *need_sweep,
+                                                            long long *coll_part, long long *wall_part,
+                                                            long long *__restrict__ scratch,
+                                                            const int32_t *__restrict__ roots,
+                                                            const int32_t *__restrict__ rcount, int nlists) {
+  resolve_clusters_body<P>(blockIdx.x, gridDim.x, pt, adj, deg, done, k, need_sweep, coll_part, wall_part, scratch, roots, rcount, nlists);
 }
 
 // Position of particle index g in the neighbour list of slot t: the number of
@@ -1142,7 +1190,7 @@ __device__ __forceinline__ int row_position(const long long *adj, const int32_t 
 
 
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
+__device__ __forceinline__ void resolve_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
                                                    const long long *__restrict__ adj, const int32_t *__restrict__ deg,
                                                    int32_t *done, int32_t *ticket, Consts<typename Prec<P>::T> k,
                                                    int32_t *flags, long long *coll_part, long long *wall_part,
@@ -1156,10 +1204,10 @@ __global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt
   // atomic ticket; chunks that hold no particle with a contact are skipped.
   const int nchunks = (k.npart + RES_CHUNK - 1) / RES_CHUNK;
   if (!*need_sweep) {  // every cluster was resolved whole: only clear the chunk marks
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < nchunks; i += gridDim.x * BLOCK) chunk_busy[i] = 0;
+    for (int i = bidx * BLOCK + threadIdx.x; i < nchunks; i += gdim * BLOCK) chunk_busy[i] = 0;
     if (threadIdx.x == 0) {
-      coll_part[blockIdx.x] = 0;
-      wall_part[blockIdx.x] = 0;
+      coll_part[bidx] = 0;
+      wall_part[bidx] = 0;
     }
     return;
   }
@@ -1254,9 +1302,17 @@ __global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt
   const long long tc = block_sum_ll(ncoll, sh);
   const long long tw = block_sum_ll(nwall, sh);
   if (threadIdx.x == 0) {
-    coll_part[blockIdx.x] = tc;
-    wall_part[blockIdx.x] = tw;
+    coll_part[bidx] = tc;
+    wall_part[bidx] = tw;
   }
+}
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
+                                                   const long long *__restrict__ adj, const int32_t *__restrict__ deg,
+                                                   int32_t *done, int32_t *ticket, Consts<typename Prec<P>::T> k,
+                                                   int32_t *flags, long long *coll_part, long long *wall_part,
+                                                   int32_t *__restrict__ chunk_busy, const int32_t *need_sweep) {
+  resolve_body<P>(blockIdx.x, gridDim.x, pt, slot, adj, deg, done, ticket, k, flags, coll_part, wall_part, chunk_busy, need_sweep);
 }
 
 // ------------------------------------------------------------------ exclusive scan of int32
@@ -1265,10 +1321,10 @@ __global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt
 // Cell starts in one pass: the tile sums were accumulated while counting, so
 // each workgroup adds the sums of all tiles before its own (a strided sum),
 // scans its SCAN_TILE counts, writes cell_start and clears the counts.
-__global__ __launch_bounds__(BLOCK) void k_scan_cells(int32_t *__restrict__ count, long long n, TileSums ts,
+__device__ __forceinline__ void scan_cells_body(const int bidx, const int gdim, int32_t *__restrict__ count, long long n, TileSums ts,
                                                       int32_t *__restrict__ out) {
   __shared__ int sh[BLOCK / 64];
-  const int b = blockIdx.x;
+  const int b = bidx;
   int v = 0;
 #pragma unroll 8
   for (int i = threadIdx.x; i < b; i += BLOCK) v += ts.tile[i];
@@ -1291,7 +1347,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan_cells(int32_t *__restrict__ coun
       run += vals[j];
       count[e0 + j] = 0;
     }
-  if (b == gridDim.x - 1 && threadIdx.x == 0) out[n] = base + total;
+  if (b == gdim - 1 && threadIdx.x == 0) out[n] = base + total;
+}
+__global__ __launch_bounds__(BLOCK) void k_scan_cells(int32_t *__restrict__ count, long long n, TileSums ts,
+                                                      int32_t *__restrict__ out) {
+  scan_cells_body(blockIdx.x, gridDim.x, count, n, ts, out);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int32_t *__restrict__ in, long long n,

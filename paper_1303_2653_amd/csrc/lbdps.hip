@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "lbdps.h"
 
@@ -154,6 +155,7 @@ struct lbdps_ctx {
   int cf = 0, cp = 0;
   bool bins_valid = false;
   long long step = 0;
+  bool in_batch = false;  // owned by a batch: destroyed with it
   DConsts dc{};
   // device buffers (carved from the workspace)
   void *f[2]{};
@@ -814,7 +816,423 @@ lbdps_status lbdps_kernel_times(lbdps_ctx *x, double *h_ms, int64_t *h_launches)
 
 lbdps_status lbdps_destroy(lbdps_ctx *x) {
   if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (x->in_batch) return fail(LBDPS_E_INVALID, "a bed of a batch is destroyed with the batch");
   delete x;
+  return LBDPS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches of beds
+struct lbdps_batch {
+  int nbeds = 0, prec = 0;
+  std::vector<lbdps_ctx *> beds;
+  hipStream_t stream = nullptr;
+  // two device tables (eager stepping, captured graph), each: BedArgs[nbeds], then off[PH_COUNT][nbeds + 1]
+  char *d_tab[2]{};
+  size_t tab_bytes = 0, args_bytes = 0;
+  char *h_tab = nullptr;  // pinned staging copy of a table
+  hipEvent_t tab_done = nullptr;
+  bool tab_inflight = false;
+  int total[2][PH_COUNT]{};
+  // bed state the graph's table describes
+  std::vector<int> snap_cf, snap_cp;
+  std::vector<long long> snap_n;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_steps = 0;
+  // per-kernel event timing of eager batched steps
+  uint32_t timed = 0;
+  std::vector<lbdps_ctx::Mark> marks;
+  size_t nmarks = 0;
+  ~lbdps_batch() {
+    for (auto &m : marks) {
+      (void)hipEventDestroy(m.a);
+      (void)hipEventDestroy(m.b);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (tab_done) (void)hipEventDestroy(tab_done);
+    if (h_tab) (void)hipHostFree(h_tab);
+    for (auto *b : beds) delete b;
+  }
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+template <int P> struct BatchImpl {
+  using T = typename Prec<P>::T;
+  using S = typename Prec<P>::S;
+  using I = Impl<P>;
+
+  static size_t args_bytes(int nbeds) { return align256((size_t)nbeds * sizeof(BedArgs<P>)); }
+  static size_t table_bytes(int nbeds) { return args_bytes(nbeds) + align256((size_t)PH_COUNT * (nbeds + 1) * 4); }
+
+  static BedArgs<P> args(const lbdps_ctx *x) {
+    BedArgs<P> a{};
+    a.k = I::consts(x);
+    for (int b = 0; b < 2; ++b) {
+      a.f[b] = (S *)x->f[b];
+      a.key[b] = x->key[b];
+      a.pid[b] = x->pid[b];
+      a.px[b] = (T *)x->px[b];
+      a.py[b] = (T *)x->py[b];
+      a.vx[b] = (T *)x->vx[b];
+      a.vy[b] = (T *)x->vy[b];
+    }
+    a.fl = I::fields(x);
+    a.lut = (const T *)x->lut;
+    a.inlet = (const T *)x->inlet;
+    a.cs = x->cs;
+    a.count = x->count;
+    a.rank = x->rank;
+    a.slot = x->slot;
+    a.flags = x->flags;
+    a.deg = x->deg;
+    a.done = x->done;
+    a.ticket = x->ticket;
+    a.chunk_busy = x->chunk_busy;
+    a.need_sweep = x->need_sweep;
+    a.roots = x->roots;
+    a.rcount = x->rcount;
+    a.adj = x->adj;
+    a.pair_part = x->pair_part;
+    a.wall0_part = x->wall0_part;
+    a.coll_part = x->coll_part;
+    a.wall_part = x->wall_part;
+    a.collc_part = x->collc_part;
+    a.wallc_part = x->wallc_part;
+    a.scratch = x->cluster_scratch;
+    a.ts = I::tiles(x);
+    a.cf = x->cf;
+    a.cp = x->cp;
+    a.cp_moves = x->n > 0;
+    a.nlists = nblocks(x->n);
+    return a;
+  }
+
+  // Workgroups of each phase for one bed, as the single-bed step launches them.
+  static void blocks(const lbdps_ctx *x, int nb[PH_COUNT]) {
+    for (int i = 0; i < PH_COUNT; ++i) nb[i] = 0;
+    nb[PH_COLLIDE] = nblocks(x->C);
+    if (x->n == 0) return;
+    nb[PH_DRAG] = I::drag_tiles(x);
+    nb[PH_SCAN] = x->ntiles;
+    nb[PH_SCATTER] = nblocks(x->n);
+    nb[PH_CONTACTS] = nblocks(x->n);
+    nb[PH_CLUSTERS] = cluster_blocks(x->n);
+    nb[PH_RESOLVE] = I::resolve_blocks(x);
+  }
+
+  // Fills table t (0 eager, 1 graph) from the beds' current state.
+  static lbdps_status write_table(lbdps_batch *B, int t) {
+    if (B->tab_inflight) {
+      lbdps_status st = check_hip(hipEventSynchronize(B->tab_done), "batch table");
+      if (st != LBDPS_OK) return st;
+      B->tab_inflight = false;
+    }
+    BedArgs<P> *a = (BedArgs<P> *)B->h_tab;
+    int *off = (int *)(B->h_tab + B->args_bytes);
+    const int nb1 = B->nbeds + 1;
+    for (int ph = 0; ph < PH_COUNT; ++ph) off[ph * nb1] = 0;
+    for (int b = 0; b < B->nbeds; ++b) {
+      const lbdps_ctx *x = B->beds[b];
+      a[b] = args(x);
+      int nb[PH_COUNT];
+      blocks(x, nb);
+      for (int ph = 0; ph < PH_COUNT; ++ph) {
+        const long long v = (long long)off[ph * nb1 + b] + nb[ph];
+        if (v > 0x7fffffffll) return fail(LBDPS_E_SHAPE, "batch too large for one launch per phase");
+        off[ph * nb1 + b + 1] = (int)v;
+      }
+    }
+    for (int ph = 0; ph < PH_COUNT; ++ph) B->total[t][ph] = off[ph * nb1 + B->nbeds];
+    lbdps_status st = check_hip(hipMemcpyAsync(B->d_tab[t], B->h_tab, B->tab_bytes, hipMemcpyHostToDevice, B->stream),
+                                "batch table upload");
+    if (st != LBDPS_OK) return st;
+    st = check_hip(hipEventRecord(B->tab_done, B->stream), "batch table upload");
+    B->tab_inflight = st == LBDPS_OK;
+    return st;
+  }
+
+  // Event bracket of kernel k of an eager batched step (k as in lbdps_kernel).
+  static void bstart(lbdps_batch *B, bool timing, int k) {
+    if (!timing || !(B->timed >> k & 1u)) return;
+    if (B->nmarks == B->marks.size()) {
+      lbdps_ctx::Mark m{};
+      if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess) return;
+      B->marks.push_back(m);
+    }
+    B->marks[B->nmarks].k = k;
+    (void)hipEventRecord(B->marks[B->nmarks].a, B->stream);
+  }
+  static void bstop(lbdps_batch *B, bool timing, int k) {
+    if (!timing || !(B->timed >> k & 1u) || B->nmarks >= B->marks.size() || B->marks[B->nmarks].k != k) return;
+    (void)hipEventRecord(B->marks[B->nmarks].b, B->stream);
+    B->nmarks += 1;
+  }
+
+  static void launch_steps(lbdps_batch *B, int t, int nsteps) {
+    const BedArgs<P> *tab = (const BedArgs<P> *)B->d_tab[t];
+    const int *off = (const int *)(B->d_tab[t] + B->args_bytes);
+    const int nb1 = B->nbeds + 1, nbeds = B->nbeds;
+    const int *tot = B->total[t];
+    const bool timing = t == 0;  // never inside a captured graph
+    for (int it = 0; it < nsteps; ++it) {
+      const int flip = it & 1;
+#define LBDPS_LAUNCH(kern, ph)                                                                                      \
+  if (tot[ph] > 0)                                                                                                  \
+    hipLaunchKernelGGL(kern<P>, dim3(tot[ph]), dim3(BLOCK), 0, B->stream, tab, off + (ph) * nb1, nbeds, flip);
+      bstart(B, timing, LBDPS_K_COLLIDE);
+      LBDPS_LAUNCH(kb_collide, PH_COLLIDE)
+      bstop(B, timing, LBDPS_K_COLLIDE);
+      bstart(B, timing, LBDPS_K_DRAG);
+      LBDPS_LAUNCH(kb_drag, PH_DRAG)
+      bstop(B, timing, LBDPS_K_DRAG);
+      bstart(B, timing, LBDPS_K_SCAN);
+      LBDPS_LAUNCH(kb_scan, PH_SCAN)
+      bstop(B, timing, LBDPS_K_SCAN);
+      bstart(B, timing, LBDPS_K_SCATTER);
+      LBDPS_LAUNCH(kb_scatter, PH_SCATTER)
+      bstop(B, timing, LBDPS_K_SCATTER);
+      bstart(B, timing, LBDPS_K_CONTACTS);
+      LBDPS_LAUNCH(kb_contacts, PH_CONTACTS)
+      bstop(B, timing, LBDPS_K_CONTACTS);
+      bstart(B, timing, LBDPS_K_RESOLVE);
+      LBDPS_LAUNCH(kb_clusters, PH_CLUSTERS)
+      LBDPS_LAUNCH(kb_resolve, PH_RESOLVE)
+      bstop(B, timing, LBDPS_K_RESOLVE);
+#undef LBDPS_LAUNCH
+    }
+  }
+
+  static void advance(lbdps_batch *B, int nsteps) {
+    for (auto *x : B->beds) {
+      x->cf ^= nsteps & 1;
+      if (x->n > 0) x->cp ^= nsteps & 1;
+      x->step += nsteps;
+    }
+  }
+
+  static void rebin_all(lbdps_batch *B) {
+    for (auto *x : B->beds)
+      if (!x->bins_valid) I::rebin(x);
+  }
+
+  static lbdps_status step(lbdps_batch *B, int nsteps) {
+    if (nsteps == 0) return LBDPS_OK;
+    rebin_all(B);
+    lbdps_status st = write_table(B, 0);
+    if (st != LBDPS_OK) return st;
+    launch_steps(B, 0, nsteps);
+    advance(B, nsteps);
+    return launch_status("lbdps_batch_step");
+  }
+
+  static lbdps_status capture(lbdps_batch *B, int nsteps) {
+    rebin_all(B);
+    lbdps_status st = write_table(B, 1);
+    if (st != LBDPS_OK) return st;
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->graph_steps = 0;
+    st = check_hip(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal), "lbdps_batch_capture");
+    if (st != LBDPS_OK) return st;
+    launch_steps(B, 1, nsteps);
+    hipGraph_t g = nullptr;
+    st = check_hip(hipStreamEndCapture(B->stream, &g), "lbdps_batch_capture");
+    if (st != LBDPS_OK) return st;
+    B->graph = g;
+    st = check_hip(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0), "lbdps_batch_capture");
+    if (st != LBDPS_OK) return st;
+    B->graph_steps = nsteps;
+    B->snap_cf.clear();
+    B->snap_cp.clear();
+    B->snap_n.clear();
+    for (auto *x : B->beds) {
+      B->snap_cf.push_back(x->cf);
+      B->snap_cp.push_back(x->cp);
+      B->snap_n.push_back(x->n);
+    }
+    return LBDPS_OK;
+  }
+};
+
+template <class F> lbdps_status dispatch_batch(int prec, F &&fn) {
+  switch (prec) {
+    case PREC_FP64: return fn(BatchImpl<PREC_FP64>{});
+    case PREC_FP32: return fn(BatchImpl<PREC_FP32>{});
+    case PREC_FP16DEV: return fn(BatchImpl<PREC_FP16DEV>{});
+    case PREC_BF16DEV: return fn(BatchImpl<PREC_BF16DEV>{});
+  }
+  return fail(LBDPS_E_INVALID, "unknown precision");
+}
+
+// Layout of a batch workspace: the two tables, then each bed's workspace.
+lbdps_status batch_layout(const lbdps_params *beds, int32_t nbeds, const int64_t *max_particles, size_t *tab,
+                          std::vector<size_t> *bed_off, size_t *total) {
+  if (!beds || !max_particles) return fail(LBDPS_E_INVALID, "beds or max_particles is NULL");
+  if (nbeds < 1) return fail(LBDPS_E_SHAPE, "nbeds must be >= 1");
+  const int prec = beds[0].precision;
+  for (int b = 0; b < nbeds; ++b) {
+    lbdps_status st = lbdps_validate_params(&beds[b], max_particles[b]);
+    if (st != LBDPS_OK) return fail(st, "bed " + std::to_string(b) + ": " + lbdps_last_error());
+    if (beds[b].precision != prec) return fail(LBDPS_E_INVALID, "all beds of a batch share one precision");
+    if (beds[b].diagnostics) return fail(LBDPS_E_UNSUPPORTED, "batched beds do not record diagnostics");
+  }
+  size_t tb = 0;
+  lbdps_status st = dispatch_batch(prec, [&](auto impl) {
+    tb = decltype(impl)::table_bytes(nbeds);
+    return LBDPS_OK;
+  });
+  if (st != LBDPS_OK) return st;
+  size_t off = 2 * tb;
+  if (bed_off) bed_off->clear();
+  for (int b = 0; b < nbeds; ++b) {
+    if (bed_off) bed_off->push_back(off);
+    off += align256(carve(beds[b], max_particles[b], nullptr, nullptr));
+  }
+  *tab = tb;
+  *total = off;
+  return LBDPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbdps_status lbdps_batch_workspace_bytes(const lbdps_params *beds, int32_t nbeds, const int64_t *max_particles,
+                                         size_t *bytes) {
+  if (!bytes) return fail(LBDPS_E_INVALID, "bytes is NULL");
+  size_t tab = 0;
+  return batch_layout(beds, nbeds, max_particles, &tab, nullptr, bytes);
+}
+
+lbdps_status lbdps_batch_create(const lbdps_params *beds, int32_t nbeds, const int64_t *max_particles,
+                                const double *const *h_inlet_uy, void *d_workspace, size_t bytes, void *stream,
+                                lbdps_batch **out) {
+  if (!out) return fail(LBDPS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  size_t tab = 0, total = 0;
+  std::vector<size_t> bed_off;
+  lbdps_status st = batch_layout(beds, nbeds, max_particles, &tab, &bed_off, &total);
+  if (st != LBDPS_OK) return st;
+  if (!d_workspace) return fail(LBDPS_E_INVALID, "workspace is NULL");
+  if (bytes < total) return fail(LBDPS_E_SHAPE, "workspace too small: need " + std::to_string(total) + " bytes");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(LBDPS_E_INVALID, "workspace must be 256-byte aligned");
+  lbdps_batch *B = new (std::nothrow) lbdps_batch();
+  if (!B) return fail(LBDPS_E_DEVICE, "host allocation failed");
+  B->nbeds = nbeds;
+  B->prec = beds[0].precision;
+  B->stream = (hipStream_t)stream;
+  B->tab_bytes = tab;
+  dispatch_batch(B->prec, [&](auto impl) {
+    B->args_bytes = decltype(impl)::args_bytes(nbeds);
+    return LBDPS_OK;
+  });
+  B->d_tab[0] = (char *)d_workspace;
+  B->d_tab[1] = (char *)d_workspace + tab;
+  st = check_hip(hipHostMalloc((void **)&B->h_tab, tab, hipHostMallocDefault), "lbdps_batch_create");
+  if (st == LBDPS_OK) st = check_hip(hipEventCreateWithFlags(&B->tab_done, hipEventDisableTiming), "lbdps_batch_create");
+  for (int b = 0; st == LBDPS_OK && b < nbeds; ++b) {
+    lbdps_ctx *x = nullptr;
+    st = lbdps_create(&beds[b], max_particles[b], (char *)d_workspace + bed_off[b], total - bed_off[b],
+                      h_inlet_uy ? h_inlet_uy[b] : nullptr, stream, &x);
+    if (st == LBDPS_OK) {
+      x->in_batch = true;
+      B->beds.push_back(x);
+    }
+  }
+  if (st != LBDPS_OK) {
+    delete B;
+    return st;
+  }
+  *out = B;
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_batch_bed(lbdps_batch *B, int32_t bed, lbdps_ctx **out) {
+  if (!B || !out) return fail(LBDPS_E_INVALID, "batch or out is NULL");
+  if (bed < 0 || bed >= B->nbeds) return fail(LBDPS_E_SHAPE, "bed index out of range");
+  *out = B->beds[bed];
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_batch_step(lbdps_batch *B, int32_t nsteps) {
+  if (!B) return fail(LBDPS_E_INVALID, "batch is NULL");
+  if (nsteps < 0) return fail(LBDPS_E_INVALID, "nsteps must be >= 0");
+  return dispatch_batch(B->prec, [&](auto impl) { return decltype(impl)::step(B, nsteps); });
+}
+
+lbdps_status lbdps_batch_capture(lbdps_batch *B, int32_t nsteps) {
+  if (!B) return fail(LBDPS_E_INVALID, "batch is NULL");
+  if (nsteps < 2 || (nsteps & 1)) return fail(LBDPS_E_INVALID, "nsteps must be even and >= 2");
+  if (!B->stream) return fail(LBDPS_E_INVALID, "capture needs a stream other than the null stream");
+  return dispatch_batch(B->prec, [&](auto impl) { return decltype(impl)::capture(B, nsteps); });
+}
+
+lbdps_status lbdps_batch_launch(lbdps_batch *B) {
+  if (!B) return fail(LBDPS_E_INVALID, "batch is NULL");
+  if (!B->exec) return fail(LBDPS_E_INVALID, "no captured graph");
+  for (int b = 0; b < B->nbeds; ++b) {
+    const lbdps_ctx *x = B->beds[b];
+    if (!x->bins_valid || x->cf != B->snap_cf[b] || x->cp != B->snap_cp[b] || x->n != B->snap_n[b])
+      return fail(LBDPS_E_INVALID, "bed " + std::to_string(b) + " changed since the capture; capture again");
+  }
+  lbdps_status st = check_hip(hipGraphLaunch(B->exec, B->stream), "lbdps_batch_launch");
+  if (st != LBDPS_OK) return st;
+  return dispatch_batch(B->prec, [&](auto impl) {
+    decltype(impl)::advance(B, B->graph_steps);
+    return LBDPS_OK;
+  });
+}
+
+lbdps_status lbdps_batch_sync(lbdps_batch *B) {
+  if (!B) return fail(LBDPS_E_INVALID, "batch is NULL");
+  for (int b = 0; b < B->nbeds; ++b) {
+    lbdps_status st = sync_and_check(B->beds[b], "lbdps_batch_sync");
+    if (st != LBDPS_OK) return fail(st, "bed " + std::to_string(b) + ": " + lbdps_last_error());
+  }
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_batch_time_kernels(lbdps_batch *B, uint32_t mask) {
+  if (!B) return fail(LBDPS_E_INVALID, "batch is NULL");
+  if (mask >> LBDPS_K_COUNT) return fail(LBDPS_E_INVALID, "unknown kernel bit in mask");
+  B->timed = mask;
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_batch_kernel_times(lbdps_batch *B, double *h_ms, int64_t *h_launches) {
+  if (!B) return fail(LBDPS_E_INVALID, "batch is NULL");
+  lbdps_status st = check_hip(hipStreamSynchronize(B->stream), "lbdps_batch_kernel_times");
+  if (st != LBDPS_OK) return st;
+  double ms[LBDPS_K_COUNT] = {0};
+  long long cnt[LBDPS_K_COUNT] = {0};
+  for (size_t i = 0; i < B->nmarks; ++i) {
+    float t = 0.f;
+    st = check_hip(hipEventElapsedTime(&t, B->marks[i].a, B->marks[i].b), "lbdps_batch_kernel_times");
+    if (st != LBDPS_OK) return st;
+    ms[B->marks[i].k] += t;
+    cnt[B->marks[i].k] += 1;
+  }
+  B->nmarks = 0;
+  for (int k = 0; k < LBDPS_K_COUNT; ++k) {
+    if (h_ms) h_ms[k] = ms[k];
+    if (h_launches) h_launches[k] = cnt[k];
+  }
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_batch_destroy(lbdps_batch *B) {
+  if (!B) return fail(LBDPS_E_INVALID, "batch is NULL");
+  (void)hipStreamSynchronize(B->stream);
+  for (auto *x : B->beds) x->in_batch = false;
+  delete B;
   return LBDPS_OK;
 }
 

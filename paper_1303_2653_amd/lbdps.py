@@ -63,6 +63,17 @@ _SIGS = {
     "lbdps_time_kernels": (c_i32, [c_vp, ctypes.c_uint32]),
     "lbdps_kernel_times": (c_i32, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
     "lbdps_destroy": (c_i32, [c_vp]),
+    "lbdps_batch_workspace_bytes": (c_i32, [_P, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbdps_batch_create": (c_i32, [_P, c_i32, ctypes.POINTER(c_i64), c_vp, c_vp, ctypes.c_size_t, c_vp,
+                                   ctypes.POINTER(c_vp)]),
+    "lbdps_batch_bed": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp)]),
+    "lbdps_batch_step": (c_i32, [c_vp, c_i32]),
+    "lbdps_batch_capture": (c_i32, [c_vp, c_i32]),
+    "lbdps_batch_launch": (c_i32, [c_vp]),
+    "lbdps_batch_sync": (c_i32, [c_vp]),
+    "lbdps_batch_time_kernels": (c_i32, [c_vp, ctypes.c_uint32]),
+    "lbdps_batch_kernel_times": (c_i32, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
+    "lbdps_batch_destroy": (c_i32, [c_vp]),
     "lbdps_status_str": (ctypes.c_char_p, [c_i32]),
     "lbdps_last_error": (ctypes.c_char_p, []),
 }
@@ -146,7 +157,19 @@ class Sim:
                            None if inlet_arr is None else inlet_arr.ctypes.data_as(c_vp),
                            self.stream.cuda_stream, ctypes.byref(ctx)), "lbdps_create")
         self.ctx = ctx
+        self._owner = None
         self.set_state(None, pos, cfg.get("vel", np.zeros_like(pos)))
+
+    @classmethod
+    def attach(cls, ctx, cfg: dict, params: lbdps_params, stream, owner):
+        """View of a context that ``owner`` (a Batch) created and releases."""
+        import torch
+        self = cls.__new__(cls)
+        self.torch = torch
+        self.cfg, self.params, self.stream, self.ctx, self._owner = cfg, params, stream, ctx, owner
+        self.nx, self.ny = params.nx, params.ny
+        self.n = self.nmax = len(np.asarray(cfg["pos"]).reshape(-1, 2))
+        return self
 
     def _dev(self, a, dtype=None):
         t = self.torch
@@ -154,11 +177,11 @@ class Sim:
 
     def set_state(self, f, pos, vel):
         t = self.torch
-        pos = self._dev(np.asarray(pos, np.float64).reshape(-1, 2))
-        vel = self._dev(np.asarray(vel, np.float64).reshape(-1, 2))
-        fd = None if f is None else self._dev(np.asarray(f, np.float64).reshape(9, self.ny, self.nx))
-        self.n = pos.shape[0]
-        with t.cuda.stream(self.stream):
+        with t.cuda.stream(self.stream):  # the uploads are ordered before the library's launches
+            pos = self._dev(np.asarray(pos, np.float64).reshape(-1, 2))
+            vel = self._dev(np.asarray(vel, np.float64).reshape(-1, 2))
+            fd = None if f is None else self._dev(np.asarray(f, np.float64).reshape(9, self.ny, self.nx))
+            self.n = pos.shape[0]
             check(lbdps_set_state(self.ctx, None if fd is None else fd.data_ptr(), pos.data_ptr(),
                                   vel.data_ptr(), self.n), "lbdps_set_state")
         self.stream.synchronize()
@@ -248,10 +271,86 @@ class Sim:
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS)}
 
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            return  # released with its batch
         if getattr(self, "ctx", None):
             self.stream.synchronize()
             lbdps_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_workspace_bytes(params, nmax) -> int:
+    out = ctypes.c_size_t(0)
+    check(lbdps_batch_workspace_bytes(params, len(params), nmax, ctypes.byref(out)), "batch_workspace_bytes")
+    return out.value
+
+
+class Batch:
+    """Independent beds stepped together: one launch per phase of the step for
+    all beds, optionally replayed from a captured hipGraph.  ``beds[i]`` is a
+    Sim view of bed i (set_state, fields, particles, state, counters ...)."""
+
+    def __init__(self, cfgs: list, precision=None, stream=None):
+        import torch
+        self.torch = torch
+        nb = len(cfgs)
+        self.params = (lbdps_params * nb)(*[make_params(c, precision) for c in cfgs])
+        self.nmax = (c_i64 * nb)(*[len(np.asarray(c["pos"]).reshape(-1, 2)) for c in cfgs])
+        nbytes = batch_workspace_bytes(self.params, self.nmax)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self._inlets = [None if c.get("inlet_uy") is None else np.ascontiguousarray(c["inlet_uy"], np.float64)
+                        for c in cfgs]
+        ptrs = (c_vp * nb)(*[None if a is None else a.ctypes.data for a in self._inlets])
+        torch.cuda.synchronize()
+        b = c_vp()
+        check(lbdps_batch_create(self.params, nb, self.nmax, ctypes.cast(ptrs, c_vp), self.ws.data_ptr(), nbytes,
+                                 self.stream.cuda_stream, ctypes.byref(b)), "lbdps_batch_create")
+        self.batch = b
+        self.beds = []
+        for i, c in enumerate(cfgs):
+            ctx = c_vp()
+            check(lbdps_batch_bed(b, i, ctypes.byref(ctx)), "lbdps_batch_bed")
+            sim = Sim.attach(ctx, c, self.params[i], self.stream, self)
+            pos = np.asarray(c["pos"], np.float64).reshape(-1, 2)
+            sim.set_state(None, pos, c.get("vel", np.zeros_like(pos)))
+            self.beds.append(sim)
+
+    def step(self, nsteps: int = 1):
+        check(lbdps_batch_step(self.batch, int(nsteps)), "lbdps_batch_step")
+
+    def capture(self, nsteps: int):
+        check(lbdps_batch_capture(self.batch, int(nsteps)), "lbdps_batch_capture")
+
+    def launch(self):
+        check(lbdps_batch_launch(self.batch), "lbdps_batch_launch")
+
+    def sync(self):
+        check(lbdps_batch_sync(self.batch), "lbdps_batch_sync")
+
+    def time_kernels(self, names):
+        mask = 0
+        for n in names:
+            mask |= 1 << KERNELS.index(n)
+        check(lbdps_batch_time_kernels(self.batch, mask), "lbdps_batch_time_kernels")
+
+    def kernel_times(self):
+        ms = (c_dbl * len(KERNELS))()
+        cnt = (c_i64 * len(KERNELS))()
+        check(lbdps_batch_kernel_times(self.batch, ms, cnt), "lbdps_batch_kernel_times")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS)}
+
+    def close(self):
+        if getattr(self, "batch", None):
+            self.stream.synchronize()
+            lbdps_batch_destroy(self.batch)
+            self.batch = None
 
     def __del__(self):
         try:

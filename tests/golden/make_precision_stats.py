@@ -8,6 +8,11 @@ Statistics: column solid area fraction phi(x) (particles with floor(P_x) = x,
 times pi d^2 / 4, over ny), mean gas velocity u_y over the cells, mean particle
 velocity v_y, and their difference (mean slip).
 
+The particle system is chaotic, so the same statistics are also taken from two
+more oracle runs whose initial x positions are moved by +-2^-40 cells
+(alternating in sign by particle).  Their largest relative difference from the
+reference run is the spread that divergence alone produces ("noise").
+
     python tests/golden/make_precision_stats.py      (about 2-3 minutes)
 """
 import json
@@ -38,10 +43,7 @@ def sample(cfg, pos, vel, ugas):
     return phi, uy, vy
 
 
-def main():
-    cfg = synth.riser_crop()
-    f0, pos0, vel0 = storage_repr.state(cfg, oracle.equilibrium_state(cfg["nx"], cfg["ny"]), cfg["pos"],
-                                        cfg["vel"], "fp32")
+def run(cfg, f0, pos0, vel0):
     sim = oracle.Sim(cfg, f=f0, pos=pos0, vel=vel0)
     acc_phi, acc_uy, acc_vy, ns = np.zeros(cfg["nx"]), 0.0, 0.0, 0
     t0 = time.time()
@@ -56,10 +58,33 @@ def main():
             ns += 1
         if k % 500 == 0:
             print(f"step {k}  {time.time() - t0:.0f} s", flush=True)
-    res = dict(workload=cfg["name"], steps=STEPS, start=START, every=EVERY, samples=ns,
-               phi_x=(acc_phi / ns).tolist(), mean_uy=acc_uy / ns, mean_vy=acc_vy / ns,
-               mean_slip=(acc_uy - acc_vy) / ns,
-               note="FP64 oracle; initial positions as cell + float32 offset")
+    return dict(samples=ns, phi_x=acc_phi / ns, mean_uy=acc_uy / ns, mean_vy=acc_vy / ns,
+                mean_slip=(acc_uy - acc_vy) / ns)
+
+
+def rel_diff(a, b):
+    return dict(phi_x=float(np.abs(a["phi_x"] - b["phi_x"]).max() / b["phi_x"].max()),
+                **{k: abs(a[k] - b[k]) / abs(b[k]) for k in ("mean_uy", "mean_vy", "mean_slip")})
+
+
+def main():
+    cfg = synth.riser_crop()
+    f0, pos0, vel0 = storage_repr.state(cfg, oracle.equilibrium_state(cfg["nx"], cfg["ny"]), cfg["pos"],
+                                        cfg["vel"], "fp32")
+    ref = run(cfg, f0, pos0, vel0)
+    noise = {k: 0.0 for k in ("phi_x", "mean_uy", "mean_vy", "mean_slip")}
+    sign = np.where(np.arange(len(pos0)) % 2 == 0, 1.0, -1.0)
+    for j in (1, 2):
+        pj = pos0.copy()
+        pj[:, 0] += (-1) ** j * sign * 2.0 ** -40
+        d = rel_diff(run(cfg, f0, pj, vel0), ref)
+        print("perturbed run", j, d, flush=True)
+        noise = {k: max(noise[k], d[k]) for k in noise}
+    res = dict(workload=cfg["name"], steps=STEPS, start=START, every=EVERY, samples=ref["samples"],
+               phi_x=ref["phi_x"].tolist(), mean_uy=ref["mean_uy"], mean_vy=ref["mean_vy"],
+               mean_slip=ref["mean_slip"], noise=noise,
+               note="FP64 oracle; initial positions as cell + float32 offset; noise = largest relative "
+                    "difference of two runs with x moved by +-2^-40")
     with open(os.path.join(HERE, "precision_riser_crop_stats.json"), "w") as fh:
         json.dump(res, fh, indent=1)
     print({k: v for k, v in res.items() if k != "phi_x"})

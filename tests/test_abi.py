@@ -90,3 +90,42 @@ def test_create_rejects_small_workspace_before_device():
 def test_status_strings():
     for s in range(-7, 1):
         assert L.lbdps_status_str(s)
+
+
+def _batch(cfgs, prec=None):
+    params = (L.lbdps_params * len(cfgs))(*[L.make_params(c, prec) for c in cfgs])
+    nmax = (ctypes.c_int64 * len(cfgs))(*[len(c["pos"]) for c in cfgs])
+    return params, nmax
+
+
+def test_batch_workspace_covers_every_bed():
+    cfgs = [synth.tiny(nx=16, ny=24, n=60), synth.tiny(nx=40, ny=20, n=10), synth.bubble_small()]
+    params, nmax = _batch(cfgs, "fp32")
+    total = L.batch_workspace_bytes(params, nmax)
+    assert total >= sum(L.workspace_bytes(params[i], nmax[i]) for i in range(len(cfgs)))
+
+
+def test_batch_rejects_mixed_precision_and_diagnostics():
+    cfgs = [synth.tiny(nx=16, ny=24, n=60), synth.tiny(nx=40, ny=20, n=10)]
+    params, nmax = _batch(cfgs, "fp32")
+    params[1].precision = L.LBDPS_FP64
+    out = ctypes.c_size_t(0)
+    assert L.lbdps_batch_workspace_bytes(params, 2, nmax, ctypes.byref(out)) == L.LBDPS_E_INVALID
+    params, nmax = _batch(cfgs, "fp32")
+    params[0].diagnostics = 1
+    assert L.lbdps_batch_workspace_bytes(params, 2, nmax, ctypes.byref(out)) == L.LBDPS_E_UNSUPPORTED
+    params, nmax = _batch(cfgs, "fp32")
+    assert L.lbdps_batch_workspace_bytes(params, 0, nmax, ctypes.byref(out)) == L.LBDPS_E_SHAPE
+    params[1].tau = 0.4
+    assert L.lbdps_batch_workspace_bytes(params, 2, nmax, ctypes.byref(out)) == L.LBDPS_E_INVALID
+    assert b"bed 1" in L.lbdps_last_error()
+
+
+def test_batch_create_rejects_small_workspace_before_device():
+    cfgs = [synth.tiny(nx=16, ny=24, n=60), synth.tiny(nx=40, ny=20, n=10)]
+    params, nmax = _batch(cfgs, "fp32")
+    b = ctypes.c_void_p()
+    st = L.lbdps_batch_create(params, 2, nmax, None, ctypes.c_void_p(256), 16, None, ctypes.byref(b))
+    assert st == L.LBDPS_E_SHAPE and not b.value
+    assert L.lbdps_batch_step(None, 1) == L.LBDPS_E_INVALID
+    assert L.lbdps_batch_capture(None, 2) == L.LBDPS_E_INVALID

@@ -1,0 +1,148 @@
+"""Batched stepping (many beds, one launch per phase) against the single-bed
+path and the FP64 oracle.
+
+- Each bed of a batch after n batched steps equals the same bed stepped alone
+  by lbdps_step, bit for bit (populations, positions, velocities, fields,
+  counters), in every precision; beds differ in lattice size, faces and
+  particle count, one has no particles.
+- FP64 beds of a batch match the oracle within 1e-12.
+- A captured graph, replayed several times with eager work and
+  synchronisations in between, gives after every replay exactly the state of
+  eager batched steps; a bed changed after the capture makes the replay refuse.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+L = pytest.importorskip("paper_1303_2653_amd.lbdps")
+import oracle  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def uneven_beds(prec):
+    """Six beds of different shapes, faces and loads, one without particles."""
+    beds = [
+        synth.tiny(nx=16, ny=24, n=60, seed=1),
+        synth.tiny(nx=37, ny=20, n=300, seed=2, bc=("wall", "wall", "periodic", "periodic"), G=(0.0, 2e-5),
+                   g=(0.0, -3e-5), vel_scale=2e-3),
+        synth.tiny(nx=9, ny=8, n=300, seed=3, bc=("periodic",) * 4, vel_scale=3e-3, g=(0.0, -2e-5)),
+        synth.tiny(nx=64, ny=40, n=0, seed=4, bc=("periodic",) * 4, G=(1e-5, 0.0)),
+        synth.tiny(nx=48, ny=64, n=900, seed=5, bc=("wall",) * 4, band=30.0, g=(2e-5, -1e-5), vel_scale=1e-3),
+        synth.tiny(nx=20, ny=50, n=200, seed=6, band=20.0),
+    ]
+    for b in beds:
+        b["precision"] = prec
+    return beds
+
+
+def snapshot(sim):
+    f, pos, vel, step = sim.state()
+    fl = sim.fields()
+    return dict(f=f, pos=pos, vel=vel, step=step, **fl, **sim.counters())
+
+
+def assert_same(a, b, what):
+    for k in a:
+        if isinstance(a[k], np.ndarray):
+            assert a[k].shape == b[k].shape and (a[k] == b[k]).all(), f"{what}: {k} differs"
+        else:
+            assert a[k] == b[k], f"{what}: {k} {a[k]} != {b[k]}"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
+def test_batch_equals_single_beds(prec):
+    cfgs = uneven_beds(prec)
+    say("batch", prec, [(c["nx"], c["ny"], len(c["pos"])) for c in cfgs])
+    batch = L.Batch(cfgs)
+    batch.step(3)
+    batch.step(4)  # an odd then an even count: buffer parities change between calls
+    batch.sync()
+    for i, c in enumerate(cfgs):
+        single = L.Sim(c)
+        single.step(7)
+        assert_same(snapshot(batch.beds[i]), snapshot(single), f"{prec} bed {i}")
+    batch.close()
+
+
+def test_batch_fp64_matches_oracle():
+    cfgs = uneven_beds("fp64")
+    batch = L.Batch(cfgs)
+    batch.step(5)
+    batch.sync()
+    for i, c in enumerate(cfgs):
+        ref = oracle.Sim(c)
+        ref.run(5)
+        f, pos, vel, _ = batch.beds[i].state()
+        scale = lambda r, fl: max(np.abs(r).max() if r.size else 0.0, fl)
+        errs = dict(f=np.abs(f - ref.f).max() / scale(ref.f, 1.0))
+        if len(pos):
+            errs.update(pos=np.abs(pos - ref.pos).max() / scale(ref.pos, 1.0),
+                        vel=np.abs(vel - ref.vel).max() / scale(ref.vel, 1e-30))
+        say("bed", i, {k: f"{v:.1e}" for k, v in errs.items()})
+        assert all(v <= 1e-12 for v in errs.values()), (i, errs)
+    batch.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_batch_graph_replays_equal_eager(prec):
+    cfgs = uneven_beds(prec)
+    graph = L.Batch(cfgs)
+    eager = L.Batch(cfgs)
+    graph.capture(4)
+    for rep in range(3):
+        graph.launch()
+        eager.step(4)
+        graph.sync()
+        eager.sync()
+        for i in range(len(cfgs)):
+            assert_same(snapshot(graph.beds[i]), snapshot(eager.beds[i]), f"replay {rep} bed {i}")
+        # eager work of the program between replays
+        torch.cuda.synchronize()
+        _ = torch.ones(1 << 16, device="cuda").sum().item()
+    graph.close()
+    eager.close()
+
+
+def test_batch_launch_refuses_changed_bed():
+    cfgs = uneven_beds("fp32")
+    batch = L.Batch(cfgs)
+    batch.capture(2)
+    batch.launch()
+    batch.sync()
+    b = batch.beds[1]
+    f, pos, vel, _ = b.state()
+    b.set_state(f, pos, vel)
+    with pytest.raises(L.LbdpsError) as e:
+        batch.launch()
+    assert e.value.status == L.LBDPS_E_INVALID
+    batch.capture(2)  # a new capture replays again
+    batch.launch()
+    batch.sync()
+    batch.close()
+
+
+def test_batch_of_64_uneven_beds_fp16():
+    """The 64-bed batching workload at full size: two batched steps, then three
+    beds (smallest, largest, one between) against the single-bed path."""
+    cfgs = synth.beds(64)
+    say("cells", sum(c["nx"] * c["ny"] for c in cfgs), "particles", sum(len(c["pos"]) for c in cfgs))
+    batch = L.Batch(cfgs)
+    batch.step(2)
+    batch.sync()
+    sizes = [c["nx"] * c["ny"] for c in cfgs]
+    pick = [int(np.argmin(sizes)), int(np.argmax(sizes)), 31]
+    for i in pick:
+        single = L.Sim(cfgs[i])
+        single.step(2)
+        assert_same(snapshot(batch.beds[i]), snapshot(single), f"bed {i}")
+        del single
+    batch.close()

@@ -12,11 +12,13 @@ that is set:
   10, 100 and 1000 free-running steps;
 - statistics: time averages over steps 1000-5000 sampled every 10 steps
   (column solid fraction phi(x), mean gas u_y, mean particle v_y, mean slip)
-  against the oracle's values in tests/golden/precision_riser_crop_stats.json,
-  beside the FP64 library path's own distance from them: the collisions make
-  the particle system chaotic, so after a few hundred steps any rounding
-  difference, even the FP64 path's few-ulp one, decorrelates the trajectories
-  and only statistics remain comparable.
+  against the oracle's values in tests/golden/precision_riser_crop_stats.json.
+  The collisions make the particle system chaotic: any rounding difference,
+  even the FP64 path's few-ulp one, grows until the trajectories decorrelate
+  (for the FP64 path after about 1000 steps), and only statistics remain
+  comparable.  Their spread between runs that differ only by that divergence
+  (two oracle runs with x moved by +-2^-40, stored with the statistics, and the
+  FP64 library path) is the yardstick.
 
 The bounds asserted below are the stated errors of the precision pattern.
 """
@@ -43,8 +45,13 @@ POINTS = (10, 100, 1000)
 STEPS, START, EVERY = 5000, 1000, 10
 PRECS = ("fp32", "fp16", "bf16")
 
-# stated pointwise bounds (gas fields and populations, norm-wise) at step 10
-BOUND10 = {"fp32": 1e-4, "fp16": 2e-2, "bf16": 2e-1}
+# stated pointwise bounds (gas fields and populations, norm-wise) at step 10;
+# measured on MI355X: FP32 3.5e-7, FP16 1.9e-3, BF16 3.1e-3
+BOUND10 = {"fp32": 2e-6, "fp16": 1e-2, "bf16": 1.5e-2}
+# statistics: within 1.5 times the spread of runs that differ only by chaotic
+# divergence (the oracle's perturbed runs, and the FP64 library path, which
+# tracks the oracle to 1e-14 for 800 steps and then diverges exponentially)
+SPREAD_FACTOR = 1.5
 
 
 def say(*a):
@@ -145,6 +152,13 @@ def test_precision_pattern(crop):
         p10 = report["runs"][prec]["pointwise"]["10"]
         for key in ("f", "rho", "ugas", "fpg", "beta"):
             assert p10[key] <= BOUND10[prec], (prec, key, p10[key])
-    for prec in ("fp64",) + PRECS:
+    spread = {k: max(ref["noise"][k], report["runs"]["fp64"]["stats_err"][k]) for k in ref["noise"]}
+    report["spread"] = spread
+    if out:
+        with open(out, "w") as fh:
+            json.dump(report, fh, indent=1)
+    say("spread", {k: f"{v:.2e}" for k, v in spread.items()})
+    for prec in PRECS:
         se = report["runs"][prec]["stats_err"]
-        assert all(np.isfinite(v) for v in se.values())
+        for key, v in se.items():
+            assert v <= SPREAD_FACTOR * spread[key], (prec, key, v, spread[key])
