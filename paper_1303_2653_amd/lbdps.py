@@ -322,6 +322,12 @@ class Batch:
             sim.set_state(None, pos, c.get("vel", np.zeros_like(pos)))
             self.beds.append(sim)
 
+    def reset(self):
+        """Every bed back to its configuration's initial state."""
+        for sim in self.beds:
+            pos = np.asarray(sim.cfg["pos"], np.float64).reshape(-1, 2)
+            sim.set_state(None, pos, sim.cfg.get("vel", np.zeros_like(pos)))
+
     def step(self, nsteps: int = 1):
         check(lbdps_batch_step(self.batch, int(nsteps)), "lbdps_batch_step")
 
