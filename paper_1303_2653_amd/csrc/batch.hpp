@@ -22,7 +22,8 @@ template <int P> struct BedArgs {
   T *px[2], *py[2], *vx[2], *vy[2];
   Fields<T> fl;
   const T *lut, *inlet;
-  int32_t *cs, *count, *rank, *slot, *flags, *deg, *done, *ticket, *chunk_busy, *need_sweep, *roots, *rcount;
+  int32_t *cs, *count, *rank, *slot, *flags, *deg, *done, *ticket, *chunk_busy, *need_sweep, *rcount;
+  long long *roots;
   long long *adj, *pair_part, *wall0_part, *coll_part, *wall_part, *collc_part, *wallc_part, *scratch;
   TileSums ts;
   int cf;        // population buffer holding the state when the table was written

@@ -814,7 +814,7 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
                                                     int32_t *__restrict__ deg, int32_t *__restrict__ done,
                                                     int32_t *ticket, int32_t *flags, long long *pair_part,
                                                     long long *wall_part, int32_t *__restrict__ chunk_busy,
-                                                    int32_t *need_sweep, int32_t *__restrict__ roots,
+                                                    int32_t *need_sweep, long long *__restrict__ roots,
                                                     int32_t *__restrict__ rcount) {
   using T = typename Prec<P>::T;
   __shared__ long long sh[BLOCK / 64];
@@ -958,7 +958,7 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
   // candidate roots of this workgroup, compacted to the front of its segment
   int nc;
   const int off = block_excl_scan(cand ? 1 : 0, shi, nc);
-  if (cand) roots[(size_t)bidx * BLOCK + off] = s;
+  if (cand) roots[(size_t)bidx * BLOCK + off] = ((long long)pt.pid[s] << 32) | (unsigned)s;
   const long long t = block_sum_ll(fwd, sh);
   const long long tw = block_sum_ll(nwall, sh);
   if (threadIdx.x == 0) {
@@ -973,7 +973,7 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
                                                     int32_t *__restrict__ deg, int32_t *__restrict__ done,
                                                     int32_t *ticket, int32_t *flags, long long *pair_part,
                                                     long long *wall_part, int32_t *__restrict__ chunk_busy,
-                                                    int32_t *need_sweep, int32_t *__restrict__ roots,
+                                                    int32_t *need_sweep, long long *__restrict__ roots,
                                                     int32_t *__restrict__ rcount) {
   contacts_body<P>(blockIdx.x, gridDim.x, pt, cs, k, adj, deg, done, ticket, flags, pair_part, wall_part, chunk_busy, need_sweep, roots, rcount);
 }
@@ -992,13 +992,13 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
 // by spin_limit polls; exceeding it latches FLAG_STALL and the wave exits.
 // Binary collision of slots s (lower particle index) and t, Eqs. 17-18 with the
 // current velocities; the pair collides only if (P_s - P_t).(v_s - v_t) < 0.
+// The collision of two particles given by value: separation (dx, dy) = P_s - P_t
+// and velocities; returns whether they approach, and then the new velocities.
 template <int P>
-__device__ __forceinline__ bool pair_collide(const Consts<typename Prec<P>::T> &k, Parts<typename Prec<P>::T> &pt,
-                                             int s, int t) {
+__device__ __forceinline__ bool pair_core(const Consts<typename Prec<P>::T> &k, typename Prec<P>::T dx,
+                                          typename Prec<P>::T dy, typename Prec<P>::T &vix, typename Prec<P>::T &viy,
+                                          typename Prec<P>::T &vjx, typename Prec<P>::T &vjy) {
   using T = typename Prec<P>::T;
-  T dx, dy;
-  Pos<P>::sep(k, pt.key[s], pt.px[s], pt.py[s], pt.key[t], pt.px[t], pt.py[t], dx, dy);
-  const T vix = pt.vx[s], viy = pt.vy[s], vjx = pt.vx[t], vjy = pt.vy[t];
   const T dvx = vix - vjx, dvy = viy - vjy;
   const T dot = dvx * dx + dvy * dy;
   if (!(dot < (T)0)) return false;
@@ -1006,10 +1006,25 @@ __device__ __forceinline__ bool pair_collide(const Consts<typename Prec<P>::T> &
   const T q0 = k.one_e * dot / r2;
   const T ci = q0 * k.m / k.msum;
   const T cj = q0 * k.m / k.msum;
-  pt.vx[s] = vix - ci * dx;
-  pt.vy[s] = viy - ci * dy;
-  pt.vx[t] = vjx + cj * dx;
-  pt.vy[t] = vjy + cj * dy;
+  vix = vix - ci * dx;
+  viy = viy - ci * dy;
+  vjx = vjx + cj * dx;
+  vjy = vjy + cj * dy;
+  return true;
+}
+
+template <int P>
+__device__ __forceinline__ bool pair_collide(const Consts<typename Prec<P>::T> &k, Parts<typename Prec<P>::T> &pt,
+                                             int s, int t) {
+  using T = typename Prec<P>::T;
+  T dx, dy;
+  Pos<P>::sep(k, pt.key[s], pt.px[s], pt.py[s], pt.key[t], pt.px[t], pt.py[t], dx, dy);
+  T vix = pt.vx[s], viy = pt.vy[s], vjx = pt.vx[t], vjy = pt.vy[t];
+  if (!pair_core<P>(k, dx, dy, vix, viy, vjx, vjy)) return false;
+  pt.vx[s] = vix;
+  pt.vy[s] = viy;
+  pt.vx[t] = vjx;
+  pt.vy[t] = vjy;
   return true;
 }
 
@@ -1045,6 +1060,7 @@ __device__ __forceinline__ int wall_pass(const Consts<typename Prec<P>::T> &k, P
 constexpr int CL_LDS = 8;
 constexpr int CLUSTER_MAX = 64;
 constexpr int RC_GRID_MAX = 2048;  // resolution workgroups (each takes <= BLOCK candidate lists)
+constexpr int RC_LISTS_MIN = 4;    // candidate lists per resolution workgroup, at least
 
 struct LdsColumn {  // entry i of a lane's column of a [CL_LDS][BLOCK] LDS array
   long long *p;
@@ -1083,13 +1099,17 @@ __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, cons
   return m;
 }
 
-// Orders the gathered members by index, applies the cluster's pairs in
-// lexicographic order, then each member's wall pass.
+// Orders the gathered members by index and applies the cluster's pairs in
+// lexicographic order: member u (ascending) meets its higher-index neighbours
+// in ascending order, with u's velocity kept in registers over its pairs.
+// Every pair with u as the higher index came before, and none follows, so u's
+// wall pass runs right after its own pairs.
 template <int P, class Row>
 __device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typename Prec<P>::T> &k,
                                                 Parts<typename Prec<P>::T> &pt, const long long *__restrict__ adj,
                                                 const int32_t *__restrict__ deg, int32_t *done, long long &ncoll,
                                                 long long &nwall) {
+  using T = typename Prec<P>::T;
   for (int i = 1; i < m; ++i) {
     const long long e = q[i];
     int j = i - 1;
@@ -1099,20 +1119,213 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typen
     }
     q[j + 1] = e;
   }
-  for (int i = 0; i < m; ++i) {  // pairs (u, w), u < w, in lexicographic order
+  for (int i = 0; i < m; ++i) {
     const int u = (int)(q[i] & 0xffffffffll), gu = (int)(q[i] >> 32);
     const long long *ru = adj + (size_t)u * KMAX;
+    const int dgu = deg[u], du = min(dgu, KMAX);
+    const long long e0 = ru[0], e1 = ru[1], e2 = ru[2], e3 = ru[3];  // a row has KMAX slots
+    const int ku = pt.key[u];
+    const T xu = pt.px[u], yu = pt.py[u];
+    T vxu = pt.vx[u], vyu = pt.vy[u];
+    for (int a = 0; a < du; ++a) {
+      const long long e = a == 0 ? e0 : (a == 1 ? e1 : (a == 2 ? e2 : (a == 3 ? e3 : ru[a])));
+      if ((int)(e >> 32) <= gu) continue;
+      const int w = (int)(e & 0xffffffffll);
+      T dx, dy;
+      Pos<P>::sep(k, ku, xu, yu, pt.key[w], pt.px[w], pt.py[w], dx, dy);
+      T vxw = pt.vx[w], vyw = pt.vy[w];
+      if (pair_core<P>(k, dx, dy, vxu, vyu, vxw, vyw)) {
+        pt.vx[w] = vxw;
+        pt.vy[w] = vyw;
+        ++ncoll;
+      }
+    }
+    nwall += Pos<P>::walls(k, ku % k.nx, ku / k.nx, xu, yu, vxu, vyu);
+    pt.vx[u] = vxu;
+    pt.vy[u] = vyu;
+    done[u] = dgu;
+  }
+}
+
+// A cluster of more than CL_LDS members is resolved by the whole workgroup with
+// everything in LDS: breadth-first gathering with an open-addressing set of
+// member slots, a bitonic sort by index, the lexicographic pair list built
+// with a workgroup scan, the pairs applied in order by one thread on the
+// members' LDS copies, then the wall pass of every member in parallel.  Beyond
+// BIG_MAX members or BIG_PAIRS pairs the cluster is left to the ordered sweep.
+constexpr int BIG_MAX = 256;                 // members (== BLOCK: one thread per member)
+constexpr int BIG_PAIRS = 1024;              // pairs
+constexpr int BIG_HASH = 512;                // set of member slots (power of two)
+constexpr int BIG_LIST = 64;                 // clusters queued per workgroup for this phase
+
+static_assert(BIG_MAX == BLOCK, "one thread per member of a whole-workgroup cluster");
+
+template <int P> struct BigCluster {
+  using T = typename Prec<P>::T;
+  long long q[BIG_MAX];
+  int hslot[BIG_HASH];
+  short hidx[BIG_HASH];
+  int key[BIG_MAX];
+  T px[BIG_MAX], py[BIG_MAX], vx[BIG_MAX], vy[BIG_MAX];
+  unsigned pairs[BIG_PAIRS];
+  int m, notroot, over;
+};
+
+__device__ __forceinline__ int big_hash(int slot) { return (int)(((unsigned)slot * 2654435761u) >> 23) & (BIG_HASH - 1); }
+
+// Insert slot into the set; returns 1 if it was new, 0 if present, -1 if full.
+template <int P> __device__ __forceinline__ int big_insert(BigCluster<P> &B, int slot) {
+  int h = big_hash(slot);
+  for (int probe = 0; probe < BIG_HASH; ++probe) {
+    const int old = atomicCAS(&B.hslot[h], -1, slot);
+    if (old == -1) return 1;
+    if (old == slot) return 0;
+    h = (h + 1) & (BIG_HASH - 1);
+  }
+  return -1;
+}
+
+template <int P> __device__ __forceinline__ int big_find(const BigCluster<P> &B, int slot) {
+  int h = big_hash(slot);
+  for (int probe = 0; probe < BIG_HASH; ++probe) {
+    const int v = B.hslot[h];
+    if (v == slot) return h;
+    if (v == -1) return -1;
+    h = (h + 1) & (BIG_HASH - 1);
+  }
+  return -1;
+}
+
+// Whole-workgroup resolution of the cluster of candidate slot s0 (index g);
+// every thread of the workgroup calls it.
+template <int P>
+__device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Consts<typename Prec<P>::T> &k,
+                            Parts<typename Prec<P>::T> &pt, const long long *__restrict__ adj,
+                            const int32_t *__restrict__ deg, int32_t *done, int32_t *need_sweep, long long &ncoll,
+                            long long &nwall) {
+  using T = typename Prec<P>::T;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < BIG_HASH; i += BLOCK) B.hslot[i] = -1;
+  if (tid == 0) {
+    B.q[0] = ((long long)g << 32) | (unsigned)s0;
+    B.m = 1;
+    B.notroot = 0;
+    B.over = 0;
+  }
+  __syncthreads();
+  if (tid == 0) big_insert<P>(B, s0);
+  __syncthreads();
+  // level-synchronous breadth-first gathering
+  int h0 = 0;
+  for (;;) {
+    const int h1 = min(B.m, BIG_MAX);
+    const bool stop = h0 >= h1 || B.notroot || B.over;
+    __syncthreads();
+    if (stop) break;
+    for (int t = h0 + tid; t < h1; t += BLOCK) {
+      const int u = (int)(B.q[t] & 0xffffffffll);
+      const long long *ru = adj + (size_t)u * KMAX;
+      const int du = min(deg[u], KMAX);
+      for (int a = 0; a < du; ++a) {
+        const long long e = ru[a];
+        if ((int)(e >> 32) < g) {
+          B.notroot = 1;  // a lower index: the cluster belongs to another candidate
+          break;
+        }
+        const int r = big_insert<P>(B, (int)(e & 0xffffffffll));
+        if (r < 0) {
+          B.over = 1;
+          break;
+        }
+        if (r == 1) {
+          const int pos = atomicAdd(&B.m, 1);
+          if (pos < BIG_MAX) B.q[pos] = e;
+          else B.over = 1;
+        }
+      }
+    }
+    __syncthreads();
+    h0 = h1;
+  }
+  if (B.notroot) return;  // uniform: read after the loop's last barrier
+  if (B.over) {
+    if (tid == 0) atomicOr(need_sweep, 1);
+    return;
+  }
+  const int m = B.m;
+  // bitonic sort of q[0 .. BIG_MAX) by (index, slot), padded past m
+  if (tid >= m) B.q[tid] = 0x7fffffffffffffffll;
+  __syncthreads();
+  for (int len = 2; len <= BIG_MAX; len <<= 1)
+    for (int st = len >> 1; st > 0; st >>= 1) {
+      const int j = tid ^ st;
+      if (j > tid) {
+        const long long a = B.q[tid], b = B.q[j];
+        const bool up = (tid & len) == 0;
+        if ((a > b) == up) {
+          B.q[tid] = b;
+          B.q[j] = a;
+        }
+      }
+      __syncthreads();
+    }
+  // member copies, slot -> sorted index, pairs (i, j), i < j, per member
+  const bool mem = tid < m;
+  const int u = mem ? (int)(B.q[tid] & 0xffffffffll) : 0;
+  const int gu = mem ? (int)(B.q[tid] >> 32) : 0;
+  int cnt = 0;
+  if (mem) {
+    B.hidx[big_find<P>(B, u)] = (short)tid;
+    B.key[tid] = pt.key[u];
+    B.px[tid] = pt.px[u];
+    B.py[tid] = pt.py[u];
+    B.vx[tid] = pt.vx[u];
+    B.vy[tid] = pt.vy[u];
+    const long long *ru = adj + (size_t)u * KMAX;
     const int du = min(deg[u], KMAX);
+    for (int a = 0; a < du; ++a) cnt += (int)(ru[a] >> 32) > gu;
+  }
+  int npairs;
+  const int off = block_excl_scan(cnt, shi, npairs);
+  if (npairs > BIG_PAIRS) {
+    if (tid == 0) atomicOr(need_sweep, 1);
+    return;
+  }
+  if (mem) {
+    const long long *ru = adj + (size_t)u * KMAX;
+    const int du = min(deg[u], KMAX);
+    int w = off;
     for (int a = 0; a < du; ++a) {
       const long long e = ru[a];
-      if ((int)(e >> 32) > gu) ncoll += pair_collide<P>(k, pt, u, (int)(e & 0xffffffffll));
+      if ((int)(e >> 32) > gu) B.pairs[w++] = ((unsigned)tid << 16) | (unsigned)B.hidx[big_find<P>(B, (int)(e & 0xffffffffll))];
     }
   }
-  for (int i = 0; i < m; ++i) {
-    const int u = (int)(q[i] & 0xffffffffll);
-    nwall += wall_pass<P>(k, pt, u);
+  __syncthreads();
+  if (tid == 0) {  // the pairs in lexicographic order, on the LDS copies
+    for (int q = 0; q < npairs; ++q) {
+      const int i = (int)(B.pairs[q] >> 16), j = (int)(B.pairs[q] & 0xffffu);
+      T dx, dy;
+      Pos<P>::sep(k, B.key[i], B.px[i], B.py[i], B.key[j], B.px[j], B.py[j], dx, dy);
+      T vix = B.vx[i], viy = B.vy[i], vjx = B.vx[j], vjy = B.vy[j];
+      if (pair_core<P>(k, dx, dy, vix, viy, vjx, vjy)) {
+        B.vx[i] = vix;
+        B.vy[i] = viy;
+        B.vx[j] = vjx;
+        B.vy[j] = vjy;
+        ++ncoll;
+      }
+    }
+  }
+  __syncthreads();
+  if (mem) {
+    T vx = B.vx[tid], vy = B.vy[tid];
+    const int key = B.key[tid];
+    nwall += Pos<P>::walls(k, key % k.nx, key / k.nx, B.px[tid], B.py[tid], vx, vy);
+    pt.vx[u] = vx;
+    pt.vy[u] = vy;
     done[u] = deg[u];
   }
+  __syncthreads();
 }
 
 template <int P>
@@ -1122,12 +1335,20 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
                                                             Consts<typename Prec<P>::T> k, int32_t *need_sweep,
                                                             long long *coll_part, long long *wall_part,
                                                             long long *__restrict__ scratch,
-                                                            const int32_t *__restrict__ roots,
+                                                            const long long *__restrict__ roots,
                                                             const int32_t *__restrict__ rcount, int nlists) {
   __shared__ long long sh[BLOCK / 64];
   __shared__ int shi[BLOCK / 64];
   __shared__ int pre[BLOCK + 1];
-  __shared__ long long qs[CL_LDS * BLOCK];
+  __shared__ long long bigc[BIG_LIST];
+  __shared__ int nbig;
+  // the per-lane gathering area, reused afterwards for the whole-workgroup clusters
+  __shared__ union {
+    long long qs[CL_LDS * BLOCK];
+    BigCluster<P> big;
+  } U;
+  long long *const qs = U.qs;
+  if (threadIdx.x == 0) nbig = 0;
   // candidate lists [b0, b0 + nb) of the contact kernel's workgroups
   const int per = (nlists + gdim - 1) / gdim;  // <= BLOCK (host grid choice)
   const int b0 = bidx * per;
@@ -1148,16 +1369,28 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
       if (pre[mid] <= f) lo = mid;
       else hi = mid;
     }
-    const int s = roots[(size_t)(b0 + lo) * BLOCK + (f - pre[lo])];
-    const int g = pt.pid[s];
+    const long long r = roots[(size_t)(b0 + lo) * BLOCK + (f - pre[lo])];
+    const int s = (int)(r & 0xffffffffll), g = (int)(r >> 32);
     int m = gather_cluster(ql, CL_LDS, s, g, adj, deg);
     if (m > 0) {
       resolve_cluster<P>(ql, m, k, pt, adj, deg, done, ncoll, nwall);
     } else if (m < 0) {
-      m = gather_cluster(qg, CLUSTER_MAX, s, g, adj, deg);
-      if (m > 0) resolve_cluster<P>(qg, m, k, pt, adj, deg, done, ncoll, nwall);
-      else if (m < 0) atomicOr(need_sweep, 1);
+      const int slot = atomicAdd(&nbig, 1);  // the workgroup resolves it below
+      if (slot < BIG_LIST) {
+        bigc[slot] = r;
+      } else {  // queue full: this lane alone, in its global scratch row
+        m = gather_cluster(qg, CLUSTER_MAX, s, g, adj, deg);
+        if (m > 0) resolve_cluster<P>(qg, m, k, pt, adj, deg, done, ncoll, nwall);
+        else if (m < 0) atomicOr(need_sweep, 1);
+      }
     }
+  }
+  __syncthreads();
+  const int nb_big = min(nbig, BIG_LIST);
+  for (int c = 0; c < nb_big; ++c) {
+    const long long r = bigc[c];
+    resolve_big<P>(U.big, shi, (int)(r & 0xffffffffll), (int)(r >> 32), k, pt, adj, deg, done, need_sweep, ncoll,
+                   nwall);
   }
   const long long tc = block_sum_ll(ncoll, sh);
   const long long tw = block_sum_ll(nwall, sh);
@@ -1173,7 +1406,7 @@ __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<
                                                             Consts<typename Prec<P>::T> k, int32_t *need_sweep,
                                                             long long *coll_part, long long *wall_part,
                                                             long long *__restrict__ scratch,
-                                                            const int32_t *__restrict__ roots,
+                                                            const long long *__restrict__ roots,
                                                             const int32_t *__restrict__ rcount, int nlists) {
   resolve_clusters_body<P>(blockIdx.x, gridDim.x, pt, adj, deg, done, k, need_sweep, coll_part, wall_part, scratch, roots, rcount, nlists);
 }

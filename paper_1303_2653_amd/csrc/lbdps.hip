@@ -27,11 +27,14 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int NB_CONS = 512;  // workgroups of the conservation reductions
 
 int nblocks(long long n) { return (int)((n + BLOCK - 1) / BLOCK); }
-// Workgroups of the cluster resolution: at most RC_GRID_MAX, and enough that
-// each takes at most BLOCK of the contact kernel's candidate lists.
+// Workgroups of the cluster resolution: each takes at least RC_LISTS_MIN of the
+// contact kernel's candidate lists (about a fifth of a list's particles are
+// candidates, so that fills its wavefronts) and at most BLOCK; at most
+// RC_GRID_MAX workgroups unless more are needed for that.
 int cluster_blocks(long long n) {
   const long long nl = std::max(1ll, (long long)nblocks(n));
-  return (int)std::max(std::min(nl, (long long)RC_GRID_MAX), (nl + BLOCK - 1) / BLOCK);
+  const long long want = std::min((nl + RC_LISTS_MIN - 1) / RC_LISTS_MIN, (long long)RC_GRID_MAX);
+  return (int)std::max(std::max(want, 1ll), (nl + BLOCK - 1) / BLOCK);
 }
 
 size_t pop_bytes(int prec) { return prec == PREC_FP64 ? 8 : (prec == PREC_FP32 ? 4 : 2); }
@@ -172,7 +175,8 @@ struct lbdps_ctx {
   int32_t *tile_sum = nullptr, *chunk_busy = nullptr, *need_sweep = nullptr;
   int tile_shift = 11;
   long long *cluster_scratch = nullptr;
-  int32_t *roots = nullptr, *rcount = nullptr;
+  long long *roots = nullptr;
+  int32_t *rcount = nullptr;
   long long *collc_part = nullptr, *wallc_part = nullptr;
   int ntiles = 0;
   double *cons_pc = nullptr, *cons_pp = nullptr, *cons_out = nullptr;
@@ -234,7 +238,8 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   const size_t ntiles = (C + ((size_t)1 << shift) - 1) >> shift;
   int32_t *tile_sum = cv.take<int32_t>(ntiles + 1);
   long long *cluster_scratch = cv.take<long long>((size_t)cluster_blocks((long long)N) * BLOCK * CLUSTER_MAX);
-  int32_t *roots = cv.take<int32_t>(nbN * BLOCK), *rcount = cv.take<int32_t>(nbN);
+  long long *roots = cv.take<long long>(nbN * BLOCK);
+  int32_t *rcount = cv.take<int32_t>(nbN);
   int32_t *chunk_busy = cv.take<int32_t>(N / RES_CHUNK + 1), *need_sweep = cv.take<int32_t>(4);
   long long *collc_part = cv.take<long long>(nbN), *wallc_part = cv.take<long long>(nbN);
   double *pc = cv.take<double>(NB_CONS * 3), *pp = cv.take<double>(NB_CONS * 2), *co = cv.take<double>(8);

@@ -188,13 +188,23 @@ def test_fp64_collision_stage_exact():
     assert c["collisions"] == nc and c["walls"] == nw
 
 
-@pytest.mark.parametrize("name", ["riser_crop", "bubble_small"])
+CLUSTER_BEDS = {
+    "riser_crop": synth.riser_crop,
+    "bubble_small": synth.bubble_small,
+    # 6000 spheres on 40x40 cells: clusters of 204, 134, 95, 68 ... members
+    "dense_box": lambda: synth.tiny(nx=40, ny=40, n=6000, seed=9, bc=("periodic",) * 4),
+    # 430 spheres on 9x8 cells: one cluster of 369 members
+    "crowded_box": lambda: synth.tiny(nx=9, ny=8, n=430, seed=17, bc=("periodic",) * 4),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CLUSTER_BEDS))
 def test_fp64_collision_stage_clusters(name):
-    """Hard-sphere stage on a whole bed with random velocities: contact clusters
-    small enough are resolved whole by one lane, larger ones by the ordered
-    sweep; either way the velocities equal the oracle's sequential
-    lexicographic sweep bit for bit."""
-    cfg = getattr(synth, name)()
+    """Hard-sphere stage on a whole bed with random velocities.  Contact
+    clusters of up to 8 members are resolved by one lane, up to 256 by a whole
+    workgroup in LDS, larger ones by the ordered sweep; in every case the
+    velocities equal the oracle's sequential lexicographic sweep bit for bit."""
+    cfg = CLUSTER_BEDS[name]()
     rng = np.random.default_rng(21)
     vel = (rng.random(cfg["pos"].shape) - 0.5) * 2e-2
     gpu = L.Sim(dict(cfg, vel=vel), precision="fp64")
