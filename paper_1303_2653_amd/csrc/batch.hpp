@@ -24,7 +24,8 @@ template <int P> struct BedArgs {
   const T *lut, *inlet;
   int32_t *cs, *count, *rank, *slot, *flags, *deg, *done, *ticket, *chunk_busy, *need_sweep, *rcount;
   long long *roots;
-  long long *adj, *pair_part, *wall0_part, *coll_part, *wall_part, *collc_part, *wallc_part, *scratch;
+  Adj adj;
+  long long *pair_part, *wall0_part, *coll_part, *wall_part, *collc_part, *wallc_part, *scratch;
   TileSums ts;
   int cf;        // population buffer holding the state when the table was written
   int cp;        // particle record set holding the state when the table was written

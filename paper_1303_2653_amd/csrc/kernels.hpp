@@ -254,6 +254,23 @@ template <int P> struct Pos {
   }
 };
 
+// Neighbour rows: particle u's contacts, sorted by particle index, as 64-bit
+// entries (index << 32 | slot).  The first ADJ_IN entries of every row are
+// stored densely ([N][ADJ_IN], one 32-byte run per particle); entries
+// ADJ_IN .. KMAX-1, which few particles have, in a second array
+// ([N][KMAX - ADJ_IN]).
+constexpr int ADJ_IN = 4;
+struct AdjRow {
+  long long *a, *b;
+  __device__ long long &operator[](int i) const { return i < ADJ_IN ? a[i] : b[i - ADJ_IN]; }
+};
+struct Adj {
+  long long *in, *ov;
+  __device__ AdjRow row(int u) const {
+    return AdjRow{in + (size_t)u * ADJ_IN, ov + (size_t)u * (KMAX - ADJ_IN)};
+  }
+};
+
 // Generic three-pass scan: SCAN_ITEMS per thread.
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
@@ -269,6 +286,7 @@ struct TileSums {
 constexpr int LUT_ROWS_MAX = 64;              // per-count table rows staged in LDS
 constexpr int SEG_REG = 4;                    // cell segments up to this length stay in registers
 constexpr int CONTACT_REG = 6;                // contacts per particle collected in registers first
+constexpr int CONTACT_CH = 8;                 // candidate positions loaded together
 constexpr int RES_ITEMS = 8;                  // particle indices per lane and resolution chunk
 constexpr int RES_CHUNK = BLOCK * RES_ITEMS;  // particle indices per chunk
 
@@ -324,23 +342,29 @@ __device__ __forceinline__ void collide_body(const int bidx, const int gdim, con
                                                    typename Prec<P>::T *dg_vsx, typename Prec<P>::T *dg_vsy) {
   using T = typename Prec<P>::T;
   __shared__ T sl[LUT_ROWS_MAX * LUT_W];  // the per-count table
+  const int c = bidx * BLOCK + threadIdx.x;
+  const bool live = c < k.C;
+  const size_t C = (size_t)k.C;
+  // the cell's populations and segment bounds are requested before the table
+  // is staged, so the two memory round trips overlap
+  T f[Q];  // f_i (FP64) or g_i = f_i - w_i
+  int a0 = 0, a1 = 0;
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = load_v<P>(fsrc, i * C + c);
+    a0 = cs[c];
+    a1 = cs[c + 1];
+  }
   for (int i = threadIdx.x; i < min(k.nlut, LUT_ROWS_MAX) * LUT_W; i += BLOCK) sl[i] = lut[i];
   __syncthreads();
-  const int c = bidx * BLOCK + threadIdx.x;
-  if (c >= k.C) return;
+  if (!live) return;
   const int x = c % k.nx, y = c / k.nx;
-  const size_t C = (size_t)k.C;
-
-  T f[Q];  // f_i (FP64) or g_i = f_i - w_i
-#pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = load_v<P>(fsrc, i * C + c);
 
   // The binning leaves each cell's particles in arrival order: put the
   // segment in ascending particle index (a segment already in order is only
   // read).  Later stages of this step sum over the segment in that order.
   // Up to SEG_REG particles are handled in registers, longer segments by an
   // insertion sort of the records in memory.
-  const int a0 = cs[c], a1 = cs[c + 1];
   const int n = a1 - a0;
   T sx = (T)0, sy = (T)0;
   if (n <= SEG_REG) {
@@ -567,20 +591,47 @@ template <int P> struct DragTile {
   using T = typename Prec<P>::T;
   T ux[DSN], uy[DSN], es[DSN], beta[DSN], gpx[DSN], gpy[DSN];
 
-  __device__ void load(const Consts<T> &k, const Fields<T> &fl, int tx0, int ty0) {
-    for (int q = threadIdx.x; q < DSN; q += BLOCK) {
-      const int i = node_idx(tx0 - 1 + q % DSX, k.nx, k.per_x);
-      const int j = node_idx(ty0 - 1 + q / DSX, k.ny, k.per_y);
-      const size_t c = (size_t)j * k.nx + i;
-      ux[q] = fl.ugx[c];
-      uy[q] = fl.ugy[c];
-      beta[q] = fl.beta[c];
-      es[q] = fl.es[c];
-      // central differences of p = rho / 3, boundary value as the ghost beyond a wall
-      const int ie = node_idx(i + 1, k.nx, k.per_x), iw = node_idx(i - 1, k.nx, k.per_x);
-      const int jn = node_idx(j + 1, k.ny, k.per_y), js = node_idx(j - 1, k.ny, k.per_y);
-      gpx[q] = (fl.rho[(size_t)j * k.nx + ie] / (T)3.0 - fl.rho[(size_t)j * k.nx + iw] / (T)3.0) * (T)0.5;
-      gpy[q] = (fl.rho[(size_t)jn * k.nx + i] / (T)3.0 - fl.rho[(size_t)js * k.nx + i] / (T)3.0) * (T)0.5;
+  // A thread's share of the tile (slots threadIdx.x + r BLOCK), fetched into
+  // registers first and stored into the tile after the workgroup has decided
+  // to stay, so the fetch overlaps the first round trip of the kernel.
+  static constexpr int R = (DSN + BLOCK - 1) / BLOCK;
+  struct Regs {
+    T ux[R], uy[R], beta[R], es[R], re[R], rw[R], rn[R], rs[R];
+  };
+  __device__ static void fetch(const Consts<T> &k, const Fields<T> &fl, int tx0, int ty0, Regs &g) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = threadIdx.x + r * BLOCK;
+      if (q < DSN) {
+        const int i = node_idx(tx0 - 1 + q % DSX, k.nx, k.per_x);
+        const int j = node_idx(ty0 - 1 + q / DSX, k.ny, k.per_y);
+        const size_t c = (size_t)j * k.nx + i;
+        g.ux[r] = fl.ugx[c];
+        g.uy[r] = fl.ugy[c];
+        g.beta[r] = fl.beta[c];
+        g.es[r] = fl.es[c];
+        // central differences of p = rho / 3, boundary value as the ghost beyond a wall
+        const int ie = node_idx(i + 1, k.nx, k.per_x), iw = node_idx(i - 1, k.nx, k.per_x);
+        const int jn = node_idx(j + 1, k.ny, k.per_y), js = node_idx(j - 1, k.ny, k.per_y);
+        g.re[r] = fl.rho[(size_t)j * k.nx + ie];
+        g.rw[r] = fl.rho[(size_t)j * k.nx + iw];
+        g.rn[r] = fl.rho[(size_t)jn * k.nx + i];
+        g.rs[r] = fl.rho[(size_t)js * k.nx + i];
+      }
+    }
+  }
+  __device__ void store(const Regs &g) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = threadIdx.x + r * BLOCK;
+      if (q < DSN) {
+        ux[q] = g.ux[r];
+        uy[q] = g.uy[r];
+        beta[q] = g.beta[r];
+        es[q] = g.es[r];
+        gpx[q] = (g.re[r] / (T)3.0 - g.rw[r] / (T)3.0) * (T)0.5;
+        gpy[q] = (g.rn[r] / (T)3.0 - g.rs[r] / (T)3.0) * (T)0.5;
+      }
     }
   }
 };
@@ -626,6 +677,8 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
   const bool inside = cx < k.nx && cy < k.ny;
   const int a0 = inside ? cs[c] : 0, a1 = inside ? cs[c + 1] : 0;
   const int n = a1 - a0;
+  typename DragTile<P>::Regs tile_regs;
+  DragTile<P>::fetch(k, fl, tx0, ty0, tile_regs);
   // a tile without particles has nothing to do
   if (!__syncthreads_or(n > 0)) {
     if (zero_part && threadIdx.x == 0) zero_part[bidx] = 0;
@@ -641,7 +694,7 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
       pvx[u] = pt.vx[a0 + u];
       pvy[u] = pt.vy[a0 + u];
     }
-  D.load(k, fl, tx0, ty0);
+  D.store(tile_regs);
   // scan tiles the new cells of this tile's particles can fall in (one cell
   // move at most, periodic jumps go straight to the global counters)
   const int klo = max(0, (ty0 - 1) * k.nx + tx0 - 1);
@@ -810,7 +863,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, c
 // binary collisions.
 template <int P>
 __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
-                                                    Consts<typename Prec<P>::T> k, long long *__restrict__ adj,
+                                                    Consts<typename Prec<P>::T> k, Adj adj,
                                                     int32_t *__restrict__ deg, int32_t *__restrict__ done,
                                                     int32_t *ticket, int32_t *flags, long long *pair_part,
                                                     long long *wall_part, int32_t *__restrict__ chunk_busy,
@@ -830,9 +883,10 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
     const int key = pt.key[s];
     const int id = pt.pid[s];
     const T x = pt.px[s], y = pt.py[s];
+    T vx0 = pt.vx[s], vy0 = pt.vy[s];  // for the wall pass of a contact-free particle
     const int cy = key / k.nx, cx = key - cy * k.nx;
     const T dd = k.d * k.d;
-    long long *row = adj + (size_t)s * KMAX;
+    const AdjRow row = adj.row(s);
     // Pass 1 keeps the first CONTACT_REG contacts sorted in registers (no
     // stores while scanning, so candidate loads overlap); a particle with more
     // contacts is scanned again and its list built in memory.
@@ -870,14 +924,32 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
         if (dx * dx + dy * dy <= dd) hit(t);
       };
       if (inner_x) {
-        // one flattened pass over the three rows' ranges
+        // one flattened pass over the three rows' ranges, CONTACT_CH candidates
+        // at a time: their positions are all loaded before any is tested
         const int n0 = rhi[0] - rlo[0], n1 = rhi[1] - rlo[1], n2 = rhi[2] - rlo[2];
-        const int tot = n0 + n1 + n2;
-#pragma unroll 4
-        for (int q = 0; q < tot; ++q) {
-          const int rw = q < n0 ? 0 : (q < n0 + n1 ? 1 : 2);
-          const int t = rlo[rw] + q - (rw == 0 ? 0 : (rw == 1 ? n0 : n0 + n1));
-          test(t, t < rm1[rw] ? -1 : (t < rm2[rw] ? 0 : 1), rw - 1);
+        const int tot = n0 + n1 + n2;  // >= 1: the particle's own cell
+        for (int q0 = 0; q0 < tot; q0 += CONTACT_CH) {
+          int tt[CONTACT_CH], ox[CONTACT_CH], oy[CONTACT_CH];
+          T xs[CONTACT_CH], ys[CONTACT_CH];
+#pragma unroll
+          for (int j = 0; j < CONTACT_CH; ++j) {
+            const int q = min(q0 + j, tot - 1);  // past the end: repeat the last candidate
+            const int rw = q < n0 ? 0 : (q < n0 + n1 ? 1 : 2);
+            const int t = rlo[rw] + q - (rw == 0 ? 0 : (rw == 1 ? n0 : n0 + n1));
+            tt[j] = t;
+            ox[j] = t < rm1[rw] ? -1 : (t < rm2[rw] ? 0 : 1);
+            oy[j] = rw - 1;
+            xs[j] = pt.px[t];
+            ys[j] = pt.py[t];
+          }
+#pragma unroll
+          for (int j = 0; j < CONTACT_CH; ++j) {
+            if (q0 + j < tot && tt[j] != s) {
+              T dx, dy;
+              Pos<P>::sep_nb(k, ox[j], oy[j], x, y, xs[j], ys[j], dx, dy);
+              if (dx * dx + dy * dy <= dd) hit(tt[j]);
+            }
+          }
         }
       } else {
         for (int oy = -1; oy <= 1; ++oy) {
@@ -946,11 +1018,10 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
     done[s] = 0;
     if (cnt > 0) chunk_busy[id / RES_CHUNK] = 1;  // the resolution visits this chunk of indices
     if (cnt == 0) {  // no binary collision: the wall pass can run now
-      T vx = pt.vx[s], vy = pt.vy[s];
-      const int h = Pos<P>::walls(k, cx, cy, x, y, vx, vy);
+      const int h = Pos<P>::walls(k, cx, cy, x, y, vx0, vy0);
       if (h) {
-        pt.vx[s] = vx;
-        pt.vy[s] = vy;
+        pt.vx[s] = vx0;
+        pt.vy[s] = vy0;
         nwall += h;
       }
     }
@@ -969,7 +1040,7 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
 }
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
-                                                    Consts<typename Prec<P>::T> k, long long *__restrict__ adj,
+                                                    Consts<typename Prec<P>::T> k, Adj adj,
                                                     int32_t *__restrict__ deg, int32_t *__restrict__ done,
                                                     int32_t *ticket, int32_t *flags, long long *pair_part,
                                                     long long *wall_part, int32_t *__restrict__ chunk_busy,
@@ -1075,15 +1146,15 @@ struct MemRow {
 // (index << 32 | slot) and returns m; returns 0 if a member has a lower index
 // than g, and -1 if the cluster has more than cap members.
 template <class Row>
-__device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, const long long *__restrict__ adj,
+__device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, Adj adj,
                                               const int32_t *__restrict__ deg) {
   q[0] = ((long long)g << 32) | (unsigned)s;
   int m = 1;
   for (int head = 0; head < m; ++head) {
     const int u = (int)(q[head] & 0xffffffffll);
-    const long long *ru = adj + (size_t)u * KMAX;
+    const AdjRow ru = adj.row(u);
     const int du = min(deg[u], KMAX);
-    // the first four entries are loaded together (a row has KMAX slots)
+    // the first four entries are loaded together (the dense part of a row)
     const long long e0 = ru[0], e1 = ru[1], e2 = ru[2], e3 = ru[3];
     for (int a = 0; a < du; ++a) {
       const long long e = a == 0 ? e0 : (a == 1 ? e1 : (a == 2 ? e2 : (a == 3 ? e3 : ru[a])));
@@ -1106,7 +1177,7 @@ __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, cons
 // wall pass runs right after its own pairs.
 template <int P, class Row>
 __device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typename Prec<P>::T> &k,
-                                                Parts<typename Prec<P>::T> &pt, const long long *__restrict__ adj,
+                                                Parts<typename Prec<P>::T> &pt, Adj adj,
                                                 const int32_t *__restrict__ deg, int32_t *done, long long &ncoll,
                                                 long long &nwall) {
   using T = typename Prec<P>::T;
@@ -1121,9 +1192,9 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typen
   }
   for (int i = 0; i < m; ++i) {
     const int u = (int)(q[i] & 0xffffffffll), gu = (int)(q[i] >> 32);
-    const long long *ru = adj + (size_t)u * KMAX;
+    const AdjRow ru = adj.row(u);
     const int dgu = deg[u], du = min(dgu, KMAX);
-    const long long e0 = ru[0], e1 = ru[1], e2 = ru[2], e3 = ru[3];  // a row has KMAX slots
+    const long long e0 = ru[0], e1 = ru[1], e2 = ru[2], e3 = ru[3];  // the dense part of the row
     const int ku = pt.key[u];
     const T xu = pt.px[u], yu = pt.py[u];
     T vxu = pt.vx[u], vyu = pt.vy[u];
@@ -1200,7 +1271,7 @@ template <int P> __device__ __forceinline__ int big_find(const BigCluster<P> &B,
 // every thread of the workgroup calls it.
 template <int P>
 __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Consts<typename Prec<P>::T> &k,
-                            Parts<typename Prec<P>::T> &pt, const long long *__restrict__ adj,
+                            Parts<typename Prec<P>::T> &pt, Adj adj,
                             const int32_t *__restrict__ deg, int32_t *done, int32_t *need_sweep, long long &ncoll,
                             long long &nwall) {
   using T = typename Prec<P>::T;
@@ -1224,7 +1295,7 @@ __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Con
     if (stop) break;
     for (int t = h0 + tid; t < h1; t += BLOCK) {
       const int u = (int)(B.q[t] & 0xffffffffll);
-      const long long *ru = adj + (size_t)u * KMAX;
+      const AdjRow ru = adj.row(u);
       const int du = min(deg[u], KMAX);
       for (int a = 0; a < du; ++a) {
         const long long e = ru[a];
@@ -1281,7 +1352,7 @@ __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Con
     B.py[tid] = pt.py[u];
     B.vx[tid] = pt.vx[u];
     B.vy[tid] = pt.vy[u];
-    const long long *ru = adj + (size_t)u * KMAX;
+    const AdjRow ru = adj.row(u);
     const int du = min(deg[u], KMAX);
     for (int a = 0; a < du; ++a) cnt += (int)(ru[a] >> 32) > gu;
   }
@@ -1292,7 +1363,7 @@ __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Con
     return;
   }
   if (mem) {
-    const long long *ru = adj + (size_t)u * KMAX;
+    const AdjRow ru = adj.row(u);
     const int du = min(deg[u], KMAX);
     int w = off;
     for (int a = 0; a < du; ++a) {
@@ -1330,7 +1401,7 @@ __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Con
 
 template <int P>
 __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
-                                                            const long long *__restrict__ adj,
+                                                            Adj adj,
                                                             const int32_t *__restrict__ deg, int32_t *done,
                                                             Consts<typename Prec<P>::T> k, int32_t *need_sweep,
                                                             long long *coll_part, long long *wall_part,
@@ -1401,7 +1472,7 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
 }
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<P>::T> pt,
-                                                            const long long *__restrict__ adj,
+                                                            Adj adj,
                                                             const int32_t *__restrict__ deg, int32_t *done,
                                                             Consts<typename Prec<P>::T> k, int32_t *need_sweep,
                                                             long long *coll_part, long long *wall_part,
@@ -1413,8 +1484,8 @@ __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<
 
 // Position of particle index g in the neighbour list of slot t: the number of
 // neighbours of t with a lower index (bounded by the list length).
-__device__ __forceinline__ int row_position(const long long *adj, const int32_t *deg, int t, int g) {
-  const long long *rt = adj + (size_t)t * KMAX;
+__device__ __forceinline__ int row_position(Adj adj, const int32_t *deg, int t, int g) {
+  const AdjRow rt = adj.row(t);
   const int n = min(deg[t], KMAX);
   int b = 0;
   while (b < n && (int)(rt[b] >> 32) < g) ++b;
@@ -1424,7 +1495,7 @@ __device__ __forceinline__ int row_position(const long long *adj, const int32_t 
 
 template <int P>
 __device__ __forceinline__ void resolve_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
-                                                   const long long *__restrict__ adj, const int32_t *__restrict__ deg,
+                                                   Adj adj, const int32_t *__restrict__ deg,
                                                    int32_t *done, int32_t *ticket, Consts<typename Prec<P>::T> k,
                                                    int32_t *flags, long long *coll_part, long long *wall_part,
                                                    int32_t *__restrict__ chunk_busy, const int32_t *need_sweep) {
@@ -1463,7 +1534,7 @@ __device__ __forceinline__ void resolve_body(const int bidx, const int gdim, Par
     int j = 0, g = base;
     int state = 2;  // 0: pair pending, 1: waiting for all pairs, 2: finished
     int s = 0, dg = 0, a = 0, t = 0, b = 0;
-    const long long *row = nullptr;
+    AdjRow row{nullptr, nullptr};
     // Set up the next owned particle that has contacts (those without had
     // their wall pass in the contact kernel).
     auto next = [&]() {
@@ -1476,7 +1547,7 @@ __device__ __forceinline__ void resolve_body(const int bidx, const int gdim, Par
         s = slot[g];
         dg = deg[s];
         if (dg == 0 || done[s] == dg) continue;  // no contacts, or resolved with its cluster
-        row = adj + (size_t)s * KMAX;
+        row = adj.row(s);
         a = 0;
         while (a < dg && (int)(row[a] >> 32) < g) ++a;
         if (a < dg) {
@@ -1541,7 +1612,7 @@ __device__ __forceinline__ void resolve_body(const int bidx, const int gdim, Par
 }
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
-                                                   const long long *__restrict__ adj, const int32_t *__restrict__ deg,
+                                                   Adj adj, const int32_t *__restrict__ deg,
                                                    int32_t *done, int32_t *ticket, Consts<typename Prec<P>::T> k,
                                                    int32_t *flags, long long *coll_part, long long *wall_part,
                                                    int32_t *__restrict__ chunk_busy, const int32_t *need_sweep) {
@@ -1826,25 +1897,25 @@ __global__ __launch_bounds__(BLOCK) void k_get_field(const T *__restrict__ a, co
 
 // Forward contacts (higher index) per particle index, then the pair list.
 __global__ __launch_bounds__(BLOCK) void k_pairs_count(const int32_t *__restrict__ slot,
-                                                       const long long *__restrict__ adj,
+                                                       Adj adj,
                                                        const int32_t *__restrict__ deg, int n, int32_t *cnt) {
   const int g = blockIdx.x * BLOCK + threadIdx.x;
   if (g >= n) return;
   const int s = slot[g];
-  const long long *row = adj + (size_t)s * KMAX;
+  const AdjRow row = adj.row(s);
   int c = 0;
   for (int a = 0; a < deg[s]; ++a) c += (int)(row[a] >> 32) > g;
   cnt[g] = c;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pairs_write(const int32_t *__restrict__ slot,
-                                                       const long long *__restrict__ adj,
+                                                       Adj adj,
                                                        const int32_t *__restrict__ deg, int n,
                                                        const int32_t *__restrict__ off, int32_t *pairs, long long cap) {
   const int g = blockIdx.x * BLOCK + threadIdx.x;
   if (g >= n) return;
   const int s = slot[g];
-  const long long *row = adj + (size_t)s * KMAX;
+  const AdjRow row = adj.row(s);
   long long o = off[g];
   for (int a = 0; a < deg[s]; ++a) {
     const int j = (int)(row[a] >> 32);

@@ -168,7 +168,8 @@ struct lbdps_ctx {
   void *px[2]{}, *py[2]{}, *vx[2]{}, *vy[2]{};
   int32_t *rank = nullptr, *perm = nullptr, *slot = nullptr, *deg = nullptr, *done = nullptr;
   int32_t *ticket = nullptr, *flags = nullptr, *nonfinite = nullptr;
-  long long *adj = nullptr;
+  long long *adj_in = nullptr, *adj_ov = nullptr;
+  Adj adj() const { return Adj{adj_in, adj_ov}; }
   void *lut = nullptr, *inlet = nullptr;
   long long *pair_part = nullptr, *coll_part = nullptr, *wall_part = nullptr, *wall0_part = nullptr,
             *zero_part = nullptr;
@@ -225,7 +226,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   }
   int32_t *rank = cv.take<int32_t>(N + 1), *perm = cv.take<int32_t>(N + 1), *slot = cv.take<int32_t>(N);
   int32_t *deg = cv.take<int32_t>(N), *done = cv.take<int32_t>(N);
-  long long *adj = cv.take<long long>(N * KMAX);
+  long long *adj_in = cv.take<long long>(N * ADJ_IN), *adj_ov = cv.take<long long>(N * (KMAX - ADJ_IN));
   int32_t *ticket = cv.take<int32_t>(4), *flags = cv.take<int32_t>(FLAG_COUNT), *nonfinite = cv.take<int32_t>(4);
   char *lut = raw((size_t)lut_rows(p.d_p) * LUT_W * sT), *inlet = raw((size_t)p.nx * sT);
   const size_t nbN = (size_t)nblocks((long long)N), nbC = (size_t)nblocks((long long)C);
@@ -272,7 +273,8 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->slot = slot;
     x->deg = deg;
     x->done = done;
-    x->adj = adj;
+    x->adj_in = adj_in;
+    x->adj_ov = adj_ov;
     x->ticket = ticket;
     x->flags = flags;
     x->nonfinite = nonfinite;
@@ -420,15 +422,15 @@ template <int P> struct Impl {
     if (N == 0) return;
     const Consts<T> k = consts(x);
     tstart(x, LBDPS_K_CONTACTS);
-    hipLaunchKernelGGL(k_contacts<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->cs, k, x->adj,
+    hipLaunchKernelGGL(k_contacts<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->cs, k, x->adj(),
                        x->deg, x->done, x->ticket, x->flags, x->pair_part, x->wall0_part, x->chunk_busy,
                        x->need_sweep, x->roots, x->rcount);
     tstop(x, LBDPS_K_CONTACTS);
     tstart(x, LBDPS_K_RESOLVE);
     hipLaunchKernelGGL(k_resolve_clusters<P>, dim3(cluster_blocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
-                       x->adj, x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part, x->cluster_scratch,
+                       x->adj(), x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part, x->cluster_scratch,
                        x->roots, x->rcount, nblocks(N));
-    hipLaunchKernelGGL(k_resolve<P>, dim3(resolve_blocks(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot, x->adj,
+    hipLaunchKernelGGL(k_resolve<P>, dim3(resolve_blocks(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot, x->adj(),
                        x->deg, x->done, x->ticket, k, x->flags, x->coll_part, x->wall_part, x->chunk_busy,
                        x->need_sweep);
     tstop(x, LBDPS_K_RESOLVE);
@@ -717,12 +719,12 @@ lbdps_status lbdps_get_pairs(lbdps_ctx *x, int32_t *d_pairs, int64_t cap, int64_
   *n_out = 0;
   if (N == 0) return sync_and_check(x, "lbdps_get_pairs");
   // rank and perm are free between steps: counts, then offsets
-  hipLaunchKernelGGL(k_pairs_count, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->slot, x->adj, x->deg, N, x->rank);
+  hipLaunchKernelGGL(k_pairs_count, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->slot, x->adj(), x->deg, N, x->rank);
   dispatch(x, [&](auto impl) {
     decltype(impl)::scan(x, x->rank, N, x->perm, 0);
     return LBDPS_OK;
   });
-  hipLaunchKernelGGL(k_pairs_write, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->slot, x->adj, x->deg, N, x->perm,
+  hipLaunchKernelGGL(k_pairs_write, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->slot, x->adj(), x->deg, N, x->perm,
                      d_pairs, (long long)cap);
   lbdps_status st = launch_status("lbdps_get_pairs");
   if (st != LBDPS_OK) return st;
@@ -902,7 +904,7 @@ template <int P> struct BatchImpl {
     a.need_sweep = x->need_sweep;
     a.roots = x->roots;
     a.rcount = x->rcount;
-    a.adj = x->adj;
+    a.adj = x->adj();
     a.pair_part = x->pair_part;
     a.wall0_part = x->wall0_part;
     a.coll_part = x->coll_part;
