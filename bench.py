@@ -75,6 +75,7 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None):
     sim = L.Sim(cfg, precision=prec)
     stream = sim.stream
     sim.step(warmup)
+    tuning = sim.autotune(4)  # launch shape of the cluster resolution (results do not depend on it)
     torch.cuda.synchronize()
     # per-kernel breakdown (separate pass): find the dominant kernel
     sim.time_kernels(L.KERNELS)
@@ -99,7 +100,7 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None):
     sim.time_kernels([])
     counters = sim.counters()
     out = dict(ms=ms, breakdown_us=breakdown, dominant=dominant, dom_ms=kt[0], dom_launches=kt[1],
-               pairs=counters["pairs"])
+               pairs=counters["pairs"], tuning=tuning)
     sim.close()
     return out
 
@@ -227,7 +228,10 @@ def run_beds(args, torch, L):
     K = args.steps + (args.steps & 1)  # graphs hold an even number of steps
     batch = L.Batch(cfgs, precision=prec)
     st = batch.stream
+    batch.step(args.warmup)
+    tunings = batch.autotune(steps=4)  # launch shapes per bed size class
     # every measured region starts again from the initial beds, after the warmup
+    batch.reset()
     batch.step(args.warmup)
     batch.time_kernels(L.KERNELS)
     batch.step(max(4, min(K, 20)))
@@ -288,6 +292,7 @@ def run_beds(args, torch, L):
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3)},
+        "autotune": sorted({(t["cluster_lists"], t["cluster_groups_max"]) for t in tunings}),
         "batched_eager_ms_per_step": round(ms_eager / K, 5),
         "graph_first_replay_ms_per_step": round(ms_first / K, 5),
         "sequential_fp32_ms_per_step": round(ms_seq / K, 5),
@@ -391,6 +396,7 @@ def main():
         "model_bytes_per_step": int(model),
         "model_bw_frac": round(model * args.steps / s / 1e9 / HBM_PEAK_GBS, 4),
         "contact_pairs": r["pairs"],
+        "autotune": [r["tuning"]["cluster_lists"], r["tuning"]["cluster_groups_max"]],
         "kernel_us": {k: round(v, 2) for k, v in r["breakdown_us"].items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

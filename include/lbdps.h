@@ -212,6 +212,30 @@ lbdps_status lbdps_time_kernels(lbdps_ctx *ctx, uint32_t mask);
  */
 lbdps_status lbdps_kernel_times(lbdps_ctx *ctx, double *h_ms, int64_t *h_launches);
 
+/*
+ * Launch shapes that do not change results (every setting gives the same
+ * numbers bit for bit), only speed:
+ *   cluster_lists      candidate lists of the contact kernel taken by one
+ *                      workgroup of the cluster resolution, [1, 256] (default 1);
+ *   cluster_groups_max most workgroups of the cluster resolution (default: no
+ *                      limit);
+ *   drag_tile          drag tile shape: 0 = 32 x 8 cells (the only one built).
+ * A context starts with the defaults.
+ */
+typedef struct {
+  int32_t cluster_lists;
+  int32_t cluster_groups_max;
+  int32_t drag_tile;
+} lbdps_tuning;
+lbdps_status lbdps_set_tuning(lbdps_ctx *ctx, const lbdps_tuning *t);
+lbdps_status lbdps_get_tuning(lbdps_ctx *ctx, lbdps_tuning *t);
+
+/* Autotuner: run `steps` steps under each candidate launch shape, time them
+ * with hipEvents on the context's stream and keep the fastest (written to
+ * *chosen if not NULL).  The bed advances by steps x (number of candidates).
+ * Synchronises. */
+lbdps_status lbdps_autotune(lbdps_ctx *ctx, int32_t steps, lbdps_tuning *chosen);
+
 /* Release the host context (the workspace stays the caller's).  A bed of a
  * batch is released by lbdps_batch_destroy instead (LBDPS_E_INVALID here). */
 lbdps_status lbdps_destroy(lbdps_ctx *ctx);
@@ -268,6 +292,17 @@ lbdps_status lbdps_batch_sync(lbdps_batch *batch);
  * timed).  LBDPS_K_RESOLVE covers both resolution launches. */
 lbdps_status lbdps_batch_time_kernels(lbdps_batch *batch, uint32_t mask);
 lbdps_status lbdps_batch_kernel_times(lbdps_batch *batch, double *h_ms, int64_t *h_launches);
+
+/*
+ * Autotuner of a batch: beds are grouped into size classes by particle count
+ * (up to 2048, 4096, 8192, ...).  Class by class, every candidate launch shape
+ * is applied to the class's beds and `steps` batched steps are timed; the
+ * fastest is kept.  Every bed advances by the steps taken.  cache_path (or
+ * NULL): a text file of chosen shapes per class and precision; classes found
+ * there are not timed again, and the file is rewritten with all classes.
+ * Synchronises.
+ */
+lbdps_status lbdps_batch_autotune(lbdps_batch *batch, int32_t steps, const char *cache_path);
 
 /* Release the batch and its beds' contexts (the workspace stays the caller's). */
 lbdps_status lbdps_batch_destroy(lbdps_batch *batch);

@@ -25,7 +25,7 @@ template <int P> struct BedArgs {
   int32_t *cs, *count, *rank, *slot, *flags, *deg, *done, *ticket, *chunk_busy, *need_sweep, *rcount;
   long long *roots;
   Adj adj;
-  long long *pair_part, *wall0_part, *coll_part, *wall_part, *collc_part, *wallc_part, *scratch;
+  long long *pair_part, *wall0_part, *coll_part, *wall_part, *collc_part, *wallc_part;
   TileSums ts;
   int cf;        // population buffer holding the state when the table was written
   int cp;        // particle record set holding the state when the table was written
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(BLOCK) void kb_clusters(const BedArgs<P> *__restric
                                                      int nbeds, int flip) {
   LBDPS_BED_PROLOGUE
   resolve_clusters_body<P>(bid, nbk, a.parts(1 - cp), a.adj, a.deg, a.done, a.k, a.need_sweep, a.collc_part,
-                           a.wallc_part, a.scratch, a.roots, a.rcount, a.nlists);
+                           a.wallc_part, a.roots, a.rcount, a.nlists);
 }
 
 template <int P>

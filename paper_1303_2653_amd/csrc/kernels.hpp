@@ -1123,23 +1123,18 @@ __device__ __forceinline__ int wall_pass(const Consts<typename Prec<P>::T> &k, P
 // of each member and marks them finished (done = number of contacts).  No lane
 // waits for another.
 //
-// The cluster is gathered into CL_LDS entries of LDS; a larger one is gathered
-// again into the lane's CLUSTER_MAX-entry row of global scratch, and a cluster
-// beyond that is left to the ordered sweep of k_resolve.  Each workgroup takes
-// the candidate lists of a run of contact-kernel workgroups and deals their
-// candidates out to its lanes densely, so lanes resolve several clusters each.
+// The cluster is gathered into CL_LDS entries of LDS; a larger one is queued
+// for the whole workgroup (below), and one the queue cannot take is left to
+// the ordered sweep of k_resolve.  Each workgroup takes the candidate lists of
+// a run of contact-kernel workgroups and deals their candidates out to its
+// lanes densely.
 constexpr int CL_LDS = 8;
-constexpr int CLUSTER_MAX = 64;
-constexpr int RC_GRID_MAX = 2048;  // resolution workgroups (each takes <= BLOCK candidate lists)
-constexpr int RC_LISTS_MIN = 4;    // candidate lists per resolution workgroup, at least
+constexpr int RC_LISTS = 1;           // candidate lists per resolution workgroup (default)
+constexpr int RC_GROUPS_MAX = 1 << 30;  // most resolution workgroups (default: no limit)
 
 struct LdsColumn {  // entry i of a lane's column of a [CL_LDS][BLOCK] LDS array
   long long *p;
   __device__ long long &operator[](int i) const { return p[i * BLOCK]; }
-};
-struct MemRow {
-  long long *p;
-  __device__ long long &operator[](int i) const { return p[i]; }
 };
 
 // Gathers the cluster of candidate slot s (index g) into q[0 .. m) as
@@ -1405,7 +1400,6 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
                                                             const int32_t *__restrict__ deg, int32_t *done,
                                                             Consts<typename Prec<P>::T> k, int32_t *need_sweep,
                                                             long long *coll_part, long long *wall_part,
-                                                            long long *__restrict__ scratch,
                                                             const long long *__restrict__ roots,
                                                             const int32_t *__restrict__ rcount, int nlists) {
   __shared__ long long sh[BLOCK / 64];
@@ -1431,7 +1425,6 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
   if (threadIdx.x == 0) pre[nb] = tot;
   __syncthreads();
   const LdsColumn ql{qs + threadIdx.x};
-  const MemRow qg{scratch + ((size_t)bidx * BLOCK + threadIdx.x) * CLUSTER_MAX};
   long long ncoll = 0, nwall = 0;
   for (int f = threadIdx.x; f < tot; f += BLOCK) {
     int lo = 0, hi = nb;  // list j with pre[j] <= f < pre[j + 1]
@@ -1447,13 +1440,8 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
       resolve_cluster<P>(ql, m, k, pt, adj, deg, done, ncoll, nwall);
     } else if (m < 0) {
       const int slot = atomicAdd(&nbig, 1);  // the workgroup resolves it below
-      if (slot < BIG_LIST) {
-        bigc[slot] = r;
-      } else {  // queue full: this lane alone, in its global scratch row
-        m = gather_cluster(qg, CLUSTER_MAX, s, g, adj, deg);
-        if (m > 0) resolve_cluster<P>(qg, m, k, pt, adj, deg, done, ncoll, nwall);
-        else if (m < 0) atomicOr(need_sweep, 1);
-      }
+      if (slot < BIG_LIST) bigc[slot] = r;
+      else atomicOr(need_sweep, 1);  // queue full: the ordered sweep takes it
     }
   }
   __syncthreads();
@@ -1476,10 +1464,9 @@ __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<
                                                             const int32_t *__restrict__ deg, int32_t *done,
                                                             Consts<typename Prec<P>::T> k, int32_t *need_sweep,
                                                             long long *coll_part, long long *wall_part,
-                                                            long long *__restrict__ scratch,
                                                             const long long *__restrict__ roots,
                                                             const int32_t *__restrict__ rcount, int nlists) {
-  resolve_clusters_body<P>(blockIdx.x, gridDim.x, pt, adj, deg, done, k, need_sweep, coll_part, wall_part, scratch, roots, rcount, nlists);
+  resolve_clusters_body<P>(blockIdx.x, gridDim.x, pt, adj, deg, done, k, need_sweep, coll_part, wall_part, roots, rcount, nlists);
 }
 
 // Position of particle index g in the neighbour list of slot t: the number of

@@ -4,6 +4,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <new>
 #include <string>
 #include <vector>
@@ -27,13 +30,12 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int NB_CONS = 512;  // workgroups of the conservation reductions
 
 int nblocks(long long n) { return (int)((n + BLOCK - 1) / BLOCK); }
-// Workgroups of the cluster resolution: each takes at least RC_LISTS_MIN of the
-// contact kernel's candidate lists (about a fifth of a list's particles are
-// candidates, so that fills its wavefronts) and at most BLOCK; at most
-// RC_GRID_MAX workgroups unless more are needed for that.
-int cluster_blocks(long long n) {
+// Workgroups of the cluster resolution for n particles: each takes at least
+// `lists` of the contact kernel's candidate lists and at most BLOCK; at most
+// `groups_max` workgroups unless more are needed for that.
+int cluster_blocks(long long n, int lists = RC_LISTS, int groups_max = RC_GROUPS_MAX) {
   const long long nl = std::max(1ll, (long long)nblocks(n));
-  const long long want = std::min((nl + RC_LISTS_MIN - 1) / RC_LISTS_MIN, (long long)RC_GRID_MAX);
+  const long long want = std::min((nl + lists - 1) / lists, (long long)groups_max);
   return (int)std::max(std::max(want, 1ll), (nl + BLOCK - 1) / BLOCK);
 }
 
@@ -159,6 +161,8 @@ struct lbdps_ctx {
   bool bins_valid = false;
   long long step = 0;
   bool in_batch = false;  // owned by a batch: destroyed with it
+  lbdps_tuning tune{RC_LISTS, RC_GROUPS_MAX, 0};
+  int cluster_groups() const { return cluster_blocks(n, tune.cluster_lists, tune.cluster_groups_max); }
   DConsts dc{};
   // device buffers (carved from the workspace)
   void *f[2]{};
@@ -175,7 +179,6 @@ struct lbdps_ctx {
             *zero_part = nullptr;
   int32_t *tile_sum = nullptr, *chunk_busy = nullptr, *need_sweep = nullptr;
   int tile_shift = 11;
-  long long *cluster_scratch = nullptr;
   long long *roots = nullptr;
   int32_t *rcount = nullptr;
   long long *collc_part = nullptr, *wallc_part = nullptr;
@@ -238,7 +241,6 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   const int shift = cell_tile_shift(C);
   const size_t ntiles = (C + ((size_t)1 << shift) - 1) >> shift;
   int32_t *tile_sum = cv.take<int32_t>(ntiles + 1);
-  long long *cluster_scratch = cv.take<long long>((size_t)cluster_blocks((long long)N) * BLOCK * CLUSTER_MAX);
   long long *roots = cv.take<long long>(nbN * BLOCK);
   int32_t *rcount = cv.take<int32_t>(nbN);
   int32_t *chunk_busy = cv.take<int32_t>(N / RES_CHUNK + 1), *need_sweep = cv.take<int32_t>(4);
@@ -287,7 +289,6 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->wall0_part = wall0_part;
     x->tile_sum = tile_sum;
     x->tile_shift = shift;
-    x->cluster_scratch = cluster_scratch;
     x->roots = roots;
     x->rcount = rcount;
     x->chunk_busy = chunk_busy;
@@ -427,8 +428,8 @@ template <int P> struct Impl {
                        x->need_sweep, x->roots, x->rcount);
     tstop(x, LBDPS_K_CONTACTS);
     tstart(x, LBDPS_K_RESOLVE);
-    hipLaunchKernelGGL(k_resolve_clusters<P>, dim3(cluster_blocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
-                       x->adj(), x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part, x->cluster_scratch,
+    hipLaunchKernelGGL(k_resolve_clusters<P>, dim3(x->cluster_groups()), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
+                       x->adj(), x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part,
                        x->roots, x->rcount, nblocks(N));
     hipLaunchKernelGGL(k_resolve<P>, dim3(resolve_blocks(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot, x->adj(),
                        x->deg, x->done, x->ticket, k, x->flags, x->coll_part, x->wall_part, x->chunk_busy,
@@ -776,7 +777,7 @@ lbdps_status lbdps_counters(lbdps_ctx *x, int64_t h_out[4]) {
   long long *src[6] = {x->pair_part, x->coll_part, x->wall_part, x->wall0_part, x->collc_part, x->wallc_part};
   const int dst[6] = {0, 1, 2, 2, 1, 2};
   const int nres = Impl<PREC_FP32>::resolve_blocks(x);
-  const int ncl = cluster_blocks(x->n);
+  const int ncl = x->cluster_groups();
   const int len[6] = {nbN, nres, nres, nbN, ncl, ncl};
   for (int j = 0; j < 4; ++j) h_out[j] = 0;
   if (x->n > 0)
@@ -818,6 +819,83 @@ lbdps_status lbdps_kernel_times(lbdps_ctx *x, double *h_ms, int64_t *h_launches)
     if (h_ms) h_ms[k] = ms[k];
     if (h_launches) h_launches[k] = cnt[k];
   }
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_set_tuning(lbdps_ctx *x, const lbdps_tuning *t) {
+  if (!x || !t) return fail(LBDPS_E_INVALID, "ctx or tuning is NULL");
+  if (t->cluster_lists < 1 || t->cluster_lists > BLOCK) return fail(LBDPS_E_INVALID, "cluster_lists must be in [1, 256]");
+  if (t->cluster_groups_max < 1) return fail(LBDPS_E_INVALID, "cluster_groups_max must be >= 1");
+  if (t->drag_tile != 0) return fail(LBDPS_E_UNSUPPORTED, "drag_tile: only 0 (32x8) is built");
+  x->tune = *t;
+  return LBDPS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Launch shapes the autotuner tries (all give identical results).
+const lbdps_tuning kTuneCandidates[] = {
+    {1, RC_GROUPS_MAX, 0}, {2, RC_GROUPS_MAX, 0}, {4, RC_GROUPS_MAX, 0},
+    {1, 4096, 0},          {1, 1024, 0},          {4, 1024, 0},
+};
+constexpr int kTuneN = (int)(sizeof(kTuneCandidates) / sizeof(kTuneCandidates[0]));
+
+// Milliseconds of the work fn enqueues on stream st.
+template <class F> lbdps_status time_on(hipStream_t st, F &&fn, float *ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  lbdps_status r = check_hip(hipEventCreate(&a), "autotune");
+  if (r == LBDPS_OK) r = check_hip(hipEventCreate(&b), "autotune");
+  if (r == LBDPS_OK) r = check_hip(hipEventRecord(a, st), "autotune");
+  if (r == LBDPS_OK) r = fn();
+  if (r == LBDPS_OK) r = check_hip(hipEventRecord(b, st), "autotune");
+  if (r == LBDPS_OK) r = check_hip(hipEventSynchronize(b), "autotune");
+  if (r == LBDPS_OK) r = check_hip(hipEventElapsedTime(ms, a, b), "autotune");
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return r;
+}
+
+// Size class of a bed: particle counts 1..2048 -> 0, ..4096 -> 1, ...; none -> -1.
+int size_class(long long n) {
+  if (n <= 0) return -1;
+  int c = 0;
+  while ((2048ll << c) < n) ++c;
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbdps_status lbdps_autotune(lbdps_ctx *x, int32_t steps, lbdps_tuning *chosen) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (steps < 1) return fail(LBDPS_E_INVALID, "steps must be >= 1");
+  float best = 0.f;
+  lbdps_tuning bt = x->tune;
+  for (int c = 0; c < kTuneN; ++c) {
+    x->tune = kTuneCandidates[c];
+    float ms = 0.f;
+    lbdps_status st = time_on(
+        x->stream, [&]() { return dispatch(x, [&](auto impl) { return decltype(impl)::step(x, steps); }); }, &ms);
+    if (st != LBDPS_OK) {
+      x->tune = bt;
+      return st;
+    }
+    if (c == 0 || ms < best) {
+      best = ms;
+      bt = kTuneCandidates[c];
+    }
+  }
+  x->tune = bt;
+  if (chosen) *chosen = bt;
+  return sync_and_check(x, "lbdps_autotune");
+}
+
+lbdps_status lbdps_get_tuning(lbdps_ctx *x, lbdps_tuning *t) {
+  if (!x || !t) return fail(LBDPS_E_INVALID, "ctx or tuning is NULL");
+  *t = x->tune;
   return LBDPS_OK;
 }
 
@@ -911,7 +989,6 @@ template <int P> struct BatchImpl {
     a.wall_part = x->wall_part;
     a.collc_part = x->collc_part;
     a.wallc_part = x->wallc_part;
-    a.scratch = x->cluster_scratch;
     a.ts = I::tiles(x);
     a.cf = x->cf;
     a.cp = x->cp;
@@ -929,7 +1006,7 @@ template <int P> struct BatchImpl {
     nb[PH_SCAN] = x->ntiles;
     nb[PH_SCATTER] = nblocks(x->n);
     nb[PH_CONTACTS] = nblocks(x->n);
-    nb[PH_CLUSTERS] = cluster_blocks(x->n);
+    nb[PH_CLUSTERS] = x->cluster_groups();
     nb[PH_RESOLVE] = I::resolve_blocks(x);
   }
 
@@ -1233,6 +1310,55 @@ lbdps_status lbdps_batch_kernel_times(lbdps_batch *B, double *h_ms, int64_t *h_l
     if (h_launches) h_launches[k] = cnt[k];
   }
   return LBDPS_OK;
+}
+
+lbdps_status lbdps_batch_autotune(lbdps_batch *B, int32_t steps, const char *cache_path) {
+  if (!B) return fail(LBDPS_E_INVALID, "batch is NULL");
+  if (steps < 1) return fail(LBDPS_E_INVALID, "steps must be >= 1");
+  std::map<int, std::vector<int>> cls;
+  for (int b = 0; b < B->nbeds; ++b) cls[size_class(B->beds[b]->n)].push_back(b);
+  cls.erase(-1);
+  const std::string head = "lbdps-tune 1 precision " + std::to_string(B->prec);
+  std::map<int, lbdps_tuning> cached;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    if (in && std::getline(in, line) && line == head) {
+      int c;
+      lbdps_tuning t{};
+      while (in >> c >> t.cluster_lists >> t.cluster_groups_max >> t.drag_tile) cached[c] = t;
+    }
+  }
+  for (auto &kv : cls) {
+    auto it = cached.find(kv.first);
+    if (it != cached.end()) {
+      for (int b : kv.second) B->beds[b]->tune = it->second;
+      continue;
+    }
+    float best = 0.f;
+    lbdps_tuning bt = kTuneCandidates[0];
+    for (int c = 0; c < kTuneN; ++c) {
+      for (int b : kv.second) B->beds[b]->tune = kTuneCandidates[c];
+      float ms = 0.f;
+      lbdps_status st = time_on(B->stream, [&]() { return lbdps_batch_step(B, steps); }, &ms);
+      if (st != LBDPS_OK) return st;
+      if (c == 0 || ms < best) {
+        best = ms;
+        bt = kTuneCandidates[c];
+      }
+    }
+    for (int b : kv.second) B->beds[b]->tune = bt;
+    cached[kv.first] = bt;
+  }
+  if (cache_path) {
+    std::ofstream out(cache_path);
+    if (!out) return fail(LBDPS_E_INVALID, std::string("cannot write the tuning cache ") + cache_path);
+    out << head << "\n";
+    for (auto &kv : cached)
+      out << kv.first << " " << kv.second.cluster_lists << " " << kv.second.cluster_groups_max << " "
+          << kv.second.drag_tile << "\n";
+  }
+  return lbdps_batch_sync(B);
 }
 
 lbdps_status lbdps_batch_destroy(lbdps_batch *B) {

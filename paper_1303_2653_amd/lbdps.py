@@ -42,6 +42,10 @@ class lbdps_params(ctypes.Structure):
     ]
 
 
+class lbdps_tuning(ctypes.Structure):
+    _fields_ = [("cluster_lists", c_i32), ("cluster_groups_max", c_i32), ("drag_tile", c_i32)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
 
@@ -62,6 +66,10 @@ _SIGS = {
     "lbdps_counters": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
     "lbdps_time_kernels": (c_i32, [c_vp, ctypes.c_uint32]),
     "lbdps_kernel_times": (c_i32, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
+    "lbdps_set_tuning": (c_i32, [c_vp, ctypes.POINTER(lbdps_tuning)]),
+    "lbdps_get_tuning": (c_i32, [c_vp, ctypes.POINTER(lbdps_tuning)]),
+    "lbdps_autotune": (c_i32, [c_vp, c_i32, ctypes.POINTER(lbdps_tuning)]),
+    "lbdps_batch_autotune": (c_i32, [c_vp, c_i32, ctypes.c_char_p]),
     "lbdps_destroy": (c_i32, [c_vp]),
     "lbdps_batch_workspace_bytes": (c_i32, [_P, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_size_t)]),
     "lbdps_batch_create": (c_i32, [_P, c_i32, ctypes.POINTER(c_i64), c_vp, c_vp, ctypes.c_size_t, c_vp,
@@ -258,6 +266,20 @@ class Sim:
         check(lbdps_counters(self.ctx, out), "lbdps_counters")
         return dict(pairs=out[0], collisions=out[1], walls=out[2], zero_den=out[3])
 
+    def tuning(self) -> dict:
+        t = lbdps_tuning()
+        check(lbdps_get_tuning(self.ctx, ctypes.byref(t)), "lbdps_get_tuning")
+        return {n: getattr(t, n) for n, _ in lbdps_tuning._fields_}
+
+    def set_tuning(self, **kw):
+        t = lbdps_tuning(**{**self.tuning(), **kw})
+        check(lbdps_set_tuning(self.ctx, ctypes.byref(t)), "lbdps_set_tuning")
+
+    def autotune(self, steps: int = 4) -> dict:
+        t = lbdps_tuning()
+        check(lbdps_autotune(self.ctx, int(steps), ctypes.byref(t)), "lbdps_autotune")
+        return {n: getattr(t, n) for n, _ in lbdps_tuning._fields_}
+
     def time_kernels(self, names):
         mask = 0
         for n in names:
@@ -330,6 +352,13 @@ class Batch:
 
     def step(self, nsteps: int = 1):
         check(lbdps_batch_step(self.batch, int(nsteps)), "lbdps_batch_step")
+
+    def autotune(self, steps: int = 4, cache_path=None) -> list:
+        """Choose launch shapes per bed size class (see lbdps_batch_autotune);
+        returns each bed's tuning."""
+        path = None if cache_path is None else os.fsencode(cache_path)
+        check(lbdps_batch_autotune(self.batch, int(steps), path), "lbdps_batch_autotune")
+        return [b.tuning() for b in self.beds]
 
     def capture(self, nsteps: int):
         check(lbdps_batch_capture(self.batch, int(nsteps)), "lbdps_batch_capture")

@@ -129,3 +129,10 @@ def test_batch_create_rejects_small_workspace_before_device():
     assert st == L.LBDPS_E_SHAPE and not b.value
     assert L.lbdps_batch_step(None, 1) == L.LBDPS_E_INVALID
     assert L.lbdps_batch_capture(None, 2) == L.LBDPS_E_INVALID
+
+
+def test_tuning_struct_layout():
+    assert ctypes.sizeof(L.lbdps_tuning) == 12
+    assert L.lbdps_set_tuning(None, None) == L.LBDPS_E_INVALID
+    assert L.lbdps_autotune(None, 1, None) == L.LBDPS_E_INVALID
+    assert L.lbdps_batch_autotune(None, 1, None) == L.LBDPS_E_INVALID

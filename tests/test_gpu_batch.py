@@ -146,3 +146,21 @@ def test_batch_of_64_uneven_beds_fp16():
         assert_same(snapshot(batch.beds[i]), snapshot(single), f"bed {i}")
         del single
     batch.close()
+
+
+def test_batch_autotune_cache(tmp_path):
+    """The batch autotuner writes its choice per size class to the cache file;
+    a second batch reads it back and gets the same launch shapes."""
+    cfgs = uneven_beds("fp16")
+    path = tmp_path / "tune.txt"
+    a = L.Batch(cfgs)
+    ta = a.autotune(2, path)
+    a.sync()
+    text = path.read_text().splitlines()
+    say(text)
+    assert text[0].startswith("lbdps-tune 1")
+    b = L.Batch(cfgs)
+    tb = b.autotune(2, path)
+    assert ta == tb
+    a.close()
+    b.close()

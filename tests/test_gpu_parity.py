@@ -360,3 +360,24 @@ def test_error_particle_outside_domain():
     assert e.value.status == L.LBDPS_E_INVALID
     gpu.step(2)
     gpu.conservation()  # the healthy context is unaffected
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_launch_shapes_do_not_change_results(prec):
+    """Every launch shape the autotuner may pick gives the same state bit for
+    bit (a dense bed: clusters of all three resolution paths)."""
+    cfg = CLUSTER_BEDS["dense_box"]()
+    cfg["vel"] = (np.random.default_rng(3).random(cfg["pos"].shape) - 0.5) * 2e-2
+    ref = None
+    for lists, gmax in ((1, 1 << 30), (4, 1 << 30), (1, 1), (256, 2)):
+        sim = L.Sim(cfg, precision=prec)
+        sim.set_tuning(cluster_lists=lists, cluster_groups_max=gmax)
+        sim.step(3)
+        st = sim.state()
+        if ref is None:
+            ref = st
+        else:
+            for a, b in zip(st[:3], ref[:3]):
+                assert (a == b).all(), (lists, gmax)
+    chosen = L.Sim(cfg, precision=prec).autotune(2)
+    assert chosen["cluster_lists"] >= 1 and chosen["cluster_groups_max"] >= 1
