@@ -22,7 +22,7 @@ template <int P> struct BedArgs {
   T *px[2], *py[2], *vx[2], *vy[2];
   Fields<T> fl;
   const T *lut, *inlet;
-  int32_t *cs, *count, *rank, *slot, *flags, *deg, *done, *ticket, *chunk_busy, *need_sweep, *rcount;
+  int32_t *cs, *count, *stay, *rank, *slot, *flags, *deg, *done, *ticket, *chunk_busy, *need_sweep, *rcount;
   long long *roots;
   Adj adj;
   long long *pair_part, *wall0_part, *coll_part, *wall_part, *collc_part, *wallc_part;
@@ -70,21 +70,21 @@ __global__ __launch_bounds__(BLOCK) void kb_drag(const BedArgs<P> *__restrict__ 
                                                  int nbeds, int flip) {
   LBDPS_BED_PROLOGUE
   drag_body<P>(bid, nbk, a.parts(cp), a.fl, a.cs, a.lut, a.k, a.count, a.rank, a.flags, nullptr, nullptr, nullptr,
-               a.ts);
+               a.ts, a.stay);
 }
 
 template <int P>
 __global__ __launch_bounds__(BLOCK) void kb_scan(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                  int nbeds, int flip) {
   LBDPS_BED_PROLOGUE
-  scan_cells_body(bid, nbk, a.count, (long long)a.k.C, a.ts, a.cs);
+  scan_cells_body(bid, nbk, a.count, (long long)a.k.C, a.ts, a.cs, a.stay);
 }
 
 template <int P>
 __global__ __launch_bounds__(BLOCK) void kb_scatter(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                     int nbeds, int flip) {
   LBDPS_BED_PROLOGUE
-  scatter_body<typename Prec<P>::T>(bid, nbk, a.parts(cp), a.parts(1 - cp), a.rank, a.cs, a.k.npart, a.slot, a.ts);
+  scatter_body<typename Prec<P>::T>(bid, nbk, a.parts(cp), a.parts(1 - cp), a.rank, a.cs, a.k.npart, a.slot, a.ts, a.stay);
 }
 
 // After the scatter the records are in the other set.

@@ -284,6 +284,7 @@ struct TileSums {
 };
 
 constexpr int LUT_ROWS_MAX = 64;              // per-count table rows staged in LDS
+constexpr int RANK_MOVED = 1 << 30;           // rank flag: the particle arrived from another cell
 constexpr int SEG_REG = 4;                    // cell segments up to this length stay in registers
 constexpr int CONTACT_REG = 6;                // contacts per particle collected in registers first
 constexpr int CONTACT_CH = 8;                 // candidate positions loaded together
@@ -665,7 +666,7 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
                                                 Consts<typename Prec<P>::T> k, int32_t *__restrict__ count,
                                                 int32_t *__restrict__ rank, int32_t *flags,
                                                 typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy,
-                                                long long *zero_part, TileSums ts) {
+                                                long long *zero_part, TileSums ts, int32_t *__restrict__ stay) {
   using T = typename Prec<P>::T;
   __shared__ long long sh[BLOCK / 64];
   __shared__ int hist[HIST_MAX];
@@ -681,6 +682,7 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
   DragTile<P>::fetch(k, fl, tx0, ty0, tile_regs);
   // a tile without particles has nothing to do
   if (!__syncthreads_or(n > 0)) {
+    if (inside) stay[c] = 0;
     if (zero_part && threadIdx.x == 0) zero_part[bidx] = 0;
     return;
   }
@@ -703,6 +705,7 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
   if (threadIdx.x < HIST_MAX) hist[threadIdx.x] = 0;
   __syncthreads();
   long long nzero = 0;
+  int nstay = 0;
   if (inside) {
     if (n > 0) {
       const T fgx = fl.fpgx[c], fgy = fl.fpgy[c];
@@ -743,8 +746,12 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
         }
         return nk;
       };
+      // A particle that stays in its cell takes the next rank among the cell's
+      // stayers (in segment order); one that moves counts atomically among
+      // the arrivals of its new cell, which come after that cell's stayers.
       auto count_new = [&](int s, int nk) {
-        rank[s] = atomicAdd(&count[nk], 1);
+        if (nk == c) rank[s] = nstay++;
+        else rank[s] = atomicAdd(&count[nk], 1) | RANK_MOVED;
         const int dt = (nk >> ts.shift) - tlo;
         if (nh <= HIST_MAX && dt >= 0 && dt < nh)
           atomicAdd(&hist[dt], 1);
@@ -794,6 +801,7 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
         }
       }
     }
+    stay[c] = nstay;
   }
   __syncthreads();
   if ((int)threadIdx.x < min(nh, HIST_MAX)) {
@@ -812,8 +820,8 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
                                                 Consts<typename Prec<P>::T> k, int32_t *__restrict__ count,
                                                 int32_t *__restrict__ rank, int32_t *flags,
                                                 typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy,
-                                                long long *zero_part, TileSums ts) {
-  drag_body<P>(blockIdx.x, gridDim.x, pt, fl, cs, lut, k, count, rank, flags, dg_fdx, dg_fdy, zero_part, ts);
+                                                long long *zero_part, TileSums ts, int32_t *__restrict__ stay) {
+  drag_body<P>(blockIdx.x, gridDim.x, pt, fl, cs, lut, k, count, rank, flags, dg_fdx, dg_fdy, zero_part, ts, stay);
 }
 
 // ------------------------------------------------------------------ A1: binning (counting sort by cell, then particle index)
@@ -821,7 +829,7 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
 __global__ __launch_bounds__(BLOCK) void k_bin(const int32_t *__restrict__ key, int n, int32_t *__restrict__ count,
                                                int32_t *__restrict__ rank) {
   const int s = blockIdx.x * BLOCK + threadIdx.x;
-  if (s < n) rank[s] = atomicAdd(&count[key[s]], 1);
+  if (s < n) rank[s] = atomicAdd(&count[key[s]], 1) | RANK_MOVED;
 }
 
 // Move every particle record to its slot cell_start[key] + rank in the other
@@ -830,12 +838,13 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const int32_t *__restrict__ key, 
 template <class T>
 __device__ __forceinline__ void scatter_body(const int bidx, const int gdim, Parts<T> src, Parts<T> dst, const int32_t *__restrict__ rank,
                                                    const int32_t *__restrict__ cs, int n, int32_t *__restrict__ slot,
-                                                   TileSums ts) {
+                                                   TileSums ts, const int32_t *__restrict__ stay) {
   const int s = bidx * BLOCK + threadIdx.x;
   for (int i = s; i < ts.ntiles; i += gdim * BLOCK) ts.tile[i] = 0;
   if (s >= n) return;
   const int key = src.key[s];
-  const int d = cs[key] + rank[s];
+  const int r = rank[s];
+  const int d = cs[key] + ((r & RANK_MOVED) ? stay[key] + (r & ~RANK_MOVED) : r);
   const int id = src.pid[s];
   dst.key[d] = key;
   dst.pid[d] = id;
@@ -848,8 +857,8 @@ __device__ __forceinline__ void scatter_body(const int bidx, const int gdim, Par
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, const int32_t *__restrict__ rank,
                                                    const int32_t *__restrict__ cs, int n, int32_t *__restrict__ slot,
-                                                   TileSums ts) {
-  scatter_body<T>(blockIdx.x, gridDim.x, src, dst, rank, cs, n, slot, ts);
+                                                   TileSums ts, const int32_t *__restrict__ stay) {
+  scatter_body<T>(blockIdx.x, gridDim.x, src, dst, rank, cs, n, slot, ts, stay);
 }
 
 // ------------------------------------------------------------------ A6: contact detection
@@ -1613,7 +1622,7 @@ __global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt
 // each workgroup adds the sums of all tiles before its own (a strided sum),
 // scans its SCAN_TILE counts, writes cell_start and clears the counts.
 __device__ __forceinline__ void scan_cells_body(const int bidx, const int gdim, int32_t *__restrict__ count, long long n, TileSums ts,
-                                                      int32_t *__restrict__ out) {
+                                                      int32_t *__restrict__ out, const int32_t *__restrict__ stay) {
   __shared__ int sh[BLOCK / 64];
   const int b = bidx;
   int v = 0;
@@ -1626,7 +1635,7 @@ __device__ __forceinline__ void scan_cells_body(const int bidx, const int gdim, 
   int sum = 0;
 #pragma unroll
   for (int j = 0; j < SCAN_ITEMS; ++j) {
-    vals[j] = e0 + j < n ? count[e0 + j] : 0;
+    vals[j] = e0 + j < n ? count[e0 + j] + stay[e0 + j] : 0;
     sum += vals[j];
   }
   int total;
@@ -1641,8 +1650,8 @@ __device__ __forceinline__ void scan_cells_body(const int bidx, const int gdim, 
   if (b == gdim - 1 && threadIdx.x == 0) out[n] = base + total;
 }
 __global__ __launch_bounds__(BLOCK) void k_scan_cells(int32_t *__restrict__ count, long long n, TileSums ts,
-                                                      int32_t *__restrict__ out) {
-  scan_cells_body(blockIdx.x, gridDim.x, count, n, ts, out);
+                                                      int32_t *__restrict__ out, const int32_t *__restrict__ stay) {
+  scan_cells_body(blockIdx.x, gridDim.x, count, n, ts, out, stay);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int32_t *__restrict__ in, long long n,

@@ -167,7 +167,7 @@ struct lbdps_ctx {
   // device buffers (carved from the workspace)
   void *f[2]{};
   void *fld[7]{};  // rho, ugx, ugy, beta, fpgx, fpgy, es
-  int32_t *count = nullptr, *cs = nullptr, *spart = nullptr;
+  int32_t *count = nullptr, *stay = nullptr, *cs = nullptr, *spart = nullptr;
   int32_t *key[2]{}, *pid[2]{};
   void *px[2]{}, *py[2]{}, *vx[2]{}, *vy[2]{};
   int32_t *rank = nullptr, *perm = nullptr, *slot = nullptr, *deg = nullptr, *done = nullptr;
@@ -216,7 +216,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   char *f0 = raw(Q * C * sS), *f1 = raw(Q * C * sS);
   char *fl[7];
   for (auto &q : fl) q = raw(C * sT);
-  int32_t *count = cv.take<int32_t>(C), *cs = cv.take<int32_t>(C + 1), *spart = cv.take<int32_t>(tiles);
+  int32_t *count = cv.take<int32_t>(C), *stay = cv.take<int32_t>(C), *cs = cv.take<int32_t>(C + 1), *spart = cv.take<int32_t>(tiles);
   int32_t *key[2], *pid[2];
   char *px[2], *py[2], *vx[2], *vy[2];
   for (int b = 0; b < 2; ++b) {
@@ -260,6 +260,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->f[1] = f1;
     for (int i = 0; i < 7; ++i) x->fld[i] = fl[i];
     x->count = count;
+    x->stay = stay;
     x->cs = cs;
     x->spart = spart;
     for (int b = 0; b < 2; ++b) {
@@ -398,20 +399,22 @@ template <int P> struct Impl {
     tstart(x, LBDPS_K_SCAN);
     if (tile_sums)
       hipLaunchKernelGGL(k_scan_cells, dim3(x->ntiles), dim3(BLOCK), 0, x->stream, x->count, (long long)x->C,
-                         tiles(x), x->cs);
+                         tiles(x), x->cs, x->stay);
     else
       scan(x, x->count, x->C, x->cs, 1);
     tstop(x, LBDPS_K_SCAN);
     const int N = (int)x->n;
     tstart(x, LBDPS_K_SCATTER);
     hipLaunchKernelGGL(k_scatter<T>, dim3(std::max(nblocks(N), 1)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
-                       parts(x, 1 - x->cp), x->rank, x->cs, N, x->slot, tiles(x));
+                       parts(x, 1 - x->cp), x->rank, x->cs, N, x->slot, tiles(x), x->stay);
     tstop(x, LBDPS_K_SCATTER);
     x->cp = 1 - x->cp;
   }
 
   static void rebin(lbdps_ctx *x) {
     const int N = (int)x->n;
+    // every particle counts as an arrival: no cell has stayers
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, x->stay, (long long)x->C, 0);
     if (N > 0)
       hipLaunchKernelGGL(k_bin, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->key[x->cp], N, x->count, x->rank);
     sort_counted(x, false);
@@ -451,7 +454,7 @@ template <int P> struct Impl {
         tstart(x, LBDPS_K_DRAG);
         hipLaunchKernelGGL(k_drag<P>, dim3(drag_tiles(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x),
                            x->cs, (const T *)x->lut, k, x->count, x->rank, x->flags, dg ? (T *)x->dg_fdx : nullptr,
-                           dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x));
+                           dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x), x->stay);
         tstop(x, LBDPS_K_DRAG);
         sort_counted(x);
         hard_spheres(x);
@@ -972,6 +975,7 @@ template <int P> struct BatchImpl {
     a.inlet = (const T *)x->inlet;
     a.cs = x->cs;
     a.count = x->count;
+    a.stay = x->stay;
     a.rank = x->rank;
     a.slot = x->slot;
     a.flags = x->flags;
