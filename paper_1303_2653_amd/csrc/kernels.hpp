@@ -1222,82 +1222,112 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typen
   }
 }
 
-// A cluster of more than CL_LDS members is resolved by the whole workgroup with
+// A cluster of more than CL_LDS members is resolved by a group of threads with
 // everything in LDS: breadth-first gathering with an open-addressing set of
 // member slots, a bitonic sort by index, the lexicographic pair list built
-// with a workgroup scan, the pairs applied in order by one thread on the
-// members' LDS copies, then the wall pass of every member in parallel.  Beyond
-// BIG_MAX members or BIG_PAIRS pairs the cluster is left to the ordered sweep.
-constexpr int BIG_MAX = 256;                 // members (== BLOCK: one thread per member)
-constexpr int BIG_PAIRS = 1024;              // pairs
-constexpr int BIG_HASH = 512;                // set of member slots (power of two)
-constexpr int BIG_LIST = 64;                 // clusters queued per workgroup for this phase
+// with a group scan, the pairs applied in order by one thread on the members'
+// LDS copies, then the wall pass of every member in parallel.  A group is one
+// wavefront (clusters of up to 64 members and 256 pairs; the four wavefronts of
+// a workgroup take queued clusters in parallel) or the whole workgroup (up to
+// 256 members and 1024 pairs, for clusters a wavefront could not hold).  A
+// cluster beyond that is left to the ordered sweep.
+constexpr int BIG_LIST = 64;  // clusters queued per workgroup for the group paths
+constexpr int WAVE = 64;
 
-static_assert(BIG_MAX == BLOCK, "one thread per member of a whole-workgroup cluster");
-
-template <int P> struct BigCluster {
-  using T = typename Prec<P>::T;
-  long long q[BIG_MAX];
-  int hslot[BIG_HASH];
-  short hidx[BIG_HASH];
-  int key[BIG_MAX];
-  T px[BIG_MAX], py[BIG_MAX], vx[BIG_MAX], vy[BIG_MAX];
-  unsigned pairs[BIG_PAIRS];
-  int m, notroot, over;
+template <int G> struct Group {  // G = BLOCK: the workgroup; G = WAVE: one wavefront
+  static_assert(G == BLOCK || G == WAVE, "group size");
+  __device__ static int rank() { return G == BLOCK ? (int)threadIdx.x : (int)(threadIdx.x & (WAVE - 1)); }
+  __device__ static void sync() {
+    if constexpr (G == BLOCK) {
+      __syncthreads();
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  // Exclusive scan of one int per thread over the group, and the group total.
+  __device__ static int excl_scan(int v, int *shi, int &total) {
+    if constexpr (G == BLOCK) {
+      return block_excl_scan(v, shi, total);
+    } else {
+      const int lane = rank();
+      int inc = v;
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const int u = __shfl_up(inc, o, WAVE);
+        if (lane >= o) inc += u;
+      }
+      total = __shfl(inc, WAVE - 1, WAVE);
+      return inc - v;
+    }
+  }
 };
 
-__device__ __forceinline__ int big_hash(int slot) { return (int)(((unsigned)slot * 2654435761u) >> 23) & (BIG_HASH - 1); }
-
-// Insert slot into the set; returns 1 if it was new, 0 if present, -1 if full.
-template <int P> __device__ __forceinline__ int big_insert(BigCluster<P> &B, int slot) {
-  int h = big_hash(slot);
-  for (int probe = 0; probe < BIG_HASH; ++probe) {
-    const int old = atomicCAS(&B.hslot[h], -1, slot);
-    if (old == -1) return 1;
-    if (old == slot) return 0;
-    h = (h + 1) & (BIG_HASH - 1);
-  }
-  return -1;
-}
-
-template <int P> __device__ __forceinline__ int big_find(const BigCluster<P> &B, int slot) {
-  int h = big_hash(slot);
-  for (int probe = 0; probe < BIG_HASH; ++probe) {
-    const int v = B.hslot[h];
-    if (v == slot) return h;
-    if (v == -1) return -1;
-    h = (h + 1) & (BIG_HASH - 1);
-  }
-  return -1;
-}
-
-// Whole-workgroup resolution of the cluster of candidate slot s0 (index g);
-// every thread of the workgroup calls it.
-template <int P>
-__device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Consts<typename Prec<P>::T> &k,
-                            Parts<typename Prec<P>::T> &pt, Adj adj,
-                            const int32_t *__restrict__ deg, int32_t *done, int32_t *need_sweep, long long &ncoll,
-                            long long &nwall) {
+template <int P, int G> struct ClusterLds {
   using T = typename Prec<P>::T;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < BIG_HASH; i += BLOCK) B.hslot[i] = -1;
+  static constexpr int MAX = G, HASH = 2 * G, PAIRS = 4 * G;
+  long long q[MAX];
+  int hslot[HASH];
+  short hidx[HASH];
+  int key[MAX];
+  T px[MAX], py[MAX], vx[MAX], vy[MAX];
+  unsigned pairs[PAIRS];
+  int m, notroot, over;
+
+  __device__ static int hash(int slot) { return (int)(((unsigned)slot * 2654435761u) >> 20) & (HASH - 1); }
+  // Insert slot into the set; returns 1 if it was new, 0 if present, -1 if full.
+  __device__ int insert(int slot) {
+    int h = hash(slot);
+    for (int probe = 0; probe < HASH; ++probe) {
+      const int old = atomicCAS(&hslot[h], -1, slot);
+      if (old == -1) return 1;
+      if (old == slot) return 0;
+      h = (h + 1) & (HASH - 1);
+    }
+    return -1;
+  }
+  __device__ int find(int slot) const {
+    int h = hash(slot);
+    for (int probe = 0; probe < HASH; ++probe) {
+      const int v = hslot[h];
+      if (v == slot) return h;
+      if (v == -1) return -1;
+      h = (h + 1) & (HASH - 1);
+    }
+    return -1;
+  }
+};
+
+// Resolution of the cluster of candidate slot s0 (index g) by group G; every
+// thread of the group calls it.  Returns 0 when resolved, 1 when a member has
+// a lower index than g (another candidate owns the cluster), 2 when the cluster
+// exceeds the group's capacity (nothing was changed).
+template <int P, int G>
+__device__ int resolve_group(ClusterLds<P, G> &B, int *shi, int s0, int g, const Consts<typename Prec<P>::T> &k,
+                             Parts<typename Prec<P>::T> &pt, Adj adj, const int32_t *__restrict__ deg, int32_t *done,
+                             long long &ncoll, long long &nwall) {
+  using T = typename Prec<P>::T;
+  using Gr = Group<G>;
+  constexpr int MAX = ClusterLds<P, G>::MAX;
+  const int tid = Gr::rank();
+  for (int i = tid; i < ClusterLds<P, G>::HASH; i += G) B.hslot[i] = -1;
   if (tid == 0) {
     B.q[0] = ((long long)g << 32) | (unsigned)s0;
     B.m = 1;
     B.notroot = 0;
     B.over = 0;
   }
-  __syncthreads();
-  if (tid == 0) big_insert<P>(B, s0);
-  __syncthreads();
+  Gr::sync();
+  if (tid == 0) B.insert(s0);
+  Gr::sync();
   // level-synchronous breadth-first gathering
   int h0 = 0;
   for (;;) {
-    const int h1 = min(B.m, BIG_MAX);
+    const int h1 = min(B.m, MAX);
     const bool stop = h0 >= h1 || B.notroot || B.over;
-    __syncthreads();
+    Gr::sync();
     if (stop) break;
-    for (int t = h0 + tid; t < h1; t += BLOCK) {
+    for (int t = h0 + tid; t < h1; t += G) {
       const int u = (int)(B.q[t] & 0xffffffffll);
       const AdjRow ru = adj.row(u);
       const int du = min(deg[u], KMAX);
@@ -1307,31 +1337,28 @@ __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Con
           B.notroot = 1;  // a lower index: the cluster belongs to another candidate
           break;
         }
-        const int r = big_insert<P>(B, (int)(e & 0xffffffffll));
+        const int r = B.insert((int)(e & 0xffffffffll));
         if (r < 0) {
           B.over = 1;
           break;
         }
         if (r == 1) {
           const int pos = atomicAdd(&B.m, 1);
-          if (pos < BIG_MAX) B.q[pos] = e;
+          if (pos < MAX) B.q[pos] = e;
           else B.over = 1;
         }
       }
     }
-    __syncthreads();
+    Gr::sync();
     h0 = h1;
   }
-  if (B.notroot) return;  // uniform: read after the loop's last barrier
-  if (B.over) {
-    if (tid == 0) atomicOr(need_sweep, 1);
-    return;
-  }
+  if (B.notroot) return 1;  // uniform: read after the loop's last barrier
+  if (B.over) return 2;
   const int m = B.m;
-  // bitonic sort of q[0 .. BIG_MAX) by (index, slot), padded past m
+  // bitonic sort of q[0 .. MAX) by (index, slot), padded past m
   if (tid >= m) B.q[tid] = 0x7fffffffffffffffll;
-  __syncthreads();
-  for (int len = 2; len <= BIG_MAX; len <<= 1)
+  Gr::sync();
+  for (int len = 2; len <= MAX; len <<= 1)
     for (int st = len >> 1; st > 0; st >>= 1) {
       const int j = tid ^ st;
       if (j > tid) {
@@ -1342,7 +1369,7 @@ __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Con
           B.q[j] = a;
         }
       }
-      __syncthreads();
+      Gr::sync();
     }
   // member copies, slot -> sorted index, pairs (i, j), i < j, per member
   const bool mem = tid < m;
@@ -1350,7 +1377,7 @@ __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Con
   const int gu = mem ? (int)(B.q[tid] >> 32) : 0;
   int cnt = 0;
   if (mem) {
-    B.hidx[big_find<P>(B, u)] = (short)tid;
+    B.hidx[B.find(u)] = (short)tid;
     B.key[tid] = pt.key[u];
     B.px[tid] = pt.px[u];
     B.py[tid] = pt.py[u];
@@ -1361,21 +1388,19 @@ __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Con
     for (int a = 0; a < du; ++a) cnt += (int)(ru[a] >> 32) > gu;
   }
   int npairs;
-  const int off = block_excl_scan(cnt, shi, npairs);
-  if (npairs > BIG_PAIRS) {
-    if (tid == 0) atomicOr(need_sweep, 1);
-    return;
-  }
+  const int off = Gr::excl_scan(cnt, shi, npairs);
+  if (npairs > ClusterLds<P, G>::PAIRS) return 2;
+  Gr::sync();  // every member's slot -> index entry is written
   if (mem) {
     const AdjRow ru = adj.row(u);
     const int du = min(deg[u], KMAX);
     int w = off;
     for (int a = 0; a < du; ++a) {
       const long long e = ru[a];
-      if ((int)(e >> 32) > gu) B.pairs[w++] = ((unsigned)tid << 16) | (unsigned)B.hidx[big_find<P>(B, (int)(e & 0xffffffffll))];
+      if ((int)(e >> 32) > gu) B.pairs[w++] = ((unsigned)tid << 16) | (unsigned)B.hidx[B.find((int)(e & 0xffffffffll))];
     }
   }
-  __syncthreads();
+  Gr::sync();
   if (tid == 0) {  // the pairs in lexicographic order, on the LDS copies
     for (int q = 0; q < npairs; ++q) {
       const int i = (int)(B.pairs[q] >> 16), j = (int)(B.pairs[q] & 0xffffu);
@@ -1391,7 +1416,7 @@ __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Con
       }
     }
   }
-  __syncthreads();
+  Gr::sync();
   if (mem) {
     T vx = B.vx[tid], vy = B.vy[tid];
     const int key = B.key[tid];
@@ -1400,7 +1425,8 @@ __device__ void resolve_big(BigCluster<P> &B, int *shi, int s0, int g, const Con
     pt.vy[u] = vy;
     done[u] = deg[u];
   }
-  __syncthreads();
+  Gr::sync();
+  return 0;
 }
 
 template <int P>
@@ -1414,15 +1440,19 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
   __shared__ long long sh[BLOCK / 64];
   __shared__ int shi[BLOCK / 64];
   __shared__ int pre[BLOCK + 1];
-  __shared__ long long bigc[BIG_LIST];
-  __shared__ int nbig;
-  // the per-lane gathering area, reused afterwards for the whole-workgroup clusters
+  __shared__ long long bigc[BIG_LIST], hugec[BIG_LIST];
+  __shared__ int nbig, nhuge;
+  // the per-lane gathering area, reused afterwards for the group paths
   __shared__ union {
     long long qs[CL_LDS * BLOCK];
-    BigCluster<P> big;
+    ClusterLds<P, WAVE> wave[BLOCK / WAVE];
+    ClusterLds<P, BLOCK> big;
   } U;
   long long *const qs = U.qs;
-  if (threadIdx.x == 0) nbig = 0;
+  if (threadIdx.x == 0) {
+    nbig = 0;
+    nhuge = 0;
+  }
   // candidate lists [b0, b0 + nb) of the contact kernel's workgroups
   const int per = (nlists + gdim - 1) / gdim;  // <= BLOCK (host grid choice)
   const int b0 = bidx * per;
@@ -1454,11 +1484,21 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
     }
   }
   __syncthreads();
-  const int nb_big = min(nbig, BIG_LIST);
-  for (int c = 0; c < nb_big; ++c) {
+  // queued clusters: one wavefront each, then the whole workgroup for those too large
+  const int nb_big = min(nbig, BIG_LIST), wv = (int)threadIdx.x / WAVE;
+  for (int c = wv; c < nb_big; c += BLOCK / WAVE) {
     const long long r = bigc[c];
-    resolve_big<P>(U.big, shi, (int)(r & 0xffffffffll), (int)(r >> 32), k, pt, adj, deg, done, need_sweep, ncoll,
-                   nwall);
+    const int st = resolve_group<P, WAVE>(U.wave[wv], shi, (int)(r & 0xffffffffll), (int)(r >> 32), k, pt, adj, deg,
+                                          done, ncoll, nwall);
+    if (st == 2 && Group<WAVE>::rank() == 0) hugec[atomicAdd(&nhuge, 1)] = r;
+  }
+  __syncthreads();
+  const int nb_huge = nhuge;
+  for (int c = 0; c < nb_huge; ++c) {
+    const long long r = hugec[c];
+    const int st = resolve_group<P, BLOCK>(U.big, shi, (int)(r & 0xffffffffll), (int)(r >> 32), k, pt, adj, deg, done,
+                                           ncoll, nwall);
+    if (st == 2 && threadIdx.x == 0) atomicOr(need_sweep, 1);
   }
   const long long tc = block_sum_ll(ncoll, sh);
   const long long tw = block_sum_ll(nwall, sh);
