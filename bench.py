@@ -208,6 +208,25 @@ def cpu_baseline(cfg, seconds):
                        f"({dt:.1f} s); particle updates/s {len(cfg['pos']) * steps / dt:.3e}")
 
 
+def copy_bandwidth(torch, nbytes: int, reps: int = 5) -> dict:
+    """A plain device-to-device copy of nbytes: read + write bytes over the mean
+    time of reps copies (the measured HBM ceiling beside the published peak)."""
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"copy_probe_bytes": n * 4, "launches": reps + 1, "ms_per_copy": round(ms, 4),
+            "GBs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
+
+
 def time_region(torch, stream, fn):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -352,13 +371,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_probe:
-        n = args.copy_probe // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}), flush=True)
+        print(json.dumps(copy_bandwidth(torch, args.copy_probe)), flush=True)
         return
     from paper_1303_2653_amd import lbdps as L
 
@@ -402,6 +415,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3)},
     }
+    cb = copy_bandwidth(torch, 1 << 30)
+    line["roofline"]["copy_GBs"] = cb["GBs"]
+    line["roofline"]["frac_of_copy"] = round(achieved / cb["GBs"], 4)
     if not args.no_variants and args.precision == "fp32":
         var = {}
         for p in ("fp16", "bf16"):
