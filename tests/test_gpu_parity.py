@@ -381,3 +381,19 @@ def test_launch_shapes_do_not_change_results(prec):
                 assert (a == b).all(), (lists, gmax)
     chosen = L.Sim(cfg, precision=prec).autotune(2)
     assert chosen["cluster_lists"] >= 1 and chosen["cluster_groups_max"] >= 1
+
+
+def test_fp64_large_lattice():
+    """A lattice of more than 512 cell-scan tiles (1100 x 1024 cells), where
+    the tiles' bases are scanned in a pass of their own: two FP64 steps within
+    1e-12 of the oracle, pair lists identical."""
+    cfg = synth.riser(nx=1100, ny=1024, n=40_000, seed=8, sort_ids=True, precision="fp64")
+    cfg["vel"] = (np.random.default_rng(5).random(cfg["pos"].shape) - 0.5) * 1e-2
+    gpu = L.Sim(cfg, precision="fp64", diagnostics=True)
+    ref = oracle.Sim(cfg)
+    for k in (1, 2):
+        gpu.step(1)
+        o = ref.step(record=True)
+        compare_step(gpu, o, ref, 1e-12, what=f"large lattice step {k}")
+    pairs, m = gpu.pairs()
+    assert m == len(o.pairs) and (pairs == o.pairs).all()
