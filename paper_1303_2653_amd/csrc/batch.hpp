@@ -84,7 +84,8 @@ template <int P>
 __global__ __launch_bounds__(BLOCK) void kb_scatter(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                     int nbeds, int flip) {
   LBDPS_BED_PROLOGUE
-  scatter_body<typename Prec<P>::T>(bid, nbk, a.parts(cp), a.parts(1 - cp), a.rank, a.cs, a.k.npart, a.slot, a.ts, a.stay);
+  scatter_body<typename Prec<P>::T>(bid, nbk, a.parts(cp), a.parts(1 - cp), a.rank, a.cs, a.k.npart, a.slot, a.ts,
+                                    a.stay);
 }
 
 // After the scatter the records are in the other set.

@@ -333,14 +333,11 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long *sh) {
 // neighbours with the boundary rules (bounce-back, equilibrium inlet,
 // zero-gradient outlet).
 template <int P>
-__device__ __forceinline__ void collide_body(const int bidx, const int gdim, const typename Prec<P>::S *__restrict__ fsrc,
-                                                   typename Prec<P>::S *__restrict__ fdst,
-                                                   Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs,
-                                                   Parts<typename Prec<P>::T> pt,
-                                                   const typename Prec<P>::T *__restrict__ lut,
-                                                   const typename Prec<P>::T *__restrict__ inlet,
-                                                   Consts<typename Prec<P>::T> k, int32_t *dg_n,
-                                                   typename Prec<P>::T *dg_vsx, typename Prec<P>::T *dg_vsy) {
+__device__ __forceinline__ void collide_body(const int bidx, const int gdim,
+    const typename Prec<P>::S *__restrict__ fsrc, typename Prec<P>::S *__restrict__ fdst,
+    Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs, Parts<typename Prec<P>::T> pt,
+    const typename Prec<P>::T *__restrict__ lut, const typename Prec<P>::T *__restrict__ inlet,
+    Consts<typename Prec<P>::T> k, int32_t *dg_n, typename Prec<P>::T *dg_vsx, typename Prec<P>::T *dg_vsy) {
   using T = typename Prec<P>::T;
   __shared__ T sl[LUT_ROWS_MAX * LUT_W];  // the per-count table
   const int c = bidx * BLOCK + threadIdx.x;
@@ -660,13 +657,11 @@ template <int P> struct Interp {
 
 // Workgroup = one DTX x DTY tile of cells, one thread per cell.
 template <int P>
-__device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
-                                                const int32_t *__restrict__ cs,
-                                                const typename Prec<P>::T *__restrict__ lut,
-                                                Consts<typename Prec<P>::T> k, int32_t *__restrict__ count,
-                                                int32_t *__restrict__ rank, int32_t *flags,
-                                                typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy,
-                                                long long *zero_part, TileSums ts, int32_t *__restrict__ stay) {
+__device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
+    Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs, const typename Prec<P>::T *__restrict__ lut,
+    Consts<typename Prec<P>::T> k, int32_t *__restrict__ count, int32_t *__restrict__ rank, int32_t *flags,
+    typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy, long long *zero_part, TileSums ts,
+    int32_t *__restrict__ stay) {
   using T = typename Prec<P>::T;
   __shared__ long long sh[BLOCK / 64];
   __shared__ int hist[HIST_MAX];
@@ -824,7 +819,7 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
   drag_body<P>(blockIdx.x, gridDim.x, pt, fl, cs, lut, k, count, rank, flags, dg_fdx, dg_fdy, zero_part, ts, stay);
 }
 
-// ------------------------------------------------------------------ A1: binning (counting sort by cell, then particle index)
+// ------------------------------------------------------------------ A1: binning (counting sort by cell)
 // Count particles per cell (slot within the cell from the atomic counter).
 __global__ __launch_bounds__(BLOCK) void k_bin(const int32_t *__restrict__ key, int n, int32_t *__restrict__ count,
                                                int32_t *__restrict__ rank) {
@@ -836,9 +831,9 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const int32_t *__restrict__ key, 
 // storage and record the slot of each particle index.  Clears the tile sums
 // for the next binning.
 template <class T>
-__device__ __forceinline__ void scatter_body(const int bidx, const int gdim, Parts<T> src, Parts<T> dst, const int32_t *__restrict__ rank,
-                                                   const int32_t *__restrict__ cs, int n, int32_t *__restrict__ slot,
-                                                   TileSums ts, const int32_t *__restrict__ stay) {
+__device__ __forceinline__ void scatter_body(const int bidx, const int gdim, Parts<T> src, Parts<T> dst,
+    const int32_t *__restrict__ rank, const int32_t *__restrict__ cs, int n, int32_t *__restrict__ slot, TileSums ts,
+    const int32_t *__restrict__ stay) {
   const int s = bidx * BLOCK + threadIdx.x;
   for (int i = s; i < ts.ntiles; i += gdim * BLOCK) ts.tile[i] = 0;
   if (s >= n) return;
@@ -871,13 +866,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, c
 // without contacts gets its wall collision here; the others get it after their
 // binary collisions.
 template <int P>
-__device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
-                                                    Consts<typename Prec<P>::T> k, Adj adj,
-                                                    int32_t *__restrict__ deg, int32_t *__restrict__ done,
-                                                    int32_t *ticket, int32_t *flags, long long *pair_part,
-                                                    long long *wall_part, int32_t *__restrict__ chunk_busy,
-                                                    int32_t *need_sweep, long long *__restrict__ roots,
-                                                    int32_t *__restrict__ rcount) {
+__device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
+    const int32_t *__restrict__ cs, Consts<typename Prec<P>::T> k, Adj adj, int32_t *__restrict__ deg,
+    int32_t *__restrict__ done, int32_t *ticket, int32_t *flags, long long *pair_part, long long *wall_part,
+    int32_t *__restrict__ chunk_busy, int32_t *need_sweep, long long *__restrict__ roots,
+    int32_t *__restrict__ rcount) {
   using T = typename Prec<P>::T;
   __shared__ long long sh[BLOCK / 64];
   __shared__ int shi[BLOCK / 64];
@@ -1055,7 +1048,8 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
                                                     long long *wall_part, int32_t *__restrict__ chunk_busy,
                                                     int32_t *need_sweep, long long *__restrict__ roots,
                                                     int32_t *__restrict__ rcount) {
-  contacts_body<P>(blockIdx.x, gridDim.x, pt, cs, k, adj, deg, done, ticket, flags, pair_part, wall_part, chunk_busy, need_sweep, roots, rcount);
+  contacts_body<P>(blockIdx.x, gridDim.x, pt, cs, k, adj, deg, done, ticket, flags, pair_part, wall_part, chunk_busy,
+      need_sweep, roots, rcount);
 }
 
 // ------------------------------------------------------------------ A7: collision resolution (Eqs. 17-18) and walls
@@ -1431,12 +1425,9 @@ __device__ int resolve_group(ClusterLds<P, G> &B, int *shi, int s0, int g, const
 
 template <int P>
 __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
-                                                            Adj adj,
-                                                            const int32_t *__restrict__ deg, int32_t *done,
-                                                            Consts<typename Prec<P>::T> k, int32_t *need_sweep,
-                                                            long long *coll_part, long long *wall_part,
-                                                            const long long *__restrict__ roots,
-                                                            const int32_t *__restrict__ rcount, int nlists) {
+    Adj adj, const int32_t *__restrict__ deg, int32_t *done, Consts<typename Prec<P>::T> k, int32_t *need_sweep,
+    long long *coll_part, long long *wall_part, const long long *__restrict__ roots,
+    const int32_t *__restrict__ rcount, int nlists) {
   __shared__ long long sh[BLOCK / 64];
   __shared__ int shi[BLOCK / 64];
   __shared__ int pre[BLOCK + 1];
@@ -1515,7 +1506,8 @@ __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<
                                                             long long *coll_part, long long *wall_part,
                                                             const long long *__restrict__ roots,
                                                             const int32_t *__restrict__ rcount, int nlists) {
-  resolve_clusters_body<P>(blockIdx.x, gridDim.x, pt, adj, deg, done, k, need_sweep, coll_part, wall_part, roots, rcount, nlists);
+  resolve_clusters_body<P>(blockIdx.x, gridDim.x, pt, adj, deg, done, k, need_sweep, coll_part, wall_part, roots,
+      rcount, nlists);
 }
 
 // Position of particle index g in the neighbour list of slot t: the number of
@@ -1530,11 +1522,10 @@ __device__ __forceinline__ int row_position(Adj adj, const int32_t *deg, int t, 
 
 
 template <int P>
-__device__ __forceinline__ void resolve_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
-                                                   Adj adj, const int32_t *__restrict__ deg,
-                                                   int32_t *done, int32_t *ticket, Consts<typename Prec<P>::T> k,
-                                                   int32_t *flags, long long *coll_part, long long *wall_part,
-                                                   int32_t *__restrict__ chunk_busy, const int32_t *need_sweep) {
+__device__ __forceinline__ void resolve_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
+    const int32_t *__restrict__ slot, Adj adj, const int32_t *__restrict__ deg, int32_t *done, int32_t *ticket,
+    Consts<typename Prec<P>::T> k, int32_t *flags, long long *coll_part, long long *wall_part,
+    int32_t *__restrict__ chunk_busy, const int32_t *need_sweep) {
   using T = typename Prec<P>::T;
   __shared__ int s_ticket;
   __shared__ long long sh[BLOCK / 64];
@@ -1652,7 +1643,8 @@ __global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt
                                                    int32_t *done, int32_t *ticket, Consts<typename Prec<P>::T> k,
                                                    int32_t *flags, long long *coll_part, long long *wall_part,
                                                    int32_t *__restrict__ chunk_busy, const int32_t *need_sweep) {
-  resolve_body<P>(blockIdx.x, gridDim.x, pt, slot, adj, deg, done, ticket, k, flags, coll_part, wall_part, chunk_busy, need_sweep);
+  resolve_body<P>(blockIdx.x, gridDim.x, pt, slot, adj, deg, done, ticket, k, flags, coll_part, wall_part, chunk_busy,
+      need_sweep);
 }
 
 // ------------------------------------------------------------------ exclusive scan of int32
@@ -1661,8 +1653,8 @@ __global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt
 // Cell starts in one pass: the tile sums were accumulated while counting, so
 // each workgroup adds the sums of all tiles before its own (a strided sum),
 // scans its SCAN_TILE counts, writes cell_start and clears the counts.
-__device__ __forceinline__ void scan_cells_body(const int bidx, const int gdim, int32_t *__restrict__ count, long long n, TileSums ts,
-                                                      int32_t *__restrict__ out, const int32_t *__restrict__ stay) {
+__device__ __forceinline__ void scan_cells_body(const int bidx, const int gdim, int32_t *__restrict__ count,
+    long long n, TileSums ts, int32_t *__restrict__ out, const int32_t *__restrict__ stay) {
   __shared__ int sh[BLOCK / 64];
   const int b = bidx;
   int v = 0;

@@ -216,7 +216,8 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   char *f0 = raw(Q * C * sS), *f1 = raw(Q * C * sS);
   char *fl[7];
   for (auto &q : fl) q = raw(C * sT);
-  int32_t *count = cv.take<int32_t>(C), *stay = cv.take<int32_t>(C), *cs = cv.take<int32_t>(C + 1), *spart = cv.take<int32_t>(tiles);
+  int32_t *count = cv.take<int32_t>(C), *stay = cv.take<int32_t>(C), *cs = cv.take<int32_t>(C + 1);
+  int32_t *spart = cv.take<int32_t>(tiles);
   int32_t *key[2], *pid[2];
   char *px[2], *py[2], *vx[2], *vy[2];
   for (int b = 0; b < 2; ++b) {
@@ -434,7 +435,8 @@ template <int P> struct Impl {
     hipLaunchKernelGGL(k_resolve_clusters<P>, dim3(x->cluster_groups()), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
                        x->adj(), x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part,
                        x->roots, x->rcount, nblocks(N));
-    hipLaunchKernelGGL(k_resolve<P>, dim3(resolve_blocks(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot, x->adj(),
+    hipLaunchKernelGGL(k_resolve<P>, dim3(resolve_blocks(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot,
+                       x->adj(),
                        x->deg, x->done, x->ticket, k, x->flags, x->coll_part, x->wall_part, x->chunk_busy,
                        x->need_sweep);
     tstop(x, LBDPS_K_RESOLVE);
@@ -447,7 +449,8 @@ template <int P> struct Impl {
       if (!x->bins_valid) rebin(x);
       tstart(x, LBDPS_K_COLLIDE);
       hipLaunchKernelGGL(k_collide<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, (const S *)x->f[x->cf],
-                         (S *)x->f[1 - x->cf], fields(x), x->cs, parts(x, x->cp), (const T *)x->lut, (const T *)x->inlet, k, dg ? x->dg_n : nullptr,
+                         (S *)x->f[1 - x->cf], fields(x), x->cs, parts(x, x->cp), (const T *)x->lut,
+                         (const T *)x->inlet, k, dg ? x->dg_n : nullptr,
                          dg ? (T *)x->dg_vsx : nullptr, dg ? (T *)x->dg_vsy : nullptr);
       tstop(x, LBDPS_K_COLLIDE);
       if (x->n > 0) {
@@ -543,7 +546,8 @@ lbdps_status sync_and_check(lbdps_ctx *x, const char *what) {
   const int32_t zero[FLAG_COUNT] = {0};
   check_hip(hipMemcpy(x->flags, zero, sizeof(zero), hipMemcpyHostToDevice), what);
   const int32_t *had = fl;
-  if (had[FLAG_DOMAIN]) return fail(LBDPS_E_INVALID, std::string(what) + ": a particle left the domain or was placed outside it");
+  if (had[FLAG_DOMAIN])
+    return fail(LBDPS_E_INVALID, std::string(what) + ": a particle left the domain or was placed outside it");
   if (had[FLAG_CAPACITY])
     return fail(LBDPS_E_CAPACITY, std::string(what) + ": a particle had more than LBDPS_MAX_CONTACTS contacts");
   if (had[FLAG_STALL]) return fail(LBDPS_E_STALL, std::string(what) + ": collision resolution exceeded its wait bound");
@@ -827,7 +831,8 @@ lbdps_status lbdps_kernel_times(lbdps_ctx *x, double *h_ms, int64_t *h_launches)
 
 lbdps_status lbdps_set_tuning(lbdps_ctx *x, const lbdps_tuning *t) {
   if (!x || !t) return fail(LBDPS_E_INVALID, "ctx or tuning is NULL");
-  if (t->cluster_lists < 1 || t->cluster_lists > BLOCK) return fail(LBDPS_E_INVALID, "cluster_lists must be in [1, 256]");
+  if (t->cluster_lists < 1 || t->cluster_lists > BLOCK)
+    return fail(LBDPS_E_INVALID, "cluster_lists must be in [1, 256]");
   if (t->cluster_groups_max < 1) return fail(LBDPS_E_INVALID, "cluster_groups_max must be >= 1");
   if (t->drag_tile != 0) return fail(LBDPS_E_UNSUPPORTED, "drag_tile: only 0 (32x8) is built");
   x->tune = *t;
@@ -1225,7 +1230,8 @@ lbdps_status lbdps_batch_create(const lbdps_params *beds, int32_t nbeds, const i
   B->d_tab[0] = (char *)d_workspace;
   B->d_tab[1] = (char *)d_workspace + tab;
   st = check_hip(hipHostMalloc((void **)&B->h_tab, tab, hipHostMallocDefault), "lbdps_batch_create");
-  if (st == LBDPS_OK) st = check_hip(hipEventCreateWithFlags(&B->tab_done, hipEventDisableTiming), "lbdps_batch_create");
+  if (st == LBDPS_OK)
+    st = check_hip(hipEventCreateWithFlags(&B->tab_done, hipEventDisableTiming), "lbdps_batch_create");
   for (int b = 0; st == LBDPS_OK && b < nbeds; ++b) {
     lbdps_ctx *x = nullptr;
     st = lbdps_create(&beds[b], max_particles[b], (char *)d_workspace + bed_off[b], total - bed_off[b],
