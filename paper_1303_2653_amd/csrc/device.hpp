@@ -115,6 +115,8 @@ template <int P> __device__ __forceinline__ void from_f64(typename Prec<P>::S *f
 // Scalar constants of a context, in the arithmetic type.
 template <class T> struct Consts {
   int nx, ny, C, nlut;
+  unsigned long long nx_m;  // key / nx = (key * nx_m) >> nx_s for 0 <= key < 2^31
+  int nx_s;
   int per_x, per_y, bc_ylo, bc_yhi;
   int drag_abs;
   int npart;
@@ -122,6 +124,35 @@ template <class T> struct Consts {
   T geff[2], fp, halfG[2], src[Q];
   unsigned spin_limit;
 };
+
+// Cell row of a key: key / nx by one multiplication and shift.  With
+// s = 31 + ceil(log2 nx) and m = ceil(2^s / nx), m nx = 2^s + e with 0 <= e < nx,
+// so key m / 2^s exceeds key / nx by less than 1 / nx and the floors agree for
+// every key < 2^31 (Granlund & Montgomery, division by invariant integers).
+template <class T> __device__ __forceinline__ int cell_row(const Consts<T> &k, int key) {
+  return (int)(((unsigned long long)(unsigned)key * k.nx_m) >> k.nx_s);
+}
+template <class T> __device__ __forceinline__ void cell_xy(const Consts<T> &k, int key, int &cx, int &cy) {
+  cy = cell_row(k, key);
+  cx = key - cy * k.nx;
+}
+
+// Division, square root and power in the arithmetic type.  FP64 keeps the
+// correctly rounded operations exactly as written (the oracle's results bit for
+// bit); the modes with FP32 arithmetic use the hardware reciprocal, square root,
+// log2 and exp2 instructions (about 1 ulp each).
+template <int P, class T> __device__ __forceinline__ T dv(T a, T b) {
+  if constexpr (P == PREC_FP64) return a / b;
+  else return a * __builtin_amdgcn_rcpf(b);
+}
+template <int P, class T> __device__ __forceinline__ T sq(T a) {
+  if constexpr (P == PREC_FP64) return sqrt(a);
+  else return __builtin_amdgcn_sqrtf(a);
+}
+template <int P, class T> __device__ __forceinline__ T pw(T a, T e) {
+  if constexpr (P == PREC_FP64) return pow(a, e);
+  else return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(a));
+}
 
 // Particle storage (structure of arrays, one "slot" per particle).
 template <class T> struct Parts {

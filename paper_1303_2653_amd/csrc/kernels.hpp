@@ -68,7 +68,10 @@ template <int P> struct Pos {
       dx = x;
       dy = y;
     } else {
-      int dcx = ka % k.nx - kb % k.nx, dcy = ka / k.nx - kb / k.nx;
+      int ax, ay, bx, by;
+      cell_xy(k, ka, ax, ay);
+      cell_xy(k, kb, bx, by);
+      int dcx = ax - bx, dcy = ay - by;
       if (k.per_x) {
         if (dcx > k.nx / 2)
           dcx -= k.nx;
@@ -206,11 +209,17 @@ template <int P> struct Pos {
   // Global coordinate along x / y as FP64 (exact for both representations).
   __device__ static double gx(const Consts<T> &k, int key, T x) {
     if constexpr (G) return (double)x;
-    else return (double)(key % k.nx) + (double)x;
+    else return (double)(key - cell_row(k, key) * k.nx) + (double)x;
   }
   __device__ static double gy(const Consts<T> &k, int key, T y) {
     if constexpr (G) return (double)y;
-    else return (double)(key / k.nx) + (double)y;
+    else return (double)cell_row(k, key) + (double)y;
+  }
+
+  __device__ static int walls_key(const Consts<T> &k, int key, T x, T y, T &vx, T &vy) {
+    int cx, cy;
+    cell_xy(k, key, cx, cy);
+    return walls(k, cx, cy, x, y, vx, vy);
   }
 
   // Particle-wall collisions on non-periodic axes (walls as infinitely heavy
@@ -356,7 +365,8 @@ __device__ __forceinline__ void collide_body(const int bidx, const int gdim,
   for (int i = threadIdx.x; i < min(k.nlut, LUT_ROWS_MAX) * LUT_W; i += BLOCK) sl[i] = lut[i];
   __syncthreads();
   if (!live) return;
-  const int x = c % k.nx, y = c / k.nx;
+  int x, y;
+  cell_xy(k, c, x, y);
 
   // The binning leaves each cell's particles in arrival order: put the
   // segment in ascending particle index (a segment already in order is only
@@ -446,8 +456,8 @@ __device__ __forceinline__ void collide_body(const int bidx, const int gdim,
   }
   T vsx = (T)0, vsy = (T)0;
   if (n > 0) {
-    vsx = sx / (T)n;
-    vsy = sy / (T)n;
+    vsx = dv<P>(sx, (T)n);
+    vsy = dv<P>(sy, (T)n);
   }
   const int row = min(n, k.nlut - 1);
   const T *L = row < LUT_ROWS_MAX ? sl + row * LUT_W : lut + (size_t)row * LUT_W;
@@ -465,7 +475,7 @@ __device__ __forceinline__ void collide_body(const int bidx, const int gdim,
   for (int i = 0; i < Q; ++i) jx += (T)cx_of(i) * f[i];
 #pragma unroll
   for (int i = 0; i < Q; ++i) jy += (T)cy_of(i) * f[i];
-  const T ux = jx / rho, uy = jy / rho;
+  const T ux = dv<P>(jx, rho), uy = dv<P>(jy, rho);
   T fu[Q], oms[Q], fs[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) fu[i] = feq_v<P>(i, rho, rho1, ux, uy);
@@ -481,20 +491,20 @@ __device__ __forceinline__ void collide_body(const int bidx, const int gdim,
 #pragma unroll
   for (int i = 0; i < Q; ++i) ssy += (T)cy_of(i) * oms[i];
   const T fpx = omg * ssx, fpy = omg * ssy;
-  const T usx = (jx + (T)0.5 * fpx + k.halfG[0]) / rho;
-  const T usy = (jy + (T)0.5 * fpy + k.halfG[1]) / rho;
-  const T ugx = usx / L[L_UDIV], ugy = usy / L[L_UDIV];
+  const T usx = dv<P>(jx + (T)0.5 * fpx + k.halfG[0], rho);
+  const T usy = dv<P>(jy + (T)0.5 * fpy + k.halfG[1], rho);
+  const T ugx = dv<P>(usx, L[L_UDIV]), ugy = dv<P>(usy, L[L_UDIV]);
   const T ddx = ugx - vsx, ddy = ugy - vsy;
-  const T slip = sqrt(ddx * ddx + ddy * ddy);
+  const T slip = sq<P>(ddx * ddx + ddy * ddy);
   T beta;
   if (L[L_DILUTE] != (T)0) {
-    const T re = L[L_BRE] * slip * k.d / k.mu;
+    const T re = dv<P>(L[L_BRE] * slip * k.d, k.mu);
     if (re < (T)1000)
-      beta = L[L_A] * ((T)1.0 + (T)0.15 * pow(re, (T)0.687));
+      beta = L[L_A] * ((T)1.0 + (T)0.15 * pw<P>(re, (T)0.687));
     else
-      beta = L[L_H] * slip * (T)0.44 * L[L_OM] / k.d;
+      beta = dv<P>(L[L_H] * slip * (T)0.44 * L[L_OM], k.d);
   } else {
-    beta = L[L_D1] + L[L_D2] * slip / k.d;
+    beta = L[L_D1] + dv<P>(L[L_D2] * slip, k.d);
   }
   fl.rho[c] = kDev<P> ? rho1 : rho;  // the deviation modes keep rho - 1
   fl.ugx[c] = ugx;
@@ -627,8 +637,8 @@ template <int P> struct DragTile {
         uy[q] = g.uy[r];
         beta[q] = g.beta[r];
         es[q] = g.es[r];
-        gpx[q] = (g.re[r] / (T)3.0 - g.rw[r] / (T)3.0) * (T)0.5;
-        gpy[q] = (g.rn[r] / (T)3.0 - g.rs[r] / (T)3.0) * (T)0.5;
+        gpx[q] = (dv<P>(g.re[r], (T)3.0) - dv<P>(g.rw[r], (T)3.0)) * (T)0.5;
+        gpy[q] = (dv<P>(g.rn[r], (T)3.0) - dv<P>(g.rs[r], (T)3.0)) * (T)0.5;
       }
     }
   }
@@ -709,19 +719,19 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
       auto finish = [&](int s, T prx, T pry, T gpx, T gpy, T Sx, T Sy, T x, T y, T vx, T vy) -> int {
         T fdx, fdy;
         if (Sx == (T)0)
-          fdx = -fgx / (T)n;
+          fdx = dv<P>(-fgx, (T)n);
         else if (k.drag_abs)
-          fdx = fabs(fgx) / fabs(Sx) * prx;
+          fdx = dv<P>(fabs(fgx), fabs(Sx)) * prx;
         else
-          fdx = -fgx * prx / Sx;
+          fdx = dv<P>(-fgx * prx, Sx);
         if (Sy == (T)0)
-          fdy = -fgy / (T)n;
+          fdy = dv<P>(-fgy, (T)n);
         else if (k.drag_abs)
-          fdy = fabs(fgy) / fabs(Sy) * pry;
+          fdy = dv<P>(fabs(fgy), fabs(Sy)) * pry;
         else
-          fdy = -fgy * pry / Sy;
-        const T ax = k.geff[0] + (fdx + k.fp * gpx) / k.m;
-        const T ay = k.geff[1] + (fdy + k.fp * gpy) / k.m;
+          fdy = dv<P>(-fgy * pry, Sy);
+        const T ax = k.geff[0] + dv<P>(fdx + k.fp * gpx, k.m);
+        const T ay = k.geff[1] + dv<P>(fdy + k.fp * gpy, k.m);
         vx = vx + ax;
         vy = vy + ay;
         int nk = Pos<P>::move(k, cx, cy, x, y, vx, vy);
@@ -763,8 +773,8 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
           if (u < n) {
             Interp<P> I;
             I.at(k, D, tx0, ty0, cx, cy, x[u], y[u]);
-            prx[u] = k.vp * I.beta / I.es * (I.ux - vx[u]);
-            pry[u] = k.vp * I.beta / I.es * (I.uy - vy[u]);
+            prx[u] = dv<P>(k.vp * I.beta, I.es) * (I.ux - vx[u]);
+            pry[u] = dv<P>(k.vp * I.beta, I.es) * (I.uy - vy[u]);
             gpx[u] = I.gpx;
             gpy[u] = I.gpy;
             Sx += prx[u];
@@ -782,16 +792,16 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
         for (int s = a0; s < a1; ++s) {
           Interp<P> I;
           I.at(k, D, tx0, ty0, cx, cy, pt.px[s], pt.py[s]);
-          Sx += k.vp * I.beta / I.es * (I.ux - pt.vx[s]);
-          Sy += k.vp * I.beta / I.es * (I.uy - pt.vy[s]);
+          Sx += dv<P>(k.vp * I.beta, I.es) * (I.ux - pt.vx[s]);
+          Sy += dv<P>(k.vp * I.beta, I.es) * (I.uy - pt.vy[s]);
         }
         nzero = (Sx == (T)0) + (Sy == (T)0);
         for (int s = a0; s < a1; ++s) {
           Interp<P> I;
           const T x = pt.px[s], y = pt.py[s], vx = pt.vx[s], vy = pt.vy[s];
           I.at(k, D, tx0, ty0, cx, cy, x, y);
-          const T prx = k.vp * I.beta / I.es * (I.ux - vx);
-          const T pry = k.vp * I.beta / I.es * (I.uy - vy);
+          const T prx = dv<P>(k.vp * I.beta, I.es) * (I.ux - vx);
+          const T pry = dv<P>(k.vp * I.beta, I.es) * (I.uy - vy);
           count_new(s, finish(s, prx, pry, I.gpx, I.gpy, Sx, Sy, x, y, vx, vy));
         }
       }
@@ -886,7 +896,8 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
     const int id = pt.pid[s];
     const T x = pt.px[s], y = pt.py[s];
     T vx0 = pt.vx[s], vy0 = pt.vy[s];  // for the wall pass of a contact-free particle
-    const int cy = key / k.nx, cx = key - cy * k.nx;
+    int cx, cy;
+    cell_xy(k, key, cx, cy);
     const T dd = k.d * k.d;
     const AdjRow row = adj.row(s);
     // Pass 1 keeps the first CONTACT_REG contacts sorted in registers (no
@@ -1077,9 +1088,9 @@ __device__ __forceinline__ bool pair_core(const Consts<typename Prec<P>::T> &k, 
   const T dot = dvx * dx + dvy * dy;
   if (!(dot < (T)0)) return false;
   const T r2 = dx * dx + dy * dy;
-  const T q0 = k.one_e * dot / r2;
-  const T ci = q0 * k.m / k.msum;
-  const T cj = q0 * k.m / k.msum;
+  const T q0 = dv<P>(k.one_e * dot, r2);
+  const T ci = dv<P>(q0 * k.m, k.msum);
+  const T cj = dv<P>(q0 * k.m, k.msum);
   vix = vix - ci * dx;
   viy = viy - ci * dy;
   vjx = vjx + cj * dx;
@@ -1107,7 +1118,7 @@ __device__ __forceinline__ int wall_pass(const Consts<typename Prec<P>::T> &k, P
   using T = typename Prec<P>::T;
   T vx = pt.vx[s], vy = pt.vy[s];
   const int key = pt.key[s];
-  const int h = Pos<P>::walls(k, key % k.nx, key / k.nx, pt.px[s], pt.py[s], vx, vy);
+  const int h = Pos<P>::walls_key(k, key, pt.px[s], pt.py[s], vx, vy);
   if (h) {
     pt.vx[s] = vx;
     pt.vy[s] = vy;
@@ -1209,7 +1220,7 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typen
         ++ncoll;
       }
     }
-    nwall += Pos<P>::walls(k, ku % k.nx, ku / k.nx, xu, yu, vxu, vyu);
+    nwall += Pos<P>::walls_key(k, ku, xu, yu, vxu, vyu);
     pt.vx[u] = vxu;
     pt.vy[u] = vyu;
     done[u] = dgu;
@@ -1414,7 +1425,7 @@ __device__ int resolve_group(ClusterLds<P, G> &B, int *shi, int s0, int g, const
   if (mem) {
     T vx = B.vx[tid], vy = B.vy[tid];
     const int key = B.key[tid];
-    nwall += Pos<P>::walls(k, key % k.nx, key / k.nx, B.px[tid], B.py[tid], vx, vy);
+    nwall += Pos<P>::walls_key(k, key, B.px[tid], B.py[tid], vx, vy);
     pt.vx[u] = vx;
     pt.vy[u] = vy;
     done[u] = deg[u];
@@ -1901,8 +1912,10 @@ __global__ __launch_bounds__(BLOCK) void k_get_parts(Parts<typename Prec<P>::T> 
     vel[2 * g + 1] = (double)pt.vy[s];
   }
   if (cell) {
-    cell[2 * g] = key % k.nx;
-    cell[2 * g + 1] = key / k.nx;
+    int cx, cy;
+    cell_xy(k, key, cx, cy);
+    cell[2 * g] = cx;
+    cell[2 * g + 1] = cy;
   }
   if (fd) {
     fd[2 * g] = (double)fdx[g];

@@ -345,6 +345,12 @@ template <int P> struct Impl {
     k.ny = x->ny;
     k.C = x->C;
     k.nlut = x->nlut;
+    {  // key / nx by multiplication (see cell_row)
+      int l = 0;
+      while ((1ll << l) < x->nx) ++l;
+      k.nx_s = 31 + l;
+      k.nx_m = (unsigned long long)(((1ull << k.nx_s) + (unsigned long long)x->nx - 1) / (unsigned long long)x->nx);
+    }
     k.per_x = x->p.bc[0] == BC_PERIODIC;
     k.per_y = x->p.bc[2] == BC_PERIODIC;
     k.bc_ylo = x->p.bc[2];

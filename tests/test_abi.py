@@ -136,3 +136,23 @@ def test_tuning_struct_layout():
     assert L.lbdps_set_tuning(None, None) == L.LBDPS_E_INVALID
     assert L.lbdps_autotune(None, 1, None) == L.LBDPS_E_INVALID
     assert L.lbdps_batch_autotune(None, 1, None) == L.LBDPS_E_INVALID
+
+
+def test_cell_row_by_multiplication_is_exact():
+    """The library computes key // nx as (key * m) >> s with s = 31 +
+    ceil(log2 nx), m = ceil(2^s / nx): exact for every key < 2^31 (the error
+    term stays below 1 / nx).  Checked here on widths 1..4096, powers of two
+    and their neighbours, at the keys where a floor changes."""
+    import random
+    rng = random.Random(3)
+    widths = list(range(1, 4097)) + [2 ** k + d for k in range(12, 31) for d in (-1, 0, 1)]
+    for nx in widths:
+        if nx < 1:
+            continue
+        s = 31 + max(0, (nx - 1).bit_length())
+        m = -(-(1 << s) // nx)
+        top = (2 ** 31 - 1) // nx * nx
+        keys = [0, 1, nx - 1, nx, nx + 1, top - 1, top, 2 ** 31 - 1] + [rng.randrange(2 ** 31) for _ in range(8)]
+        for key in keys:
+            if 0 <= key < 2 ** 31:
+                assert (key * m) >> s == key // nx, (nx, key)
