@@ -387,7 +387,10 @@ __device__ __forceinline__ void collide_body(const int bidx, const int gdim,
         vx[u] = pt.vx[a0 + u];
         vy[u] = pt.vy[a0 + u];
       }
-    bool moved = false;
+    bool moved = false, unsorted = false;
+#pragma unroll
+    for (int q = 0; q < SEG_REG - 1; ++q) unsorted |= q + 1 < n && id[q] > id[q + 1];
+    if (unsorted)  // cells whose particles stayed keep their order: usually nothing to do
 #pragma unroll
     for (int pass = 0; pass < SEG_REG - 1; ++pass)
 #pragma unroll
@@ -520,6 +523,11 @@ __device__ __forceinline__ void collide_body(const int bidx, const int gdim,
   }
 
   // Streaming, push form.  An x wall takes precedence at corners.
+  if (x >= 1 && x < k.nx - 1 && y >= 1 && y < k.ny - 1) {  // interior: every neighbour is a lattice node
+#pragma unroll
+    for (int i = 0; i < Q; ++i) store_v<P>(fdst, i * C + c + cy_of(i) * k.nx + cx_of(i), fs[i]);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     int tx = x + cx_of(i), ty = y + cy_of(i);
