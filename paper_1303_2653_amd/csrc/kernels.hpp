@@ -295,7 +295,7 @@ struct TileSums {
 constexpr int LUT_ROWS_MAX = 64;              // per-count table rows staged in LDS
 constexpr int RANK_MOVED = 1 << 30;           // rank flag: the particle arrived from another cell
 constexpr int SEG_REG = 4;                    // cell segments up to this length stay in registers
-constexpr int CONTACT_REG = 6;                // contacts per particle collected in registers first
+constexpr int CONTACT_REG = 4;                // contacts per particle collected in registers first
 constexpr int CONTACT_CH = 4;                 // candidate positions loaded together
 constexpr int RES_ITEMS = 8;                  // particle indices per lane and resolution chunk
 constexpr int RES_CHUNK = BLOCK * RES_ITEMS;  // particle indices per chunk
