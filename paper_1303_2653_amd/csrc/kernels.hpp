@@ -1470,6 +1470,13 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
   int tot;
   const int c = (int)threadIdx.x < nb ? rcount[b0 + threadIdx.x] : 0;
   const int o = block_excl_scan(c, shi, tot);
+  if (tot == 0) {  // no candidate roots in these lists (uniform: the scan's total)
+    if (threadIdx.x == 0) {
+      coll_part[bidx] = 0;
+      wall_part[bidx] = 0;
+    }
+    return;
+  }
   if ((int)threadIdx.x < nb) pre[threadIdx.x] = o;
   if (threadIdx.x == 0) pre[nb] = tot;
   __syncthreads();
