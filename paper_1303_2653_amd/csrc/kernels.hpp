@@ -382,15 +382,21 @@ __device__ __forceinline__ void collide_body(const int bidx, const int gdim,
     for (int u = 0; u < SEG_REG; ++u)
       if (u < n) {
         id[u] = pt.pid[a0 + u];
-        px[u] = pt.px[a0 + u];
-        py[u] = pt.py[a0 + u];
         vx[u] = pt.vx[a0 + u];
         vy[u] = pt.vy[a0 + u];
       }
     bool moved = false, unsorted = false;
 #pragma unroll
     for (int q = 0; q < SEG_REG - 1; ++q) unsorted |= q + 1 < n && id[q] > id[q + 1];
-    if (unsorted)  // cells whose particles stayed keep their order: usually nothing to do
+    if (unsorted) {  // positions are needed only to move records: usually the cell is in order
+#pragma unroll
+      for (int u = 0; u < SEG_REG; ++u)
+        if (u < n) {
+          px[u] = pt.px[a0 + u];
+          py[u] = pt.py[a0 + u];
+        }
+    }
+    if (unsorted)
 #pragma unroll
     for (int pass = 0; pass < SEG_REG - 1; ++pass)
 #pragma unroll
