@@ -909,9 +909,16 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
     const int key = pt.key[s];
     const int id = pt.pid[s];
     const T x = pt.px[s], y = pt.py[s];
-    T vx0 = pt.vx[s], vy0 = pt.vy[s];  // for the wall pass of a contact-free particle
     int cx, cy;
     cell_xy(k, key, cx, cy);
+    // velocity for the wall pass of a contact-free particle: only a particle in a
+    // cell next to a wall can need it
+    const bool by_wall = (!k.per_x && (cx == 0 || cx == k.nx - 1)) || (!k.per_y && (cy == 0 || cy == k.ny - 1));
+    T vx0 = (T)0, vy0 = (T)0;
+    if (by_wall) {
+      vx0 = pt.vx[s];
+      vy0 = pt.vy[s];
+    }
     const T dd = k.d * k.d;
     const AdjRow row = adj.row(s);
     // Pass 1 keeps the first CONTACT_REG contacts sorted in registers (no
@@ -1044,7 +1051,7 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
     deg[s] = cnt;
     done[s] = 0;
     if (cnt > 0) chunk_busy[id / RES_CHUNK] = 1;  // the resolution visits this chunk of indices
-    if (cnt == 0) {  // no binary collision: the wall pass can run now
+    if (cnt == 0 && by_wall) {  // no binary collision: the wall pass can run now
       const int h = Pos<P>::walls(k, cx, cy, x, y, vx0, vy0);
       if (h) {
         pt.vx[s] = vx0;
