@@ -49,10 +49,11 @@ __device__ __forceinline__ int bed_of(const int *__restrict__ off, int nbeds, in
 // flip = parity of the step within the batched sequence: the population
 // buffers swap every step, the particle record sets every step of a bed with
 // particles.
-#define LBDPS_BED_PROLOGUE                                        \
-  const int b = bed_of(off, nbeds, blockIdx.x);                   \
+#define LBDPS_BED_PROLOGUE(RUN)                                   \
+  const int gb = xcd_block<RUN>(blockIdx.x, gridDim.x);          \
+  const int b = bed_of(off, nbeds, gb);                           \
   const BedArgs<P> &a = tab[b];                                   \
-  const int bid = (int)blockIdx.x - off[b], nbk = off[b + 1] - off[b]; \
+  const int bid = gb - off[b], nbk = off[b + 1] - off[b];         \
   const int cf = a.cf ^ flip, cp = a.cp ^ (flip & a.cp_moves);    \
   (void)cf;                                                       \
   (void)cp;
@@ -60,7 +61,7 @@ __device__ __forceinline__ int bed_of(const int *__restrict__ off, int nbeds, in
 template <int P>
 __global__ __launch_bounds__(BLOCK) void kb_collide(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                     int nbeds, int flip) {
-  LBDPS_BED_PROLOGUE
+  LBDPS_BED_PROLOGUE(XCD_RUN_COLLIDE)
   collide_body<P>(bid, nbk, a.f[cf], a.f[1 - cf], a.fl, a.cs, a.parts(cp), a.lut, a.inlet, a.k, nullptr, nullptr,
                   nullptr);
 }
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(BLOCK) void kb_collide(const BedArgs<P> *__restrict
 template <int P>
 __global__ __launch_bounds__(BLOCK) void kb_drag(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                  int nbeds, int flip) {
-  LBDPS_BED_PROLOGUE
+  LBDPS_BED_PROLOGUE(XCD_RUN_DRAG)
   drag_body<P>(bid, nbk, a.parts(cp), a.fl, a.cs, a.lut, a.k, a.count, a.rank, a.flags, nullptr, nullptr, nullptr,
                a.ts, a.stay);
 }
@@ -76,14 +77,14 @@ __global__ __launch_bounds__(BLOCK) void kb_drag(const BedArgs<P> *__restrict__ 
 template <int P>
 __global__ __launch_bounds__(BLOCK) void kb_scan(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                  int nbeds, int flip) {
-  LBDPS_BED_PROLOGUE
+  LBDPS_BED_PROLOGUE(XCD_RUN_SCAN)
   scan_cells_body(bid, nbk, a.count, (long long)a.k.C, a.ts, a.cs, a.stay);
 }
 
 template <int P>
 __global__ __launch_bounds__(BLOCK) void kb_scatter(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                     int nbeds, int flip) {
-  LBDPS_BED_PROLOGUE
+  LBDPS_BED_PROLOGUE(XCD_RUN_SCATTER)
   scatter_body<typename Prec<P>::T>(bid, nbk, a.parts(cp), a.parts(1 - cp), a.rank, a.cs, a.k.npart, a.slot, a.ts,
                                     a.stay);
 }
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(BLOCK) void kb_scatter(const BedArgs<P> *__restrict
 template <int P>
 __global__ __launch_bounds__(BLOCK) void kb_contacts(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                      int nbeds, int flip) {
-  LBDPS_BED_PROLOGUE
+  LBDPS_BED_PROLOGUE(XCD_RUN_CONTACTS)
   contacts_body<P>(bid, nbk, a.parts(1 - cp), a.cs, a.k, a.adj, a.deg, a.done, a.ticket, a.flags, a.pair_part,
                    a.wall0_part, a.chunk_busy, a.need_sweep, a.roots, a.rcount);
 }
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(BLOCK) void kb_contacts(const BedArgs<P> *__restric
 template <int P>
 __global__ __launch_bounds__(BLOCK) void kb_clusters(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                      int nbeds, int flip) {
-  LBDPS_BED_PROLOGUE
+  LBDPS_BED_PROLOGUE(XCD_RUN_CLUSTERS)
   resolve_clusters_body<P>(bid, nbk, a.parts(1 - cp), a.adj, a.deg, a.done, a.k, a.need_sweep, a.collc_part,
                            a.wallc_part, a.roots, a.rcount, a.nlists);
 }
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(BLOCK) void kb_clusters(const BedArgs<P> *__restric
 template <int P>
 __global__ __launch_bounds__(BLOCK) void kb_resolve(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                     int nbeds, int flip) {
-  LBDPS_BED_PROLOGUE
+  LBDPS_BED_PROLOGUE(XCD_RUN_RESOLVE)
   resolve_body<P>(bid, nbk, a.parts(1 - cp), a.slot, a.adj, a.deg, a.done, a.ticket, a.k, a.flags, a.coll_part,
                   a.wall_part, a.chunk_busy, a.need_sweep);
 }

@@ -590,7 +590,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
                                                    const typename Prec<P>::T *__restrict__ inlet,
                                                    Consts<typename Prec<P>::T> k, int32_t *dg_n,
                                                    typename Prec<P>::T *dg_vsx, typename Prec<P>::T *dg_vsy) {
-  collide_body<P>(blockIdx.x, gridDim.x, fsrc, fdst, fl, cs, pt, lut, inlet, k, dg_n, dg_vsx, dg_vsy);
+  collide_body<P>(xcd_block<XCD_RUN_COLLIDE>(blockIdx.x, gridDim.x), gridDim.x, fsrc, fdst, fl, cs, pt, lut, inlet, k, dg_n, dg_vsx, dg_vsy);
 }
 
 // ------------------------------------------------------------------ A4 + A5: drag and integration, fused with binning
@@ -840,7 +840,7 @@ __global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, F
                                                 int32_t *__restrict__ rank, int32_t *flags,
                                                 typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy,
                                                 long long *zero_part, TileSums ts, int32_t *__restrict__ stay) {
-  drag_body<P>(blockIdx.x, gridDim.x, pt, fl, cs, lut, k, count, rank, flags, dg_fdx, dg_fdy, zero_part, ts, stay);
+  drag_body<P>(xcd_block<XCD_RUN_DRAG>(blockIdx.x, gridDim.x), gridDim.x, pt, fl, cs, lut, k, count, rank, flags, dg_fdx, dg_fdy, zero_part, ts, stay);
 }
 
 // ------------------------------------------------------------------ A1: binning (counting sort by cell)
@@ -877,7 +877,7 @@ template <class T>
 __global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, const int32_t *__restrict__ rank,
                                                    const int32_t *__restrict__ cs, int n, int32_t *__restrict__ slot,
                                                    TileSums ts, const int32_t *__restrict__ stay) {
-  scatter_body<T>(blockIdx.x, gridDim.x, src, dst, rank, cs, n, slot, ts, stay);
+  scatter_body<T>(xcd_block<XCD_RUN_SCATTER>(blockIdx.x, gridDim.x), gridDim.x, src, dst, rank, cs, n, slot, ts, stay);
 }
 
 // ------------------------------------------------------------------ A6: contact detection
@@ -1080,7 +1080,7 @@ __global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> p
                                                     long long *wall_part, int32_t *__restrict__ chunk_busy,
                                                     int32_t *need_sweep, long long *__restrict__ roots,
                                                     int32_t *__restrict__ rcount) {
-  contacts_body<P>(blockIdx.x, gridDim.x, pt, cs, k, adj, deg, done, ticket, flags, pair_part, wall_part, chunk_busy,
+  contacts_body<P>(xcd_block<XCD_RUN_CONTACTS>(blockIdx.x, gridDim.x), gridDim.x, pt, cs, k, adj, deg, done, ticket, flags, pair_part, wall_part, chunk_busy,
       need_sweep, roots, rcount);
 }
 
@@ -1545,7 +1545,7 @@ __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<
                                                             long long *coll_part, long long *wall_part,
                                                             const long long *__restrict__ roots,
                                                             const int32_t *__restrict__ rcount, int nlists) {
-  resolve_clusters_body<P>(blockIdx.x, gridDim.x, pt, adj, deg, done, k, need_sweep, coll_part, wall_part, roots,
+  resolve_clusters_body<P>(xcd_block<XCD_RUN_CLUSTERS>(blockIdx.x, gridDim.x), gridDim.x, pt, adj, deg, done, k, need_sweep, coll_part, wall_part, roots,
       rcount, nlists);
 }
 
@@ -1722,7 +1722,7 @@ __device__ __forceinline__ void scan_cells_body(const int bidx, const int gdim, 
 }
 __global__ __launch_bounds__(BLOCK) void k_scan_cells(int32_t *__restrict__ count, long long n, TileSums ts,
                                                       int32_t *__restrict__ out, const int32_t *__restrict__ stay) {
-  scan_cells_body(blockIdx.x, gridDim.x, count, n, ts, out, stay);
+  scan_cells_body(xcd_block<XCD_RUN_SCAN>(blockIdx.x, gridDim.x), gridDim.x, count, n, ts, out, stay);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int32_t *__restrict__ in, long long n,
