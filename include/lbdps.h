@@ -77,7 +77,7 @@ typedef enum {
 #define LBDPS_MAX_CONTACTS 32
 
 typedef struct {
-  int32_t nx, ny;            /* lattice size, nx, ny >= 3, nx * ny < 2^31            */
+  int32_t nx, ny;            /* lattice size, nx, ny >= 3, nx * ny < 2^29            */
   int32_t bc[4];             /* lbdps_bc of faces x-, x+, y-, y+                       */
   double tau;                /* relaxation time, tau = 3 nu + 1/2 (Eq. 3), > 0.5      */
   double rho_g;              /* gas density in the drag laws (Eqs. 19, 22), > 0       */
@@ -103,7 +103,8 @@ typedef struct {
 
 typedef struct lbdps_ctx lbdps_ctx;
 
-/* Check parameters without touching any device.  max_particles >= 0. */
+/* Check parameters without touching any device.  0 <= max_particles < 2^29 (arrays
+ * are addressed by 32-bit byte offsets); LBDPS_E_SHAPE otherwise. */
 lbdps_status lbdps_validate_params(const lbdps_params *p, int64_t max_particles);
 
 /* Workspace size for a context holding up to max_particles particles.  Device-free. */

@@ -182,6 +182,15 @@ template <int P, class T> __device__ __forceinline__ T pw(T a, T e) {
   else return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(a));
 }
 
+// Element i of an array whose base address is uniform across the wavefront,
+// addressed by a 32-bit byte offset: the load then takes the base from scalar
+// registers and one 32-bit vector offset, with no 64-bit address arithmetic
+// per lane.  Needs 0 <= i and i * sizeof(T) < 2^32 (the library bounds the
+// particle count and the lattice size at creation).
+template <class T> __device__ __forceinline__ T ldu(const T *base, int i) {
+  return *(const T *)((const char *)base + (unsigned)i * (unsigned)sizeof(T));
+}
+
 // Particle storage (structure of arrays, one "slot" per particle).
 template <class T> struct Parts {
   int32_t *key;  // cell index y * nx + x

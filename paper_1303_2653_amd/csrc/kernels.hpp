@@ -273,6 +273,14 @@ struct AdjRow {
   long long *a, *b;
   __device__ long long &operator[](int i) const { return i < ADJ_IN ? a[i] : b[i - ADJ_IN]; }
 };
+// The dense part of a row held in registers; get() selects an entry without
+// indexing (which would put the values in scratch memory).
+struct Dense4 {
+  long long e0, e1, e2, e3;
+  __device__ explicit Dense4(const long long *a) : e0(a[0]), e1(a[1]), e2(a[2]), e3(a[3]) {}
+  __device__ long long get(int i) const { return i == 0 ? e0 : (i == 1 ? e1 : (i == 2 ? e2 : e3)); }
+};
+static_assert(ADJ_IN == 4, "Dense4 holds the dense part of a row");
 struct Adj {
   long long *in, *ov;
   __device__ AdjRow row(int u) const {
@@ -311,6 +319,26 @@ __device__ __forceinline__ int block_excl_scan(int v, int *sh, int &total) {
   if (lane == 63) sh[wv] = inc;
   __syncthreads();
   int base = 0;
+  total = 0;
+  for (int w = 0; w < BLOCK / 64; ++w) {
+    if (w < wv) base += sh[w];
+    total += sh[w];
+  }
+  __syncthreads();
+  return base + inc - v;
+}
+
+// Block-wide exclusive scan of one 64-bit integer per thread; total = block sum.
+__device__ __forceinline__ long long block_excl_scan_ll(long long v, long long *sh, long long &total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  long long inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) sh[wv] = inc;
+  __syncthreads();
+  long long base = 0;
   total = 0;
   for (int w = 0; w < BLOCK / 64; ++w) {
     if (w < wv) base += sh[w];
@@ -955,33 +983,39 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
         if (t == s) return;
         T dx, dy;
         Pos<P>::sep_nb(k, ox, oy, x, y, pt.px[t], pt.py[t], dx, dy);
-        if (dx * dx + dy * dy <= dd) hit(t);
+        if (dx * dx + dy * dy <= dd) hit(t, pt.pid[t]);
       };
       if (inner_x) {
         // one flattened pass over the three rows' ranges, CONTACT_CH candidates
-        // at a time: their positions are all loaded before any is tested
-        const int n0 = rhi[0] - rlo[0], n1 = rhi[1] - rlo[1], n2 = rhi[2] - rlo[2];
-        const int tot = n0 + n1 + n2;  // >= 1: the particle's own cell
+        // at a time: their positions and indices are all loaded before any is
+        // tested.  Candidate q of the flattened range is slot q + sh_r in row r.
+        const int n0 = rhi[0] - rlo[0], n01 = n0 + rhi[1] - rlo[1];
+        const int tot = n01 + rhi[2] - rlo[2];  // >= 1: the particle's own cell
+        const int sh0 = rlo[0], sh1 = rlo[1] - n0, sh2 = rlo[2] - n01;
+        // column boundaries as plain values (selected per candidate, not indexed)
+        const int a0 = rm1[0], a1 = rm1[1], a2 = rm1[2], b0 = rm2[0], b1 = rm2[1], b2 = rm2[2];
         for (int q0 = 0; q0 < tot; q0 += CONTACT_CH) {
-          int tt[CONTACT_CH], ox[CONTACT_CH], oy[CONTACT_CH];
+          int tt[CONTACT_CH], ox[CONTACT_CH], oy[CONTACT_CH], ids[CONTACT_CH];
           T xs[CONTACT_CH], ys[CONTACT_CH];
 #pragma unroll
           for (int j = 0; j < CONTACT_CH; ++j) {
             const int q = min(q0 + j, tot - 1);  // past the end: repeat the last candidate
-            const int rw = q < n0 ? 0 : (q < n0 + n1 ? 1 : 2);
-            const int t = rlo[rw] + q - (rw == 0 ? 0 : (rw == 1 ? n0 : n0 + n1));
+            const bool r0 = q < n0, r1 = q < n01;
+            const int t = q + (r0 ? sh0 : (r1 ? sh1 : sh2));
+            const int m1 = r0 ? a0 : (r1 ? a1 : a2), m2 = r0 ? b0 : (r1 ? b1 : b2);
             tt[j] = t;
-            ox[j] = t < rm1[rw] ? -1 : (t < rm2[rw] ? 0 : 1);
-            oy[j] = rw - 1;
-            xs[j] = pt.px[t];
-            ys[j] = pt.py[t];
+            ox[j] = t < m1 ? -1 : (t < m2 ? 0 : 1);
+            oy[j] = r0 ? -1 : (r1 ? 0 : 1);
+            xs[j] = ldu(pt.px, t);
+            ys[j] = ldu(pt.py, t);
+            ids[j] = ldu(pt.pid, t);
           }
 #pragma unroll
           for (int j = 0; j < CONTACT_CH; ++j) {
             if (q0 + j < tot && tt[j] != s) {
               T dx, dy;
               Pos<P>::sep_nb(k, ox[j], oy[j], x, y, xs[j], ys[j], dx, dy);
-              if (dx * dx + dy * dy <= dd) hit(tt[j]);
+              if (dx * dx + dy * dy <= dd) hit(tt[j], ids[j]);
             }
           }
         }
@@ -1005,8 +1039,7 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
         }
       }
     };
-    scan([&](int t) {
-      const int tid = pt.pid[t];
+    scan([&](int t, int tid) {
       if (tid > id) ++fwd;
       if (cnt < CONTACT_REG) {
         const long long e = ((long long)tid << 32) | (unsigned)t;
@@ -1030,12 +1063,12 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
         if (u < cnt) row[u] = r[u];
     } else {
       int m = 0;
-      scan([&](int t) {
+      scan([&](int t, int tid) {
         if (m == KMAX) {
           over = true;
           return;
         }
-        const long long e = ((long long)pt.pid[t] << 32) | (unsigned)t;
+        const long long e = ((long long)tid << 32) | (unsigned)t;
         int j = m;
         while (j > 0 && row[j - 1] > e) {
           row[j] = row[j - 1];
@@ -1174,28 +1207,45 @@ struct LdsColumn {  // entry i of a lane's column of a [CL_LDS][BLOCK] LDS array
 
 // Gathers the cluster of candidate slot s (index g) into q[0 .. m) as
 // (index << 32 | slot) and returns m; returns 0 if a member has a lower index
-// than g, and -1 if the cluster has more than cap members.
+// than g, and -1 if the cluster has more than cap members.  Members are
+// expanded two at a time, so the rows of both are loaded together.
 template <class Row>
 __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, Adj adj,
                                               const int32_t *__restrict__ deg) {
   q[0] = ((long long)g << 32) | (unsigned)s;
   int m = 1;
-  for (int head = 0; head < m; ++head) {
-    const int u = (int)(q[head] & 0xffffffffll);
-    const AdjRow ru = adj.row(u);
-    const int du = min(deg[u], KMAX);
-    // the first four entries are loaded together (the dense part of a row)
-    const long long e0 = ru[0], e1 = ru[1], e2 = ru[2], e3 = ru[3];
+  // adds the neighbours of one member; false when the candidate gives up
+  auto expand = [&](const AdjRow &ru, int du, const Dense4 &e4, int &res) {
     for (int a = 0; a < du; ++a) {
-      const long long e = a == 0 ? e0 : (a == 1 ? e1 : (a == 2 ? e2 : (a == 3 ? e3 : ru[a])));
-      if ((int)(e >> 32) < g) return 0;
+      const long long e = a < ADJ_IN ? e4.get(a) : ru[a];
+      if ((int)(e >> 32) < g) {
+        res = 0;
+        return false;
+      }
       bool seen = false;
       for (int i = 0; i < m; ++i) seen |= q[i] == e;
       if (seen) continue;
-      if (m == cap) return -1;
+      if (m == cap) {
+        res = -1;
+        return false;
+      }
       q[m] = e;
       ++m;
     }
+    return true;
+  };
+  for (int head = 0; head < m;) {
+    const bool two = head + 1 < m;
+    const int u0 = (int)(q[head] & 0xffffffffll);
+    const int u1 = two ? (int)(q[head + 1] & 0xffffffffll) : u0;
+    const AdjRow r0 = adj.row(u0), r1 = adj.row(u1);
+    const int d0 = min(ldu(deg, u0), KMAX), d1 = two ? min(ldu(deg, u1), KMAX) : 0;
+    // the dense parts of both rows
+    const Dense4 f(r0.a), h(r1.a);
+    int res = 0;
+    if (!expand(r0, d0, f, res)) return res;
+    if (!expand(r1, d1, h, res)) return res;
+    head += two ? 2 : 1;
   }
   return m;
 }
@@ -1204,7 +1254,9 @@ __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, Adj 
 // lexicographic order: member u (ascending) meets its higher-index neighbours
 // in ascending order, with u's velocity kept in registers over its pairs.
 // Every pair with u as the higher index came before, and none follows, so u's
-// wall pass runs right after its own pairs.
+// wall pass runs right after its own pairs.  The records of the neighbours in
+// the dense part of u's row are all loaded before the first of u's pairs: they
+// are distinct particles, so none of those pairs changes another's record.
 template <int P, class Row>
 __device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typename Prec<P>::T> &k,
                                                 Parts<typename Prec<P>::T> &pt, Adj adj,
@@ -1223,21 +1275,48 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typen
   for (int i = 0; i < m; ++i) {
     const int u = (int)(q[i] & 0xffffffffll), gu = (int)(q[i] >> 32);
     const AdjRow ru = adj.row(u);
-    const int dgu = deg[u], du = min(dgu, KMAX);
-    const long long e0 = ru[0], e1 = ru[1], e2 = ru[2], e3 = ru[3];  // the dense part of the row
-    const int ku = pt.key[u];
-    const T xu = pt.px[u], yu = pt.py[u];
-    T vxu = pt.vx[u], vyu = pt.vy[u];
-    for (int a = 0; a < du; ++a) {
-      const long long e = a == 0 ? e0 : (a == 1 ? e1 : (a == 2 ? e2 : (a == 3 ? e3 : ru[a])));
-      if ((int)(e >> 32) <= gu) continue;
-      const int w = (int)(e & 0xffffffffll);
+    const int dgu = ldu(deg, u), du = min(dgu, KMAX);
+    const Dense4 e4(ru.a);  // the dense part of the row
+    const int ku = ldu(pt.key, u);
+    const T xu = ldu(pt.px, u), yu = ldu(pt.py, u);
+    T vxu = ldu(pt.vx, u), vyu = ldu(pt.vy, u);
+    int w[ADJ_IN], kw[ADJ_IN];
+    bool up[ADJ_IN];
+    T xw[ADJ_IN], yw[ADJ_IN], vxw[ADJ_IN], vyw[ADJ_IN];
+#pragma unroll
+    for (int a = 0; a < ADJ_IN; ++a) {
+      const long long e = e4.get(a);  // a is a constant here
+      up[a] = a < du && (int)(e >> 32) > gu;
+      w[a] = up[a] ? (int)(e & 0xffffffffll) : u;
+      if (up[a]) {
+        kw[a] = ldu(pt.key, w[a]);
+        xw[a] = ldu(pt.px, w[a]);
+        yw[a] = ldu(pt.py, w[a]);
+        vxw[a] = ldu(pt.vx, w[a]);
+        vyw[a] = ldu(pt.vy, w[a]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < ADJ_IN; ++a) {
+      if (!up[a]) continue;
       T dx, dy;
-      Pos<P>::sep(k, ku, xu, yu, pt.key[w], pt.px[w], pt.py[w], dx, dy);
-      T vxw = pt.vx[w], vyw = pt.vy[w];
-      if (pair_core<P>(k, dx, dy, vxu, vyu, vxw, vyw)) {
-        pt.vx[w] = vxw;
-        pt.vy[w] = vyw;
+      Pos<P>::sep(k, ku, xu, yu, kw[a], xw[a], yw[a], dx, dy);
+      if (pair_core<P>(k, dx, dy, vxu, vyu, vxw[a], vyw[a])) {
+        pt.vx[w[a]] = vxw[a];
+        pt.vy[w[a]] = vyw[a];
+        ++ncoll;
+      }
+    }
+    for (int a = ADJ_IN; a < du; ++a) {
+      const long long e = ru[a];
+      if ((int)(e >> 32) <= gu) continue;
+      const int x = (int)(e & 0xffffffffll);
+      T dx, dy;
+      Pos<P>::sep(k, ku, xu, yu, ldu(pt.key, x), ldu(pt.px, x), ldu(pt.py, x), dx, dy);
+      T vx = ldu(pt.vx, x), vy = ldu(pt.vy, x);
+      if (pair_core<P>(k, dx, dy, vxu, vyu, vx, vy)) {
+        pt.vx[x] = vx;
+        pt.vy[x] = vy;
         ++ncoll;
       }
     }
@@ -1691,34 +1770,64 @@ __global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt
 
 // Cell starts in one pass: the tile sums were accumulated while counting, so
 // each workgroup adds the sums of all tiles before its own (a strided sum),
-// scans its SCAN_TILE counts, writes cell_start and clears the counts.
+// scans its SCAN_TILE counts, writes cell_start and clears the counts.  A
+// thread takes SCAN_ITEMS consecutive cells with 16-byte loads and stores, and
+// one 64-bit workgroup scan carries both sums: the high word the tile sums
+// before this tile, the low word this tile's counts (below 2^31, so no carry
+// crosses into the high word).
 __device__ __forceinline__ void scan_cells_body(const int bidx, const int gdim, int32_t *__restrict__ count,
     long long n, TileSums ts, int32_t *__restrict__ out, const int32_t *__restrict__ stay) {
-  __shared__ int sh[BLOCK / 64];
+  static_assert(SCAN_ITEMS == 8, "two 16-byte vectors per thread");
+  __shared__ long long sh[BLOCK / 64];
   const int b = bidx;
+  const long long e0 = (long long)b * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  const bool full = e0 + SCAN_ITEMS <= n;
+  int vals[SCAN_ITEMS];
+  if (full) {
+    const int4 c0 = *(const int4 *)(count + e0), c1 = *(const int4 *)(count + e0 + 4);
+    const int4 s0 = *(const int4 *)(stay + e0), s1 = *(const int4 *)(stay + e0 + 4);
+    vals[0] = c0.x + s0.x;
+    vals[1] = c0.y + s0.y;
+    vals[2] = c0.z + s0.z;
+    vals[3] = c0.w + s0.w;
+    vals[4] = c1.x + s1.x;
+    vals[5] = c1.y + s1.y;
+    vals[6] = c1.z + s1.z;
+    vals[7] = c1.w + s1.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) vals[j] = e0 + j < n ? count[e0 + j] + stay[e0 + j] : 0;
+  }
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) sum += vals[j];
   int v = 0;
 #pragma unroll 8
   for (int i = threadIdx.x; i < b; i += BLOCK) v += ts.tile[i];
-  int base;
-  block_excl_scan(v, sh, base);
-  const long long e0 = (long long)b * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
-  int vals[SCAN_ITEMS];
-  int sum = 0;
+  long long tot;
+  const long long pre = block_excl_scan_ll(((long long)v << 32) | (unsigned)sum, sh, tot);
+  const int base = (int)(tot >> 32);
+  int o[SCAN_ITEMS];
+  int run = base + (int)(pre & 0xffffffffll);
 #pragma unroll
   for (int j = 0; j < SCAN_ITEMS; ++j) {
-    vals[j] = e0 + j < n ? count[e0 + j] + stay[e0 + j] : 0;
-    sum += vals[j];
+    o[j] = run;
+    run += vals[j];
   }
-  int total;
-  int run = base + block_excl_scan(sum, sh, total);
+  if (full) {
+    *(int4 *)(out + e0) = make_int4(o[0], o[1], o[2], o[3]);
+    *(int4 *)(out + e0 + 4) = make_int4(o[4], o[5], o[6], o[7]);
+    *(int4 *)(count + e0) = make_int4(0, 0, 0, 0);
+    *(int4 *)(count + e0 + 4) = make_int4(0, 0, 0, 0);
+  } else {
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j)
-    if (e0 + j < n) {
-      out[e0 + j] = run;
-      run += vals[j];
-      count[e0 + j] = 0;
-    }
-  if (b == gdim - 1 && threadIdx.x == 0) out[n] = base + total;
+    for (int j = 0; j < SCAN_ITEMS; ++j)
+      if (e0 + j < n) {
+        out[e0 + j] = o[j];
+        count[e0 + j] = 0;
+      }
+  }
+  if (b == gdim - 1 && threadIdx.x == 0) out[n] = base + (int)(tot & 0xffffffffll);
 }
 __global__ __launch_bounds__(BLOCK) void k_scan_cells(int32_t *__restrict__ count, long long n, TileSums ts,
                                                       int32_t *__restrict__ out, const int32_t *__restrict__ stay) {

@@ -585,7 +585,7 @@ const char *lbdps_last_error(void) { return g_err.c_str(); }
 lbdps_status lbdps_validate_params(const lbdps_params *p, int64_t max_particles) {
   if (!p) return fail(LBDPS_E_INVALID, "params is NULL");
   if (p->nx < 3 || p->ny < 3) return fail(LBDPS_E_SHAPE, "nx and ny must be >= 3");
-  if ((long long)p->nx * p->ny >= 0x7fffffffll) return fail(LBDPS_E_SHAPE, "nx * ny must be < 2^31 - 1");
+  if ((long long)p->nx * p->ny >= (1ll << 29)) return fail(LBDPS_E_SHAPE, "nx * ny must be < 2^29");
   for (int i = 0; i < 4; ++i)
     if (p->bc[i] < 0 || p->bc[i] > 3) return fail(LBDPS_E_INVALID, "bc values must be 0..3");
   if (p->bc[0] > 1 || p->bc[1] > 1) return fail(LBDPS_E_INVALID, "x faces must be PERIODIC or WALL");
@@ -609,8 +609,9 @@ lbdps_status lbdps_validate_params(const lbdps_params *p, int64_t max_particles)
   if (p->cs_smag != 0.0) return fail(LBDPS_E_UNSUPPORTED, "Smagorinsky LES (cs_smag > 0) is not supported");
   if (p->precision < 0 || p->precision > 3) return fail(LBDPS_E_INVALID, "precision must be 0..3");
   if (p->diagnostics < 0 || p->diagnostics > 1) return fail(LBDPS_E_INVALID, "diagnostics must be 0 or 1");
-  if (max_particles < 0 || max_particles > 0x7fffffffll)
-    return fail(LBDPS_E_SHAPE, "max_particles must be in [0, 2^31 - 1]");
+  // below 2^29: every per-particle and per-cell array is addressed by 32-bit byte offsets
+  if (max_particles < 0 || max_particles >= (1ll << 29))
+    return fail(LBDPS_E_SHAPE, "max_particles must be in [0, 2^29)");
   return LBDPS_OK;
 }
 

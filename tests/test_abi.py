@@ -156,3 +156,14 @@ def test_cell_row_by_multiplication_is_exact():
         for key in keys:
             if 0 <= key < 2 ** 31:
                 assert (key * m) >> s == key // nx, (nx, key)
+
+
+def test_size_limits_for_32_bit_offsets():
+    """Arrays are addressed by 32-bit byte offsets: fewer than 2^29 particles and cells."""
+    p = L.make_params(synth.bubble_small())
+    assert _status(p, (1 << 29) - 1) == L.LBDPS_OK
+    assert _status(p, 1 << 29) == L.LBDPS_E_SHAPE
+    p.nx, p.ny = 1 << 15, 1 << 14  # exactly 2^29 cells
+    assert _status(p) == L.LBDPS_E_SHAPE
+    p.ny = (1 << 14) - 1
+    assert _status(p) == L.LBDPS_OK, L.lbdps_last_error()
