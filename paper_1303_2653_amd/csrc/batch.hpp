@@ -67,7 +67,7 @@ __global__ __launch_bounds__(BLOCK) void kb_collide(const BedArgs<P> *__restrict
 }
 
 template <int P>
-__global__ __launch_bounds__(BLOCK) void kb_drag(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
+__global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void kb_drag(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                  int nbeds, int flip) {
   LBDPS_BED_PROLOGUE(XCD_RUN_DRAG)
   drag_body<P>(bid, nbk, a.parts(cp), a.fl, a.cs, a.lut, a.k, a.count, a.rank, a.flags, nullptr, nullptr, nullptr,
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(BLOCK) void kb_scatter(const BedArgs<P> *__restrict
 
 // After the scatter the records are in the other set.
 template <int P>
-__global__ __launch_bounds__(BLOCK) void kb_contacts(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
+__global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void kb_contacts(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                      int nbeds, int flip) {
   LBDPS_BED_PROLOGUE(XCD_RUN_CONTACTS)
   contacts_body<P>(bid, nbk, a.parts(1 - cp), a.cs, a.k, a.adj, a.deg, a.done, a.ticket, a.flags, a.pair_part,

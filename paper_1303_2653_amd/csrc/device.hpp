@@ -12,6 +12,13 @@ constexpr int KMAX = 32;      // contacts stored per particle
 constexpr int BLOCK = 256;    // threads per workgroup (4 waves)
 constexpr int LUT_W = 12;     // columns of the per-count table
 
+// Eight wavefronts per SIMD (at most 64 VGPRs) for the drag and contact
+// kernels: they are bound by memory round trips, and one more resident
+// wavefront per SIMD hides more of them than the registers it costs (5 % and
+// 3 % on a 16 M-particle bed).  The cluster kernel spills at 64 VGPRs and
+// runs slower, so it keeps its own register count.
+#define LBDPS_WAVES8 __attribute__((amdgpu_waves_per_eu(8, 8)))
+
 // The launch's workgroups are dealt to the chip's eight XCDs in turn (dispatch
 // index i runs on XCD i mod 8), and each XCD has an L2 of its own.
 // xcd_block<R> maps the dispatch index to a tile index so that each XCD takes

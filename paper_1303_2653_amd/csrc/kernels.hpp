@@ -39,10 +39,13 @@ __device__ __forceinline__ typename Prec<P>::T feq_v(int i, typename Prec<P>::T 
 __device__ __forceinline__ int wrap_i(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // Node index for interpolation and gradients: wrap on periodic axes, clamp
-// otherwise (node (i, j) sits at the cell centre (i + 1/2, j + 1/2)).
+// otherwise (node (i, j) sits at the cell centre (i + 1/2, j + 1/2)).  For
+// i >= -n; the remainder is taken only beyond 2n (lattices narrower than a
+// drag tile).
 __device__ __forceinline__ int node_idx(int i, int n, int per) {
-  if (per) return ((i % n) + n) % n;
-  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+  if (!per) return i < 0 ? 0 : (i >= n ? n - 1 : i);
+  if (i < 0) return i + n;
+  return i < n ? i : (i - n < n ? i - n : i % n);
 }
 
 template <int P> struct Pos {
@@ -649,24 +652,39 @@ template <int P> struct DragTile {
     T ux[R], uy[R], beta[R], es[R], re[R], rw[R], rn[R], rs[R];
   };
   __device__ static void fetch(const Consts<T> &k, const Fields<T> &fl, int tx0, int ty0, Regs &g) {
+    // the tile and its two-node border inside the lattice: no wrapping or clamping
+    const bool inner = tx0 >= 2 && tx0 + DTX + 2 <= k.nx && ty0 >= 2 && ty0 + DTY + 2 <= k.ny;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int q = threadIdx.x + r * BLOCK;
       if (q < DSN) {
-        const int i = node_idx(tx0 - 1 + q % DSX, k.nx, k.per_x);
-        const int j = node_idx(ty0 - 1 + q / DSX, k.ny, k.per_y);
-        const size_t c = (size_t)j * k.nx + i;
-        g.ux[r] = fl.ugx[c];
-        g.uy[r] = fl.ugy[c];
-        g.beta[r] = fl.beta[c];
-        g.es[r] = fl.es[c];
-        // central differences of p = rho / 3, boundary value as the ghost beyond a wall
-        const int ie = node_idx(i + 1, k.nx, k.per_x), iw = node_idx(i - 1, k.nx, k.per_x);
-        const int jn = node_idx(j + 1, k.ny, k.per_y), js = node_idx(j - 1, k.ny, k.per_y);
-        g.re[r] = fl.rho[(size_t)j * k.nx + ie];
-        g.rw[r] = fl.rho[(size_t)j * k.nx + iw];
-        g.rn[r] = fl.rho[(size_t)jn * k.nx + i];
-        g.rs[r] = fl.rho[(size_t)js * k.nx + i];
+        const int x = tx0 - 1 + q % DSX, y = ty0 - 1 + q / DSX;
+        int c, ie, iw, jn, js;
+        if (inner) {
+          c = y * k.nx + x;
+          ie = c + 1;
+          iw = c - 1;
+          jn = c + k.nx;
+          js = c - k.nx;
+        } else {
+          const int i = node_idx(x, k.nx, k.per_x), j = node_idx(y, k.ny, k.per_y);
+          const int row = j * k.nx;
+          c = row + i;
+          // the boundary value serves as the ghost beyond a wall
+          ie = row + node_idx(i + 1, k.nx, k.per_x);
+          iw = row + node_idx(i - 1, k.nx, k.per_x);
+          jn = node_idx(j + 1, k.ny, k.per_y) * k.nx + i;
+          js = node_idx(j - 1, k.ny, k.per_y) * k.nx + i;
+        }
+        g.ux[r] = ldu(fl.ugx, c);
+        g.uy[r] = ldu(fl.ugy, c);
+        g.beta[r] = ldu(fl.beta, c);
+        g.es[r] = ldu(fl.es, c);
+        // central differences of p = rho / 3
+        g.re[r] = ldu(fl.rho, ie);
+        g.rw[r] = ldu(fl.rho, iw);
+        g.rn[r] = ldu(fl.rho, jn);
+        g.rs[r] = ldu(fl.rho, js);
       }
     }
   }
@@ -861,7 +879,7 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
   }
 }
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k_drag(Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
+__global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void k_drag(Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
                                                 const int32_t *__restrict__ cs,
                                                 const typename Prec<P>::T *__restrict__ lut,
                                                 Consts<typename Prec<P>::T> k, int32_t *__restrict__ count,
@@ -1106,7 +1124,7 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
   }
 }
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k_contacts(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
+__global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void k_contacts(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
                                                     Consts<typename Prec<P>::T> k, Adj adj,
                                                     int32_t *__restrict__ deg, int32_t *__restrict__ done,
                                                     int32_t *ticket, int32_t *flags, long long *pair_part,
