@@ -1223,64 +1223,81 @@ struct LdsColumn {  // entry i of a lane's column of a [CL_LDS][BLOCK] LDS array
   __device__ long long &operator[](int i) const { return p[i * BLOCK]; }
 };
 
-// Gathers the cluster of candidate slot s (index g) into q[0 .. m) as
-// (index << 32 | slot) and returns m; returns 0 if a member has a lower index
-// than g, and -1 if the cluster has more than cap members.  Members are
-// expanded two at a time, so the rows of both are loaded together.
+// A gathered member is stored as (index << 32 | pos << 29 | slot): pos is its
+// place in the breadth-first order (slots are below 2^29), so ordering the
+// entries orders the members by index and each keeps its place.  The cluster's
+// contacts are kept as an 8 x 8 bit matrix over those places (bit 8 a + b:
+// places a and b touch); every contact of a member is inside the cluster, so
+// the matrix holds each member's whole neighbour list.
+constexpr long long CL_POS = 7ll << 29;
+static_assert(CL_LDS <= 8, "places of the members fit in three bits");
+__device__ __forceinline__ unsigned long long cl_bit(int a, int b) { return 1ull << (8 * a + b); }
+
+// Gathers the cluster of candidate slot s (index g) into q[0 .. m) and its
+// contacts into A; returns m, 0 if a member has a lower index than g, and -1
+// if the cluster has more than cap members.  Members are expanded two at a
+// time, so the rows of both are loaded together.
 template <class Row>
 __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, Adj adj,
-                                              const int32_t *__restrict__ deg) {
+                                              const int32_t *__restrict__ deg, unsigned long long &A) {
   q[0] = ((long long)g << 32) | (unsigned)s;
+  A = 0;
   int m = 1;
-  // adds the neighbours of one member; false when the candidate gives up
-  auto expand = [&](const AdjRow &ru, int du, const Dense4 &e4, int &res) {
+  // adds the contacts of the member at place h; false when the candidate gives up
+  auto expand = [&](int h, const AdjRow &ru, int du, const Dense4 &e4, int &res) {
     for (int a = 0; a < du; ++a) {
       const long long e = a < ADJ_IN ? e4.get(a) : ru[a];
       if ((int)(e >> 32) < g) {
         res = 0;
         return false;
       }
-      bool seen = false;
-      for (int i = 0; i < m; ++i) seen |= q[i] == e;
-      if (seen) continue;
-      if (m == cap) {
-        res = -1;
-        return false;
+      int p = -1;
+      for (int i = 0; i < m; ++i)
+        if ((q[i] & ~CL_POS) == e) p = i;
+      if (p < 0) {
+        if (m == cap) {
+          res = -1;
+          return false;
+        }
+        p = m;
+        q[m] = e | ((long long)m << 29);
+        ++m;
       }
-      q[m] = e;
-      ++m;
+      A |= cl_bit(h, p) | cl_bit(p, h);
     }
     return true;
   };
   for (int head = 0; head < m;) {
     const bool two = head + 1 < m;
-    const int u0 = (int)(q[head] & 0xffffffffll);
-    const int u1 = two ? (int)(q[head + 1] & 0xffffffffll) : u0;
+    const int u0 = (int)(q[head] & 0x1fffffffll);
+    const int u1 = two ? (int)(q[head + 1] & 0x1fffffffll) : u0;
     const AdjRow r0 = adj.row(u0), r1 = adj.row(u1);
     const int d0 = min(ldu(deg, u0), KMAX), d1 = two ? min(ldu(deg, u1), KMAX) : 0;
     // the dense parts of both rows
     const Dense4 f(r0.a), h(r1.a);
     int res = 0;
-    if (!expand(r0, d0, f, res)) return res;
-    if (!expand(r1, d1, h, res)) return res;
+    if (!expand(head, r0, d0, f, res)) return res;
+    if (two && !expand(head + 1, r1, d1, h, res)) return res;
     head += two ? 2 : 1;
   }
   return m;
 }
 
 // Orders the gathered members by index and applies the cluster's pairs in
-// lexicographic order: member u (ascending) meets its higher-index neighbours
-// in ascending order, with u's velocity kept in registers over its pairs.
-// Every pair with u as the higher index came before, and none follows, so u's
-// wall pass runs right after its own pairs.  The records of the neighbours in
-// the dense part of u's row are all loaded before the first of u's pairs: they
-// are distinct particles, so none of those pairs changes another's record.
+// lexicographic order: member i (ascending) meets its higher-index neighbours
+// in ascending order, with its velocity kept in registers over its pairs.
+// Every pair with it as the higher index came before, and none follows, so
+// its wall pass runs right after its own pairs.  The neighbours come from the
+// contact matrix, so no row is read again: one round of loads per member
+// brings its record and those of its higher neighbours (distinct particles,
+// so none of its pairs changes another's record).
 template <int P, class Row>
-__device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typename Prec<P>::T> &k,
-                                                Parts<typename Prec<P>::T> &pt, Adj adj,
-                                                const int32_t *__restrict__ deg, int32_t *done, long long &ncoll,
+__device__ __forceinline__ void resolve_cluster(Row q, int m, unsigned long long A,
+                                                const Consts<typename Prec<P>::T> &k,
+                                                Parts<typename Prec<P>::T> &pt, int32_t *done, long long &ncoll,
                                                 long long &nwall) {
   using T = typename Prec<P>::T;
+  constexpr int NB = 4;  // higher neighbours loaded together
   for (int i = 1; i < m; ++i) {
     const long long e = q[i];
     int j = i - 1;
@@ -1291,57 +1308,53 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, const Consts<typen
     q[j + 1] = e;
   }
   for (int i = 0; i < m; ++i) {
-    const int u = (int)(q[i] & 0xffffffffll), gu = (int)(q[i] >> 32);
-    const AdjRow ru = adj.row(u);
-    const int dgu = ldu(deg, u), du = min(dgu, KMAX);
-    const Dense4 e4(ru.a);  // the dense part of the row
+    const long long qi = q[i];
+    const int u = (int)(qi & 0x1fffffffll);
+    const unsigned nbr = (unsigned)(A >> (8 * (int)((qi >> 29) & 7))) & 0xffu;  // places of u's neighbours
     const int ku = ldu(pt.key, u);
     const T xu = ldu(pt.px, u), yu = ldu(pt.py, u);
     T vxu = ldu(pt.vx, u), vyu = ldu(pt.vy, u);
-    int w[ADJ_IN], kw[ADJ_IN];
-    bool up[ADJ_IN];
-    T xw[ADJ_IN], yw[ADJ_IN], vxw[ADJ_IN], vyw[ADJ_IN];
+    int j = i + 1;  // next member (in index order) to look at
+    while (true) {
+      // the next NB higher neighbours, in index order, loaded together
+      int w[NB], kw[NB];
+      T xw[NB], yw[NB], vxw[NB], vyw[NB];
+      int nw = 0;
+      for (; j < m && nw < NB; ++j) {
+        const long long qj = q[j];
+        if (nbr >> (int)((qj >> 29) & 7) & 1u) {
 #pragma unroll
-    for (int a = 0; a < ADJ_IN; ++a) {
-      const long long e = e4.get(a);  // a is a constant here
-      up[a] = a < du && (int)(e >> 32) > gu;
-      w[a] = up[a] ? (int)(e & 0xffffffffll) : u;
-      if (up[a]) {
-        kw[a] = ldu(pt.key, w[a]);
-        xw[a] = ldu(pt.px, w[a]);
-        yw[a] = ldu(pt.py, w[a]);
-        vxw[a] = ldu(pt.vx, w[a]);
-        vyw[a] = ldu(pt.vy, w[a]);
+          for (int b = 0; b < NB; ++b)
+            if (b == nw) w[b] = (int)(qj & 0x1fffffffll);
+          ++nw;
+        }
       }
-    }
 #pragma unroll
-    for (int a = 0; a < ADJ_IN; ++a) {
-      if (!up[a]) continue;
-      T dx, dy;
-      Pos<P>::sep(k, ku, xu, yu, kw[a], xw[a], yw[a], dx, dy);
-      if (pair_core<P>(k, dx, dy, vxu, vyu, vxw[a], vyw[a])) {
-        pt.vx[w[a]] = vxw[a];
-        pt.vy[w[a]] = vyw[a];
-        ++ncoll;
-      }
-    }
-    for (int a = ADJ_IN; a < du; ++a) {
-      const long long e = ru[a];
-      if ((int)(e >> 32) <= gu) continue;
-      const int x = (int)(e & 0xffffffffll);
-      T dx, dy;
-      Pos<P>::sep(k, ku, xu, yu, ldu(pt.key, x), ldu(pt.px, x), ldu(pt.py, x), dx, dy);
-      T vx = ldu(pt.vx, x), vy = ldu(pt.vy, x);
-      if (pair_core<P>(k, dx, dy, vxu, vyu, vx, vy)) {
-        pt.vx[x] = vx;
-        pt.vy[x] = vy;
-        ++ncoll;
-      }
+      for (int b = 0; b < NB; ++b)
+        if (b < nw) {
+          kw[b] = ldu(pt.key, w[b]);
+          xw[b] = ldu(pt.px, w[b]);
+          yw[b] = ldu(pt.py, w[b]);
+          vxw[b] = ldu(pt.vx, w[b]);
+          vyw[b] = ldu(pt.vy, w[b]);
+        }
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (b < nw) {
+          T dx, dy;
+          Pos<P>::sep(k, ku, xu, yu, kw[b], xw[b], yw[b], dx, dy);
+          if (pair_core<P>(k, dx, dy, vxu, vyu, vxw[b], vyw[b])) {
+            pt.vx[w[b]] = vxw[b];
+            pt.vy[w[b]] = vyw[b];
+            ++ncoll;
+          }
+        }
+      if (j >= m) break;
     }
     nwall += Pos<P>::walls_key(k, ku, xu, yu, vxu, vyu);
     pt.vx[u] = vxu;
     pt.vy[u] = vyu;
-    done[u] = dgu;
+    done[u] = __builtin_popcount(nbr);  // its contacts, all inside the cluster
   }
 }
 
@@ -1601,9 +1614,10 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
     }
     const long long r = roots[(size_t)(b0 + lo) * BLOCK + (f - pre[lo])];
     const int s = (int)(r & 0xffffffffll), g = (int)(r >> 32);
-    int m = gather_cluster(ql, CL_LDS, s, g, adj, deg);
+    unsigned long long A;
+    int m = gather_cluster(ql, CL_LDS, s, g, adj, deg, A);
     if (m > 0) {
-      resolve_cluster<P>(ql, m, k, pt, adj, deg, done, ncoll, nwall);
+      resolve_cluster<P>(ql, m, A, k, pt, done, ncoll, nwall);
     } else if (m < 0) {
       const int slot = atomicAdd(&nbig, 1);  // the workgroup resolves it below
       if (slot < BIG_LIST) bigc[slot] = r;
