@@ -725,9 +725,10 @@ template <int P> struct Interp {
   }
 };
 
-// Workgroup = one DTX x DTY tile of cells, one thread per cell.
+// Workgroup = one DTX x DTY tile of cells, one thread per cell (its particles
+// in registers up to SEG_REG of them, in two passes over memory beyond).
 template <int P>
-__device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
+__device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
     Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs, const typename Prec<P>::T *__restrict__ lut,
     Consts<typename Prec<P>::T> k, int32_t *__restrict__ count, int32_t *__restrict__ rank, int32_t *flags,
     typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy, long long *zero_part, TileSums ts,
@@ -878,15 +879,246 @@ __device__ __forceinline__ void drag_body(const int bidx, const int gdim, Parts<
     if (threadIdx.x == 0) zero_part[bidx] = t;
   }
 }
+// Workgroup = one DTX x DTY tile of cells.  One thread per cell stages the
+// tile; the particles of the tile are then dealt out flat, particle k of the
+// tile (in cell order) to thread k mod BLOCK, so that every thread carries one
+// to DR_PT particles whatever the spread of the per-cell counts.  Eq. 27's
+// cell sums are taken by the cell's own thread from LDS in segment order, so
+// every result equals the one-thread-per-cell evaluation bit for bit.  A tile
+// holding more than DR_PT BLOCK particles runs one thread per cell instead.
+constexpr int DR_PT = 3, DR_CAP = DR_PT * BLOCK;
+
 template <int P>
-__global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void k_drag(Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
-                                                const int32_t *__restrict__ cs,
-                                                const typename Prec<P>::T *__restrict__ lut,
-                                                Consts<typename Prec<P>::T> k, int32_t *__restrict__ count,
-                                                int32_t *__restrict__ rank, int32_t *flags,
-                                                typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy,
-                                                long long *zero_part, TileSums ts, int32_t *__restrict__ stay) {
-  drag_body<P>(xcd_block<XCD_RUN_DRAG>(blockIdx.x, gridDim.x), gridDim.x, pt, fl, cs, lut, k, count, rank, flags, dg_fdx, dg_fdy, zero_part, ts, stay);
+__device__ __forceinline__ void drag_body_flat(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
+    Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs, const typename Prec<P>::T *__restrict__ lut,
+    Consts<typename Prec<P>::T> k, int32_t *__restrict__ count, int32_t *__restrict__ rank, int32_t *flags,
+    typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy, long long *zero_part, TileSums ts,
+    int32_t *__restrict__ stay) {
+  using T = typename Prec<P>::T;
+  __shared__ long long sh[BLOCK / 64];
+  __shared__ int shi[BLOCK / 64];
+  __shared__ int hist[HIST_MAX];
+  __shared__ DragTile<P> D;
+  __shared__ int f_off[BLOCK + 1];   // first flat index of each cell's particles
+  __shared__ int f_base[BLOCK];      // slot of flat index j of cell i: f_base[i] + j
+  __shared__ short f_cell[DR_CAP];   // cell of each flat index
+  __shared__ T f_px[DR_CAP], f_py[DR_CAP];  // pre-drags, then each cell's sums at its first index
+  __shared__ unsigned char f_stays[DR_CAP];
+  const int ntx = (k.nx + DTX - 1) / DTX;
+  const int tx0 = (bidx % ntx) * DTX, ty0 = (bidx / ntx) * DTY;
+  const int cx = tx0 + (int)threadIdx.x % DTX, cy = ty0 + (int)threadIdx.x / DTX;
+  const int c = cy * k.nx + cx;
+  const bool inside = cx < k.nx && cy < k.ny;
+  const int a0 = inside ? cs[c] : 0, a1 = inside ? cs[c + 1] : 0;
+  const int n = a1 - a0;
+  typename DragTile<P>::Regs tile_regs;
+  DragTile<P>::fetch(k, fl, tx0, ty0, tile_regs);
+  // a tile without particles has nothing to do
+  if (!__syncthreads_or(n > 0)) {
+    if (inside) stay[c] = 0;
+    if (zero_part && threadIdx.x == 0) zero_part[bidx] = 0;
+    return;
+  }
+  D.store(tile_regs);
+  // scan tiles the new cells of this tile's particles can fall in (one cell
+  // move at most, periodic jumps go straight to the global counters)
+  const int klo = max(0, (ty0 - 1) * k.nx + tx0 - 1);
+  const int khi = min(k.C - 1, (ty0 + DTY) * k.nx + tx0 + DTX);
+  const int tlo = klo >> ts.shift, nh = (khi >> ts.shift) - tlo + 1;
+  if (threadIdx.x < HIST_MAX) hist[threadIdx.x] = 0;
+  long long nzero = 0;
+  // Eq. 28 for one particle of cell (pcx, pcy) = pc holding np particles, then
+  // Eq. 16: v <- v + g_eff + (F_d + s V_p grad p) / m, P <- P + v, and the
+  // particle's new cell.
+  auto finish = [&](int s, int pcx, int pcy, int pc, int np, T fgx, T fgy, T prx, T pry, T gpx, T gpy, T Sx, T Sy,
+                    T x, T y, T vx, T vy) -> int {
+    T fdx, fdy;
+    if (Sx == (T)0)
+      fdx = dv<P>(-fgx, (T)np);
+    else if (k.drag_abs)
+      fdx = dv<P>(fabs(fgx), fabs(Sx)) * prx;
+    else
+      fdx = dv<P>(-fgx * prx, Sx);
+    if (Sy == (T)0)
+      fdy = dv<P>(-fgy, (T)np);
+    else if (k.drag_abs)
+      fdy = dv<P>(fabs(fgy), fabs(Sy)) * pry;
+    else
+      fdy = dv<P>(-fgy * pry, Sy);
+    const T ax = k.geff[0] + dv<P>(fdx + k.fp * gpx, k.m);
+    const T ay = k.geff[1] + dv<P>(fdy + k.fp * gpy, k.m);
+    vx = vx + ax;
+    vy = vy + ay;
+    int nk = Pos<P>::move(k, pcx, pcy, x, y, vx, vy);
+    if (nk < 0) {
+      atomicOr(&flags[FLAG_DOMAIN], 1);
+      nk = pc;
+    }
+    pt.key[s] = nk;
+    pt.px[s] = x;
+    pt.py[s] = y;
+    pt.vx[s] = vx;
+    pt.vy[s] = vy;
+    if (dg_fdx) {
+      const int id = pt.pid[s];
+      dg_fdx[id] = fdx;
+      dg_fdy[id] = fdy;
+    }
+    return nk;
+  };
+  // The new cell's count: a particle that stays takes the given rank among its
+  // cell's stayers (segment order); one that moves counts atomically among the
+  // arrivals of its new cell, which come after that cell's stayers.
+  auto count_new = [&](int s, int nk, bool stays, int stay_rank) {
+    if (stays) rank[s] = stay_rank;
+    else rank[s] = atomicAdd(&count[nk], 1) | RANK_MOVED;
+    const int dt = (nk >> ts.shift) - tlo;
+    if (nh <= HIST_MAX && dt >= 0 && dt < nh)
+      atomicAdd(&hist[dt], 1);
+    else
+      ts.add(nk >> ts.shift, 1);
+  };
+  int ptot;
+  const int off = block_excl_scan(n, shi, ptot);  // uniform ptot; its barriers order the tile and hist
+  if (ptot <= DR_CAP) {
+    // ---- flat: particle k of the tile to thread k mod BLOCK
+    f_off[threadIdx.x] = off;
+    if (threadIdx.x == 0) f_off[BLOCK] = ptot;
+    f_base[threadIdx.x] = a0 - off;
+    for (int u = 0; u < n; ++u) f_cell[off + u] = (short)threadIdx.x;
+    __syncthreads();
+    // pre-drags (Eq. 26); the records are read again after the cell sums
+    int pcl[DR_PT];
+    T prx[DR_PT], pry[DR_PT], gpx[DR_PT], gpy[DR_PT];
+#pragma unroll
+    for (int j = 0; j < DR_PT; ++j) {
+      const int q = (int)threadIdx.x + j * BLOCK;
+      if (q < ptot) {
+        const int cl = f_cell[q];
+        const int s = f_base[cl] + q;
+        pcl[j] = cl;
+        const T vx = ldu(pt.vx, s), vy = ldu(pt.vy, s);
+        Interp<P> I;
+        I.at(k, D, tx0, ty0, tx0 + cl % DTX, ty0 + cl / DTX, ldu(pt.px, s), ldu(pt.py, s));
+        prx[j] = dv<P>(k.vp * I.beta, I.es) * (I.ux - vx);
+        pry[j] = dv<P>(k.vp * I.beta, I.es) * (I.uy - vy);
+        gpx[j] = I.gpx;
+        gpy[j] = I.gpy;
+        f_px[q] = prx[j];
+        f_py[q] = pry[j];
+      }
+    }
+    __syncthreads();
+    // Eq. 27: the cell's sums in segment order, left at its first flat index
+    if (n > 0) {
+      T Sx = (T)0, Sy = (T)0;
+      for (int u = 0; u < n; ++u) {
+        Sx += f_px[off + u];
+        Sy += f_py[off + u];
+      }
+      nzero = (Sx == (T)0) + (Sy == (T)0);
+      f_px[off] = Sx;
+      f_py[off] = Sy;
+    }
+    __syncthreads();
+    int nk[DR_PT];
+#pragma unroll
+    for (int j = 0; j < DR_PT; ++j) {
+      const int q = (int)threadIdx.x + j * BLOCK;
+      if (q < ptot) {
+        const int cl = pcl[j], o = f_off[cl], s = f_base[cl] + q;
+        const int pcx = tx0 + cl % DTX, pcy = ty0 + cl / DTX, pc = pcy * k.nx + pcx;
+        nk[j] = finish(s, pcx, pcy, pc, f_off[cl + 1] - o, ldu(fl.fpgx, pc), ldu(fl.fpgy, pc), prx[j], pry[j],
+                       gpx[j], gpy[j], f_px[o], f_py[o], ldu(pt.px, s), ldu(pt.py, s), ldu(pt.vx, s), ldu(pt.vy, s));
+        f_stays[q] = nk[j] == pc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < DR_PT; ++j) {
+      const int q = (int)threadIdx.x + j * BLOCK;
+      if (q < ptot) {
+        const bool st = f_stays[q];
+        int r = 0;
+        if (st)
+          for (int t = f_off[pcl[j]]; t < q; ++t) r += f_stays[t];
+        count_new(f_base[pcl[j]] + q, nk[j], st, r);
+      }
+    }
+    if (inside) {
+      int ns = 0;
+      for (int u = 0; u < n; ++u) ns += f_stays[off + u];
+      stay[c] = ns;
+    }
+  } else {
+    // ---- one thread per cell (a tile denser than the flat capacity): two
+    // passes over the cell's segment, the sums first
+    int nstay = 0;
+    if (inside) {
+      if (n > 0) {
+        const T fgx = fl.fpgx[c], fgy = fl.fpgy[c];
+        T Sx = (T)0, Sy = (T)0;
+        for (int s = a0; s < a1; ++s) {
+          Interp<P> I;
+          I.at(k, D, tx0, ty0, cx, cy, pt.px[s], pt.py[s]);
+          Sx += dv<P>(k.vp * I.beta, I.es) * (I.ux - pt.vx[s]);
+          Sy += dv<P>(k.vp * I.beta, I.es) * (I.uy - pt.vy[s]);
+        }
+        nzero = (Sx == (T)0) + (Sy == (T)0);
+        for (int s = a0; s < a1; ++s) {
+          Interp<P> I;
+          const T x = pt.px[s], y = pt.py[s], vx = pt.vx[s], vy = pt.vy[s];
+          I.at(k, D, tx0, ty0, cx, cy, x, y);
+          const T prx = dv<P>(k.vp * I.beta, I.es) * (I.ux - vx);
+          const T pry = dv<P>(k.vp * I.beta, I.es) * (I.uy - vy);
+          const int nk = finish(s, cx, cy, c, n, fgx, fgy, prx, pry, I.gpx, I.gpy, Sx, Sy, x, y, vx, vy);
+          const bool st = nk == c;
+          count_new(s, nk, st, nstay);
+          nstay += st;
+        }
+      }
+      stay[c] = nstay;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < min(nh, HIST_MAX)) {
+    const int h = hist[threadIdx.x];
+    if (h) ts.add(tlo + (int)threadIdx.x, h);
+  }
+  if (zero_part) {
+    const long long t = block_sum_ll(nzero, sh);
+    if (threadIdx.x == 0) zero_part[bidx] = t;
+  }
+}
+// Two forms: one thread per cell, for grids that fit on the chip in one round
+// (the step is then one chain of round trips, and the flat form's extra
+// barriers lengthen it); the flat form for larger grids, where the even
+// per-thread work pays: 22 % faster on a 16 M-particle bed, 16 % on a batch of
+// 64 uneven beds.
+template <int P>
+__global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void k_drag(Parts<typename Prec<P>::T> pt,
+                                                             Fields<typename Prec<P>::T> fl,
+                                                             const int32_t *__restrict__ cs,
+                                                             const typename Prec<P>::T *__restrict__ lut,
+                                                             Consts<typename Prec<P>::T> k,
+                                                             int32_t *__restrict__ count, int32_t *__restrict__ rank,
+                                                             int32_t *flags, typename Prec<P>::T *dg_fdx,
+                                                             typename Prec<P>::T *dg_fdy, long long *zero_part,
+                                                             TileSums ts, int32_t *__restrict__ stay) {
+  drag_body_cells<P>(xcd_block<XCD_RUN_DRAG>(blockIdx.x, gridDim.x), gridDim.x, pt, fl, cs, lut, k, count, rank,
+                     flags, dg_fdx, dg_fdy, zero_part, ts, stay);
+}
+template <int P>
+__global__ __launch_bounds__(BLOCK) LBDPS_WAVES6 void k_drag_flat(Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
+                                                     const int32_t *__restrict__ cs,
+                                                     const typename Prec<P>::T *__restrict__ lut,
+                                                     Consts<typename Prec<P>::T> k, int32_t *__restrict__ count,
+                                                     int32_t *__restrict__ rank, int32_t *flags,
+                                                     typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy,
+                                                     long long *zero_part, TileSums ts,
+                                                     int32_t *__restrict__ stay) {
+  drag_body_flat<P>(xcd_block<XCD_RUN_DRAG>(blockIdx.x, gridDim.x), gridDim.x, pt, fl, cs, lut, k, count, rank,
+                    flags, dg_fdx, dg_fdy, zero_part, ts, stay);
 }
 
 // ------------------------------------------------------------------ A1: binning (counting sort by cell)

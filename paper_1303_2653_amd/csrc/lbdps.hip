@@ -30,6 +30,10 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int NB_CONS = 512;  // workgroups of the conservation reductions
 
 int nblocks(long long n) { return (int)((n + BLOCK - 1) / BLOCK); }
+// The drag kernel's flat form pays once the grid needs more than one round of
+// resident workgroups (about 8 per CU on 256 CUs).
+constexpr int DRAG_FLAT_MIN = 2048;
+bool drag_flat(long long tiles) { return tiles > DRAG_FLAT_MIN; }
 // Workgroups of the cluster resolution for n particles: each takes at least
 // `lists` of the contact kernel's candidate lists and at most BLOCK; at most
 // `groups_max` workgroups unless more are needed for that.
@@ -461,9 +465,15 @@ template <int P> struct Impl {
       tstop(x, LBDPS_K_COLLIDE);
       if (x->n > 0) {
         tstart(x, LBDPS_K_DRAG);
-        hipLaunchKernelGGL(k_drag<P>, dim3(drag_tiles(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x),
-                           x->cs, (const T *)x->lut, k, x->count, x->rank, x->flags, dg ? (T *)x->dg_fdx : nullptr,
-                           dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x), x->stay);
+        const int nt = drag_tiles(x);
+        if (drag_flat(nt))
+          hipLaunchKernelGGL(k_drag_flat<P>, dim3(nt), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x), x->cs,
+                             (const T *)x->lut, k, x->count, x->rank, x->flags, dg ? (T *)x->dg_fdx : nullptr,
+                             dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x), x->stay);
+        else
+          hipLaunchKernelGGL(k_drag<P>, dim3(nt), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x), x->cs,
+                             (const T *)x->lut, k, x->count, x->rank, x->flags, dg ? (T *)x->dg_fdx : nullptr,
+                             dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x), x->stay);
         tstop(x, LBDPS_K_DRAG);
         sort_counted(x);
         hard_spheres(x);
@@ -1089,7 +1099,11 @@ template <int P> struct BatchImpl {
       LBDPS_LAUNCH(kb_collide, PH_COLLIDE)
       bstop(B, timing, LBDPS_K_COLLIDE);
       bstart(B, timing, LBDPS_K_DRAG);
-      LBDPS_LAUNCH(kb_drag, PH_DRAG)
+      if (drag_flat(tot[PH_DRAG])) {
+        LBDPS_LAUNCH(kb_drag_flat, PH_DRAG)
+      } else {
+        LBDPS_LAUNCH(kb_drag, PH_DRAG)
+      }
       bstop(B, timing, LBDPS_K_DRAG);
       bstart(B, timing, LBDPS_K_SCAN);
       LBDPS_LAUNCH(kb_scan, PH_SCAN)

@@ -383,6 +383,28 @@ def test_launch_shapes_do_not_change_results(prec):
     assert chosen["cluster_lists"] >= 1 and chosen["cluster_groups_max"] >= 1
 
 
+def test_fp64_flat_drag_with_dense_tiles():
+    """A lattice of more than 2048 drag tiles (1024 x 520 cells), where the drag
+    kernel deals each tile's particles out flat, with a patch of 4 particles
+    per cell whose tiles exceed the flat capacity (768 particles) and take the
+    per-cell passes: two FP64 steps within 1e-12 of the oracle, pair lists
+    identical."""
+    cfg = synth.riser(nx=1024, ny=520, n=10_000, seed=9, sort_ids=False, precision="fp64")
+    u = synth.uniform(11, 2 * 4096).reshape(-1, 2)
+    patch = np.stack([400.0 + 64.0 * u[:, 0], 200.0 + 16.0 * u[:, 1]], axis=1)  # 64 x 16 cells, 4 per cell
+    pos = np.concatenate([cfg["pos"], patch])
+    cfg["pos"] = pos[synth.cell_order(pos, cfg["nx"])]
+    cfg["vel"] = (np.random.default_rng(6).random(cfg["pos"].shape) - 0.5) * 1e-2
+    gpu = L.Sim(cfg, precision="fp64", diagnostics=True)
+    ref = oracle.Sim(cfg)
+    for k in (1, 2):
+        gpu.step(1)
+        o = ref.step(record=True)
+        compare_step(gpu, o, ref, 1e-12, what=f"flat drag step {k}")
+    pairs, m = gpu.pairs()
+    assert m == len(o.pairs) and (pairs == o.pairs).all()
+
+
 def test_fp64_large_lattice():
     """A lattice of more than 512 cell-scan tiles (1100 x 1024 cells), where
     the tiles' bases are scanned in a pass of their own: two FP64 steps within
