@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "liblbdps.so")
 # written evaluation order.  Packed FP32 instructions are disabled for gfx950.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-command-line-argument"]
+         "-Wno-unused-command-line-argument", "-Wno-pass-failed"]
 
 
 def hipcc() -> str:
