@@ -1209,22 +1209,31 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
     // range away from a periodic seam; the column offset of a candidate follows
     // from the cell starts.  All starts are loaded first.
     const bool inner_x = cx >= 1 && cx + 1 < k.nx;
+    // A partner lies within d of the particle, so only the columns and rows of
+    // cells that come within d of its position can hold one: with d <= 1/2
+    // two of the three in each direction.  The margin keeps every candidate
+    // whose rounded distance test could pass (rounding of a separation is
+    // below 1e-6 at any lattice size the library accepts).
+    const T fx = Pos<P>::G ? x - (T)cx : x, fy = Pos<P>::G ? y - (T)cy : y;  // position in the cell
+    const T margin = (T)1e-5;
+    const bool use_l = fx < k.d + margin, use_r = fx > (T)1 - k.d - margin;
+    const bool use_b = fy < k.d + margin, use_t = fy > (T)1 - k.d - margin;
     int rlo[3], rm1[3], rm2[3], rhi[3];
 #pragma unroll
     for (int rw = 0; rw < 3; ++rw) {
       int yy = cy + rw - 1;
-      bool ok = true;
+      bool ok = rw == 0 ? use_b : (rw == 2 ? use_t : true);
       if (yy < 0 || yy >= k.ny) {
-        ok = k.per_y != 0;
+        ok = ok && k.per_y != 0;
         yy = wrap_i(yy, k.ny);
       }
       const int c0 = yy * k.nx + cx - 1;
       if (ok && inner_x) {
-        rlo[rw] = cs[c0];
-        rm1[rw] = cs[c0 + 1];
-        rm2[rw] = cs[c0 + 2];
-        rhi[rw] = cs[c0 + 3];
-      } else {  // a row beyond a wall (empty), or a seam column walked cell by cell below
+        rm1[rw] = ldu(cs, c0 + 1);
+        rm2[rw] = ldu(cs, c0 + 2);
+        rlo[rw] = use_l ? ldu(cs, c0) : rm1[rw];
+        rhi[rw] = use_r ? ldu(cs, c0 + 3) : rm2[rw];
+      } else {  // a row not needed or beyond a wall (empty), or a seam column walked cell by cell below
         rlo[rw] = rm1[rw] = rm2[rw] = rhi[rw] = 0;
       }
     }
