@@ -64,6 +64,15 @@ def algorithmic_bytes(kernel: str, prec: str, C: int, N: int, pairs: int) -> flo
     raise KeyError(kernel)
 
 
+# Error bounds of the storage precisions against the FP64 oracle (norm-wise
+# relative error of populations and gas fields after 10 steps from one state
+# on the 64 x 512 riser crop), asserted by tests/test_precision_study.py; the
+# measured errors are in profiles/precision_riser-crop-64x512.md.
+STATED_ERR = {p: {"bound": b, "fields": "f, rho, u_gas, F_pg, beta", "after_steps": 10,
+                  "source": "profiles/precision_riser-crop-64x512.md"}
+              for p, b in (("fp32", 2e-6), ("fp16", 1e-2), ("bf16", 1.5e-2))}
+
+
 def model_bytes_per_step(prec: str, C: int, N: int, pairs: int) -> float:
     """Whole-step byte model: 18 s_f + 16 s_c + 20 per cell, 14 s_p + 16 per
     particle, 16 + 8 s_p per contact pair."""
@@ -444,7 +453,8 @@ def main():
             rv = run_gpu(cfg, p, args.steps, args.warmup, torch, L, dominant=dom)
             sv = rv["ms"] / 1e3
             var[p] = {"MLUPS": round(C * args.steps / sv / 1e6, 2), "ms_per_step": round(rv["ms"] / args.steps, 5),
-                      "speedup_vs_fp32": round(r["ms"] / rv["ms"], 3)}
+                      "speedup_vs_fp32": round(r["ms"] / rv["ms"], 3),
+                      "stated_err_vs_fp64_oracle": STATED_ERR[p]}
         line["variants"] = var
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
