@@ -351,6 +351,23 @@ __device__ __forceinline__ long long block_excl_scan_ll(long long v, long long *
   return base + inc - v;
 }
 
+// Block-wide sums of two non-negative counts (each total below 2^31) in one
+// pass: packed as a << 32 | b, so one reduction and one pair of barriers
+// serve both.  Valid in thread 0.
+__device__ __forceinline__ void block_sum2(long long a, long long b, long long *sh, long long &ta, long long &tb) {
+  long long v = (a << 32) + b;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  long long t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < BLOCK / 64; ++w) t += sh[w];
+  __syncthreads();
+  ta = t >> 32;
+  tb = t & 0xffffffffll;
+}
+
 // Block-wide sum of a 64-bit integer (BLOCK threads), result valid in thread 0.
 __device__ __forceinline__ long long block_sum_ll(long long v, long long *sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -1356,8 +1373,8 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
   int nc;
   const int off = block_excl_scan(cand ? 1 : 0, shi, nc);
   if (cand) roots[(size_t)bidx * BLOCK + off] = ((long long)pt.pid[s] << 32) | (unsigned)s;
-  const long long t = block_sum_ll(fwd, sh);
-  const long long tw = block_sum_ll(nwall, sh);
+  long long t, tw;
+  block_sum2(fwd, nwall, sh, t, tw);
   if (threadIdx.x == 0) {
     pair_part[bidx] = t;
     wall_part[bidx] = tw;
@@ -1882,8 +1899,8 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
                                            ncoll, nwall);
     if (st == 2 && threadIdx.x == 0) atomicOr(need_sweep, 1);
   }
-  const long long tc = block_sum_ll(ncoll, sh);
-  const long long tw = block_sum_ll(nwall, sh);
+  long long tc, tw;
+  block_sum2(ncoll, nwall, sh, tc, tw);
   if (threadIdx.x == 0) {
     coll_part[bidx] = tc;
     wall_part[bidx] = tw;
