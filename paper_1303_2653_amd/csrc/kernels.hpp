@@ -1177,10 +1177,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, c
 
 // ------------------------------------------------------------------ A6: contact detection
 // One thread per particle slot.  Candidates come from the 3x3 cells around the
-// particle (d < 1 cell); a contact is a centre distance <= d (Sec. 2.2), with
-// the periodic minimum image.  Away from a periodic seam the three cells of a
-// neighbour row are one contiguous slot range, and a candidate's column offset
-// follows from the cell starts.  Each particle keeps its full neighbour list
+// particle (d < 1 cell), narrowed to the columns and rows that come within d
+// of it; a contact is a centre distance <= d (Sec. 2.2), with the periodic
+// minimum image.  Away from a periodic seam the cells of a neighbour row are
+// one contiguous slot range, and a candidate's column offset follows from the
+// cell starts.  Each particle keeps its full neighbour list
 // sorted by particle index, as 64-bit entries (index << 32 | slot).  A particle
 // without contacts gets its wall collision here; the others get it after their
 // binary collisions.
