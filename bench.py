@@ -95,7 +95,7 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None):
     breakdown = {k: ms / max(n, 1) * 1e3 for k, (ms, n) in bd.items()}  # us per launch
     if dominant is None:
         dominant = max(breakdown, key=lambda k: breakdown[k])
-    # timed region: whole steps, with only the dominant kernel bracketed by events
+    # timed region: whole steps, with only the dominant kernel's launches carrying timing events
     torch.cuda.synchronize()
     sim.time_kernels([dominant])
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -108,9 +108,8 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None):
     kt = sim.kernel_times()[dominant]
     sim.time_kernels([])
     counters = sim.counters()
-    ev_us = event_overhead_us(torch, stream)
     out = dict(ms=ms, breakdown_us=breakdown, dominant=dominant, dom_ms=kt[0], dom_launches=kt[1],
-               pairs=counters["pairs"], tuning=tuning, event_us=ev_us)
+               pairs=counters["pairs"], tuning=tuning)
     sim.close()
     return out
 
@@ -237,19 +236,6 @@ def copy_bandwidth(torch, nbytes: int, reps: int = 5) -> dict:
             "GBs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
 
 
-def event_overhead_us(torch, stream, reps: int = 200) -> float:
-    """Mean time between two timing events recorded back to back on `stream`
-    with no work between them: what each per-launch event bracket adds to a
-    kernel's own duration."""
-    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    torch.cuda.synchronize()
-    for a, b in pairs:
-        a.record(stream)
-        b.record(stream)
-    torch.cuda.synchronize()
-    return sum(a.elapsed_time(b) for a, b in pairs) / reps * 1e3
-
-
 def time_region(torch, stream, fn):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -314,9 +300,7 @@ def run_beds(args, torch, L):
     for sm in sims:
         sm.close()
     s = ms_graph / 1e3
-    ev_us = event_overhead_us(torch, st)
-    dom_bracket_us = kt[0] / max(kt[1], 1) * 1e3
-    dom_us = dom_bracket_us - ev_us
+    dom_us = kt[0] / max(kt[1], 1) * 1e3
     dom_bytes = sum(algorithmic_bytes(dom, prec, C, N, pr) for C, N, pr in zip(Cs, Ns, pairs))
     achieved = dom_bytes / (dom_us * 1e-6) / 1e9
     model = sum(model_bytes_per_step(prec, C, N, pr) for C, N, pr in zip(Cs, Ns, pairs))
@@ -335,8 +319,7 @@ def run_beds(args, torch, L):
         "kernel_us": {k: round(v, 2) for k, v in breakdown.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3),
-                     "us_event_bracket": round(dom_bracket_us, 3), "us_empty_bracket": round(ev_us, 3)},
+                     "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3)},
         "autotune": sorted({(t["cluster_lists"], t["cluster_groups_max"]) for t in tunings}),
         "batched_eager_ms_per_step": round(ms_eager / K, 5),
         "graph_first_replay_ms_per_step": round(ms_first / K, 5),
@@ -411,9 +394,8 @@ def main():
     mlups = C * args.steps / s / 1e6
     pups = N * args.steps / s
     dom = r["dominant"]
-    # the kernel's own duration: its event bracket less what an empty bracket takes
-    dom_bracket_us = r["dom_ms"] / max(r["dom_launches"], 1) * 1e3
-    dom_us = dom_bracket_us - r["event_us"]
+    # the kernel's own duration per launch, from events its dispatch stamps
+    dom_us = r["dom_ms"] / max(r["dom_launches"], 1) * 1e3
     dom_bytes = algorithmic_bytes(dom, args.precision, C, N, r["pairs"])
     achieved = dom_bytes / (dom_us * 1e-6) / 1e9
     model = model_bytes_per_step(args.precision, C, N, r["pairs"])
@@ -441,8 +423,7 @@ def main():
         "kernel_us": {k: round(v, 2) for k, v in r["breakdown_us"].items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3),
-                     "us_event_bracket": round(dom_bracket_us, 3), "us_empty_bracket": round(r["event_us"], 3)},
+                     "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3)},
     }
     cb = copy_bandwidth(torch, 1 << 30)
     line["roofline"]["copy_GBs"] = cb["GBs"]

@@ -200,16 +200,18 @@ typedef enum {
 } lbdps_kernel;
 
 /*
- * Bracket every later launch of the kernels in `mask` (bit k = lbdps_kernel k)
- * with a pair of hipEvents on the context's stream; mask 0 stops.  For
- * measurement only: the events add a little work to the stream.
+ * Time every later launch of the kernels in `mask` (bit k = lbdps_kernel k):
+ * the launch carries a pair of hipEvents that its dispatch stamps at the
+ * kernel's start and end (hipExtLaunchKernel), so the time is the kernel's own.
+ * mask 0 stops.  For measurement only; the events belong to the context.
  */
 lbdps_status lbdps_time_kernels(lbdps_ctx *ctx, uint32_t mask);
 
 /*
- * Wait for the stream, then return per kernel the summed event time in
- * milliseconds (h_ms[LBDPS_K_COUNT]) and the number of timed launches
- * (h_launches[LBDPS_K_COUNT]) since the previous call, and reset both.
+ * Wait for the stream, then return per kernel the summed time in milliseconds
+ * (h_ms[LBDPS_K_COUNT]) and the number of timed steps (h_launches[LBDPS_K_COUNT];
+ * LBDPS_K_RESOLVE sums its two launches per step) since the previous call, and
+ * reset both.
  */
 lbdps_status lbdps_kernel_times(lbdps_ctx *ctx, double *h_ms, int64_t *h_launches);
 
@@ -290,7 +292,8 @@ lbdps_status lbdps_batch_sync(lbdps_batch *batch);
 
 /* As lbdps_time_kernels / lbdps_kernel_times, for the batched launches of
  * lbdps_batch_step (each timed launch covers every bed; graph replays are not
- * timed).  LBDPS_K_RESOLVE covers both resolution launches. */
+ * timed).  LBDPS_K_RESOLVE sums both resolution launches of a step and counts
+ * them as one. */
 lbdps_status lbdps_batch_time_kernels(lbdps_batch *batch, uint32_t mask);
 lbdps_status lbdps_batch_kernel_times(lbdps_batch *batch, double *h_ms, int64_t *h_launches);
 

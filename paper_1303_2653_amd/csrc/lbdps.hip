@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "batch.hpp"
 #include "kernels.hpp"
 #include "lbdps.h"
@@ -195,6 +197,7 @@ struct lbdps_ctx {
   struct Mark {
     hipEvent_t a, b;
     int k;
+    bool extra;  // a further launch of the same phase: its time adds, its launch does not count
   };
   std::vector<Mark> marks;
   size_t nmarks = 0;
@@ -323,12 +326,40 @@ void tstart(lbdps_ctx *x, int k) {
     x->marks.push_back(m);
   }
   x->marks[x->nmarks].k = k;
+  x->marks[x->nmarks].extra = false;
   (void)hipEventRecord(x->marks[x->nmarks].a, x->stream);
 }
 void tstop(lbdps_ctx *x, int k) {
   if (!(x->timed >> k & 1u) || x->nmarks >= x->marks.size() || x->marks[x->nmarks].k != k) return;
   (void)hipEventRecord(x->marks[x->nmarks].b, x->stream);
   x->nmarks += 1;
+}
+
+// Launches a step kernel on x's stream.  When its phase k is being timed, the
+// launch carries a pair of events that the dispatch itself stamps at the
+// kernel's start and end, so the time is the kernel's own (an event pair
+// recorded around a launch also counts the queue's work between them, a few
+// microseconds).  extra: a further launch of the same phase.
+template <typename F, typename... Args>
+void tlaunch(lbdps_ctx *x, int k, bool extra, F kern, dim3 grid, Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (x->timed >> k & 1u) {
+    if (x->nmarks == x->marks.size()) {
+      lbdps_ctx::Mark m{};
+      if (hipEventCreate(&m.a) == hipSuccess && hipEventCreate(&m.b) == hipSuccess) x->marks.push_back(m);
+    }
+    if (x->nmarks < x->marks.size()) {
+      lbdps_ctx::Mark &m = x->marks[x->nmarks++];
+      m.k = k;
+      m.extra = extra;
+      a = m.a;
+      b = m.b;
+    }
+  }
+  if (a)
+    hipExtLaunchKernelGGL(kern, grid, dim3(BLOCK), 0, x->stream, a, b, 0, args...);
+  else
+    hipLaunchKernelGGL(kern, grid, dim3(BLOCK), 0, x->stream, args...);
 }
 
 lbdps_status check_hip(hipError_t e, const char *what) {
@@ -407,18 +438,18 @@ template <int P> struct Impl {
   // in one pass, then every record moves to its slot in the other storage.
   // Each cell's segment is put in particle-index order by the next collision.
   static void sort_counted(lbdps_ctx *x, bool tile_sums = true) {
-    tstart(x, LBDPS_K_SCAN);
-    if (tile_sums)
-      hipLaunchKernelGGL(k_scan_cells, dim3(x->ntiles), dim3(BLOCK), 0, x->stream, x->count, (long long)x->C,
-                         tiles(x), x->cs, x->stay);
-    else
+    if (tile_sums) {
+      tlaunch(x, LBDPS_K_SCAN, false, k_scan_cells, dim3(x->ntiles), x->count, (long long)x->C, tiles(x), x->cs,
+              (const int32_t *)x->stay);
+    } else {
+      tstart(x, LBDPS_K_SCAN);
       scan(x, x->count, x->C, x->cs, 1);
-    tstop(x, LBDPS_K_SCAN);
+      tstop(x, LBDPS_K_SCAN);
+    }
     const int N = (int)x->n;
-    tstart(x, LBDPS_K_SCATTER);
-    hipLaunchKernelGGL(k_scatter<T>, dim3(std::max(nblocks(N), 1)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
-                       parts(x, 1 - x->cp), x->rank, x->cs, N, x->slot, tiles(x), x->stay);
-    tstop(x, LBDPS_K_SCATTER);
+    tlaunch(x, LBDPS_K_SCATTER, false, k_scatter<T>, dim3(std::max(nblocks(N), 1)), parts(x, x->cp),
+            parts(x, 1 - x->cp), (const int32_t *)x->rank, (const int32_t *)x->cs, N, x->slot, tiles(x),
+            (const int32_t *)x->stay);
     x->cp = 1 - x->cp;
   }
 
@@ -436,20 +467,15 @@ template <int P> struct Impl {
     const int N = (int)x->n;
     if (N == 0) return;
     const Consts<T> k = consts(x);
-    tstart(x, LBDPS_K_CONTACTS);
-    hipLaunchKernelGGL(k_contacts<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->cs, k, x->adj(),
-                       x->deg, x->done, x->ticket, x->flags, x->pair_part, x->wall0_part, x->chunk_busy,
-                       x->need_sweep, x->roots, x->rcount);
-    tstop(x, LBDPS_K_CONTACTS);
-    tstart(x, LBDPS_K_RESOLVE);
-    hipLaunchKernelGGL(k_resolve_clusters<P>, dim3(x->cluster_groups()), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
-                       x->adj(), x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part,
-                       x->roots, x->rcount, nblocks(N));
-    hipLaunchKernelGGL(k_resolve<P>, dim3(resolve_blocks(x)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), x->slot,
-                       x->adj(),
-                       x->deg, x->done, x->ticket, k, x->flags, x->coll_part, x->wall_part, x->chunk_busy,
-                       x->need_sweep);
-    tstop(x, LBDPS_K_RESOLVE);
+    tlaunch(x, LBDPS_K_CONTACTS, false, k_contacts<P>, dim3(nblocks(N)), parts(x, x->cp), (const int32_t *)x->cs, k,
+            x->adj(), x->deg, x->done, x->ticket, x->flags, x->pair_part, x->wall0_part, x->chunk_busy,
+            x->need_sweep, x->roots, x->rcount);
+    tlaunch(x, LBDPS_K_RESOLVE, false, k_resolve_clusters<P>, dim3(x->cluster_groups()), parts(x, x->cp), x->adj(),
+            (const int32_t *)x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part,
+            (const long long *)x->roots, (const int32_t *)x->rcount, nblocks(N));
+    tlaunch(x, LBDPS_K_RESOLVE, true, k_resolve<P>, dim3(resolve_blocks(x)), parts(x, x->cp),
+            (const int32_t *)x->slot, x->adj(), (const int32_t *)x->deg, x->done, x->ticket, k, x->flags,
+            x->coll_part, x->wall_part, x->chunk_busy, (const int32_t *)x->need_sweep);
   }
 
   static lbdps_status step(lbdps_ctx *x, int nsteps) {
@@ -457,24 +483,16 @@ template <int P> struct Impl {
     const bool dg = x->p.diagnostics != 0;
     for (int it = 0; it < nsteps; ++it) {
       if (!x->bins_valid) rebin(x);
-      tstart(x, LBDPS_K_COLLIDE);
-      hipLaunchKernelGGL(k_collide<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, (const S *)x->f[x->cf],
-                         (S *)x->f[1 - x->cf], fields(x), x->cs, parts(x, x->cp), (const T *)x->lut,
-                         (const T *)x->inlet, k, dg ? x->dg_n : nullptr,
-                         dg ? (T *)x->dg_vsx : nullptr, dg ? (T *)x->dg_vsy : nullptr);
-      tstop(x, LBDPS_K_COLLIDE);
+      tlaunch(x, LBDPS_K_COLLIDE, false, k_collide<P>, dim3(nblocks(x->C)), (const S *)x->f[x->cf],
+              (S *)x->f[1 - x->cf], fields(x), (const int32_t *)x->cs, parts(x, x->cp), (const T *)x->lut,
+              (const T *)x->inlet, k, dg ? x->dg_n : nullptr, dg ? (T *)x->dg_vsx : nullptr,
+              dg ? (T *)x->dg_vsy : nullptr);
       if (x->n > 0) {
-        tstart(x, LBDPS_K_DRAG);
         const int nt = drag_tiles(x);
-        if (drag_flat(nt))
-          hipLaunchKernelGGL(k_drag_flat<P>, dim3(nt), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x), x->cs,
-                             (const T *)x->lut, k, x->count, x->rank, x->flags, dg ? (T *)x->dg_fdx : nullptr,
-                             dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x), x->stay);
-        else
-          hipLaunchKernelGGL(k_drag<P>, dim3(nt), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x), x->cs,
-                             (const T *)x->lut, k, x->count, x->rank, x->flags, dg ? (T *)x->dg_fdx : nullptr,
-                             dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x), x->stay);
-        tstop(x, LBDPS_K_DRAG);
+        tlaunch(x, LBDPS_K_DRAG, false, drag_flat(nt) ? k_drag_flat<P> : k_drag<P>, dim3(nt), parts(x, x->cp),
+                fields(x), (const int32_t *)x->cs, (const T *)x->lut, k, x->count, x->rank, x->flags,
+                dg ? (T *)x->dg_fdx : nullptr, dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x),
+                x->stay);
         sort_counted(x);
         hard_spheres(x);
       }
@@ -836,7 +854,7 @@ lbdps_status lbdps_kernel_times(lbdps_ctx *x, double *h_ms, int64_t *h_launches)
     st = check_hip(hipEventElapsedTime(&t, x->marks[i].a, x->marks[i].b), "lbdps_kernel_times");
     if (st != LBDPS_OK) return st;
     ms[x->marks[i].k] += t;
-    cnt[x->marks[i].k] += 1;
+    cnt[x->marks[i].k] += x->marks[i].extra ? 0 : 1;
   }
   x->nmarks = 0;
   for (int k = 0; k < LBDPS_K_COUNT; ++k) {
@@ -1067,21 +1085,33 @@ template <int P> struct BatchImpl {
     return st;
   }
 
-  // Event bracket of kernel k of an eager batched step (k as in lbdps_kernel).
-  static void bstart(lbdps_batch *B, bool timing, int k) {
-    if (!timing || !(B->timed >> k & 1u)) return;
+  // The step phase's kernel class (k as in lbdps_kernel).
+  static int phase_kernel(int ph) {
+    switch (ph) {
+      case PH_COLLIDE: return LBDPS_K_COLLIDE;
+      case PH_DRAG: return LBDPS_K_DRAG;
+      case PH_SCAN: return LBDPS_K_SCAN;
+      case PH_SCATTER: return LBDPS_K_SCATTER;
+      case PH_CONTACTS: return LBDPS_K_CONTACTS;
+      default: return LBDPS_K_RESOLVE;  // the cluster kernel and the ordered sweep
+    }
+  }
+  // Events for a timed launch of kernel class k in an eager batched step,
+  // stamped by the dispatch itself (the kernel's own time); false when k is
+  // not timed.  extra: a further launch of the same class in the step.
+  static bool bmark(lbdps_batch *B, int k, bool extra, hipEvent_t &a, hipEvent_t &b) {
+    if (!(B->timed >> k & 1u)) return false;
     if (B->nmarks == B->marks.size()) {
       lbdps_ctx::Mark m{};
-      if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess) return;
+      if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess) return false;
       B->marks.push_back(m);
     }
-    B->marks[B->nmarks].k = k;
-    (void)hipEventRecord(B->marks[B->nmarks].a, B->stream);
-  }
-  static void bstop(lbdps_batch *B, bool timing, int k) {
-    if (!timing || !(B->timed >> k & 1u) || B->nmarks >= B->marks.size() || B->marks[B->nmarks].k != k) return;
-    (void)hipEventRecord(B->marks[B->nmarks].b, B->stream);
-    B->nmarks += 1;
+    lbdps_ctx::Mark &m = B->marks[B->nmarks++];
+    m.k = k;
+    m.extra = extra;
+    a = m.a;
+    b = m.b;
+    return true;
   }
 
   static void launch_steps(lbdps_batch *B, int t, int nsteps) {
@@ -1093,31 +1123,25 @@ template <int P> struct BatchImpl {
     for (int it = 0; it < nsteps; ++it) {
       const int flip = it & 1;
 #define LBDPS_LAUNCH(kern, ph)                                                                                      \
-  if (tot[ph] > 0)                                                                                                  \
-    hipLaunchKernelGGL(kern<P>, dim3(tot[ph]), dim3(BLOCK), 0, B->stream, tab, off + (ph) * nb1, nbeds, flip);
-      bstart(B, timing, LBDPS_K_COLLIDE);
+  if (tot[ph] > 0) {                                                                                                \
+    hipEvent_t ea = nullptr, eb = nullptr;                                                                          \
+    if (timing && bmark(B, phase_kernel(ph), ph == PH_RESOLVE, ea, eb))                                             \
+      hipExtLaunchKernelGGL(kern<P>, dim3(tot[ph]), dim3(BLOCK), 0, B->stream, ea, eb, 0, tab, off + (ph) * nb1,    \
+                            nbeds, flip);                                                                           \
+    else                                                                                                            \
+      hipLaunchKernelGGL(kern<P>, dim3(tot[ph]), dim3(BLOCK), 0, B->stream, tab, off + (ph) * nb1, nbeds, flip);    \
+  }
       LBDPS_LAUNCH(kb_collide, PH_COLLIDE)
-      bstop(B, timing, LBDPS_K_COLLIDE);
-      bstart(B, timing, LBDPS_K_DRAG);
       if (drag_flat(tot[PH_DRAG])) {
         LBDPS_LAUNCH(kb_drag_flat, PH_DRAG)
       } else {
         LBDPS_LAUNCH(kb_drag, PH_DRAG)
       }
-      bstop(B, timing, LBDPS_K_DRAG);
-      bstart(B, timing, LBDPS_K_SCAN);
       LBDPS_LAUNCH(kb_scan, PH_SCAN)
-      bstop(B, timing, LBDPS_K_SCAN);
-      bstart(B, timing, LBDPS_K_SCATTER);
       LBDPS_LAUNCH(kb_scatter, PH_SCATTER)
-      bstop(B, timing, LBDPS_K_SCATTER);
-      bstart(B, timing, LBDPS_K_CONTACTS);
       LBDPS_LAUNCH(kb_contacts, PH_CONTACTS)
-      bstop(B, timing, LBDPS_K_CONTACTS);
-      bstart(B, timing, LBDPS_K_RESOLVE);
       LBDPS_LAUNCH(kb_clusters, PH_CLUSTERS)
       LBDPS_LAUNCH(kb_resolve, PH_RESOLVE)
-      bstop(B, timing, LBDPS_K_RESOLVE);
 #undef LBDPS_LAUNCH
     }
   }
@@ -1333,7 +1357,7 @@ lbdps_status lbdps_batch_kernel_times(lbdps_batch *B, double *h_ms, int64_t *h_l
     st = check_hip(hipEventElapsedTime(&t, B->marks[i].a, B->marks[i].b), "lbdps_batch_kernel_times");
     if (st != LBDPS_OK) return st;
     ms[B->marks[i].k] += t;
-    cnt[B->marks[i].k] += 1;
+    cnt[B->marks[i].k] += B->marks[i].extra ? 0 : 1;
   }
   B->nmarks = 0;
   for (int k = 0; k < LBDPS_K_COUNT; ++k) {
