@@ -880,8 +880,9 @@ namespace {
 
 // Launch shapes the autotuner tries (all give identical results).
 const lbdps_tuning kTuneCandidates[] = {
-    {1, RC_GROUPS_MAX, 0}, {2, RC_GROUPS_MAX, 0}, {4, RC_GROUPS_MAX, 0},
-    {1, 4096, 0},          {1, 1024, 0},          {4, 1024, 0},
+    {1, RC_GROUPS_MAX, 0}, {2, RC_GROUPS_MAX, 0}, {4, RC_GROUPS_MAX, 0}, {8, RC_GROUPS_MAX, 0},
+    {16, RC_GROUPS_MAX, 0}, {1, 4096, 0},         {1, 1024, 0},          {4, 1024, 0},
+    {1, 128, 0},  // few contacts: a small grid reads the candidate counts and is done
 };
 constexpr int kTuneN = (int)(sizeof(kTuneCandidates) / sizeof(kTuneCandidates[0]));
 
