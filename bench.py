@@ -73,6 +73,13 @@ STATED_ERR = {p: {"bound": b, "fields": "f, rho, u_gas, F_pg, beta", "after_step
               for p, b in (("fp32", 2e-6), ("fp16", 1e-2), ("bf16", 1.5e-2))}
 
 
+def workload_name(name: str, prec: str) -> str:
+    """A workload's name with the storage precision actually run in place of
+    the one the recipe names."""
+    head, _, tail = name.rpartition("-")
+    return f"{head}-{prec}" if tail in SIZES else name
+
+
 def model_bytes_per_step(prec: str, C: int, N: int, pairs: int) -> float:
     """Whole-step byte model: 18 s_f + 16 s_c + 20 per cell, 14 s_p + 16 per
     particle, 16 + 8 s_p per contact pair."""
@@ -413,7 +420,8 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)", "bf16": "f32 (bf16 storage)"}[args.precision],
         "data": "synthetic (seeded splitmix64 bed, recipe in DESIGN.md)",
-        "config": {"workload": cfg["name"], "nx": cfg["nx"], "ny": cfg["ny"], "particles": N,
+        "config": {"workload": workload_name(cfg["name"], args.precision), "nx": cfg["nx"], "ny": cfg["ny"],
+                   "particles": N,
                    "precision": args.precision, "d_p": cfg["d"], "tau": cfg["tau"]},
         "particle_updates_per_s": float(f"{pups:.4e}"),
         "model_bytes_per_step": int(model),
