@@ -95,7 +95,7 @@ typedef struct {
   int32_t omega_mode;        /* 0 EMMS correction of Eq. 20 (default), 1 omega = 1 (Eq. 6) */
   int32_t pressure_force_sign; /* sign s of the s V_p grad p term of Eq. 16: -1 (default), 0, +1 */
   double omega_dense;        /* omega used where eps_g <= 0.74 (Eq. 20 undefined), default 1 */
-  double cs_smag;            /* Smagorinsky constant of Eqs. 12-15; 0 = plain BGK (only 0 supported) */
+  double cs_smag;            /* Smagorinsky constant C_s of Eqs. 12-15 (>= 0); 0 = plain BGK     */
   int32_t precision;         /* lbdps_precision                                        */
   int32_t diagnostics;       /* 1: each step also records per-cell n, v_s and per-particle
                                 drag for lbdps_get_fields / lbdps_get_particles          */

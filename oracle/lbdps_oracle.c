@@ -14,7 +14,7 @@
  * Units: lattice units, h = dt = 1, so c = h/dt = 1 (note after Eq. 14),
  * c_s^2 = 1/3 (Sec. 2.1, text after Eq. 4) and every h^2/dt factor is 1 (Eq. 25).
  *
- * Interpretations of points the paper leaves open are numbered R1..R33 in the
+ * Interpretations of points the paper leaves open are numbered R1..R40 in the
  * design notes; the comment at each use says which one applies.
  *
  * Parity status: every function is pinned by a closed form, an invariant,
@@ -179,8 +179,35 @@ double orc_beta(const orc_params *p, double eg, double om, double slip) {
 }
 
 /*
- * Collision at one node, Eq. 23 with tau_t = tau (LES off, R30; R4), the solid
- * term of Eq. 7 and the gas body-force source of R29.
+ * Relaxation time of the BGK part with the Smagorinsky sub-grid model
+ * (Eqs. 12-15).  The momentum flux of the non-equilibrium populations,
+ * Q_ij = sum_k c_ki c_kj (f_k - f_k^eq) (Eq. 13), with f^eq at the raw moment
+ * velocity (R5), has the norm Q = sqrt(2 Q_ij Q_ij).  Eq. 13 gives the strain
+ * rate S = Q / (2 rho c_s^2 tau_t), Eq. 12 the eddy viscosity
+ * nu_e = C_s^2 S (dx = 1) and Eq. 14 tau_t = 3 (nu + nu_e) + 1/2 = tau + 3 nu_e;
+ * together tau_t^2 - tau tau_t - 9 C_s^2 Q / (2 rho) = 0, whose positive root is
+ * Eq. 15 with Q / rho in place of the printed Q (R40; rho is close to 1).
+ * With C_s = 0 this is tau itself (LES off, R30).
+ */
+double orc_tau_les(const orc_params *p, const double *f, const double *feq, double rho) {
+  if (p->cs_smag == 0.0) return p->tau;
+  double qxx = 0.0, qyy = 0.0, qxy = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    double ne = f[i] - feq[i];
+    qxx += CX[i] * CX[i] * ne;
+    qyy += CY[i] * CY[i] * ne;
+    qxy += CX[i] * CY[i] * ne;
+  }
+  double q = sqrt(2.0 * (qxx * qxx + qyy * qyy + 2.0 * (qxy * qxy)));
+  double cs18 = 18.0 * p->cs_smag * p->cs_smag;
+  return 0.5 * (p->tau + sqrt(p->tau * p->tau + cs18 * q / rho));
+}
+
+/*
+ * Collision at one node, Eq. 23 with tau_t from orc_tau_les (R4: the BGK part
+ * relaxes with 1/tau_t and gamma(eps_s, tau_t), the solid term keeps
+ * gamma(eps_s, tau)), the solid term of Eq. 7 and the gas body-force source of
+ * R29.
  *   f[9]      pre-collision populations
  *   n, vs[2]  particles in the cell and their mean velocity (Eq. 8, R8)
  *   fstar[9]  post-collision populations
@@ -210,6 +237,10 @@ void orc_collide_node(const orc_params *p, const double *f, int64_t n, const dou
   for (int i = 0; i < 9; ++i) oms[i] = f[OPP[i]] - f[i] + fv[i] - fu[OPP[i]];
   double omg = om * gam;
   double relax = (1.0 - gam) / p->tau;
+  if (p->cs_smag != 0.0) {  /* Eqs. 12-15 (R40) */
+    double tt = orc_tau_les(p, f, fu, rho);
+    relax = (1.0 - orc_gamma(pr[0], tt)) / tt;
+  }
   for (int i = 0; i < 9; ++i) {
     double src = 3.0 * W[i] * (CX[i] * p->G[0] + CY[i] * p->G[1]);
     fstar[i] = f[i] - relax * (f[i] - fu[i]) + omg * oms[i] + src;

@@ -67,7 +67,8 @@ enum {
   L_OM,       // omega (Eq. 20)
   L_D1,       // Ergun viscous term 150 (1-eg)^2 mu / (eg d^2)
   L_D2,       // Ergun inertial prefactor 1.75 (1-eg) rho_g
-  L_DILUTE    // 1 if eg > 0.74
+  L_DILUTE,   // 1 if eg > 0.74
+  L_ES2       // 2-D solid fraction eps_s,2d (Eq. 10), for gamma at tau_t (Eq. 9)
 };
 
 // D2Q9, numbering 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1).
@@ -160,6 +161,8 @@ template <class T> struct Consts {
   int drag_abs;
   int npart;
   T tau, d, mu, vp, m, msum, one_e, e_pw, r;
+  int les;  // Smagorinsky sub-grid model on (Eqs. 12-15)
+  T cs18;   // 18 C_s^2 of Eq. 15
   T geff[2], fp, halfG[2], src[Q];
   unsigned spin_limit;
 };

@@ -539,7 +539,30 @@ __device__ __forceinline__ void collide_body(const int bidx, const int gdim,
   // Eq. 7 (the weights cancel between f_-i and f_i, so the same form holds for deviations)
 #pragma unroll
   for (int i = 0; i < Q; ++i) oms[i] = f[opp9(i)] - f[i] + feq_v<P>(i, rho, rho1, vsx, vsy) - fu[opp9(i)];
-  const T omg = L[L_OMG], relax = L[L_RELAX];
+  const T omg = L[L_OMG];
+  T relax = L[L_RELAX];
+  if (k.les) {
+    // Smagorinsky sub-grid model (Eqs. 12-15): the momentum flux of the
+    // non-equilibrium part, Q_ij = sum_k c_ki c_kj (f_k - f_k^eq) (Eq. 13), its
+    // norm Q = sqrt(2 Q_ij Q_ij), and tau_t, the positive root of
+    // tau_t^2 - tau tau_t - 9 C_s^2 Q / (2 rho) = 0 (Eqs. 12-14; Eq. 15 with
+    // Q / rho).  The BGK part relaxes with 1/tau_t and gamma(eps_s, tau_t)
+    // (Eq. 23); the solid term keeps gamma(eps_s, tau).  Deviations cancel in
+    // f - f^eq, so every storage mode forms the same Q_ij.
+    T qxx = (T)0, qyy = (T)0, qxy = (T)0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const T ne = f[i] - fu[i];
+      qxx += (T)(cx_of(i) * cx_of(i)) * ne;
+      qyy += (T)(cy_of(i) * cy_of(i)) * ne;
+      qxy += (T)(cx_of(i) * cy_of(i)) * ne;
+    }
+    const T q = sq<P>((T)2.0 * (qxx * qxx + qyy * qyy + (T)2.0 * (qxy * qxy)));
+    const T tt = (T)0.5 * (k.tau + sq<P>(k.tau * k.tau + dv<P>(k.cs18 * q, rho)));
+    const T es2 = L[L_ES2];
+    const T gt = dv<P>(es2 * (tt - (T)0.5), ((T)1.0 - es2) + (tt - (T)0.5));
+    relax = dv<P>((T)1.0 - gt, tt);
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) fs[i] = f[i] - relax * (f[i] - fu[i]) + omg * oms[i] + k.src[i];
   T ssx = (T)0, ssy = (T)0;

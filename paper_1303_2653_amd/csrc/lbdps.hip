@@ -108,12 +108,14 @@ std::vector<double> build_lut(const lbdps_params &p) {
     r[L_D1] = 150.0 * (1.0 - eg) * (1.0 - eg) * mu / (eg * d * d);
     r[L_D2] = 1.75 * (1.0 - eg) * p.rho_g;
     r[L_DILUTE] = eg > 0.74 ? 1.0 : 0.0;
+    r[L_ES2] = es2;
   }
   return L;
 }
 
 struct DConsts {  // FP64 master copy of the kernel constants
   double tau, d, mu, vp, m, msum, one_e, e_pw, r, geff[2], fp, halfG[2], src[Q];
+  double cs18;  // 18 C_s^2 (Eq. 15)
 };
 
 DConsts make_dconsts(const lbdps_params &p) {
@@ -130,6 +132,7 @@ DConsts make_dconsts(const lbdps_params &p) {
   c.geff[0] = (1.0 - p.rho_g / p.rho_s) * p.g[0];
   c.geff[1] = (1.0 - p.rho_g / p.rho_s) * p.g[1];
   c.fp = (double)p.pressure_force_sign * c.vp;
+  c.cs18 = 18.0 * p.cs_smag * p.cs_smag;
   c.halfG[0] = 0.5 * p.body_force[0];
   c.halfG[1] = 0.5 * p.body_force[1];
   for (int i = 0; i < Q; ++i)
@@ -401,6 +404,8 @@ template <int P> struct Impl {
     k.one_e = (T)d.one_e;
     k.e_pw = (T)d.e_pw;
     k.r = (T)d.r;
+    k.les = x->p.cs_smag != 0.0;
+    k.cs18 = (T)d.cs18;
     for (int a = 0; a < 2; ++a) {
       k.geff[a] = (T)d.geff[a];
       k.halfG[a] = (T)d.halfG[a];
@@ -634,7 +639,6 @@ lbdps_status lbdps_validate_params(const lbdps_params *p, int64_t max_particles)
     return fail(LBDPS_E_INVALID, "pressure_force_sign must be -1, 0 or 1");
   if (!is_fin(p->omega_dense)) return fail(LBDPS_E_INVALID, "omega_dense must be finite");
   if (!is_fin(p->cs_smag) || p->cs_smag < 0) return fail(LBDPS_E_INVALID, "cs_smag must be >= 0");
-  if (p->cs_smag != 0.0) return fail(LBDPS_E_UNSUPPORTED, "Smagorinsky LES (cs_smag > 0) is not supported");
   if (p->precision < 0 || p->precision > 3) return fail(LBDPS_E_INVALID, "precision must be 0..3");
   if (p->diagnostics < 0 || p->diagnostics > 1) return fail(LBDPS_E_INVALID, "diagnostics must be 0 or 1");
   // below 2^29: every per-particle and per-cell array is addressed by 32-bit byte offsets

@@ -43,7 +43,8 @@ def test_validation_accepts_workloads():
     ("tau", float("nan"), L.LBDPS_E_INVALID), ("d_p", 1.0, L.LBDPS_E_INVALID), ("d_p", 0.0, L.LBDPS_E_INVALID),
     ("e_pp", 1.5, L.LBDPS_E_INVALID), ("e_pw", -0.1, L.LBDPS_E_INVALID), ("rho_s", 0.0, L.LBDPS_E_INVALID),
     ("precision", 7, L.LBDPS_E_INVALID), ("pressure_force_sign", 2, L.LBDPS_E_INVALID),
-    ("cs_smag", 0.1, L.LBDPS_E_UNSUPPORTED), ("drag_ratio_mode", 3, L.LBDPS_E_INVALID),
+    ("cs_smag", -0.1, L.LBDPS_E_INVALID), ("cs_smag", float("inf"), L.LBDPS_E_INVALID),
+    ("drag_ratio_mode", 3, L.LBDPS_E_INVALID),
 ])
 def test_validation_rejects(field, value, code):
     p = L.make_params(synth.bubble_small())

@@ -64,6 +64,9 @@ TINY_CASES = {
     "abs-ratio": dict(bc=("periodic", "periodic", "wall", "wall"), drag_ratio_mode=1, pressure_sign=1,
                       u_gas_porosity=1),
     "omega1": dict(bc=("periodic", "periodic", "inlet", "outlet"), omega_mode=1, u_gas_porosity=2),
+    # Smagorinsky sub-grid model on (Eqs. 12-15)
+    "les-riser": dict(bc=("wall", "wall", "periodic", "periodic"), G=(0.0, 4e-5), g=(0.0, -3e-5), cs_smag=2.0),
+    "les-inlet": dict(bc=("periodic", "periodic", "inlet", "outlet"), band=10.0, cs_smag=1.0),
 }
 
 
@@ -277,7 +280,7 @@ def drag_error_bound(ref_out, pos0, vel0, cfg, eta):
     return bound, K
 
 
-@pytest.mark.parametrize("name", ["bubble", "riser_crop"])
+@pytest.mark.parametrize("name", ["bubble", "riser_crop", "riser_crop_les"])
 def test_fp32_one_step_full_size(name):
     """One coupled step in FP32 at the workload's full size from a shared
     FP32-representable state, against the FP64 oracle step from the same state.
@@ -285,8 +288,11 @@ def test_fp32_one_step_full_size(name):
     Eq. 28 is a ratio of sums that can nearly cancel, so its FP32 error is held
     to the first-order bound of drag_error_bound with eta = 1e-5, and the
     velocity to 1e-5 max|v| plus that bound over the particle mass."""
-    cfg = getattr(synth, name)()
-    say("workload", cfg["name"])
+    les = name.endswith("_les")
+    cfg = getattr(synth, name[:-4] if les else name)()
+    if les:
+        cfg["cs_smag"] = 4.0  # Smagorinsky model on (Eqs. 12-15)
+    say("workload", cfg["name"], "C_s", cfg.get("cs_smag", 0.0))
     warm = oracle.Sim(cfg)
     warm.run(20)  # develop flow and velocities, then hand the FP32-held state to both sides
     f, pos, vel = storage_repr.state(cfg, warm.f, warm.pos, warm.vel, "fp32")
