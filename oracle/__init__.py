@@ -48,6 +48,7 @@ class OrcParams(ctypes.Structure):
         ("omega_mode", ctypes.c_int32), ("pressure_sign", ctypes.c_int32),
         ("omega_dense", ctypes.c_double),
         ("cs_smag", ctypes.c_double),
+        ("n_sub", ctypes.c_int32),
     ]
 
 
@@ -141,6 +142,7 @@ def make_params(cfg: dict) -> OrcParams:
     p.pressure_sign = int(cfg.get("pressure_sign", -1))
     p.omega_dense = float(cfg.get("omega_dense", 1.0))
     p.cs_smag = float(cfg.get("cs_smag", 0.0))
+    p.n_sub = int(cfg.get("n_sub", 1))
     return p
 
 

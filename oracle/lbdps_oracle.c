@@ -14,7 +14,7 @@
  * Units: lattice units, h = dt = 1, so c = h/dt = 1 (note after Eq. 14),
  * c_s^2 = 1/3 (Sec. 2.1, text after Eq. 4) and every h^2/dt factor is 1 (Eq. 25).
  *
- * Interpretations of points the paper leaves open are numbered R1..R40 in the
+ * Interpretations of points the paper leaves open are numbered R1..R41 in the
  * design notes; the comment at each use says which one applies.
  *
  * Parity status: every function is pinned by a closed form, an invariant,
@@ -52,6 +52,7 @@ typedef struct {
   int32_t pressure_sign;   /* -1 physical (R17), 0 off, +1 as printed in Eq. 16 */
   double omega_dense;      /* omega for eps_g <= 0.74 (R9) */
   double cs_smag;          /* Smagorinsky constant, 0 = plain BGK (Eqs. 12-15) */
+  int32_t n_sub;           /* particle sub-steps per lattice step, 0 or 1 = one (R41) */
 } orc_params;
 
 typedef struct {
@@ -402,29 +403,49 @@ static double mirror_coord(double x, double L) {
 }
 
 /*
- * Eq. 16 integrated with symplectic Euler and dt_p = 1 (R18):
- *   v <- v + g_eff + (F_d + s V_p grad p_k) / m,   P <- P + v,
- * with s = pressure_sign (R17), then periodic wrap (R26) or wall mirror (R23).
- * fd[N][2] and gpk[N][2] are the drag and the interpolated pressure gradient.
+ * Acceleration of Eq. 16 for every particle:
+ *   a = g_eff + (F_d + s V_p grad p_k) / m,
+ * with s = pressure_sign (R17).  fd[N][2] and gpk[N][2] are the drag and the
+ * interpolated pressure gradient; acc[N][2] receives a.
  */
-void orc_integrate(const orc_params *p, int64_t np, double *pos, double *vel, const double *fd,
-                   const double *gpk) {
+static void accelerations(const orc_params *p, int64_t np, const double *fd, const double *gpk, double *acc) {
   double vp = vol_p(p), m = mass_p(p);
   double fp = (double)p->pressure_sign * vp;
   double gex = (1.0 - p->rho_g / p->rho_s) * p->g[0];
   double gey = (1.0 - p->rho_g / p->rho_s) * p->g[1];
   for (int64_t k = 0; k < np; ++k) {
-    double ax = gex + (fd[2 * k] + fp * gpk[2 * k]) / m;
-    double ay = gey + (fd[2 * k + 1] + fp * gpk[2 * k + 1]) / m;
-    vel[2 * k] = vel[2 * k] + ax;
-    vel[2 * k + 1] = vel[2 * k + 1] + ay;
-    double x = pos[2 * k] + vel[2 * k];
-    double y = pos[2 * k + 1] + vel[2 * k + 1];
+    acc[2 * k] = gex + (fd[2 * k] + fp * gpk[2 * k]) / m;
+    acc[2 * k + 1] = gey + (fd[2 * k + 1] + fp * gpk[2 * k + 1]) / m;
+  }
+}
+
+/*
+ * One symplectic Euler step of length h (R18): v <- v + a h, P <- P + v h, then
+ * periodic wrap (R26) or wall mirror (R23).
+ */
+static void advance(const orc_params *p, int64_t np, double *pos, double *vel, const double *acc, double h) {
+  for (int64_t k = 0; k < np; ++k) {
+    vel[2 * k] = vel[2 * k] + acc[2 * k] * h;
+    vel[2 * k + 1] = vel[2 * k + 1] + acc[2 * k + 1] * h;
+    double x = pos[2 * k] + vel[2 * k] * h;
+    double y = pos[2 * k + 1] + vel[2 * k + 1] * h;
     x = is_periodic_x(p) ? wrap_coord(x, p->nx) : mirror_coord(x, p->nx);
     y = is_periodic_y(p) ? wrap_coord(y, p->ny) : mirror_coord(y, p->ny);
     pos[2 * k] = x;
     pos[2 * k + 1] = y;
   }
+}
+
+/*
+ * Eq. 16 integrated with symplectic Euler over one whole step, dt_p = 1 (R18):
+ *   v <- v + g_eff + (F_d + s V_p grad p_k) / m,   P <- P + v.
+ */
+void orc_integrate(const orc_params *p, int64_t np, double *pos, double *vel, const double *fd,
+                   const double *gpk) {
+  double *acc = (double *)malloc((size_t)(np > 0 ? np : 1) * 2 * sizeof(double));
+  accelerations(p, np, fd, gpk, acc);
+  advance(p, np, pos, vel, acc, 1.0);
+  free(acc);
 }
 
 /* Minimum-image separation P_i - P_j along each axis (R25). */
@@ -702,6 +723,9 @@ void orc_walls(const orc_params *p, int64_t np, const double *pos, double *vel, 
  *   5) integration of Eq. 16
  *   6) contact detection at the new positions and binary collisions (Eqs. 17-18),
  *      then particle-wall collisions
+ * With n_sub > 1 sub-steps (R41), 5) and 6) run n_sub times with h = 1 / n_sub
+ * under the accelerations of step 4, held over the whole lattice step; the
+ * pair list and the counters then describe the last sub-step.
  * f[9][ny][nx] (pre-collision, advanced in place), pos[N][2], vel[N][2] (id
  * order, advanced in place).  Per-cell sums run in ascending particle index (R28).
  */
@@ -828,19 +852,26 @@ int orc_step(const orc_params *p, const double *inlet_uy, double *f, int64_t np,
     }
   }
 
-  /* ---- 5) integration ---- */
-  orc_integrate(p, np, pos, vel, fd, gpk);
-
-  /* ---- 6) contacts at the new positions, collisions, walls ---- */
+  /* ---- 5) and 6): integration, then contacts at the new positions,
+   * collisions and walls, once per sub-step (R41) ---- */
+  const int nsub = p->n_sub > 1 ? p->n_sub : 1;
+  const double h = 1.0 / (double)nsub;
+  double *acc = (double *)malloc(NP * 2 * sizeof(double));
+  accelerations(p, np, fd, gpk, acc);
   int64_t cap = out && out->pairs ? out->pair_cap : 0;
   int64_t cap_eff = cap > 0 ? cap : (np * 16 + 16);
   int32_t *pairs = out && out->pairs ? out->pairs : (int32_t *)malloc((size_t)cap_eff * 2 * sizeof(int32_t));
   int64_t npairs = 0, ncoll = 0, nwall = 0;
-  rc = orc_contacts_cells(p, np, pos, pairs, cap_eff, &npairs);
-  if (rc == ORC_OK) {
-    orc_resolve(p, np, pos, vel, pairs, npairs, &ncoll);
-    orc_walls(p, np, pos, vel, &nwall);
+  for (int sub = 0; sub < nsub && rc == ORC_OK; ++sub) {
+    advance(p, np, pos, vel, acc, h);
+    npairs = ncoll = nwall = 0;
+    rc = orc_contacts_cells(p, np, pos, pairs, cap_eff, &npairs);
+    if (rc == ORC_OK) {
+      orc_resolve(p, np, pos, vel, pairs, npairs, &ncoll);
+      orc_walls(p, np, pos, vel, &nwall);
+    }
   }
+  free(acc);
 
   if (out) {
     if (out->ncell) memcpy(out->ncell, ncell, (size_t)C * sizeof(int32_t));

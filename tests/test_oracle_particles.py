@@ -309,10 +309,12 @@ def test_drag_correction_newton3(orc):
 def test_momentum_bookkeeping(orc):
     """Periodic bed, SIGNED Eq. 28, pressure force off: gas + particle momentum is
     conserved to roundoff; with gravity g and gas body force G it grows by
-    steps * (N m g_eff + C G) exactly (contacts and walls conserve it)."""
-    for g, G in (((0.0, 0.0), (0.0, 0.0)), ((0.0, -1e-5), (2e-6, 3e-6))):
+    steps * (N m g_eff + C G) exactly (contacts and walls conserve it), with
+    one or three particle sub-steps per lattice step (R41)."""
+    for g, G, nsub in (((0.0, 0.0), (0.0, 0.0), 1), ((0.0, -1e-5), (2e-6, 3e-6), 1),
+                       ((0.0, -1e-5), (2e-6, 3e-6), 3)):
         cfg = synth.tiny(nx=12, ny=12, n=120, seed=5, bc=("periodic",) * 4, vel_scale=2e-3,
-                         pressure_sign=0, g=g, G=G)
+                         pressure_sign=0, g=g, G=G, n_sub=nsub)
         sim = orc.Sim(cfg)
         c0 = sim.conservation()
         steps = 25
@@ -340,3 +342,61 @@ def test_deposition_counts_and_means(orc):
     cnt = np.bincount(cell, minlength=81)
     want[cnt > 0] /= cnt[cnt > 0, None]
     assert (o.vs.reshape(-1, 2) == want).all()
+
+
+# ---------------------------------------------------------------- sub-steps (R41)
+@pytest.mark.parametrize("nsub", [2, 3, 8])
+def test_substep_free_flight(orc, nsub):
+    """R41: the accelerations of Eq. 16 are held over the lattice step, so n
+    symplectic Euler sub-steps of h = 1/n leave the velocity at v0 + a (as one
+    step does) and move the particle by v0 + a (n + 1) / (2 n).  The same state
+    stepped once with n = 1 gives a = v1 - v0; dilute periodic bed, no walls or
+    contacts (the largest speed keeps every pair apart)."""
+    rng = np.random.default_rng(8)
+    y, x = np.mgrid[0:6, 0:6] * 2.0 + 1.0
+    pos = np.stack([x.ravel(), y.ravel()], 1) + (rng.random((36, 2)) - 0.5) * 0.4
+    vel = (rng.random((36, 2)) - 0.5) * 4e-3
+    cfg = _cfg(nx=12, ny=12, pos=pos, vel=vel, g=(0.0, -1e-5), G=(1e-6, 2e-6))
+    one = orc.Sim(cfg)
+    one.run(3)  # develop a flow
+    f, pos0, vel0 = one.f.copy(), one.pos.copy(), one.vel.copy()
+    o1 = one.step(record=True)
+    assert len(o1.pairs) == 0
+    a = one.vel - vel0
+    sub = orc.Sim(dict(cfg, n_sub=nsub), f=f, pos=pos0, vel=vel0)
+    on = sub.step(record=True)
+    assert len(on.pairs) == 0 and on.nwall == 0
+    assert np.array_equal(on.fd, o1.fd)  # forces from the state at the start of the step
+    assert np.allclose(sub.vel, one.vel, rtol=0, atol=1e-15)
+    want = pos0 + vel0 + a * (nsub + 1) / (2 * nsub)
+    dx = (sub.pos - want + 6.0) % 12.0 - 6.0
+    assert np.abs(dx).max() < 1e-13
+    assert np.abs(a).max() > 1e-7  # the test has an acceleration to integrate
+    # n = 1 is the plain step, bit for bit
+    same = orc.Sim(dict(cfg, n_sub=1), f=f, pos=pos0, vel=vel0)
+    same.step()
+    assert np.array_equal(same.pos, one.pos) and np.array_equal(same.vel, one.vel)
+
+
+@pytest.mark.parametrize("nsub", [1, 2, 4, 7, 8])
+def test_substep_collision_time(orc, nsub):
+    """R41 with Eqs. 17-18: two equal spheres approach head-on at 0.3 each, one
+    cell apart (d = 0.5, e = 1).  Contacts are tested after every sub-step, so
+    the collision happens at the first sub-step k whose separation
+    1 - 0.6 k h is at most d, the velocities swap there and the spheres recede
+    for the remaining sub-steps.  A huge solid density makes the gas forces on
+    the spheres negligible (below 1e-12 per step)."""
+    h = 1.0 / nsub
+    k = next(j for j in range(1, nsub + 1) if 1.0 - 0.6 * j * h <= 0.5)
+    xa = 4.0 + 0.3 * k * h - 0.3 * (nsub - k) * h
+    xb = 5.0 - 0.3 * k * h + 0.3 * (nsub - k) * h
+    pos = np.array([[4.0, 8.2], [5.0, 8.2]])
+    vel = np.array([[0.3, 0.0], [-0.3, 0.0]])
+    cfg = _cfg(nx=16, ny=16, pos=pos, vel=vel, d=0.5, e_pp=1.0, rho_s=1e12, g=(0.0, 0.0), n_sub=nsub)
+    sim = orc.Sim(cfg)
+    o = sim.step(record=True)
+    assert np.allclose(sim.pos[:, 0], [xa, xb], rtol=0, atol=1e-11)
+    assert np.allclose(sim.pos[:, 1], 8.2, rtol=0, atol=1e-11)
+    assert np.allclose(sim.vel, [[-0.3, 0.0], [0.3, 0.0]], rtol=0, atol=1e-11)
+    # the counters describe the last sub-step: the collision is counted only if it fell there
+    assert o.ncollisions == (1 if k == nsub else 0)
