@@ -358,6 +358,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="bubble", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=sorted(SIZES))
+    ap.add_argument("--n-sub", type=int, default=1, help="particle sub-steps per lattice step")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -395,6 +396,8 @@ def main():
         print(json.dumps(run_beds(args, torch, L)), flush=True)
         return
     cfg = WORKLOADS[args.workload]()
+    if args.n_sub > 1:
+        cfg["n_sub"] = args.n_sub
     C, N = cfg["nx"] * cfg["ny"], len(cfg["pos"])
     r = run_gpu(cfg, args.precision, args.steps, args.warmup, torch, L)
     s = r["ms"] / 1e3
@@ -404,9 +407,16 @@ def main():
     # the kernel's own duration per launch, from events its dispatch stamps
     dom_us = r["dom_ms"] / max(r["dom_launches"], 1) * 1e3
     dom_bytes = algorithmic_bytes(dom, args.precision, C, N, r["pairs"])
+    if args.n_sub > 1:  # the phase's time per step covers every sub-step's launch
+        if dom == "drag":
+            sf, st = SIZES[args.precision]
+            dom_bytes += (args.n_sub - 1) * N * (2 * (4 + 4 * st) + 4 + 2 * st + 8)
+        elif dom != "collide":
+            dom_bytes *= args.n_sub
     achieved = dom_bytes / (dom_us * 1e-6) / 1e9
     model = model_bytes_per_step(args.precision, C, N, r["pairs"])
-    traffic = measured_traffic(args.workload if args.precision == "fp32" else f"{args.workload}-{args.precision}", dom)
+    traffic = None if args.n_sub > 1 else measured_traffic(
+        args.workload if args.precision == "fp32" else f"{args.workload}-{args.precision}", dom)
     line = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -420,9 +430,11 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)", "bf16": "f32 (bf16 storage)"}[args.precision],
         "data": "synthetic (seeded splitmix64 bed, recipe in DESIGN.md)",
-        "config": {"workload": workload_name(cfg["name"], args.precision), "nx": cfg["nx"], "ny": cfg["ny"],
+        "config": {"workload": workload_name(cfg["name"], args.precision)
+                   + (f"-nsub{args.n_sub}" if args.n_sub > 1 else ""), "nx": cfg["nx"], "ny": cfg["ny"],
                    "particles": N,
-                   "precision": args.precision, "d_p": cfg["d"], "tau": cfg["tau"]},
+                   "precision": args.precision, "d_p": cfg["d"], "tau": cfg["tau"],
+                   "n_sub": cfg.get("n_sub", 1)},
         "particle_updates_per_s": float(f"{pups:.4e}"),
         "model_bytes_per_step": int(model),
         "model_bw_frac": round(model * args.steps / s / 1e9 / HBM_PEAK_GBS, 4),

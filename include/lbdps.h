@@ -73,6 +73,9 @@ typedef enum {
   LBDPS_BC_OUTLET = 3 /* incoming populations copied from the boundary row         */
 } lbdps_bc;
 
+/* Largest number of particle sub-steps per lattice step (lbdps_params.n_sub). */
+#define LBDPS_MAX_SUBSTEPS 64
+
 /* Contacts recorded per particle; a particle with more is an LBDPS_E_CAPACITY error. */
 #define LBDPS_MAX_CONTACTS 32
 
@@ -99,6 +102,14 @@ typedef struct {
   int32_t precision;         /* lbdps_precision                                        */
   int32_t diagnostics;       /* 1: each step also records per-cell n, v_s and per-particle
                                 drag for lbdps_get_fields / lbdps_get_particles          */
+  int32_t n_sub;             /* particle sub-steps per lattice step, 0..LBDPS_MAX_SUBSTEPS
+                                (0 and 1: one).  The drag, pressure and gravity
+                                accelerations of Eq. 16 are taken once per lattice step
+                                and held; each sub-step of length 1/n_sub integrates
+                                Eq. 16 and runs the collision stage (Sec. 2.2, time-driven
+                                hard spheres at the finer interval).  lbdps_counters and
+                                lbdps_get_pairs then describe the last sub-step.  Batched
+                                beds (lbdps_batch_*) take one: LBDPS_E_UNSUPPORTED else */
 } lbdps_params;
 
 typedef struct lbdps_ctx lbdps_ctx;

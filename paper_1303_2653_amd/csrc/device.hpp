@@ -164,6 +164,8 @@ template <class T> struct Consts {
   int les;  // Smagorinsky sub-grid model on (Eqs. 12-15)
   T cs18;   // 18 C_s^2 of Eq. 15
   T geff[2], fp, halfG[2], src[Q];
+  T h;          // particle sub-step length, 1 / n_sub
+  T *acx, *acy; // accelerations held over the lattice step by particle index (n_sub > 1), else null
   unsigned spin_limit;
 };
 

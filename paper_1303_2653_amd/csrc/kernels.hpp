@@ -664,6 +664,30 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename Prec<P>::S *__
   collide_body<P>(xcd_block<XCD_RUN_COLLIDE>(blockIdx.x, gridDim.x), gridDim.x, fsrc, fdst, fl, cs, pt, lut, inlet, k, dg_n, dg_vsx, dg_vsy);
 }
 
+// One symplectic Euler step of length h = 1 / n_sub of Eq. 16 for the particle
+// in slot s of cell (cx, cy) = c: v <- v + a h, P <- P + v h, then the periodic
+// wrap or wall mirror.  Stores the record and returns the new cell (the old
+// one, with the domain flag raised, if the result is not a valid cell).
+template <int P>
+__device__ __forceinline__ int advance_one(const Consts<typename Prec<P>::T> &k, Parts<typename Prec<P>::T> &pt,
+                                           int s, int cx, int cy, int c, typename Prec<P>::T x,
+                                           typename Prec<P>::T y, typename Prec<P>::T vx, typename Prec<P>::T vy,
+                                           typename Prec<P>::T ax, typename Prec<P>::T ay, int32_t *flags) {
+  vx = vx + ax * k.h;
+  vy = vy + ay * k.h;
+  int nk = Pos<P>::move(k, cx, cy, x, y, vx * k.h, vy * k.h);
+  if (nk < 0) {
+    atomicOr(&flags[FLAG_DOMAIN], 1);
+    nk = c;
+  }
+  pt.key[s] = nk;
+  pt.px[s] = x;
+  pt.py[s] = y;
+  pt.vx[s] = vx;
+  pt.vy[s] = vy;
+  return nk;
+}
+
 // ------------------------------------------------------------------ A4 + A5: drag and integration, fused with binning
 // One thread per cell, looping over its particles (ascending index).  Pass 1
 // interpolates u_gas, the solid fraction, beta and grad p at each particle
@@ -833,24 +857,18 @@ __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, 
           fdy = dv<P>(-fgy * pry, Sy);
         const T ax = k.geff[0] + dv<P>(fdx + k.fp * gpx, k.m);
         const T ay = k.geff[1] + dv<P>(fdy + k.fp * gpy, k.m);
-        vx = vx + ax;
-        vy = vy + ay;
-        int nk = Pos<P>::move(k, cx, cy, x, y, vx, vy);
-        if (nk < 0) {
-          atomicOr(&flags[FLAG_DOMAIN], 1);
-          nk = c;
-        }
-        pt.key[s] = nk;
-        pt.px[s] = x;
-        pt.py[s] = y;
-        pt.vx[s] = vx;
-        pt.vy[s] = vy;
-        if (dg_fdx) {
+        if (dg_fdx || k.acx) {
           const int id = pt.pid[s];
-          dg_fdx[id] = fdx;
-          dg_fdy[id] = fdy;
+          if (dg_fdx) {
+            dg_fdx[id] = fdx;
+            dg_fdy[id] = fdy;
+          }
+          if (k.acx) {
+            k.acx[id] = ax;
+            k.acy[id] = ay;
+          }
         }
-        return nk;
+        return advance_one<P>(k, pt, s, cx, cy, c, x, y, vx, vy, ax, ay, flags);
       };
       // A particle that stays in its cell takes the next rank among the cell's
       // stayers (in segment order); one that moves counts atomically among
@@ -987,24 +1005,18 @@ __device__ __forceinline__ void drag_body_flat(const int bidx, const int gdim, P
       fdy = dv<P>(-fgy * pry, Sy);
     const T ax = k.geff[0] + dv<P>(fdx + k.fp * gpx, k.m);
     const T ay = k.geff[1] + dv<P>(fdy + k.fp * gpy, k.m);
-    vx = vx + ax;
-    vy = vy + ay;
-    int nk = Pos<P>::move(k, pcx, pcy, x, y, vx, vy);
-    if (nk < 0) {
-      atomicOr(&flags[FLAG_DOMAIN], 1);
-      nk = pc;
-    }
-    pt.key[s] = nk;
-    pt.px[s] = x;
-    pt.py[s] = y;
-    pt.vx[s] = vx;
-    pt.vy[s] = vy;
-    if (dg_fdx) {
+    if (dg_fdx || k.acx) {
       const int id = pt.pid[s];
-      dg_fdx[id] = fdx;
-      dg_fdy[id] = fdy;
+      if (dg_fdx) {
+        dg_fdx[id] = fdx;
+        dg_fdy[id] = fdy;
+      }
+      if (k.acx) {
+        k.acx[id] = ax;
+        k.acy[id] = ay;
+      }
     }
-    return nk;
+    return advance_one<P>(k, pt, s, pcx, pcy, pc, x, y, vx, vy, ax, ay, flags);
   };
   // The new cell's count: a particle that stays takes the given rank among its
   // cell's stayers (segment order); one that moves counts atomically among the
@@ -1159,6 +1171,52 @@ __global__ __launch_bounds__(BLOCK) LBDPS_WAVES6 void k_drag_flat(Parts<typename
                                                      int32_t *__restrict__ stay) {
   drag_body_flat<P>(xcd_block<XCD_RUN_DRAG>(blockIdx.x, gridDim.x), gridDim.x, pt, fl, cs, lut, k, count, rank,
                     flags, dg_fdx, dg_fdy, zero_part, ts, stay);
+}
+
+// Sub-steps after the first of a lattice step (n_sub > 1): one thread per slot
+// advances its particle by h under the acceleration the drag kernel held for
+// its index, then counts it into its new cell as an arrival.  Every cell's
+// segment is rebuilt from arrivals, so each particle also clears its old
+// cell's stayer count (every cell with stayers still holds them, since the
+// collision stage moves no particle).  The per-tile counts of the arrivals go
+// through a workgroup histogram over the tiles near the workgroup's first cell.
+template <int P>
+__device__ __forceinline__ void advance_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
+    Consts<typename Prec<P>::T> k, int32_t *__restrict__ count, int32_t *__restrict__ rank,
+    int32_t *__restrict__ stay, int32_t *flags, TileSums ts) {
+  using T = typename Prec<P>::T;
+  __shared__ int hist[HIST_MAX];
+  const int s = bidx * BLOCK + threadIdx.x;
+  const int k0 = pt.key[min(bidx * BLOCK, k.npart - 1)];
+  const int tlo = max(0, k0 - k.nx - 1) >> ts.shift;
+  if (threadIdx.x < HIST_MAX) hist[threadIdx.x] = 0;
+  __syncthreads();
+  if (s < k.npart) {
+    const int key = pt.key[s], id = pt.pid[s];
+    int cx, cy;
+    cell_xy(k, key, cx, cy);
+    const T x = pt.px[s], y = pt.py[s], vx = pt.vx[s], vy = pt.vy[s];
+    const T ax = k.acx[id], ay = k.acy[id];
+    const int nk = advance_one<P>(k, pt, s, cx, cy, key, x, y, vx, vy, ax, ay, flags);
+    stay[key] = 0;
+    rank[s] = atomicAdd(&count[nk], 1) | RANK_MOVED;
+    const int dt = (nk >> ts.shift) - tlo;
+    if (dt >= 0 && dt < HIST_MAX)
+      atomicAdd(&hist[dt], 1);
+    else
+      ts.add(nk >> ts.shift, 1);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < HIST_MAX && tlo + (int)threadIdx.x < ts.ntiles) {
+    const int h = hist[threadIdx.x];
+    if (h) ts.add(tlo + (int)threadIdx.x, h);
+  }
+}
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_advance(Parts<typename Prec<P>::T> pt, Consts<typename Prec<P>::T> k,
+                                                   int32_t *__restrict__ count, int32_t *__restrict__ rank,
+                                                   int32_t *__restrict__ stay, int32_t *flags, TileSums ts) {
+  advance_body<P>(blockIdx.x, gridDim.x, pt, k, count, rank, stay, flags, ts);
 }
 
 // ------------------------------------------------------------------ A1: binning (counting sort by cell)

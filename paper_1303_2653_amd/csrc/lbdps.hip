@@ -113,9 +113,13 @@ std::vector<double> build_lut(const lbdps_params &p) {
   return L;
 }
 
+// Particle sub-steps per lattice step (0 is taken as 1).
+int n_sub_of(const lbdps_params &p) { return p.n_sub > 1 ? p.n_sub : 1; }
+
 struct DConsts {  // FP64 master copy of the kernel constants
   double tau, d, mu, vp, m, msum, one_e, e_pw, r, geff[2], fp, halfG[2], src[Q];
   double cs18;  // 18 C_s^2 (Eq. 15)
+  double h;     // particle sub-step length 1 / n_sub
 };
 
 DConsts make_dconsts(const lbdps_params &p) {
@@ -133,6 +137,7 @@ DConsts make_dconsts(const lbdps_params &p) {
   c.geff[1] = (1.0 - p.rho_g / p.rho_s) * p.g[1];
   c.fp = (double)p.pressure_force_sign * c.vp;
   c.cs18 = 18.0 * p.cs_smag * p.cs_smag;
+  c.h = 1.0 / (double)n_sub_of(p);
   c.halfG[0] = 0.5 * p.body_force[0];
   c.halfG[1] = 0.5 * p.body_force[1];
   for (int i = 0; i < Q; ++i)
@@ -195,6 +200,7 @@ struct lbdps_ctx {
   double *cons_pc = nullptr, *cons_pp = nullptr, *cons_out = nullptr;
   int32_t *dg_n = nullptr;
   void *dg_vsx = nullptr, *dg_vsy = nullptr, *dg_fdx = nullptr, *dg_fdy = nullptr;
+  void *acx = nullptr, *acy = nullptr;  // accelerations held over the lattice step (n_sub > 1)
   // per-kernel event timing
   uint32_t timed = 0;
   struct Mark {
@@ -266,6 +272,11 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     dfx = raw(N * sT);
     dfy = raw(N * sT);
   }
+  char *acx = nullptr, *acy = nullptr;
+  if (n_sub_of(p) > 1) {
+    acx = raw(N * sT);
+    acy = raw(N * sT);
+  }
   if (x) {
     x->f[0] = f0;
     x->f[1] = f1;
@@ -316,6 +327,8 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->dg_vsy = dvy;
     x->dg_fdx = dfx;
     x->dg_fdy = dfy;
+    x->acx = acx;
+    x->acy = acy;
   }
   return cv.off + 256;
 }
@@ -412,6 +425,9 @@ template <int P> struct Impl {
     }
     k.fp = (T)d.fp;
     for (int i = 0; i < Q; ++i) k.src[i] = (T)d.src[i];
+    k.h = (T)d.h;
+    k.acx = (T *)x->acx;
+    k.acy = (T *)x->acy;
     k.spin_limit = 1u << 22;
     return k;
   }
@@ -442,9 +458,9 @@ template <int P> struct Impl {
   // x->count (slots in x->rank) and the tile sums in x->tile_sum; cell starts
   // in one pass, then every record moves to its slot in the other storage.
   // Each cell's segment is put in particle-index order by the next collision.
-  static void sort_counted(lbdps_ctx *x, bool tile_sums = true) {
+  static void sort_counted(lbdps_ctx *x, bool tile_sums = true, bool extra = false) {
     if (tile_sums) {
-      tlaunch(x, LBDPS_K_SCAN, false, k_scan_cells, dim3(x->ntiles), x->count, (long long)x->C, tiles(x), x->cs,
+      tlaunch(x, LBDPS_K_SCAN, extra, k_scan_cells, dim3(x->ntiles), x->count, (long long)x->C, tiles(x), x->cs,
               (const int32_t *)x->stay);
     } else {
       tstart(x, LBDPS_K_SCAN);
@@ -452,7 +468,7 @@ template <int P> struct Impl {
       tstop(x, LBDPS_K_SCAN);
     }
     const int N = (int)x->n;
-    tlaunch(x, LBDPS_K_SCATTER, false, k_scatter<T>, dim3(std::max(nblocks(N), 1)), parts(x, x->cp),
+    tlaunch(x, LBDPS_K_SCATTER, extra, k_scatter<T>, dim3(std::max(nblocks(N), 1)), parts(x, x->cp),
             parts(x, 1 - x->cp), (const int32_t *)x->rank, (const int32_t *)x->cs, N, x->slot, tiles(x),
             (const int32_t *)x->stay);
     x->cp = 1 - x->cp;
@@ -468,14 +484,16 @@ template <int P> struct Impl {
     x->bins_valid = true;
   }
 
-  static void hard_spheres(lbdps_ctx *x) {
+  // extra: a further sub-step of the same lattice step (its launches add time,
+  // not launch counts)
+  static void hard_spheres(lbdps_ctx *x, bool extra = false) {
     const int N = (int)x->n;
     if (N == 0) return;
     const Consts<T> k = consts(x);
-    tlaunch(x, LBDPS_K_CONTACTS, false, k_contacts<P>, dim3(nblocks(N)), parts(x, x->cp), (const int32_t *)x->cs, k,
+    tlaunch(x, LBDPS_K_CONTACTS, extra, k_contacts<P>, dim3(nblocks(N)), parts(x, x->cp), (const int32_t *)x->cs, k,
             x->adj(), x->deg, x->done, x->ticket, x->flags, x->pair_part, x->wall0_part, x->chunk_busy,
             x->need_sweep, x->roots, x->rcount);
-    tlaunch(x, LBDPS_K_RESOLVE, false, k_resolve_clusters<P>, dim3(x->cluster_groups()), parts(x, x->cp), x->adj(),
+    tlaunch(x, LBDPS_K_RESOLVE, extra, k_resolve_clusters<P>, dim3(x->cluster_groups()), parts(x, x->cp), x->adj(),
             (const int32_t *)x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part,
             (const long long *)x->roots, (const int32_t *)x->rcount, nblocks(N));
     tlaunch(x, LBDPS_K_RESOLVE, true, k_resolve<P>, dim3(resolve_blocks(x)), parts(x, x->cp),
@@ -500,6 +518,13 @@ template <int P> struct Impl {
                 x->stay);
         sort_counted(x);
         hard_spheres(x);
+        // further particle sub-steps under the accelerations the drag kernel held
+        for (int sub = 1; sub < n_sub_of(x->p); ++sub) {
+          tlaunch(x, LBDPS_K_DRAG, true, k_advance<P>, dim3(nblocks(x->n)), parts(x, x->cp), k, x->count, x->rank,
+                  x->stay, x->flags, tiles(x));
+          sort_counted(x, true, true);
+          hard_spheres(x, true);
+        }
       }
       x->cf = 1 - x->cf;
       x->step += 1;
@@ -639,6 +664,8 @@ lbdps_status lbdps_validate_params(const lbdps_params *p, int64_t max_particles)
     return fail(LBDPS_E_INVALID, "pressure_force_sign must be -1, 0 or 1");
   if (!is_fin(p->omega_dense)) return fail(LBDPS_E_INVALID, "omega_dense must be finite");
   if (!is_fin(p->cs_smag) || p->cs_smag < 0) return fail(LBDPS_E_INVALID, "cs_smag must be >= 0");
+  if (p->n_sub < 0 || p->n_sub > LBDPS_MAX_SUBSTEPS)
+    return fail(LBDPS_E_INVALID, "n_sub must be in [0, " + std::to_string(LBDPS_MAX_SUBSTEPS) + "]");
   if (p->precision < 0 || p->precision > 3) return fail(LBDPS_E_INVALID, "precision must be 0..3");
   if (p->diagnostics < 0 || p->diagnostics > 1) return fail(LBDPS_E_INVALID, "diagnostics must be 0 or 1");
   // below 2^29: every per-particle and per-cell array is addressed by 32-bit byte offsets
@@ -1226,6 +1253,7 @@ lbdps_status batch_layout(const lbdps_params *beds, int32_t nbeds, const int64_t
     if (st != LBDPS_OK) return fail(st, "bed " + std::to_string(b) + ": " + lbdps_last_error());
     if (beds[b].precision != prec) return fail(LBDPS_E_INVALID, "all beds of a batch share one precision");
     if (beds[b].diagnostics) return fail(LBDPS_E_UNSUPPORTED, "batched beds do not record diagnostics");
+    if (n_sub_of(beds[b]) > 1) return fail(LBDPS_E_UNSUPPORTED, "batched beds take one particle sub-step");
   }
   size_t tb = 0;
   lbdps_status st = dispatch_batch(prec, [&](auto impl) {

@@ -23,6 +23,7 @@ LBDPS_E_UNSUPPORTED, LBDPS_E_NONFINITE, LBDPS_E_CAPACITY, LBDPS_E_STALL = -4, -5
 LBDPS_FP64, LBDPS_FP32, LBDPS_FP32_STORE_FP16, LBDPS_FP32_STORE_BF16 = 0, 1, 2, 3
 LBDPS_BC_PERIODIC, LBDPS_BC_WALL, LBDPS_BC_INLET, LBDPS_BC_OUTLET = 0, 1, 2, 3
 LBDPS_MAX_CONTACTS = 32
+LBDPS_MAX_SUBSTEPS = 64
 KERNELS = ["collide", "drag", "scan", "scatter", "contacts", "resolve"]
 
 PRECISIONS = {"fp64": LBDPS_FP64, "fp32": LBDPS_FP32, "fp16": LBDPS_FP32_STORE_FP16, "bf16": LBDPS_FP32_STORE_BF16}
@@ -38,7 +39,7 @@ class lbdps_params(ctypes.Structure):
         ("e_pp", c_dbl), ("e_pw", c_dbl), ("g", c_dbl * 2), ("body_force", c_dbl * 2),
         ("drag_ratio_mode", c_i32), ("u_gas_porosity", c_i32), ("omega_mode", c_i32),
         ("pressure_force_sign", c_i32), ("omega_dense", c_dbl), ("cs_smag", c_dbl),
-        ("precision", c_i32), ("diagnostics", c_i32),
+        ("precision", c_i32), ("diagnostics", c_i32), ("n_sub", c_i32),
     ]
 
 
@@ -134,6 +135,7 @@ def make_params(cfg: dict, precision=None, diagnostics: bool = False) -> lbdps_p
     prec = precision if precision is not None else cfg.get("precision", "fp32")
     p.precision = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
     p.diagnostics = int(bool(diagnostics))
+    p.n_sub = int(cfg.get("n_sub", 1))
     return p
 
 

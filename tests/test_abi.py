@@ -25,7 +25,8 @@ def test_struct_layout_matches_header():
     assert L.lbdps_params.drag_ratio_mode.offset == 104
     assert L.lbdps_params.omega_dense.offset == 120
     assert L.lbdps_params.precision.offset == 136
-    assert ctypes.sizeof(L.lbdps_params) == 144
+    assert L.lbdps_params.n_sub.offset == 144
+    assert ctypes.sizeof(L.lbdps_params) == 152
 
 
 def _status(p, nmax=10):
@@ -44,7 +45,8 @@ def test_validation_accepts_workloads():
     ("e_pp", 1.5, L.LBDPS_E_INVALID), ("e_pw", -0.1, L.LBDPS_E_INVALID), ("rho_s", 0.0, L.LBDPS_E_INVALID),
     ("precision", 7, L.LBDPS_E_INVALID), ("pressure_force_sign", 2, L.LBDPS_E_INVALID),
     ("cs_smag", -0.1, L.LBDPS_E_INVALID), ("cs_smag", float("inf"), L.LBDPS_E_INVALID),
-    ("drag_ratio_mode", 3, L.LBDPS_E_INVALID),
+    ("drag_ratio_mode", 3, L.LBDPS_E_INVALID), ("n_sub", -1, L.LBDPS_E_INVALID),
+    ("n_sub", L.LBDPS_MAX_SUBSTEPS + 1, L.LBDPS_E_INVALID),
 ])
 def test_validation_rejects(field, value, code):
     p = L.make_params(synth.bubble_small())
@@ -63,6 +65,20 @@ def test_validation_rejects_bad_faces():
     p = L.make_params(synth.bubble_small())
     assert _status(p, -1) == L.LBDPS_E_SHAPE
     assert L.lbdps_validate_params(None, 0) == L.LBDPS_E_INVALID
+
+
+def test_substeps_accepted_and_sized():
+    """n_sub 0 and 1 mean one sub-step; more keep two accelerations per particle."""
+    p = L.make_params(synth.bubble_small())
+    for v in (0, 1, 4, L.LBDPS_MAX_SUBSTEPS):
+        p.n_sub = v
+        assert _status(p) == L.LBDPS_OK
+    p.n_sub = 1
+    b1 = L.workspace_bytes(p, 2000)
+    p.n_sub = 0
+    assert L.workspace_bytes(p, 2000) == b1
+    p.n_sub = 3
+    assert L.workspace_bytes(p, 2000) >= b1 + 2 * 2000 * 4
 
 
 def test_workspace_bytes_scale():
@@ -115,6 +131,11 @@ def test_batch_rejects_mixed_precision_and_diagnostics():
     params, nmax = _batch(cfgs, "fp32")
     params[0].diagnostics = 1
     assert L.lbdps_batch_workspace_bytes(params, 2, nmax, ctypes.byref(out)) == L.LBDPS_E_UNSUPPORTED
+    params, nmax = _batch(cfgs, "fp32")
+    params[1].n_sub = 2  # batched beds take one particle sub-step
+    assert L.lbdps_batch_workspace_bytes(params, 2, nmax, ctypes.byref(out)) == L.LBDPS_E_UNSUPPORTED
+    params[1].n_sub = 1
+    assert L.lbdps_batch_workspace_bytes(params, 2, nmax, ctypes.byref(out)) == L.LBDPS_OK
     params, nmax = _batch(cfgs, "fp32")
     assert L.lbdps_batch_workspace_bytes(params, 0, nmax, ctypes.byref(out)) == L.LBDPS_E_SHAPE
     params[1].tau = 0.4

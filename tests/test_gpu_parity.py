@@ -67,6 +67,9 @@ TINY_CASES = {
     # Smagorinsky sub-grid model on (Eqs. 12-15)
     "les-riser": dict(bc=("wall", "wall", "periodic", "periodic"), G=(0.0, 4e-5), g=(0.0, -3e-5), cs_smag=2.0),
     "les-inlet": dict(bc=("periodic", "periodic", "inlet", "outlet"), band=10.0, cs_smag=1.0),
+    # particle sub-steps: contacts and collisions after every sub-step of a lattice step
+    "substeps-riser": dict(bc=("wall", "wall", "periodic", "periodic"), G=(0.0, 2e-5), g=(0.0, -3e-5), n_sub=4),
+    "substeps-box": dict(bc=("wall",) * 4, band=12.0, g=(2e-5, -1e-5), n_sub=3),
 }
 
 
@@ -280,7 +283,7 @@ def drag_error_bound(ref_out, pos0, vel0, cfg, eta):
     return bound, K
 
 
-@pytest.mark.parametrize("name", ["bubble", "riser_crop", "riser_crop_les"])
+@pytest.mark.parametrize("name", ["bubble", "riser_crop", "riser_crop_les", "bubble_sub4"])
 def test_fp32_one_step_full_size(name):
     """One coupled step in FP32 at the workload's full size from a shared
     FP32-representable state, against the FP64 oracle step from the same state.
@@ -288,11 +291,15 @@ def test_fp32_one_step_full_size(name):
     Eq. 28 is a ratio of sums that can nearly cancel, so its FP32 error is held
     to the first-order bound of drag_error_bound with eta = 1e-5, and the
     velocity to 1e-5 max|v| plus that bound over the particle mass."""
-    les = name.endswith("_les")
-    cfg = getattr(synth, name[:-4] if les else name)()
-    if les:
+    base, _, variant = name.rpartition("_")
+    if variant not in ("les", "sub4"):
+        base, variant = name, ""
+    cfg = getattr(synth, base)()
+    if variant == "les":
         cfg["cs_smag"] = 4.0  # Smagorinsky model on (Eqs. 12-15)
-    say("workload", cfg["name"], "C_s", cfg.get("cs_smag", 0.0))
+    if variant == "sub4":
+        cfg["n_sub"] = 4  # four particle sub-steps per lattice step
+    say("workload", cfg["name"], "C_s", cfg.get("cs_smag", 0.0), "n_sub", cfg.get("n_sub", 1))
     warm = oracle.Sim(cfg)
     warm.run(20)  # develop flow and velocities, then hand the FP32-held state to both sides
     f, pos, vel = storage_repr.state(cfg, warm.f, warm.pos, warm.vel, "fp32")

@@ -12,8 +12,11 @@ if not torch.cuda.is_available():
 L = pytest.importorskip("paper_1303_2653_amd.lbdps")
 
 
-def test_kernel_times_single_bed():
-    cfg = synth.tiny(nx=64, ny=48, n=600, seed=21, band=24.0, vel_scale=1e-3)
+@pytest.mark.parametrize("nsub", [1, 3])
+def test_kernel_times_single_bed(nsub):
+    """With particle sub-steps every phase still counts one launch per step
+    (the later sub-steps' launches add their time)."""
+    cfg = synth.tiny(nx=64, ny=48, n=600, seed=21, band=24.0, vel_scale=1e-3, n_sub=nsub)
     sim = L.Sim(cfg, precision="fp32")
     sim.step(2)
     sim.time_kernels(L.KERNELS)
