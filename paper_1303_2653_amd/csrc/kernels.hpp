@@ -863,7 +863,7 @@ __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, 
             dg_fdx[id] = fdx;
             dg_fdy[id] = fdy;
           }
-          if (k.acx) {
+          if (k.acx) {  // held for the later sub-steps, by particle index
             k.acx[id] = ax;
             k.acy[id] = ay;
           }
@@ -1011,7 +1011,7 @@ __device__ __forceinline__ void drag_body_flat(const int bidx, const int gdim, P
         dg_fdx[id] = fdx;
         dg_fdy[id] = fdy;
       }
-      if (k.acx) {
+      if (k.acx) {  // held for the later sub-steps, by particle index
         k.acx[id] = ax;
         k.acy[id] = ay;
       }
@@ -1173,50 +1173,78 @@ __global__ __launch_bounds__(BLOCK) LBDPS_WAVES6 void k_drag_flat(Parts<typename
                     flags, dg_fdx, dg_fdy, zero_part, ts, stay);
 }
 
-// Sub-steps after the first of a lattice step (n_sub > 1): one thread per slot
-// advances its particle by h under the acceleration the drag kernel held for
-// its index, then counts it into its new cell as an arrival.  Every cell's
-// segment is rebuilt from arrivals, so each particle also clears its old
-// cell's stayer count (every cell with stayers still holds them, since the
-// collision stage moves no particle).  The per-tile counts of the arrivals go
-// through a workgroup histogram over the tiles near the workgroup's first cell.
+// Sub-steps after the first of a lattice step (n_sub > 1): one thread per
+// cell advances the cell's particles by h under the accelerations the drag
+// kernel held for their indices, and counts each into its new cell as the
+// drag kernel does: a particle that stays takes the next rank among its cell's
+// stayers (segment order), one that moves counts atomically among the
+// arrivals of its new cell.  A workgroup covers BLOCK consecutive cells; the
+// per-tile counts go through a workgroup histogram over the tiles its
+// particles can reach in one cell move (periodic jumps go to the global sums).
 template <int P>
 __device__ __forceinline__ void advance_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
-    Consts<typename Prec<P>::T> k, int32_t *__restrict__ count, int32_t *__restrict__ rank,
-    int32_t *__restrict__ stay, int32_t *flags, TileSums ts) {
+    Consts<typename Prec<P>::T> k, const int32_t *__restrict__ cs, int32_t *__restrict__ count,
+    int32_t *__restrict__ rank, int32_t *__restrict__ stay, int32_t *flags, TileSums ts) {
   using T = typename Prec<P>::T;
   __shared__ int hist[HIST_MAX];
-  const int s = bidx * BLOCK + threadIdx.x;
-  const int k0 = pt.key[min(bidx * BLOCK, k.npart - 1)];
-  const int tlo = max(0, k0 - k.nx - 1) >> ts.shift;
+  const int c0 = bidx * BLOCK, c = c0 + (int)threadIdx.x;
+  const int tlo = max(0, c0 - k.nx - 1) >> ts.shift;
+  const int thi = min(k.C - 1, c0 + BLOCK + k.nx) >> ts.shift;
+  const int nh = thi - tlo + 1;
   if (threadIdx.x < HIST_MAX) hist[threadIdx.x] = 0;
   __syncthreads();
-  if (s < k.npart) {
-    const int key = pt.key[s], id = pt.pid[s];
+  if (c < k.C) {
+    const int a0 = cs[c], a1 = cs[c + 1], n = a1 - a0;
     int cx, cy;
-    cell_xy(k, key, cx, cy);
-    const T x = pt.px[s], y = pt.py[s], vx = pt.vx[s], vy = pt.vy[s];
-    const T ax = k.acx[id], ay = k.acy[id];
-    const int nk = advance_one<P>(k, pt, s, cx, cy, key, x, y, vx, vy, ax, ay, flags);
-    stay[key] = 0;
-    rank[s] = atomicAdd(&count[nk], 1) | RANK_MOVED;
-    const int dt = (nk >> ts.shift) - tlo;
-    if (dt >= 0 && dt < HIST_MAX)
-      atomicAdd(&hist[dt], 1);
-    else
-      ts.add(nk >> ts.shift, 1);
+    cell_xy(k, c, cx, cy);
+    int nstay = 0;
+    auto count_new = [&](int s, int nk) {
+      if (nk == c) rank[s] = nstay++;
+      else rank[s] = atomicAdd(&count[nk], 1) | RANK_MOVED;
+      const int dt = (nk >> ts.shift) - tlo;
+      if (nh <= HIST_MAX && dt >= 0 && dt < nh)
+        atomicAdd(&hist[dt], 1);
+      else
+        ts.add(nk >> ts.shift, 1);
+    };
+    if (n <= SEG_REG) {  // short segment: every record loaded before any is advanced
+      int id[SEG_REG];
+      T x[SEG_REG], y[SEG_REG], vx[SEG_REG], vy[SEG_REG];
+#pragma unroll
+      for (int u = 0; u < SEG_REG; ++u)
+        if (u < n) {
+          id[u] = pt.pid[a0 + u];
+          x[u] = pt.px[a0 + u];
+          y[u] = pt.py[a0 + u];
+          vx[u] = pt.vx[a0 + u];
+          vy[u] = pt.vy[a0 + u];
+        }
+#pragma unroll
+      for (int u = 0; u < SEG_REG; ++u)
+        if (u < n)
+          count_new(a0 + u, advance_one<P>(k, pt, a0 + u, cx, cy, c, x[u], y[u], vx[u], vy[u], k.acx[id[u]],
+                                           k.acy[id[u]], flags));
+    } else {
+      for (int s = a0; s < a1; ++s) {
+        const int id = pt.pid[s];
+        count_new(s, advance_one<P>(k, pt, s, cx, cy, c, pt.px[s], pt.py[s], pt.vx[s], pt.vy[s], k.acx[id],
+                                    k.acy[id], flags));
+      }
+    }
+    stay[c] = nstay;
   }
   __syncthreads();
-  if ((int)threadIdx.x < HIST_MAX && tlo + (int)threadIdx.x < ts.ntiles) {
+  if ((int)threadIdx.x < min(nh, HIST_MAX)) {
     const int h = hist[threadIdx.x];
     if (h) ts.add(tlo + (int)threadIdx.x, h);
   }
 }
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_advance(Parts<typename Prec<P>::T> pt, Consts<typename Prec<P>::T> k,
-                                                   int32_t *__restrict__ count, int32_t *__restrict__ rank,
-                                                   int32_t *__restrict__ stay, int32_t *flags, TileSums ts) {
-  advance_body<P>(blockIdx.x, gridDim.x, pt, k, count, rank, stay, flags, ts);
+                                                   const int32_t *__restrict__ cs, int32_t *__restrict__ count,
+                                                   int32_t *__restrict__ rank, int32_t *__restrict__ stay,
+                                                   int32_t *flags, TileSums ts) {
+  advance_body<P>(blockIdx.x, gridDim.x, pt, k, cs, count, rank, stay, flags, ts);
 }
 
 // ------------------------------------------------------------------ A1: binning (counting sort by cell)

@@ -513,15 +513,15 @@ template <int P> struct Impl {
       if (x->n > 0) {
         const int nt = drag_tiles(x);
         tlaunch(x, LBDPS_K_DRAG, false, drag_flat(nt) ? k_drag_flat<P> : k_drag<P>, dim3(nt), parts(x, x->cp),
-                fields(x), (const int32_t *)x->cs, (const T *)x->lut, k, x->count, x->rank, x->flags,
+                fields(x), (const int32_t *)x->cs, (const T *)x->lut, consts(x), x->count, x->rank, x->flags,
                 dg ? (T *)x->dg_fdx : nullptr, dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x),
                 x->stay);
         sort_counted(x);
         hard_spheres(x);
         // further particle sub-steps under the accelerations the drag kernel held
         for (int sub = 1; sub < n_sub_of(x->p); ++sub) {
-          tlaunch(x, LBDPS_K_DRAG, true, k_advance<P>, dim3(nblocks(x->n)), parts(x, x->cp), k, x->count, x->rank,
-                  x->stay, x->flags, tiles(x));
+          tlaunch(x, LBDPS_K_DRAG, true, k_advance<P>, dim3(nblocks(x->C)), parts(x, x->cp), consts(x),
+                  (const int32_t *)x->cs, x->count, x->rank, x->stay, x->flags, tiles(x));
           sort_counted(x, true, true);
           hard_spheres(x, true);
         }
