@@ -280,6 +280,26 @@ def conservation(p: OrcParams, f, vel):
     return out
 
 
+def voidage(p: OrcParams, pos, y0=0, y1=None, threshold=0.85):
+    """Voidage statistics of Sec. 3 at particle positions pos [N][2]: the gas
+    voidage of each cell is the 3-D one of Eq. 11 for the cell's count (the
+    voidage of the drag laws, R42).  Returns (row_sum [ny]: sum over x of
+    eps_g per row; col_sum [nx]: sum over rows y0..y1-1 per column; count:
+    cells of rows y0..y1-1 with eps_g > threshold).  The equivalent bubble
+    diameter of Sec. 3.1 is then sqrt(4 count / pi) cells."""
+    nx, ny = p.nx, p.ny
+    y1 = ny if y1 is None else y1
+    pos = np.asarray(pos, np.float64).reshape(-1, 2)
+    cell = (np.floor(pos[:, 1]).astype(np.int64) * nx + np.floor(pos[:, 0]).astype(np.int64))
+    n = np.bincount(cell, minlength=nx * ny).reshape(ny, nx)
+    eg = {k: cell_props(p, k)["eps_g"] for k in np.unique(n)}
+    e = np.vectorize(eg.get, otypes=[np.float64])(n)
+    rows = e.sum(axis=1)
+    cols = e[y0:y1].sum(axis=0)
+    count = int((e[y0:y1] > threshold).sum())
+    return rows, cols, count
+
+
 def equilibrium_state(nx, ny, rho=1.0, ux=0.0, uy=0.0):
     """f = f^eq(rho, u) on every node, [9][ny][nx] (R33 initial state)."""
     f = np.empty((9, ny, nx))

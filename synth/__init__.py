@@ -10,7 +10,8 @@ stream with seed s is mix(s + (k+1) * 0x9E3779B97F4A7C15); a uniform double is
 (x >> 11) * 2^-53.  Draws are consumed in particle-index order, x then y.
 
 The workloads borrow the shapes of the paper's two experiments (bubble
-injection, Table 1; riser, Table 2) at the sizes of the benchmark plan.  No
+injection, Table 1; riser, Table 2) at the sizes of the benchmark plan;
+paper_bubble and paper_riser take the tables' own sizes and parameters.  No
 dataset is involved.
 """
 from __future__ import annotations
@@ -139,6 +140,78 @@ def riser_crop(seed: int = 3, precision: str = "fp32") -> dict:
 def riser_large(seed: int = 3) -> dict:
     """2048x8192 bed (16.8 M cells) at the riser's density: 16 000 000 spheres."""
     return riser(2048, 8192, 16_000_000, seed, True, "fp32")
+
+
+# The paper's own experiments in lattice units (Tables 1 and 2; h = 2.7e-4 m).
+# Velocities convert by dt / h, gravity 9.81 m/s^2 to 9.81 dt^2 / h, and the gas
+# viscosity to mu_lu = mu_g dt / (rho_g h^2), which gives tau = 3 mu_lu + 1/2
+# (Eq. 3, rho_g = 1 in lattice units).  Where a printed dimensionless value
+# disagrees with its dimensional one (the bubble's jet velocity, the riser's
+# viscosity), the converted value is taken.  tau lies so close to 1/2 that the
+# Smagorinsky model (Eqs. 12-15) is on, with C_s = PAPER_CS (the paper gives no
+# value).
+PAPER_H = 2.7e-4
+PAPER_CS = 0.3
+
+
+def paper_gravity(dt: float) -> float:
+    """9.81 m/s^2 in lattice units for time step dt (s) and cell size PAPER_H."""
+    return 9.81 * dt * dt / PAPER_H
+
+
+def paper_tau(dt: float, mu_g: float = 1.8872e-5, rho_g: float = 1.1795) -> float:
+    """tau = 3 mu_lu + 1/2 with mu_lu = mu_g dt / (rho_g h^2)."""
+    return 3.0 * mu_g * dt / (rho_g * PAPER_H * PAPER_H) + 0.5
+
+
+def paper_bubble(seed: int = 11, phi: float = 0.5) -> dict:
+    """Table 1: a 25 x 100 bed (walls at x, gas inlet at the bottom, outlet at
+    the top) holding 15 000 spheres of d = 0.2 at incipient fluidization; gas
+    enters at v_mf = 0.0025 m/s = 1.25e-5 except through the 3-cell central
+    orifice x in [11, 14), where a jet of 0.8 m/s = 0.004 lasts 0.006 s = 4 444
+    steps of 1.35e-6 s (cfg["pulse_steps"]; cfg["inlet_after"] is the profile
+    afterwards).  tau = 3 (2.963e-4) + 1/2.  The spheres sit on a jittered 100 x 150 lattice
+    filling a bottom band of 2-D solid fraction phi (37.7 rows at 0.5), jitter
+    +-0.02 per axis so no two touch at t = 0."""
+    nx, ny, n, d = 25, 100, 15_000, 0.2
+    ncol, nrow = 100, 150
+    band = n * math.pi * d * d / 4.0 / (phi * nx)
+    dx, dy = nx / ncol, band / nrow
+    k = np.arange(n)
+    jit = (uniform(seed, 2 * n).reshape(n, 2) * 2.0 - 1.0) * 0.02
+    pos = np.empty((n, 2))
+    pos[:, 0] = (k % ncol + 0.5) * dx + jit[:, 0]
+    pos[:, 1] = (k // ncol + 0.5) * dy + jit[:, 1]
+    v_mf, v_inj = 0.0025 * 1.35e-6 / PAPER_H, 0.8 * 1.35e-6 / PAPER_H
+    after = np.full(nx, v_mf)
+    inlet = after.copy()
+    inlet[11:14] = v_inj
+    return _cfg("paper-bubble-25x100-15k-fp64", nx, ny, ["wall", "wall", "inlet", "outlet"], pos, 26_000,
+                d=d, tau=paper_tau(1.35e-6), cs_smag=PAPER_CS, inlet_uy=inlet, inlet_after=after,
+                pulse_steps=int(0.006 / 1.35e-6), g=(0.0, -paper_gravity(1.35e-6)), precision="fp64")
+
+
+def paper_riser(seed: int = 12) -> dict:
+    """Table 2: a 60 x 720 riser holding 123 921 spheres of d = 0.2 (2-D solid
+    fraction 0.09012, uniform), time step 6e-6 s, tau = 3 (1.317e-3) + 1/2.  The
+    circulating loop is closed through a periodic y axis (particles leaving
+    the top re-enter at the bottom); the gas starts uniform at the table's
+    inlet velocity 1.52 m/s = 0.0338 (cfg["u0"]) and is driven by a body force equal to
+    the suspension's weight per cell, so the bed neither accelerates nor
+    settles as a whole (R43)."""
+    nx, ny, n, d = 60, 720, 123_921, 0.2
+    r = 0.5 * d
+    u = uniform(seed, 2 * n).reshape(n, 2)
+    pos = np.empty((n, 2))
+    pos[:, 0] = r + (nx - 2 * r) * u[:, 0]
+    pos[:, 1] = ny * u[:, 1]
+    pos = pos[cell_order(pos, nx)]
+    g = paper_gravity(6.0e-6)
+    m = 788.5 * math.pi * d ** 3 / 6.0
+    body = n * m * (1.0 - 1.0 / 788.5) * g / (nx * ny)
+    return _cfg("paper-riser-60x720-124k-fp64", nx, ny, ["wall", "wall", "periodic", "periodic"], pos, 100_000,
+                d=d, tau=paper_tau(6.0e-6), cs_smag=PAPER_CS, inlet_uy=None, u0=(0.0, 1.52 * 6.0e-6 / PAPER_H),
+                g=(0.0, -g), G=(0.0, body), precision="fp64")
 
 
 # Gravity of the batched beds: the bubble bed's balance of bed weight against
