@@ -199,6 +199,32 @@ lbdps_status lbdps_conservation(lbdps_ctx *ctx, double h_out[6]);
  */
 lbdps_status lbdps_counters(lbdps_ctx *ctx, int64_t h_out[4]);
 
+/*
+ * Replace the inlet profile used by INLET faces (Sec. 3.1: the gas pulse of the
+ * bubble experiment is switched off this way).  h_inlet_uy: host array of nx
+ * finite y velocities, read before return.  Waits for the context's queued work
+ * first, so steps already enqueued keep the old profile.  LBDPS_E_INVALID for a
+ * NULL array or a non-finite value.
+ */
+lbdps_status lbdps_set_inlet(lbdps_ctx *ctx, const double *h_inlet_uy);
+
+/*
+ * Voidage statistics of the current particle positions (Sec. 3: the equivalent
+ * bubble diameter of Sec. 3.1 and the time-averaged voidage profiles of
+ * Sec. 3.2).  The gas voidage of a cell is the 3-D voidage of Eq. 11 for the
+ * cell's particle count, eps_g = 1 - eps_s,3d, as the drag laws see it.
+ *   d_row_sum: device [ny] FP64, or NULL.  Row j gets += sum over x of eps_g.
+ *   d_col_sum: device [nx] FP64, or NULL.  Column i gets += sum of eps_g over
+ *              rows y0 .. y1-1.  Both accumulate, for time averages.
+ *   d_count:   device int64, or NULL.  Set (=) to the number of cells in rows
+ *              y0 .. y1-1 whose eps_g exceeds threshold; the equivalent bubble
+ *              diameter is sqrt(4 count / pi) cells.
+ * Sums run in a fixed order.  0 <= y0 <= y1 <= ny and a finite threshold, else
+ * LBDPS_E_INVALID.  Asynchronous (stream order).
+ */
+lbdps_status lbdps_voidage(lbdps_ctx *ctx, int32_t y0, int32_t y1, double threshold, double *d_row_sum,
+                           double *d_col_sum, int64_t *d_count);
+
 /* Kernels of one step, for per-kernel timing. */
 typedef enum {
   LBDPS_K_COLLIDE = 0,    /* deposition + collision + streaming                     */

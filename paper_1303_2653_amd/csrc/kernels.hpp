@@ -2507,6 +2507,55 @@ __global__ __launch_bounds__(BLOCK) void k_pairs_write(const int32_t *__restrict
   }
 }
 
+// ------------------------------------------------------------------ voidage statistics (Sec. 3 observables)
+// The gas voidage of a cell is the 3-D voidage of Eq. 11 for its particle
+// count, from an FP64 column of the per-count table.  Workgroups 0 .. ny-1 sum
+// one row each (strided, then a fixed tree); the next ones take BLOCK columns
+// each and walk rows y0 .. y1-1 in order, summing eps_g and counting the
+// cells above the threshold (one partial count per workgroup).
+__global__ __launch_bounds__(BLOCK) void k_voidage(const int32_t *__restrict__ cs, int nx, int ny, int nlut,
+                                                   const double *__restrict__ eg_tab, int y0, int y1, double thr,
+                                                   double *row_sum, double *col_sum, long long *part) {
+  __shared__ double shd[BLOCK / 64];
+  __shared__ long long shl[BLOCK / 64];
+  const int b = blockIdx.x;
+  if (b < ny) {
+    if (!row_sum) return;
+    double v = 0.0;
+    for (int x = threadIdx.x; x < nx; x += BLOCK) {
+      const int c = b * nx + x;
+      v += eg_tab[min(cs[c + 1] - cs[c], nlut - 1)];
+    }
+    const double t = block_sum_d(v, shd);
+    if (threadIdx.x == 0) row_sum[b] += t;
+    return;
+  }
+  const int x = (b - ny) * BLOCK + (int)threadIdx.x;
+  double v = 0.0;
+  long long cnt = 0;
+  if (x < nx) {
+    for (int y = y0; y < y1; ++y) {
+      const int c = y * nx + x;
+      const double e = eg_tab[min(cs[c + 1] - cs[c], nlut - 1)];
+      v += e;
+      cnt += e > thr;
+    }
+    if (col_sum) col_sum[x] += v;
+  }
+  const long long t = block_sum_ll(cnt, shl);
+  if (threadIdx.x == 0) part[b - ny] = t;
+}
+
+// One workgroup: the partial counts of k_voidage in a fixed order.
+__global__ __launch_bounds__(BLOCK) void k_voidage_count(const long long *__restrict__ part, int n,
+                                                         long long *out) {
+  __shared__ long long shl[BLOCK / 64];
+  long long v = 0;
+  for (int i = threadIdx.x; i < n; i += BLOCK) v += part[i];
+  const long long t = block_sum_ll(v, shl);
+  if (threadIdx.x == 0) *out = t;
+}
+
 __global__ void k_fill_i32(int32_t *p, long long n, int32_t v) {
   const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
   if (i < n) p[i] = v;

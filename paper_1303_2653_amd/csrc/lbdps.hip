@@ -198,6 +198,8 @@ struct lbdps_ctx {
   long long *collc_part = nullptr, *wallc_part = nullptr;
   int ntiles = 0;
   double *cons_pc = nullptr, *cons_pp = nullptr, *cons_out = nullptr;
+  double *eg_tab = nullptr;        // FP64 gas voidage per particle count (Eq. 11), for lbdps_voidage
+  long long *obs_part = nullptr;   // per-workgroup partial counts of lbdps_voidage
   int32_t *dg_n = nullptr;
   void *dg_vsx = nullptr, *dg_vsy = nullptr, *dg_fdx = nullptr, *dg_fdy = nullptr;
   void *acx = nullptr, *acy = nullptr;  // accelerations held over the lattice step (n_sub > 1)
@@ -263,6 +265,8 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   int32_t *chunk_busy = cv.take<int32_t>(N / RES_CHUNK + 1), *need_sweep = cv.take<int32_t>(4);
   long long *collc_part = cv.take<long long>(nbN), *wallc_part = cv.take<long long>(nbN);
   double *pc = cv.take<double>(NB_CONS * 3), *pp = cv.take<double>(NB_CONS * 2), *co = cv.take<double>(8);
+  double *egt = cv.take<double>((size_t)lut_rows(p.d_p));
+  long long *obs = cv.take<long long>((size_t)nblocks(p.nx) + 1);
   int32_t *dg_n = nullptr;
   char *dvx = nullptr, *dvy = nullptr, *dfx = nullptr, *dfy = nullptr;
   if (p.diagnostics) {
@@ -322,6 +326,8 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->cons_pc = pc;
     x->cons_pp = pp;
     x->cons_out = co;
+    x->eg_tab = egt;
+    x->obs_part = obs;
     x->dg_n = dg_n;
     x->dg_vsx = dvx;
     x->dg_vsy = dvy;
@@ -532,6 +538,18 @@ template <int P> struct Impl {
     return launch_status("lbdps_step");
   }
 
+  static lbdps_status voidage(lbdps_ctx *x, int y0, int y1, double thr, double *rows, double *cols,
+                              int64_t *count) {
+    if (!x->bins_valid) rebin(x);
+    const int ncb = nblocks(x->nx);
+    hipLaunchKernelGGL(k_voidage, dim3(x->ny + ncb), dim3(BLOCK), 0, x->stream, (const int32_t *)x->cs, x->nx,
+                       x->ny, x->nlut, (const double *)x->eg_tab, y0, y1, thr, rows, cols, x->obs_part);
+    if (count)
+      hipLaunchKernelGGL(k_voidage_count, dim3(1), dim3(BLOCK), 0, x->stream, (const long long *)x->obs_part, ncb,
+                         (long long *)count);
+    return launch_status("lbdps_voidage");
+  }
+
   static lbdps_status collide_particles(lbdps_ctx *x) {
     if (!x->bins_valid) rebin(x);
     hard_spheres(x);
@@ -715,7 +733,11 @@ lbdps_status lbdps_create(const lbdps_params *p, int64_t max_particles, void *d_
     std::vector<float> f(v.begin(), v.end());
     return check_hip(hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice), "upload");
   };
-  if ((st = upload(x->lut, lut)) != LBDPS_OK || (st = upload(x->inlet, inl)) != LBDPS_OK) {
+  std::vector<double> egv((size_t)x->nlut);
+  for (int n = 0; n < x->nlut; ++n) egv[(size_t)n] = 1.0 - lut[(size_t)n * LUT_W + L_ES3];
+  if ((st = upload(x->lut, lut)) != LBDPS_OK || (st = upload(x->inlet, inl)) != LBDPS_OK ||
+      (st = check_hip(hipMemcpy(x->eg_tab, egv.data(), egv.size() * 8, hipMemcpyHostToDevice), "upload")) !=
+          LBDPS_OK) {
     delete x;
     return st;
   }
@@ -751,6 +773,27 @@ lbdps_status lbdps_step(lbdps_ctx *x, int32_t nsteps) {
 lbdps_status lbdps_collide_particles(lbdps_ctx *x) {
   if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
   return dispatch(x, [&](auto impl) { return decltype(impl)::collide_particles(x); });
+}
+
+lbdps_status lbdps_set_inlet(lbdps_ctx *x, const double *h_inlet_uy) {
+  if (!x || !h_inlet_uy) return fail(LBDPS_E_INVALID, "ctx or inlet profile is NULL");
+  for (int i = 0; i < x->nx; ++i)
+    if (!is_fin(h_inlet_uy[i])) return fail(LBDPS_E_INVALID, "inlet velocities must be finite");
+  lbdps_status st = check_hip(hipStreamSynchronize(x->stream), "lbdps_set_inlet");
+  if (st != LBDPS_OK) return st;
+  if (x->prec == PREC_FP64)
+    return check_hip(hipMemcpy(x->inlet, h_inlet_uy, (size_t)x->nx * 8, hipMemcpyHostToDevice), "lbdps_set_inlet");
+  std::vector<float> f(h_inlet_uy, h_inlet_uy + x->nx);
+  return check_hip(hipMemcpy(x->inlet, f.data(), f.size() * 4, hipMemcpyHostToDevice), "lbdps_set_inlet");
+}
+
+lbdps_status lbdps_voidage(lbdps_ctx *x, int32_t y0, int32_t y1, double threshold, double *d_row_sum,
+                           double *d_col_sum, int64_t *d_count) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (y0 < 0 || y1 > x->ny || y0 > y1) return fail(LBDPS_E_INVALID, "rows must satisfy 0 <= y0 <= y1 <= ny");
+  if (!is_fin(threshold)) return fail(LBDPS_E_INVALID, "threshold must be finite");
+  return dispatch(x, [&](auto impl) { return decltype(impl)::voidage(x, y0, y1, threshold, d_row_sum, d_col_sum,
+                                                                     d_count); });
 }
 
 lbdps_status lbdps_get_fields(lbdps_ctx *x, double *d_rho, double *d_ugas, double *d_fpg, double *d_beta,

@@ -59,6 +59,8 @@ _SIGS = {
     "lbdps_set_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64]),
     "lbdps_step": (c_i32, [c_vp, c_i32]),
     "lbdps_collide_particles": (c_i32, [c_vp]),
+    "lbdps_set_inlet": (c_i32, [c_vp, c_vp]),
+    "lbdps_voidage": (c_i32, [c_vp, c_i32, c_i32, c_dbl, c_vp, c_vp, c_vp]),
     "lbdps_get_fields": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lbdps_get_particles": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lbdps_get_pairs": (c_i32, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]),
@@ -201,6 +203,26 @@ class Sim:
 
     def collide_particles(self):
         check(lbdps_collide_particles(self.ctx), "lbdps_collide_particles")
+
+    def set_inlet(self, inlet_uy):
+        a = np.ascontiguousarray(inlet_uy, np.float64)
+        if a.shape != (self.nx,):
+            raise ValueError(f"inlet profile must have {self.nx} entries")
+        check(lbdps_set_inlet(self.ctx, a.ctypes.data), "lbdps_set_inlet")
+
+    def voidage(self, y0: int = 0, y1=None, threshold: float = 0.85):
+        """(row sums [ny], column sums over rows y0..y1-1 [nx], cells of those rows
+        with eps_g > threshold) of the current positions (lbdps_voidage)."""
+        t = self.torch
+        y1 = self.ny if y1 is None else y1
+        with t.cuda.stream(self.stream):  # zeroed before the library's launches
+            rows = t.zeros(self.ny, dtype=t.float64, device="cuda")
+            cols = t.zeros(self.nx, dtype=t.float64, device="cuda")
+            cnt = t.zeros(1, dtype=t.int64, device="cuda")
+            check(lbdps_voidage(self.ctx, int(y0), int(y1), float(threshold), rows.data_ptr(), cols.data_ptr(),
+                                cnt.data_ptr()), "lbdps_voidage")
+        self.stream.synchronize()
+        return rows.cpu().numpy(), cols.cpu().numpy(), int(cnt.item())
 
     def fields(self):
         t = self.torch
