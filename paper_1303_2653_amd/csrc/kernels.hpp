@@ -308,6 +308,7 @@ constexpr int RANK_MOVED = 1 << 30;           // rank flag: the particle arrived
 constexpr int SEG_REG = 4;                    // cell segments up to this length stay in registers
 constexpr int CONTACT_REG = 4;                // contacts per particle collected in registers first
 constexpr int CONTACT_CH = 4;                 // candidate positions loaded together
+constexpr int CONTACT_W = 2;                  // slots each side of a particle loaded before its cell starts
 constexpr int RES_ITEMS = 8;                  // particle indices per lane and resolution chunk
 constexpr int RES_CHUNK = BLOCK * RES_ITEMS;  // particle indices per chunk
 
@@ -1326,6 +1327,19 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
     }
     const T dd = k.d * k.d;
     const AdjRow row = adj.row(s);
+    // The particle's own row of cells (its cell and the cells left and right of
+    // it) is one slot range around s, so the CONTACT_W slots on each side are
+    // loaded now, before the cell starts arrive; the ones inside the row's
+    // range are tested from registers.
+    T wx[2 * CONTACT_W], wy[2 * CONTACT_W];
+    int wid[2 * CONTACT_W];
+#pragma unroll
+    for (int j = 0; j < 2 * CONTACT_W; ++j) {
+      const int t = min(max(j < CONTACT_W ? s - CONTACT_W + j : s + 1 + (j - CONTACT_W), 0), k.npart - 1);
+      wx[j] = ldu(pt.px, t);
+      wy[j] = ldu(pt.py, t);
+      wid[j] = ldu(pt.pid, t);
+    }
     // Pass 1 keeps the first CONTACT_REG contacts sorted in registers (no
     // stores while scanning, so candidate loads overlap); a particle with more
     // contacts is scanned again and its list built in memory.
@@ -1425,7 +1439,57 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
         }
       }
     };
-    scan([&](int t, int tid) {
+    // Pass 1 over a row of cells away from a periodic seam: the window slots
+    // inside the own row's range from registers, then the rest of the three
+    // ranges (row below, own row left and right of the window, row above),
+    // CONTACT_CH candidates at a time.
+    auto first_scan = [&](auto &&hit) {
+      if (!inner_x) {
+        scan(hit);
+        return;
+      }
+      const int lo1 = rlo[1], hi1 = rhi[1], a1 = rm1[1], b1 = rm2[1];
+#pragma unroll
+      for (int j = 0; j < 2 * CONTACT_W; ++j) {
+        const int t = j < CONTACT_W ? s - CONTACT_W + j : s + 1 + (j - CONTACT_W);
+        if (t >= lo1 && t < hi1) {
+          T dx, dy;
+          Pos<P>::sep_nb(k, t < a1 ? -1 : (t < b1 ? 0 : 1), 0, x, y, wx[j], wy[j], dx, dy);
+          if (dx * dx + dy * dy <= dd) hit(t, wid[j]);
+        }
+      }
+      const int mlo = max(lo1, s + CONTACT_W + 1);
+      const int n0 = rhi[0] - rlo[0], n1 = n0 + max(0, min(hi1, s - CONTACT_W) - lo1);
+      const int n2 = n1 + max(0, hi1 - mlo), tot = n2 + rhi[2] - rlo[2];
+      const int sh0 = rlo[0], sh1 = lo1 - n0, sh2 = mlo - n1, sh3 = rlo[2] - n2;
+      const int a0 = rm1[0], a2 = rm1[2], b0 = rm2[0], b2 = rm2[2];
+      for (int q0 = 0; q0 < tot; q0 += CONTACT_CH) {
+        int tt[CONTACT_CH], ox[CONTACT_CH], oy[CONTACT_CH], ids[CONTACT_CH];
+        T xs[CONTACT_CH], ys[CONTACT_CH];
+#pragma unroll
+        for (int j = 0; j < CONTACT_CH; ++j) {
+          const int q = min(q0 + j, tot - 1);  // past the end: repeat the last candidate
+          const bool r0 = q < n0, r1 = q < n1, r2 = q < n2;
+          const int t = q + (r0 ? sh0 : (r1 ? sh1 : (r2 ? sh2 : sh3)));
+          const int m1 = r0 ? a0 : (r2 ? a1 : a2), m2 = r0 ? b0 : (r2 ? b1 : b2);
+          tt[j] = t;
+          ox[j] = t < m1 ? -1 : (t < m2 ? 0 : 1);
+          oy[j] = r0 ? -1 : (r2 ? 0 : 1);
+          xs[j] = ldu(pt.px, t);
+          ys[j] = ldu(pt.py, t);
+          ids[j] = ldu(pt.pid, t);
+        }
+#pragma unroll
+        for (int j = 0; j < CONTACT_CH; ++j) {
+          if (q0 + j < tot) {
+            T dx, dy;
+            Pos<P>::sep_nb(k, ox[j], oy[j], x, y, xs[j], ys[j], dx, dy);
+            if (dx * dx + dy * dy <= dd) hit(tt[j], ids[j]);
+          }
+        }
+      }
+    };
+    first_scan([&](int t, int tid) {
       if (tid > id) ++fwd;
       if (cnt < CONTACT_REG) {
         const long long e = ((long long)tid << 32) | (unsigned)t;
