@@ -13,6 +13,11 @@ import os
 import re
 
 import numpy as np
+# torch first: the library's HIP runtime dependency then binds to the runtime
+# torch has already loaded, so the process holds one HIP (and HSA) runtime.
+# Loaded the other way round, the process holds two, and the library's finds
+# no device.
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbdps.so")

@@ -189,3 +189,20 @@ def test_size_limits_for_32_bit_offsets():
     assert _status(p) == L.LBDPS_E_SHAPE
     p.ny = (1 << 14) - 1
     assert _status(p) == L.LBDPS_OK, L.lbdps_last_error()
+
+
+def test_one_hip_runtime_in_the_process():
+    """Importing the binding first (as the test collection does) must leave a
+    single HIP runtime mapped: the library binds to the one torch loads.  With
+    two runtimes in one process the library's finds no device."""
+    import os
+    import subprocess
+    import sys
+
+    code = ("import paper_1303_2653_amd.lbdps\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
