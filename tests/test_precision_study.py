@@ -45,9 +45,18 @@ POINTS = (10, 100, 1000)
 STEPS, START, EVERY = 5000, 1000, 10
 PRECS = ("fp32", "fp16", "bf16")
 
-# stated pointwise bounds (gas fields and populations, norm-wise) at step 10;
-# measured on MI355X: FP32 3.5e-7, FP16 1.9e-3, BF16 3.1e-3
-BOUND10 = {"fp32": 2e-6, "fp16": 1e-2, "bf16": 1.5e-2}
+# stated pointwise bounds (gas fields and populations, norm-wise) at step 10.
+# FP16 and BF16: the storage rounding, measured 1.9e-3 and 3.1e-3.  FP32: the
+# random placement leaves overlapping pairs nearly at rest relative to each
+# other, whose approach test and impulse direction (Eqs. 17-18) are decided by
+# rounding; the velocity a pair takes then reaches u_gas and F_pg through the
+# cell's mean solid velocity (Eqs. 8, 24-25).  Over seeds 3-10 of the crop
+# the largest FP32 errors at step 10 were 5.4e-6 (u_gas) and 3.2e-5 (F_pg),
+# 5.3e-10 for populations and density and 8.2e-8 for beta, and an exact
+# division instead of the hardware reciprocal moves them within the same
+# range (F_pg up to 1.4e-4 on one seed).
+BOUND10 = {"fp32": dict(f=1e-8, rho=1e-8, ugas=1e-4, fpg=3e-4, beta=1e-6),
+           "fp16": 1e-2, "bf16": 1.5e-2}
 # statistics: within 1.5 times the spread of runs that differ only by chaotic
 # divergence (the oracle's perturbed runs, and the FP64 library path, which
 # tracks the oracle to 1e-14 for 800 steps and then diverges exponentially)
@@ -151,7 +160,8 @@ def test_precision_pattern(crop):
     for prec in PRECS:
         p10 = report["runs"][prec]["pointwise"]["10"]
         for key in ("f", "rho", "ugas", "fpg", "beta"):
-            assert p10[key] <= BOUND10[prec], (prec, key, p10[key])
+            b = BOUND10[prec][key] if isinstance(BOUND10[prec], dict) else BOUND10[prec]
+            assert p10[key] <= b, (prec, key, p10[key])
     spread = {k: max(ref["noise"][k], report["runs"]["fp64"]["stats_err"][k]) for k in ref["noise"]}
     report["spread"] = spread
     if out:
@@ -162,3 +172,27 @@ def test_precision_pattern(crop):
         se = report["runs"][prec]["stats_err"]
         for key, v in se.items():
             assert v <= SPREAD_FACTOR * spread[key], (prec, key, v, spread[key])
+
+
+@pytest.mark.parametrize("seed", range(3, 11))
+def test_fp32_step10_over_seeds(seed):
+    """The FP32 bounds at step 10 hold for other draws of the crop too: the
+    errors of u_gas and F_pg depend on which overlapping pairs the placement
+    makes (their collisions are decided by rounding), not on the seed-3 crop."""
+    cfg = synth.riser_crop(seed=seed)
+    f0, pos0, vel0 = storage_repr.state(cfg, oracle.equilibrium_state(cfg["nx"], cfg["ny"]), cfg["pos"],
+                                        cfg["vel"], "fp32")
+    ref = oracle.Sim(cfg, f=f0, pos=pos0, vel=vel0)
+    for _ in range(9):
+        ref.step()
+    o = ref.step(record=True)
+    gpu = L.Sim(cfg, precision="fp32")
+    gpu.set_state(f0, pos0, vel0)
+    gpu.step(10)
+    fl = gpu.fields()
+    f, _, _, _ = gpu.state()
+    err = dict(f=nrel(f, ref.f, 1.0), rho=nrel(fl["rho"], o.rho, 1.0), ugas=nrel(fl["ugas"], o.ugas),
+               fpg=nrel(fl["fpg"], o.fpg), beta=nrel(fl["beta"], o.beta))
+    say("seed", seed, "fp32 step 10", {k: f"{v:.2e}" for k, v in err.items()})
+    for key, v in err.items():
+        assert v <= BOUND10["fp32"][key], (seed, key, v)
