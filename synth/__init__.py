@@ -164,24 +164,33 @@ def paper_tau(dt: float, mu_g: float = 1.8872e-5, rho_g: float = 1.1795) -> floa
     return 3.0 * mu_g * dt / (rho_g * PAPER_H * PAPER_H) + 0.5
 
 
-def paper_bubble(seed: int = 11, phi: float = 0.5) -> dict:
+def paper_bubble(seed: int = 11) -> dict:
     """Table 1: a 25 x 100 bed (walls at x, gas inlet at the bottom, outlet at
     the top) holding 15 000 spheres of d = 0.2 at incipient fluidization; gas
     enters at v_mf = 0.0025 m/s = 1.25e-5 except through the 3-cell central
     orifice x in [11, 14), where a jet of 0.8 m/s = 0.004 lasts 0.006 s = 4 444
     steps of 1.35e-6 s (cfg["pulse_steps"]; cfg["inlet_after"] is the profile
-    afterwards).  tau = 3 (2.963e-4) + 1/2.  The spheres sit on a jittered 100 x 150 lattice
-    filling a bottom band of 2-D solid fraction phi (37.7 rows at 0.5), jitter
-    +-0.02 per axis so no two touch at t = 0."""
+    afterwards).  tau = 3 (2.963e-4) + 1/2.  Incipient fluidization: the drag
+    of Eqs. 19-22 at v_mf carries the weight of a cell of about 25.3 spheres
+    (2-D solid fraction 0.795, 3-D voidage 0.57), so the spheres sit on a
+    hexagonal lattice of that fraction (spacing 0.2137; rows of 117 and 116
+    alternately, 23.9 rows in all, the outer centres 0.104 from the walls),
+    with a jitter of +-0.004 per axis so no two touch at t = 0 and none
+    reaches a wall."""
     nx, ny, n, d = 25, 100, 15_000, 0.2
-    ncol, nrow = 100, 150
-    band = n * math.pi * d * d / 4.0 / (phi * nx)
-    dx, dy = nx / ncol, band / nrow
-    k = np.arange(n)
-    jit = (uniform(seed, 2 * n).reshape(n, 2) * 2.0 - 1.0) * 0.02
+    a = (nx - d - 0.008) / 116.0       # spacing: 117 centres from x = 0.104 to 24.896
+    dy = a * math.sqrt(3.0) / 2.0
     pos = np.empty((n, 2))
-    pos[:, 0] = (k % ncol + 0.5) * dx + jit[:, 0]
-    pos[:, 1] = (k // ncol + 0.5) * dy + jit[:, 1]
+    k, row = 0, 0
+    while k < n:
+        cols = 117 if row % 2 == 0 else 116
+        m = min(cols, n - k)
+        x0 = 0.5 * d + 0.004 + (0.0 if row % 2 == 0 else 0.5 * a)
+        pos[k:k + m, 0] = x0 + a * np.arange(m)
+        pos[k:k + m, 1] = 0.5 * d + 0.004 + dy * row
+        k += m
+        row += 1
+    pos += (uniform(seed, 2 * n).reshape(n, 2) * 2.0 - 1.0) * 0.004
     v_mf, v_inj = 0.0025 * 1.35e-6 / PAPER_H, 0.8 * 1.35e-6 / PAPER_H
     after = np.full(nx, v_mf)
     inlet = after.copy()

@@ -70,6 +70,24 @@ def test_bubble_area_of_a_hole(orc):
     assert abs(math.sqrt(4 * count / math.pi) - 2 * R) < 1.0
 
 
+def test_paper_bubble_at_incipient_fluidization(orc):
+    """The Table 1 bed is packed where the drag of Eqs. 19-22 (Eq. 26 per
+    sphere) at v_mf carries the spheres' weight: at the bed's mean count per
+    cell the ratio of drag to weight lies between 0.8 and 1.25."""
+    c = synth.paper_bubble()
+    p = orc.make_params(c)
+    pos = c["pos"]
+    cell = (np.floor(pos[:, 1]) * c["nx"] + np.floor(pos[:, 0])).astype(int)
+    counts = np.bincount(cell, minlength=c["nx"] * c["ny"])
+    n = int(round(counts[: 23 * c["nx"]].mean()))  # the full rows of the bed
+    pr = orc.cell_props(p, n)
+    u = min(c["inlet_uy"]) / pr["eps_2"]  # actual gas velocity at the superficial v_mf (R6)
+    vp = math.pi * c["d"] ** 3 / 6
+    drag = n * vp * orc.beta(p, pr["eps_g"], pr["omega"], u) / (1 - pr["eps_g"]) * u
+    weight = n * c["rho_s"] * vp * (1 - 1 / c["rho_s"]) * -c["g"][1]
+    assert 0.8 < drag / weight < 1.25, (n, drag / weight)
+
+
 def test_paper_bubble_parameters():
     """Table 1 in lattice units: the lattice, orifice, particle size and number
     are the dimensionless column; v_mf, the jet, tau and gravity follow from
@@ -99,6 +117,7 @@ def test_paper_bubble_parameters():
     from scipy.spatial import cKDTree
     dist, _ = cKDTree(c["pos"]).query(c["pos"], 2)
     assert dist[:, 1].min() > c["d"]
+    assert c["pos"][:, 0].min() >= c["d"] / 2 and c["pos"][:, 0].max() <= c["nx"] - c["d"] / 2
 
 
 def test_paper_riser_parameters():
