@@ -42,6 +42,8 @@ WORKLOADS = {
     "riser_crop": lambda: __import__("synth").riser_crop(),
     "riser_large": lambda: __import__("synth").riser_large(),
     "beds": lambda: __import__("synth").beds(64),
+    "paper_bubble": lambda: __import__("synth").paper_bubble(),
+    "paper_riser": lambda: __import__("synth").paper_riser(),
 }
 SIZES = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4), "bf16": (2, 4)}  # (population, scalar) bytes
 
