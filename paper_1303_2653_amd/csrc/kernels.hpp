@@ -309,6 +309,7 @@ constexpr int SEG_REG = 4;                    // cell segments up to this length
 constexpr int CONTACT_REG = 4;                // contacts per particle collected in registers first
 constexpr int CONTACT_CH = 4;                 // candidate positions loaded together
 constexpr int CONTACT_W = 2;                  // slots each side of a particle loaded before its cell starts
+constexpr int CONTACT_W_SMALL = 3;            // the same for grids that fit on the chip at six waves per SIMD
 constexpr int RES_ITEMS = 8;                  // particle indices per lane and resolution chunk
 constexpr int RES_CHUNK = BLOCK * RES_ITEMS;  // particle indices per chunk
 
@@ -1295,7 +1296,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, c
 // sorted by particle index, as 64-bit entries (index << 32 | slot).  A particle
 // without contacts gets its wall collision here; the others get it after their
 // binary collisions.
-template <int P>
+template <int P, int W = CONTACT_W>
 __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
     const int32_t *__restrict__ cs, Consts<typename Prec<P>::T> k, Adj adj, int32_t *__restrict__ deg,
     int32_t *__restrict__ done, int32_t *ticket, int32_t *flags, long long *pair_part, long long *wall_part,
@@ -1328,14 +1329,14 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
     const T dd = k.d * k.d;
     const AdjRow row = adj.row(s);
     // The particle's own row of cells (its cell and the cells left and right of
-    // it) is one slot range around s, so the CONTACT_W slots on each side are
+    // it) is one slot range around s, so the W slots on each side are
     // loaded now, before the cell starts arrive; the ones inside the row's
     // range are tested from registers.
-    T wx[2 * CONTACT_W], wy[2 * CONTACT_W];
-    int wid[2 * CONTACT_W];
+    T wx[2 * W], wy[2 * W];
+    int wid[2 * W];
 #pragma unroll
-    for (int j = 0; j < 2 * CONTACT_W; ++j) {
-      const int t = min(max(j < CONTACT_W ? s - CONTACT_W + j : s + 1 + (j - CONTACT_W), 0), k.npart - 1);
+    for (int j = 0; j < 2 * W; ++j) {
+      const int t = min(max(j < W ? s - W + j : s + 1 + (j - W), 0), k.npart - 1);
       wx[j] = ldu(pt.px, t);
       wy[j] = ldu(pt.py, t);
       wid[j] = ldu(pt.pid, t);
@@ -1450,16 +1451,16 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
       }
       const int lo1 = rlo[1], hi1 = rhi[1], a1 = rm1[1], b1 = rm2[1];
 #pragma unroll
-      for (int j = 0; j < 2 * CONTACT_W; ++j) {
-        const int t = j < CONTACT_W ? s - CONTACT_W + j : s + 1 + (j - CONTACT_W);
+      for (int j = 0; j < 2 * W; ++j) {
+        const int t = j < W ? s - W + j : s + 1 + (j - W);
         if (t >= lo1 && t < hi1) {
           T dx, dy;
           Pos<P>::sep_nb(k, t < a1 ? -1 : (t < b1 ? 0 : 1), 0, x, y, wx[j], wy[j], dx, dy);
           if (dx * dx + dy * dy <= dd) hit(t, wid[j]);
         }
       }
-      const int mlo = max(lo1, s + CONTACT_W + 1);
-      const int n0 = rhi[0] - rlo[0], n1 = n0 + max(0, min(hi1, s - CONTACT_W) - lo1);
+      const int mlo = max(lo1, s + W + 1);
+      const int n0 = rhi[0] - rlo[0], n1 = n0 + max(0, min(hi1, s - W) - lo1);
       const int n2 = n1 + max(0, hi1 - mlo), tot = n2 + rhi[2] - rlo[2];
       const int sh0 = rlo[0], sh1 = lo1 - n0, sh2 = mlo - n1, sh3 = rlo[2] - n2;
       const int a0 = rm1[0], a2 = rm1[2], b0 = rm2[0], b2 = rm2[2];
@@ -1565,6 +1566,20 @@ __global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void k_contacts(Parts<typename 
                                                     int32_t *__restrict__ rcount) {
   contacts_body<P>(xcd_block<XCD_RUN_CONTACTS>(blockIdx.x, gridDim.x), gridDim.x, pt, cs, k, adj, deg, done, ticket, flags, pair_part, wall_part, chunk_busy,
       need_sweep, roots, rcount);
+}
+// Grids whose workgroups are all resident at once (CONTACTS_SMALL_MAX): a wider
+// early-loaded window at six waves per SIMD, since latency rather than the
+// number of waves in flight bounds such a launch.
+constexpr int CONTACTS_SMALL_MAX = 1536;
+template <int P>
+__global__ __launch_bounds__(BLOCK) LBDPS_WAVES6 void k_contacts_small(Parts<typename Prec<P>::T> pt,
+    const int32_t *__restrict__ cs, Consts<typename Prec<P>::T> k, Adj adj, int32_t *__restrict__ deg,
+    int32_t *__restrict__ done, int32_t *ticket, int32_t *flags, long long *pair_part, long long *wall_part,
+    int32_t *__restrict__ chunk_busy, int32_t *need_sweep, long long *__restrict__ roots,
+    int32_t *__restrict__ rcount) {
+  contacts_body<P, CONTACT_W_SMALL>(xcd_block<XCD_RUN_CONTACTS>(blockIdx.x, gridDim.x), gridDim.x, pt, cs, k, adj,
+                                    deg, done, ticket, flags, pair_part, wall_part, chunk_busy, need_sweep, roots,
+                                    rcount);
 }
 
 // ------------------------------------------------------------------ A7: collision resolution (Eqs. 17-18) and walls

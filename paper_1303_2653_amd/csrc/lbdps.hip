@@ -496,7 +496,8 @@ template <int P> struct Impl {
     const int N = (int)x->n;
     if (N == 0) return;
     const Consts<T> k = consts(x);
-    tlaunch(x, LBDPS_K_CONTACTS, extra, k_contacts<P>, dim3(nblocks(N)), parts(x, x->cp), (const int32_t *)x->cs, k,
+    tlaunch(x, LBDPS_K_CONTACTS, extra, nblocks(N) <= CONTACTS_SMALL_MAX ? k_contacts_small<P> : k_contacts<P>,
+            dim3(nblocks(N)), parts(x, x->cp), (const int32_t *)x->cs, k,
             x->adj(), x->deg, x->done, x->ticket, x->flags, x->pair_part, x->wall0_part, x->chunk_busy,
             x->need_sweep, x->roots, x->rcount);
     tlaunch(x, LBDPS_K_RESOLVE, extra, k_resolve_clusters<P>, dim3(x->cluster_groups()), parts(x, x->cp), x->adj(),

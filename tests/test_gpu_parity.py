@@ -201,6 +201,8 @@ CLUSTER_BEDS = {
     "dense_box": lambda: synth.tiny(nx=40, ny=40, n=6000, seed=9, bc=("periodic",) * 4),
     # 430 spheres on 9x8 cells: one cluster of 369 members
     "crowded_box": lambda: synth.tiny(nx=9, ny=8, n=430, seed=17, bc=("periodic",) * 4),
+    # more contact workgroups than are resident at once: the eight-wave contact kernel
+    "riser_430k": lambda: synth.riser(512, 880, 430_000, 5, True, "fp64"),
 }
 
 
@@ -226,11 +228,13 @@ def test_fp64_collision_stage_clusters(name):
     assert (st["vel"] == v1).all(), rel(st["vel"], v1)
 
 
-def test_fp32_contacts_exact_single_precision():
+@pytest.mark.parametrize("nx,ny,n", [(48, 40, 5000), (512, 640, 450_000)])
+def test_fp32_contacts_exact_single_precision(nx, ny, n):
     """Contact pairs in FP32 mode equal the oracle's single-precision predicate
-    on the same cell + offset state, bit for bit, including the periodic wrap."""
+    on the same cell + offset state, bit for bit, including the periodic wrap;
+    on a grid that fits on the chip at once (the six-wave contact kernel) and
+    on one that does not (the eight-wave kernel)."""
     rng = np.random.default_rng(12)
-    nx, ny, n = 48, 40, 5000
     cell = np.stack([rng.integers(0, nx, n), rng.integers(0, ny, n)], 1).astype(np.int32)
     off = rng.random((n, 2)).astype(np.float32)
     pos = cell.astype(np.float64) + off.astype(np.float64)
