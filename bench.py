@@ -195,7 +195,10 @@ def summarize(args):
                   f"make a plain {args.copy_bytes} byte copy ({copy_name}) read and write exactly its size.", "",
                   "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes per launch |", "|---|---:|---:|---:|"]
         for key, kname in KERNEL_KEYS.items():
-            if kname in fetch and kname in write:
+            # the phase's kernel under either of its forms (k_drag / k_drag_flat, k_contacts / k_contacts_small)
+            names = [n for n in fetch if (n == kname or n.startswith(kname + "_")) and n in write]
+            if names:
+                kname = names[0]
                 b = fetch[kname] * f_scale + write[kname] * w_scale
                 traffic[key] = int(b)
                 lines.append(f"| {kname} | {fetch[kname] / 1024:.1f} | {write[kname] / 1024:.1f} | {int(b)} |")
