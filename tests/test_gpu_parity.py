@@ -203,6 +203,10 @@ CLUSTER_BEDS = {
     "crowded_box": lambda: synth.tiny(nx=9, ny=8, n=430, seed=17, bc=("periodic",) * 4),
     # more contact workgroups than are resident at once: the eight-wave contact kernel
     "riser_430k": lambda: synth.riser(512, 880, 430_000, 5, True, "fp64"),
+    # clusters of thousands, beyond the workgroup path: the ordered sweep
+    # (15 000 particles, one cluster of 13 438; 80 000, the largest of 8 506)
+    "dense_15k": lambda: synth.tiny(nx=50, ny=50, n=15_000, seed=23, bc=("periodic",) * 4),
+    "dense_80k": lambda: synth.tiny(nx=120, ny=120, n=80_000, seed=19, bc=("periodic",) * 4),
 }
 
 
