@@ -440,3 +440,29 @@ def test_fp64_large_lattice():
         compare_step(gpu, o, ref, 1e-12, what=f"large lattice step {k}")
     pairs, m = gpu.pairs()
     assert m == len(o.pairs) and (pairs == o.pairs).all()
+
+
+@pytest.mark.parametrize("prec,bound", [("fp16", 1e-2), ("bf16", 1.5e-2)])
+def test_reduced_storage_with_les_and_substeps(prec, bound):
+    """FP16 and BF16 population storage with the Smagorinsky model on and two
+    particle sub-steps per lattice step: after 10 steps from the same stored
+    state the populations and gas fields stay within the storage precisions'
+    stated bounds against the FP64 oracle."""
+    cfg = synth.riser_crop()
+    cfg.update(cs_smag=2.0, n_sub=2)
+    f0, pos0, vel0 = storage_repr.state(cfg, oracle.equilibrium_state(cfg["nx"], cfg["ny"]), cfg["pos"],
+                                        cfg["vel"], prec)
+    ref = oracle.Sim(cfg, f=f0, pos=pos0, vel=vel0)
+    for _ in range(9):
+        ref.step()
+    o = ref.step(record=True)
+    gpu = L.Sim(cfg, precision=prec)
+    gpu.set_state(f0, pos0, vel0)
+    gpu.step(10)
+    fl = gpu.fields()
+    f, _, _, _ = gpu.state()
+    errs = dict(f=rel(f, ref.f, 1.0), rho=rel(fl["rho"], o.rho, 1.0), ugas=rel(fl["ugas"], o.ugas),
+                fpg=rel(fl["fpg"], o.fpg), beta=rel(fl["beta"], o.beta))
+    say(prec, "LES + 2 sub-steps, step 10", {k: f"{v:.2e}" for k, v in errs.items()})
+    bad = {k: v for k, v in errs.items() if not v <= bound}
+    assert not bad, bad
