@@ -272,7 +272,9 @@ def run_beds(args, torch, L):
     batch = L.Batch(cfgs, precision=prec)
     st = batch.stream
     batch.step(args.warmup)
-    tunings = batch.autotune(steps=4)  # launch shapes per bed size class
+    # launch shapes per bed size class; two rounds of 2 steps per candidate and
+    # class keep the tuning run within the beds' stable span (they are reset below)
+    tunings = batch.autotune(steps=2)
     # every measured region starts again from the initial beds, after the warmup
     batch.reset()
     batch.step(args.warmup)
@@ -367,6 +369,7 @@ def main():
     ap.add_argument("--workload", default="bubble", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=sorted(SIZES))
     ap.add_argument("--n-sub", type=int, default=1, help="particle sub-steps per lattice step")
+    ap.add_argument("--cs-smag", type=float, default=None, help="Smagorinsky constant (sub-grid model on)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -406,6 +409,8 @@ def main():
     cfg = WORKLOADS[args.workload]()
     if args.n_sub > 1:
         cfg["n_sub"] = args.n_sub
+    if args.cs_smag is not None:
+        cfg["cs_smag"] = args.cs_smag
     C, N = cfg["nx"] * cfg["ny"], len(cfg["pos"])
     r = run_gpu(cfg, args.precision, args.steps, args.warmup, torch, L)
     s = r["ms"] / 1e3
@@ -423,7 +428,7 @@ def main():
             dom_bytes *= args.n_sub
     achieved = dom_bytes / (dom_us * 1e-6) / 1e9
     model = model_bytes_per_step(args.precision, C, N, r["pairs"])
-    traffic = None if args.n_sub > 1 else measured_traffic(
+    traffic = None if args.n_sub > 1 or args.cs_smag is not None else measured_traffic(
         args.workload if args.precision == "fp32" else f"{args.workload}-{args.precision}", dom)
     line = {
         "metric": METRIC,
@@ -439,10 +444,11 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)", "bf16": "f32 (bf16 storage)"}[args.precision],
         "data": "synthetic (seeded splitmix64 bed, recipe in DESIGN.md)",
         "config": {"workload": workload_name(cfg["name"], args.precision)
-                   + (f"-nsub{args.n_sub}" if args.n_sub > 1 else ""), "nx": cfg["nx"], "ny": cfg["ny"],
+                   + (f"-nsub{args.n_sub}" if args.n_sub > 1 else "")
+                   + (f"-les{args.cs_smag:g}" if args.cs_smag is not None else ""), "nx": cfg["nx"], "ny": cfg["ny"],
                    "particles": N,
                    "precision": args.precision, "d_p": cfg["d"], "tau": cfg["tau"],
-                   "n_sub": cfg.get("n_sub", 1)},
+                   "n_sub": cfg.get("n_sub", 1), "cs_smag": cfg.get("cs_smag", 0.0)},
         "particle_updates_per_s": float(f"{pups:.4e}"),
         "model_bytes_per_step": int(model),
         "model_bw_frac": round(model * args.steps / s / 1e9 / HBM_PEAK_GBS, 4),

@@ -270,9 +270,10 @@ typedef struct {
 lbdps_status lbdps_set_tuning(lbdps_ctx *ctx, const lbdps_tuning *t);
 lbdps_status lbdps_get_tuning(lbdps_ctx *ctx, lbdps_tuning *t);
 
-/* Autotuner: run `steps` steps under each candidate launch shape, time them
- * with hipEvents on the context's stream and keep the fastest (written to
- * *chosen if not NULL).  The bed advances by steps x (number of candidates).
+/* Autotuner: run `steps` steps under each candidate launch shape, twice over
+ * the candidates in turn, time them with hipEvents on the context's stream and
+ * keep the candidate with the fastest of its two times (written to *chosen if
+ * not NULL).  The bed advances by 2 x steps x (number of candidates).
  * Synchronises. */
 lbdps_status lbdps_autotune(lbdps_ctx *ctx, int32_t steps, lbdps_tuning *chosen);
 
@@ -337,8 +338,9 @@ lbdps_status lbdps_batch_kernel_times(lbdps_batch *batch, double *h_ms, int64_t 
 /*
  * Autotuner of a batch: beds are grouped into size classes by particle count
  * (up to 2048, 4096, 8192, ...).  Class by class, every candidate launch shape
- * is applied to the class's beds and `steps` batched steps are timed; the
- * fastest is kept.  Every bed advances by the steps taken.  cache_path (or
+ * is applied to the class's beds and `steps` batched steps are timed, twice
+ * over the candidates in turn; the candidate with the fastest of its two times
+ * is kept.  Every bed advances by the steps taken.  cache_path (or
  * NULL): a text file of chosen shapes per class and precision; classes found
  * there are not timed again, and the file is rewritten with all classes.
  * Synchronises.

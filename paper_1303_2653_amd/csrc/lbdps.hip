@@ -991,22 +991,27 @@ extern "C" {
 lbdps_status lbdps_autotune(lbdps_ctx *x, int32_t steps, lbdps_tuning *chosen) {
   if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
   if (steps < 1) return fail(LBDPS_E_INVALID, "steps must be >= 1");
-  float best = 0.f;
-  lbdps_tuning bt = x->tune;
-  for (int c = 0; c < kTuneN; ++c) {
-    x->tune = kTuneCandidates[c];
-    float ms = 0.f;
-    lbdps_status st = time_on(
-        x->stream, [&]() { return dispatch(x, [&](auto impl) { return decltype(impl)::step(x, steps); }); }, &ms);
-    if (st != LBDPS_OK) {
-      x->tune = bt;
-      return st;
+  // Two interleaved rounds over the candidates; each keeps its faster time, so
+  // a single disturbed measurement does not decide.
+  const lbdps_tuning start = x->tune;
+  float t[kTuneN];
+  for (int round = 0; round < 2; ++round)
+    for (int c = 0; c < kTuneN; ++c) {
+      x->tune = kTuneCandidates[c];
+      float ms = 0.f;
+      lbdps_status st = time_on(
+          x->stream, [&]() { return dispatch(x, [&](auto impl) { return decltype(impl)::step(x, steps); }); },
+          &ms);
+      if (st != LBDPS_OK) {
+        x->tune = start;
+        return st;
+      }
+      t[c] = round == 0 ? ms : std::min(t[c], ms);
     }
-    if (c == 0 || ms < best) {
-      best = ms;
-      bt = kTuneCandidates[c];
-    }
-  }
+  int bc = 0;
+  for (int c = 1; c < kTuneN; ++c)
+    if (t[c] < t[bc]) bc = c;
+  const lbdps_tuning bt = kTuneCandidates[bc];
   x->tune = bt;
   if (chosen) *chosen = bt;
   return sync_and_check(x, "lbdps_autotune");
@@ -1467,18 +1472,19 @@ lbdps_status lbdps_batch_autotune(lbdps_batch *B, int32_t steps, const char *cac
       for (int b : kv.second) B->beds[b]->tune = it->second;
       continue;
     }
-    float best = 0.f;
-    lbdps_tuning bt = kTuneCandidates[0];
-    for (int c = 0; c < kTuneN; ++c) {
-      for (int b : kv.second) B->beds[b]->tune = kTuneCandidates[c];
-      float ms = 0.f;
-      lbdps_status st = time_on(B->stream, [&]() { return lbdps_batch_step(B, steps); }, &ms);
-      if (st != LBDPS_OK) return st;
-      if (c == 0 || ms < best) {
-        best = ms;
-        bt = kTuneCandidates[c];
+    float t[kTuneN];
+    for (int round = 0; round < 2; ++round)  // as lbdps_autotune: the faster of two times per candidate
+      for (int c = 0; c < kTuneN; ++c) {
+        for (int b : kv.second) B->beds[b]->tune = kTuneCandidates[c];
+        float ms = 0.f;
+        lbdps_status st = time_on(B->stream, [&]() { return lbdps_batch_step(B, steps); }, &ms);
+        if (st != LBDPS_OK) return st;
+        t[c] = round == 0 ? ms : std::min(t[c], ms);
       }
-    }
+    int bc = 0;
+    for (int c = 1; c < kTuneN; ++c)
+      if (t[c] < t[bc]) bc = c;
+    const lbdps_tuning bt = kTuneCandidates[bc];
     for (int b : kv.second) B->beds[b]->tune = bt;
     cached[kv.first] = bt;
   }
