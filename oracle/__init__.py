@@ -49,6 +49,7 @@ class OrcParams(ctypes.Structure):
         ("omega_dense", ctypes.c_double),
         ("cs_smag", ctypes.c_double),
         ("n_sub", ctypes.c_int32),
+        ("particles_periodic_y", ctypes.c_int32),
     ]
 
 
@@ -143,6 +144,7 @@ def make_params(cfg: dict) -> OrcParams:
     p.omega_dense = float(cfg.get("omega_dense", 1.0))
     p.cs_smag = float(cfg.get("cs_smag", 0.0))
     p.n_sub = int(cfg.get("n_sub", 1))
+    p.particles_periodic_y = int(cfg.get("particles_periodic_y", 0))
     return p
 
 

@@ -14,7 +14,7 @@
  * Units: lattice units, h = dt = 1, so c = h/dt = 1 (note after Eq. 14),
  * c_s^2 = 1/3 (Sec. 2.1, text after Eq. 4) and every h^2/dt factor is 1 (Eq. 25).
  *
- * Interpretations of points the paper leaves open are numbered R1..R41 in the
+ * Interpretations of points the paper leaves open are numbered R1..R44 in the
  * design notes; the comment at each use says which one applies.
  *
  * Parity status: every function is pinned by a closed form, an invariant,
@@ -53,6 +53,9 @@ typedef struct {
   double omega_dense;      /* omega for eps_g <= 0.74 (R9) */
   double cs_smag;          /* Smagorinsky constant, 0 = plain BGK (Eqs. 12-15) */
   int32_t n_sub;           /* particle sub-steps per lattice step, 0 or 1 = one (R41) */
+  int32_t particles_periodic_y; /* 1: particles leaving through a non-periodic y face re-enter at the
+                                   other one (the circulating loop of Sec. 3.2, R44); the gas keeps
+                                   its faces */
 } orc_params;
 
 typedef struct {
@@ -276,6 +279,9 @@ void orc_collide_node(const orc_params *p, const double *f, int64_t n, const dou
 
 static int is_periodic_x(const orc_params *p) { return p->bc[0] == ORC_PERIODIC; }
 static int is_periodic_y(const orc_params *p) { return p->bc[2] == ORC_PERIODIC; }
+/* Periodicity of the particles along y: that of the gas, or the circulating
+ * loop (R44). */
+static int particles_periodic_y(const orc_params *p) { return is_periodic_y(p) || p->particles_periodic_y; }
 
 /* Node index along x for interpolation and gradients: wrap on periodic axes,
  * clamp into [0, nx-1] otherwise (R11, R17). */
@@ -430,7 +436,7 @@ static void advance(const orc_params *p, int64_t np, double *pos, double *vel, c
     double x = pos[2 * k] + vel[2 * k] * h;
     double y = pos[2 * k + 1] + vel[2 * k + 1] * h;
     x = is_periodic_x(p) ? wrap_coord(x, p->nx) : mirror_coord(x, p->nx);
-    y = is_periodic_y(p) ? wrap_coord(y, p->ny) : mirror_coord(y, p->ny);
+    y = particles_periodic_y(p) ? wrap_coord(y, p->ny) : mirror_coord(y, p->ny);
     pos[2 * k] = x;
     pos[2 * k + 1] = y;
   }
@@ -457,7 +463,7 @@ static void separation(const orc_params *p, const double *a, const double *b, do
     else if (x < -0.5 * p->nx)
       x += p->nx;
   }
-  if (is_periodic_y(p)) {
+  if (particles_periodic_y(p)) {
     if (y > 0.5 * p->ny)
       y -= p->ny;
     else if (y < -0.5 * p->ny)
@@ -538,7 +544,7 @@ int orc_contacts_cells(const orc_params *p, int64_t np, const double *pos, int32
           x = (x + nx) % nx;
         }
         if (y < 0 || y >= ny) {
-          if (!is_periodic_y(p)) continue;
+          if (!particles_periodic_y(p)) continue;
           y = (y + ny) % ny;
         }
         int64_t c = (int64_t)y * nx + x;
@@ -700,7 +706,7 @@ void orc_walls(const orc_params *p, int64_t np, const double *pos, double *vel, 
         ++nw;
       }
     }
-    if (!is_periodic_y(p)) {
+    if (!particles_periodic_y(p)) {
       if (y <= r && vel[2 * k + 1] < 0.0) {
         vel[2 * k + 1] = -p->e_pw * vel[2 * k + 1];
         ++nw;

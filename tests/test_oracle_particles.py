@@ -106,12 +106,15 @@ def _brute_numpy(pos, d, nx, ny, per_x, per_y):
     return np.array(out, np.int32).reshape(-1, 2)
 
 
-@pytest.mark.parametrize("bc", [("periodic",) * 4, ("wall", "wall", "periodic", "periodic"),
-                                ("periodic", "periodic", "inlet", "outlet"), ("wall",) * 4])
-def test_contacts_cells_equal_brute(orc, bc):
+@pytest.mark.parametrize("bc,ppy", [(("periodic",) * 4, 0), (("wall", "wall", "periodic", "periodic"), 0),
+                                    (("periodic", "periodic", "inlet", "outlet"), 0), (("wall",) * 4, 0),
+                                    (("wall", "wall", "inlet", "outlet"), 1)])
+def test_contacts_cells_equal_brute(orc, bc, ppy):
     """Sec. 2.2 contact set: the 3x3-cell search returns exactly the O(N^2) set,
-    with periodic minimum images and exact ties (distance == d) included (R25)."""
-    cfg = synth.tiny(nx=7, ny=6, n=90, seed=11, bc=bc)
+    with periodic minimum images and exact ties (distance == d) included (R25);
+    with particles periodic in y over an inlet and an outlet (R44) the image
+    across the y faces counts too."""
+    cfg = synth.tiny(nx=7, ny=6, n=90, seed=11, bc=bc, particles_periodic_y=ppy)
     pos = cfg["pos"].copy()
     # plant exact ties and a wrap-around pair
     pos[0] = (1.0, 1.0)
@@ -123,11 +126,15 @@ def test_contacts_cells_equal_brute(orc, bc):
     p = orc.make_params(cfg)
     a = orc.contacts(p, pos, brute=True)
     b = orc.contacts(p, pos, brute=False)
-    c = _brute_numpy(pos, p.d, p.nx, p.ny, bc[0] == "periodic", bc[2] == "periodic")
+    c = _brute_numpy(pos, p.d, p.nx, p.ny, bc[0] == "periodic", bc[2] == "periodic" or ppy == 1)
     assert a.shape == c.shape and (a == c).all()
     assert (a == b).all()
     assert {(0, 1), (2, 3)} <= set(map(tuple, a.tolist()))
     assert ((4, 5) in set(map(tuple, a.tolist()))) == (bc[0] == "periodic")
+    # a pair touching only through the y faces
+    pos[6], pos[7] = (5.0, 0.1), (5.2, 5.9)
+    pairs = set(map(tuple, orc.contacts(p, pos).tolist()))
+    assert ((6, 7) in pairs) == (bc[2] == "periodic" or ppy == 1)
 
 
 @pytest.mark.slow
@@ -400,3 +407,23 @@ def test_substep_collision_time(orc, nsub):
     assert np.allclose(sim.vel, [[-0.3, 0.0], [0.3, 0.0]], rtol=0, atol=1e-11)
     # the counters describe the last sub-step: the collision is counted only if it fell there
     assert o.ncollisions == (1 if k == nsub else 0)
+
+
+
+def test_circulating_loop_wraps_particles_not_gas(orc):
+    """R44: with the particles periodic in y over an inlet and an outlet, a
+    sphere rising through the top re-enters at the bottom without a wall
+    collision, while the gas keeps its inlet and outlet (the step with the
+    flag off mirrors the sphere at the top and reverses it)."""
+    pos = np.array([[3.5, 5.95]])
+    vel = np.array([[0.0, 0.2]])
+    base = dict(nx=7, ny=6, bc=["wall", "wall", "inlet", "outlet"], pos=pos, vel=vel, g=(0.0, 0.0),
+                inlet_uy=np.full(7, 0.01))
+    on = orc.Sim(_cfg(**base, particles_periodic_y=1))
+    o = on.step(record=True)
+    assert 0.0 <= on.pos[0, 1] < 0.2 and on.vel[0, 1] > 0.19 and o.nwall == 0
+    off = orc.Sim(_cfg(**base))
+    o2 = off.step(record=True)
+    assert 5.8 < off.pos[0, 1] < 6.0 and off.vel[0, 1] < 0 and o2.nwall == 1
+    # the gas is the same in both runs: the flag does not touch the lattice
+    assert np.abs(on.f - off.f).max() < 1e-6
