@@ -65,7 +65,7 @@ typedef enum {
 
 /* Boundary type of a lattice face.  x faces take PERIODIC or WALL; y faces take
  * any.  PERIODIC must be set on both faces of an axis.  Particles see a wall on
- * every non-periodic face. */
+ * every non-periodic face (unless lbdps_params.particles_periodic_y). */
 typedef enum {
   LBDPS_BC_PERIODIC = 0,
   LBDPS_BC_WALL = 1,  /* halfway bounce-back for the gas; particle walls           */
@@ -110,6 +110,10 @@ typedef struct {
                                 hard spheres at the finer interval).  lbdps_counters and
                                 lbdps_get_pairs then describe the last sub-step.  Batched
                                 beds (lbdps_batch_*) take one: LBDPS_E_UNSUPPORTED else */
+  int32_t particles_periodic_y; /* 1: particles leaving through a non-periodic y face re-enter
+                                   at the opposite one, with no particle wall there (the
+                                   circulating loop of the riser, Sec. 3.2); the gas keeps its
+                                   faces.  0 (default): particles follow the gas faces */
 } lbdps_params;
 
 typedef struct lbdps_ctx lbdps_ctx;

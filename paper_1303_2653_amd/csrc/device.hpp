@@ -157,7 +157,8 @@ template <class T> struct Consts {
   int nx, ny, C, nlut;
   unsigned long long nx_m;  // key / nx = (key * nx_m) >> nx_s for 0 <= key < 2^31
   int nx_s;
-  int per_x, per_y, bc_ylo, bc_yhi;
+  int per_x, per_y, bc_ylo, bc_yhi;  // per_y: the particles' periodicity along y
+  int gas_per_y;                     // the lattice's periodicity along y
   int drag_abs;
   int npart;
   T tau, d, mu, vp, m, msum, one_e, e_pw, r;

@@ -733,14 +733,14 @@ template <int P> struct DragTile {
           jn = c + k.nx;
           js = c - k.nx;
         } else {
-          const int i = node_idx(x, k.nx, k.per_x), j = node_idx(y, k.ny, k.per_y);
+          const int i = node_idx(x, k.nx, k.per_x), j = node_idx(y, k.ny, k.gas_per_y);
           const int row = j * k.nx;
           c = row + i;
           // the boundary value serves as the ghost beyond a wall
           ie = row + node_idx(i + 1, k.nx, k.per_x);
           iw = row + node_idx(i - 1, k.nx, k.per_x);
-          jn = node_idx(j + 1, k.ny, k.per_y) * k.nx + i;
-          js = node_idx(j - 1, k.ny, k.per_y) * k.nx + i;
+          jn = node_idx(j + 1, k.ny, k.gas_per_y) * k.nx + i;
+          js = node_idx(j - 1, k.ny, k.gas_per_y) * k.nx + i;
         }
         g.ux[r] = ldu(fl.ugx, c);
         g.uy[r] = ldu(fl.ugy, c);

@@ -409,7 +409,8 @@ template <int P> struct Impl {
       k.nx_m = (unsigned long long)(((1ull << k.nx_s) + (unsigned long long)x->nx - 1) / (unsigned long long)x->nx);
     }
     k.per_x = x->p.bc[0] == BC_PERIODIC;
-    k.per_y = x->p.bc[2] == BC_PERIODIC;
+    k.gas_per_y = x->p.bc[2] == BC_PERIODIC;
+    k.per_y = k.gas_per_y || x->p.particles_periodic_y != 0;  // the circulating loop
     k.bc_ylo = x->p.bc[2];
     k.bc_yhi = x->p.bc[3];
     k.drag_abs = x->p.drag_ratio_mode == 1;
@@ -683,6 +684,8 @@ lbdps_status lbdps_validate_params(const lbdps_params *p, int64_t max_particles)
     return fail(LBDPS_E_INVALID, "pressure_force_sign must be -1, 0 or 1");
   if (!is_fin(p->omega_dense)) return fail(LBDPS_E_INVALID, "omega_dense must be finite");
   if (!is_fin(p->cs_smag) || p->cs_smag < 0) return fail(LBDPS_E_INVALID, "cs_smag must be >= 0");
+  if (p->particles_periodic_y < 0 || p->particles_periodic_y > 1)
+    return fail(LBDPS_E_INVALID, "particles_periodic_y must be 0 or 1");
   if (p->n_sub < 0 || p->n_sub > LBDPS_MAX_SUBSTEPS)
     return fail(LBDPS_E_INVALID, "n_sub must be in [0, " + std::to_string(LBDPS_MAX_SUBSTEPS) + "]");
   if (p->precision < 0 || p->precision > 3) return fail(LBDPS_E_INVALID, "precision must be 0..3");

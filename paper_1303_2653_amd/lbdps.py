@@ -44,7 +44,7 @@ class lbdps_params(ctypes.Structure):
         ("e_pp", c_dbl), ("e_pw", c_dbl), ("g", c_dbl * 2), ("body_force", c_dbl * 2),
         ("drag_ratio_mode", c_i32), ("u_gas_porosity", c_i32), ("omega_mode", c_i32),
         ("pressure_force_sign", c_i32), ("omega_dense", c_dbl), ("cs_smag", c_dbl),
-        ("precision", c_i32), ("diagnostics", c_i32), ("n_sub", c_i32),
+        ("precision", c_i32), ("diagnostics", c_i32), ("n_sub", c_i32), ("particles_periodic_y", c_i32),
     ]
 
 
@@ -143,6 +143,7 @@ def make_params(cfg: dict, precision=None, diagnostics: bool = False) -> lbdps_p
     p.precision = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
     p.diagnostics = int(bool(diagnostics))
     p.n_sub = int(cfg.get("n_sub", 1))
+    p.particles_periodic_y = int(cfg.get("particles_periodic_y", 0))
     return p
 
 

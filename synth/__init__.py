@@ -202,12 +202,12 @@ def paper_bubble(seed: int = 11) -> dict:
 
 def paper_riser(seed: int = 12) -> dict:
     """Table 2: a 60 x 720 riser holding 123 921 spheres of d = 0.2 (2-D solid
-    fraction 0.09012, uniform), time step 6e-6 s, tau = 3 (1.317e-3) + 1/2.  The
-    circulating loop is closed through a periodic y axis (particles leaving
-    the top re-enter at the bottom); the gas starts uniform at the table's
-    inlet velocity 1.52 m/s = 0.0338 (cfg["u0"]) and is driven by a body force equal to
-    the suspension's weight per cell, so the bed neither accelerates nor
-    settles as a whole (R43)."""
+    fraction 0.09012, uniform), time step 6e-6 s, tau = 3 (1.317e-3) + 1/2.
+    Gas enters at the bottom at the table's 1.52 m/s = 0.0338 and leaves at
+    the top; the spheres circulate: one leaving through the top re-enters at
+    the bottom (cfg["particles_periodic_y"]), as the riser's solids return
+    through the loop of a circulating bed.  The gas starts uniform at the
+    inlet velocity (cfg["u0"]) (R43)."""
     nx, ny, n, d = 60, 720, 123_921, 0.2
     r = 0.5 * d
     u = uniform(seed, 2 * n).reshape(n, 2)
@@ -215,12 +215,10 @@ def paper_riser(seed: int = 12) -> dict:
     pos[:, 0] = r + (nx - 2 * r) * u[:, 0]
     pos[:, 1] = ny * u[:, 1]
     pos = pos[cell_order(pos, nx)]
-    g = paper_gravity(6.0e-6)
-    m = 788.5 * math.pi * d ** 3 / 6.0
-    body = n * m * (1.0 - 1.0 / 788.5) * g / (nx * ny)
-    return _cfg("paper-riser-60x720-124k-fp64", nx, ny, ["wall", "wall", "periodic", "periodic"], pos, 100_000,
-                d=d, tau=paper_tau(6.0e-6), cs_smag=PAPER_CS, inlet_uy=None, u0=(0.0, 1.52 * 6.0e-6 / PAPER_H),
-                g=(0.0, -g), G=(0.0, body), precision="fp64")
+    v_in = 1.52 * 6.0e-6 / PAPER_H
+    return _cfg("paper-riser-60x720-124k-fp64", nx, ny, ["wall", "wall", "inlet", "outlet"], pos, 100_000,
+                d=d, tau=paper_tau(6.0e-6), cs_smag=PAPER_CS, inlet_uy=np.full(nx, v_in), u0=(0.0, v_in),
+                particles_periodic_y=1, g=(0.0, -paper_gravity(6.0e-6)), precision="fp64")
 
 
 # Gravity of the batched beds: the bubble bed's balance of bed weight against

@@ -26,6 +26,7 @@ def test_struct_layout_matches_header():
     assert L.lbdps_params.omega_dense.offset == 120
     assert L.lbdps_params.precision.offset == 136
     assert L.lbdps_params.n_sub.offset == 144
+    assert L.lbdps_params.particles_periodic_y.offset == 148
     assert ctypes.sizeof(L.lbdps_params) == 152
 
 
@@ -46,7 +47,7 @@ def test_validation_accepts_workloads():
     ("precision", 7, L.LBDPS_E_INVALID), ("pressure_force_sign", 2, L.LBDPS_E_INVALID),
     ("cs_smag", -0.1, L.LBDPS_E_INVALID), ("cs_smag", float("inf"), L.LBDPS_E_INVALID),
     ("drag_ratio_mode", 3, L.LBDPS_E_INVALID), ("n_sub", -1, L.LBDPS_E_INVALID),
-    ("n_sub", L.LBDPS_MAX_SUBSTEPS + 1, L.LBDPS_E_INVALID),
+    ("n_sub", L.LBDPS_MAX_SUBSTEPS + 1, L.LBDPS_E_INVALID), ("particles_periodic_y", 2, L.LBDPS_E_INVALID),
 ])
 def test_validation_rejects(field, value, code):
     p = L.make_params(synth.bubble_small())
