@@ -326,7 +326,7 @@ def run_beds(args, torch, L):
         "warmup": args.warmup, "ms_per_step": round(ms_graph / K, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)", "bf16": "f32 (bf16 storage)"}[prec],
-        "data": "synthetic (seeded splitmix64 beds, recipe in DESIGN.md)",
+        "data": "synthetic (seeded splitmix64 beds)",
         "config": {"workload": f"beds-64-uneven-{prec}", "beds": len(cfgs), "cells": sum(Cs), "particles": sum(Ns),
                    "precision": prec, "launch": "hipGraph of batched phases"},
         "particle_updates_per_s": float(f"{sum(Ns) * K / s:.4e}"),
@@ -442,7 +442,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)", "bf16": "f32 (bf16 storage)"}[args.precision],
-        "data": "synthetic (seeded splitmix64 bed, recipe in DESIGN.md)",
+        "data": "synthetic (seeded splitmix64 bed)",
         "config": {"workload": workload_name(cfg["name"], args.precision)
                    + (f"-nsub{args.n_sub}" if args.n_sub > 1 else "")
                    + (f"-les{args.cs_smag:g}" if args.cs_smag is not None else ""), "nx": cfg["nx"], "ny": cfg["ny"],
