@@ -29,7 +29,8 @@ def say(*a):
 
 
 def uneven_beds(prec):
-    """Six beds of different shapes, faces and loads, one without particles."""
+    """Eight beds of different shapes, faces and loads, one without particles,
+    one with the Smagorinsky model and one whose particles circulate in y."""
     beds = [
         synth.tiny(nx=16, ny=24, n=60, seed=1),
         synth.tiny(nx=37, ny=20, n=300, seed=2, bc=("wall", "wall", "periodic", "periodic"), G=(0.0, 2e-5),
@@ -38,6 +39,11 @@ def uneven_beds(prec):
         synth.tiny(nx=64, ny=40, n=0, seed=4, bc=("periodic",) * 4, G=(1e-5, 0.0)),
         synth.tiny(nx=48, ny=64, n=900, seed=5, bc=("wall",) * 4, band=30.0, g=(2e-5, -1e-5), vel_scale=1e-3),
         synth.tiny(nx=20, ny=50, n=200, seed=6, band=20.0),
+        # the Smagorinsky model on; particles circulating over an inlet and an outlet
+        synth.tiny(nx=24, ny=30, n=250, seed=7, bc=("wall", "wall", "periodic", "periodic"), G=(0.0, 3e-5),
+                   g=(0.0, -2e-5), vel_scale=2e-3, cs_smag=1.5),
+        synth.tiny(nx=21, ny=26, n=220, seed=8, bc=("wall", "wall", "inlet", "outlet"), band=26.0,
+                   particles_periodic_y=1, vel_scale=2e-2),
     ]
     for b in beds:
         b["precision"] = prec
