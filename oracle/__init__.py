@@ -109,6 +109,10 @@ def lib():
         L.orc_step.argtypes = [P, vp, vp, i64, vp, vp, ctypes.POINTER(OrcOut)]
         L.orc_conservation.argtypes = [P, vp, i64, vp, vp]
         L.orc_lattice.argtypes = [vp, vp, vp]
+        L.orc3_lattice.argtypes = [vp, vp]
+        L.orc3_feq.restype = ctypes.c_double
+        L.orc3_feq.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc3_bgk_step.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, vp]
         _lib = L
     return _lib
 
@@ -300,6 +304,26 @@ def voidage(p: OrcParams, pos, y0=0, y1=None, threshold=0.85):
     cols = e[y0:y1].sum(axis=0)
     count = int((e[y0:y1] > threshold).sum())
     return rows, cols, count
+
+
+# ---------------------------------------------------------------- 3-D gas lattice
+def lattice3():
+    c = np.zeros((19, 3), np.int32)
+    w = np.zeros(19)
+    lib().orc3_lattice(_ptr(c), _ptr(w))
+    return c, w
+
+
+def feq3(i, rho, ux, uy, uz):
+    return lib().orc3_feq(int(i), float(rho), float(ux), float(uy), float(uz))
+
+
+def bgk3_step(f, tau):
+    """One periodic D3Q19 BGK step of f [19][nz][ny][nx] (returns a new array)."""
+    f = np.array(f, np.float64, copy=True)
+    _, nz, ny, nx = f.shape
+    lib().orc3_bgk_step(nx, ny, nz, float(tau), _ptr(f))
+    return f
 
 
 def equilibrium_state(nx, ny, rho=1.0, ux=0.0, uy=0.0):

@@ -939,3 +939,65 @@ void orc_conservation(const orc_params *p, const double *f, int64_t np, const do
   out[3] = qx;
   out[4] = qy;
 }
+
+/* ==== 3-D gas lattice (the 3-D extension the paper names as future work) ====
+ * D3Q19: the rest velocity, the 6 face neighbours (weight 1/18) and the 12
+ * edge neighbours (weight 1/36), rest weight 1/3, c_s^2 = 1/3; the
+ * equilibrium has the same second-order form as in 2-D (Eq. 2 with
+ * c_i.u in three dimensions).  Only the gas part is here: the BGK step on a
+ * fully periodic box, the first piece of the 3-D coupled step. */
+static const int C3[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                              {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+                              {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+static double w3(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+void orc3_lattice(int32_t *c, double *w) {
+  for (int i = 0; i < 19; ++i) {
+    for (int a = 0; a < 3; ++a) c[3 * i + a] = C3[i][a];
+    w[i] = w3(i);
+  }
+}
+
+double orc3_feq(int i, double rho, double ux, double uy, double uz) {
+  double cu = C3[i][0] * ux + C3[i][1] * uy + C3[i][2] * uz;
+  double uu = ux * ux + uy * uy + uz * uz;
+  return w3(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+}
+
+/*
+ * One BGK step on a periodic nx x ny x nz box (Eq. 1 with the 3-D lattice):
+ * moments, relaxation towards f^eq with 1/tau, then pull streaming
+ * f_i(x) <- f*_i(x - c_i).  f[19][nz][ny][nx] is advanced in place.
+ */
+void orc3_bgk_step(int32_t nx, int32_t ny, int32_t nz, double tau, double *f) {
+  const int64_t C = (int64_t)nx * ny * nz;
+  double *fs = (double *)malloc((size_t)(19 * C) * sizeof(double));
+  for (int64_t c = 0; c < C; ++c) {
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int i = 0; i < 19; ++i) {
+      double v = f[i * C + c];
+      rho += v;
+      jx += C3[i][0] * v;
+      jy += C3[i][1] * v;
+      jz += C3[i][2] * v;
+    }
+    double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    for (int i = 0; i < 19; ++i) {
+      double v = f[i * C + c];
+      fs[i * C + c] = v - (v - orc3_feq(i, rho, ux, uy, uz)) / tau;
+    }
+  }
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        int64_t c = ((int64_t)z * ny + y) * nx + x;
+        for (int i = 0; i < 19; ++i) {
+          int sx = ((x - C3[i][0]) % nx + nx) % nx;
+          int sy = ((y - C3[i][1]) % ny + ny) % ny;
+          int sz = ((z - C3[i][2]) % nz + nz) % nz;
+          f[i * C + c] = fs[i * C + ((int64_t)sz * ny + sy) * nx + sx];
+        }
+      }
+  free(fs);
+}
