@@ -44,6 +44,7 @@ WORKLOADS = {
     "beds": lambda: __import__("synth").beds(64),
     "paper_bubble": lambda: __import__("synth").paper_bubble(),
     "paper_riser": lambda: __import__("synth").paper_riser(),
+    "d3q19_gas": None,  # the 3-D gas lattice alone: run_d3q19
 }
 SIZES = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4), "bf16": (2, 4)}  # (population, scalar) bytes
 
@@ -262,6 +263,58 @@ def time_region(torch, stream, fn):
     return e0.elapsed_time(e1)
 
 
+def run_d3q19(args, torch, L):
+    """The 3-D gas lattice alone (D3Q19 BGK collide-stream, periodic box) on the
+    3-D riser's lattice, 256 x 256 x 1024 cells, in FP16 deviation storage by
+    default: MLUPS, and the kernel against the HBM roofline (each step reads
+    and writes 19 populations per cell)."""
+    prec = args.precision if args.precision_given else "fp16"
+    nx, ny, nz = 256, 256, 1024
+    C = nx * ny * nz
+    code = {"fp64": L.LBDPS_FP64, "fp32": L.LBDPS_FP32, "fp16": L.LBDPS_FP32_STORE_FP16,
+            "bf16": L.LBDPS_FP32_STORE_BF16}[prec]
+    dt = {"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.float16, "bf16": torch.bfloat16}[prec]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        a = torch.zeros(19 * C, dtype=dt, device="cuda")  # deviations 0: gas at rest (FP64: filled below)
+        if prec == "fp64":
+            for i, w in enumerate([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12):
+                a[i * C:(i + 1) * C] = w
+        b = torch.empty_like(a)
+    stream.synchronize()
+
+    def step(n):
+        nonlocal a, b
+        for _ in range(n):
+            L.check(L.lbdps3_bgk_step(a.data_ptr(), b.data_ptr(), nx, ny, nz, 0.6, code, stream.cuda_stream),
+                    "lbdps3_bgk_step")
+            a, b = b, a
+
+    step(args.warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream.synchronize()
+    e0.record(stream)
+    step(args.steps)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    us = ms / args.steps * 1e3
+    nbytes = 2 * 19 * SIZES[prec][0] * C
+    achieved = nbytes / (us * 1e-6) / 1e9
+    cb = copy_bandwidth(torch, 1 << 30)
+    return {"metric": METRIC, "value": round(C * args.steps / (ms / 1e3) / 1e6, 2), "unit": "MLUPS", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)", "bf16": "f32 (bf16 storage)"}[prec],
+            "data": "synthetic (gas at rest, periodic box)",
+            "config": {"workload": f"d3q19-gas-{nx}x{ny}x{nz}-{prec}", "nx": nx, "ny": ny, "nz": nz,
+                       "precision": prec, "tau": 0.6, "particles": 0},
+            "roofline": {"bound": "hbm", "kernel": "k3_bgk", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "bytes_per_launch": int(nbytes), "us_per_launch": round(us, 3), "copy_GBs": cb["GBs"],
+                         "frac_of_copy": round(achieved / cb["GBs"], 4)}}
+
+
 def run_beds(args, torch, L):
     """The batching workload: one JSON line (see the module docstring)."""
     cfgs = WORKLOADS["beds"]()
@@ -403,6 +456,9 @@ def main():
         return
     from paper_1303_2653_amd import lbdps as L
 
+    if args.workload == "d3q19_gas":
+        print(json.dumps(run_d3q19(args, torch, L)), flush=True)
+        return
     if args.workload == "beds":
         print(json.dumps(run_beds(args, torch, L)), flush=True)
         return

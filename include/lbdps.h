@@ -229,6 +229,24 @@ lbdps_status lbdps_set_inlet(lbdps_ctx *ctx, const double *h_inlet_uy);
 lbdps_status lbdps_voidage(lbdps_ctx *ctx, int32_t y0, int32_t y1, double threshold, double *d_row_sum,
                            double *d_col_sum, int64_t *d_count);
 
+/*
+ * The 3-D gas lattice, first piece of the 3-D extension (the paper names 3-D
+ * as future work): one BGK collide-stream step (the 3-D form of Eq. 1, no
+ * particles) of the D3Q19 lattice on a periodic nx x ny x nz box.  D3Q19: the
+ * rest velocity (weight 1/3), the 6 face neighbours (1/18) and the 12 edge
+ * neighbours (1/36) in the order rest, +x, -x, +y, -y, +z, -z, (+x+y),
+ * (-x-y), (+x-y), (-x+y), (+x+z), (-x-z), (+x-z), (-x+z), (+y+z), (-y-z),
+ * (+y-z), (-y+z); f^eq of Eq. 2 with c_s^2 = 1/3.
+ *   d_fin, d_fout: distinct device buffers [19][nz][ny][nx] in the storage of
+ *   precision (lbdps_precision): FP64 values, or the deviations f_i - w_i as
+ *   FP32, FP16 or BF16 with FP32 arithmetic.  The caller owns both.
+ *   tau > 0.5.  stream: hipStream_t (NULL = default).  Asynchronous.
+ * LBDPS_E_INVALID for NULL or equal buffers, a bad tau or precision;
+ * LBDPS_E_SHAPE for a dimension below 1.
+ */
+lbdps_status lbdps3_bgk_step(const void *d_fin, void *d_fout, int32_t nx, int32_t ny, int32_t nz, double tau,
+                             int32_t precision, void *stream);
+
 /* Kernels of one step, for per-kernel timing. */
 typedef enum {
   LBDPS_K_COLLIDE = 0,    /* deposition + collision + streaming                     */

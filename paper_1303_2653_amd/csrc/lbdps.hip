@@ -15,6 +15,7 @@
 
 #include "batch.hpp"
 #include "kernels.hpp"
+#include "lattice3d.hpp"
 #include "lbdps.h"
 
 using namespace lbdps;
@@ -777,6 +778,37 @@ lbdps_status lbdps_step(lbdps_ctx *x, int32_t nsteps) {
 lbdps_status lbdps_collide_particles(lbdps_ctx *x) {
   if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
   return dispatch(x, [&](auto impl) { return decltype(impl)::collide_particles(x); });
+}
+
+lbdps_status lbdps3_bgk_step(const void *d_fin, void *d_fout, int32_t nx, int32_t ny, int32_t nz, double tau,
+                             int32_t precision, void *stream) {
+  if (!d_fin || !d_fout || d_fin == d_fout) return fail(LBDPS_E_INVALID, "d_fin and d_fout must be distinct buffers");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(LBDPS_E_SHAPE, "nx, ny and nz must be >= 1");
+  if (!(std::isfinite(tau) && tau > 0.5)) return fail(LBDPS_E_INVALID, "tau must be > 0.5");
+  const long long C = (long long)nx * ny * nz;
+  const unsigned grid = (unsigned)((C + BLOCK - 1) / BLOCK);
+  const hipStream_t st = (hipStream_t)stream;
+  switch (precision) {
+    case PREC_FP64:
+      hipLaunchKernelGGL(k3_bgk<PREC_FP64>, dim3(grid), dim3(BLOCK), 0, st, (const double *)d_fin, (double *)d_fout,
+                         nx, ny, nz, tau);
+      break;
+    case PREC_FP32:
+      hipLaunchKernelGGL(k3_bgk<PREC_FP32>, dim3(grid), dim3(BLOCK), 0, st, (const float *)d_fin, (float *)d_fout, nx,
+                         ny, nz, (float)tau);
+      break;
+    case PREC_FP16DEV:
+      hipLaunchKernelGGL(k3_bgk<PREC_FP16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const _Float16 *)d_fin,
+                         (_Float16 *)d_fout, nx, ny, nz, (float)tau);
+      break;
+    case PREC_BF16DEV:
+      hipLaunchKernelGGL(k3_bgk<PREC_BF16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const uint16_t *)d_fin,
+                         (uint16_t *)d_fout, nx, ny, nz, (float)tau);
+      break;
+    default:
+      return fail(LBDPS_E_INVALID, "precision must be 0..3");
+  }
+  return launch_status("lbdps3_bgk_step");
 }
 
 lbdps_status lbdps_set_inlet(lbdps_ctx *x, const double *h_inlet_uy) {

@@ -65,6 +65,7 @@ _SIGS = {
     "lbdps_step": (c_i32, [c_vp, c_i32]),
     "lbdps_collide_particles": (c_i32, [c_vp]),
     "lbdps_set_inlet": (c_i32, [c_vp, c_vp]),
+    "lbdps3_bgk_step": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_dbl, c_i32, c_vp]),
     "lbdps_voidage": (c_i32, [c_vp, c_i32, c_i32, c_dbl, c_vp, c_vp, c_vp]),
     "lbdps_get_fields": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lbdps_get_particles": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -102,7 +103,7 @@ for _name, (_res, _args) in _SIGS.items():
 def header_functions(path: str = HEADER) -> list:
     """Names of the functions declared in include/lbdps.h."""
     text = open(path).read()
-    decl = r"^\s*(?:lbdps_status|const\s+char\s*\*)\s*(lbdps_[a-z_]+)\s*\("
+    decl = r"^\s*(?:lbdps_status|const\s+char\s*\*)\s*(lbdps[0-9]*_[a-z0-9_]+)\s*\("
     return sorted(set(re.findall(decl, text, flags=re.M)))
 
 

@@ -1,0 +1,72 @@
+"""The 3-D gas lattice (D3Q19 BGK on a periodic box, the first piece of the
+3-D extension) through the C ABI against the oracle's step on the same
+state: FP64 bit for bit; the deviation storages within their rounding."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+L = pytest.importorskip("paper_1303_2653_amd.lbdps")
+import oracle  # noqa: E402
+
+DT = {"fp64": (L.LBDPS_FP64, torch.float64), "fp32": (L.LBDPS_FP32, torch.float32),
+      "fp16": (L.LBDPS_FP32_STORE_FP16, torch.float16), "bf16": (L.LBDPS_FP32_STORE_BF16, torch.bfloat16)}
+
+
+def state(nx, ny, nz, seed=4):
+    """A flow of u ~ 0.02 with a 1e-3 perturbation, [19][nz][ny][nx]."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ux = 0.02 * np.sin(2 * np.pi * z / nz)
+    uy = 0.01 * np.cos(2 * np.pi * x / nx)
+    f = np.empty((19, nz, ny, nx))
+    for i in range(19):
+        f[i] = np.vectorize(lambda a, b: oracle.feq3(i, 1.0, a, b, 0.0))(ux, uy)
+    return f + (rng.random(f.shape) - 0.5) * 1e-3
+
+
+def to_storage(f, prec):
+    code, dt = DT[prec]
+    if prec == "fp64":
+        return torch.tensor(f, dtype=dt, device="cuda")
+    _, w = oracle.lattice3()
+    return torch.tensor(f - w[:, None, None, None], dtype=torch.float64, device="cuda").to(dt)
+
+
+def from_storage(t, prec):
+    a = t.to(torch.float64).cpu().numpy()
+    if prec == "fp64":
+        return a
+    _, w = oracle.lattice3()
+    return a + w[:, None, None, None]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 0.0), ("fp32", 1e-7), ("fp16", 1e-5), ("bf16", 1e-4)])
+def test_d3q19_steps_match_oracle(prec, tol):
+    nx, ny, nz, steps, tau = 12, 10, 9, 5, 0.7
+    f0 = state(nx, ny, nz)
+    a = to_storage(f0, prec)
+    ref = from_storage(a, prec)  # the oracle starts from the stored state
+    b = torch.empty_like(a)
+    code = DT[prec][0]
+    for _ in range(steps):
+        L.check(L.lbdps3_bgk_step(a.data_ptr(), b.data_ptr(), nx, ny, nz, tau, code, None), "lbdps3_bgk_step")
+        a, b = b, a
+        ref = oracle.bgk3_step(ref, tau)
+    torch.cuda.synchronize()
+    got = from_storage(a, prec)
+    err = float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1.0))
+    print(prec, "D3Q19 after", steps, "steps: error", err, flush=True)
+    assert err <= tol
+
+
+def test_d3q19_rejects_bad_arguments():
+    a = torch.zeros(19 * 8, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    assert L.lbdps3_bgk_step(a.data_ptr(), a.data_ptr(), 2, 2, 2, 0.7, L.LBDPS_FP32, None) == L.LBDPS_E_INVALID
+    assert L.lbdps3_bgk_step(a.data_ptr(), b.data_ptr(), 0, 2, 2, 0.7, L.LBDPS_FP32, None) == L.LBDPS_E_SHAPE
+    assert L.lbdps3_bgk_step(a.data_ptr(), b.data_ptr(), 2, 2, 2, 0.5, L.LBDPS_FP32, None) == L.LBDPS_E_INVALID
+    assert L.lbdps3_bgk_step(a.data_ptr(), b.data_ptr(), 2, 2, 2, 0.7, 9, None) == L.LBDPS_E_INVALID
