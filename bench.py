@@ -127,9 +127,10 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None):
     return out
 
 
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_2653_amd", "csrc", f) for f in ("kernels.hpp", "device.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_2653_amd", "csrc", f)
+                  for f in ("kernels.hpp", "device.hpp", "lattice3d.hpp")]
 KERNEL_KEYS = {"collide": "k_collide", "drag": "k_drag", "scan": "k_scan_cells", "scatter": "k_scatter",
-               "contacts": "k_contacts", "resolve": "k_resolve_clusters"}
+               "contacts": "k_contacts", "resolve": "k_resolve_clusters", "k3_bgk": "k3_bgk"}
 
 
 def kernel_source_hash() -> str:
@@ -310,7 +311,8 @@ def run_d3q19(args, torch, L):
             "config": {"workload": f"d3q19-gas-{nx}x{ny}x{nz}-{prec}", "nx": nx, "ny": ny, "nz": nz,
                        "precision": prec, "tau": 0.6, "particles": 0},
             "roofline": {"bound": "hbm", "kernel": "k3_bgk", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic("d3q19_gas", "k3_bgk") if prec == "fp16" else None,
                          "bytes_per_launch": int(nbytes), "us_per_launch": round(us, 3), "copy_GBs": cb["GBs"],
                          "frac_of_copy": round(achieved / cb["GBs"], 4)}}
 
