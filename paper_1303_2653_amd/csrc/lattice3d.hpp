@@ -96,4 +96,76 @@ __global__ __launch_bounds__(BLOCK) void k3_bgk(const typename Prec<P>::S *__res
   }
 }
 
+// The 16-bit storages with an even nx: one thread per pair of cells (x, x+1),
+// x even, so each plane is read with one 4-byte load per thread (a whole
+// 256-byte run per wavefront instruction).  Populations that stay in their
+// column (c_x = 0) are stored as pairs; the others go out one by one.  The
+// arithmetic per cell is that of k3_bgk.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S *__restrict__ fin,
+                                                      typename Prec<P>::S *__restrict__ fout, int nx, int ny, int nz,
+                                                      float tau) {
+  static_assert(sizeof(typename Prec<P>::S) == 2, "16-bit storage");
+  using S = typename Prec<P>::S;
+  const long long C = (long long)nx * ny * nz;
+  const long long p = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (2 * p >= C) return;
+  const long long c = 2 * p;  // even: x even, x + 1 in the same row
+  const int x = (int)(c % nx);
+  const long long yz = c / nx;
+  const int y = (int)(yz % ny), z = (int)(yz / ny);
+  float f0[Q3], f1[Q3];
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) {
+    struct alignas(4) S2 { S a, b; };
+    const S2 v = *reinterpret_cast<const S2 *>(fin + (size_t)i * C + c);
+    f0[i] = load_v<P>(&v.a, 0);
+    f1[i] = load_v<P>(&v.b, 0);
+  }
+  const float omg = dv<P>(1.0f, tau);
+  auto relax = [&](float *f) {
+    float r1 = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      r1 += f[i];
+      jx += (float)c3(i, 0) * f[i];
+      jy += (float)c3(i, 1) * f[i];
+      jz += (float)c3(i, 2) * f[i];
+    }
+    const float rho = 1.f + r1;
+    const float ir = dv<P>(1.0f, rho);
+    const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    const float uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      const float cu = (float)c3(i, 0) * ux + (float)c3(i, 1) * uy + (float)c3(i, 2) * uz;
+      const float geq = w3<float>(i) * (r1 + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+      f[i] = f[i] - (f[i] - geq) * omg;
+    }
+  };
+  relax(f0);
+  relax(f1);
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) {
+    int ty = y + c3(i, 1), tz = z + c3(i, 2);
+    ty = ty < 0 ? ty + ny : (ty >= ny ? ty - ny : ty);
+    tz = tz < 0 ? tz + nz : (tz >= nz ? tz - nz : tz);
+    const long long row = ((long long)tz * ny + ty) * nx;
+    S *plane = fout + (size_t)i * C;
+    if (c3(i, 0) == 0) {
+      struct alignas(4) S2 { S a, b; };
+      S2 v;
+      store_v<P>(&v.a, 0, f0[i]);
+      store_v<P>(&v.b, 0, f1[i]);
+      *reinterpret_cast<S2 *>(plane + row + x) = v;
+    } else {
+      int t0 = x + c3(i, 0), t1 = x + 1 + c3(i, 0);
+      t0 = t0 < 0 ? t0 + nx : (t0 >= nx ? t0 - nx : t0);
+      t1 = t1 < 0 ? t1 + nx : (t1 >= nx ? t1 - nx : t1);
+      store_v<P>(plane, (size_t)(row + t0), f0[i]);
+      store_v<P>(plane, (size_t)(row + t1), f1[i]);
+    }
+  }
+}
+
 }  // namespace lbdps

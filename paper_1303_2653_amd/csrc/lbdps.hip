@@ -787,6 +787,9 @@ lbdps_status lbdps3_bgk_step(const void *d_fin, void *d_fout, int32_t nx, int32_
   if (!(std::isfinite(tau) && tau > 0.5)) return fail(LBDPS_E_INVALID, "tau must be > 0.5");
   const long long C = (long long)nx * ny * nz;
   const unsigned grid = (unsigned)((C + BLOCK - 1) / BLOCK);
+  // 16-bit storage, even rows and 4-byte aligned buffers: two cells per thread
+  const bool pairs = nx % 2 == 0 && ((uintptr_t)d_fin & 3) == 0 && ((uintptr_t)d_fout & 3) == 0;
+  const unsigned grid2 = (unsigned)((C / 2 + BLOCK - 1) / BLOCK);
   const hipStream_t st = (hipStream_t)stream;
   switch (precision) {
     case PREC_FP64:
@@ -798,12 +801,20 @@ lbdps_status lbdps3_bgk_step(const void *d_fin, void *d_fout, int32_t nx, int32_
                          ny, nz, (float)tau);
       break;
     case PREC_FP16DEV:
-      hipLaunchKernelGGL(k3_bgk<PREC_FP16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const _Float16 *)d_fin,
-                         (_Float16 *)d_fout, nx, ny, nz, (float)tau);
+      if (pairs)
+        hipLaunchKernelGGL(k3_bgk_pairs<PREC_FP16DEV>, dim3(grid2), dim3(BLOCK), 0, st, (const _Float16 *)d_fin,
+                           (_Float16 *)d_fout, nx, ny, nz, (float)tau);
+      else
+        hipLaunchKernelGGL(k3_bgk<PREC_FP16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const _Float16 *)d_fin,
+                           (_Float16 *)d_fout, nx, ny, nz, (float)tau);
       break;
     case PREC_BF16DEV:
-      hipLaunchKernelGGL(k3_bgk<PREC_BF16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const uint16_t *)d_fin,
-                         (uint16_t *)d_fout, nx, ny, nz, (float)tau);
+      if (pairs)
+        hipLaunchKernelGGL(k3_bgk_pairs<PREC_BF16DEV>, dim3(grid2), dim3(BLOCK), 0, st, (const uint16_t *)d_fin,
+                           (uint16_t *)d_fout, nx, ny, nz, (float)tau);
+      else
+        hipLaunchKernelGGL(k3_bgk<PREC_BF16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const uint16_t *)d_fin,
+                           (uint16_t *)d_fout, nx, ny, nz, (float)tau);
       break;
     default:
       return fail(LBDPS_E_INVALID, "precision must be 0..3");
