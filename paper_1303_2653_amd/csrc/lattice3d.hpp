@@ -99,7 +99,9 @@ __global__ __launch_bounds__(BLOCK) void k3_bgk(const typename Prec<P>::S *__res
 // The 16-bit storages with an even nx: one thread per pair of cells (x, x+1),
 // x even, so each plane is read with one 4-byte load per thread (a whole
 // 256-byte run per wavefront instruction).  Populations that stay in their
-// column (c_x = 0) are stored as pairs; the others go out one by one.  The
+// column (c_x = 0) are stored as pairs; for the others each thread assembles
+// the word of its own pair from one of its values and one of the adjacent
+// lane's, so nearly every store is a full 4-byte word as well.  The
 // arithmetic per cell is that of k3_bgk.
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S *__restrict__ fin,
@@ -114,6 +116,8 @@ __global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S 
   const int x = (int)(c % nx);
   const long long yz = c / nx;
   const int y = (int)(yz % ny), z = (int)(yz / ny);
+  const int q = x / 2, nq = nx / 2;       // pair index within the row
+  const int lane = (int)(threadIdx.x & 63);
   float f0[Q3], f1[Q3];
 #pragma unroll
   for (int i = 0; i < Q3; ++i) {
@@ -159,11 +163,36 @@ __global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S 
       store_v<P>(&v.b, 0, f1[i]);
       *reinterpret_cast<S2 *>(plane + row + x) = v;
     } else {
-      int t0 = x + c3(i, 0), t1 = x + 1 + c3(i, 0);
-      t0 = t0 < 0 ? t0 + nx : (t0 >= nx ? t0 - nx : t0);
-      t1 = t1 < 0 ? t1 + nx : (t1 >= nx ? t1 - nx : t1);
-      store_v<P>(plane, (size_t)(row + t0), f0[i]);
-      store_v<P>(plane, (size_t)(row + t1), f1[i]);
+      // The pair moves one cell along x, so its two values straddle two
+      // aligned words. Each thread writes the word of its own pair, taking
+      // the half that comes from the neighbouring pair from the adjacent
+      // lane; at a wave's edge and at the row's periodic seam the value
+      // without a partner in the wave goes out as a single 2-byte store.
+      S t;
+      store_v<P>(&t, 0, f0[i]);
+      const unsigned s0 = *reinterpret_cast<const unsigned short *>(&t);
+      store_v<P>(&t, 0, f1[i]);
+      const unsigned s1 = *reinterpret_cast<const unsigned short *>(&t);
+      unsigned *word = reinterpret_cast<unsigned *>(plane + row + x);
+      if (c3(i, 0) > 0) {
+        // cell x-1 (previous pair's second) -> x, cell x -> x+1, cell x+1 -> x+2
+        const unsigned prev = (unsigned)__shfl_up((int)s1, 1, 64);
+        if (lane > 0 && q > 0) {
+          *word = (prev & 0xffffu) | (s0 << 16);
+        } else {
+          store_v<P>(plane, (size_t)(row + x + 1), f0[i]);
+        }
+        if (lane == 63 || q == nq - 1) store_v<P>(plane, (size_t)(row + (x + 2 == nx ? 0 : x + 2)), f1[i]);
+      } else {
+        // cell x+1 -> x, cell x+2 (next pair's first) -> x+1, cell x -> x-1
+        const unsigned next = (unsigned)__shfl_down((int)s0, 1, 64);
+        if (lane < 63 && q < nq - 1) {
+          *word = s1 | ((next & 0xffffu) << 16);
+        } else {
+          store_v<P>(plane, (size_t)(row + x), f1[i]);
+        }
+        if (lane == 0 || q == 0) store_v<P>(plane, (size_t)(row + (x == 0 ? nx - 1 : x - 1)), f0[i]);
+      }
     }
   }
 }

@@ -73,3 +73,35 @@ def test_d3q19_rejects_bad_arguments():
     assert L.lbdps3_bgk_step(a.data_ptr(), b.data_ptr(), 0, 2, 2, 0.7, L.LBDPS_FP32, None) == L.LBDPS_E_SHAPE
     assert L.lbdps3_bgk_step(a.data_ptr(), b.data_ptr(), 2, 2, 2, 0.5, L.LBDPS_FP32, None) == L.LBDPS_E_INVALID
     assert L.lbdps3_bgk_step(a.data_ptr(), b.data_ptr(), 2, 2, 2, 0.7, 9, None) == L.LBDPS_E_INVALID
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("nx", [2, 12, 130, 160, 256])
+def test_d3q19_pairs_match_single_cells(prec, nx):
+    """The two-cells-per-thread form (even nx, 4-byte aligned planes) against
+    the one-cell form on the same state, bit for bit: both do the same
+    arithmetic, so any difference is a misplaced store. A buffer offset by
+    one element takes the one-cell form. The state is the rest weights plus
+    deviations of 1e-2 drawn per population, so that a value written to a
+    neighbour's slot is far from the right one; nx of 130 and 160 put row
+    ends inside a wavefront and wavefront ends inside a row."""
+    ny, nz, steps, tau = 5, 3, 3, 0.8
+    code, dt = DT[prec]
+    C = nx * ny * nz
+    rng = np.random.default_rng(nx)
+    g = torch.tensor((rng.random(19 * C) - 0.5) * 2e-2, dtype=torch.float64).to(dt).cuda()
+    outs = []
+    for off in (0, 1):
+        a = torch.zeros(19 * C + 2, dtype=dt, device="cuda")
+        b = torch.zeros_like(a)
+        a[off:off + 19 * C] = g
+        pa, pb = a[off:].data_ptr(), b[off:].data_ptr()
+        assert (pa % 4 == 0) == (off == 0)
+        for _ in range(steps):
+            L.check(L.lbdps3_bgk_step(pa, pb, nx, ny, nz, tau, code, None), "lbdps3_bgk_step")
+            pa, pb = pb, pa
+        torch.cuda.synchronize()
+        res = a if steps % 2 == 0 else b
+        outs.append(res[off:off + 19 * C].view(torch.int16).cpu().numpy())
+    bad = np.flatnonzero(outs[0] != outs[1])
+    assert bad.size == 0, f"{bad.size} values differ, first at plane {bad[0] // C} cell {bad[0] % C}"
