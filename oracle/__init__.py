@@ -113,6 +113,8 @@ def lib():
         L.orc3_feq.restype = ctypes.c_double
         L.orc3_feq.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc3_bgk_step.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, vp]
+        L.orc3_psm_step.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                    vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -324,6 +326,20 @@ def bgk3_step(f, tau):
     _, nz, ny, nx = f.shape
     lib().orc3_bgk_step(nx, ny, nz, float(tau), _ptr(f))
     return f
+
+
+def psm3_step(f, tau, d, n, vs):
+    """One periodic D3Q19 step with the solids' partial saturation (Eqs. 6-7,
+    9, 25 on the 3-D lattice): n [nz][ny][nx] spheres of diameter d per cell
+    moving with vs [3][nz][ny][nx].  Returns (new f, force [3][nz][ny][nx])."""
+    f = np.array(f, np.float64, copy=True)
+    _, nz, ny, nx = f.shape
+    n = np.ascontiguousarray(n, np.int32)
+    vs = np.ascontiguousarray(vs, np.float64)
+    assert n.shape == (nz, ny, nx) and vs.shape == (3, nz, ny, nx)
+    force = np.zeros((3, nz, ny, nx))
+    lib().orc3_psm_step(nx, ny, nz, float(tau), float(d), _ptr(n), _ptr(vs), _ptr(f), _ptr(force))
+    return f, force
 
 
 def equilibrium_state(nx, ny, rho=1.0, ux=0.0, uy=0.0):
