@@ -45,6 +45,7 @@ WORKLOADS = {
     "paper_bubble": lambda: __import__("synth").paper_bubble(),
     "paper_riser": lambda: __import__("synth").paper_riser(),
     "d3q19_gas": None,  # the 3-D gas lattice alone: run_d3q19
+    "d3q19_psm": None,  # the 3-D lattice with solids given per cell: run_d3q19
 }
 SIZES = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4), "bf16": (2, 4)}  # (population, scalar) bytes
 
@@ -130,7 +131,7 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None):
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_2653_amd", "csrc", f)
                   for f in ("kernels.hpp", "device.hpp", "lattice3d.hpp")]
 KERNEL_KEYS = {"collide": "k_collide", "drag": "k_drag", "scan": "k_scan_cells", "scatter": "k_scatter",
-               "contacts": "k_contacts", "resolve": "k_resolve_clusters", "k3_bgk": "k3_bgk"}
+               "contacts": "k_contacts", "resolve": "k_resolve_clusters", "k3_bgk": "k3_bgk", "k3_psm": "k3_psm"}
 
 
 def kernel_source_hash() -> str:
@@ -284,11 +285,29 @@ def run_d3q19(args, torch, L):
         b = torch.empty_like(a)
     stream.synchronize()
 
+    psm = args.workload == "d3q19_psm"
+    sT = SIZES[prec][1]
+    if psm:
+        # the 3-D riser's solids: 10 M spheres of d = 0.5 over the 67.1 M cells,
+        # Poisson counts per cell (mean 0.149), velocities up to 0.01
+        with torch.cuda.stream(stream):
+            g = torch.Generator(device="cuda").manual_seed(7)
+            n_cell = torch.poisson(torch.full((C,), 1.0e7 / C, device="cuda"), generator=g).to(torch.int32)
+            vdt = torch.float64 if prec == "fp64" else torch.float32
+            vs = ((torch.rand(3 * C, device="cuda", generator=g) - 0.5) * 0.02).to(vdt)
+            force = torch.empty_like(vs)
+        stream.synchronize()
+
     def step(n):
         nonlocal a, b
         for _ in range(n):
-            L.check(L.lbdps3_bgk_step(a.data_ptr(), b.data_ptr(), nx, ny, nz, 0.6, code, stream.cuda_stream),
-                    "lbdps3_bgk_step")
+            if psm:
+                L.check(L.lbdps3_psm_step(a.data_ptr(), b.data_ptr(), n_cell.data_ptr(), vs.data_ptr(),
+                                          force.data_ptr(), nx, ny, nz, 0.6, 0.5, code, stream.cuda_stream),
+                        "lbdps3_psm_step")
+            else:
+                L.check(L.lbdps3_bgk_step(a.data_ptr(), b.data_ptr(), nx, ny, nz, 0.6, code, stream.cuda_stream),
+                        "lbdps3_bgk_step")
             a, b = b, a
 
     step(args.warmup)
@@ -300,19 +319,22 @@ def run_d3q19(args, torch, L):
     e1.synchronize()
     ms = e0.elapsed_time(e1)
     us = ms / args.steps * 1e3
-    nbytes = 2 * 19 * SIZES[prec][0] * C
+    # populations in and out; with solids also the count, v_s in and F out
+    nbytes = (2 * 19 * SIZES[prec][0] + (4 + 6 * sT if psm else 0)) * C
+    kern = "k3_psm" if psm else "k3_bgk"
     achieved = nbytes / (us * 1e-6) / 1e9
     cb = copy_bandwidth(torch, 1 << 30)
     return {"metric": METRIC, "value": round(C * args.steps / (ms / 1e3) / 1e6, 2), "unit": "MLUPS", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)", "bf16": "f32 (bf16 storage)"}[prec],
-            "data": "synthetic (gas at rest, periodic box)",
-            "config": {"workload": f"d3q19-gas-{nx}x{ny}x{nz}-{prec}", "nx": nx, "ny": ny, "nz": nz,
-                       "precision": prec, "tau": 0.6, "particles": 0},
-            "roofline": {"bound": "hbm", "kernel": "k3_bgk", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "data": "synthetic (gas at rest, periodic box" + (", seeded Poisson solids per cell)" if psm else ")"),
+            "config": {"workload": f"d3q19-{'psm' if psm else 'gas'}-{nx}x{ny}x{nz}-{prec}", "nx": nx, "ny": ny,
+                       "nz": nz, "precision": prec, "tau": 0.6, "particles": int(1e7) if psm else 0,
+                       **({"d_p": 0.5} if psm else {})},
+            "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic("d3q19_gas", "k3_bgk") if prec == "fp16" else None,
+                         "traffic": measured_traffic(args.workload, kern) if prec == "fp16" else None,
                          "bytes_per_launch": int(nbytes), "us_per_launch": round(us, 3), "copy_GBs": cb["GBs"],
                          "frac_of_copy": round(achieved / cb["GBs"], 4)}}
 
@@ -458,7 +480,7 @@ def main():
         return
     from paper_1303_2653_amd import lbdps as L
 
-    if args.workload == "d3q19_gas":
+    if args.workload in ("d3q19_gas", "d3q19_psm"):
         print(json.dumps(run_d3q19(args, torch, L)), flush=True)
         return
     if args.workload == "beds":

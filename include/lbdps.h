@@ -247,6 +247,31 @@ lbdps_status lbdps_voidage(lbdps_ctx *ctx, int32_t y0, int32_t y1, double thresh
 lbdps_status lbdps3_bgk_step(const void *d_fin, void *d_fout, int32_t nx, int32_t ny, int32_t nz, double tau,
                              int32_t precision, void *stream);
 
+/*
+ * The 3-D lattice with solids in its cells, second piece of the 3-D
+ * extension: one collide-stream step of the D3Q19 lattice above on a
+ * periodic box with the partially saturated collision of Eqs. 6-7, its
+ * weighting gamma of Eq. 9 and the solids' force of Eq. 25, with the solids
+ * given per cell (the deposition of Eq. 8 done by the caller):
+ *   eps_s = min(n pi d^3 / 6, pi / (3 sqrt 2))   (h = 1; the densest sphere
+ *           packing bounds it as the densest disc packing bounds Eq. 10)
+ *   Om_i  = f_opp(i) - f_i + f^eq_i(rho, v_s) - f^eq_opp(i)(rho, u)
+ *   f*_i  = f_i - (1 - gamma) / tau (f_i - f^eq_i(rho, u)) + gamma Om_i
+ *   F     = gamma sum_i c_i Om_i, then push streaming with periodic wrap.
+ *   d_fin, d_fout: as for lbdps3_bgk_step.
+ *   d_n:     device [nz][ny][nx] int32, spheres per cell (>= 0).
+ *   d_vs:    device [3][nz][ny][nx], their mean velocity (x plane, y plane,
+ *            z plane), FP64 for LBDPS_FP64, else FP32.
+ *   d_force: device [3][nz][ny][nx], same type, receives F (=).
+ *   tau > 0.5, d > 0 (sphere diameter in lattice units).  The caller owns
+ *   every buffer.  Asynchronous (stream order).
+ * LBDPS_E_INVALID for NULL or equal buffers, a bad tau, d or precision;
+ * LBDPS_E_SHAPE for a dimension below 1.
+ */
+lbdps_status lbdps3_psm_step(const void *d_fin, void *d_fout, const int32_t *d_n, const void *d_vs, void *d_force,
+                             int32_t nx, int32_t ny, int32_t nz, double tau, double d, int32_t precision,
+                             void *stream);
+
 /* Kernels of one step, for per-kernel timing. */
 typedef enum {
   LBDPS_K_COLLIDE = 0,    /* deposition + collision + streaming                     */

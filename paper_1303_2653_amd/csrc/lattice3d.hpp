@@ -197,4 +197,107 @@ __global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S 
   }
 }
 
+__device__ __forceinline__ constexpr int opp3(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// One partially saturated step of the 3-D lattice (the collision of Eqs. 6-7
+// with the weighting of Eq. 9 and the force of Eq. 25, on D3Q19): cell c
+// holds n[c] spheres of volume vol moving with vs[.][c]; its solid fraction
+// is n vol, at most cap; the momentum the solids give the gas goes to
+// force[.][c].  FP64 follows the oracle's operation order (bit for bit); the
+// reduced storages work on deviations, where Eq. 7's term reads
+// g_opp - g_i + g^eq_i(v_s) - g^eq_opp(u) because w_i = w_opp.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k3_psm(const typename Prec<P>::S *__restrict__ fin,
+                                                typename Prec<P>::S *__restrict__ fout,
+                                                const int32_t *__restrict__ n,
+                                                const typename Prec<P>::T *__restrict__ vs,
+                                                typename Prec<P>::T *__restrict__ force, int nx, int ny, int nz,
+                                                typename Prec<P>::T tau, typename Prec<P>::T vol,
+                                                typename Prec<P>::T cap) {
+  using T = typename Prec<P>::T;
+  const long long C = (long long)nx * ny * nz;
+  const long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= C) return;
+  const int x = (int)(c % nx);
+  const long long yz = c / nx;
+  const int y = (int)(yz % ny), z = (int)(yz / ny);
+  T f[Q3];
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) f[i] = load_v<P>(fin, (size_t)i * C + c);
+  T es = (T)n[c] * vol;
+  if (es > cap) es = cap;
+  const T half = (T)0.5;
+  const T gam = dv<P>(es * (tau - half), ((T)1 - es) + (tau - half));
+  const T vx = vs[c], vy = vs[C + c], vz = vs[2 * C + c];
+  T out[Q3];
+  T fx = (T)0, fy = (T)0, fz = (T)0;
+  if constexpr (P == PREC_FP64) {
+    T rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      rho += f[i];
+      jx += (T)c3(i, 0) * f[i];
+      jy += (T)c3(i, 1) * f[i];
+      jz += (T)c3(i, 2) * f[i];
+    }
+    const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T vv = vx * vx + vy * vy + vz * vz;
+    auto feq = [&](int i, T ax, T ay, T az, T aa) {
+      const T cu = (T)c3(i, 0) * ax + (T)c3(i, 1) * ay + (T)c3(i, 2) * az;
+      return w3<T>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * aa);
+    };
+    const T relax = (1.0 - gam) / tau;
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      const int o = opp3(i);
+      const T om = f[o] - f[i] + feq(i, vx, vy, vz, vv) - feq(o, ux, uy, uz, uu);
+      out[i] = f[i] - relax * (f[i] - feq(i, ux, uy, uz, uu)) + gam * om;
+      fx += (T)c3(i, 0) * om;
+      fy += (T)c3(i, 1) * om;
+      fz += (T)c3(i, 2) * om;
+    }
+  } else {
+    T r1 = (T)0, jx = (T)0, jy = (T)0, jz = (T)0;
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      r1 += f[i];
+      jx += (T)c3(i, 0) * f[i];
+      jy += (T)c3(i, 1) * f[i];
+      jz += (T)c3(i, 2) * f[i];
+    }
+    const T rho = (T)1 + r1;
+    const T ir = dv<P>((T)1, rho);
+    const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T vv = vx * vx + vy * vy + vz * vz;
+    auto geq = [&](int i, T ax, T ay, T az, T aa) {
+      const T cu = (T)c3(i, 0) * ax + (T)c3(i, 1) * ay + (T)c3(i, 2) * az;
+      return w3<T>(i) * (r1 + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * aa));
+    };
+    const T relax = dv<P>((T)1 - gam, tau);
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      const int o = opp3(i);
+      const T om = f[o] - f[i] + geq(i, vx, vy, vz, vv) - geq(o, ux, uy, uz, uu);
+      out[i] = f[i] - relax * (f[i] - geq(i, ux, uy, uz, uu)) + gam * om;
+      fx += (T)c3(i, 0) * om;
+      fy += (T)c3(i, 1) * om;
+      fz += (T)c3(i, 2) * om;
+    }
+  }
+  force[c] = gam * fx;
+  force[C + c] = gam * fy;
+  force[2 * C + c] = gam * fz;
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) {
+    int tx = x + c3(i, 0), ty = y + c3(i, 1), tz = z + c3(i, 2);
+    tx = tx < 0 ? tx + nx : (tx >= nx ? tx - nx : tx);
+    ty = ty < 0 ? ty + ny : (ty >= ny ? ty - ny : ty);
+    tz = tz < 0 ? tz + nz : (tz >= nz ? tz - nz : tz);
+    store_v<P>(fout, (size_t)i * C + ((long long)tz * ny + ty) * nx + tx, out[i]);
+  }
+}
+
+
 }  // namespace lbdps

@@ -822,6 +822,44 @@ lbdps_status lbdps3_bgk_step(const void *d_fin, void *d_fout, int32_t nx, int32_
   return launch_status("lbdps3_bgk_step");
 }
 
+lbdps_status lbdps3_psm_step(const void *d_fin, void *d_fout, const int32_t *d_n, const void *d_vs, void *d_force,
+                             int32_t nx, int32_t ny, int32_t nz, double tau, double d, int32_t precision,
+                             void *stream) {
+  if (!d_fin || !d_fout || d_fin == d_fout) return fail(LBDPS_E_INVALID, "d_fin and d_fout must be distinct buffers");
+  if (!d_n || !d_vs || !d_force) return fail(LBDPS_E_INVALID, "d_n, d_vs and d_force must be device buffers");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(LBDPS_E_SHAPE, "nx, ny and nz must be >= 1");
+  if (!(std::isfinite(tau) && tau > 0.5)) return fail(LBDPS_E_INVALID, "tau must be > 0.5");
+  if (!(std::isfinite(d) && d > 0.0)) return fail(LBDPS_E_INVALID, "d must be > 0");
+  const long long C = (long long)nx * ny * nz;
+  const unsigned grid = (unsigned)((C + BLOCK - 1) / BLOCK);
+  const double vol = M_PI * d * d * d / 6.0;          // sphere volume in cells
+  const double cap = M_PI / (3.0 * std::sqrt(2.0));  // densest sphere packing
+  const hipStream_t st = (hipStream_t)stream;
+  switch (precision) {
+    case PREC_FP64:
+      hipLaunchKernelGGL(k3_psm<PREC_FP64>, dim3(grid), dim3(BLOCK), 0, st, (const double *)d_fin, (double *)d_fout,
+                         d_n, (const double *)d_vs, (double *)d_force, nx, ny, nz, tau, vol, cap);
+      break;
+    case PREC_FP32:
+      hipLaunchKernelGGL(k3_psm<PREC_FP32>, dim3(grid), dim3(BLOCK), 0, st, (const float *)d_fin, (float *)d_fout, d_n,
+                         (const float *)d_vs, (float *)d_force, nx, ny, nz, (float)tau, (float)vol, (float)cap);
+      break;
+    case PREC_FP16DEV:
+      hipLaunchKernelGGL(k3_psm<PREC_FP16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const _Float16 *)d_fin,
+                         (_Float16 *)d_fout, d_n, (const float *)d_vs, (float *)d_force, nx, ny, nz, (float)tau,
+                         (float)vol, (float)cap);
+      break;
+    case PREC_BF16DEV:
+      hipLaunchKernelGGL(k3_psm<PREC_BF16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const uint16_t *)d_fin,
+                         (uint16_t *)d_fout, d_n, (const float *)d_vs, (float *)d_force, nx, ny, nz, (float)tau,
+                         (float)vol, (float)cap);
+      break;
+    default:
+      return fail(LBDPS_E_INVALID, "precision must be 0..3");
+  }
+  return launch_status("lbdps3_psm_step");
+}
+
 lbdps_status lbdps_set_inlet(lbdps_ctx *x, const double *h_inlet_uy) {
   if (!x || !h_inlet_uy) return fail(LBDPS_E_INVALID, "ctx or inlet profile is NULL");
   for (int i = 0; i < x->nx; ++i)

@@ -66,6 +66,7 @@ _SIGS = {
     "lbdps_collide_particles": (c_i32, [c_vp]),
     "lbdps_set_inlet": (c_i32, [c_vp, c_vp]),
     "lbdps3_bgk_step": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_dbl, c_i32, c_vp]),
+    "lbdps3_psm_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_dbl, c_dbl, c_i32, c_vp]),
     "lbdps_voidage": (c_i32, [c_vp, c_i32, c_i32, c_dbl, c_vp, c_vp, c_vp]),
     "lbdps_get_fields": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lbdps_get_particles": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),

@@ -105,3 +105,64 @@ def test_d3q19_pairs_match_single_cells(prec, nx):
         outs.append(res[off:off + 19 * C].view(torch.int16).cpu().numpy())
     bad = np.flatnonzero(outs[0] != outs[1])
     assert bad.size == 0, f"{bad.size} values differ, first at plane {bad[0] // C} cell {bad[0] % C}"
+
+
+# (f tolerance against max(|f|, 1), force tolerance against max |F|)
+PSM_TOL = {"fp64": (0.0, 0.0), "fp32": (1e-6, 1e-4), "fp16": (3e-5, 2e-2), "bf16": (3e-4, 1e-1)}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("nx", [12, 13])
+def test_d3q19_psm_steps_match_oracle(prec, nx):
+    """Partially saturated cells (Eqs. 6-7, 9, 25 on D3Q19) through the C ABI
+    against the oracle, 4 steps with fixed solids: 0-3 spheres per cell, one
+    cell far beyond the densest packing, velocities up to 0.03. FP64 bit for
+    bit, populations and force; the other storages within their rounding."""
+    ny, nz, steps, tau, d = 10, 9, 4, 0.7, 0.9
+    C = nx * ny * nz
+    rng = np.random.default_rng(nx)
+    n = rng.integers(0, 4, (nz, ny, nx)).astype(np.int32)
+    n[1, 2, 3] = 50
+    vs = (rng.random((3, nz, ny, nx)) - 0.5) * 0.06
+    f0 = state(nx, ny, nz)
+    a = to_storage(f0, prec)
+    ref = from_storage(a, prec)
+    b = torch.empty_like(a)
+    code, dt = DT[prec]
+    vdt = torch.float64 if prec == "fp64" else torch.float32
+    dn = torch.tensor(n, device="cuda")
+    dvs = torch.tensor(vs, dtype=vdt, device="cuda")
+    vs_ref = dvs.to(torch.float64).cpu().numpy()  # the oracle sees the velocities the kernel reads
+    dF = torch.full((3, C), float("nan"), dtype=vdt, device="cuda")
+    for _ in range(steps):
+        L.check(L.lbdps3_psm_step(a.data_ptr(), b.data_ptr(), dn.data_ptr(), dvs.data_ptr(), dF.data_ptr(),
+                                  nx, ny, nz, tau, d, code, None), "lbdps3_psm_step")
+        a, b = b, a
+        ref, F_ref = oracle.psm3_step(ref, tau, d, n, vs_ref)
+    torch.cuda.synchronize()
+    got = from_storage(a, prec)
+    F = dF.to(torch.float64).cpu().numpy().reshape(3, nz, ny, nx)
+    err = float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1.0))
+    ferr = float(np.abs(F - F_ref).max() / np.abs(F_ref).max())
+    print(prec, nx, "PSM after", steps, "steps: f error", err, "force error", ferr, flush=True)
+    tol, ftol = PSM_TOL[prec]
+    assert np.isfinite(F).all()
+    assert err <= tol and ferr <= ftol
+
+
+def test_d3q19_psm_rejects_bad_arguments():
+    a = torch.zeros(19 * 8, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    n = torch.zeros(8, dtype=torch.int32, device="cuda")
+    v = torch.zeros(24, dtype=torch.float32, device="cuda")
+    F = torch.zeros_like(v)
+    ok = (a.data_ptr(), b.data_ptr(), n.data_ptr(), v.data_ptr(), F.data_ptr(), 2, 2, 2, 0.7, 0.5, L.LBDPS_FP32, None)
+    assert L.lbdps3_psm_step(*ok) == L.LBDPS_OK
+    torch.cuda.synchronize()
+    bad = [(1, a.data_ptr(), L.LBDPS_E_INVALID), (2, 0, L.LBDPS_E_INVALID), (4, 0, L.LBDPS_E_INVALID),
+           (5, 0, L.LBDPS_E_SHAPE), (8, 0.5, L.LBDPS_E_INVALID), (9, 0.0, L.LBDPS_E_INVALID),
+           (9, float("nan"), L.LBDPS_E_INVALID), (10, 7, L.LBDPS_E_INVALID)]
+    for k, val, want in bad:
+        args = list(ok)
+        args[k] = val
+        assert L.lbdps3_psm_step(*args) == want, (k, val)
