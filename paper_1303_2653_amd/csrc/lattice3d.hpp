@@ -103,10 +103,17 @@ __global__ __launch_bounds__(BLOCK) void k3_bgk(const typename Prec<P>::S *__res
 // the word of its own pair from one of its values and one of the adjacent
 // lane's, so nearly every store is a full 4-byte word as well.  The
 // arithmetic per cell is that of k3_bgk.
-template <int P>
+__device__ __forceinline__ constexpr int opp3(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// With PSM the pair also carries its solids (count, v_s in; F out, as in
+// k3_psm) through 8-byte loads and stores, and collides as k3_psm does.
+template <int P, bool PSM = false>
 __global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S *__restrict__ fin,
                                                       typename Prec<P>::S *__restrict__ fout, int nx, int ny, int nz,
-                                                      float tau) {
+                                                      float tau, const int32_t *__restrict__ n = nullptr,
+                                                      const float *__restrict__ vs = nullptr,
+                                                      float *__restrict__ force = nullptr, float vol = 0.f,
+                                                      float cap = 0.f) {
   static_assert(sizeof(typename Prec<P>::S) == 2, "16-bit storage");
   using S = typename Prec<P>::S;
   const long long C = (long long)nx * ny * nz;
@@ -127,7 +134,24 @@ __global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S 
     f1[i] = load_v<P>(&v.b, 0);
   }
   const float omg = dv<P>(1.0f, tau);
-  auto relax = [&](float *f) {
+  float gm[2] = {0.f, 0.f}, v[2][3] = {}, F[2][3] = {};
+  if constexpr (PSM) {
+    const int2 nn = *reinterpret_cast<const int2 *>(n + c);
+    const int cnt[2] = {nn.x, nn.y};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      float es = (float)cnt[k] * vol;
+      if (es > cap) es = cap;
+      gm[k] = dv<P>(es * (tau - 0.5f), (1.f - es) + (tau - 0.5f));
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float2 t = *reinterpret_cast<const float2 *>(vs + (size_t)a * C + c);
+      v[0][a] = t.x;
+      v[1][a] = t.y;
+    }
+  }
+  auto relax = [&](float *f, int k) {
     float r1 = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
@@ -140,15 +164,44 @@ __global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S 
     const float ir = dv<P>(1.0f, rho);
     const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
     const float uu = ux * ux + uy * uy + uz * uz;
+    if constexpr (PSM) {
+      const float vx = v[k][0], vy = v[k][1], vz = v[k][2], gam = gm[k];
+      const float vv = vx * vx + vy * vy + vz * vz;
+      auto geq = [&](int i, float ax, float ay, float az, float aa) {
+        const float cu = (float)c3(i, 0) * ax + (float)c3(i, 1) * ay + (float)c3(i, 2) * az;
+        return w3<float>(i) * (r1 + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * aa));
+      };
+      const float relax_ = dv<P>(1.f - gam, tau);
+      float g[Q3], fx = 0.f, fy = 0.f, fz = 0.f;
 #pragma unroll
-    for (int i = 0; i < Q3; ++i) {
-      const float cu = (float)c3(i, 0) * ux + (float)c3(i, 1) * uy + (float)c3(i, 2) * uz;
-      const float geq = w3<float>(i) * (r1 + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-      f[i] = f[i] - (f[i] - geq) * omg;
+      for (int i = 0; i < Q3; ++i) {
+        const int o = opp3(i);
+        const float om = f[o] - f[i] + geq(i, vx, vy, vz, vv) - geq(o, ux, uy, uz, uu);
+        g[i] = f[i] - relax_ * (f[i] - geq(i, ux, uy, uz, uu)) + gam * om;
+        fx += (float)c3(i, 0) * om;
+        fy += (float)c3(i, 1) * om;
+        fz += (float)c3(i, 2) * om;
+      }
+#pragma unroll
+      for (int i = 0; i < Q3; ++i) f[i] = g[i];
+      F[k][0] = gam * fx;
+      F[k][1] = gam * fy;
+      F[k][2] = gam * fz;
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q3; ++i) {
+        const float cu = (float)c3(i, 0) * ux + (float)c3(i, 1) * uy + (float)c3(i, 2) * uz;
+        const float geq = w3<float>(i) * (r1 + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+        f[i] = f[i] - (f[i] - geq) * omg;
+      }
     }
   };
-  relax(f0);
-  relax(f1);
+  relax(f0, 0);
+  relax(f1, 1);
+  if constexpr (PSM) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) *reinterpret_cast<float2 *>(force + (size_t)a * C + c) = make_float2(F[0][a], F[1][a]);
+  }
 #pragma unroll
   for (int i = 0; i < Q3; ++i) {
     int ty = y + c3(i, 1), tz = z + c3(i, 2);
@@ -196,8 +249,6 @@ __global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S 
     }
   }
 }
-
-__device__ __forceinline__ constexpr int opp3(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
 // One partially saturated step of the 3-D lattice (the collision of Eqs. 6-7
 // with the weighting of Eq. 9 and the force of Eq. 25, on D3Q19): cell c

@@ -834,6 +834,11 @@ lbdps_status lbdps3_psm_step(const void *d_fin, void *d_fout, const int32_t *d_n
   const unsigned grid = (unsigned)((C + BLOCK - 1) / BLOCK);
   const double vol = M_PI * d * d * d / 6.0;          // sphere volume in cells
   const double cap = M_PI / (3.0 * std::sqrt(2.0));  // densest sphere packing
+  // 16-bit storage, even rows, 4-byte aligned populations and 8-byte aligned
+  // solids: two cells per thread
+  const bool pairs = nx % 2 == 0 && ((uintptr_t)d_fin & 3) == 0 && ((uintptr_t)d_fout & 3) == 0 &&
+                     ((uintptr_t)d_n & 7) == 0 && ((uintptr_t)d_vs & 7) == 0 && ((uintptr_t)d_force & 7) == 0;
+  const unsigned grid2 = (unsigned)((C / 2 + BLOCK - 1) / BLOCK);
   const hipStream_t st = (hipStream_t)stream;
   switch (precision) {
     case PREC_FP64:
@@ -845,14 +850,24 @@ lbdps_status lbdps3_psm_step(const void *d_fin, void *d_fout, const int32_t *d_n
                          (const float *)d_vs, (float *)d_force, nx, ny, nz, (float)tau, (float)vol, (float)cap);
       break;
     case PREC_FP16DEV:
-      hipLaunchKernelGGL(k3_psm<PREC_FP16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const _Float16 *)d_fin,
-                         (_Float16 *)d_fout, d_n, (const float *)d_vs, (float *)d_force, nx, ny, nz, (float)tau,
-                         (float)vol, (float)cap);
+      if (pairs)
+        hipLaunchKernelGGL((k3_bgk_pairs<PREC_FP16DEV, true>), dim3(grid2), dim3(BLOCK), 0, st, (const _Float16 *)d_fin,
+                           (_Float16 *)d_fout, nx, ny, nz, (float)tau, d_n, (const float *)d_vs, (float *)d_force,
+                           (float)vol, (float)cap);
+      else
+        hipLaunchKernelGGL(k3_psm<PREC_FP16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const _Float16 *)d_fin,
+                           (_Float16 *)d_fout, d_n, (const float *)d_vs, (float *)d_force, nx, ny, nz, (float)tau,
+                           (float)vol, (float)cap);
       break;
     case PREC_BF16DEV:
-      hipLaunchKernelGGL(k3_psm<PREC_BF16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const uint16_t *)d_fin,
-                         (uint16_t *)d_fout, d_n, (const float *)d_vs, (float *)d_force, nx, ny, nz, (float)tau,
-                         (float)vol, (float)cap);
+      if (pairs)
+        hipLaunchKernelGGL((k3_bgk_pairs<PREC_BF16DEV, true>), dim3(grid2), dim3(BLOCK), 0, st, (const uint16_t *)d_fin,
+                           (uint16_t *)d_fout, nx, ny, nz, (float)tau, d_n, (const float *)d_vs, (float *)d_force,
+                           (float)vol, (float)cap);
+      else
+        hipLaunchKernelGGL(k3_psm<PREC_BF16DEV>, dim3(grid), dim3(BLOCK), 0, st, (const uint16_t *)d_fin,
+                           (uint16_t *)d_fout, d_n, (const float *)d_vs, (float *)d_force, nx, ny, nz, (float)tau,
+                           (float)vol, (float)cap);
       break;
     default:
       return fail(LBDPS_E_INVALID, "precision must be 0..3");

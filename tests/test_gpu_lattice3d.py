@@ -166,3 +166,36 @@ def test_d3q19_psm_rejects_bad_arguments():
         args = list(ok)
         args[k] = val
         assert L.lbdps3_psm_step(*args) == want, (k, val)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("nx", [2, 130, 160])
+def test_d3q19_psm_pairs_match_single_cells(prec, nx):
+    """As test_d3q19_pairs_match_single_cells, with solids in the cells: the
+    paired form (populations, counts, v_s and F two cells at a time) against
+    the one-cell form, populations and force bit for bit."""
+    ny, nz, steps, tau, d = 5, 3, 3, 0.8, 0.9
+    code, dt = DT[prec]
+    C = nx * ny * nz
+    rng = np.random.default_rng(nx + 1)
+    g = torch.tensor((rng.random(19 * C) - 0.5) * 2e-2, dtype=torch.float64).to(dt).cuda()
+    n = torch.tensor(rng.integers(0, 5, C).astype(np.int32), device="cuda")
+    vs = torch.tensor((rng.random(3 * C) - 0.5) * 0.06, dtype=torch.float32, device="cuda")
+    outs, forces = [], []
+    for off in (0, 1):
+        a = torch.zeros(19 * C + 2, dtype=dt, device="cuda")
+        b = torch.zeros_like(a)
+        a[off:off + 19 * C] = g
+        F = torch.full((3 * C,), float("nan"), dtype=torch.float32, device="cuda")
+        pa, pb = a[off:].data_ptr(), b[off:].data_ptr()
+        for _ in range(steps):
+            L.check(L.lbdps3_psm_step(pa, pb, n.data_ptr(), vs.data_ptr(), F.data_ptr(), nx, ny, nz, tau, d, code,
+                                      None), "lbdps3_psm_step")
+            pa, pb = pb, pa
+        torch.cuda.synchronize()
+        res = a if steps % 2 == 0 else b
+        outs.append(res[off:off + 19 * C].view(torch.int16).cpu().numpy())
+        forces.append(F.view(torch.int32).cpu().numpy())
+    bad = np.flatnonzero(outs[0] != outs[1])
+    assert bad.size == 0, f"{bad.size} values differ, first at plane {bad[0] // C} cell {bad[0] % C}"
+    assert np.array_equal(forces[0], forces[1])
