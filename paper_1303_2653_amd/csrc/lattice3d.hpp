@@ -107,13 +107,11 @@ __device__ __forceinline__ constexpr int opp3(int i) { return i == 0 ? 0 : ((i &
 
 // With PSM the pair also carries its solids (count, v_s in; F out, as in
 // k3_psm) through 8-byte loads and stores, and collides as k3_psm does.
-template <int P, bool PSM = false>
-__global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S *__restrict__ fin,
-                                                      typename Prec<P>::S *__restrict__ fout, int nx, int ny, int nz,
-                                                      float tau, const int32_t *__restrict__ n = nullptr,
-                                                      const float *__restrict__ vs = nullptr,
-                                                      float *__restrict__ force = nullptr, float vol = 0.f,
-                                                      float cap = 0.f) {
+template <int P, bool PSM>
+__device__ __forceinline__ void pairs_step(const typename Prec<P>::S *__restrict__ fin,
+                                           typename Prec<P>::S *__restrict__ fout, int nx, int ny, int nz, float tau,
+                                           const int32_t *__restrict__ n, const float *__restrict__ vs,
+                                           float *__restrict__ force, float vol, float cap) {
   static_assert(sizeof(typename Prec<P>::S) == 2, "16-bit storage");
   using S = typename Prec<P>::S;
   const long long C = (long long)nx * ny * nz;
@@ -248,6 +246,22 @@ __global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S 
       }
     }
   }
+}
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k3_bgk_pairs(const typename Prec<P>::S *__restrict__ fin,
+                                                      typename Prec<P>::S *__restrict__ fout, int nx, int ny, int nz,
+                                                      float tau) {
+  pairs_step<P, false>(fin, fout, nx, ny, nz, tau, nullptr, nullptr, nullptr, 0.f, 0.f);
+}
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k3_psm_pairs(const typename Prec<P>::S *__restrict__ fin,
+                                                      typename Prec<P>::S *__restrict__ fout, int nx, int ny, int nz,
+                                                      float tau, const int32_t *__restrict__ n,
+                                                      const float *__restrict__ vs, float *__restrict__ force,
+                                                      float vol, float cap) {
+  pairs_step<P, true>(fin, fout, nx, ny, nz, tau, n, vs, force, vol, cap);
 }
 
 // One partially saturated step of the 3-D lattice (the collision of Eqs. 6-7

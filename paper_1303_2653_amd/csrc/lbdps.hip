@@ -851,7 +851,7 @@ lbdps_status lbdps3_psm_step(const void *d_fin, void *d_fout, const int32_t *d_n
       break;
     case PREC_FP16DEV:
       if (pairs)
-        hipLaunchKernelGGL((k3_bgk_pairs<PREC_FP16DEV, true>), dim3(grid2), dim3(BLOCK), 0, st, (const _Float16 *)d_fin,
+        hipLaunchKernelGGL(k3_psm_pairs<PREC_FP16DEV>, dim3(grid2), dim3(BLOCK), 0, st, (const _Float16 *)d_fin,
                            (_Float16 *)d_fout, nx, ny, nz, (float)tau, d_n, (const float *)d_vs, (float *)d_force,
                            (float)vol, (float)cap);
       else
@@ -861,7 +861,7 @@ lbdps_status lbdps3_psm_step(const void *d_fin, void *d_fout, const int32_t *d_n
       break;
     case PREC_BF16DEV:
       if (pairs)
-        hipLaunchKernelGGL((k3_bgk_pairs<PREC_BF16DEV, true>), dim3(grid2), dim3(BLOCK), 0, st, (const uint16_t *)d_fin,
+        hipLaunchKernelGGL(k3_psm_pairs<PREC_BF16DEV>, dim3(grid2), dim3(BLOCK), 0, st, (const uint16_t *)d_fin,
                            (uint16_t *)d_fout, nx, ny, nz, (float)tau, d_n, (const float *)d_vs, (float *)d_force,
                            (float)vol, (float)cap);
       else
