@@ -21,18 +21,23 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbdps_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# The same source built with -fopenmp: the per-cell loops run over all host
+# cores, bit-identical results (the all-cores CPU baseline of the benchmark).
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 PERIODIC, WALL, INLET, OUTLET = 0, 1, 2, 3
 BC_NAMES = {"periodic": PERIODIC, "wall": WALL, "inlet": INLET, "outlet": OUTLET}
 
 
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (FP64, -ffp-contract=off)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-               "-o", LIB + ".tmp", SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(LIB + ".tmp", LIB)
+    """Compile liboracle.so (single thread) and liboracle_omp.so (per-cell
+    loops over OpenMP threads) with gcc (FP64, -ffp-contract=off)."""
+    for out, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+            cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fPIC", "-shared", *extra,
+                   "-o", out + ".tmp", SRC, "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(out + ".tmp", out)
     return LIB
 
 
@@ -65,15 +70,16 @@ class OrcOut(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build()
-        L = ctypes.CDLL(LIB)
+def lib(omp: bool = False):
+    """The loaded oracle library; omp=True: the OpenMP build."""
+    path = LIB_OMP if omp else LIB
+    if path not in _libs:
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+            build(force=False)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER(OrcParams)
         vp = ctypes.c_void_p
         i64 = ctypes.c_int64
@@ -115,8 +121,8 @@ def lib():
         L.orc3_bgk_step.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, vp]
         L.orc3_psm_step.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                     vp, vp, vp, vp]
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _ptr(a):
@@ -371,8 +377,9 @@ class StepOut:
 class Sim:
     """Holds an oracle state (f, pos, vel) and advances it with orc_step."""
 
-    def __init__(self, cfg: dict, f=None, pos=None, vel=None):
+    def __init__(self, cfg: dict, f=None, pos=None, vel=None, omp: bool = False):
         self.cfg = cfg
+        self.omp = omp
         self.p = make_params(cfg)
         nx, ny = self.p.nx, self.p.ny
         self.inlet_uy = None
@@ -401,7 +408,7 @@ class Sim:
             for k, v in bufs.items():
                 setattr(o, k, v.ctypes.data)
             o.pair_cap = cap
-        rc = lib().orc_step(ctypes.byref(self.p), _ptr(self.inlet_uy), _ptr(self.f), n,
+        rc = lib(self.omp).orc_step(ctypes.byref(self.p), _ptr(self.inlet_uy), _ptr(self.f), n,
                             _ptr(self.pos), _ptr(self.vel), ctypes.byref(o))
         if rc != 0:
             raise RuntimeError(f"oracle step failed rc={rc}")
