@@ -3,16 +3,22 @@
 
 A step is one pass of the whole method over the bed: deposition, modified
 collision + streaming, drag + integration, binning, contact detection and
-collisions.  Default workload: the bubble-injection-shaped bed (256 x 1024
-D2Q9 lattice, 200 000 spheres, FP32), inputs resident in HBM before timing.
+collisions.  Default workload: the riser-shaped bed with the precision
+pattern (512 x 4096 D2Q9 lattice, 2 000 000 spheres of d = 0.5, y periodic,
+x walls, body-force-driven gas; FP32, with FP16 and BF16 deviation storage as
+variants), inputs resident in HBM before timing.
 
 Prints ONE JSON line:
   value             coupled MLUPS (lattice cells updated per second / 1e6)
   particle_updates  particles advanced per second
-  roofline          the dominant kernel: algorithmic bytes per launch over its
-                    mean launch time (hipEvents on the library's stream, timed
-                    region), against the 8 TB/s HBM3E peak
-  cpu_baseline      the FP64 oracle timed on the host on a bounded sample
+  roofline          the dominant kernel: the bytes the whole-step model gives
+                    its phase (model_kernel_bytes) per launch over its mean
+                    launch time (events its dispatch stamps, on the library's
+                    stream, timed region), against the 8 TB/s HBM3E peak; the
+                    bytes the kernel itself must move as built are beside it
+                    (impl_*)
+  cpu_baseline      the FP64 oracle timed on the host on a bounded sample, on
+                    all cores (per-cell loops over OpenMP threads) and on one
   variants          the same workload with FP16 / BF16 population storage
 
 --workload beds: the batching pattern, 64 independent beds of uneven size
@@ -39,6 +45,7 @@ WORKLOADS = {
     "bubble": lambda: __import__("synth").bubble(),
     "bubble_small": lambda: __import__("synth").bubble_small(),
     "riser": lambda: __import__("synth").riser(),
+    "riser_random_ids": lambda: __import__("synth").riser(sort_ids=False),
     "riser_crop": lambda: __import__("synth").riser_crop(),
     "riser_large": lambda: __import__("synth").riser_large(),
     "beds": lambda: __import__("synth").beds(64),
@@ -50,8 +57,36 @@ WORKLOADS = {
 SIZES = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4), "bf16": (2, 4)}  # (population, scalar) bytes
 
 
+def model_kernel_bytes(kernel: str, prec: str, C: int, N: int, pairs: int) -> float:
+    """The whole-step byte model (model_bytes_per_step) split over the phases
+    that the kernels carry.  Per cell: populations in and out (18 s_f), the
+    deposited solid velocity written and read (4 s_c), the six node fields
+    u_gas, beta, p, F_pg written by the collision and read by the drag
+    (12 s_c), the count n written once and read twice, the cell start written
+    and read.  Per particle: the state read and written by the integration
+    (8 s_p), the position read by the binning and by the contact search, the
+    velocity read by the deposition (2 s_p each), key and permutation (16 B).
+    Per contact pair: its two indices written and read (16 B), the two
+    positions and velocities read by the collision (8 s_p)."""
+    sf, st = SIZES[prec]
+    if kernel == "collide":   # deposition + collision + streaming
+        return C * (18 * sf + 10 * st + 4) + N * 2 * st
+    if kernel == "drag":      # interpolation, drag, integration
+        return C * (6 * st + 4) + N * 8 * st
+    if kernel == "scan":      # counts in, cell starts out
+        return C * 8
+    if kernel == "scatter":   # binning read of the position, key and permutation
+        return N * (2 * st + 16)
+    if kernel == "contacts":  # cell starts, positions, pairs written
+        return C * 4 + N * 2 * st + pairs * 8
+    if kernel == "resolve":   # pairs read, both particles' positions and velocities
+        return pairs * (8 + 8 * st)
+    raise KeyError(kernel)
+
+
 def algorithmic_bytes(kernel: str, prec: str, C: int, N: int, pairs: int) -> float:
-    """Bytes a launch of `kernel` must move at minimum (each operand once)."""
+    """Bytes a launch of `kernel` must move at minimum as built (each operand
+    it reads or writes once, including its own keys, degrees and counters)."""
     sf, st = SIZES[prec]
     if kernel == "collide":   # f read + write, cell starts, 6 node fields written, particle velocities read
         return C * (18 * sf + 4 + 6 * st) + N * 2 * st
@@ -94,11 +129,14 @@ def model_bytes_per_step(prec: str, C: int, N: int, pairs: int) -> float:
     return C * (18 * sf + 16 * st + 20) + N * (14 * st + 16) + pairs * (16 + 8 * st)
 
 
-def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None):
+def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None, tuning=None):
     sim = L.Sim(cfg, precision=prec)
     stream = sim.stream
     sim.step(warmup)
-    tuning = sim.autotune(4)  # launch shape of the cluster resolution (results do not depend on it)
+    if tuning is None:
+        tuning = sim.autotune(4)  # launch shape of the cluster resolution (results do not depend on it)
+    else:
+        sim.set_tuning(**tuning)
     torch.cuda.synchronize()
     # per-kernel breakdown (separate pass): find the dominant kernel
     sim.time_kernels(L.KERNELS)
@@ -219,20 +257,34 @@ def summarize(args):
 
 
 def cpu_baseline(cfg, seconds):
+    """The FP64 oracle stepping the bed from its initial state for about
+    `seconds` each: first the OpenMP build (per-cell loops on every host core,
+    bit-identical results), then the single-thread build."""
     import oracle
-    sim = oracle.Sim(cfg)
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        sim.step()
-        steps += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    C = cfg["nx"] * cfg["ny"]
-    return dict(value=round(C * steps / dt / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
-                sample=f"{cfg['name']}: first {steps} coupled steps from the initial state, FP64, single thread "
-                       f"({dt:.1f} s); particle updates/s {len(cfg['pos']) * steps / dt:.3e}")
+    C, N = cfg["nx"] * cfg["ny"], len(cfg["pos"])
+
+    def leg(omp):
+        sim = oracle.Sim(cfg, omp=omp)
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            sim.step()
+            steps += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        return steps, time.perf_counter() - t0
+
+    threads = oracle.threads(omp=True)
+    s_all, t_all = leg(True)
+    s_one, t_one = leg(False)
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return dict(value=round(C * s_all / t_all / 1e6, 4), unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"{cfg['name']}: first {s_all} coupled steps from the initial state, FP64, per-cell loops "
+                       f"on {threads} OpenMP threads ({t_all:.1f} s; host nproc {nproc}); particle updates/s "
+                       f"{N * s_all / t_all:.3e}",
+                single_thread=dict(value=round(C * s_one / t_one / 1e6, 4), unit="MLUPS", cores=1,
+                                   sample=f"first {s_one} coupled steps, FP64, one thread ({t_one:.1f} s); "
+                                          f"particle updates/s {N * s_one / t_one:.3e}"))
 
 
 def copy_bandwidth(torch, nbytes: int, reps: int = 5) -> dict:
@@ -395,8 +447,10 @@ def run_beds(args, torch, L):
         sm.close()
     s = ms_graph / 1e3
     dom_us = kt[0] / max(kt[1], 1) * 1e3
-    dom_bytes = sum(algorithmic_bytes(dom, prec, C, N, pr) for C, N, pr in zip(Cs, Ns, pairs))
+    dom_bytes = sum(model_kernel_bytes(dom, prec, C, N, pr) for C, N, pr in zip(Cs, Ns, pairs))
+    impl_bytes = sum(algorithmic_bytes(dom, prec, C, N, pr) for C, N, pr in zip(Cs, Ns, pairs))
     achieved = dom_bytes / (dom_us * 1e-6) / 1e9
+    impl_achieved = impl_bytes / (dom_us * 1e-6) / 1e9
     model = sum(model_bytes_per_step(prec, C, N, pr) for C, N, pr in zip(Cs, Ns, pairs))
     line = {
         "metric": METRIC, "value": round(sum(Cs) * K / s / 1e6, 2), "unit": "MLUPS", "n_gpus": 1, "steps": K,
@@ -413,7 +467,10 @@ def run_beds(args, torch, L):
         "kernel_us": {k: round(v, 2) for k, v in breakdown.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3)},
+                     "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3),
+                     "bytes_model": "model_kernel_bytes",
+                     "impl_bytes_per_launch": int(impl_bytes), "impl_achieved": round(impl_achieved, 1),
+                     "impl_frac": round(impl_achieved / HBM_PEAK_GBS, 4)},
         "autotune": sorted({(t["cluster_lists"], t["cluster_groups_max"]) for t in tunings}),
         "batched_eager_ms_per_step": round(ms_eager / K, 5),
         "graph_first_replay_ms_per_step": round(ms_first / K, 5),
@@ -443,11 +500,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="bubble", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="riser", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=sorted(SIZES))
     ap.add_argument("--n-sub", type=int, default=1, help="particle sub-steps per lattice step")
     ap.add_argument("--cs-smag", type=float, default=None, help="Smagorinsky constant (sub-grid model on)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="seconds of each oracle leg")
+    ap.add_argument("--tuning", default=None, metavar="LISTS,GROUPS",
+                    help="fixed cluster-resolution launch shape instead of the autotuner (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -492,21 +551,29 @@ def main():
     if args.cs_smag is not None:
         cfg["cs_smag"] = args.cs_smag
     C, N = cfg["nx"] * cfg["ny"], len(cfg["pos"])
-    r = run_gpu(cfg, args.precision, args.steps, args.warmup, torch, L)
+    fixed = None
+    if args.tuning:
+        lists, groups = (int(v) for v in args.tuning.split(","))
+        fixed = dict(cluster_lists=lists, cluster_groups_max=groups)
+    r = run_gpu(cfg, args.precision, args.steps, args.warmup, torch, L, tuning=fixed)
     s = r["ms"] / 1e3
     mlups = C * args.steps / s / 1e6
     pups = N * args.steps / s
     dom = r["dominant"]
     # the kernel's own duration per launch, from events its dispatch stamps
     dom_us = r["dom_ms"] / max(r["dom_launches"], 1) * 1e3
-    dom_bytes = algorithmic_bytes(dom, args.precision, C, N, r["pairs"])
+    dom_bytes = model_kernel_bytes(dom, args.precision, C, N, r["pairs"])
+    impl_bytes = algorithmic_bytes(dom, args.precision, C, N, r["pairs"])
     if args.n_sub > 1:  # the phase's time per step covers every sub-step's launch
+        sf, st = SIZES[args.precision]
         if dom == "drag":
-            sf, st = SIZES[args.precision]
-            dom_bytes += (args.n_sub - 1) * N * (2 * (4 + 4 * st) + 4 + 2 * st + 8)
+            dom_bytes += (args.n_sub - 1) * N * 8 * st
+            impl_bytes += (args.n_sub - 1) * N * (2 * (4 + 4 * st) + 4 + 2 * st + 8)
         elif dom != "collide":
             dom_bytes *= args.n_sub
+            impl_bytes *= args.n_sub
     achieved = dom_bytes / (dom_us * 1e-6) / 1e9
+    impl_achieved = impl_bytes / (dom_us * 1e-6) / 1e9
     model = model_bytes_per_step(args.precision, C, N, r["pairs"])
     traffic = None if args.n_sub > 1 or args.cs_smag is not None else measured_traffic(
         args.workload if args.precision == "fp32" else f"{args.workload}-{args.precision}", dom)
@@ -537,15 +604,20 @@ def main():
         "kernel_us": {k: round(v, 2) for k, v in r["breakdown_us"].items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3)},
+                     "bytes_per_launch": int(dom_bytes), "us_per_launch": round(dom_us, 3),
+                     "bytes_model": "model_kernel_bytes",
+                     "impl_bytes_per_launch": int(impl_bytes), "impl_achieved": round(impl_achieved, 1),
+                     "impl_frac": round(impl_achieved / HBM_PEAK_GBS, 4)},
     }
+    if fixed is not None:
+        line["tuning_fixed"] = True
     cb = copy_bandwidth(torch, 1 << 30)
     line["roofline"]["copy_GBs"] = cb["GBs"]
     line["roofline"]["frac_of_copy"] = round(achieved / cb["GBs"], 4)
     if not args.no_variants and args.precision == "fp32":
         var = {}
         for p in ("fp16", "bf16"):
-            rv = run_gpu(cfg, p, args.steps, args.warmup, torch, L, dominant=dom)
+            rv = run_gpu(cfg, p, args.steps, args.warmup, torch, L, dominant=dom, tuning=fixed)
             sv = rv["ms"] / 1e3
             var[p] = {"MLUPS": round(C * args.steps / sv / 1e6, 2), "ms_per_step": round(rv["ms"] / args.steps, 5),
                       "speedup_vs_fp32": round(r["ms"] / rv["ms"], 3),

@@ -31,6 +31,25 @@ def test_byte_models_scale_with_the_work():
         bench.algorithmic_bytes("nope", "fp32", C, N, P)
 
 
+def test_phase_split_sums_to_the_step_model():
+    """The per-phase bytes of the roofline figure add up to the whole-step
+    model: 18 s_f + 16 s_c + 20 per cell, 14 s_p + 16 per particle, 16 + 8 s_p
+    per pair."""
+    C, N, P = 2_097_152, 2_000_000, 747_730
+    for prec in ("fp64", "fp32", "fp16", "bf16"):
+        parts = sum(bench.model_kernel_bytes(k, prec, C, N, P)
+                    for k in ("collide", "drag", "scan", "scatter", "contacts", "resolve"))
+        assert parts == bench.model_bytes_per_step(prec, C, N, P)
+    assert bench.model_bytes_per_step("fp32", 1, 0, 0) == 156
+    assert bench.model_bytes_per_step("fp16", 1, 0, 0) == 120
+    assert bench.model_bytes_per_step("fp64", 1, 0, 0) == 292
+    assert bench.model_bytes_per_step("fp32", 0, 1, 0) == 72 and bench.model_bytes_per_step("fp32", 0, 0, 1) == 48
+    # the contact phase: cell starts, positions, pairs written
+    assert bench.model_kernel_bytes("contacts", "fp32", C, N, P) == 4 * C + 8 * N + 8 * P
+    with pytest.raises(KeyError):
+        bench.model_kernel_bytes("nope", "fp32", C, N, P)
+
+
 def test_workload_names_carry_the_precision_run():
     assert bench.workload_name("bubble-256x1024-200k-fp32", "fp16") == "bubble-256x1024-200k-fp16"
     assert bench.workload_name("riser-2048x8192-16000000-fp32", "fp32") == "riser-2048x8192-16000000-fp32"
