@@ -63,6 +63,7 @@ class OrcOut(ctypes.Structure):
         ("ncell", ctypes.c_void_p), ("vs", ctypes.c_void_p), ("rho", ctypes.c_void_p),
         ("ugas", ctypes.c_void_p), ("fpg", ctypes.c_void_p), ("beta", ctypes.c_void_p),
         ("fd", ctypes.c_void_p), ("fpre", ctypes.c_void_p), ("upart", ctypes.c_void_p),
+        ("acc", ctypes.c_void_p),
         ("pairs", ctypes.c_void_p),
         ("pair_cap", ctypes.c_int64), ("npairs", ctypes.c_int64),
         ("ncollisions", ctypes.c_int64), ("nwall", ctypes.c_int64),
@@ -83,6 +84,7 @@ def lib(omp: bool = False):
         P = ctypes.POINTER(OrcParams)
         vp = ctypes.c_void_p
         i64 = ctypes.c_int64
+        L.orc_threads.restype = ctypes.c_int32
         L.orc_feq.restype = ctypes.c_double
         L.orc_feq.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_gamma.restype = ctypes.c_double
@@ -109,6 +111,11 @@ def lib(omp: bool = False):
         L.orc_contacts_f32.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_float, i64, vp, vp, ctypes.c_int32, vp, i64,
                                        ctypes.POINTER(i64)]
+        L.orc_collide_f32.restype = ctypes.c_int
+        L.orc_collide_f32.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, i64,
+                                      vp, vp, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64)]
         L.orc_resolve.argtypes = [P, i64, vp, vp, vp, i64, ctypes.POINTER(i64)]
         L.orc_walls.argtypes = [P, i64, vp, vp, ctypes.POINTER(i64)]
         L.orc_step.restype = ctypes.c_int
@@ -123,6 +130,11 @@ def lib(omp: bool = False):
                                     vp, vp, vp, vp]
         _libs[path] = L
     return _libs[path]
+
+
+def threads(omp: bool = False) -> int:
+    """Threads the oracle's per-cell loops use (1 for the plain build)."""
+    return int(lib(omp).orc_threads())
 
 
 def _ptr(a):
@@ -268,6 +280,27 @@ def contacts_f32(nx, ny, per_x, per_y, d, cell, off, brute=False, cap=None):
     return pairs[: m.value].copy()
 
 
+def collide_f32(p: OrcParams, cell, off, vel, cap=None):
+    """The hard-sphere stage in single precision (orc_collide_f32): contacts,
+    binary collisions in lexicographic order, then walls, on the cell
+    [N][2] int32 + offset [N][2] float32 state with float32 velocities.
+    Returns (pairs, new velocities float32 [N][2], collisions, wall hits)."""
+    cell = np.ascontiguousarray(cell, np.int32)
+    off = np.ascontiguousarray(off, np.float32)
+    v = np.array(vel, np.float32, copy=True).reshape(-1, 2)
+    n = len(cell)
+    cap = cap if cap is not None else max(16, 32 * n)
+    pairs = np.zeros((cap, 2), np.int32)
+    m, nc, nw = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    per_x = int(p.bc[0] == PERIODIC)
+    per_y = int(p.bc[2] == PERIODIC or p.particles_periodic_y)
+    rc = lib().orc_collide_f32(p.nx, p.ny, per_x, per_y, p.d, p.rho_s, p.e_pp, p.e_pw, n, _ptr(cell), _ptr(off),
+                               _ptr(v), _ptr(pairs), cap, ctypes.byref(m), ctypes.byref(nc), ctypes.byref(nw))
+    if rc != 0:
+        raise RuntimeError(f"oracle collide_f32 failed rc={rc}")
+    return pairs[: m.value].copy(), v, nc.value, nw.value
+
+
 def resolve(p: OrcParams, pos, vel, pairs):
     pos = np.ascontiguousarray(pos, np.float64)
     vel = np.ascontiguousarray(vel, np.float64).copy()
@@ -368,6 +401,7 @@ class StepOut:
     fd: np.ndarray
     fpre: np.ndarray
     upart: np.ndarray
+    acc: np.ndarray
     pairs: np.ndarray
     ncollisions: int
     nwall: int
@@ -402,7 +436,7 @@ class Sim:
             bufs = dict(ncell=np.zeros(C, np.int32), vs=np.zeros((C, 2)), rho=np.zeros(C),
                         ugas=np.zeros((C, 2)), fpg=np.zeros((C, 2)), beta=np.zeros(C),
                         fd=np.zeros((max(n, 1), 2)), fpre=np.zeros((max(n, 1), 2)),
-                        upart=np.zeros((max(n, 1), 2)))
+                        upart=np.zeros((max(n, 1), 2)), acc=np.zeros((max(n, 1), 2)))
             cap = pair_cap if pair_cap is not None else max(16, 32 * n)
             bufs["pairs"] = np.zeros((cap, 2), np.int32)
             for k, v in bufs.items():
@@ -419,7 +453,7 @@ class Sim:
                        rho=bufs["rho"].reshape(ny, nx), ugas=bufs["ugas"].reshape(ny, nx, 2),
                        fpg=bufs["fpg"].reshape(ny, nx, 2), beta=bufs["beta"].reshape(ny, nx),
                        fd=bufs["fd"][:n].copy(), fpre=bufs["fpre"][:n].copy(),
-                       upart=bufs["upart"][:n].copy(), pairs=bufs["pairs"][: o.npairs].copy(),
+                       upart=bufs["upart"][:n].copy(), acc=bufs["acc"][:n].copy(), pairs=bufs["pairs"][: o.npairs].copy(),
                        ncollisions=o.ncollisions, nwall=o.nwall, nzero_den=o.nzero_den)
 
     def run(self, nsteps):

@@ -31,6 +31,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PERIODIC 0
 #define ORC_WALL 1
@@ -45,6 +48,15 @@ static const double PI = 3.14159265358979323846;
  * results are bit-identical to the plain build, which ignores the pragma.
  * Particle loops and every sum over particles stay sequential. */
 #define ORC_CELLS_PARALLEL _Pragma("omp parallel for schedule(static)")
+
+/* Threads the per-cell loops use: 1 in the plain build. */
+int32_t orc_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 #define ORC_OK 0
 #define ORC_E_DOMAIN (-1)
@@ -80,6 +92,7 @@ typedef struct {
   double *fd;     /* [N][2] corrected drag on each particle (Eq. 28) */
   double *fpre;   /* [N][2] pre-estimated drag (Eq. 26) */
   double *upart;  /* [N][2] gas velocity interpolated at the particle */
+  double *acc;    /* [N][2] acceleration of Eq. 16 (held over the sub-steps, R41) */
   int32_t *pairs; /* [cap][2] contact pairs after the move, lexicographic */
   int64_t pair_cap;
   int64_t npairs;      /* out */
@@ -735,6 +748,82 @@ void orc_walls(const orc_params *p, int64_t np, const double *pos, double *vel, 
 }
 
 /*
+ * The hard-sphere stage (Sec. 2.2) in single precision on a cell + offset
+ * state (R25, R27, R46): the contact pairs of orc_contacts_f32 (cell bins),
+ * then the binary collisions of Eqs. 17-18 over the pairs in lexicographic
+ * order with the current velocities (R24), then the particle-wall collisions
+ * (R23), every operation rounded to float in the order written:
+ *   dx  = (float)dcx + (off_i - off_j), dcx the minimum-image cell difference
+ *   dot = (v_ix - v_jx) dx + (v_iy - v_jy) dy;  the pair collides iff dot < 0
+ *   q   = ((1 + e) dot) / (dx dx + dy dy)
+ *   c   = (q m) / (m + m)       (m_j / (m_i + m_j) with one mass m)
+ *   v_i <- v_i - c (dx, dy),  v_j <- v_j + c (dx, dy)
+ * and, per particle in index order, on each non-periodic axis: in the first
+ * cell with offset <= r, or in the last with 1 - offset <= r (r = d/2), and
+ * moving into that wall, v_n <- -e_w v_n (face x- before x+).  1 + e, e_w,
+ * r, d and m = rho_s pi d^3 / 6 are formed in FP64 and rounded to float once.
+ * cell[N][2], off[N][2] (float, [0, 1)), vel[N][2] float in and out, index
+ * order.  pairs[cap][2] receives the contact pairs; the counts go to
+ * npairs, ncoll (pairs that collided) and nwall.
+ */
+int orc_collide_f32(int32_t nx, int32_t ny, int32_t per_x, int32_t per_y, double d, double rho_s, double e_pp,
+                    double e_pw, int64_t np, const int32_t *cell, const float *off, float *vel, int32_t *pairs,
+                    int64_t cap, int64_t *npairs, int64_t *ncoll, int64_t *nwall) {
+  const float one_e = (float)(1.0 + e_pp), ew = (float)e_pw, r = (float)(0.5 * d);
+  const float m = (float)(rho_s * (PI * d * d * d / 6.0));
+  int rc = orc_contacts_f32(nx, ny, per_x, per_y, (float)d, np, cell, off, 0, pairs, cap, npairs);
+  *ncoll = 0;
+  *nwall = 0;
+  if (rc != ORC_OK) return rc;
+  for (int64_t q = 0; q < *npairs; ++q) {
+    int64_t i = pairs[2 * q], j = pairs[2 * q + 1];
+    int dcx = cell[2 * i] - cell[2 * j], dcy = cell[2 * i + 1] - cell[2 * j + 1];
+    if (per_x) {
+      if (dcx > nx / 2)
+        dcx -= nx;
+      else if (dcx < -(nx / 2))
+        dcx += nx;
+    }
+    if (per_y) {
+      if (dcy > ny / 2)
+        dcy -= ny;
+      else if (dcy < -(ny / 2))
+        dcy += ny;
+    }
+    float ox = off[2 * i] - off[2 * j], oy = off[2 * i + 1] - off[2 * j + 1];
+    float dx = (float)dcx + ox, dy = (float)dcy + oy;
+    float dvx = vel[2 * i] - vel[2 * j], dvy = vel[2 * i + 1] - vel[2 * j + 1];
+    float dot = dvx * dx + dvy * dy;
+    if (!(dot < 0.0f)) continue;
+    float r2 = dx * dx + dy * dy;
+    float q0 = (one_e * dot) / r2;
+    float c = (q0 * m) / (m + m);
+    vel[2 * i] = vel[2 * i] - c * dx;
+    vel[2 * i + 1] = vel[2 * i + 1] - c * dy;
+    vel[2 * j] = vel[2 * j] + c * dx;
+    vel[2 * j + 1] = vel[2 * j + 1] + c * dy;
+    ++*ncoll;
+  }
+  for (int64_t k = 0; k < np; ++k) {
+    float *v = vel + 2 * k;
+    for (int a = 0; a < 2; ++a) {
+      if (a == 0 ? per_x : per_y) continue;
+      int c = cell[2 * k + a], n = a == 0 ? nx : ny;
+      float o = off[2 * k + a];
+      if (c == 0 && o <= r && v[a] < 0.0f) {
+        v[a] = -ew * v[a];
+        ++*nwall;
+      }
+      if (c == n - 1 && 1.0f - o <= r && v[a] > 0.0f) {
+        v[a] = -ew * v[a];
+        ++*nwall;
+      }
+    }
+  }
+  return ORC_OK;
+}
+
+/*
  * One coupled time step, the procedure of Sec. 2.4 (steps 2 to 6):
  *   2) per-cell particle count, mean solid velocity and porosities (Eqs. 8, 10, 11)
  *   3) collision (Eq. 23) with moments, F_p->g and beta (Eqs. 19-25), then streaming
@@ -895,7 +984,6 @@ int orc_step(const orc_params *p, const double *inlet_uy, double *f, int64_t np,
       orc_walls(p, np, pos, vel, &nwall);
     }
   }
-  free(acc);
 
   if (out) {
     if (out->ncell) memcpy(out->ncell, ncell, (size_t)C * sizeof(int32_t));
@@ -906,12 +994,14 @@ int orc_step(const orc_params *p, const double *inlet_uy, double *f, int64_t np,
     if (out->beta) memcpy(out->beta, beta, (size_t)C * sizeof(double));
     if (out->fd && np > 0) memcpy(out->fd, fd, NP * 2 * sizeof(double));
     if (out->fpre && np > 0) memcpy(out->fpre, fpre, NP * 2 * sizeof(double));
+    if (out->acc && np > 0) memcpy(out->acc, acc, NP * 2 * sizeof(double));
     out->npairs = npairs;
     out->ncollisions = ncoll;
     out->nwall = nwall;
     out->nzero_den = nzero;
   }
   if (!(out && out->pairs)) free(pairs);
+  free(acc);
   free(cell);
   free(ncell);
   free(sv);

@@ -65,3 +65,13 @@ def state(cfg: dict, f, pos, vel, precision: str):
     per_x, per_y = cfg["bc"][0] == "periodic", cfg["bc"][2] == "periodic"
     fr = populations(f, precision).reshape(9, cfg["ny"], cfg["nx"])
     return fr, positions(pos, cfg["nx"], cfg["ny"], per_x, per_y, precision), velocities(vel, precision)
+
+
+def cell_offset(pos: np.ndarray):
+    """Split positions held as cell + float32 offset (see positions) into the
+    int32 cell [N][2] and the float32 offset [N][2], exactly."""
+    pos = np.asarray(pos, np.float64).reshape(-1, 2)
+    cell = np.floor(pos)
+    off = pos - cell
+    assert (off.astype(np.float32).astype(np.float64) == off).all(), "not a cell + float32 offset state"
+    return cell.astype(np.int32), off.astype(np.float32)

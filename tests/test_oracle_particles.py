@@ -427,3 +427,93 @@ def test_circulating_loop_wraps_particles_not_gas(orc):
     assert 5.8 < off.pos[0, 1] < 6.0 and off.vel[0, 1] < 0 and o2.nwall == 1
     # the gas is the same in both runs: the flag does not touch the lattice
     assert np.abs(on.f - off.f).max() < 1e-6
+
+
+# ---------------------------------------------------------------- the hard-sphere stage in single precision
+def _split(pos):
+    cell = np.floor(pos)
+    return cell.astype(np.int32), (pos - cell).astype(np.float32)
+
+
+@pytest.mark.parametrize("e", [0.0, 0.9, 1.0])
+def test_f32_two_sphere_collision(orc, e):
+    """orc_collide_f32, Eqs. 17-18 in float: for two spheres in contact the
+    normal relative velocity becomes -e times itself and the tangential part
+    and the momentum are kept, each to float rounding; spheres moving apart or
+    not touching are left alone; the pair list is the float predicate's."""
+    p = orc.make_params(_cfg(nx=8, ny=8, e_pp=e))
+    cases = [((2.25, 3.5), (2.625, 3.5), (0.01, 0.0), (-0.01, 0.0)),    # head-on along x, one cell
+             ((2.75, 3.75), (3.125, 4.0), (0.02, 0.01), (-0.01, -0.03)),  # oblique, across cells
+             ((7.875, 0.125), (0.25, 7.875), (0.01, -0.01), (-0.01, 0.02)),  # across the periodic corner
+             ((2.25, 3.5), (2.625, 3.5), (-0.01, 0.0), (0.01, 0.0)),     # separating overlap
+             ((2.0, 2.0), (2.75, 2.0), (0.05, 0.0), (-0.05, 0.0))]       # 0.75 apart: no contact
+    for P1, P2, v1, v2 in cases:
+        pos = np.array([P1, P2], float)
+        cell, off = _split(pos)
+        vel = np.array([v1, v2], np.float32)
+        pairs, out, nc, nw = orc.collide_f32(p, cell, off, vel)
+        d = pos[0] - pos[1]
+        d -= 8 * np.round(d / 8)
+        touching = np.hypot(*d) <= 0.5
+        assert len(pairs) == int(touching) and nw == 0
+        n = d / np.linalg.norm(d)
+        t = np.array([-n[1], n[0]])
+        r0 = vel[0].astype(float) - vel[1]
+        if not touching or r0 @ n >= 0:
+            assert nc == 0 and (out == vel).all()
+            continue
+        assert nc == 1
+        r1 = out[0].astype(float) - out[1]
+        eps = 4 * np.finfo(np.float32).eps * np.abs(vel).max()
+        assert abs(r1 @ n + e * (r0 @ n)) < eps
+        assert abs(r1 @ t - r0 @ t) < eps
+        assert np.abs(out.astype(float).sum(0) - vel.astype(float).sum(0)).max() < eps
+
+
+def test_f32_wall_collision(orc):
+    """Walls in float (R23): in the first or last cell within r of the wall
+    plane and moving into it, v_n -> -e_w v_n exactly (one float product);
+    tangential and outward motion untouched; periodic axes have no walls."""
+    p = orc.make_params(_cfg(nx=10, ny=10, bc=["wall", "wall", "periodic", "periodic"], e_pw=0.7))
+    pos = np.array([[0.2, 5.5], [9.875, 5.5], [5.5, 0.125], [0.2, 5.5], [3.5, 5.5]])
+    vel = np.array([[-0.1, 0.3], [0.2, 0.1], [0.05, -0.4], [0.1, 0.0], [-1.0, -1.0]], np.float32)
+    # spread them out so none touch: one per row
+    pos[:, 1] = [1.5, 3.5, 5.5, 7.5, 9.5]
+    pos[2] = (5.5, 5.5)
+    cell, off = _split(pos)
+    pairs, out, nc, nw = orc.collide_f32(p, cell, off, vel)
+    want = vel.copy()
+    want[0, 0] = np.float32(-0.7) * vel[0, 0]
+    want[1, 0] = np.float32(-0.7) * vel[1, 0]
+    assert len(pairs) == 0 and nc == 0 and nw == 2 and (out == want).all()
+    pw = orc.make_params(_cfg(nx=10, ny=10, bc=["wall"] * 4, e_pw=0.5))
+    pos = np.array([[5.5, 0.125], [5.5, 9.9], [2.5, 0.3]])
+    vel = np.array([[0.05, -0.4], [0.0, 0.3], [0.0, -0.2]], np.float32)
+    cell, off = _split(pos)
+    _, out, _, nw = orc.collide_f32(pw, cell, off, vel)
+    assert nw == 2 and out[0, 1] == np.float32(0.2) and out[1, 1] == np.float32(-0.5) * np.float32(0.3)
+    assert out[2, 1] == vel[2, 1]
+
+
+def test_f32_stage_follows_the_fp64_sweep(orc):
+    """On a whole bed (the 64 x 512 riser crop, 31 250 spheres, random
+    velocities) the float stage takes the same decisions as the FP64 oracle's
+    sequential sweep and walls on the same float-held state, and its
+    velocities agree to float rounding; pair lists are identical."""
+    cfg = synth.riser_crop()
+    p = orc.make_params(cfg)
+    pos = cfg["pos"].copy()
+    rng = np.random.default_rng(5)
+    near = rng.choice(len(pos), 400, replace=False)  # some spheres within r of the x walls
+    pos[near[:200], 0] = 0.05 + 0.2 * rng.random(200)
+    pos[near[200:], 0] = 63.95 - 0.2 * rng.random(200)
+    cell, off = _split(pos)
+    pos32 = cell + off.astype(np.float64)
+    vel = ((rng.random(pos.shape) - 0.5) * 2e-2).astype(np.float32)
+    pairs, out, nc, nw = orc.collide_f32(p, cell, off, vel)
+    ref_pairs = orc.contacts(p, pos32)
+    assert (pairs == ref_pairs).all()
+    v64, nc64 = orc.resolve(p, pos32, vel.astype(np.float64), ref_pairs)
+    v64, nw64 = orc.walls(p, pos32, v64)
+    assert nc == nc64 and nw == nw64 and nc > 1000 and nw > 10
+    assert np.abs(out - v64).max() <= 1e-5 * np.abs(v64).max()
