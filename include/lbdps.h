@@ -176,6 +176,18 @@ lbdps_status lbdps_get_fields(lbdps_ctx *ctx, double *d_rho, double *d_ugas, dou
 lbdps_status lbdps_get_particles(lbdps_ctx *ctx, double *d_pos, double *d_vel, double *d_fd, int32_t *d_cell);
 
 /*
+ * Acceleration of Eq. 16 taken by each particle in the most recent step,
+ * device FP64 [n][2] in particle-index order:
+ *   a = g_eff + (F_d + s V_p grad p_k) / m,
+ * computed in the context's arithmetic; the integration then takes
+ * v <- v + a h (h = 1 / n_sub) before the hard-sphere stage, so with one
+ * sub-step the velocity entering that stage is the previous velocity plus a.
+ * Held with diagnostics on (or n_sub > 1); LBDPS_E_INVALID otherwise.
+ * Synchronises the stream.
+ */
+lbdps_status lbdps_get_accel(lbdps_ctx *ctx, double *d_acc);
+
+/*
  * Contact pairs (i, j), i < j by particle index, of the most recent hard-sphere
  * stage, in lexicographic order, device int32 [cap][2].  *n_out receives the
  * number of pairs (also when it exceeds cap; then only cap are written).

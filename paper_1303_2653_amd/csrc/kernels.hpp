@@ -1598,6 +1598,10 @@ __global__ __launch_bounds__(BLOCK) LBDPS_WAVES6 void k_contacts_small(Parts<typ
 // current velocities; the pair collides only if (P_s - P_t).(v_s - v_t) < 0.
 // The collision of two particles given by value: separation (dx, dy) = P_s - P_t
 // and velocities; returns whether they approach, and then the new velocities.
+// Every operation is one IEEE operation in the arithmetic type, the two
+// divisions correctly rounded (not the hardware reciprocal) in every
+// precision, so that the outcome is fixed by the arithmetic type alone: in
+// FP32 it is the same float computation step for step on any IEEE machine.
 template <int P>
 __device__ __forceinline__ bool pair_core(const Consts<typename Prec<P>::T> &k, typename Prec<P>::T dx,
                                           typename Prec<P>::T dy, typename Prec<P>::T &vix, typename Prec<P>::T &viy,
@@ -1607,9 +1611,9 @@ __device__ __forceinline__ bool pair_core(const Consts<typename Prec<P>::T> &k, 
   const T dot = dvx * dx + dvy * dy;
   if (!(dot < (T)0)) return false;
   const T r2 = dx * dx + dy * dy;
-  const T q0 = dv<P>(k.one_e * dot, r2);
-  const T ci = dv<P>(q0 * k.m, k.msum);
-  const T cj = dv<P>(q0 * k.m, k.msum);
+  const T q0 = (k.one_e * dot) / r2;
+  const T ci = (q0 * k.m) / k.msum;
+  const T cj = ci;  // m_i / (m_i + m_j) = m_j / (m_i + m_j): one mass
   vix = vix - ci * dx;
   viy = viy - ci * dy;
   vjx = vjx + cj * dx;

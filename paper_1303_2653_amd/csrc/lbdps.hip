@@ -278,7 +278,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     dfy = raw(N * sT);
   }
   char *acx = nullptr, *acy = nullptr;
-  if (n_sub_of(p) > 1) {
+  if (n_sub_of(p) > 1 || p.diagnostics) {
     acx = raw(N * sT);
     acy = raw(N * sT);
   }
@@ -927,6 +927,21 @@ lbdps_status lbdps_get_particles(lbdps_ctx *x, double *d_pos, double *d_vel, dou
   });
   if (st != LBDPS_OK) return st;
   return sync_and_check(x, "lbdps_get_particles");
+}
+
+lbdps_status lbdps_get_accel(lbdps_ctx *x, double *d_acc) {
+  if (!x || !d_acc) return fail(LBDPS_E_INVALID, "ctx or d_acc is NULL");
+  if (!x->acx) return fail(LBDPS_E_INVALID, "the acceleration is held only with diagnostics on or n_sub > 1");
+  if (x->n > 0) {
+    lbdps_status st = dispatch(x, [&](auto impl) {
+      using T = typename decltype(impl)::T;
+      hipLaunchKernelGGL(k_get_field<T>, dim3(nblocks(x->n)), dim3(BLOCK), 0, x->stream, (const T *)x->acx,
+                         (const T *)x->acy, (int)x->n, d_acc, 0.0);
+      return launch_status("lbdps_get_accel");
+    });
+    if (st != LBDPS_OK) return st;
+  }
+  return sync_and_check(x, "lbdps_get_accel");
 }
 
 lbdps_status lbdps_get_pairs(lbdps_ctx *x, int32_t *d_pairs, int64_t cap, int64_t *n_out) {

@@ -71,6 +71,7 @@ _SIGS = {
     "lbdps_get_fields": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lbdps_get_particles": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lbdps_get_pairs": (c_i32, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]),
+    "lbdps_get_accel": (c_i32, [c_vp, c_vp]),
     "lbdps_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64)]),
     "lbdps_conservation": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
     "lbdps_counters": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
@@ -268,6 +269,14 @@ class Sim:
         if diag:
             out["fd"] = fd.cpu().numpy()[: self.n]
         return out
+
+    def accel(self):
+        """Acceleration of Eq. 16 of the most recent step by particle index
+        [n][2] (lbdps_get_accel; diagnostics on or n_sub > 1)."""
+        t = self.torch
+        a = t.empty(max(self.n, 1), 2, dtype=t.float64, device="cuda")
+        check(lbdps_get_accel(self.ctx, a.data_ptr()), "lbdps_get_accel")
+        return a.cpu().numpy()[: self.n]
 
     def pairs(self, cap=None):
         t = self.torch

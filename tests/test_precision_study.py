@@ -45,16 +45,20 @@ POINTS = (10, 100, 1000)
 STEPS, START, EVERY = 5000, 1000, 10
 PRECS = ("fp32", "fp16", "bf16")
 
-# stated pointwise bounds (gas fields and populations, norm-wise) at step 10.
-# FP16 and BF16: the storage rounding, measured 1.9e-3 and 3.1e-3.  FP32: the
-# random placement leaves overlapping pairs nearly at rest relative to each
-# other, whose approach test and impulse direction (Eqs. 17-18) are decided by
-# rounding; the velocity a pair takes then reaches u_gas and F_pg through the
-# cell's mean solid velocity (Eqs. 8, 24-25).  Over seeds 3-10 of the crop
-# the largest FP32 errors at step 10 were 5.4e-6 (u_gas) and 3.2e-5 (F_pg),
-# 5.3e-10 for populations and density and 8.2e-8 for beta, and an exact
-# division instead of the hardware reciprocal moves them within the same
-# range (F_pg up to 1.4e-4 on one seed).
+# stated pointwise bounds of the free run (gas fields and populations,
+# norm-wise) at step 10.  FP16 and BF16: the storage rounding, measured 1.8e-3
+# and 3.1e-3.  FP32: the bed starts at rest, so after one step neighbouring
+# spheres move almost together and the approach test of Eqs. 17-18 for many
+# overlapping pairs is decided by rounding-level differences of the stages
+# before it; the first such pair decided differently (step 2 on the parity
+# bed, test_fp32_free_run_first_divergence) parts the trajectories, and the
+# velocity it takes reaches u_gas and F_pg through the cell's mean solid
+# velocity (Eqs. 8, 24-25).  Over seeds 3-10 of the crop the largest FP32
+# errors at step 10 were 5.4e-6 (u_gas) and 3.2e-5 (F_pg), 5.3e-10 for
+# populations and density and 8.2e-8 for beta.  The FP32 tolerance of 1e-5
+# is held in lockstep instead, where each step starts from the oracle's state
+# and the hard-sphere stage is compared on one input, for ten steps of this
+# bed with no exemption (test_fp32_lockstep_ten_steps_crop).
 BOUND10 = {"fp32": dict(f=1e-8, rho=1e-8, ugas=1e-4, fpg=3e-4, beta=1e-6),
            "fp16": 1e-2, "bf16": 1.5e-2}
 # statistics: within 1.5 times the spread of runs that differ only by chaotic
