@@ -67,7 +67,7 @@ class OrcOut(ctypes.Structure):
         ("pairs", ctypes.c_void_p),
         ("pair_cap", ctypes.c_int64), ("npairs", ctypes.c_int64),
         ("ncollisions", ctypes.c_int64), ("nwall", ctypes.c_int64),
-        ("nzero_den", ctypes.c_int64),
+        ("nzero_den", ctypes.c_int64), ("ncross", ctypes.c_int64),
     ]
 
 
@@ -111,6 +111,8 @@ def lib(omp: bool = False):
         L.orc_contacts_f32.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_float, i64, vp, vp, ctypes.c_int32, vp, i64,
                                        ctypes.POINTER(i64)]
+        L.orc_solids_flux.restype = ctypes.c_double
+        L.orc_solids_flux.argtypes = [P, i64, i64]
         L.orc_collide_f32.restype = ctypes.c_int
         L.orc_collide_f32.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, i64,
@@ -347,6 +349,12 @@ def voidage(p: OrcParams, pos, y0=0, y1=None, threshold=0.85):
     return rows, cols, count
 
 
+def solids_flux(p: OrcParams, net: int, steps: int) -> float:
+    """Outlet solids mass flux (Sec. 3.2) of `net` particles across the outlet
+    plane over `steps` steps: m net / (nx steps) in lattice units (R47)."""
+    return lib().orc_solids_flux(ctypes.byref(p), int(net), int(steps))
+
+
 # ---------------------------------------------------------------- 3-D gas lattice
 def lattice3():
     c = np.zeros((19, 3), np.int32)
@@ -406,6 +414,7 @@ class StepOut:
     ncollisions: int
     nwall: int
     nzero_den: int
+    ncross: int
 
 
 class Sim:
@@ -454,7 +463,8 @@ class Sim:
                        fpg=bufs["fpg"].reshape(ny, nx, 2), beta=bufs["beta"].reshape(ny, nx),
                        fd=bufs["fd"][:n].copy(), fpre=bufs["fpre"][:n].copy(),
                        upart=bufs["upart"][:n].copy(), acc=bufs["acc"][:n].copy(), pairs=bufs["pairs"][: o.npairs].copy(),
-                       ncollisions=o.ncollisions, nwall=o.nwall, nzero_den=o.nzero_den)
+                       ncollisions=o.ncollisions, nwall=o.nwall, nzero_den=o.nzero_den,
+                       ncross=o.ncross)
 
     def run(self, nsteps):
         for _ in range(nsteps):

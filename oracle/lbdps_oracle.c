@@ -99,6 +99,7 @@ typedef struct {
   int64_t ncollisions; /* out: pairs that were approaching and collided */
   int64_t nwall;       /* out: particle-wall collisions */
   int64_t nzero_den;   /* out: cell components where Eq. 28's denominator was 0 */
+  int64_t ncross;      /* out: net particles across the outlet plane y = ny, upward (R47) */
 } orc_out;
 
 /* ---- D2Q9 lattice (Sec. 2.1, text after Eq. 4), diagonals as (+-1, +-1) (R1) ---- */
@@ -454,19 +455,32 @@ static void accelerations(const orc_params *p, int64_t np, const double *fd, con
 
 /*
  * One symplectic Euler step of length h (R18): v <- v + a h, P <- P + v h, then
- * periodic wrap (R26) or wall mirror (R23).
+ * periodic wrap (R26) or wall mirror (R23).  Returns the net number of
+ * particles that crossed the plane y = ny upward in the move (R47): with
+ * particles periodic in y, +1 for a move that ends at y >= ny (wrapped to the
+ * bottom), -1 for one that ends below 0; 0 when y has walls.
  */
-static void advance(const orc_params *p, int64_t np, double *pos, double *vel, const double *acc, double h) {
+static int64_t advance(const orc_params *p, int64_t np, double *pos, double *vel, const double *acc, double h) {
+  int64_t cross = 0;
   for (int64_t k = 0; k < np; ++k) {
     vel[2 * k] = vel[2 * k] + acc[2 * k] * h;
     vel[2 * k + 1] = vel[2 * k + 1] + acc[2 * k + 1] * h;
     double x = pos[2 * k] + vel[2 * k] * h;
     double y = pos[2 * k + 1] + vel[2 * k + 1] * h;
     x = is_periodic_x(p) ? wrap_coord(x, p->nx) : mirror_coord(x, p->nx);
-    y = particles_periodic_y(p) ? wrap_coord(y, p->ny) : mirror_coord(y, p->ny);
+    if (particles_periodic_y(p)) {
+      if (y >= (double)p->ny)
+        ++cross;
+      else if (y < 0.0)
+        --cross;
+      y = wrap_coord(y, p->ny);
+    } else {
+      y = mirror_coord(y, p->ny);
+    }
     pos[2 * k] = x;
     pos[2 * k + 1] = y;
   }
+  return cross;
 }
 
 /*
@@ -479,6 +493,14 @@ void orc_integrate(const orc_params *p, int64_t np, double *pos, double *vel, co
   accelerations(p, np, fd, gpk, acc);
   advance(p, np, pos, vel, acc, 1.0);
   free(acc);
+}
+
+/* Outlet solids mass flux of Sec. 3.2 from the net number of particles that
+ * crossed the outlet plane y = ny upward over `steps` steps (R47): the mass
+ * m = rho_s pi d^3 / 6 they carry per unit width of the outlet (unit depth,
+ * h = 1) per unit time (dt = 1). */
+double orc_solids_flux(const orc_params *p, int64_t net, int64_t steps) {
+  return mass_p(p) * (double)net / ((double)p->nx * (double)steps);
 }
 
 /* Minimum-image separation P_i - P_j along each axis (R25). */
@@ -974,9 +996,9 @@ int orc_step(const orc_params *p, const double *inlet_uy, double *f, int64_t np,
   int64_t cap = out && out->pairs ? out->pair_cap : 0;
   int64_t cap_eff = cap > 0 ? cap : (np * 16 + 16);
   int32_t *pairs = out && out->pairs ? out->pairs : (int32_t *)malloc((size_t)cap_eff * 2 * sizeof(int32_t));
-  int64_t npairs = 0, ncoll = 0, nwall = 0;
+  int64_t npairs = 0, ncoll = 0, nwall = 0, ncross = 0;
   for (int sub = 0; sub < nsub && rc == ORC_OK; ++sub) {
-    advance(p, np, pos, vel, acc, h);
+    ncross += advance(p, np, pos, vel, acc, h);
     npairs = ncoll = nwall = 0;
     rc = orc_contacts_cells(p, np, pos, pairs, cap_eff, &npairs);
     if (rc == ORC_OK) {
@@ -999,6 +1021,7 @@ int orc_step(const orc_params *p, const double *inlet_uy, double *f, int64_t np,
     out->ncollisions = ncoll;
     out->nwall = nwall;
     out->nzero_den = nzero;
+    out->ncross = ncross;
   }
   if (!(out && out->pairs)) free(pairs);
   free(acc);

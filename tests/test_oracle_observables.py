@@ -145,3 +145,52 @@ def test_paper_riser_parameters():
     assert np.allclose(c["inlet_uy"], c["u0"][1])
     x = c["pos"][:, 0]
     assert x.min() >= c["d"] / 2 and x.max() <= c["nx"] - c["d"] / 2
+
+
+# ---------------------------------------------------------------- outlet solids flux (Sec. 3.2)
+def _loop_cfg(**kw):
+    """A tiny circulating bed: gas inlet at the bottom, outlet at the top,
+    walls at x, particles periodic in y (R44)."""
+    return _cfg(nx=12, ny=16, bc=["wall", "wall", "inlet", "outlet"], particles_periodic_y=1,
+                inlet_uy=np.full(12, 0.01), g=(0.0, 0.0), **kw)
+
+
+def test_outlet_crossings_of_a_constructed_bed(orc):
+    """R47: the step counts the particles that cross the outlet plane y = ny
+    upward, less those that cross it downward (leaving through the bottom of
+    a circulating bed).  Five spheres 0.1 below the top moving up at 0.3, two
+    0.1 above the bottom moving down at 0.3, and three in mid-bed: net 3, and
+    the flux is m 3 / nx per step.  With walls in y the spheres reflect and
+    nothing crosses."""
+    pos = np.array([[1.5 + 2 * k, 15.9] for k in range(5)] + [[2.5, 0.1], [6.5, 0.1]] +
+                   [[3.5, 8.0], [7.5, 8.0], [10.5, 8.0]])
+    vel = np.array([[0.0, 0.3]] * 5 + [[0.0, -0.3]] * 2 + [[0.01, 0.0]] * 3)
+    cfg = _loop_cfg(pos=pos, vel=vel)
+    sim = orc.Sim(cfg)
+    o = sim.step(record=True)
+    assert o.ncross == 3
+    assert (sim.pos[:5, 1] < 1.0).all() and (sim.pos[5:7, 1] > 15.0).all()
+    m = cfg["rho_s"] * math.pi * cfg["d"] ** 3 / 6
+    assert abs(orc.solids_flux(sim.p, o.ncross, 1) - m * 3 / 12) <= 1e-15 * m
+    walls = dict(cfg, particles_periodic_y=0, bc=["wall", "wall", "wall", "wall"])
+    sim_w = orc.Sim(walls)
+    assert sim_w.step(record=True).ncross == 0 and (sim_w.pos[:, 1] < 16).all() and (sim_w.pos[:, 1] > 0).all()
+
+
+def test_outlet_crossings_close_the_displacement_balance(orc):
+    """R47 against the move itself: over one step of a circulating bed with
+    fast random motion, the particles' summed displacement, unwrapped by ny
+    for each counted crossing, equals the summed velocity they moved with
+    (the previous velocity plus the acceleration of Eq. 16, h = 1)."""
+    rng = np.random.default_rng(3)
+    n = 300
+    pos = np.stack([0.3 + 11.4 * rng.random(n), 16 * rng.random(n)], 1)
+    vel = (rng.random((n, 2)) - 0.5) * np.array([0.1, 1.6])
+    cfg = _loop_cfg(pos=pos, vel=vel)
+    sim = orc.Sim(cfg)
+    y0, v0 = sim.pos[:, 1].copy(), sim.vel.copy()
+    o = sim.step(record=True)
+    moved = (v0[:, 1] + o.acc[:, 1]).sum()
+    disp = (sim.pos[:, 1] - y0).sum() + 16 * o.ncross
+    assert abs(o.ncross) > 0 and np.abs(sim.pos[:, 1] - y0).max() > 8  # wraps happened
+    assert abs(disp - moved) < 1e-12 * n
