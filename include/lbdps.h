@@ -208,6 +208,21 @@ lbdps_status lbdps_get_state(lbdps_ctx *ctx, double *d_f, double *d_pos, double 
 lbdps_status lbdps_conservation(lbdps_ctx *ctx, double h_out[6]);
 
 /*
+ * lbdps_conservation without any scratch of the context's: for callers that
+ * cannot allocate device memory or must not touch more of it (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation).  The
+ * same kernels and the same fixed-order sums, so h_out equals lbdps_conservation's
+ * bit for bit; the reduction's partial sums, outputs and flag live in one
+ * library-static device array per GPU (about 21 KB, held until the process
+ * ends).  Its size does not depend on the bed (the reduction always runs on
+ * the same fixed grid), so every context fits.  Allocates nothing.  Calls
+ * that overlap on one GPU (contexts on different streams, or threads) share
+ * that array and race: serialise them.  Returns LBDPS_E_NONFINITE as
+ * lbdps_conservation does.  Synchronises the stream.
+ */
+lbdps_status lbdps_conservation_noalloc(lbdps_ctx *ctx, double h_out[6]);
+
+/*
  * Event counts of the most recent hard-sphere stage: h_out[0] contact pairs,
  * h_out[1] pairs that collided, h_out[2] particle-wall collisions, h_out[3]
  * (diagnostics on) cell components with a zero Eq. 28 denominator in the most

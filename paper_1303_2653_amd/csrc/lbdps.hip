@@ -6,6 +6,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <new>
 #include <string>
@@ -31,6 +32,44 @@ lbdps_status fail(lbdps_status s, const std::string &m) {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int NB_CONS = 512;  // workgroups of the conservation reductions
+
+// Scratch of lbdps_conservation_noalloc: the conservation reduction's
+// per-workgroup partial sums (NB_CONS x 3 for the populations, NB_CONS x 2
+// for the particles), its six outputs and its non-finite flag, in a
+// library-static device array instead of a context's workspace.  The
+// reduction runs on a fixed grid of NB_CONS workgroups whatever the bed, so
+// this size serves every context.  Each GPU the library runs on holds its own
+// copy until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (the array's name in host code is
+// a host-side stand-in, not a device address).
+constexpr size_t NOALLOC_PC = 0, NOALLOC_PP = NOALLOC_PC + (size_t)NB_CONS * 3,
+                 NOALLOC_OUT = NOALLOC_PP + (size_t)NB_CONS * 2, NOALLOC_FLAG = NOALLOC_OUT + 8;
+constexpr size_t NOALLOC_SCRATCH_BYTES = NOALLOC_FLAG * sizeof(double) + 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on device `dev`, looked up once per device with
+// that device current (the caller's current device is restored).
+lbdps_status scratch_address(int dev, void **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(LBDPS_E_DEVICE, "device index beyond the scratch table");
+  if (!g_scratch_dev[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(LBDPS_E_DEVICE, "hipGetDevice failed");
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return fail(LBDPS_E_DEVICE, "hipSetDevice failed");
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr)
+      return fail(LBDPS_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return LBDPS_OK;
+}
 
 int nblocks(long long n) { return (int)((n + BLOCK - 1) / BLOCK); }
 // The drag kernel's flat form pays once the grid needs more than one round of
@@ -172,6 +211,8 @@ struct lbdps_ctx {
   int prec = 0, nx = 0, ny = 0, C = 0, nlut = 0;
   long long nmax = 0, n = 0;
   hipStream_t stream = nullptr;
+  int device = 0;           // the HIP device current at creation
+  void *scratch = nullptr;  // that device's address of the static scratch array
   int cf = 0, cp = 0;
   bool bins_valid = false;
   long long step = 0;
@@ -596,14 +637,16 @@ template <int P> struct Impl {
                        (const S *)x->f[x->cf], out, x->C);
   }
 
-  static void conservation(lbdps_ctx *x) {
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, x->nonfinite, 1ll, 0);
+  // The FP64 conservation sums with the given scratch: partials pc [NB_CONS][3]
+  // and pp [NB_CONS][2], output out [6], flag (cleared here first).
+  static void conservation(lbdps_ctx *x, double *pc, double *pp, double *out, int32_t *flag) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, flag, 1ll, 0);
     hipLaunchKernelGGL(k_cons_cells<P>, dim3(NB_CONS), dim3(BLOCK), 0, x->stream, (const S *)x->f[x->cf], x->C,
-                       x->cons_pc, x->nonfinite);
+                       pc, flag);
     hipLaunchKernelGGL(k_cons_parts<T>, dim3(NB_CONS), dim3(BLOCK), 0, x->stream, (const T *)x->vx[x->cp],
-                       (const T *)x->vy[x->cp], (int)x->n, x->dc.m, x->cons_pp, x->nonfinite);
-    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(BLOCK), 0, x->stream, x->cons_pc, NB_CONS, x->cons_pp, NB_CONS,
-                       x->nonfinite, x->cons_out);
+                       (const T *)x->vy[x->cp], (int)x->n, x->dc.m, pp, flag);
+    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(BLOCK), 0, x->stream, (const double *)pc, NB_CONS,
+                       (const double *)pp, NB_CONS, (const int32_t *)flag, out);
   }
 };
 
@@ -726,6 +769,11 @@ lbdps_status lbdps_create(const lbdps_params *p, int64_t max_particles, void *d_
   x->nlut = lut_rows(p->d_p);
   x->stream = (hipStream_t)stream;
   x->dc = make_dconsts(*p);
+  if ((st = check_hip(hipGetDevice(&x->device), "lbdps_create")) != LBDPS_OK ||
+      (st = scratch_address(x->device, &x->scratch)) != LBDPS_OK) {
+    delete x;
+    return st;
+  }
   carve(*p, max_particles, (char *)d_workspace, x);
 
   // per-count table and inlet profile, converted to the arithmetic type
@@ -981,20 +1029,35 @@ lbdps_status lbdps_get_state(lbdps_ctx *x, double *d_f, double *d_pos, double *d
   return sync_and_check(x, "lbdps_get_state");
 }
 
-lbdps_status lbdps_conservation(lbdps_ctx *x, double h_out[6]) {
-  if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
+// The conservation sums into the given scratch, copied to h_out.
+lbdps_status conservation_with(lbdps_ctx *x, double *pc, double *pp, double *out, int32_t *flag, double h_out[6],
+                               const char *what) {
   lbdps_status st = dispatch(x, [&](auto impl) {
-    decltype(impl)::conservation(x);
-    return launch_status("lbdps_conservation");
+    decltype(impl)::conservation(x, pc, pp, out, flag);
+    return launch_status(what);
   });
   if (st != LBDPS_OK) return st;
-  st = check_hip(hipMemcpyAsync(h_out, x->cons_out, 6 * sizeof(double), hipMemcpyDeviceToHost, x->stream),
-                 "lbdps_conservation");
+  st = check_hip(hipMemcpyAsync(h_out, out, 6 * sizeof(double), hipMemcpyDeviceToHost, x->stream), what);
   if (st != LBDPS_OK) return st;
-  st = sync_and_check(x, "lbdps_conservation");
+  st = sync_and_check(x, what);
   if (st != LBDPS_OK) return st;
   if (h_out[5] != 0.0) return fail(LBDPS_E_NONFINITE, "non-finite value in populations or velocities");
   return LBDPS_OK;
+}
+
+lbdps_status lbdps_conservation(lbdps_ctx *x, double h_out[6]) {
+  if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
+  return conservation_with(x, x->cons_pc, x->cons_pp, x->cons_out, x->nonfinite, h_out, "lbdps_conservation");
+}
+
+lbdps_status lbdps_conservation_noalloc(lbdps_ctx *x, double h_out[6]) {
+  if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
+  static_assert(NOALLOC_FLAG * sizeof(double) + sizeof(int32_t) <= NOALLOC_SCRATCH_BYTES,
+                "the conservation scratch fits the static array");
+  if (!x->scratch) return fail(LBDPS_E_DEVICE, "no scratch address for the context's device");
+  double *base = (double *)x->scratch;
+  return conservation_with(x, base + NOALLOC_PC, base + NOALLOC_PP, base + NOALLOC_OUT,
+                           (int32_t *)(base + NOALLOC_FLAG), h_out, "lbdps_conservation_noalloc");
 }
 
 lbdps_status lbdps_counters(lbdps_ctx *x, int64_t h_out[4]) {

@@ -74,6 +74,7 @@ _SIGS = {
     "lbdps_get_accel": (c_i32, [c_vp, c_vp]),
     "lbdps_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64)]),
     "lbdps_conservation": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
+    "lbdps_conservation_noalloc": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
     "lbdps_counters": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
     "lbdps_time_kernels": (c_i32, [c_vp, ctypes.c_uint32]),
     "lbdps_kernel_times": (c_i32, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
@@ -300,6 +301,13 @@ class Sim:
     def conservation(self):
         out = (c_dbl * 6)()
         check(lbdps_conservation(self.ctx, out), "lbdps_conservation")
+        return np.array(out[:])
+
+    def conservation_noalloc(self):
+        """lbdps_conservation_noalloc: the same sums, scratch in the library's
+        static device array."""
+        out = (c_dbl * 6)()
+        check(lbdps_conservation_noalloc(self.ctx, out), "lbdps_conservation_noalloc")
         return np.array(out[:])
 
     def counters(self):
