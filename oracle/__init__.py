@@ -71,6 +71,20 @@ class OrcOut(ctypes.Structure):
     ]
 
 
+class Orc3Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("rho_g", ctypes.c_double), ("rho_s", ctypes.c_double),
+                ("d", ctypes.c_double), ("e_pp", ctypes.c_double), ("g", ctypes.c_double * 3),
+                ("G", ctypes.c_double * 3), ("omega_dense", ctypes.c_double), ("pressure_sign", ctypes.c_int32)]
+
+
+class Orc3Out(ctypes.Structure):
+    _fields_ = [("ncell", ctypes.c_void_p), ("vs", ctypes.c_void_p), ("rho", ctypes.c_void_p),
+                ("ugas", ctypes.c_void_p), ("fpg", ctypes.c_void_p), ("beta", ctypes.c_void_p),
+                ("fd", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("pairs", ctypes.c_void_p),
+                ("pair_cap", ctypes.c_int64), ("npairs", ctypes.c_int64), ("ncollisions", ctypes.c_int64)]
+
+
 _libs = {}
 
 
@@ -125,6 +139,19 @@ def lib(omp: bool = False):
         L.orc_conservation.argtypes = [P, vp, i64, vp, vp]
         L.orc_lattice.argtypes = [vp, vp, vp]
         L.orc3_lattice.argtypes = [vp, vp]
+        P3 = ctypes.POINTER(Orc3Params)
+        L.orc3_cell_props.argtypes = [P3, i64, vp]
+        L.orc3_stencil.argtypes = [P3, vp, vp, vp]
+        L.orc3_interp.restype = ctypes.c_double
+        L.orc3_interp.argtypes = [P3, vp, vp]
+        L.orc3_contacts_brute.restype = ctypes.c_int
+        L.orc3_contacts_brute.argtypes = [P3, i64, vp, vp, i64, ctypes.POINTER(i64)]
+        L.orc3_contacts_cells.restype = ctypes.c_int
+        L.orc3_contacts_cells.argtypes = [P3, i64, vp, vp, i64, ctypes.POINTER(i64)]
+        L.orc3_resolve.argtypes = [P3, vp, vp, vp, i64, ctypes.POINTER(i64)]
+        L.orc3_step.restype = ctypes.c_int
+        L.orc3_step.argtypes = [P3, vp, i64, vp, vp, ctypes.POINTER(Orc3Out)]
+        L.orc3_conservation.argtypes = [P3, vp, i64, vp, vp]
         L.orc3_feq.restype = ctypes.c_double
         L.orc3_feq.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc3_bgk_step.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, vp]
@@ -472,3 +499,129 @@ class Sim:
 
     def conservation(self):
         return conservation(self.p, self.f, self.vel)
+
+
+# ---------------------------------------------------------------- the 3-D coupled step
+def make_params3(cfg: dict) -> Orc3Params:
+    """3-D parameters from a workload dict (nx, ny, nz, tau, rho_g, rho_s, d,
+    e_pp, g[3], G[3], omega_dense)."""
+    p = Orc3Params()
+    p.nx, p.ny, p.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
+    for k in ("tau", "rho_g", "rho_s", "d", "e_pp", "omega_dense"):
+        setattr(p, k, float(cfg[k]))
+    p.pressure_sign = int(cfg.get("pressure_sign", -1))
+    for a in range(3):
+        p.g[a] = float(cfg["g"][a])
+        p.G[a] = float(cfg["G"][a])
+    return p
+
+
+def cell_props3(p: Orc3Params, n: int) -> dict:
+    out = np.zeros(4)
+    lib().orc3_cell_props(ctypes.byref(p), int(n), _ptr(out))
+    return dict(eps_s=out[0], eps_g=out[1], gamma=out[2], omega=out[3])
+
+
+def stencil3(p: Orc3Params, P):
+    P = np.ascontiguousarray(P, np.float64)
+    idx, wt = np.zeros(8, np.int64), np.zeros(8)
+    lib().orc3_stencil(ctypes.byref(p), _ptr(P), _ptr(idx), _ptr(wt))
+    return idx, wt
+
+
+def interp3(p: Orc3Params, q, P):
+    q = np.ascontiguousarray(q, np.float64).reshape(-1)
+    return lib().orc3_interp(ctypes.byref(p), _ptr(q), _ptr(np.ascontiguousarray(P, np.float64)))
+
+
+def contacts3(p: Orc3Params, pos, brute=False, cap=None):
+    pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+    n = len(pos)
+    cap = cap if cap is not None else max(16, 32 * n)
+    pairs = np.zeros((cap, 2), np.int32)
+    m = ctypes.c_int64(0)
+    fn = lib().orc3_contacts_brute if brute else lib().orc3_contacts_cells
+    rc = fn(ctypes.byref(p), n, _ptr(pos), _ptr(pairs), cap, ctypes.byref(m))
+    if rc != 0:
+        raise RuntimeError(f"oracle contacts3 failed rc={rc}")
+    return pairs[: m.value].copy()
+
+
+def resolve3(p: Orc3Params, pos, vel, pairs):
+    pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+    vel = np.array(vel, np.float64, copy=True).reshape(-1, 3)
+    pairs = np.ascontiguousarray(pairs, np.int32)
+    nc = ctypes.c_int64(0)
+    lib().orc3_resolve(ctypes.byref(p), _ptr(pos), _ptr(vel), _ptr(pairs), len(pairs), ctypes.byref(nc))
+    return vel, nc.value
+
+
+def conservation3(p: Orc3Params, f, vel):
+    f = np.ascontiguousarray(f, np.float64)
+    vel = np.ascontiguousarray(vel, np.float64).reshape(-1, 3)
+    out = np.zeros(7)
+    lib().orc3_conservation(ctypes.byref(p), _ptr(f), len(vel), _ptr(vel), _ptr(out))
+    return out
+
+
+def equilibrium_state3(nx, ny, nz, rho=1.0, u=(0.0, 0.0, 0.0)):
+    f = np.empty((19, nz, ny, nx))
+    for i in range(19):
+        f[i] = feq3(i, rho, *u)
+    return f
+
+
+@dataclass
+class Step3Out:
+    ncell: np.ndarray
+    vs: np.ndarray
+    rho: np.ndarray
+    ugas: np.ndarray
+    fpg: np.ndarray
+    beta: np.ndarray
+    fd: np.ndarray
+    acc: np.ndarray
+    pairs: np.ndarray
+    ncollisions: int
+
+
+class Sim3:
+    """An oracle state of the 3-D coupled step (f [19][nz][ny][nx], pos and
+    vel [N][3]) advanced with orc3_step."""
+
+    def __init__(self, cfg: dict, f=None, pos=None, vel=None, omp: bool = False):
+        self.cfg, self.omp = cfg, omp
+        self.p = make_params3(cfg)
+        nx, ny, nz = self.p.nx, self.p.ny, self.p.nz
+        self.f = equilibrium_state3(nx, ny, nz) if f is None else np.array(f, np.float64, copy=True)
+        self.pos = np.array(cfg["pos"] if pos is None else pos, np.float64, copy=True).reshape(-1, 3)
+        self.vel = np.array(cfg["vel"] if vel is None else vel, np.float64, copy=True).reshape(-1, 3)
+
+    def step(self, record=False, pair_cap=None):
+        nx, ny, nz = self.p.nx, self.p.ny, self.p.nz
+        C, n = nx * ny * nz, len(self.pos)
+        o = Orc3Out()
+        bufs = {}
+        if record:
+            bufs = dict(ncell=np.zeros(C, np.int32), vs=np.zeros((C, 3)), rho=np.zeros(C), ugas=np.zeros((C, 3)),
+                        fpg=np.zeros((C, 3)), beta=np.zeros(C), fd=np.zeros((max(n, 1), 3)),
+                        acc=np.zeros((max(n, 1), 3)))
+            cap = pair_cap if pair_cap is not None else max(16, 32 * n)
+            bufs["pairs"] = np.zeros((cap, 2), np.int32)
+            for k, v in bufs.items():
+                setattr(o, k, v.ctypes.data)
+            o.pair_cap = cap
+        rc = lib(self.omp).orc3_step(ctypes.byref(self.p), _ptr(self.f), n, _ptr(self.pos), _ptr(self.vel),
+                                     ctypes.byref(o))
+        if rc != 0:
+            raise RuntimeError(f"oracle 3-D step failed rc={rc}")
+        if not record:
+            return None
+        sh = (nz, ny, nx)
+        return Step3Out(ncell=bufs["ncell"].reshape(sh), vs=bufs["vs"].reshape(*sh, 3), rho=bufs["rho"].reshape(sh),
+                        ugas=bufs["ugas"].reshape(*sh, 3), fpg=bufs["fpg"].reshape(*sh, 3),
+                        beta=bufs["beta"].reshape(sh), fd=bufs["fd"][:n].copy(), acc=bufs["acc"][:n].copy(),
+                        pairs=bufs["pairs"][: o.npairs].copy(), ncollisions=o.ncollisions)
+
+    def conservation(self):
+        return conservation3(self.p, self.f, self.vel)

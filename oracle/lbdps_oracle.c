@@ -1074,7 +1074,7 @@ void orc_conservation(const orc_params *p, const double *f, int64_t np, const do
 /* ==== 3-D gas lattice (the 3-D extension the paper names as future work) ====
  * D3Q19: the rest velocity, the 6 face neighbours (weight 1/18) and the 12
  * edge neighbours (weight 1/36), rest weight 1/3, c_s^2 = 1/3; the
- * equilibrium has the same second-order form as in 2-D (Eq. 2 with
+ * equilibrium has the same second-order form as in 2-D (Eq. 4 with
  * c_i.u in three dimensions).  Only the gas part is here: the BGK step on a
  * fully periodic box, the first piece of the 3-D coupled step. */
 static const int C3[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
@@ -1097,7 +1097,7 @@ double orc3_feq(int i, double rho, double ux, double uy, double uz) {
 }
 
 /*
- * One BGK step on a periodic nx x ny x nz box (Eq. 1 with the 3-D lattice):
+ * One BGK step on a periodic nx x ny x nz box (Eqs. 2-3 on the 3-D lattice):
  * moments, relaxation towards f^eq with 1/tau, then pull streaming
  * f_i(x) <- f*_i(x - c_i).  f[19][nz][ny][nx] is advanced in place.
  */
@@ -1200,4 +1200,398 @@ void orc3_psm_step(int32_t nx, int32_t ny, int32_t nz, double tau, double d, con
         }
       }
   free(fs);
+}
+
+/* ==== the 3-D coupled step (the fully 3-D simulation the paper names as the
+ * natural extension, Sec. 4) ====
+ * The procedure of Sec. 2.4 on a fully periodic D3Q19 box with spheres of
+ * diameter d (R48):
+ *   2) per cell: n (Eq. 8's count), v_s (Eq. 8, ascending index), the solid
+ *      fraction eps_s = min(n pi d^3 / 6, pi / (3 sqrt 2)) (R45), the voidage
+ *      eps_g = 1 - eps_s, gamma (Eq. 9 at eps_s), omega (Eq. 20 at eps_g, or
+ *      omega_dense where eps_g <= 0.74);
+ *   3) Eq. 23 with the solid term of Eq. 7 on D3Q19 and the body-force source
+ *      3 w_i c_i.G; F_pg = omega gamma sum c_i Om_i (Eq. 25); the superficial
+ *      velocity of Eq. 24 with G/2, the actual gas velocity u_sup / eps_g; beta
+ *      of Eqs. 19, 21, 22 at eps_g with the slip |u_gas - v_s|; p = rho / 3;
+ *      pull streaming on the periodic box;
+ *   4) trilinear interpolation (nodes at the cell centres, s = P - 1/2) of
+ *      u_gas, eps_s, beta and grad p (central differences of p); F_pre of
+ *      Eq. 26, the cell sums of Eq. 27 in ascending index, Eq. 28 signed with
+ *      the equal split of a zero denominator (R15, R16);
+ *   5) v <- v + g_eff + (F_d - V_p grad p_k) / m, P <- P + v, periodic wrap;
+ *   6) contacts |P_i - P_j|^2 <= d^2 (minimum image, i < j), binary
+ *      collisions of Eqs. 17-18 in lexicographic order.
+ */
+typedef struct {
+  int32_t nx, ny, nz;
+  double tau, rho_g, rho_s, d, e_pp;
+  double g[3];  /* gravity on particles, before the (1 - rho_g/rho_s) factor */
+  double G[3];  /* body force on the gas per cell */
+  double omega_dense;
+  int32_t pressure_sign; /* -1 physical (R17), 0 off */
+} orc3_params;
+
+typedef struct {
+  int32_t *ncell; /* [C] */
+  double *vs;     /* [C][3] */
+  double *rho;    /* [C] */
+  double *ugas;   /* [C][3] */
+  double *fpg;    /* [C][3] */
+  double *beta;   /* [C] */
+  double *fd;     /* [N][3] */
+  double *acc;    /* [N][3] acceleration of Eq. 16 */
+  int32_t *pairs; /* [cap][2] */
+  int64_t pair_cap;
+  int64_t npairs, ncollisions; /* out */
+} orc3_out;
+
+static int64_t cell3(const orc3_params *p, int x, int y, int z) {
+  return ((int64_t)z * p->ny + y) * p->nx + x;
+}
+static int wrap_i3(int i, int n) { return ((i % n) + n) % n; }
+
+/* Per-count cell quantities in 3-D: out[0] eps_s, out[1] eps_g, out[2] gamma,
+ * out[3] omega. */
+void orc3_cell_props(const orc3_params *p, int64_t n, double *out) {
+  double es = (double)n * (PI * p->d * p->d * p->d / 6.0);
+  double cap = PI / (3.0 * sqrt(2.0));
+  if (es > cap) es = cap;
+  double eg = 1.0 - es;
+  out[0] = es;
+  out[1] = eg;
+  out[2] = orc_gamma(es, p->tau);
+  out[3] = eg > 0.74 ? orc_omega_emms(eg) : p->omega_dense;
+}
+
+/* Trilinear stencil on the periodic box: the 8 nodes around P (node (i,j,k)
+ * at the cell centre) and their weights. */
+void orc3_stencil(const orc3_params *p, const double *P, int64_t *idx, double *wt) {
+  double s[3], t[3];
+  int i0[3];
+  const int n[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a) {
+    s[a] = P[a] - 0.5;
+    double fl = floor(s[a]);
+    t[a] = s[a] - fl;
+    i0[a] = (int)fl;
+  }
+  for (int q = 0; q < 8; ++q) {
+    int ox = q & 1, oy = (q >> 1) & 1, oz = q >> 2;
+    idx[q] = cell3(p, wrap_i3(i0[0] + ox, n[0]), wrap_i3(i0[1] + oy, n[1]), wrap_i3(i0[2] + oz, n[2]));
+    wt[q] = (ox ? t[0] : 1.0 - t[0]) * (oy ? t[1] : 1.0 - t[1]) * (oz ? t[2] : 1.0 - t[2]);
+  }
+}
+
+double orc3_interp(const orc3_params *p, const double *q, const double *P) {
+  int64_t idx[8];
+  double wt[8];
+  orc3_stencil(p, P, idx, wt);
+  double v = 0.0;
+  for (int k = 0; k < 8; ++k) v += wt[k] * q[idx[k]];
+  return v;
+}
+
+static void sep3(const orc3_params *p, const double *a, const double *b, double *d) {
+  const int n[3] = {p->nx, p->ny, p->nz};
+  for (int k = 0; k < 3; ++k) {
+    double x = a[k] - b[k];
+    if (x > 0.5 * n[k])
+      x -= n[k];
+    else if (x < -0.5 * n[k])
+      x += n[k];
+    d[k] = x;
+  }
+}
+
+static int in_contact3(const orc3_params *p, const double *a, const double *b) {
+  double d[3];
+  sep3(p, a, b, d);
+  return d[0] * d[0] + d[1] * d[1] + d[2] * d[2] <= p->d * p->d;
+}
+
+int orc3_contacts_brute(const orc3_params *p, int64_t np, const double *pos, int32_t *pairs, int64_t cap,
+                        int64_t *npairs) {
+  int64_t m = 0;
+  for (int64_t i = 0; i < np; ++i)
+    for (int64_t j = i + 1; j < np; ++j)
+      if (in_contact3(p, pos + 3 * i, pos + 3 * j)) {
+        if (m >= cap) {
+          *npairs = m;
+          return ORC_E_CAPACITY;
+        }
+        pairs[2 * m] = (int32_t)i;
+        pairs[2 * m + 1] = (int32_t)j;
+        ++m;
+      }
+  *npairs = m;
+  return ORC_OK;
+}
+
+/* The same set through 1-cell bins: a partner lies in one of the 27 cells
+ * around a particle (d < 1); lexicographic order. */
+int orc3_contacts_cells(const orc3_params *p, int64_t np, const double *pos, int32_t *pairs, int64_t cap,
+                        int64_t *npairs) {
+  const int64_t C = (int64_t)p->nx * p->ny * p->nz;
+  int32_t *cell = (int32_t *)malloc((size_t)(np > 0 ? np : 1) * sizeof(int32_t));
+  int64_t *start = (int64_t *)malloc((size_t)(C + 1) * sizeof(int64_t));
+  int64_t *list = (int64_t *)malloc((size_t)(np > 0 ? np : 1) * sizeof(int64_t));
+  for (int64_t k = 0; k < np; ++k)
+    cell[k] = (int32_t)cell3(p, (int)floor(pos[3 * k]), (int)floor(pos[3 * k + 1]), (int)floor(pos[3 * k + 2]));
+  bucket(C, np, cell, start, list);
+  int64_t m = 0;
+  int rc = ORC_OK;
+  for (int64_t i = 0; i < np && rc == ORC_OK; ++i) {
+    int cx = (int)floor(pos[3 * i]), cy = (int)floor(pos[3 * i + 1]), cz = (int)floor(pos[3 * i + 2]);
+    /* distinct neighbour cells only (a box narrower than 3 cells repeats them) */
+    int64_t seen[27];
+    int nseen = 0;
+    for (int oz = -1; oz <= 1; ++oz)
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          int64_t c = cell3(p, wrap_i3(cx + ox, p->nx), wrap_i3(cy + oy, p->ny), wrap_i3(cz + oz, p->nz));
+          int dup = 0;
+          for (int q = 0; q < nseen; ++q) dup |= seen[q] == c;
+          if (dup) continue;
+          seen[nseen++] = c;
+          for (int64_t s = start[c]; s < start[c + 1] && rc == ORC_OK; ++s) {
+            int64_t j = list[s];
+            if (j <= i || !in_contact3(p, pos + 3 * i, pos + 3 * j)) continue;
+            if (m >= cap) {
+              rc = ORC_E_CAPACITY;
+              break;
+            }
+            pairs[2 * m] = (int32_t)i;
+            pairs[2 * m + 1] = (int32_t)j;
+            ++m;
+          }
+        }
+  }
+  qsort(pairs, (size_t)m, 2 * sizeof(int32_t), cmp_pair);
+  *npairs = m;
+  free(cell);
+  free(start);
+  free(list);
+  return rc;
+}
+
+/* Eqs. 17-18 for spheres in 3-D over the pairs in order, current velocities;
+ * a pair collides only if (P_1 - P_2).(v_1 - v_2) < 0. */
+void orc3_resolve(const orc3_params *p, const double *pos, double *vel, const int32_t *pairs, int64_t npairs,
+                  int64_t *ncoll) {
+  double m1 = p->rho_s * PI * p->d * p->d * p->d / 6.0, m2 = m1;
+  int64_t nc = 0;
+  for (int64_t q = 0; q < npairs; ++q) {
+    int64_t i = pairs[2 * q], j = pairs[2 * q + 1];
+    double d[3];
+    sep3(p, pos + 3 * i, pos + 3 * j, d);
+    double dv[3] = {vel[3 * i] - vel[3 * j], vel[3 * i + 1] - vel[3 * j + 1], vel[3 * i + 2] - vel[3 * j + 2]};
+    double dot = dv[0] * d[0] + dv[1] * d[1] + dv[2] * d[2];
+    if (!(dot < 0.0)) continue;
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double q0 = (1.0 + p->e_pp) * dot / r2;
+    double ci = q0 * m2 / (m1 + m2), cj = q0 * m1 / (m1 + m2);
+    for (int a = 0; a < 3; ++a) {
+      vel[3 * i + a] = vel[3 * i + a] - ci * d[a];
+      vel[3 * j + a] = vel[3 * j + a] + cj * d[a];
+    }
+    ++nc;
+  }
+  if (ncoll) *ncoll = nc;
+}
+
+static double wrap3(double x, double L) {
+  if (x >= L) {
+    x -= L;
+  } else if (x < 0.0) {
+    x += L;
+    if (x >= L) x = 0.0;
+  }
+  return x;
+}
+
+int orc3_step(const orc3_params *p, double *f, int64_t np, double *pos, double *vel, orc3_out *out) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const int64_t C = (int64_t)nx * ny * nz;
+  const size_t NP = (size_t)(np > 0 ? np : 1);
+  const double vp = PI * p->d * p->d * p->d / 6.0, m = p->rho_s * vp;
+  const double mu = p->rho_g * ((p->tau - 0.5) / 3.0);
+  /* ---- 2) deposition ---- */
+  int32_t *cell = (int32_t *)malloc(NP * sizeof(int32_t));
+  int32_t *ncell = (int32_t *)calloc((size_t)C, sizeof(int32_t));
+  double *vs = (double *)calloc((size_t)(3 * C), sizeof(double));
+  for (int64_t k = 0; k < np; ++k) {
+    int ix = (int)floor(pos[3 * k]), iy = (int)floor(pos[3 * k + 1]), iz = (int)floor(pos[3 * k + 2]);
+    if (ix < 0 || ix >= nx || iy < 0 || iy >= ny || iz < 0 || iz >= nz) {
+      free(cell);
+      free(ncell);
+      free(vs);
+      return ORC_E_DOMAIN;
+    }
+    int64_t c = cell3(p, ix, iy, iz);
+    cell[k] = (int32_t)c;
+    ncell[c] += 1;
+    for (int a = 0; a < 3; ++a) vs[3 * c + a] += vel[3 * k + a];
+  }
+  for (int64_t c = 0; c < C; ++c)
+    if (ncell[c] > 0)
+      for (int a = 0; a < 3; ++a) vs[3 * c + a] = vs[3 * c + a] / ncell[c];
+  /* ---- 3) collision and streaming ---- */
+  double *fs = (double *)malloc((size_t)(19 * C) * sizeof(double));
+  double *rho = (double *)malloc((size_t)C * sizeof(double));
+  double *ug = (double *)malloc((size_t)(3 * C) * sizeof(double));
+  double *fpg = (double *)malloc((size_t)(3 * C) * sizeof(double));
+  double *beta = (double *)malloc((size_t)C * sizeof(double));
+  double *es = (double *)malloc((size_t)C * sizeof(double));
+  orc_params bp; /* the drag law's parameters (orc_beta) */
+  memset(&bp, 0, sizeof bp);
+  bp.tau = p->tau;
+  bp.rho_g = p->rho_g;
+  bp.d = p->d;
+  ORC_CELLS_PARALLEL
+  for (int64_t c = 0; c < C; ++c) {
+    double pr[4];
+    orc3_cell_props(p, ncell[c], pr);
+    const double gam = pr[2], omg = pr[3] * pr[2];
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 19; ++i) {
+      double v = f[i * C + c];
+      r += v;
+      for (int a = 0; a < 3; ++a) j[a] += C3[i][a] * v;
+    }
+    double u[3] = {j[0] / r, j[1] / r, j[2] / r};
+    const double *v = vs + 3 * c;
+    double F[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 19; ++i) {
+      int o = opp3(i);
+      double fi = f[i * C + c];
+      double om = f[o * C + c] - fi + orc3_feq(i, r, v[0], v[1], v[2]) - orc3_feq(o, r, u[0], u[1], u[2]);
+      double src = 3.0 * w3(i) * (C3[i][0] * p->G[0] + C3[i][1] * p->G[1] + C3[i][2] * p->G[2]);
+      fs[i * C + c] = fi - (1.0 - gam) / p->tau * (fi - orc3_feq(i, r, u[0], u[1], u[2])) + omg * om + src;
+      for (int a = 0; a < 3; ++a) F[a] += C3[i][a] * om;
+    }
+    double sl2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      fpg[3 * c + a] = omg * F[a];
+      double usup = (j[a] + 0.5 * fpg[3 * c + a] + 0.5 * p->G[a]) / r;
+      ug[3 * c + a] = usup / pr[1];
+      double dd = ug[3 * c + a] - v[a];
+      sl2 += dd * dd;
+    }
+    rho[c] = r;
+    es[c] = pr[0];
+    beta[c] = orc_beta(&bp, pr[1], pr[3], sqrt(sl2));
+  }
+  ORC_CELLS_PARALLEL
+  for (int64_t c = 0; c < C; ++c) {
+    int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
+    for (int i = 0; i < 19; ++i)
+      f[i * C + c] = fs[i * C + cell3(p, wrap_i3(x - C3[i][0], nx), wrap_i3(y - C3[i][1], ny),
+                                       wrap_i3(z - C3[i][2], nz))];
+  }
+  free(fs);
+  /* ---- 4) drag ---- */
+  double *gp = (double *)malloc((size_t)(3 * C) * sizeof(double));
+  ORC_CELLS_PARALLEL
+  for (int64_t c = 0; c < C; ++c) {
+    int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
+    gp[3 * c] = (rho[cell3(p, wrap_i3(x + 1, nx), y, z)] / 3.0 - rho[cell3(p, wrap_i3(x - 1, nx), y, z)] / 3.0) * 0.5;
+    gp[3 * c + 1] = (rho[cell3(p, x, wrap_i3(y + 1, ny), z)] / 3.0 - rho[cell3(p, x, wrap_i3(y - 1, ny), z)] / 3.0) * 0.5;
+    gp[3 * c + 2] = (rho[cell3(p, x, y, wrap_i3(z + 1, nz))] / 3.0 - rho[cell3(p, x, y, wrap_i3(z - 1, nz))] / 3.0) * 0.5;
+  }
+  double *comp = (double *)malloc((size_t)C * sizeof(double));
+  double *fpre = (double *)malloc(NP * 3 * sizeof(double));
+  double *gpk = (double *)malloc(NP * 3 * sizeof(double));
+  double *fcell = (double *)calloc((size_t)(3 * C), sizeof(double));
+  double *uk = (double *)malloc(NP * 3 * sizeof(double));
+  double *ek = (double *)malloc(NP * sizeof(double));
+  double *bk = (double *)malloc(NP * sizeof(double));
+  for (int a = 0; a < 3; ++a) {
+    for (int64_t c = 0; c < C; ++c) comp[c] = ug[3 * c + a];
+    for (int64_t k = 0; k < np; ++k) uk[3 * k + a] = orc3_interp(p, comp, pos + 3 * k);
+    for (int64_t c = 0; c < C; ++c) comp[c] = gp[3 * c + a];
+    for (int64_t k = 0; k < np; ++k) gpk[3 * k + a] = orc3_interp(p, comp, pos + 3 * k);
+  }
+  for (int64_t k = 0; k < np; ++k) {
+    ek[k] = orc3_interp(p, es, pos + 3 * k);
+    bk[k] = orc3_interp(p, beta, pos + 3 * k);
+  }
+  for (int64_t k = 0; k < np; ++k)
+    for (int a = 0; a < 3; ++a) {
+      fpre[3 * k + a] = vp * bk[k] / ek[k] * (uk[3 * k + a] - vel[3 * k + a]); /* Eq. 26 */
+      fcell[3 * cell[k] + a] += fpre[3 * k + a];                                /* Eq. 27 */
+    }
+  double *fd = (double *)malloc(NP * 3 * sizeof(double));
+  double *acc = (double *)malloc(NP * 3 * sizeof(double));
+  const double sgn = (double)p->pressure_sign; /* pressure force s V_p grad p, s = -1 (R17) */
+  for (int64_t k = 0; k < np; ++k)
+    for (int a = 0; a < 3; ++a) {
+      int32_t c = cell[k];
+      double den = fcell[3 * c + a], fg = fpg[3 * c + a];
+      fd[3 * k + a] = den == 0.0 ? -fg / ncell[c] : -fg * fpre[3 * k + a] / den; /* Eq. 28 */
+      double geff = (1.0 - p->rho_g / p->rho_s) * p->g[a];
+      acc[3 * k + a] = geff + (fd[3 * k + a] + sgn * vp * gpk[3 * k + a]) / m;
+    }
+  /* ---- 5) integration ---- */
+  const double L[3] = {nx, ny, nz};
+  for (int64_t k = 0; k < np; ++k)
+    for (int a = 0; a < 3; ++a) {
+      vel[3 * k + a] = vel[3 * k + a] + acc[3 * k + a];
+      pos[3 * k + a] = wrap3(pos[3 * k + a] + vel[3 * k + a], L[a]);
+    }
+  /* ---- 6) contacts and collisions ---- */
+  int64_t cap = out && out->pairs ? out->pair_cap : 0;
+  int64_t cap_eff = cap > 0 ? cap : (np * 32 + 16);
+  int32_t *pairs = out && out->pairs ? out->pairs : (int32_t *)malloc((size_t)cap_eff * 2 * sizeof(int32_t));
+  int64_t npairs = 0, ncoll = 0;
+  int rc = orc3_contacts_cells(p, np, pos, pairs, cap_eff, &npairs);
+  if (rc == ORC_OK) orc3_resolve(p, pos, vel, pairs, npairs, &ncoll);
+  if (out) {
+    if (out->ncell) memcpy(out->ncell, ncell, (size_t)C * sizeof(int32_t));
+    if (out->vs) memcpy(out->vs, vs, (size_t)(3 * C) * sizeof(double));
+    if (out->rho) memcpy(out->rho, rho, (size_t)C * sizeof(double));
+    if (out->ugas) memcpy(out->ugas, ug, (size_t)(3 * C) * sizeof(double));
+    if (out->fpg) memcpy(out->fpg, fpg, (size_t)(3 * C) * sizeof(double));
+    if (out->beta) memcpy(out->beta, beta, (size_t)C * sizeof(double));
+    if (out->fd && np > 0) memcpy(out->fd, fd, NP * 3 * sizeof(double));
+    if (out->acc && np > 0) memcpy(out->acc, acc, NP * 3 * sizeof(double));
+    out->npairs = npairs;
+    out->ncollisions = ncoll;
+  }
+  if (!(out && out->pairs)) free(pairs);
+  free(cell);
+  free(ncell);
+  free(vs);
+  free(rho);
+  free(ug);
+  free(fpg);
+  free(beta);
+  free(es);
+  free(gp);
+  free(comp);
+  free(fpre);
+  free(gpk);
+  free(fcell);
+  free(uk);
+  free(ek);
+  free(bk);
+  free(fd);
+  free(acc);
+  return rc;
+}
+
+/* FP64 conservation sums of the 3-D state: out[0] mass, out[1..3] gas
+ * momentum, out[4..6] particle momentum. */
+void orc3_conservation(const orc3_params *p, const double *f, int64_t np, const double *vel, double *out) {
+  const int64_t C = (int64_t)p->nx * p->ny * p->nz;
+  const double m = p->rho_s * PI * p->d * p->d * p->d / 6.0;
+  for (int k = 0; k < 7; ++k) out[k] = 0.0;
+  for (int64_t c = 0; c < C; ++c)
+    for (int i = 0; i < 19; ++i) {
+      double v = f[i * C + c];
+      out[0] += v;
+      for (int a = 0; a < 3; ++a) out[1 + a] += C3[i][a] * v;
+    }
+  for (int64_t k = 0; k < np; ++k)
+    for (int a = 0; a < 3; ++a) out[4 + a] += m * vel[3 * k + a];
 }

@@ -274,3 +274,45 @@ def tiny(nx: int = 16, ny: int = 24, n: int = 60, seed: int = 7, bc=("periodic",
     inlet = kw.pop("inlet_uy", np.full(nx, 0.01) if "inlet" in bc else None)
     kw.setdefault("g", (0.0, -1e-5))
     return _cfg(f"tiny-{nx}x{ny}-{n}", nx, ny, list(bc), pos, 10, vel=vel, inlet_uy=inlet, **kw)
+
+
+# ---------------------------------------------------------------- 3-D beds
+# 3-D riser: gravity along -z (the long axis), a body force on the gas balances
+# the particles' weight, every face periodic.
+RISER3_G = 2.82e-7
+
+
+def riser3d(nx: int = 256, ny: int = 256, nz: int = 1024, n: int = 10_000_000, seed: int = 5,
+            sort_ids: bool = True) -> dict:
+    """3-D riser shape: a fully periodic D3Q19 box, n spheres of d = 0.5
+    uniform in it at rest (default 256 x 256 x 1024 with 10 000 000: 0.149 per
+    cell, 3-D solid fraction 0.0098), particle gravity 2.82e-7 along -z, and
+    the gas driven along +z by the body force n m g_eff / C that balances the
+    particles' weight.  sort_ids numbers particles in cell order (z, y, x)."""
+    u = uniform(seed, 3 * n).reshape(n, 3)
+    pos = u * np.array([nx, ny, nz], np.float64)
+    if sort_ids:
+        key = (np.floor(pos[:, 2]).astype(np.int64) * ny + np.floor(pos[:, 1]).astype(np.int64)) * nx \
+            + np.floor(pos[:, 0]).astype(np.int64)
+        pos = pos[np.argsort(key, kind="stable")]
+    c = dict(DEFAULTS)
+    m = c["rho_s"] * math.pi * c["d"] ** 3 / 6
+    geff = (1 - c["rho_g"] / c["rho_s"]) * RISER3_G
+    c.update(name=f"riser3d-{nx}x{ny}x{nz}-{n}", nx=nx, ny=ny, nz=nz, pos=np.ascontiguousarray(pos),
+             vel=np.zeros_like(pos), g=(0.0, 0.0, -RISER3_G), G=(0.0, 0.0, n * m * geff / (nx * ny * nz)),
+             steps=500)
+    return c
+
+
+def tiny3d(nx: int = 6, ny: int = 5, nz: int = 7, n: int = 60, seed: int = 7, vel_scale: float = 0.0,
+           **kw) -> dict:
+    """Small periodic 3-D bed for unit and parity tests: n spheres uniform in
+    the box, velocities uniform in +-vel_scale."""
+    u = uniform(seed, 6 * n).reshape(n, 6)
+    pos = u[:, :3] * np.array([nx, ny, nz], np.float64)
+    vel = (u[:, 3:] * 2.0 - 1.0) * vel_scale
+    c = dict(DEFAULTS)
+    c.update(name=f"tiny3d-{nx}x{ny}x{nz}-{n}", nx=nx, ny=ny, nz=nz, pos=pos, vel=vel, g=(0.0, 0.0, -1e-5),
+             G=(0.0, 0.0, 0.0), steps=10)
+    c.update(kw)
+    return c
