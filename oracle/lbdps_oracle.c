@@ -1379,7 +1379,7 @@ int orc3_contacts_cells(const orc3_params *p, int64_t np, const double *pos, int
  * a pair collides only if (P_1 - P_2).(v_1 - v_2) < 0. */
 void orc3_resolve(const orc3_params *p, const double *pos, double *vel, const int32_t *pairs, int64_t npairs,
                   int64_t *ncoll) {
-  double m1 = p->rho_s * PI * p->d * p->d * p->d / 6.0, m2 = m1;
+  double m1 = p->rho_s * (PI * p->d * p->d * p->d / 6.0), m2 = m1; /* m = rho_s V_p (R19) */
   int64_t nc = 0;
   for (int64_t q = 0; q < npairs; ++q) {
     int64_t i = pairs[2 * q], j = pairs[2 * q + 1];
@@ -1584,7 +1584,7 @@ int orc3_step(const orc3_params *p, double *f, int64_t np, double *pos, double *
  * momentum, out[4..6] particle momentum. */
 void orc3_conservation(const orc3_params *p, const double *f, int64_t np, const double *vel, double *out) {
   const int64_t C = (int64_t)p->nx * p->ny * p->nz;
-  const double m = p->rho_s * PI * p->d * p->d * p->d / 6.0;
+  const double m = p->rho_s * (PI * p->d * p->d * p->d / 6.0);
   for (int k = 0; k < 7; ++k) out[k] = 0.0;
   for (int64_t c = 0; c < C; ++c)
     for (int i = 0; i < 19; ++i) {
