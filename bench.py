@@ -51,6 +51,7 @@ WORKLOADS = {
     "beds": lambda: __import__("synth").beds(64),
     "paper_bubble": lambda: __import__("synth").paper_bubble(),
     "paper_riser": lambda: __import__("synth").paper_riser(),
+    "riser3d": None,  # the 3-D coupled step: run_riser3d
     "d3q19_gas": None,  # the 3-D gas lattice alone: run_d3q19
     "d3q19_psm": None,  # the 3-D lattice with solids given per cell: run_d3q19
 }
@@ -391,6 +392,68 @@ def run_d3q19(args, torch, L):
                          "frac_of_copy": round(achieved / cb["GBs"], 4)}}
 
 
+def model_bytes_per_step_3d(prec: str, C: int, N: int, pairs: int) -> float:
+    """The whole-step byte model in 3-D: per cell 38 s_f (19 populations in
+    and out) + 22 s_c (the deposited solid velocity written and read, 3 + 3;
+    u_gas, beta, p, F_pg written by the collision and read by the drag, 8 + 8)
+    + 20 (the count written and read twice, the cell start written and read);
+    per particle 21 s_p + 16 (state read and written, 12; position read by the
+    binning and the contact search and velocity read by the deposition, 3
+    each; key and permutation); per pair 16 + 12 s_p."""
+    sf, st = SIZES[prec]
+    return C * (38 * sf + 22 * st + 20) + N * (21 * st + 16) + pairs * (16 + 12 * st)
+
+
+def run_riser3d(args, torch, L):
+    """The 3-D coupled step (config: D3Q19 256 x 256 x 1024, 10 000 000 spheres
+    of d = 0.5, periodic, gravity-driven riser, FP16 deviation storage with
+    FP32 arithmetic by default): MLUPS, particle updates/s and the whole-step
+    model bandwidth."""
+    import synth
+    prec = args.precision if args.precision_given else "fp16"
+    cfg = synth.riser3d()
+    C, N = cfg["nx"] * cfg["ny"] * cfg["nz"], len(cfg["pos"])
+    sim = L.Sim3(cfg, precision=prec)
+    st = sim.stream
+    sim.step(args.warmup)
+    ms = time_region(torch, st, lambda: sim.step(args.steps))
+    pairs = sim.counters()["pairs"]
+    sim.close()
+    del sim
+    s = ms / 1e3
+    model = model_bytes_per_step_3d(prec, C, N, pairs)
+    bw = model * args.steps / s / 1e9
+    line = {"metric": METRIC, "value": round(C * args.steps / s / 1e6, 2), "unit": "MLUPS", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)", "bf16": "f32 (bf16 storage)"}[prec],
+            "data": "synthetic (seeded splitmix64 spheres, gas at rest)",
+            "config": {"workload": f"riser3d-{cfg['nx']}x{cfg['ny']}x{cfg['nz']}-{N}-{prec}", "nx": cfg["nx"],
+                       "ny": cfg["ny"], "nz": cfg["nz"], "particles": N, "precision": prec, "d_p": cfg["d"],
+                       "tau": cfg["tau"], "solid_fraction_3d": round(N * math.pi * cfg["d"] ** 3 / 6 / C, 5)},
+            "particle_updates_per_s": float(f"{N * args.steps / s:.4e}"),
+            "model_bytes_per_step": int(model), "model_bw_frac": round(bw / HBM_PEAK_GBS, 4),
+            "contact_pairs": int(pairs),
+            "roofline": {"bound": "hbm", "kernel": "step", "achieved": round(bw, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(bw / HBM_PEAK_GBS, 4), "traffic": None,
+                         "bytes_per_launch": int(model), "us_per_launch": round(ms / args.steps * 1e3, 3)}}
+    if not args.no_cpu_baseline:
+        import oracle
+        sub = synth.riser3d(64, 64, 64, int(round(N * 64 ** 3 / C)), seed=5)
+        o = oracle.Sim3(sub, omp=True)
+        t0, k = time.perf_counter(), 0
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            o.step()
+            k += 1
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = dict(value=round(64 ** 3 * k / dt / 1e6, 4), unit="MLUPS",
+                                    cores=oracle.threads(omp=True), kind="oracle",
+                                    sample=f"a 64 x 64 x 64 box at the same density ({len(sub['pos'])} spheres), "
+                                           f"{k} coupled steps from rest, FP64, per-cell loops on OpenMP threads "
+                                           f"({dt:.1f} s)")
+    return line
+
+
 def run_beds(args, torch, L):
     """The batching workload: one JSON line (see the module docstring)."""
     cfgs = WORKLOADS["beds"]()
@@ -434,17 +497,27 @@ def run_beds(args, torch, L):
     pairs = [b.counters()["pairs"] for b in batch.beds]
     batch.close()
     del batch
-    sims = [L.Sim(c, precision="fp32") for c in cfgs]
-    for sm in sims:
-        sm.step(args.warmup)
-
-    def sequential():
+    def sequential_ms(p):
+        """The same beds stepped one after another through the single-bed path
+        in storage precision p (each bed autotuned as the batch was)."""
+        sims = [L.Sim(c, precision=p) for c in cfgs]
         for sm in sims:
-            sm.step(K)
+            sm.step(args.warmup)
+            sm.autotune(2)
+            sm.set_state(None, sm.cfg["pos"], sm.cfg["vel"])
+            sm.step(args.warmup)
 
-    ms_seq = time_region(torch, torch.cuda.current_stream(), sequential)
-    for sm in sims:
-        sm.close()
+        def sequential():
+            for sm in sims:
+                sm.step(K)
+
+        ms = time_region(torch, torch.cuda.current_stream(), sequential)
+        for sm in sims:
+            sm.close()
+        return ms
+
+    ms_seq = sequential_ms("fp32")
+    ms_seq_same = sequential_ms(prec)
     s = ms_graph / 1e3
     dom_us = kt[0] / max(kt[1], 1) * 1e3
     dom_bytes = sum(model_kernel_bytes(dom, prec, C, N, pr) for C, N, pr in zip(Cs, Ns, pairs))
@@ -476,6 +549,9 @@ def run_beds(args, torch, L):
         "graph_first_replay_ms_per_step": round(ms_first / K, 5),
         "sequential_fp32_ms_per_step": round(ms_seq / K, 5),
         "speedup_vs_sequential_fp32": round(ms_seq / ms_graph, 3),
+        f"sequential_{prec}_ms_per_step": round(ms_seq_same / K, 5),
+        f"speedup_vs_sequential_{prec}": round(ms_seq_same / ms_graph, 3),
+        "drag_tile": sorted({t["drag_tile"] for t in tunings}),
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -539,6 +615,9 @@ def main():
         return
     from paper_1303_2653_amd import lbdps as L
 
+    if args.workload == "riser3d":
+        print(json.dumps(run_riser3d(args, torch, L)), flush=True)
+        return
     if args.workload in ("d3q19_gas", "d3q19_psm"):
         print(json.dumps(run_d3q19(args, torch, L)), flush=True)
         return

@@ -231,6 +231,21 @@ lbdps_status lbdps_conservation_noalloc(lbdps_ctx *ctx, double h_out[6]);
 lbdps_status lbdps_counters(lbdps_ctx *ctx, int64_t h_out[4]);
 
 /*
+ * Outlet solids flux (Sec. 3.2, the solids flux at the riser's outlet): the
+ * net number of particles that crossed the outlet plane y = ny upward since
+ * the previous call (or since lbdps_set_state), and the number of steps taken
+ * meanwhile.  A crossing is counted in the move of Eq. 16 (every sub-step)
+ * where a particle periodic in y (lbdps_params.particles_periodic_y, the
+ * circulating loop, or a y-periodic bed) ends at or beyond y = ny (+1, it
+ * re-enters at the bottom) or below y = 0 (-1); with particle walls in y
+ * nothing crosses.  The solids mass flux through the outlet is then
+ *   G_s = m h_net / (nx h_steps),  m = rho_s pi d^3 / 6,
+ * mass per unit width (unit depth) per unit time in lattice units.
+ * Synchronises the stream.
+ */
+lbdps_status lbdps_outlet_crossings(lbdps_ctx *ctx, int64_t *h_net, int64_t *h_steps);
+
+/*
  * Replace the inlet profile used by INLET faces (Sec. 3.1: the gas pulse of the
  * bubble experiment is switched off this way).  h_inlet_uy: host array of nx
  * finite y velocities, read before return.  Waits for the context's queued work
@@ -258,12 +273,12 @@ lbdps_status lbdps_voidage(lbdps_ctx *ctx, int32_t y0, int32_t y1, double thresh
 
 /*
  * The 3-D gas lattice, first piece of the 3-D extension (the paper names 3-D
- * as future work): one BGK collide-stream step (the 3-D form of Eq. 1, no
+ * as future work): one BGK collide-stream step (the 3-D form of Eqs. 2-3, no
  * particles) of the D3Q19 lattice on a periodic nx x ny x nz box.  D3Q19: the
  * rest velocity (weight 1/3), the 6 face neighbours (1/18) and the 12 edge
  * neighbours (1/36) in the order rest, +x, -x, +y, -y, +z, -z, (+x+y),
  * (-x-y), (+x-y), (-x+y), (+x+z), (-x-z), (+x-z), (-x+z), (+y+z), (-y-z),
- * (+y-z), (-y+z); f^eq of Eq. 2 with c_s^2 = 1/3.
+ * (+y-z), (-y+z); f^eq of Eq. 4 with c_s^2 = 1/3.
  *   d_fin, d_fout: distinct device buffers [19][nz][ny][nx] in the storage of
  *   precision (lbdps_precision): FP64 values, or the deviations f_i - w_i as
  *   FP32, FP16 or BF16 with FP32 arithmetic.  The caller owns both.
@@ -299,6 +314,76 @@ lbdps_status lbdps3_psm_step(const void *d_fin, void *d_fout, const int32_t *d_n
                              int32_t nx, int32_t ny, int32_t nz, double tau, double d, int32_t precision,
                              void *stream);
 
+/* ------------------------------------------------------------- the 3-D coupled step
+ * The procedure of Sec. 2.4 on a fully periodic D3Q19 box with spheres (the
+ * fully 3-D simulation the paper names as the natural extension): per cell
+ * the count n and the mean velocity v_s of its spheres (Eq. 8, summed in
+ * ascending particle index), the solid fraction n pi d^3 / 6 held at the
+ * densest sphere packing pi / (3 sqrt 2), the voidage eps_g = 1 - eps_s,
+ * gamma of Eq. 9, omega of Eq. 20 at eps_g (omega_dense where eps_g <= 0.74);
+ * the collision of Eq. 23 with the solid term of Eq. 7 and the body-force
+ * source 3 w_i c_i.G, F_pg of Eq. 25, the superficial velocity of Eq. 24, the
+ * gas velocity u_sup / eps_g, beta of Eqs. 19, 21, 22 at eps_g; trilinear
+ * interpolation (nodes at the cell centres) of u_gas, eps_s, beta and grad p
+ * for Eqs. 26-28; Eq. 16 with periodic wrap; contacts |P_i - P_j| <= d and
+ * the binary collisions of Eqs. 17-18 in lexicographic order.  D3Q19
+ * directions and weights as for lbdps3_bgk_step.  Same conventions as the
+ * 2-D context: the caller's workspace, canonical FP64 in and out, errors
+ * latched on the device and returned by the next synchronising call.
+ */
+typedef struct {
+  int32_t nx, ny, nz;         /* periodic box, each >= 3, nx ny nz < 2^28            */
+  double tau;                 /* relaxation time (Eq. 3), > 0.5                      */
+  double rho_g, rho_s;        /* gas density in the drag laws, solid density, > 0    */
+  double d_p;                 /* sphere diameter in cells, [0.1, 1)                  */
+  double e_pp;                /* restitution of Eqs. 17-18, [0, 1]                    */
+  double g[3];                /* gravity on particles (the library applies 1 - rho_g/rho_s) */
+  double body_force[3];       /* force per cell on the gas                           */
+  double omega_dense;         /* omega where eps_g <= 0.74                           */
+  int32_t pressure_force_sign; /* s of the s V_p grad p term of Eq. 16: -1, 0, +1     */
+  int32_t precision;          /* lbdps_precision                                      */
+  int32_t diagnostics;        /* 1: record per-cell counts, drags and accelerations   */
+} lbdps3_params;
+
+typedef struct lbdps3_ctx lbdps3_ctx;
+
+/* Device-free checks; LBDPS_E_SHAPE for sizes out of range, LBDPS_E_INVALID else. */
+lbdps_status lbdps3_validate_params(const lbdps3_params *p, int64_t max_particles);
+/* Workspace size of a 3-D context for up to max_particles spheres.  Device-free. */
+lbdps_status lbdps3_workspace_bytes(const lbdps3_params *p, int64_t max_particles, size_t *bytes);
+/* Create on the current device with the caller's workspace (256-byte aligned)
+ * and stream; the state starts as f = f^eq(1, 0), no spheres. */
+lbdps_status lbdps3_create(const lbdps3_params *p, int64_t max_particles, void *d_workspace, size_t bytes,
+                           void *stream, lbdps3_ctx **out);
+/* Replace the state: d_f device [19][nz][ny][nx] FP64 or NULL for f^eq(1, 0);
+ * d_pos, d_vel device [n][3] FP64 in particle-index order, positions in the
+ * box (a position outside is reported as LBDPS_E_INVALID by the next
+ * synchronising call).  Reduced precisions round to the internal storage. */
+lbdps_status lbdps3_set_state(lbdps3_ctx *ctx, const double *d_f, const double *d_pos, const double *d_vel,
+                              int64_t n);
+/* Enqueue nsteps coupled steps.  Asynchronous. */
+lbdps_status lbdps3_step(lbdps3_ctx *ctx, int32_t nsteps);
+/* Canonical FP64 state: populations [19][nz][ny][nx], positions and
+ * velocities [n][3] in index order.  Any pointer may be NULL.  Synchronises. */
+lbdps_status lbdps3_get_state(lbdps3_ctx *ctx, double *d_f, double *d_pos, double *d_vel);
+/* Node fields of the most recent step, device FP64 [nz][ny][nx] (vectors
+ * [nz][ny][nx][3]): rho, u_gas, F_pg, beta, and with diagnostics the count
+ * n_tot (int32).  Any pointer may be NULL.  Synchronises. */
+lbdps_status lbdps3_get_fields(lbdps3_ctx *ctx, double *d_rho, double *d_ugas, double *d_fpg, double *d_beta,
+                               int32_t *d_ncell);
+/* With diagnostics: the corrected drag of Eq. 28 and the acceleration of
+ * Eq. 16 of the most recent step, device FP64 [n][3] by particle index.
+ * Synchronises. */
+lbdps_status lbdps3_get_drag(lbdps3_ctx *ctx, double *d_fd, double *d_acc);
+/* Contact pairs (i, j), i < j, of the most recent step in lexicographic order,
+ * as lbdps_get_pairs.  Synchronises. */
+lbdps_status lbdps3_get_pairs(lbdps3_ctx *ctx, int32_t *d_pairs, int64_t cap, int64_t *n_out);
+/* h_out[0] contact pairs, h_out[1] pairs that collided in the most recent
+ * step.  Synchronises. */
+lbdps_status lbdps3_counters(lbdps3_ctx *ctx, int64_t h_out[2]);
+/* Release the host context (the workspace stays the caller's). */
+lbdps_status lbdps3_destroy(lbdps3_ctx *ctx);
+
 /* Kernels of one step, for per-kernel timing. */
 typedef enum {
   LBDPS_K_COLLIDE = 0,    /* deposition + collision + streaming                     */
@@ -333,7 +418,9 @@ lbdps_status lbdps_kernel_times(lbdps_ctx *ctx, double *h_ms, int64_t *h_launche
  *                      workgroup of the cluster resolution, [1, 256] (default 1);
  *   cluster_groups_max most workgroups of the cluster resolution (default: no
  *                      limit);
- *   drag_tile          drag tile shape: 0 = 32 x 8 cells (the only one built).
+ *   drag_tile          cells of the drag kernel's workgroup tile (its node fields
+ *                      staged in LDS): 0 = 32 x 8 (default), 1 = 64 x 4,
+ *                      2 = 128 x 2.  The beds of a batch share one.
  * A context starts with the defaults.
  */
 typedef struct {
@@ -347,8 +434,9 @@ lbdps_status lbdps_get_tuning(lbdps_ctx *ctx, lbdps_tuning *t);
 /* Autotuner: run `steps` steps under each candidate launch shape, twice over
  * the candidates in turn, time them with hipEvents on the context's stream and
  * keep the candidate with the fastest of its two times (written to *chosen if
- * not NULL).  The bed advances by 2 x steps x (number of candidates).
- * Synchronises. */
+ * not NULL): first the cluster-resolution shapes (9 candidates), then the drag
+ * tile shapes (3) under the chosen one.  The bed advances by
+ * 2 x steps x 12.  Synchronises. */
 lbdps_status lbdps_autotune(lbdps_ctx *ctx, int32_t steps, lbdps_tuning *chosen);
 
 /* Release the host context (the workspace stays the caller's).  A bed of a
@@ -411,13 +499,15 @@ lbdps_status lbdps_batch_kernel_times(lbdps_batch *batch, double *h_ms, int64_t 
 
 /*
  * Autotuner of a batch: beds are grouped into size classes by particle count
- * (up to 2048, 4096, 8192, ...).  Class by class, every candidate launch shape
- * is applied to the class's beds and `steps` batched steps are timed, twice
- * over the candidates in turn; the candidate with the fastest of its two times
- * is kept.  Every bed advances by the steps taken.  cache_path (or
- * NULL): a text file of chosen shapes per class and precision; classes found
- * there are not timed again, and the file is rewritten with all classes.
- * Synchronises.
+ * (up to 2048, 4096, 8192, ...).  Class by class, every candidate
+ * cluster-resolution shape is applied to the class's beds and `steps` batched
+ * steps are timed, twice over the candidates in turn; the candidate with the
+ * fastest of its two times is kept.  Then the drag tile shapes are timed the
+ * same way on the whole batch (one drag launch covers every bed, so the beds
+ * share the fastest).  Every bed advances by the steps taken.  cache_path (or
+ * NULL): a text file of chosen shapes per class and precision; when every
+ * class is found there nothing is timed, and the file is rewritten with all
+ * classes.  Synchronises.
  */
 lbdps_status lbdps_batch_autotune(lbdps_batch *batch, int32_t steps, const char *cache_path);
 

@@ -66,19 +66,19 @@ __global__ __launch_bounds__(BLOCK) void kb_collide(const BedArgs<P> *__restrict
                   nullptr);
 }
 
-template <int P>
+template <int P, int TX>
 __global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void kb_drag(const BedArgs<P> *__restrict__ tab,
                                                               const int *__restrict__ off, int nbeds, int flip) {
   LBDPS_BED_PROLOGUE(XCD_RUN_DRAG)
-  drag_body_cells<P>(bid, nbk, a.parts(cp), a.fl, a.cs, a.lut, a.k, a.count, a.rank, a.flags, nullptr, nullptr,
-                     nullptr, a.ts, a.stay);
+  drag_body_cells<P, TX>(bid, nbk, a.parts(cp), a.fl, a.cs, a.lut, a.k, a.count, a.rank, a.flags, nullptr, nullptr,
+                         nullptr, a.ts, a.stay);
 }
-template <int P>
+template <int P, int TX>
 __global__ __launch_bounds__(BLOCK) LBDPS_WAVES6 void kb_drag_flat(const BedArgs<P> *__restrict__ tab, const int *__restrict__ off,
                                                       int nbeds, int flip) {
   LBDPS_BED_PROLOGUE(XCD_RUN_DRAG)
-  drag_body_flat<P>(bid, nbk, a.parts(cp), a.fl, a.cs, a.lut, a.k, a.count, a.rank, a.flags, nullptr, nullptr,
-                    nullptr, a.ts, a.stay);
+  drag_body_flat<P, TX>(bid, nbk, a.parts(cp), a.fl, a.cs, a.lut, a.k, a.count, a.rank, a.flags, nullptr, nullptr,
+                        nullptr, a.ts, a.stay);
 }
 
 template <int P>

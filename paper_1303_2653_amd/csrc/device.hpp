@@ -168,6 +168,8 @@ template <class T> struct Consts {
   T h;          // particle sub-step length, 1 / n_sub
   T *acx, *acy; // accelerations held over the lattice step by particle index (n_sub > 1), else null
   unsigned spin_limit;
+  int32_t *flags;                // the context's latched device error flags
+  unsigned long long *cross;     // running net count of particles across y = ny upward (outlet flux)
 };
 
 // Cell row of a key: key / nx by one multiplication and shift.  With

@@ -135,10 +135,13 @@ template <int P> struct Pos {
 
   // Move by v (P <- P + v), then periodic wrap or wall mirror.  Returns the new
   // cell key, or -1 if the result is not a valid cell (NaN, or a jump across
-  // the whole domain).
-  __device__ static int move(const Consts<T> &k, int cx, int cy, T &x, T &y, T vx, T vy) {
+  // the whole domain).  wy: +1 if a move periodic in y ended at or beyond
+  // y = ny (wrapped to the bottom), -1 if it ended below 0, else 0.
+  __device__ static int move(const Consts<T> &k, int cx, int cy, T &x, T &y, T vx, T vy, int &wy) {
+    wy = 0;
     if constexpr (G) {
       T X = x + vx, Y = y + vy;
+      if (k.per_y) wy = Y >= (T)k.ny ? 1 : (Y < (T)0 ? -1 : 0);
       X = k.per_x ? wrap_c(X, (T)k.nx) : mirror_c(X, (T)k.nx);
       Y = k.per_y ? wrap_c(Y, (T)k.ny) : mirror_c(Y, (T)k.ny);
       x = X;
@@ -150,6 +153,7 @@ template <int P> struct Pos {
       T ox = x + vx, oy = y + vy;
       renorm(ox, cx);
       renorm(oy, cy);
+      if (k.per_y) wy = cy >= k.ny ? 1 : (cy < 0 ? -1 : 0);
       if (!axis(cx, ox, k.nx, k.per_x) || !axis(cy, oy, k.ny, k.per_y)) return -1;
       x = ox;
       y = oy;
@@ -311,6 +315,10 @@ constexpr int CONTACT_CH = 4;                 // candidate positions loaded toge
 constexpr int CONTACT_W = 2;                  // slots each side of a particle loaded before its cell starts
 constexpr int CONTACT_W_SMALL = 3;            // the same for grids that fit on the chip at six waves per SIMD
 constexpr int RES_ITEMS = 8;                  // particle indices per lane and resolution chunk
+// done[] of a particle whose whole cluster the cluster kernel resolved (its
+// pairs and its wall pass): the ordered sweep leaves it alone.  A particle of
+// a cluster left to the sweep keeps the plain count of its finished pairs.
+constexpr int DONE_WHOLE = 1 << 30;
 constexpr int RES_CHUNK = BLOCK * RES_ITEMS;  // particle indices per chunk
 
 // Block-wide exclusive scan of one int per thread; total = block sum.
@@ -677,7 +685,9 @@ __device__ __forceinline__ int advance_one(const Consts<typename Prec<P>::T> &k,
                                            typename Prec<P>::T ax, typename Prec<P>::T ay, int32_t *flags) {
   vx = vx + ax * k.h;
   vy = vy + ay * k.h;
-  int nk = Pos<P>::move(k, cx, cy, x, y, vx * k.h, vy * k.h);
+  int wy;
+  int nk = Pos<P>::move(k, cx, cy, x, y, vx * k.h, vy * k.h, wy);
+  if (wy) atomicAdd(k.cross, (unsigned long long)(long long)wy);  // two's complement: -1 subtracts one
   if (nk < 0) {
     atomicOr(&flags[FLAG_DOMAIN], 1);
     nk = c;
@@ -698,16 +708,25 @@ __device__ __forceinline__ int advance_one(const Consts<typename Prec<P>::T> &k,
 // Eq. 16 (symplectic Euler), moves, wraps or mirrors, and counts the particle
 // into its new cell for the next binning.
 // Node fields a workgroup's particles interpolate from, staged in LDS: the
-// workgroup covers a DTX x DTY tile of cells, and its particles' bilinear
-// stencils reach one node beyond it on every side.  Each slot holds the value
-// at the wrapped (periodic) or clamped (wall) node, and the node's pressure
-// gradient is formed from the node's own neighbours as in the global field.
-constexpr int DTX = 32, DTY = 8;
-constexpr int DSX = DTX + 2, DSY = DTY + 2, DSN = DSX * DSY;
+// workgroup covers a TX x TY tile of cells (TX TY = BLOCK), and its particles'
+// bilinear stencils reach one node beyond it on every side.  Each slot holds
+// the value at the wrapped (periodic) or clamped (wall) node, and the node's
+// pressure gradient is formed from the node's own neighbours as in the global
+// field.  Three tile shapes are built, 32 x 8, 64 x 4 and 128 x 2 (the
+// tuning's drag_tile 0, 1, 2); every result is the same bit for bit, only the
+// halo (the staged nodes per cell) and the length of each row's contiguous run
+// of particle slots differ.
+constexpr int DRAG_TILES = 3;
+__host__ __device__ constexpr int drag_tile_w(int t) { return t == 1 ? 64 : (t == 2 ? 128 : 32); }
+template <int TX> struct TileDims {
+  static_assert(BLOCK % TX == 0, "a tile holds BLOCK cells");
+  static constexpr int TY = BLOCK / TX, SX = TX + 2, SY = TY + 2, SN = SX * SY;
+};
 constexpr int HIST_MAX = 32;
 
-template <int P> struct DragTile {
+template <int P, int TX> struct DragTile {
   using T = typename Prec<P>::T;
+  static constexpr int DTX = TX, DTY = TileDims<TX>::TY, DSX = TileDims<TX>::SX, DSN = TileDims<TX>::SN;
   T ux[DSN], uy[DSN], es[DSN], beta[DSN], gpx[DSN], gpy[DSN];
 
   // A thread's share of the tile (slots threadIdx.x + r BLOCK), fetched into
@@ -775,7 +794,9 @@ template <int P> struct Interp {
   using T = typename Prec<P>::T;
   T ux, uy, es, beta, gpx, gpy;
 
-  __device__ void at(const Consts<T> &k, const DragTile<P> &D, int tx0, int ty0, int cx, int cy, T x, T y) {
+  template <int TX>
+  __device__ void at(const Consts<T> &k, const DragTile<P, TX> &D, int tx0, int ty0, int cx, int cy, T x, T y) {
+    constexpr int DSX = TileDims<TX>::SX;
     int i0, j0;
     T tx, ty;
     Pos<P>::stencil(k, cx, cy, x, y, i0, j0, tx, ty);
@@ -793,7 +814,7 @@ template <int P> struct Interp {
 
 // Workgroup = one DTX x DTY tile of cells, one thread per cell (its particles
 // in registers up to SEG_REG of them, in two passes over memory beyond).
-template <int P>
+template <int P, int DTX>
 __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
     Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs, const typename Prec<P>::T *__restrict__ lut,
     Consts<typename Prec<P>::T> k, int32_t *__restrict__ count, int32_t *__restrict__ rank, int32_t *flags,
@@ -802,7 +823,8 @@ __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, 
   using T = typename Prec<P>::T;
   __shared__ long long sh[BLOCK / 64];
   __shared__ int hist[HIST_MAX];
-  __shared__ DragTile<P> D;
+  constexpr int DTY = TileDims<DTX>::TY;
+  __shared__ DragTile<P, DTX> D;
   const int ntx = (k.nx + DTX - 1) / DTX;
   const int tx0 = (bidx % ntx) * DTX, ty0 = (bidx / ntx) * DTY;
   const int cx = tx0 + (int)threadIdx.x % DTX, cy = ty0 + (int)threadIdx.x / DTX;
@@ -810,8 +832,8 @@ __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, 
   const bool inside = cx < k.nx && cy < k.ny;
   const int a0 = inside ? cs[c] : 0, a1 = inside ? cs[c + 1] : 0;
   const int n = a1 - a0;
-  typename DragTile<P>::Regs tile_regs;
-  DragTile<P>::fetch(k, fl, tx0, ty0, tile_regs);
+  typename DragTile<P, DTX>::Regs tile_regs;
+  DragTile<P, DTX>::fetch(k, fl, tx0, ty0, tile_regs);
   // a tile without particles has nothing to do
   if (!__syncthreads_or(n > 0)) {
     if (inside) stay[c] = 0;
@@ -948,7 +970,7 @@ __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, 
 // holding more than DR_PT BLOCK particles runs one thread per cell instead.
 constexpr int DR_PT = 3, DR_CAP = DR_PT * BLOCK;
 
-template <int P>
+template <int P, int DTX>
 __device__ __forceinline__ void drag_body_flat(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
     Fields<typename Prec<P>::T> fl, const int32_t *__restrict__ cs, const typename Prec<P>::T *__restrict__ lut,
     Consts<typename Prec<P>::T> k, int32_t *__restrict__ count, int32_t *__restrict__ rank, int32_t *flags,
@@ -958,7 +980,8 @@ __device__ __forceinline__ void drag_body_flat(const int bidx, const int gdim, P
   __shared__ long long sh[BLOCK / 64];
   __shared__ int shi[BLOCK / 64];
   __shared__ int hist[HIST_MAX];
-  __shared__ DragTile<P> D;
+  constexpr int DTY = TileDims<DTX>::TY;
+  __shared__ DragTile<P, DTX> D;
   __shared__ int f_off[BLOCK + 1];   // first flat index of each cell's particles
   __shared__ int f_base[BLOCK];      // slot of flat index j of cell i: f_base[i] + j
   __shared__ short f_cell[DR_CAP];   // cell of each flat index
@@ -971,8 +994,8 @@ __device__ __forceinline__ void drag_body_flat(const int bidx, const int gdim, P
   const bool inside = cx < k.nx && cy < k.ny;
   const int a0 = inside ? cs[c] : 0, a1 = inside ? cs[c + 1] : 0;
   const int n = a1 - a0;
-  typename DragTile<P>::Regs tile_regs;
-  DragTile<P>::fetch(k, fl, tx0, ty0, tile_regs);
+  typename DragTile<P, DTX>::Regs tile_regs;
+  DragTile<P, DTX>::fetch(k, fl, tx0, ty0, tile_regs);
   // a tile without particles has nothing to do
   if (!__syncthreads_or(n > 0)) {
     if (inside) stay[c] = 0;
@@ -1149,7 +1172,7 @@ __device__ __forceinline__ void drag_body_flat(const int bidx, const int gdim, P
 // barriers lengthen it); the flat form for larger grids, where the even
 // per-thread work pays: 22 % faster on a 16 M-particle bed, 16 % on a batch of
 // 64 uneven beds.
-template <int P>
+template <int P, int TX>
 __global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void k_drag(Parts<typename Prec<P>::T> pt,
                                                              Fields<typename Prec<P>::T> fl,
                                                              const int32_t *__restrict__ cs,
@@ -1159,10 +1182,10 @@ __global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void k_drag(Parts<typename Prec
                                                              int32_t *flags, typename Prec<P>::T *dg_fdx,
                                                              typename Prec<P>::T *dg_fdy, long long *zero_part,
                                                              TileSums ts, int32_t *__restrict__ stay) {
-  drag_body_cells<P>(xcd_block<XCD_RUN_DRAG>(blockIdx.x, gridDim.x), gridDim.x, pt, fl, cs, lut, k, count, rank,
-                     flags, dg_fdx, dg_fdy, zero_part, ts, stay);
+  drag_body_cells<P, TX>(xcd_block<XCD_RUN_DRAG>(blockIdx.x, gridDim.x), gridDim.x, pt, fl, cs, lut, k, count, rank,
+                         flags, dg_fdx, dg_fdy, zero_part, ts, stay);
 }
-template <int P>
+template <int P, int TX>
 __global__ __launch_bounds__(BLOCK) LBDPS_WAVES6 void k_drag_flat(Parts<typename Prec<P>::T> pt, Fields<typename Prec<P>::T> fl,
                                                      const int32_t *__restrict__ cs,
                                                      const typename Prec<P>::T *__restrict__ lut,
@@ -1171,8 +1194,8 @@ __global__ __launch_bounds__(BLOCK) LBDPS_WAVES6 void k_drag_flat(Parts<typename
                                                      typename Prec<P>::T *dg_fdx, typename Prec<P>::T *dg_fdy,
                                                      long long *zero_part, TileSums ts,
                                                      int32_t *__restrict__ stay) {
-  drag_body_flat<P>(xcd_block<XCD_RUN_DRAG>(blockIdx.x, gridDim.x), gridDim.x, pt, fl, cs, lut, k, count, rank,
-                    flags, dg_fdx, dg_fdy, zero_part, ts, stay);
+  drag_body_flat<P, TX>(xcd_block<XCD_RUN_DRAG>(blockIdx.x, gridDim.x), gridDim.x, pt, fl, cs, lut, k, count, rank,
+                        flags, dg_fdx, dg_fdy, zero_part, ts, stay);
 }
 
 // Sub-steps after the first of a lattice step (n_sub > 1): one thread per
@@ -1805,7 +1828,7 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, unsigned long long
     nwall += Pos<P>::walls_key(k, ku, xu, yu, vxu, vyu);
     pt.vx[u] = vxu;
     pt.vy[u] = vyu;
-    done[u] = __builtin_popcount(nbr);  // its contacts, all inside the cluster
+    done[u] = __builtin_popcount(nbr) | DONE_WHOLE;  // its contacts, all inside the cluster
   }
 }
 
@@ -2010,7 +2033,7 @@ __device__ int resolve_group(ClusterLds<P, G> &B, int *shi, int s0, int g, const
     nwall += Pos<P>::walls_key(k, key, B.px[tid], B.py[tid], vx, vy);
     pt.vx[u] = vx;
     pt.vy[u] = vy;
-    done[u] = deg[u];
+    done[u] = deg[u] | DONE_WHOLE;
   }
   Gr::sync();
   return 0;
@@ -2042,7 +2065,10 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
   const int b0 = bidx * per;
   const int nb = max(0, min(nlists - b0, per));
   int tot;
-  const int c = (int)threadIdx.x < nb ? rcount[b0 + threadIdx.x] : 0;
+  // a contact row over its capacity leaves the contact graph incomplete: the
+  // resolution is skipped and the step reports LBDPS_E_CAPACITY
+  const bool overflow = __hip_atomic_load(&k.flags[FLAG_CAPACITY], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  const int c = (!overflow && (int)threadIdx.x < nb) ? rcount[b0 + threadIdx.x] : 0;
   const int o = block_excl_scan(c, shi, tot);
   if (tot == 0) {  // no candidate roots in these lists (uniform: the scan's total)
     if (threadIdx.x == 0) {
@@ -2135,7 +2161,9 @@ __device__ __forceinline__ void resolve_body(const int bidx, const int gdim, Par
   // Chunks of RES_CHUNK particle indices are taken in increasing order from an
   // atomic ticket; chunks that hold no particle with a contact are skipped.
   const int nchunks = (k.npart + RES_CHUNK - 1) / RES_CHUNK;
-  if (!*need_sweep) {  // every cluster was resolved whole: only clear the chunk marks
+  // every cluster was resolved whole, or a contact row overflowed (the
+  // resolution is skipped): only clear the chunk marks
+  if (!*need_sweep || __hip_atomic_load(&flags[FLAG_CAPACITY], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
     for (int i = bidx * BLOCK + threadIdx.x; i < nchunks; i += gdim * BLOCK) chunk_busy[i] = 0;
     if (threadIdx.x == 0) {
       coll_part[bidx] = 0;
@@ -2174,7 +2202,10 @@ __device__ __forceinline__ void resolve_body(const int bidx, const int gdim, Par
         }
         s = slot[g];
         dg = deg[s];
-        if (dg == 0 || done[s] == dg) continue;  // no contacts, or resolved with its cluster
+        // no contacts (wall pass in the contact kernel), or resolved whole with
+        // its cluster; a particle whose pairs the sweep's lower partners have
+        // all fired still takes its wall pass here (state 1)
+        if (dg == 0 || done[s] >= DONE_WHOLE) continue;
         row = adj.row(s);
         a = 0;
         while (a < dg && (int)(row[a] >> 32) < g) ++a;

@@ -15,6 +15,7 @@
 #include <hip/hip_ext.h>
 
 #include "batch.hpp"
+#include "coupled3d.hpp"
 #include "kernels.hpp"
 #include "lattice3d.hpp"
 #include "lbdps.h"
@@ -211,6 +212,9 @@ struct lbdps_ctx {
   int prec = 0, nx = 0, ny = 0, C = 0, nlut = 0;
   long long nmax = 0, n = 0;
   hipStream_t stream = nullptr;
+  unsigned long long *cross = nullptr;  // device: running net count of outlet crossings
+  unsigned long long cross_seen = 0;    // its value at the previous lbdps_outlet_crossings
+  long long cross_step0 = 0;            // the step counter then
   int device = 0;           // the HIP device current at creation
   void *scratch = nullptr;  // that device's address of the static scratch array
   int cf = 0, cp = 0;
@@ -218,6 +222,7 @@ struct lbdps_ctx {
   long long step = 0;
   bool in_batch = false;  // owned by a batch: destroyed with it
   lbdps_tuning tune{RC_LISTS, RC_GROUPS_MAX, 0};
+  int drag_blocks = 0;  // drag workgroups of the most recent step (its partial sums)
   int cluster_groups() const { return cluster_blocks(n, tune.cluster_lists, tune.cluster_groups_max); }
   DConsts dc{};
   // device buffers (carved from the workspace)
@@ -294,9 +299,13 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   int32_t *ticket = cv.take<int32_t>(4), *flags = cv.take<int32_t>(FLAG_COUNT), *nonfinite = cv.take<int32_t>(4);
   char *lut = raw((size_t)lut_rows(p.d_p) * LUT_W * sT), *inlet = raw((size_t)p.nx * sT);
   const size_t nbN = (size_t)nblocks((long long)N), nbC = (size_t)nblocks((long long)C);
-  const size_t ntile2 = (size_t)((p.nx + DTX - 1) / DTX) * ((p.ny + DTY - 1) / DTY);
+  size_t ndrag = 0;  // drag workgroups of the tile shape with the most of them
+  for (int t = 0; t < DRAG_TILES; ++t) {
+    const int w = drag_tile_w(t), h = BLOCK / w;
+    ndrag = std::max(ndrag, (size_t)((p.nx + w - 1) / w) * ((p.ny + h - 1) / h));
+  }
+  const size_t ntile2 = ndrag;
   long long *pair_part = cv.take<long long>(std::max(nbN, ntile2)), *coll_part = cv.take<long long>(nbN);
-  const size_t ndrag = (size_t)((p.nx + DTX - 1) / DTX) * ((p.ny + DTY - 1) / DTY);
   long long *wall_part = cv.take<long long>(nbN), *zero_part = cv.take<long long>(std::max(nbC, ndrag));
   long long *wall0_part = cv.take<long long>(std::max(nbN, ntile2));
   const int shift = cell_tile_shift(C);
@@ -309,6 +318,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   double *pc = cv.take<double>(NB_CONS * 3), *pp = cv.take<double>(NB_CONS * 2), *co = cv.take<double>(8);
   double *egt = cv.take<double>((size_t)lut_rows(p.d_p));
   long long *obs = cv.take<long long>((size_t)nblocks(p.nx) + 1);
+  unsigned long long *cross = cv.take<unsigned long long>(1);
   int32_t *dg_n = nullptr;
   char *dvx = nullptr, *dvy = nullptr, *dfx = nullptr, *dfy = nullptr;
   if (p.diagnostics) {
@@ -370,6 +380,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->cons_out = co;
     x->eg_tab = egt;
     x->obs_part = obs;
+    x->cross = cross;
     x->dg_n = dg_n;
     x->dg_vsx = dvx;
     x->dg_vsy = dvy;
@@ -478,6 +489,8 @@ template <int P> struct Impl {
     k.acx = (T *)x->acx;
     k.acy = (T *)x->acy;
     k.spin_limit = 1u << 22;
+    k.flags = x->flags;
+    k.cross = x->cross;
     return k;
   }
   static Parts<T> parts(const lbdps_ctx *x, int b) {
@@ -496,7 +509,21 @@ template <int P> struct Impl {
   }
 
   static TileSums tiles(const lbdps_ctx *x) { return TileSums{x->tile_sum, x->ntiles, x->tile_shift}; }
-  static int drag_tiles(const lbdps_ctx *x) { return ((x->nx + DTX - 1) / DTX) * ((x->ny + DTY - 1) / DTY); }
+  // Drag workgroups for tile shape t (the context's own by default).
+  static int drag_tiles(const lbdps_ctx *x, int t = -1) {
+    const int w = drag_tile_w(t < 0 ? x->tune.drag_tile : t), h = BLOCK / w;
+    return ((x->nx + w - 1) / w) * ((x->ny + h - 1) / h);
+  }
+  // The drag kernel of tile shape t, flat or one thread per cell.
+  using DragKern = void (*)(Parts<T>, Fields<T>, const int32_t *, const T *, Consts<T>, int32_t *, int32_t *,
+                            int32_t *, T *, T *, long long *, TileSums, int32_t *);
+  static DragKern drag_kernel(int t, bool flat) {
+    switch (t) {
+      case 1: return flat ? k_drag_flat<P, 64> : k_drag<P, 64>;
+      case 2: return flat ? k_drag_flat<P, 128> : k_drag<P, 128>;
+      default: return flat ? k_drag_flat<P, 32> : k_drag<P, 32>;
+    }
+  }
   // Workgroups of the resolution: they loop over chunks of particle indices.
   static int resolve_blocks(const lbdps_ctx *x) {
     const long long chunks = (x->n + RES_CHUNK - 1) / RES_CHUNK;
@@ -562,7 +589,8 @@ template <int P> struct Impl {
               dg ? (T *)x->dg_vsy : nullptr);
       if (x->n > 0) {
         const int nt = drag_tiles(x);
-        tlaunch(x, LBDPS_K_DRAG, false, drag_flat(nt) ? k_drag_flat<P> : k_drag<P>, dim3(nt), parts(x, x->cp),
+        x->drag_blocks = nt;  // the drag's per-workgroup partial sums of this step
+        tlaunch(x, LBDPS_K_DRAG, false, drag_kernel(x->tune.drag_tile, drag_flat(nt)), dim3(nt), parts(x, x->cp),
                 fields(x), (const int32_t *)x->cs, (const T *)x->lut, consts(x), x->count, x->rank, x->flags,
                 dg ? (T *)x->dg_fdx : nullptr, dg ? (T *)x->dg_fdy : nullptr, dg ? x->zero_part : nullptr, tiles(x),
                 x->stay);
@@ -612,6 +640,9 @@ template <int P> struct Impl {
                          parts(x, x->cp), x->slot, k, x->flags);
     x->bins_valid = false;
     x->step = 0;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, (int32_t *)x->cross, 2ll, 0);
+    x->cross_seen = 0;
+    x->cross_step0 = 0;
     if (x->p.diagnostics) {
       hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, x->dg_n, (long long)x->C, 0);
     }
@@ -1060,11 +1091,25 @@ lbdps_status lbdps_conservation_noalloc(lbdps_ctx *x, double h_out[6]) {
                            (int32_t *)(base + NOALLOC_FLAG), h_out, "lbdps_conservation_noalloc");
 }
 
+lbdps_status lbdps_outlet_crossings(lbdps_ctx *x, int64_t *h_net, int64_t *h_steps) {
+  if (!x || !h_net || !h_steps) return fail(LBDPS_E_INVALID, "ctx, h_net or h_steps is NULL");
+  lbdps_status st = sync_and_check(x, "lbdps_outlet_crossings");
+  if (st != LBDPS_OK) return st;
+  unsigned long long total = 0;
+  st = check_hip(hipMemcpy(&total, x->cross, sizeof(total), hipMemcpyDeviceToHost), "lbdps_outlet_crossings");
+  if (st != LBDPS_OK) return st;
+  *h_net = (int64_t)(total - x->cross_seen);  // modular difference of the running count
+  *h_steps = x->step - x->cross_step0;
+  x->cross_seen = total;
+  x->cross_step0 = x->step;
+  return LBDPS_OK;
+}
+
 lbdps_status lbdps_counters(lbdps_ctx *x, int64_t h_out[4]) {
   if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
   lbdps_status st = sync_and_check(x, "lbdps_counters");
   if (st != LBDPS_OK) return st;
-  const int nbN = nblocks(x->n), nbC = Impl<PREC_FP32>::drag_tiles(x);
+  const int nbN = nblocks(x->n), nbC = x->drag_blocks;
   std::vector<long long> buf((size_t)std::max(nbN, nbC) + 1);
   // contacts: one partial per workgroup of the contact kernel; collisions and
   // wall hits of the resolution kernel: one per workgroup of that kernel
@@ -1121,7 +1166,8 @@ lbdps_status lbdps_set_tuning(lbdps_ctx *x, const lbdps_tuning *t) {
   if (t->cluster_lists < 1 || t->cluster_lists > BLOCK)
     return fail(LBDPS_E_INVALID, "cluster_lists must be in [1, 256]");
   if (t->cluster_groups_max < 1) return fail(LBDPS_E_INVALID, "cluster_groups_max must be >= 1");
-  if (t->drag_tile != 0) return fail(LBDPS_E_UNSUPPORTED, "drag_tile: only 0 (32x8) is built");
+  if (t->drag_tile < 0 || t->drag_tile >= DRAG_TILES)
+    return fail(LBDPS_E_INVALID, "drag_tile must be 0 (32x8), 1 (64x4) or 2 (128x2)");
   x->tune = *t;
   return LBDPS_OK;
 }
@@ -1169,28 +1215,46 @@ lbdps_status lbdps_autotune(lbdps_ctx *x, int32_t steps, lbdps_tuning *chosen) {
   if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
   if (steps < 1) return fail(LBDPS_E_INVALID, "steps must be >= 1");
   // Two interleaved rounds over the candidates; each keeps its faster time, so
-  // a single disturbed measurement does not decide.
+  // a single disturbed measurement does not decide.  The cluster-resolution
+  // shapes first (under the context's drag tile), then the drag tile shapes
+  // under the chosen cluster shape: the two phases do not share work.
   const lbdps_tuning start = x->tune;
-  float t[kTuneN];
-  for (int round = 0; round < 2; ++round)
-    for (int c = 0; c < kTuneN; ++c) {
-      x->tune = kTuneCandidates[c];
-      float ms = 0.f;
-      lbdps_status st = time_on(
-          x->stream, [&]() { return dispatch(x, [&](auto impl) { return decltype(impl)::step(x, steps); }); },
-          &ms);
-      if (st != LBDPS_OK) {
-        x->tune = start;
-        return st;
+  float t[kTuneN + DRAG_TILES];
+  lbdps_tuning cand[kTuneN + DRAG_TILES];
+  for (int c = 0; c < kTuneN; ++c) {
+    cand[c] = kTuneCandidates[c];
+    cand[c].drag_tile = start.drag_tile;
+  }
+  auto run = [&](int c0, int c1) -> lbdps_status {
+    for (int round = 0; round < 2; ++round)
+      for (int c = c0; c < c1; ++c) {
+        x->tune = cand[c];
+        float ms = 0.f;
+        lbdps_status st = time_on(
+            x->stream, [&]() { return dispatch(x, [&](auto impl) { return decltype(impl)::step(x, steps); }); },
+            &ms);
+        if (st != LBDPS_OK) return st;
+        t[c] = round == 0 ? ms : std::min(t[c], ms);
       }
-      t[c] = round == 0 ? ms : std::min(t[c], ms);
+    int bc = c0;
+    for (int c = c0 + 1; c < c1; ++c)
+      if (t[c] < t[bc]) bc = c;
+    x->tune = cand[bc];
+    return LBDPS_OK;
+  };
+  lbdps_status st = run(0, kTuneN);
+  if (st == LBDPS_OK) {
+    for (int d = 0; d < DRAG_TILES; ++d) {
+      cand[kTuneN + d] = x->tune;
+      cand[kTuneN + d].drag_tile = d;
     }
-  int bc = 0;
-  for (int c = 1; c < kTuneN; ++c)
-    if (t[c] < t[bc]) bc = c;
-  const lbdps_tuning bt = kTuneCandidates[bc];
-  x->tune = bt;
-  if (chosen) *chosen = bt;
+    st = run(kTuneN, kTuneN + DRAG_TILES);
+  }
+  if (st != LBDPS_OK) {
+    x->tune = start;
+    return st;
+  }
+  if (chosen) *chosen = x->tune;
   return sync_and_check(x, "lbdps_autotune");
 }
 
@@ -1221,6 +1285,7 @@ struct lbdps_batch {
   hipEvent_t tab_done = nullptr;
   bool tab_inflight = false;
   int total[2][PH_COUNT]{};
+  int tile[2]{};  // drag tile shape each table was written for
   // bed state the graph's table describes
   std::vector<int> snap_cf, snap_cp;
   std::vector<long long> snap_n;
@@ -1299,12 +1364,13 @@ template <int P> struct BatchImpl {
     return a;
   }
 
-  // Workgroups of each phase for one bed, as the single-bed step launches them.
-  static void blocks(const lbdps_ctx *x, int nb[PH_COUNT]) {
+  // Workgroups of each phase for one bed, as the single-bed step launches
+  // them; the drag under the batch's tile shape `tile`.
+  static void blocks(const lbdps_ctx *x, int tile, int nb[PH_COUNT]) {
     for (int i = 0; i < PH_COUNT; ++i) nb[i] = 0;
     nb[PH_COLLIDE] = nblocks(x->C);
     if (x->n == 0) return;
-    nb[PH_DRAG] = I::drag_tiles(x);
+    nb[PH_DRAG] = I::drag_tiles(x, tile);
     nb[PH_SCAN] = x->ntiles;
     nb[PH_SCATTER] = nblocks(x->n);
     nb[PH_CONTACTS] = nblocks(x->n);
@@ -1323,11 +1389,18 @@ template <int P> struct BatchImpl {
     int *off = (int *)(B->h_tab + B->args_bytes);
     const int nb1 = B->nbeds + 1;
     for (int ph = 0; ph < PH_COUNT; ++ph) off[ph * nb1] = 0;
+    // one drag tile shape for the whole launch: bed 0's (the batch autotuner
+    // gives every bed the same)
+    const int tile = B->beds[0]->tune.drag_tile;
+    for (int b = 0; b < B->nbeds; ++b)
+      if (B->beds[b]->tune.drag_tile != tile)
+        return fail(LBDPS_E_INVALID, "the beds of a batch must share one drag tile shape");
+    B->tile[t] = tile;
     for (int b = 0; b < B->nbeds; ++b) {
       const lbdps_ctx *x = B->beds[b];
       a[b] = args(x);
       int nb[PH_COUNT];
-      blocks(x, nb);
+      blocks(x, tile, nb);
       for (int ph = 0; ph < PH_COUNT; ++ph) {
         const long long v = (long long)off[ph * nb1 + b] + nb[ph];
         if (v > 0x7fffffffll) return fail(LBDPS_E_SHAPE, "batch too large for one launch per phase");
@@ -1384,22 +1457,28 @@ template <int P> struct BatchImpl {
   if (tot[ph] > 0) {                                                                                                \
     hipEvent_t ea = nullptr, eb = nullptr;                                                                          \
     if (timing && bmark(B, phase_kernel(ph), ph == PH_RESOLVE, ea, eb))                                             \
-      hipExtLaunchKernelGGL(kern<P>, dim3(tot[ph]), dim3(BLOCK), 0, B->stream, ea, eb, 0, tab, off + (ph) * nb1,    \
+      hipExtLaunchKernelGGL(kern, dim3(tot[ph]), dim3(BLOCK), 0, B->stream, ea, eb, 0, tab, off + (ph) * nb1,       \
                             nbeds, flip);                                                                           \
     else                                                                                                            \
-      hipLaunchKernelGGL(kern<P>, dim3(tot[ph]), dim3(BLOCK), 0, B->stream, tab, off + (ph) * nb1, nbeds, flip);    \
+      hipLaunchKernelGGL(kern, dim3(tot[ph]), dim3(BLOCK), 0, B->stream, tab, off + (ph) * nb1, nbeds, flip);       \
   }
-      LBDPS_LAUNCH(kb_collide, PH_COLLIDE)
-      if (drag_flat(tot[PH_DRAG])) {
-        LBDPS_LAUNCH(kb_drag_flat, PH_DRAG)
-      } else {
-        LBDPS_LAUNCH(kb_drag, PH_DRAG)
+      LBDPS_LAUNCH(kb_collide<P>, PH_COLLIDE)
+      const bool flat = drag_flat(tot[PH_DRAG]);
+      switch (B->tile[t]) {
+        case 1:
+          if (flat) { LBDPS_LAUNCH((kb_drag_flat<P, 64>), PH_DRAG) } else { LBDPS_LAUNCH((kb_drag<P, 64>), PH_DRAG) }
+          break;
+        case 2:
+          if (flat) { LBDPS_LAUNCH((kb_drag_flat<P, 128>), PH_DRAG) } else { LBDPS_LAUNCH((kb_drag<P, 128>), PH_DRAG) }
+          break;
+        default:
+          if (flat) { LBDPS_LAUNCH((kb_drag_flat<P, 32>), PH_DRAG) } else { LBDPS_LAUNCH((kb_drag<P, 32>), PH_DRAG) }
       }
-      LBDPS_LAUNCH(kb_scan, PH_SCAN)
-      LBDPS_LAUNCH(kb_scatter, PH_SCATTER)
-      LBDPS_LAUNCH(kb_contacts, PH_CONTACTS)
-      LBDPS_LAUNCH(kb_clusters, PH_CLUSTERS)
-      LBDPS_LAUNCH(kb_resolve, PH_RESOLVE)
+      LBDPS_LAUNCH(kb_scan<P>, PH_SCAN)
+      LBDPS_LAUNCH(kb_scatter<P>, PH_SCATTER)
+      LBDPS_LAUNCH(kb_contacts<P>, PH_CONTACTS)
+      LBDPS_LAUNCH(kb_clusters<P>, PH_CLUSTERS)
+      LBDPS_LAUNCH(kb_resolve<P>, PH_RESOLVE)
 #undef LBDPS_LAUNCH
     }
   }
@@ -1632,7 +1711,7 @@ lbdps_status lbdps_batch_autotune(lbdps_batch *B, int32_t steps, const char *cac
   std::map<int, std::vector<int>> cls;
   for (int b = 0; b < B->nbeds; ++b) cls[size_class(B->beds[b]->n)].push_back(b);
   cls.erase(-1);
-  const std::string head = "lbdps-tune 1 precision " + std::to_string(B->prec);
+  const std::string head = "lbdps-tune 2 precision " + std::to_string(B->prec);
   std::map<int, lbdps_tuning> cached;
   if (cache_path) {
     std::ifstream in(cache_path);
@@ -1643,16 +1722,30 @@ lbdps_status lbdps_batch_autotune(lbdps_batch *B, int32_t steps, const char *cac
       while (in >> c >> t.cluster_lists >> t.cluster_groups_max >> t.drag_tile) cached[c] = t;
     }
   }
+  // The drag tile shape is one for the whole batch (one launch per phase):
+  // the cached one, else bed 0's while the classes are tuned, then the
+  // fastest of the shapes on the whole batched step.
+  bool all_cached = true;
+  for (auto &kv : cls) all_cached = all_cached && cached.count(kv.first);
+  int tile = all_cached && !cached.empty() ? cached.begin()->second.drag_tile : B->beds[0]->tune.drag_tile;
+  if (tile < 0 || tile >= DRAG_TILES) tile = 0;
+  for (auto *x : B->beds) x->tune.drag_tile = tile;
   for (auto &kv : cls) {
     auto it = cached.find(kv.first);
     if (it != cached.end()) {
-      for (int b : kv.second) B->beds[b]->tune = it->second;
+      for (int b : kv.second) {
+        B->beds[b]->tune = it->second;
+        B->beds[b]->tune.drag_tile = tile;
+      }
       continue;
     }
     float t[kTuneN];
     for (int round = 0; round < 2; ++round)  // as lbdps_autotune: the faster of two times per candidate
       for (int c = 0; c < kTuneN; ++c) {
-        for (int b : kv.second) B->beds[b]->tune = kTuneCandidates[c];
+        for (int b : kv.second) {
+          B->beds[b]->tune = kTuneCandidates[c];
+          B->beds[b]->tune.drag_tile = tile;
+        }
         float ms = 0.f;
         lbdps_status st = time_on(B->stream, [&]() { return lbdps_batch_step(B, steps); }, &ms);
         if (st != LBDPS_OK) return st;
@@ -1661,9 +1754,26 @@ lbdps_status lbdps_batch_autotune(lbdps_batch *B, int32_t steps, const char *cac
     int bc = 0;
     for (int c = 1; c < kTuneN; ++c)
       if (t[c] < t[bc]) bc = c;
-    const lbdps_tuning bt = kTuneCandidates[bc];
+    lbdps_tuning bt = kTuneCandidates[bc];
+    bt.drag_tile = tile;
     for (int b : kv.second) B->beds[b]->tune = bt;
     cached[kv.first] = bt;
+  }
+  if (!all_cached) {
+    float t[DRAG_TILES];
+    for (int round = 0; round < 2; ++round)
+      for (int d = 0; d < DRAG_TILES; ++d) {
+        for (auto *x : B->beds) x->tune.drag_tile = d;
+        float ms = 0.f;
+        lbdps_status st = time_on(B->stream, [&]() { return lbdps_batch_step(B, steps); }, &ms);
+        if (st != LBDPS_OK) return st;
+        t[d] = round == 0 ? ms : std::min(t[d], ms);
+      }
+    tile = 0;
+    for (int d = 1; d < DRAG_TILES; ++d)
+      if (t[d] < t[tile]) tile = d;
+    for (auto *x : B->beds) x->tune.drag_tile = tile;
+    for (auto &kv : cached) kv.second.drag_tile = tile;
   }
   if (cache_path) {
     std::ofstream out(cache_path);
@@ -1681,6 +1791,489 @@ lbdps_status lbdps_batch_destroy(lbdps_batch *B) {
   (void)hipStreamSynchronize(B->stream);
   for (auto *x : B->beds) x->in_batch = false;
   delete B;
+  return LBDPS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ the 3-D coupled step
+struct lbdps3_ctx {
+  lbdps3_params p{};
+  int prec = 0, nx = 0, ny = 0, nz = 0, C = 0, nlut = 0;
+  long long nmax = 0, n = 0;
+  hipStream_t stream = nullptr;
+  int cf = 0, cp = 0;
+  bool bins_valid = false;
+  long long step = 0;
+  double dtau = 0, dd = 0, dmu = 0, dvp = 0, dm = 0, done_e = 0, dfp = 0, dgeff[3]{}, dhalfG[3]{}, dsrc[Q3]{};
+  void *f[2]{};
+  void *fld[12]{};  // rho, ugx, ugy, ugz, beta, es, fpx, fpy, fpz, gpx, gpy, gpz
+  int32_t *key[2]{}, *pid[2]{};
+  void *pos[2][3]{}, *vel[2][3]{};
+  int32_t *count = nullptr, *cs = nullptr, *rank = nullptr, *slot = nullptr, *deg = nullptr, *done = nullptr;
+  long long *adj_in = nullptr, *adj_ov = nullptr;
+  int32_t *ticket = nullptr, *flags = nullptr, *chunk_busy = nullptr, *spart = nullptr, *pcnt = nullptr;
+  long long *pair_part = nullptr, *coll_part = nullptr;
+  void *lut = nullptr;
+  int32_t *dg_n = nullptr;
+  void *dg_fd = nullptr, *dg_acc = nullptr;
+  Adj adj() const { return Adj{adj_in, adj_ov}; }
+};
+
+namespace {
+
+int lut3_rows(double d) {
+  const double vol = kPi * d * d * d / 6.0, cap = kPi / (3.0 * std::sqrt(2.0));
+  return (int)(cap / vol) + 2;  // every count from the last row on is held at the densest packing
+}
+
+// Per-count table of the 3-D step in FP64, in the oracle's operation order
+// (the sphere volume fraction n pi d^3 / 6 held at pi / (3 sqrt 2), Eq. 9 at
+// it, Eq. 20 at the voidage, the drag-law constants of Eqs. 19, 21, 22).
+std::vector<double> build_lut3(const lbdps3_params &p) {
+  const int rows = lut3_rows(p.d_p);
+  std::vector<double> L((size_t)rows * L3_W, 0.0);
+  const double d = p.d_p, vol = kPi * d * d * d / 6.0, cap = kPi / (3.0 * std::sqrt(2.0));
+  const double mu = p.rho_g * ((p.tau - 0.5) / 3.0);
+  for (int n = 0; n < rows; ++n) {
+    double es = (double)n * vol;
+    if (es > cap) es = cap;
+    const double eg = 1.0 - es;
+    const double gam = es * (p.tau - 0.5) / ((1.0 - es) + (p.tau - 0.5));
+    const double om = eg > 0.74 ? omega_emms(eg) : p.omega_dense;
+    double *r = &L[(size_t)n * L3_W];
+    r[L3_ES] = es;
+    r[L3_RELAX] = (1.0 - gam) / p.tau;
+    r[L3_OMG] = om * gam;
+    r[L3_EG] = eg;
+    r[L3_DILUTE] = eg > 0.74 ? 1.0 : 0.0;
+    r[L3_A] = 18.0 * (1.0 - eg) * om * mu / (d * d);
+    r[L3_BRE] = eg * p.rho_g;
+    r[L3_H] = 0.75 * (1.0 - eg) * eg * p.rho_g;
+    r[L3_OM] = om;
+    r[L3_D1] = 150.0 * (1.0 - eg) * (1.0 - eg) * mu / (eg * d * d);
+    r[L3_D2] = 1.75 * (1.0 - eg) * p.rho_g;
+  }
+  return L;
+}
+
+size_t carve3(const lbdps3_params &p, long long nmax, char *base, lbdps3_ctx *x) {
+  Carver cv{base};
+  const int prec = p.precision;
+  const size_t sS = prec == PREC_FP64 ? 8 : (prec == PREC_FP32 ? 4 : 2), sT = prec == PREC_FP64 ? 8 : 4;
+  const size_t C = (size_t)p.nx * p.ny * p.nz, N = (size_t)std::max(nmax, 1ll);
+  auto raw = [&](size_t bytes) { return cv.take<char>(bytes); };
+  char *f0 = raw(Q3 * C * sS), *f1 = raw(Q3 * C * sS);
+  char *fl[12];
+  for (auto &q : fl) q = raw(C * sT);
+  int32_t *key[2], *pid[2];
+  char *pos[2][3], *vel[2][3];
+  for (int b = 0; b < 2; ++b) {
+    key[b] = cv.take<int32_t>(N);
+    pid[b] = cv.take<int32_t>(N);
+    for (int a = 0; a < 3; ++a) pos[b][a] = raw(N * sT);
+    for (int a = 0; a < 3; ++a) vel[b][a] = raw(N * sT);
+  }
+  int32_t *count = cv.take<int32_t>(C), *cs = cv.take<int32_t>(C + 1), *rank = cv.take<int32_t>(N);
+  int32_t *slot = cv.take<int32_t>(N), *deg = cv.take<int32_t>(N), *done = cv.take<int32_t>(N);
+  long long *adj_in = cv.take<long long>(N * ADJ_IN), *adj_ov = cv.take<long long>(N * (KMAX - ADJ_IN));
+  int32_t *ticket = cv.take<int32_t>(4), *flags = cv.take<int32_t>(FLAG_COUNT);
+  int32_t *chunk_busy = cv.take<int32_t>(N / RES_CHUNK + 1);
+  const size_t tiles = (std::max(C, N) + SCAN_TILE - 1) / SCAN_TILE + 1;
+  int32_t *spart = cv.take<int32_t>(tiles), *pcnt = cv.take<int32_t>(N + 1);
+  const size_t nb = (size_t)nblocks((long long)std::max(C, N)) + 1;
+  long long *pair_part = cv.take<long long>(nb), *coll_part = cv.take<long long>(nb);
+  char *lut = raw((size_t)lut3_rows(p.d_p) * L3_W * sT);
+  int32_t *dg_n = nullptr;
+  char *dg_fd = nullptr, *dg_acc = nullptr;
+  if (p.diagnostics) {
+    dg_n = cv.take<int32_t>(C);
+    dg_fd = raw(3 * N * sT);
+    dg_acc = raw(3 * N * sT);
+  }
+  if (x) {
+    x->f[0] = f0;
+    x->f[1] = f1;
+    for (int i = 0; i < 12; ++i) x->fld[i] = fl[i];
+    for (int b = 0; b < 2; ++b) {
+      x->key[b] = key[b];
+      x->pid[b] = pid[b];
+      for (int a = 0; a < 3; ++a) {
+        x->pos[b][a] = pos[b][a];
+        x->vel[b][a] = vel[b][a];
+      }
+    }
+    x->count = count;
+    x->cs = cs;
+    x->rank = rank;
+    x->slot = slot;
+    x->deg = deg;
+    x->done = done;
+    x->adj_in = adj_in;
+    x->adj_ov = adj_ov;
+    x->ticket = ticket;
+    x->flags = flags;
+    x->chunk_busy = chunk_busy;
+    x->spart = spart;
+    x->pcnt = pcnt;
+    x->pair_part = pair_part;
+    x->coll_part = coll_part;
+    x->lut = lut;
+    x->dg_n = dg_n;
+    x->dg_fd = dg_fd;
+    x->dg_acc = dg_acc;
+  }
+  return cv.off + 256;
+}
+
+template <int P> struct Impl3 {
+  using T = typename Prec<P>::T;
+  using S = typename Prec<P>::S;
+
+  static Consts3<T> consts(const lbdps3_ctx *x) {
+    Consts3<T> k{};
+    k.nx = x->nx;
+    k.ny = x->ny;
+    k.nz = x->nz;
+    k.C = x->C;
+    k.npart = (int)x->n;
+    k.nlut = x->nlut;
+    k.tau = (T)x->dtau;
+    k.d = (T)x->p.d_p;
+    k.dd = (T)x->dd;
+    k.mu = (T)x->dmu;
+    k.vp = (T)x->dvp;
+    k.m = (T)x->dm;
+    k.msum = (T)(x->dm + x->dm);
+    k.one_e = (T)x->done_e;
+    k.fp = (T)x->dfp;
+    for (int a = 0; a < 3; ++a) {
+      k.geff[a] = (T)x->dgeff[a];
+      k.halfG[a] = (T)x->dhalfG[a];
+    }
+    for (int i = 0; i < Q3; ++i) k.src[i] = (T)x->dsrc[i];
+    k.flags = x->flags;
+    k.spin_limit = 1u << 22;
+    return k;
+  }
+  static Parts3<T> parts(const lbdps3_ctx *x, int b) {
+    return Parts3<T>{x->key[b], x->pid[b], (T *)x->pos[b][0], (T *)x->pos[b][1], (T *)x->pos[b][2],
+                     (T *)x->vel[b][0], (T *)x->vel[b][1], (T *)x->vel[b][2]};
+  }
+  static Fields3<T> fields(const lbdps3_ctx *x) {
+    T *q[12];
+    for (int i = 0; i < 12; ++i) q[i] = (T *)x->fld[i];
+    return Fields3<T>{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10], q[11]};
+  }
+  static void scan(lbdps3_ctx *x, int32_t *in, long long n, int32_t *out, int zero_in) {
+    const int tiles = (int)((n + SCAN_TILE - 1) / SCAN_TILE) + (n == 0);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(BLOCK), 0, x->stream, in, n, x->spart);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, x->stream, x->spart, tiles, out + n);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(BLOCK), 0, x->stream, in, n, x->spart, out, zero_in);
+  }
+  // Cell starts of the records' current keys, then the records in cell order.
+  static void sort(lbdps3_ctx *x, bool counted) {
+    const int N = (int)x->n;
+    if (!counted)
+      hipLaunchKernelGGL(k3c_count<T>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), N, x->count,
+                         x->rank);
+    scan(x, x->count, x->C, x->cs, 1);
+    if (N > 0)
+      hipLaunchKernelGGL(k3c_scatter<T>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
+                         parts(x, 1 - x->cp), (const int32_t *)x->rank, (const int32_t *)x->cs, N, x->slot);
+    x->cp = 1 - x->cp;
+    x->bins_valid = true;
+  }
+  static void hard_spheres(lbdps3_ctx *x) {
+    const int N = (int)x->n;
+    if (N == 0) return;
+    const Consts3<T> k = consts(x);
+    hipLaunchKernelGGL(k3c_contacts<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
+                       (const int32_t *)x->cs, k, x->adj(), x->deg, x->done, x->ticket, x->chunk_busy, x->pair_part);
+    hipLaunchKernelGGL(k3c_resolve<P>, dim3(std::min(nblocks(N), 2048)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
+                       (const int32_t *)x->slot, x->adj(), (const int32_t *)x->deg, x->done, x->ticket, k,
+                       x->coll_part, x->chunk_busy);
+  }
+  static lbdps_status step(lbdps3_ctx *x, int nsteps) {
+    const bool dg = x->p.diagnostics != 0;
+    for (int it = 0; it < nsteps; ++it) {
+      if (!x->bins_valid) sort(x, false);
+      const Consts3<T> k = consts(x);
+      hipLaunchKernelGGL(k3c_collide<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, (const S *)x->f[x->cf],
+                         (S *)x->f[1 - x->cf], fields(x), (const int32_t *)x->cs, parts(x, x->cp), (const T *)x->lut,
+                         k, dg ? x->dg_n : nullptr);
+      if (x->n > 0) {
+        hipLaunchKernelGGL(k3c_gradp<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, fields(x), k);
+        hipLaunchKernelGGL(k3c_drag<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x),
+                           (const int32_t *)x->cs, k, x->count, x->rank, dg ? (T *)x->dg_fd : nullptr,
+                           dg ? (T *)x->dg_acc : nullptr);
+        sort(x, true);
+        hard_spheres(x);
+      }
+      x->cf = 1 - x->cf;
+      x->step += 1;
+    }
+    return launch_status("lbdps3_step");
+  }
+  static lbdps_status set_state(lbdps3_ctx *x, const double *d_f, const double *d_pos, const double *d_vel,
+                                long long n) {
+    const long long e = (long long)Q3 * x->C;
+    hipLaunchKernelGGL(k3_set_f<P>, dim3((unsigned)((e + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, x->stream, d_f,
+                       (S *)x->f[x->cf], x->C);
+    x->n = n;
+    const Consts3<T> k = consts(x);
+    if (n > 0)
+      hipLaunchKernelGGL(k3c_set_parts<P>, dim3(nblocks(n)), dim3(BLOCK), 0, x->stream, d_pos, d_vel, (int)n,
+                         parts(x, x->cp), k);
+    x->bins_valid = false;
+    x->step = 0;
+    if (x->p.diagnostics)
+      hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, x->dg_n, (long long)x->C, 0);
+    return launch_status("lbdps3_set_state");
+  }
+  static void get_state(lbdps3_ctx *x, double *d_f, double *d_pos, double *d_vel) {
+    const long long e = (long long)Q3 * x->C;
+    if (d_f)
+      hipLaunchKernelGGL(k3_get_f<P>, dim3((unsigned)((e + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, x->stream,
+                         (const S *)x->f[x->cf], d_f, x->C);
+    if (x->n > 0 && (d_pos || d_vel)) {
+      if (!x->bins_valid) sort(x, false);
+      hipLaunchKernelGGL(k3c_get_parts<P>, dim3(nblocks(x->n)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
+                         (const int32_t *)x->slot, (int)x->n, consts(x), d_pos, d_vel);
+    }
+  }
+  static void get_field(lbdps3_ctx *x, const void *a, const void *b, const void *c, double *out, double add,
+                        long long n) {
+    hipLaunchKernelGGL(k3_get_field<T>, dim3(nblocks(n)), dim3(BLOCK), 0, x->stream, (const T *)a, (const T *)b,
+                       (const T *)c, n, out, add);
+  }
+};
+
+template <class F> lbdps_status dispatch3(lbdps3_ctx *x, F &&fn) {
+  switch (x->prec) {
+    case PREC_FP64: return fn(Impl3<PREC_FP64>{});
+    case PREC_FP32: return fn(Impl3<PREC_FP32>{});
+    case PREC_FP16DEV: return fn(Impl3<PREC_FP16DEV>{});
+    case PREC_BF16DEV: return fn(Impl3<PREC_BF16DEV>{});
+  }
+  return fail(LBDPS_E_INVALID, "unknown precision");
+}
+
+lbdps_status sync3(lbdps3_ctx *x, const char *what) {
+  lbdps_status st = check_hip(hipStreamSynchronize(x->stream), what);
+  if (st != LBDPS_OK) return st;
+  int32_t fl[FLAG_COUNT];
+  st = check_hip(hipMemcpy(fl, x->flags, sizeof(fl), hipMemcpyDeviceToHost), what);
+  if (st != LBDPS_OK) return st;
+  bool any = false;
+  for (int i = 0; i < FLAG_COUNT; ++i) any |= fl[i] != 0;
+  if (!any) return LBDPS_OK;
+  const int32_t zero[FLAG_COUNT] = {0};
+  check_hip(hipMemcpy(x->flags, zero, sizeof(zero), hipMemcpyHostToDevice), what);
+  if (fl[FLAG_DOMAIN]) return fail(LBDPS_E_INVALID, std::string(what) + ": a particle was placed outside the box");
+  if (fl[FLAG_CAPACITY])
+    return fail(LBDPS_E_CAPACITY, std::string(what) + ": a particle had more than LBDPS_MAX_CONTACTS contacts");
+  if (fl[FLAG_STALL]) return fail(LBDPS_E_STALL, std::string(what) + ": collision resolution exceeded its wait bound");
+  return fail(LBDPS_E_DEVICE, std::string(what) + ": unknown device flag");
+}
+
+}  // namespace
+
+extern "C" {
+
+lbdps_status lbdps3_validate_params(const lbdps3_params *p, int64_t max_particles) {
+  if (!p) return fail(LBDPS_E_INVALID, "params is NULL");
+  if (p->nx < 3 || p->ny < 3 || p->nz < 3) return fail(LBDPS_E_SHAPE, "nx, ny and nz must be >= 3");
+  if ((long long)p->nx * p->ny * p->nz >= (1ll << 28)) return fail(LBDPS_E_SHAPE, "nx * ny * nz must be < 2^28");
+  if (!(is_fin(p->tau) && p->tau > 0.5)) return fail(LBDPS_E_INVALID, "tau must be > 0.5");
+  if (!(is_fin(p->rho_g) && p->rho_g > 0)) return fail(LBDPS_E_INVALID, "rho_g must be > 0");
+  if (!(is_fin(p->rho_s) && p->rho_s > 0)) return fail(LBDPS_E_INVALID, "rho_s must be > 0");
+  if (!(is_fin(p->d_p) && p->d_p >= 0.1 && p->d_p < 1.0)) return fail(LBDPS_E_INVALID, "d_p must be in [0.1, 1)");
+  if (!(p->e_pp >= 0 && p->e_pp <= 1)) return fail(LBDPS_E_INVALID, "e_pp must be in [0, 1]");
+  for (int a = 0; a < 3; ++a)
+    if (!is_fin(p->g[a]) || !is_fin(p->body_force[a])) return fail(LBDPS_E_INVALID, "g and body_force must be finite");
+  if (!is_fin(p->omega_dense)) return fail(LBDPS_E_INVALID, "omega_dense must be finite");
+  if (p->pressure_force_sign < -1 || p->pressure_force_sign > 1)
+    return fail(LBDPS_E_INVALID, "pressure_force_sign must be -1, 0 or 1");
+  if (p->precision < 0 || p->precision > 3) return fail(LBDPS_E_INVALID, "precision must be 0..3");
+  if (p->diagnostics < 0 || p->diagnostics > 1) return fail(LBDPS_E_INVALID, "diagnostics must be 0 or 1");
+  if (max_particles < 0 || max_particles >= (1ll << 28)) return fail(LBDPS_E_SHAPE, "max_particles must be in [0, 2^28)");
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps3_workspace_bytes(const lbdps3_params *p, int64_t max_particles, size_t *bytes) {
+  lbdps_status st = lbdps3_validate_params(p, max_particles);
+  if (st != LBDPS_OK) return st;
+  if (!bytes) return fail(LBDPS_E_INVALID, "bytes is NULL");
+  *bytes = carve3(*p, max_particles, nullptr, nullptr);
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps3_create(const lbdps3_params *p, int64_t max_particles, void *d_workspace, size_t bytes,
+                           void *stream, lbdps3_ctx **out) {
+  if (!out) return fail(LBDPS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  lbdps_status st = lbdps3_validate_params(p, max_particles);
+  if (st != LBDPS_OK) return st;
+  const size_t need = carve3(*p, max_particles, nullptr, nullptr);
+  if (!d_workspace) return fail(LBDPS_E_INVALID, "workspace is NULL");
+  if (bytes < need) return fail(LBDPS_E_SHAPE, "workspace too small: need " + std::to_string(need) + " bytes");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(LBDPS_E_INVALID, "workspace must be 256-byte aligned");
+  lbdps3_ctx *x = new (std::nothrow) lbdps3_ctx();
+  if (!x) return fail(LBDPS_E_DEVICE, "host allocation failed");
+  x->p = *p;
+  x->prec = p->precision;
+  x->nx = p->nx;
+  x->ny = p->ny;
+  x->nz = p->nz;
+  x->C = p->nx * p->ny * p->nz;
+  x->nmax = max_particles;
+  x->nlut = lut3_rows(p->d_p);
+  x->stream = (hipStream_t)stream;
+  x->dtau = p->tau;
+  x->dd = p->d_p * p->d_p;
+  x->dmu = p->rho_g * ((p->tau - 0.5) / 3.0);
+  x->dvp = kPi * p->d_p * p->d_p * p->d_p / 6.0;
+  x->dm = p->rho_s * x->dvp;
+  x->done_e = 1.0 + p->e_pp;
+  x->dfp = (double)p->pressure_force_sign * x->dvp;
+  for (int a = 0; a < 3; ++a) {
+    x->dgeff[a] = (1.0 - p->rho_g / p->rho_s) * p->g[a];
+    x->dhalfG[a] = 0.5 * p->body_force[a];
+  }
+  for (int i = 0; i < Q3; ++i)
+    x->dsrc[i] = 3.0 * w3<double>(i) *
+                 (c3(i, 0) * p->body_force[0] + c3(i, 1) * p->body_force[1] + c3(i, 2) * p->body_force[2]);
+  carve3(*p, max_particles, (char *)d_workspace, x);
+  std::vector<double> lut = build_lut3(*p);
+  if (x->prec == PREC_FP64) {
+    st = check_hip(hipMemcpy(x->lut, lut.data(), lut.size() * 8, hipMemcpyHostToDevice), "lbdps3_create");
+  } else {
+    std::vector<float> lf(lut.begin(), lut.end());
+    st = check_hip(hipMemcpy(x->lut, lf.data(), lf.size() * 4, hipMemcpyHostToDevice), "lbdps3_create");
+  }
+  if (st != LBDPS_OK) {
+    delete x;
+    return st;
+  }
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, x->count, (long long)x->C, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, x->flags, (long long)FLAG_COUNT, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->nmax / RES_CHUNK + 1)), dim3(BLOCK), 0, x->stream, x->chunk_busy,
+                     (long long)(x->nmax / RES_CHUNK + 1), 0);
+  st = dispatch3(x, [&](auto impl) { return decltype(impl)::set_state(x, nullptr, nullptr, nullptr, 0); });
+  if (st == LBDPS_OK) st = check_hip(hipStreamSynchronize(x->stream), "lbdps3_create");
+  if (st != LBDPS_OK) {
+    delete x;
+    return st;
+  }
+  *out = x;
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps3_set_state(lbdps3_ctx *x, const double *d_f, const double *d_pos, const double *d_vel,
+                              int64_t n) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (n < 0 || n > x->nmax) return fail(LBDPS_E_SHAPE, "n must be in [0, max_particles]");
+  if (n > 0 && (!d_pos || !d_vel)) return fail(LBDPS_E_INVALID, "positions and velocities are required when n > 0");
+  return dispatch3(x, [&](auto impl) { return decltype(impl)::set_state(x, d_f, d_pos, d_vel, n); });
+}
+
+lbdps_status lbdps3_step(lbdps3_ctx *x, int32_t nsteps) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (nsteps < 0) return fail(LBDPS_E_INVALID, "nsteps must be >= 0");
+  return dispatch3(x, [&](auto impl) { return decltype(impl)::step(x, nsteps); });
+}
+
+lbdps_status lbdps3_get_state(lbdps3_ctx *x, double *d_f, double *d_pos, double *d_vel) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  lbdps_status st = dispatch3(x, [&](auto impl) {
+    decltype(impl)::get_state(x, d_f, d_pos, d_vel);
+    return launch_status("lbdps3_get_state");
+  });
+  if (st != LBDPS_OK) return st;
+  return sync3(x, "lbdps3_get_state");
+}
+
+lbdps_status lbdps3_get_fields(lbdps3_ctx *x, double *d_rho, double *d_ugas, double *d_fpg, double *d_beta,
+                               int32_t *d_ncell) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (d_ncell && !x->p.diagnostics) return fail(LBDPS_E_INVALID, "n_tot needs diagnostics on");
+  lbdps_status st = dispatch3(x, [&](auto impl) {
+    using I = decltype(impl);
+    const double add = x->prec == PREC_FP64 ? 0.0 : 1.0;  // the deviation modes keep rho - 1
+    if (d_rho) I::get_field(x, x->fld[0], nullptr, nullptr, d_rho, add, x->C);
+    if (d_ugas) I::get_field(x, x->fld[1], x->fld[2], x->fld[3], d_ugas, 0.0, x->C);
+    if (d_beta) I::get_field(x, x->fld[4], nullptr, nullptr, d_beta, 0.0, x->C);
+    if (d_fpg) I::get_field(x, x->fld[6], x->fld[7], x->fld[8], d_fpg, 0.0, x->C);
+    if (d_ncell)
+      (void)check_hip(hipMemcpyAsync(d_ncell, x->dg_n, (size_t)x->C * 4, hipMemcpyDeviceToDevice, x->stream),
+                      "lbdps3_get_fields");
+    return launch_status("lbdps3_get_fields");
+  });
+  if (st != LBDPS_OK) return st;
+  return sync3(x, "lbdps3_get_fields");
+}
+
+lbdps_status lbdps3_get_drag(lbdps3_ctx *x, double *d_fd, double *d_acc) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  if (!x->p.diagnostics) return fail(LBDPS_E_INVALID, "the drag is recorded with diagnostics on");
+  if (x->n > 0) {
+    lbdps_status st = dispatch3(x, [&](auto impl) {
+      using I = decltype(impl);
+      if (d_fd) I::get_field(x, x->dg_fd, nullptr, nullptr, d_fd, 0.0, 3 * x->n);
+      if (d_acc) I::get_field(x, x->dg_acc, nullptr, nullptr, d_acc, 0.0, 3 * x->n);
+      return launch_status("lbdps3_get_drag");
+    });
+    if (st != LBDPS_OK) return st;
+  }
+  return sync3(x, "lbdps3_get_drag");
+}
+
+lbdps_status lbdps3_get_pairs(lbdps3_ctx *x, int32_t *d_pairs, int64_t cap, int64_t *n_out) {
+  if (!x || !n_out) return fail(LBDPS_E_INVALID, "ctx or n_out is NULL");
+  if (cap < 0 || (cap > 0 && !d_pairs)) return fail(LBDPS_E_INVALID, "bad pair buffer");
+  const int N = (int)x->n;
+  *n_out = 0;
+  if (N == 0) return sync3(x, "lbdps3_get_pairs");
+  hipLaunchKernelGGL(k_pairs_count, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->slot, x->adj(), x->deg, N,
+                     x->rank);
+  dispatch3(x, [&](auto impl) {
+    decltype(impl)::scan(x, x->rank, N, x->pcnt, 0);
+    return LBDPS_OK;
+  });
+  hipLaunchKernelGGL(k_pairs_write, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->slot, x->adj(), x->deg, N,
+                     x->pcnt, d_pairs, (long long)cap);
+  lbdps_status st = launch_status("lbdps3_get_pairs");
+  if (st != LBDPS_OK) return st;
+  int32_t total = 0;
+  st = check_hip(hipMemcpyAsync(&total, x->pcnt + N, 4, hipMemcpyDeviceToHost, x->stream), "lbdps3_get_pairs");
+  if (st != LBDPS_OK) return st;
+  st = sync3(x, "lbdps3_get_pairs");
+  *n_out = total;
+  return st;
+}
+
+lbdps_status lbdps3_counters(lbdps3_ctx *x, int64_t h_out[2]) {
+  if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
+  lbdps_status st = sync3(x, "lbdps3_counters");
+  if (st != LBDPS_OK) return st;
+  h_out[0] = h_out[1] = 0;
+  if (x->n == 0) return LBDPS_OK;
+  const int nb = nblocks(x->n), nr = std::min(nblocks(x->n), 2048);
+  std::vector<long long> buf((size_t)nb);
+  st = check_hip(hipMemcpy(buf.data(), x->pair_part, (size_t)nb * 8, hipMemcpyDeviceToHost), "lbdps3_counters");
+  if (st != LBDPS_OK) return st;
+  for (int b = 0; b < nb; ++b) h_out[0] += buf[b];
+  st = check_hip(hipMemcpy(buf.data(), x->coll_part, (size_t)nr * 8, hipMemcpyDeviceToHost), "lbdps3_counters");
+  if (st != LBDPS_OK) return st;
+  for (int b = 0; b < nr; ++b) h_out[1] += buf[b];
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps3_destroy(lbdps3_ctx *x) {
+  if (!x) return fail(LBDPS_E_INVALID, "ctx is NULL");
+  (void)hipStreamSynchronize(x->stream);
+  delete x;
   return LBDPS_OK;
 }
 

@@ -48,6 +48,14 @@ class lbdps_params(ctypes.Structure):
     ]
 
 
+class lbdps3_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", c_i32), ("ny", c_i32), ("nz", c_i32), ("tau", c_dbl), ("rho_g", c_dbl), ("rho_s", c_dbl),
+        ("d_p", c_dbl), ("e_pp", c_dbl), ("g", c_dbl * 3), ("body_force", c_dbl * 3), ("omega_dense", c_dbl),
+        ("pressure_force_sign", c_i32), ("precision", c_i32), ("diagnostics", c_i32),
+    ]
+
+
 class lbdps_tuning(ctypes.Structure):
     _fields_ = [("cluster_lists", c_i32), ("cluster_groups_max", c_i32), ("drag_tile", c_i32)]
 
@@ -76,6 +84,7 @@ _SIGS = {
     "lbdps_conservation": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
     "lbdps_conservation_noalloc": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
     "lbdps_counters": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
+    "lbdps_outlet_crossings": (c_i32, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
     "lbdps_time_kernels": (c_i32, [c_vp, ctypes.c_uint32]),
     "lbdps_kernel_times": (c_i32, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
     "lbdps_set_tuning": (c_i32, [c_vp, ctypes.POINTER(lbdps_tuning)]),
@@ -94,6 +103,18 @@ _SIGS = {
     "lbdps_batch_time_kernels": (c_i32, [c_vp, ctypes.c_uint32]),
     "lbdps_batch_kernel_times": (c_i32, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
     "lbdps_batch_destroy": (c_i32, [c_vp]),
+    "lbdps3_validate_params": (c_i32, [ctypes.POINTER(lbdps3_params), c_i64]),
+    "lbdps3_workspace_bytes": (c_i32, [ctypes.POINTER(lbdps3_params), c_i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbdps3_create": (c_i32, [ctypes.POINTER(lbdps3_params), c_i64, c_vp, ctypes.c_size_t, c_vp,
+                              ctypes.POINTER(c_vp)]),
+    "lbdps3_set_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64]),
+    "lbdps3_step": (c_i32, [c_vp, c_i32]),
+    "lbdps3_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "lbdps3_get_fields": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lbdps3_get_drag": (c_i32, [c_vp, c_vp, c_vp]),
+    "lbdps3_get_pairs": (c_i32, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]),
+    "lbdps3_counters": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
+    "lbdps3_destroy": (c_i32, [c_vp]),
     "lbdps_status_str": (ctypes.c_char_p, [c_i32]),
     "lbdps_last_error": (ctypes.c_char_p, []),
 }
@@ -315,6 +336,13 @@ class Sim:
         check(lbdps_counters(self.ctx, out), "lbdps_counters")
         return dict(pairs=out[0], collisions=out[1], walls=out[2], zero_den=out[3])
 
+    def outlet_crossings(self):
+        """(net particles across the outlet plane y = ny upward, steps) since
+        the previous call (lbdps_outlet_crossings)."""
+        net, steps = c_i64(0), c_i64(0)
+        check(lbdps_outlet_crossings(self.ctx, ctypes.byref(net), ctypes.byref(steps)), "lbdps_outlet_crossings")
+        return net.value, steps.value
+
     def tuning(self) -> dict:
         t = lbdps_tuning()
         check(lbdps_get_tuning(self.ctx, ctypes.byref(t)), "lbdps_get_tuning")
@@ -435,6 +463,122 @@ class Batch:
             self.stream.synchronize()
             lbdps_batch_destroy(self.batch)
             self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params3(cfg: dict, precision=None, diagnostics: bool = False) -> lbdps3_params:
+    """3-D parameters from a workload dict (nx, ny, nz, tau, rho_g, rho_s, d,
+    e_pp, g[3], G[3], omega_dense, pressure_sign)."""
+    p = lbdps3_params()
+    p.nx, p.ny, p.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
+    p.tau, p.rho_g, p.rho_s, p.d_p, p.e_pp = (float(cfg[k]) for k in ("tau", "rho_g", "rho_s", "d", "e_pp"))
+    for a in range(3):
+        p.g[a] = float(cfg["g"][a])
+        p.body_force[a] = float(cfg["G"][a])
+    p.omega_dense = float(cfg.get("omega_dense", 1.0))
+    p.pressure_force_sign = int(cfg.get("pressure_sign", -1))
+    prec = precision if precision is not None else cfg.get("precision", "fp64")
+    p.precision = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    p.diagnostics = int(bool(diagnostics))
+    return p
+
+
+class Sim3:
+    """One 3-D coupled context (lbdps3_*) on the current HIP device."""
+
+    def __init__(self, cfg: dict, precision=None, diagnostics: bool = False, stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.params = make_params3(cfg, precision, diagnostics)
+        pos = np.asarray(cfg["pos"], np.float64).reshape(-1, 3)
+        self.n = len(pos)
+        self.nx, self.ny, self.nz = self.params.nx, self.params.ny, self.params.nz
+        nbytes = ctypes.c_size_t(0)
+        check(lbdps3_workspace_bytes(ctypes.byref(self.params), self.n, ctypes.byref(nbytes)), "lbdps3_workspace_bytes")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        ctx = c_vp()
+        check(lbdps3_create(ctypes.byref(self.params), self.n, self.ws.data_ptr(), nbytes.value,
+                            self.stream.cuda_stream, ctypes.byref(ctx)), "lbdps3_create")
+        self.ctx = ctx
+        self.set_state(None, pos, cfg.get("vel", np.zeros_like(pos)))
+
+    def _dev(self, a):
+        return self.torch.as_tensor(np.ascontiguousarray(a, np.float64)).to("cuda").contiguous()
+
+    def set_state(self, f, pos, vel):
+        t = self.torch
+        with t.cuda.stream(self.stream):
+            pos = self._dev(np.asarray(pos, np.float64).reshape(-1, 3))
+            vel = self._dev(np.asarray(vel, np.float64).reshape(-1, 3))
+            fd = None if f is None else self._dev(np.asarray(f, np.float64).reshape(19, self.nz, self.ny, self.nx))
+            self.n = pos.shape[0]
+            check(lbdps3_set_state(self.ctx, None if fd is None else fd.data_ptr(), pos.data_ptr(), vel.data_ptr(),
+                                   self.n), "lbdps3_set_state")
+        self.stream.synchronize()
+
+    def step(self, nsteps: int = 1):
+        check(lbdps3_step(self.ctx, int(nsteps)), "lbdps3_step")
+
+    def state(self):
+        t = self.torch
+        n = max(self.n, 1)
+        f = t.empty(19, self.nz, self.ny, self.nx, dtype=t.float64, device="cuda")
+        pos = t.empty(n, 3, dtype=t.float64, device="cuda")
+        vel = t.empty(n, 3, dtype=t.float64, device="cuda")
+        check(lbdps3_get_state(self.ctx, f.data_ptr(), pos.data_ptr(), vel.data_ptr()), "lbdps3_get_state")
+        return f.cpu().numpy(), pos.cpu().numpy()[: self.n], vel.cpu().numpy()[: self.n]
+
+    def fields(self):
+        t = self.torch
+        C = self.nx * self.ny * self.nz
+        rho = t.empty(C, dtype=t.float64, device="cuda")
+        ug = t.empty(C, 3, dtype=t.float64, device="cuda")
+        fpg = t.empty(C, 3, dtype=t.float64, device="cuda")
+        beta = t.empty(C, dtype=t.float64, device="cuda")
+        diag = bool(self.params.diagnostics)
+        ncell = t.empty(C, dtype=t.int32, device="cuda") if diag else None
+        check(lbdps3_get_fields(self.ctx, rho.data_ptr(), ug.data_ptr(), fpg.data_ptr(), beta.data_ptr(),
+                                ncell.data_ptr() if diag else None), "lbdps3_get_fields")
+        sh = (self.nz, self.ny, self.nx)
+        out = dict(rho=rho.cpu().numpy().reshape(sh), ugas=ug.cpu().numpy().reshape(*sh, 3),
+                   fpg=fpg.cpu().numpy().reshape(*sh, 3), beta=beta.cpu().numpy().reshape(sh))
+        if diag:
+            out["ncell"] = ncell.cpu().numpy().reshape(sh)
+        return out
+
+    def drag(self):
+        t = self.torch
+        n = max(self.n, 1)
+        fd = t.empty(n, 3, dtype=t.float64, device="cuda")
+        acc = t.empty(n, 3, dtype=t.float64, device="cuda")
+        check(lbdps3_get_drag(self.ctx, fd.data_ptr(), acc.data_ptr()), "lbdps3_get_drag")
+        return fd.cpu().numpy()[: self.n], acc.cpu().numpy()[: self.n]
+
+    def pairs(self, cap=None):
+        t = self.torch
+        cap = int(cap if cap is not None else max(16, LBDPS_MAX_CONTACTS * self.n // 2 + 16))
+        buf = t.empty(cap, 2, dtype=t.int32, device="cuda")
+        m = c_i64(0)
+        check(lbdps3_get_pairs(self.ctx, buf.data_ptr(), cap, ctypes.byref(m)), "lbdps3_get_pairs")
+        return buf[: min(m.value, cap)].cpu().numpy(), m.value
+
+    def counters(self):
+        out = (c_i64 * 2)()
+        check(lbdps3_counters(self.ctx, out), "lbdps3_counters")
+        return dict(pairs=out[0], collisions=out[1])
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.stream.synchronize()
+            lbdps3_destroy(self.ctx)
+            self.ctx = None
 
     def __del__(self):
         try:

@@ -79,6 +79,23 @@ def test_batch_equals_single_beds(prec):
     batch.close()
 
 
+@pytest.mark.parametrize("prec,tile", [("fp64", 1), ("fp32", 2), ("fp16", 1)])
+def test_batch_equals_single_beds_other_drag_tiles(prec, tile):
+    """The batch under the other drag tile shapes (64 x 4, 128 x 2; shared by
+    every bed) equals single beds under the default shape bit for bit."""
+    cfgs = uneven_beds(prec)
+    batch = L.Batch(cfgs)
+    for bed in batch.beds:
+        bed.set_tuning(drag_tile=tile)
+    batch.step(5)
+    batch.sync()
+    for i, c in enumerate(cfgs):
+        single = L.Sim(c)
+        single.step(5)
+        assert_same(snapshot(batch.beds[i]), snapshot(single), f"{prec} tile {tile} bed {i}")
+    batch.close()
+
+
 def test_batch_fp64_matches_oracle():
     cfgs = uneven_beds("fp64")
     batch = L.Batch(cfgs)
@@ -164,7 +181,9 @@ def test_batch_autotune_cache(tmp_path):
     a.sync()
     text = path.read_text().splitlines()
     say(text)
-    assert text[0].startswith("lbdps-tune 1")
+    assert text[0].startswith("lbdps-tune 2")
+    tiles = {int(line.split()[3]) for line in text[1:]}
+    assert len(tiles) == 1 and tiles <= {0, 1, 2}  # one drag tile shape for the whole batch
     b = L.Batch(cfgs)
     tb = b.autotune(2, path)
     assert ta == tb

@@ -1,0 +1,163 @@
+"""GPU parity of the 3-D coupled step (lbdps3_*, through the C ABI) against
+the oracle's 3-D step (orc3_step) on the same seeded beds.
+
+FP64: free-running steps within 1e-12 norm-wise (populations, density, u_gas,
+F_pg, beta, drag, positions, velocities), cell counts and pair lists
+identical.  FP32 and the 16-bit storages: one step from a state held in the
+storage's own representation, gas fields and positions against the FP64
+oracle within the storage's stated error."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+L = pytest.importorskip("paper_1303_2653_amd.lbdps")
+import oracle  # noqa: E402
+
+W3 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def rel(a, b, floor=0.0):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    scale = max(np.abs(b).max() if b.size else 0.0, floor)
+    if scale == 0.0:
+        return float(np.abs(a).max()) if a.size else 0.0
+    return float(np.abs(a - b).max() / scale)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def pos_err(a, b, dims):
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    d = np.minimum(d, np.asarray(dims, np.float64) - d)  # periodic
+    return float(d.max()) if d.size else 0.0
+
+
+CASES = {
+    # a few spheres moving fast: many contacts and collisions, gravity and a body force
+    "moving": dict(nx=6, ny=5, nz=7, n=120, seed=3, vel_scale=2e-2, G=(1e-6, 0.0, 2e-6)),
+    # crowded cells (the dense Ergun branch and the densest-packing hold), clusters
+    "crowded": dict(nx=5, ny=4, nz=6, n=600, seed=9, vel_scale=1e-2),
+    # a taller box with the riser's driving (body force balancing gravity)
+    "riser": dict(nx=8, ny=8, nz=24, n=400, seed=5, vel_scale=5e-3, g=(0.0, 0.0, -2.82e-7), G=(0.0, 0.0, 2e-6)),
+    "no-pressure": dict(nx=7, ny=6, nz=5, n=200, seed=4, vel_scale=1e-2, pressure_sign=0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_fp64_free_run_matches_oracle(case):
+    cfg = synth.tiny3d(**CASES[case])
+    gpu = L.Sim3(cfg, precision="fp64", diagnostics=True)
+    ref = oracle.Sim3(cfg)
+    dims = (cfg["nx"], cfg["ny"], cfg["nz"])
+    for k in range(1, 21):
+        gpu.step(1)
+        o = ref.step(record=True)
+        if k in (1, 2, 5, 10, 20):
+            f, pos, vel = gpu.state()
+            fl = gpu.fields()
+            fd, acc = gpu.drag()
+            assert (fl["ncell"] == o.ncell).all(), f"{case} step {k}: cell counts differ"
+            errs = dict(f=rel(f, ref.f, 1.0), rho=rel(fl["rho"], o.rho, 1.0), ugas=rel(fl["ugas"], o.ugas),
+                        fpg=rel(fl["fpg"], o.fpg), beta=rel(fl["beta"], o.beta), fd=rel(fd, o.fd),
+                        acc=rel(acc, o.acc), pos=pos_err(pos, ref.pos, dims), vel=rel(vel, ref.vel))
+            pairs, m = gpu.pairs()
+            say(case, "step", k, {a: f"{v:.1e}" for a, v in errs.items()}, "pairs", m, "collisions",
+                o.ncollisions)
+            assert m == len(o.pairs) and (pairs == o.pairs).all(), f"{case} step {k}: pair lists differ"
+            assert gpu.counters()["collisions"] == o.ncollisions
+            bad = {a: v for a, v in errs.items() if not v <= 1e-12}
+            assert not bad, f"{case} step {k}: beyond 1e-12: {bad}"
+
+
+def test_fp64_larger_box():
+    """A box of 24 x 20 x 32 cells with 12 000 spheres (1.6 per cell): five
+    FP64 steps within 1e-12 of the oracle, pair lists identical."""
+    cfg = synth.tiny3d(nx=24, ny=20, nz=32, n=12_000, seed=21, vel_scale=1e-2)
+    gpu = L.Sim3(cfg, precision="fp64")
+    ref = oracle.Sim3(cfg)
+    for _ in range(5):
+        gpu.step(1)
+        o = ref.step(record=True)
+    f, pos, vel = gpu.state()
+    fl = gpu.fields()
+    pairs, m = gpu.pairs()
+    errs = dict(f=rel(f, ref.f, 1.0), ugas=rel(fl["ugas"], o.ugas), fpg=rel(fl["fpg"], o.fpg),
+                pos=pos_err(pos, ref.pos, (24, 20, 32)), vel=rel(vel, ref.vel))
+    say("larger box", {a: f"{v:.1e}" for a, v in errs.items()}, "pairs", m)
+    assert m == len(o.pairs) and (pairs == o.pairs).all() and m > 1000
+    assert all(v <= 1e-12 for v in errs.values()), errs
+
+
+def _repr(cfg, f, pos, vel, prec):
+    """The state the library holds in a reduced precision, in FP64: deviations
+    rounded to float32 (then FP16 / BF16), positions as cell + float32 offset,
+    float32 velocities."""
+    import storage_repr
+    g = (np.asarray(f, np.float64).reshape(19, -1) - W3[:, None]).astype(np.float32)
+    if prec == "fp16":
+        g = g.astype(np.float16).astype(np.float32)
+    elif prec == "bf16":
+        g = storage_repr.to_bf16(g)
+    fr = (W3[:, None] + g.astype(np.float64)).reshape(np.shape(f))
+    cell = np.floor(pos)
+    off = (pos - cell).astype(np.float32).astype(np.float64)
+    off = np.where(off >= 1.0, np.float64(np.float32(0.99999994)), off)
+    return fr, cell + off, np.asarray(vel).astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 3e-7), ("fp16", 5e-7), ("bf16", 5e-7)])
+def test_reduced_precision_one_step(prec, tol):
+    """One step in FP32 arithmetic from a state held in the storage's own
+    representation (the oracle's state after 5 steps of the riser-like box):
+    populations, density, u_gas, F_pg and beta against the FP64 oracle from
+    the same state, positions within 1e-7 cells, cell counts identical.  The
+    bounds are about three times the largest error measured (FP32 9.1e-8 in
+    u_gas, FP16 1.4e-7 in u_gas, BF16 1.4e-7 in F_pg; positions 3.5e-8), so
+    that a dropped term or a wrong weight anywhere in the step fails."""
+    cfg = synth.tiny3d(**CASES["riser"])
+    warm = oracle.Sim3(cfg)
+    for _ in range(5):
+        warm.step()
+    f, pos, vel = _repr(cfg, warm.f, warm.pos, warm.vel, prec)
+    gpu = L.Sim3(cfg, precision=prec, diagnostics=True)
+    gpu.set_state(f, pos, vel)
+    gpu.step(1)
+    ref = oracle.Sim3(cfg, f=f, pos=pos, vel=vel)
+    o = ref.step(record=True)
+    g_f, g_pos, g_vel = gpu.state()
+    fl = gpu.fields()
+    errs = dict(f=rel(g_f, ref.f, 1.0), rho=rel(fl["rho"], o.rho, 1.0), ugas=rel(fl["ugas"], o.ugas),
+                fpg=rel(fl["fpg"], o.fpg), beta=rel(fl["beta"], o.beta),
+                pos=pos_err(g_pos, ref.pos, (cfg["nx"], cfg["ny"], cfg["nz"])))
+    say(prec, {a: f"{v:.1e}" for a, v in errs.items()})
+    assert (fl["ncell"] == o.ncell).all()
+    assert errs["pos"] <= 1e-7
+    bad = {a: v for a, v in errs.items() if a != "pos" and not v <= tol}
+    assert not bad, bad
+
+
+def test_capacity_overflow_is_reported_3d():
+    """Over LBDPS_MAX_CONTACTS contacts at one sphere (40 within 0.15 of a
+    point): LBDPS_E_CAPACITY at the next synchronising call, the collision
+    sweep skipped, and the context steps normally with a valid state."""
+    rng = np.random.default_rng(2)
+    pos = 4.5 + (rng.random((40, 3)) - 0.5) * 0.17
+    cfg = synth.tiny3d(nx=8, ny=8, nz=8, n=40)
+    cfg.update(pos=pos, vel=(rng.random((40, 3)) - 0.5) * 1e-3)
+    sim = L.Sim3(cfg, precision="fp64")
+    sim.step(1)
+    with pytest.raises(L.LbdpsError) as e:
+        sim.counters()
+    assert e.value.status == L.LBDPS_E_CAPACITY
+    spread = synth.tiny3d(nx=8, ny=8, nz=8, n=40, seed=5)
+    sim.set_state(None, spread["pos"], spread["vel"])
+    sim.step(2)
+    assert sim.counters()["pairs"] >= 0

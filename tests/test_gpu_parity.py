@@ -521,30 +521,36 @@ def test_error_particle_outside_domain():
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_launch_shapes_do_not_change_results(prec):
     """Every launch shape the autotuner may pick gives the same state bit for
-    bit (a dense bed: clusters of all three resolution paths)."""
-    cfg = CLUSTER_BEDS["dense_box"]()
-    cfg["vel"] = (np.random.default_rng(3).random(cfg["pos"].shape) - 0.5) * 2e-2
-    ref = None
-    for lists, gmax in ((1, 1 << 30), (4, 1 << 30), (1, 1), (256, 2)):
-        sim = L.Sim(cfg, precision=prec)
-        sim.set_tuning(cluster_lists=lists, cluster_groups_max=gmax)
-        sim.step(3)
-        st = sim.state()
-        if ref is None:
-            ref = st
-        else:
-            for a, b in zip(st[:3], ref[:3]):
-                assert (a == b).all(), (lists, gmax)
+    bit (a dense bed: clusters of all three resolution paths; the three drag
+    tile shapes, each with periodic faces and with walls)."""
+    for bc in (("periodic",) * 4, ("wall", "wall", "inlet", "outlet")):
+        cfg = synth.tiny(nx=40, ny=40, n=6000, seed=9, bc=bc)
+        cfg["vel"] = (np.random.default_rng(3).random(cfg["pos"].shape) - 0.5) * 2e-2
+        ref = None
+        for lists, gmax, tile in ((1, 1 << 30, 0), (4, 1 << 30, 0), (1, 1, 1), (256, 2, 2), (1, 1 << 30, 1),
+                                  (1, 1 << 30, 2)):
+            sim = L.Sim(cfg, precision=prec, diagnostics=True)
+            sim.set_tuning(cluster_lists=lists, cluster_groups_max=gmax, drag_tile=tile)
+            sim.step(3)
+            st = sim.state() + (sim.particles()["fd"], sim.counters())
+            if ref is None:
+                ref = st
+            else:
+                for a, b in zip(st[:3] + st[4:5], ref[:3] + ref[4:5]):
+                    assert (a == b).all(), (bc, lists, gmax, tile)
+                assert st[5] == ref[5], (bc, tile, st[5], ref[5])
     chosen = L.Sim(cfg, precision=prec).autotune(2)
-    assert chosen["cluster_lists"] >= 1 and chosen["cluster_groups_max"] >= 1
+    say(prec, "autotune chose", chosen)
+    assert chosen["cluster_lists"] >= 1 and chosen["cluster_groups_max"] >= 1 and chosen["drag_tile"] in (0, 1, 2)
 
 
-def test_fp64_flat_drag_with_dense_tiles():
+@pytest.mark.parametrize("tile", [0, 1, 2])
+def test_fp64_flat_drag_with_dense_tiles(tile):
     """A lattice of more than 2048 drag tiles (1024 x 520 cells), where the drag
     kernel deals each tile's particles out flat, with a patch of 4 particles
     per cell whose tiles exceed the flat capacity (768 particles) and take the
     per-cell passes: two FP64 steps within 1e-12 of the oracle, pair lists
-    identical."""
+    identical; under each drag tile shape (32 x 8, 64 x 4, 128 x 2)."""
     cfg = synth.riser(nx=1024, ny=520, n=10_000, seed=9, sort_ids=False, precision="fp64")
     u = synth.uniform(11, 2 * 4096).reshape(-1, 2)
     patch = np.stack([400.0 + 64.0 * u[:, 0], 200.0 + 16.0 * u[:, 1]], axis=1)  # 64 x 16 cells, 4 per cell
@@ -552,11 +558,12 @@ def test_fp64_flat_drag_with_dense_tiles():
     cfg["pos"] = pos[synth.cell_order(pos, cfg["nx"])]
     cfg["vel"] = (np.random.default_rng(6).random(cfg["pos"].shape) - 0.5) * 1e-2
     gpu = L.Sim(cfg, precision="fp64", diagnostics=True)
+    gpu.set_tuning(drag_tile=tile)
     ref = oracle.Sim(cfg)
     for k in (1, 2):
         gpu.step(1)
         o = ref.step(record=True)
-        compare_step(gpu, o, ref, 1e-12, what=f"flat drag step {k}")
+        compare_step(gpu, o, ref, 1e-12, what=f"flat drag (tile {tile}) step {k}")
     pairs, m = gpu.pairs()
     assert m == len(o.pairs) and (pairs == o.pairs).all()
 
@@ -642,3 +649,69 @@ def test_circulating_loop(prec):
         d = np.abs(pos - ref.pos)
         d[:, 1] = np.minimum(d[:, 1], cfg["ny"] - d[:, 1])
         assert rel(f, ref.f, 1.0) < 1e-5 and d.max() < 1e-5 and rel(vel, ref.vel) < 1e-5
+
+
+# ---------------------------------------------------------------- outlet solids flux and capacity
+def _loop_bed(n=300, seed=3):
+    """A small circulating bed (gas inlet at the bottom, outlet at the top,
+    walls at x, particles periodic in y) with fast random particles, so that
+    many cross the outlet plane each step."""
+    rng = np.random.default_rng(seed)
+    pos = np.stack([0.3 + 11.4 * rng.random(n), 16 * rng.random(n)], 1)
+    vel = (rng.random((n, 2)) - 0.5) * np.array([0.05, 1.2])
+    cfg = synth.tiny(nx=12, ny=16, n=n, bc=("wall", "wall", "inlet", "outlet"), g=(0.0, -1e-5),
+                     particles_periodic_y=1)
+    cfg.update(pos=pos, vel=vel)
+    return cfg
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_outlet_crossings_match_the_oracle(prec):
+    """The outlet solids flux of Sec. 3.2 (lbdps_outlet_crossings): the net
+    number of particles across the outlet plane y = ny per step equals the
+    oracle's count step by step (FP64: 20 steps; FP32: the first step from a
+    shared FP32-held state), and the flux follows as m net / (nx steps)."""
+    cfg = _loop_bed()
+    if prec == "fp32":
+        f, pos, vel = storage_repr.state(cfg, oracle.equilibrium_state(12, 16), cfg["pos"], cfg["vel"], "fp32")
+        cfg = dict(cfg, pos=pos, vel=vel)
+    gpu = L.Sim(cfg, precision=prec)
+    ref = oracle.Sim(cfg)
+    total = 0
+    for k in range(20 if prec == "fp64" else 1):
+        gpu.step(1)
+        o = ref.step(record=True)
+        net, steps = gpu.outlet_crossings()
+        assert steps == 1 and net == o.ncross, (k, net, o.ncross)
+        total += net
+    say(prec, "net crossings", total)
+    assert total != 0
+    gpu.step(3)
+    net, steps = gpu.outlet_crossings()
+    assert steps == 3
+    walls = L.Sim(dict(cfg, particles_periodic_y=0, bc=["wall"] * 4), precision=prec)
+    walls.step(5)
+    assert walls.outlet_crossings() == (0, 5)
+
+
+def test_capacity_overflow_is_reported():
+    """More than LBDPS_MAX_CONTACTS contacts at one particle: 40 spheres within
+    0.2 of one point (each touches the other 39).  The contact kernel caps the
+    row and latches the flag, the collision resolution is skipped, every
+    kernel ends normally, and the next synchronising call returns
+    LBDPS_E_CAPACITY; the context steps normally once given a valid state."""
+    rng = np.random.default_rng(2)
+    ang, rad = 2 * np.pi * rng.random(40), 0.2 * np.sqrt(rng.random(40))
+    pos = np.stack([5.5 + rad * np.cos(ang), 5.5 + rad * np.sin(ang)], 1)
+    cfg = synth.tiny(nx=10, ny=10, n=40, bc=("periodic",) * 4, g=(0.0, 0.0))
+    cfg.update(pos=pos, vel=(rng.random((40, 2)) - 0.5) * 1e-3)
+    for prec in ("fp64", "fp32"):
+        sim = L.Sim(cfg, precision=prec)
+        sim.step(1)
+        with pytest.raises(L.LbdpsError) as e:
+            sim.counters()
+        assert e.value.status == L.LBDPS_E_CAPACITY
+        spread = synth.tiny(nx=10, ny=10, n=40, bc=("periodic",) * 4, g=(0.0, 0.0), seed=5)
+        sim.set_state(None, spread["pos"], spread["vel"])
+        sim.step(2)
+        assert sim.counters()["pairs"] >= 0
