@@ -384,7 +384,10 @@ def run_d3q19(args, torch, L):
             "data": "synthetic (gas at rest, periodic box" + (", seeded Poisson solids per cell)" if psm else ")"),
             "config": {"workload": f"d3q19-{'psm' if psm else 'gas'}-{nx}x{ny}x{nz}-{prec}", "nx": nx, "ny": ny,
                        "nz": nz, "precision": prec, "tau": 0.6, "particles": int(1e7) if psm else 0,
-                       **({"d_p": 0.5} if psm else {})},
+                       # the sphere count is kept, so the mean solid fraction is
+                       # 1e7 (pi d^3 / 6) / C, not the 0.1 a denser riser would have
+                       **({"d_p": 0.5, "solid_fraction_3d": round(1e7 * math.pi * 0.5 ** 3 / 6 / C, 5)}
+                          if psm else {})},
             "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                          "traffic": measured_traffic(args.workload, kern) if prec == "fp16" else None,
