@@ -135,7 +135,7 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None, tuning=None):
     stream = sim.stream
     sim.step(warmup)
     if tuning is None:
-        tuning = sim.autotune(4)  # launch shape of the cluster resolution (results do not depend on it)
+        tuning = sim.autotune(4)  # launch shapes (results do not depend on them)
     else:
         sim.set_tuning(**tuning)
     torch.cuda.synchronize()
@@ -162,15 +162,19 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None, tuning=None):
     sim.time_kernels([])
     counters = sim.counters()
     out = dict(ms=ms, breakdown_us=breakdown, dominant=dominant, dom_ms=kt[0], dom_launches=kt[1],
-               pairs=counters["pairs"], tuning=tuning)
+               pairs=counters["pairs"], tuning=sim.tuning())
     sim.close()
     return out
 
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_2653_amd", "csrc", f)
-                  for f in ("kernels.hpp", "device.hpp", "lattice3d.hpp")]
-KERNEL_KEYS = {"collide": "k_collide", "drag": "k_drag", "scan": "k_scan_cells", "scatter": "k_scatter",
-               "contacts": "k_contacts", "resolve": "k_resolve_clusters", "k3_bgk": "k3_bgk", "k3_psm": "k3_psm"}
+                  for f in ("kernels.hpp", "device.hpp", "lattice3d.hpp", "spheres_tile.hpp")]
+# the kernels of each phase (either form of a kernel, and every launch of the
+# phase: the collision stage's tile kernel with the contact kernel on what it
+# left, the cluster kernel with the ordered sweep)
+KERNEL_KEYS = {"collide": ("k_collide",), "drag": ("k_drag", "k_drag_flat"), "scan": ("k_scan_cells",),
+               "scatter": ("k_scatter",), "contacts": ("k_spheres_tile", "k_contacts", "k_contacts_small"),
+               "resolve": ("k_resolve_clusters", "k_resolve"), "k3_bgk": ("k3_bgk",), "k3_psm": ("k3_psm", "k3_psm_pairs")}
 
 
 def kernel_source_hash() -> str:
@@ -236,14 +240,15 @@ def summarize(args):
         lines += ["", f"HBM-side bytes per launch: FETCH_SIZE x {f_scale:.3f} + WRITE_SIZE x {w_scale:.3f}; the factors "
                   f"make a plain {args.copy_bytes} byte copy ({copy_name}) read and write exactly its size.", "",
                   "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes per launch |", "|---|---:|---:|---:|"]
-        for key, kname in KERNEL_KEYS.items():
-            # the phase's kernel under either of its forms (k_drag / k_drag_flat, k_contacts / k_contacts_small)
-            names = [n for n in fetch if (n == kname or n.startswith(kname + "_")) and n in write]
+        for key, knames in KERNEL_KEYS.items():
+            names = [n for n in knames if n in fetch and n in write]
             if names:
-                kname = names[0]
-                b = fetch[kname] * f_scale + write[kname] * w_scale
+                b = 0.0
+                for kname in names:
+                    bk = fetch[kname] * f_scale + write[kname] * w_scale
+                    b += bk
+                    lines.append(f"| {kname} | {fetch[kname] / 1024:.1f} | {write[kname] / 1024:.1f} | {int(bk)} |")
                 traffic[key] = int(b)
-                lines.append(f"| {kname} | {fetch[kname] / 1024:.1f} | {write[kname] / 1024:.1f} | {int(b)} |")
         lines += ["", "Counter commands: the same program under `rocprofv3 --pmc FETCH_SIZE` and "
                   "`rocprofv3 --pmc WRITE_SIZE` (one counter per run), and `bench.py --copy-probe "
                   f"{args.copy_bytes}` under each for the scale factors."]
@@ -584,8 +589,9 @@ def main():
     ap.add_argument("--n-sub", type=int, default=1, help="particle sub-steps per lattice step")
     ap.add_argument("--cs-smag", type=float, default=None, help="Smagorinsky constant (sub-grid model on)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="seconds of each oracle leg")
-    ap.add_argument("--tuning", default=None, metavar="LISTS,GROUPS",
-                    help="fixed cluster-resolution launch shape instead of the autotuner (profiling runs)")
+    ap.add_argument("--tuning", default=None, metavar="LISTS,GROUPS[,DRAG[,SPHERE]]",
+                    help="fixed launch shapes instead of the autotuner (profiling runs): cluster lists and "
+                         "groups, drag tile, collision-stage tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -635,8 +641,8 @@ def main():
     C, N = cfg["nx"] * cfg["ny"], len(cfg["pos"])
     fixed = None
     if args.tuning:
-        lists, groups = (int(v) for v in args.tuning.split(","))
-        fixed = dict(cluster_lists=lists, cluster_groups_max=groups)
+        vals = [int(v) for v in args.tuning.split(",")]
+        fixed = dict(zip(("cluster_lists", "cluster_groups_max", "drag_tile", "sphere_tile"), vals))
     r = run_gpu(cfg, args.precision, args.steps, args.warmup, torch, L, tuning=fixed)
     s = r["ms"] / 1e3
     mlups = C * args.steps / s / 1e6
@@ -682,7 +688,7 @@ def main():
         "model_bytes_per_step": int(model),
         "model_bw_frac": round(model * args.steps / s / 1e9 / HBM_PEAK_GBS, 4),
         "contact_pairs": r["pairs"],
-        "autotune": [r["tuning"]["cluster_lists"], r["tuning"]["cluster_groups_max"]],
+        "autotune": [r["tuning"][f] for f in ("cluster_lists", "cluster_groups_max", "drag_tile", "sphere_tile")],
         "kernel_us": {k: round(v, 2) for k, v in r["breakdown_us"].items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

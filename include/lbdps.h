@@ -188,10 +188,11 @@ lbdps_status lbdps_get_particles(lbdps_ctx *ctx, double *d_pos, double *d_vel, d
 lbdps_status lbdps_get_accel(lbdps_ctx *ctx, double *d_acc);
 
 /*
- * Contact pairs (i, j), i < j by particle index, of the most recent hard-sphere
- * stage, in lexicographic order, device int32 [cap][2].  *n_out receives the
- * number of pairs (also when it exceeds cap; then only cap are written).
- * Synchronises the stream.
+ * Contact pairs (i, j), i < j by particle index, at the current positions
+ * (after a step: those of its last hard-sphere stage, since positions do not
+ * change after it), in lexicographic order, device int32 [cap][2] (Sec. 2.2:
+ * centres at most d_p apart).  *n_out receives the number of pairs (also when
+ * it exceeds cap; then only cap are written).  Synchronises the stream.
  */
 lbdps_status lbdps_get_pairs(lbdps_ctx *ctx, int32_t *d_pairs, int64_t cap, int64_t *n_out);
 
@@ -421,12 +422,19 @@ lbdps_status lbdps_kernel_times(lbdps_ctx *ctx, double *h_ms, int64_t *h_launche
  *   drag_tile          cells of the drag kernel's workgroup tile (its node fields
  *                      staged in LDS): 0 = 32 x 8 (default), 1 = 64 x 4,
  *                      2 = 128 x 2.  The beds of a batch share one.
+ *   sphere_tile        cells of the collision stage's workgroup tile, whose
+ *                      particles and the ring of cells around it are held in LDS
+ *                      (contacts, clusters inside the tile resolved there, the
+ *                      rest through neighbour rows): 0 = none, every particle
+ *                      through the rows, 1 = 32 x 8 (default), 2 = 16 x 16,
+ *                      3 = 64 x 4.  A batched step takes the rows.
  * A context starts with the defaults.
  */
 typedef struct {
   int32_t cluster_lists;
   int32_t cluster_groups_max;
   int32_t drag_tile;
+  int32_t sphere_tile;
 } lbdps_tuning;
 lbdps_status lbdps_set_tuning(lbdps_ctx *ctx, const lbdps_tuning *t);
 lbdps_status lbdps_get_tuning(lbdps_ctx *ctx, lbdps_tuning *t);
@@ -434,9 +442,10 @@ lbdps_status lbdps_get_tuning(lbdps_ctx *ctx, lbdps_tuning *t);
 /* Autotuner: run `steps` steps under each candidate launch shape, twice over
  * the candidates in turn, time them with hipEvents on the context's stream and
  * keep the candidate with the fastest of its two times (written to *chosen if
- * not NULL): first the cluster-resolution shapes (9 candidates), then the drag
- * tile shapes (3) under the chosen one.  The bed advances by
- * 2 x steps x 12.  Synchronises. */
+ * not NULL): first the collision stage's tile shapes (4, none among them),
+ * then the cluster-resolution shapes (9) and then the drag tile shapes (3),
+ * each under the choices before it.  The bed advances by 2 x steps x 16.
+ * Synchronises. */
 lbdps_status lbdps_autotune(lbdps_ctx *ctx, int32_t steps, lbdps_tuning *chosen);
 
 /* Release the host context (the workspace stays the caller's).  A bed of a

@@ -1319,7 +1319,12 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, c
 // sorted by particle index, as 64-bit entries (index << 32 | slot).  A particle
 // without contacts gets its wall collision here; the others get it after their
 // binary collisions.
-template <int P, int W = CONTACT_W>
+// MODE: CT_ALL, every particle; CT_LEFT, only the particles the tile kernel
+// left (done < DONE_WHOLE), the others keep their marks and take no part;
+// CT_ROWS, the rows and degrees of every particle and nothing else (no wall
+// pass, marks, counters or flags), for the pair listing.
+constexpr int CT_ALL = 0, CT_LEFT = 1, CT_ROWS = 2;
+template <int P, int W = CONTACT_W, int MODE = CT_ALL>
 __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
     const int32_t *__restrict__ cs, Consts<typename Prec<P>::T> k, Adj adj, int32_t *__restrict__ deg,
     int32_t *__restrict__ done, int32_t *ticket, int32_t *flags, long long *pair_part, long long *wall_part,
@@ -1331,11 +1336,14 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
   const int s = bidx * BLOCK + threadIdx.x;
   long long fwd = 0, nwall = 0;
   bool cand = false;  // has contacts, all with higher indices: a possible cluster root
-  if (s == 0) {
+  bool by_wall_pass = true;
+  if (MODE != CT_ROWS && s == 0) {
     *ticket = 0;
     *need_sweep = 0;
   }
-  if (s < k.npart) {
+  bool act = s < k.npart;
+  if constexpr (MODE == CT_LEFT) act = act && ldu(done, s) < DONE_WHOLE;
+  if (act) {
     const int key = pt.key[s];
     const int id = pt.pid[s];
     const T x = pt.px[s], y = pt.py[s];
@@ -1553,12 +1561,17 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
       });
       cnt = m;
     }
-    if (over) atomicOr(&flags[FLAG_CAPACITY], 1);
-    if (cnt > 0) cand = (int)((cnt <= CONTACT_REG ? r[0] : row[0]) >> 32) > id;
     deg[s] = cnt;
-    done[s] = 0;
-    if (cnt > 0) chunk_busy[id / RES_CHUNK] = 1;  // the resolution visits this chunk of indices
-    if (cnt == 0 && by_wall) {  // no binary collision: the wall pass can run now
+    if constexpr (MODE == CT_ROWS) {
+      fwd = 0;
+      by_wall_pass = false;
+    } else {
+      if (over) atomicOr(&flags[FLAG_CAPACITY], 1);
+      if (cnt > 0) cand = (int)((cnt <= CONTACT_REG ? r[0] : row[0]) >> 32) > id;
+      done[s] = 0;
+      if (cnt > 0) chunk_busy[id / RES_CHUNK] = 1;  // the resolution visits this chunk of indices
+    }
+    if (by_wall_pass && cnt == 0 && by_wall) {  // no binary collision: the wall pass can run now
       const int h = Pos<P>::walls(k, cx, cy, x, y, vx0, vy0);
       if (h) {
         pt.vx[s] = vx0;
@@ -1567,6 +1580,7 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
       }
     }
   }
+  if constexpr (MODE == CT_ROWS) return;  // uniform
   // candidate roots of this workgroup, compacted to the front of its segment
   int nc;
   const int off = block_excl_scan(cand ? 1 : 0, shi, nc);
@@ -1579,7 +1593,7 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
     rcount[bidx] = nc;
   }
 }
-template <int P>
+template <int P, int MODE = CT_ALL>
 __global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void k_contacts(Parts<typename Prec<P>::T> pt, const int32_t *__restrict__ cs,
                                                     Consts<typename Prec<P>::T> k, Adj adj,
                                                     int32_t *__restrict__ deg, int32_t *__restrict__ done,
@@ -1587,20 +1601,20 @@ __global__ __launch_bounds__(BLOCK) LBDPS_WAVES8 void k_contacts(Parts<typename 
                                                     long long *wall_part, int32_t *__restrict__ chunk_busy,
                                                     int32_t *need_sweep, long long *__restrict__ roots,
                                                     int32_t *__restrict__ rcount) {
-  contacts_body<P>(xcd_block<XCD_RUN_CONTACTS>(blockIdx.x, gridDim.x), gridDim.x, pt, cs, k, adj, deg, done, ticket, flags, pair_part, wall_part, chunk_busy,
+  contacts_body<P, CONTACT_W, MODE>(xcd_block<XCD_RUN_CONTACTS>(blockIdx.x, gridDim.x), gridDim.x, pt, cs, k, adj, deg, done, ticket, flags, pair_part, wall_part, chunk_busy,
       need_sweep, roots, rcount);
 }
 // Grids whose workgroups are all resident at once (CONTACTS_SMALL_MAX): a wider
 // early-loaded window at six waves per SIMD, since latency rather than the
 // number of waves in flight bounds such a launch.
 constexpr int CONTACTS_SMALL_MAX = 1536;
-template <int P>
+template <int P, int MODE = CT_ALL>
 __global__ __launch_bounds__(BLOCK) LBDPS_WAVES6 void k_contacts_small(Parts<typename Prec<P>::T> pt,
     const int32_t *__restrict__ cs, Consts<typename Prec<P>::T> k, Adj adj, int32_t *__restrict__ deg,
     int32_t *__restrict__ done, int32_t *ticket, int32_t *flags, long long *pair_part, long long *wall_part,
     int32_t *__restrict__ chunk_busy, int32_t *need_sweep, long long *__restrict__ roots,
     int32_t *__restrict__ rcount) {
-  contacts_body<P, CONTACT_W_SMALL>(xcd_block<XCD_RUN_CONTACTS>(blockIdx.x, gridDim.x), gridDim.x, pt, cs, k, adj,
+  contacts_body<P, CONTACT_W_SMALL, MODE>(xcd_block<XCD_RUN_CONTACTS>(blockIdx.x, gridDim.x), gridDim.x, pt, cs, k, adj,
                                     deg, done, ticket, flags, pair_part, wall_part, chunk_busy, need_sweep, roots,
                                     rcount);
 }

@@ -19,6 +19,7 @@
 #include "kernels.hpp"
 #include "lattice3d.hpp"
 #include "lbdps.h"
+#include "spheres_tile.hpp"
 
 using namespace lbdps;
 
@@ -221,7 +222,8 @@ struct lbdps_ctx {
   bool bins_valid = false;
   long long step = 0;
   bool in_batch = false;  // owned by a batch: destroyed with it
-  lbdps_tuning tune{RC_LISTS, RC_GROUPS_MAX, 0};
+  lbdps_tuning tune{RC_LISTS, RC_GROUPS_MAX, 0, 1};
+  int sphere_tiles = 0;  // tiles of the tile kernel in the most recent collision stage (0: not used)
   int drag_blocks = 0;  // drag workgroups of the most recent step (its partial sums)
   int cluster_groups() const { return cluster_blocks(n, tune.cluster_lists, tune.cluster_groups_max); }
   DConsts dc{};
@@ -243,6 +245,7 @@ struct lbdps_ctx {
   long long *roots = nullptr;
   int32_t *rcount = nullptr;
   long long *collc_part = nullptr, *wallc_part = nullptr;
+  long long *tile_part = nullptr;  // the tile kernel's pairs, collisions and wall hits per tile
   int ntiles = 0;
   double *cons_pc = nullptr, *cons_pp = nullptr, *cons_out = nullptr;
   double *eg_tab = nullptr;        // FP64 gas voidage per particle count (Eq. 11), for lbdps_voidage
@@ -315,6 +318,13 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   int32_t *rcount = cv.take<int32_t>(nbN);
   int32_t *chunk_busy = cv.take<int32_t>(N / RES_CHUNK + 1), *need_sweep = cv.take<int32_t>(4);
   long long *collc_part = cv.take<long long>(nbN), *wallc_part = cv.take<long long>(nbN);
+  size_t nst = 1;  // tiles of the sphere tile shape with the most of them
+  for (int t = 1; t < SPHERE_TILES; ++t) {
+    int tw, th;
+    sphere_tile_dims(t, tw, th);
+    nst = std::max(nst, (size_t)st_tiles(p.nx, p.ny, tw, th));
+  }
+  long long *tile_part = cv.take<long long>(3 * nst);
   double *pc = cv.take<double>(NB_CONS * 3), *pp = cv.take<double>(NB_CONS * 2), *co = cv.take<double>(8);
   double *egt = cv.take<double>((size_t)lut_rows(p.d_p));
   long long *obs = cv.take<long long>((size_t)nblocks(p.nx) + 1);
@@ -373,6 +383,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->chunk_busy = chunk_busy;
     x->need_sweep = need_sweep;
     x->collc_part = collc_part;
+    x->tile_part = tile_part;
     x->wallc_part = wallc_part;
     x->ntiles = (int)ntiles;
     x->cons_pc = pc;
@@ -562,14 +573,42 @@ template <int P> struct Impl {
 
   // extra: a further sub-step of the same lattice step (its launches add time,
   // not launch counts)
+  using TileKern = void (*)(Parts<T>, const int32_t *, Consts<T>, int32_t *, long long *);
+  static TileKern tile_kernel(int t) {
+    switch (t) {
+      case 2: return k_spheres_tile<P, 16, 16>;
+      case 3: return k_spheres_tile<P, 64, 4>;
+      default: return k_spheres_tile<P, 32, 8>;
+    }
+  }
+  static int sphere_tiles(const lbdps_ctx *x, int t) {
+    int tw, th;
+    sphere_tile_dims(t, tw, th);
+    return st_tiles(x->nx, x->ny, tw, th);
+  }
+  // The collision stage (A6 + A7).  With a sphere tile shape, the tile kernel
+  // resolves the clusters that lie inside its tiles, and the contact kernel
+  // builds rows only for the particles it left; the cluster kernel and the
+  // ordered sweep then take those as before.
   static void hard_spheres(lbdps_ctx *x, bool extra = false) {
     const int N = (int)x->n;
     if (N == 0) return;
     const Consts<T> k = consts(x);
-    tlaunch(x, LBDPS_K_CONTACTS, extra, nblocks(N) <= CONTACTS_SMALL_MAX ? k_contacts_small<P> : k_contacts<P>,
-            dim3(nblocks(N)), parts(x, x->cp), (const int32_t *)x->cs, k,
-            x->adj(), x->deg, x->done, x->ticket, x->flags, x->pair_part, x->wall0_part, x->chunk_busy,
-            x->need_sweep, x->roots, x->rcount);
+    const int st = x->tune.sphere_tile;
+    x->sphere_tiles = st > 0 ? sphere_tiles(x, st) : 0;
+    if (st > 0) {
+      tlaunch(x, LBDPS_K_CONTACTS, extra, tile_kernel(st), dim3(x->sphere_tiles), parts(x, x->cp),
+              (const int32_t *)x->cs, k, x->done, x->tile_part);
+      tlaunch(x, LBDPS_K_CONTACTS, true,
+              nblocks(N) <= CONTACTS_SMALL_MAX ? k_contacts_small<P, CT_LEFT> : k_contacts<P, CT_LEFT>,
+              dim3(nblocks(N)), parts(x, x->cp), (const int32_t *)x->cs, k, x->adj(), x->deg, x->done, x->ticket,
+              x->flags, x->pair_part, x->wall0_part, x->chunk_busy, x->need_sweep, x->roots, x->rcount);
+    } else {
+      tlaunch(x, LBDPS_K_CONTACTS, extra, nblocks(N) <= CONTACTS_SMALL_MAX ? k_contacts_small<P> : k_contacts<P>,
+              dim3(nblocks(N)), parts(x, x->cp), (const int32_t *)x->cs, k,
+              x->adj(), x->deg, x->done, x->ticket, x->flags, x->pair_part, x->wall0_part, x->chunk_busy,
+              x->need_sweep, x->roots, x->rcount);
+    }
     tlaunch(x, LBDPS_K_RESOLVE, extra, k_resolve_clusters<P>, dim3(x->cluster_groups()), parts(x, x->cp), x->adj(),
             (const int32_t *)x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part,
             (const long long *)x->roots, (const int32_t *)x->rcount, nblocks(N));
@@ -626,6 +665,17 @@ template <int P> struct Impl {
     if (!x->bins_valid) rebin(x);
     hard_spheres(x);
     return launch_status("lbdps_collide_particles");
+  }
+
+  // Neighbour rows and degrees of every particle at the current positions (the
+  // contacts of the most recent collision stage: positions do not change
+  // after it), for the pair listing; nothing else is written.
+  static void rows(lbdps_ctx *x) {
+    const int N = (int)x->n;
+    if (!x->bins_valid) rebin(x);
+    hipLaunchKernelGGL((k_contacts<P, CT_ROWS>), dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
+                       (const int32_t *)x->cs, consts(x), x->adj(), x->deg, x->done, x->ticket, x->flags,
+                       x->pair_part, x->wall0_part, x->chunk_busy, x->need_sweep, x->roots, x->rcount);
   }
 
   static lbdps_status set_state(lbdps_ctx *x, const double *d_f, const double *d_pos, const double *d_vel,
@@ -1029,6 +1079,10 @@ lbdps_status lbdps_get_pairs(lbdps_ctx *x, int32_t *d_pairs, int64_t cap, int64_
   const int N = (int)x->n;
   *n_out = 0;
   if (N == 0) return sync_and_check(x, "lbdps_get_pairs");
+  dispatch(x, [&](auto impl) {
+    decltype(impl)::rows(x);
+    return LBDPS_OK;
+  });
   // rank and perm are free between steps: counts, then offsets
   hipLaunchKernelGGL(k_pairs_count, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, x->slot, x->adj(), x->deg, N, x->rank);
   dispatch(x, [&](auto impl) {
@@ -1125,6 +1179,15 @@ lbdps_status lbdps_counters(lbdps_ctx *x, int64_t h_out[4]) {
       if (st != LBDPS_OK) return st;
       for (int b = 0; b < len[j]; ++b) h_out[dst[j]] += buf[b];
     }
+  // the tile kernel's pairs, collisions and wall hits of the particles it resolved
+  const int nst = x->n > 0 ? x->sphere_tiles : 0;
+  if (nst > 0) {
+    buf.resize((size_t)3 * nst);
+    st = check_hip(hipMemcpy(buf.data(), x->tile_part, (size_t)3 * nst * 8, hipMemcpyDeviceToHost), "lbdps_counters");
+    if (st != LBDPS_OK) return st;
+    for (int j = 0; j < 3; ++j)
+      for (int b = 0; b < nst; ++b) h_out[j] += buf[(size_t)j * nst + b];
+  }
   if (x->p.diagnostics && x->n > 0) {
     st = check_hip(hipMemcpy(buf.data(), x->zero_part, (size_t)nbC * 8, hipMemcpyDeviceToHost), "lbdps_counters");
     if (st != LBDPS_OK) return st;
@@ -1168,6 +1231,8 @@ lbdps_status lbdps_set_tuning(lbdps_ctx *x, const lbdps_tuning *t) {
   if (t->cluster_groups_max < 1) return fail(LBDPS_E_INVALID, "cluster_groups_max must be >= 1");
   if (t->drag_tile < 0 || t->drag_tile >= DRAG_TILES)
     return fail(LBDPS_E_INVALID, "drag_tile must be 0 (32x8), 1 (64x4) or 2 (128x2)");
+  if (t->sphere_tile < 0 || t->sphere_tile >= SPHERE_TILES)
+    return fail(LBDPS_E_INVALID, "sphere_tile must be 0 (none), 1 (32x8), 2 (16x16) or 3 (64x4)");
   x->tune = *t;
   return LBDPS_OK;
 }
@@ -1219,12 +1284,9 @@ lbdps_status lbdps_autotune(lbdps_ctx *x, int32_t steps, lbdps_tuning *chosen) {
   // shapes first (under the context's drag tile), then the drag tile shapes
   // under the chosen cluster shape: the two phases do not share work.
   const lbdps_tuning start = x->tune;
-  float t[kTuneN + DRAG_TILES];
-  lbdps_tuning cand[kTuneN + DRAG_TILES];
-  for (int c = 0; c < kTuneN; ++c) {
-    cand[c] = kTuneCandidates[c];
-    cand[c].drag_tile = start.drag_tile;
-  }
+  constexpr int NC = SPHERE_TILES + kTuneN + DRAG_TILES;
+  float t[NC];
+  lbdps_tuning cand[NC];
   auto run = [&](int c0, int c1) -> lbdps_status {
     for (int round = 0; round < 2; ++round)
       for (int c = c0; c < c1; ++c) {
@@ -1242,13 +1304,27 @@ lbdps_status lbdps_autotune(lbdps_ctx *x, int32_t steps, lbdps_tuning *chosen) {
     x->tune = cand[bc];
     return LBDPS_OK;
   };
-  lbdps_status st = run(0, kTuneN);
+  // the collision stage's tile shapes (none among them), then the cluster
+  // shapes, then the drag tiles, each under the choices before it
+  for (int c = 0; c < SPHERE_TILES; ++c) {
+    cand[c] = start;
+    cand[c].sphere_tile = c;
+  }
+  lbdps_status st = run(0, SPHERE_TILES);
+  if (st == LBDPS_OK) {
+    for (int c = 0; c < kTuneN; ++c) {
+      cand[SPHERE_TILES + c] = kTuneCandidates[c];
+      cand[SPHERE_TILES + c].drag_tile = x->tune.drag_tile;
+      cand[SPHERE_TILES + c].sphere_tile = x->tune.sphere_tile;
+    }
+    st = run(SPHERE_TILES, SPHERE_TILES + kTuneN);
+  }
   if (st == LBDPS_OK) {
     for (int d = 0; d < DRAG_TILES; ++d) {
-      cand[kTuneN + d] = x->tune;
-      cand[kTuneN + d].drag_tile = d;
+      cand[SPHERE_TILES + kTuneN + d] = x->tune;
+      cand[SPHERE_TILES + kTuneN + d].drag_tile = d;
     }
-    st = run(kTuneN, kTuneN + DRAG_TILES);
+    st = run(SPHERE_TILES + kTuneN, NC);
   }
   if (st != LBDPS_OK) {
     x->tune = start;
@@ -1485,6 +1561,7 @@ template <int P> struct BatchImpl {
 
   static void advance(lbdps_batch *B, int nsteps) {
     for (auto *x : B->beds) {
+      x->sphere_tiles = 0;  // the batched collision stage is the row path
       x->cf ^= nsteps & 1;
       if (x->n > 0) x->cp ^= nsteps & 1;
       x->step += nsteps;

@@ -57,7 +57,7 @@ class lbdps3_params(ctypes.Structure):
 
 
 class lbdps_tuning(ctypes.Structure):
-    _fields_ = [("cluster_lists", c_i32), ("cluster_groups_max", c_i32), ("drag_tile", c_i32)]
+    _fields_ = [("cluster_lists", c_i32), ("cluster_groups_max", c_i32), ("drag_tile", c_i32), ("sphere_tile", c_i32)]
 
 
 if not os.path.exists(LIB_PATH):

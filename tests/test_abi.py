@@ -155,7 +155,7 @@ def test_batch_create_rejects_small_workspace_before_device():
 
 
 def test_tuning_struct_layout():
-    assert ctypes.sizeof(L.lbdps_tuning) == 12
+    assert ctypes.sizeof(L.lbdps_tuning) == 16 and L.lbdps_tuning.sphere_tile.offset == 12
     assert L.lbdps_set_tuning(None, None) == L.LBDPS_E_INVALID
     assert L.lbdps_autotune(None, 1, None) == L.LBDPS_E_INVALID
     assert L.lbdps_batch_autotune(None, 1, None) == L.LBDPS_E_INVALID

@@ -210,16 +210,19 @@ CLUSTER_BEDS = {
 }
 
 
+@pytest.mark.parametrize("sphere_tile", [0, 1])
 @pytest.mark.parametrize("name", sorted(CLUSTER_BEDS))
-def test_fp64_collision_stage_clusters(name):
+def test_fp64_collision_stage_clusters(name, sphere_tile):
     """Hard-sphere stage on a whole bed with random velocities.  Contact
-    clusters of up to 8 members are resolved by one lane, up to 256 by a whole
+    clusters inside one tile of cells are resolved there (sphere_tile 1); of
+    the rest, clusters of up to 8 members by one lane, up to 256 by a whole
     workgroup in LDS, larger ones by the ordered sweep; in every case the
     velocities equal the oracle's sequential lexicographic sweep bit for bit."""
     cfg = CLUSTER_BEDS[name]()
     rng = np.random.default_rng(21)
     vel = (rng.random(cfg["pos"].shape) - 0.5) * 2e-2
     gpu = L.Sim(dict(cfg, vel=vel), precision="fp64")
+    gpu.set_tuning(sphere_tile=sphere_tile)
     gpu.collide_particles()
     p = oracle.make_params(cfg)
     ref_pairs = oracle.contacts(p, cfg["pos"])
@@ -522,15 +525,16 @@ def test_error_particle_outside_domain():
 def test_launch_shapes_do_not_change_results(prec):
     """Every launch shape the autotuner may pick gives the same state bit for
     bit (a dense bed: clusters of all three resolution paths; the three drag
-    tile shapes, each with periodic faces and with walls)."""
+    tile shapes and the collision stage's tile shapes, each with periodic
+    faces and with walls)."""
     for bc in (("periodic",) * 4, ("wall", "wall", "inlet", "outlet")):
         cfg = synth.tiny(nx=40, ny=40, n=6000, seed=9, bc=bc)
         cfg["vel"] = (np.random.default_rng(3).random(cfg["pos"].shape) - 0.5) * 2e-2
         ref = None
-        for lists, gmax, tile in ((1, 1 << 30, 0), (4, 1 << 30, 0), (1, 1, 1), (256, 2, 2), (1, 1 << 30, 1),
-                                  (1, 1 << 30, 2)):
+        for lists, gmax, tile, sph in ((1, 1 << 30, 0, 0), (4, 1 << 30, 0, 0), (1, 1, 1, 0), (256, 2, 2, 0),
+                                       (1, 1 << 30, 1, 1), (1, 1 << 30, 2, 2), (1, 1, 0, 3), (4, 2, 0, 1)):
             sim = L.Sim(cfg, precision=prec, diagnostics=True)
-            sim.set_tuning(cluster_lists=lists, cluster_groups_max=gmax, drag_tile=tile)
+            sim.set_tuning(cluster_lists=lists, cluster_groups_max=gmax, drag_tile=tile, sphere_tile=sph)
             sim.step(3)
             st = sim.state() + (sim.particles()["fd"], sim.counters())
             if ref is None:
@@ -542,6 +546,7 @@ def test_launch_shapes_do_not_change_results(prec):
     chosen = L.Sim(cfg, precision=prec).autotune(2)
     say(prec, "autotune chose", chosen)
     assert chosen["cluster_lists"] >= 1 and chosen["cluster_groups_max"] >= 1 and chosen["drag_tile"] in (0, 1, 2)
+    assert chosen["sphere_tile"] in (0, 1, 2, 3)
 
 
 @pytest.mark.parametrize("tile", [0, 1, 2])
