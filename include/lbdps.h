@@ -397,6 +397,14 @@ typedef enum {
 } lbdps_kernel;
 
 /*
+ * How the most recent collision stage (Sec. 2.2, Eqs. 17-18) was split:
+ * h_out[0] = particles whose contacts and collisions the tile kernel resolved
+ * in LDS (sphere_tile > 0), h_out[1] = particles it left to the neighbour rows
+ * (all of them with sphere_tile 0 or after a batched step).  Synchronises.
+ */
+lbdps_status lbdps_tile_stats(lbdps_ctx *ctx, int64_t h_out[2]);
+
+/*
  * Time every later launch of the kernels in `mask` (bit k = lbdps_kernel k):
  * the launch carries a pair of hipEvents that its dispatch stamps at the
  * kernel's start and end (hipExtLaunchKernel), so the time is the kernel's own.
@@ -426,7 +434,7 @@ lbdps_status lbdps_kernel_times(lbdps_ctx *ctx, double *h_ms, int64_t *h_launche
  *                      particles and the ring of cells around it are held in LDS
  *                      (contacts, clusters inside the tile resolved there, the
  *                      rest through neighbour rows): 0 = none, every particle
- *                      through the rows, 1 = 32 x 8 (default), 2 = 16 x 16,
+ *                      through the rows (default), 1 = 32 x 8, 2 = 16 x 16,
  *                      3 = 64 x 4.  A batched step takes the rows.
  * A context starts with the defaults.
  */

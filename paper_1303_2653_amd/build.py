@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = [os.path.join(HERE, "csrc", "lbdps.hip")]
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("device.hpp", "kernels.hpp", "batch.hpp", "lattice3d.hpp")] + [os.path.join(ROOT, "include", "lbdps.h")]
+DEPS = [os.path.join(HERE, "csrc", f) for f in ("device.hpp", "kernels.hpp", "batch.hpp", "lattice3d.hpp", "coupled3d.hpp", "spheres_tile.hpp")] + [os.path.join(ROOT, "include", "lbdps.h")]
 LIB = os.path.join(HERE, "liblbdps.so")
 
 # -ffp-contract=off: no fused multiply-add contraction, so FP64 results follow the

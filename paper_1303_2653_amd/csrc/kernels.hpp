@@ -1319,11 +1319,10 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Parts<T> src, Parts<T> dst, c
 // sorted by particle index, as 64-bit entries (index << 32 | slot).  A particle
 // without contacts gets its wall collision here; the others get it after their
 // binary collisions.
-// MODE: CT_ALL, every particle; CT_LEFT, only the particles the tile kernel
-// left (done < DONE_WHOLE), the others keep their marks and take no part;
-// CT_ROWS, the rows and degrees of every particle and nothing else (no wall
-// pass, marks, counters or flags), for the pair listing.
-constexpr int CT_ALL = 0, CT_LEFT = 1, CT_ROWS = 2;
+// MODE: CT_ALL, the collision stage's contacts; CT_ROWS, the rows and degrees
+// of every particle and nothing else (no wall pass, marks, counters or flags),
+// for the pair listing.
+constexpr int CT_ALL = 0, CT_ROWS = 2;
 template <int P, int W = CONTACT_W, int MODE = CT_ALL>
 __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
     const int32_t *__restrict__ cs, Consts<typename Prec<P>::T> k, Adj adj, int32_t *__restrict__ deg,
@@ -1341,9 +1340,7 @@ __device__ __forceinline__ void contacts_body(const int bidx, const int gdim, Pa
     *ticket = 0;
     *need_sweep = 0;
   }
-  bool act = s < k.npart;
-  if constexpr (MODE == CT_LEFT) act = act && ldu(done, s) < DONE_WHOLE;
-  if (act) {
+  if (s < k.npart) {
     const int key = pt.key[s];
     const int id = pt.pid[s];
     const T x = pt.px[s], y = pt.py[s];
@@ -1773,19 +1770,18 @@ __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, Adj 
 
 // Orders the gathered members by index and applies the cluster's pairs in
 // lexicographic order: member i (ascending) meets its higher-index neighbours
-// in ascending order, with its velocity kept in registers over its pairs.
-// Every pair with it as the higher index came before, and none follows, so
-// its wall pass runs right after its own pairs.  The neighbours come from the
-// contact matrix, so no row is read again: one round of loads per member
-// brings its record and those of its higher neighbours (distinct particles,
-// so none of its pairs changes another's record).
+// in ascending order.  Every pair with it as the higher index came before, and
+// none follows, so its wall pass runs right after its own pairs.  The
+// neighbours come from the contact matrix, so no row is read again, and the
+// records of all members are loaded in one round (registers indexed by the
+// members' places in index order), so the pairs run with no memory round
+// trip between them.
 template <int P, class Row>
 __device__ __forceinline__ void resolve_cluster(Row q, int m, unsigned long long A,
                                                 const Consts<typename Prec<P>::T> &k,
                                                 Parts<typename Prec<P>::T> &pt, int32_t *done, long long &ncoll,
                                                 long long &nwall) {
   using T = typename Prec<P>::T;
-  constexpr int NB = 4;  // higher neighbours loaded together
   for (int i = 1; i < m; ++i) {
     const long long e = q[i];
     int j = i - 1;
@@ -1795,54 +1791,40 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, unsigned long long
     }
     q[j + 1] = e;
   }
-  for (int i = 0; i < m; ++i) {
-    const long long qi = q[i];
-    const int u = (int)(qi & 0x1fffffffll);
-    const unsigned nbr = (unsigned)(A >> (8 * (int)((qi >> 29) & 7))) & 0xffu;  // places of u's neighbours
-    const int ku = ldu(pt.key, u);
-    const T xu = ldu(pt.px, u), yu = ldu(pt.py, u);
-    T vxu = ldu(pt.vx, u), vyu = ldu(pt.vy, u);
-    int j = i + 1;  // next member (in index order) to look at
-    while (true) {
-      // the next NB higher neighbours, in index order, loaded together
-      int w[NB], kw[NB];
-      T xw[NB], yw[NB], vxw[NB], vyw[NB];
-      int nw = 0;
-      for (; j < m && nw < NB; ++j) {
-        const long long qj = q[j];
-        if (nbr >> (int)((qj >> 29) & 7) & 1u) {
+  int us[CL_LDS], pl[CL_LDS], kk[CL_LDS];
+  T xx[CL_LDS], yy[CL_LDS], vx[CL_LDS], vy[CL_LDS];
 #pragma unroll
-          for (int b = 0; b < NB; ++b)
-            if (b == nw) w[b] = (int)(qj & 0x1fffffffll);
-          ++nw;
+  for (int i = 0; i < CL_LDS; ++i) {
+    us[i] = 0;
+    pl[i] = 0;
+    if (i < m) {
+      const long long qi = q[i];
+      us[i] = (int)(qi & 0x1fffffffll);
+      pl[i] = (int)((qi >> 29) & 7);
+      kk[i] = ldu(pt.key, us[i]);
+      xx[i] = ldu(pt.px, us[i]);
+      yy[i] = ldu(pt.py, us[i]);
+      vx[i] = ldu(pt.vx, us[i]);
+      vy[i] = ldu(pt.vy, us[i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < CL_LDS; ++i) {
+    if (i < m) {
+      const unsigned nbr = (unsigned)(A >> (8 * pl[i])) & 0xffu;  // places of its neighbours
+#pragma unroll
+      for (int j = i + 1; j < CL_LDS; ++j) {
+        if (j < m && ((nbr >> pl[j]) & 1u)) {
+          T dx, dy;
+          Pos<P>::sep(k, kk[i], xx[i], yy[i], kk[j], xx[j], yy[j], dx, dy);
+          ncoll += pair_core<P>(k, dx, dy, vx[i], vy[i], vx[j], vy[j]);
         }
       }
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-        if (b < nw) {
-          kw[b] = ldu(pt.key, w[b]);
-          xw[b] = ldu(pt.px, w[b]);
-          yw[b] = ldu(pt.py, w[b]);
-          vxw[b] = ldu(pt.vx, w[b]);
-          vyw[b] = ldu(pt.vy, w[b]);
-        }
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-        if (b < nw) {
-          T dx, dy;
-          Pos<P>::sep(k, ku, xu, yu, kw[b], xw[b], yw[b], dx, dy);
-          if (pair_core<P>(k, dx, dy, vxu, vyu, vxw[b], vyw[b])) {
-            pt.vx[w[b]] = vxw[b];
-            pt.vy[w[b]] = vyw[b];
-            ++ncoll;
-          }
-        }
-      if (j >= m) break;
+      nwall += Pos<P>::walls_key(k, kk[i], xx[i], yy[i], vx[i], vy[i]);
+      pt.vx[us[i]] = vx[i];
+      pt.vy[us[i]] = vy[i];
+      done[us[i]] = __builtin_popcount(nbr) | DONE_WHOLE;  // its contacts, all inside the cluster
     }
-    nwall += Pos<P>::walls_key(k, ku, xu, yu, vxu, vyu);
-    pt.vx[u] = vxu;
-    pt.vy[u] = vyu;
-    done[u] = __builtin_popcount(nbr) | DONE_WHOLE;  // its contacts, all inside the cluster
   }
 }
 
@@ -2057,7 +2039,7 @@ template <int P>
 __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
     Adj adj, const int32_t *__restrict__ deg, int32_t *done, Consts<typename Prec<P>::T> k, int32_t *need_sweep,
     long long *coll_part, long long *wall_part, const long long *__restrict__ roots,
-    const int32_t *__restrict__ rcount, int nlists) {
+    const int32_t *__restrict__ rcount, int nlists, const int32_t *nroots = nullptr) {
   __shared__ long long sh[BLOCK / 64];
   __shared__ int shi[BLOCK / 64];
   __shared__ int pre[BLOCK + 1];
@@ -2082,7 +2064,11 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
   // a contact row over its capacity leaves the contact graph incomplete: the
   // resolution is skipped and the step reports LBDPS_E_CAPACITY
   const bool overflow = __hip_atomic_load(&k.flags[FLAG_CAPACITY], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-  const int c = (!overflow && (int)threadIdx.x < nb) ? rcount[b0 + threadIdx.x] : 0;
+  // list j holds rcount[j] candidates, or, with one compact list of *nroots
+  // (the tile kernel's), its j-th run of BLOCK
+  int c = 0;
+  if (!overflow && (int)threadIdx.x < nb)
+    c = nroots ? min(max(*nroots - (b0 + (int)threadIdx.x) * BLOCK, 0), BLOCK) : rcount[b0 + threadIdx.x];
   const int o = block_excl_scan(c, shi, tot);
   if (tot == 0) {  // no candidate roots in these lists (uniform: the scan's total)
     if (threadIdx.x == 0) {
@@ -2146,9 +2132,10 @@ __global__ __launch_bounds__(BLOCK) void k_resolve_clusters(Parts<typename Prec<
                                                             Consts<typename Prec<P>::T> k, int32_t *need_sweep,
                                                             long long *coll_part, long long *wall_part,
                                                             const long long *__restrict__ roots,
-                                                            const int32_t *__restrict__ rcount, int nlists) {
+                                                            const int32_t *__restrict__ rcount, int nlists,
+                                                            const int32_t *nroots) {
   resolve_clusters_body<P>(xcd_block<XCD_RUN_CLUSTERS>(blockIdx.x, gridDim.x), gridDim.x, pt, adj, deg, done, k, need_sweep, coll_part, wall_part, roots,
-      rcount, nlists);
+      rcount, nlists, nroots);
 }
 
 // Position of particle index g in the neighbour list of slot t: the number of
@@ -2166,9 +2153,11 @@ template <int P>
 __device__ __forceinline__ void resolve_body(const int bidx, const int gdim, Parts<typename Prec<P>::T> pt,
     const int32_t *__restrict__ slot, Adj adj, const int32_t *__restrict__ deg, int32_t *done, int32_t *ticket,
     Consts<typename Prec<P>::T> k, int32_t *flags, long long *coll_part, long long *wall_part,
-    int32_t *__restrict__ chunk_busy, const int32_t *need_sweep) {
+    int32_t *__restrict__ chunk_busy, int32_t *need_sweep) {
   using T = typename Prec<P>::T;
   __shared__ int s_ticket;
+  // the tile kernel's compact root list is consumed: empty it for the next stage
+  if (bidx == 0 && threadIdx.x == 0) need_sweep[1] = 0;
   __shared__ long long sh[BLOCK / 64];
   long long ncoll = 0, nwall = 0;
   unsigned spins = 0;
@@ -2288,7 +2277,7 @@ __global__ __launch_bounds__(BLOCK) void k_resolve(Parts<typename Prec<P>::T> pt
                                                    Adj adj, const int32_t *__restrict__ deg,
                                                    int32_t *done, int32_t *ticket, Consts<typename Prec<P>::T> k,
                                                    int32_t *flags, long long *coll_part, long long *wall_part,
-                                                   int32_t *__restrict__ chunk_busy, const int32_t *need_sweep) {
+                                                   int32_t *__restrict__ chunk_busy, int32_t *need_sweep) {
   resolve_body<P>(blockIdx.x, gridDim.x, pt, slot, adj, deg, done, ticket, k, flags, coll_part, wall_part, chunk_busy,
       need_sweep);
 }

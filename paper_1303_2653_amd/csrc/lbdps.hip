@@ -222,7 +222,7 @@ struct lbdps_ctx {
   bool bins_valid = false;
   long long step = 0;
   bool in_batch = false;  // owned by a batch: destroyed with it
-  lbdps_tuning tune{RC_LISTS, RC_GROUPS_MAX, 0, 1};
+  lbdps_tuning tune{RC_LISTS, RC_GROUPS_MAX, 0, 0};
   int sphere_tiles = 0;  // tiles of the tile kernel in the most recent collision stage (0: not used)
   int drag_blocks = 0;  // drag workgroups of the most recent step (its partial sums)
   int cluster_groups() const { return cluster_blocks(n, tune.cluster_lists, tune.cluster_groups_max); }
@@ -245,7 +245,7 @@ struct lbdps_ctx {
   long long *roots = nullptr;
   int32_t *rcount = nullptr;
   long long *collc_part = nullptr, *wallc_part = nullptr;
-  long long *tile_part = nullptr;  // the tile kernel's pairs, collisions and wall hits per tile
+  long long *tile_part = nullptr;  // the tile kernel's pairs, collisions, wall hits and particles left, per tile
   int ntiles = 0;
   double *cons_pc = nullptr, *cons_pp = nullptr, *cons_out = nullptr;
   double *eg_tab = nullptr;        // FP64 gas voidage per particle count (Eq. 11), for lbdps_voidage
@@ -324,7 +324,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     sphere_tile_dims(t, tw, th);
     nst = std::max(nst, (size_t)st_tiles(p.nx, p.ny, tw, th));
   }
-  long long *tile_part = cv.take<long long>(3 * nst);
+  long long *tile_part = cv.take<long long>(4 * nst);
   double *pc = cv.take<double>(NB_CONS * 3), *pp = cv.take<double>(NB_CONS * 2), *co = cv.take<double>(8);
   double *egt = cv.take<double>((size_t)lut_rows(p.d_p));
   long long *obs = cv.take<long long>((size_t)nblocks(p.nx) + 1);
@@ -573,7 +573,8 @@ template <int P> struct Impl {
 
   // extra: a further sub-step of the same lattice step (its launches add time,
   // not launch counts)
-  using TileKern = void (*)(Parts<T>, const int32_t *, Consts<T>, int32_t *, long long *);
+  using TileKern = void (*)(Parts<T>, const int32_t *, Consts<T>, Adj, int32_t *, int32_t *, int32_t *, int32_t *,
+                            int32_t *, long long *, long long *);
   static TileKern tile_kernel(int t) {
     switch (t) {
       case 2: return k_spheres_tile<P, 16, 16>;
@@ -587,9 +588,9 @@ template <int P> struct Impl {
     return st_tiles(x->nx, x->ny, tw, th);
   }
   // The collision stage (A6 + A7).  With a sphere tile shape, the tile kernel
-  // resolves the clusters that lie inside its tiles, and the contact kernel
-  // builds rows only for the particles it left; the cluster kernel and the
-  // ordered sweep then take those as before.
+  // finds the contacts and resolves the clusters that lie within its tiles'
+  // reach, and writes rows and one compact root list only for the rest,
+  // which the cluster kernel and the ordered sweep then take as before.
   static void hard_spheres(lbdps_ctx *x, bool extra = false) {
     const int N = (int)x->n;
     if (N == 0) return;
@@ -598,11 +599,8 @@ template <int P> struct Impl {
     x->sphere_tiles = st > 0 ? sphere_tiles(x, st) : 0;
     if (st > 0) {
       tlaunch(x, LBDPS_K_CONTACTS, extra, tile_kernel(st), dim3(x->sphere_tiles), parts(x, x->cp),
-              (const int32_t *)x->cs, k, x->done, x->tile_part);
-      tlaunch(x, LBDPS_K_CONTACTS, true,
-              nblocks(N) <= CONTACTS_SMALL_MAX ? k_contacts_small<P, CT_LEFT> : k_contacts<P, CT_LEFT>,
-              dim3(nblocks(N)), parts(x, x->cp), (const int32_t *)x->cs, k, x->adj(), x->deg, x->done, x->ticket,
-              x->flags, x->pair_part, x->wall0_part, x->chunk_busy, x->need_sweep, x->roots, x->rcount);
+              (const int32_t *)x->cs, k, x->adj(), x->deg, x->done, x->ticket, x->need_sweep, x->chunk_busy,
+              x->roots, x->tile_part);
     } else {
       tlaunch(x, LBDPS_K_CONTACTS, extra, nblocks(N) <= CONTACTS_SMALL_MAX ? k_contacts_small<P> : k_contacts<P>,
               dim3(nblocks(N)), parts(x, x->cp), (const int32_t *)x->cs, k,
@@ -611,10 +609,11 @@ template <int P> struct Impl {
     }
     tlaunch(x, LBDPS_K_RESOLVE, extra, k_resolve_clusters<P>, dim3(x->cluster_groups()), parts(x, x->cp), x->adj(),
             (const int32_t *)x->deg, x->done, k, x->need_sweep, x->collc_part, x->wallc_part,
-            (const long long *)x->roots, (const int32_t *)x->rcount, nblocks(N));
+            (const long long *)x->roots, (const int32_t *)x->rcount, nblocks(N),
+            st > 0 ? (const int32_t *)x->need_sweep + 1 : nullptr);
     tlaunch(x, LBDPS_K_RESOLVE, true, k_resolve<P>, dim3(resolve_blocks(x)), parts(x, x->cp),
             (const int32_t *)x->slot, x->adj(), (const int32_t *)x->deg, x->done, x->ticket, k, x->flags,
-            x->coll_part, x->wall_part, x->chunk_busy, (const int32_t *)x->need_sweep);
+            x->coll_part, x->wall_part, x->chunk_busy, x->need_sweep);
   }
 
   static lbdps_status step(lbdps_ctx *x, int nsteps) {
@@ -877,6 +876,7 @@ lbdps_status lbdps_create(const lbdps_params *p, int64_t max_particles, void *d_
   }
   hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, x->count, (long long)x->C, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, x->flags, (long long)FLAG_COUNT, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, x->need_sweep, 4ll, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->nmax / RES_CHUNK + 1)), dim3(BLOCK), 0, x->stream, x->chunk_busy,
                      (long long)(x->nmax / RES_CHUNK + 1), 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(x->ntiles + 1)), dim3(BLOCK), 0, x->stream, x->tile_sum,
@@ -1175,6 +1175,7 @@ lbdps_status lbdps_counters(lbdps_ctx *x, int64_t h_out[4]) {
   for (int j = 0; j < 4; ++j) h_out[j] = 0;
   if (x->n > 0)
     for (int j = 0; j < 6; ++j) {
+      if (x->sphere_tiles > 0 && (j == 0 || j == 3)) continue;  // the tile kernel counts these
       st = check_hip(hipMemcpy(buf.data(), src[j], (size_t)len[j] * 8, hipMemcpyDeviceToHost), "lbdps_counters");
       if (st != LBDPS_OK) return st;
       for (int b = 0; b < len[j]; ++b) h_out[dst[j]] += buf[b];
@@ -1193,6 +1194,26 @@ lbdps_status lbdps_counters(lbdps_ctx *x, int64_t h_out[4]) {
     if (st != LBDPS_OK) return st;
     for (int b = 0; b < nbC; ++b) h_out[3] += buf[b];
   }
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps_tile_stats(lbdps_ctx *x, int64_t h_out[2]) {
+  if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
+  lbdps_status st = sync_and_check(x, "lbdps_tile_stats");
+  if (st != LBDPS_OK) return st;
+  h_out[0] = 0;
+  h_out[1] = 0;
+  const int nst = x->n > 0 ? x->sphere_tiles : 0;
+  if (nst == 0) {
+    h_out[1] = x->n;
+    return LBDPS_OK;
+  }
+  std::vector<long long> buf((size_t)nst);
+  st = check_hip(hipMemcpy(buf.data(), x->tile_part + (size_t)3 * nst, (size_t)nst * 8, hipMemcpyDeviceToHost),
+                 "lbdps_tile_stats");
+  if (st != LBDPS_OK) return st;
+  for (long long v : buf) h_out[1] += v;
+  h_out[0] = x->n - h_out[1];
   return LBDPS_OK;
 }
 

@@ -85,6 +85,7 @@ _SIGS = {
     "lbdps_conservation_noalloc": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
     "lbdps_counters": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
     "lbdps_outlet_crossings": (c_i32, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
+    "lbdps_tile_stats": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
     "lbdps_time_kernels": (c_i32, [c_vp, ctypes.c_uint32]),
     "lbdps_kernel_times": (c_i32, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
     "lbdps_set_tuning": (c_i32, [c_vp, ctypes.POINTER(lbdps_tuning)]),
@@ -335,6 +336,13 @@ class Sim:
         out = (c_i64 * 4)()
         check(lbdps_counters(self.ctx, out), "lbdps_counters")
         return dict(pairs=out[0], collisions=out[1], walls=out[2], zero_den=out[3])
+
+    def tile_stats(self):
+        """(particles resolved in LDS tiles, particles left to the neighbour
+        rows) of the most recent collision stage (lbdps_tile_stats)."""
+        out = (c_i64 * 2)()
+        check(lbdps_tile_stats(self.ctx, out), "lbdps_tile_stats")
+        return out[0], out[1]
 
     def outlet_crossings(self):
         """(net particles across the outlet plane y = ny upward, steps) since
