@@ -128,7 +128,8 @@ def riser(nx: int = 512, ny: int = 4096, n: int = 2_000_000, seed: int = 3, sort
     pos[:, 1] = ny * u[:, 1]
     if sort_ids:
         pos = pos[cell_order(pos, nx)]
-    return _cfg(f"riser-{nx}x{ny}-{n}-{precision}", nx, ny, ["wall", "wall", "periodic", "periodic"], pos,
+    ids = "" if sort_ids else "-random-ids"
+    return _cfg(f"riser-{nx}x{ny}-{n}{ids}-{precision}", nx, ny, ["wall", "wall", "periodic", "periodic"], pos,
                 5000, inlet_uy=None, g=RISER_G, G=RISER_BODY, precision=precision)
 
 
