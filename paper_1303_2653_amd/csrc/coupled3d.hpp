@@ -19,7 +19,9 @@
 //                 count of each particle's new cell;
 //   scan, k3c_scatter   the records to their new cell order;
 //   k3c_contacts  the contact rows (the cells within d of a particle);
-//   k3c_resolve   binary collisions (Eqs. 17-18) in lexicographic pair order.
+//   k3c_clusters  binary collisions (Eqs. 17-18) of each small contact cluster
+//                 in lexicographic pair order;
+//   k3c_resolve   the ordered sweep for clusters too large for k3c_clusters.
 #pragma once
 
 #include "kernels.hpp"
@@ -38,8 +40,14 @@ template <class T> struct Parts3 {
   T *vx, *vy, *vz;
 };
 
+// node: per cell the eight values the particle interpolation reads, packed
+// (u_gas x, y, z, solid fraction, beta, grad p x, y, z) so that a node is one
+// contiguous 8-value load.
 template <class T> struct Fields3 {
-  T *rho, *ugx, *ugy, *ugz, *beta, *es, *fpx, *fpy, *fpz, *gpx, *gpy, *gpz;
+  T *rho, *ugx, *ugy, *ugz, *beta, *es, *fpx, *fpy, *fpz, *node;
+};
+template <class T> struct alignas(8 * sizeof(T)) Node8 {
+  T v[8];
 };
 
 template <class T> struct Consts3 {
@@ -355,7 +363,8 @@ __global__ __launch_bounds__(BLOCK) void k3c_collide(const typename Prec<P>::S *
   }
 }
 
-// Node pressure gradient: central differences of p = rho / 3, periodic.
+// Node pressure gradient (central differences of p = rho / 3, periodic),
+// packed with the node's u_gas, solid fraction and beta for the interpolation.
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k3c_gradp(Fields3<typename Prec<P>::T> fl, Consts3<typename Prec<P>::T> k) {
   using T = typename Prec<P>::T;
@@ -367,9 +376,16 @@ __global__ __launch_bounds__(BLOCK) void k3c_gradp(Fields3<typename Prec<P>::T> 
   const int xp = z * nxy + y * k.nx + wrap_p(x + 1, k.nx), xm = z * nxy + y * k.nx + wrap_p(x - 1, k.nx);
   const int yp = z * nxy + wrap_p(y + 1, k.ny) * k.nx + x, ym = z * nxy + wrap_p(y - 1, k.ny) * k.nx + x;
   const int zp = wrap_p(z + 1, k.nz) * nxy + y * k.nx + x, zm = wrap_p(z - 1, k.nz) * nxy + y * k.nx + x;
-  fl.gpx[c] = (dv<P>(fl.rho[xp], (T)3.0) - dv<P>(fl.rho[xm], (T)3.0)) * (T)0.5;
-  fl.gpy[c] = (dv<P>(fl.rho[yp], (T)3.0) - dv<P>(fl.rho[ym], (T)3.0)) * (T)0.5;
-  fl.gpz[c] = (dv<P>(fl.rho[zp], (T)3.0) - dv<P>(fl.rho[zm], (T)3.0)) * (T)0.5;
+  Node8<T> nd;
+  nd.v[0] = fl.ugx[c];
+  nd.v[1] = fl.ugy[c];
+  nd.v[2] = fl.ugz[c];
+  nd.v[3] = fl.es[c];
+  nd.v[4] = fl.beta[c];
+  nd.v[5] = (dv<P>(fl.rho[xp], (T)3.0) - dv<P>(fl.rho[xm], (T)3.0)) * (T)0.5;
+  nd.v[6] = (dv<P>(fl.rho[yp], (T)3.0) - dv<P>(fl.rho[ym], (T)3.0)) * (T)0.5;
+  nd.v[7] = (dv<P>(fl.rho[zp], (T)3.0) - dv<P>(fl.rho[zm], (T)3.0)) * (T)0.5;
+  reinterpret_cast<Node8<T> *>(fl.node)[c] = nd;
 }
 
 // Gas quantities at one particle: trilinear interpolation of u_gas, the solid
@@ -393,83 +409,100 @@ template <int P> struct Interp3 {
       const int ox = q & 1, oy = (q >> 1) & 1, oz = q >> 2;
       const int id = (wrap_p(i0[2] + oz, k.nz) * k.ny + wrap_p(i0[1] + oy, k.ny)) * k.nx + wrap_p(i0[0] + ox, k.nx);
       const T w = (ox ? t[0] : (T)1.0 - t[0]) * (oy ? t[1] : (T)1.0 - t[1]) * (oz ? t[2] : (T)1.0 - t[2]);
-      u[0] += w * fl.ugx[id];
-      u[1] += w * fl.ugy[id];
-      u[2] += w * fl.ugz[id];
-      es += w * fl.es[id];
-      beta += w * fl.beta[id];
-      gp[0] += w * fl.gpx[id];
-      gp[1] += w * fl.gpy[id];
-      gp[2] += w * fl.gpz[id];
+      const Node8<T> nd = reinterpret_cast<const Node8<T> *>(fl.node)[id];
+      u[0] += w * nd.v[0];
+      u[1] += w * nd.v[1];
+      u[2] += w * nd.v[2];
+      es += w * nd.v[3];
+      beta += w * nd.v[4];
+      gp[0] += w * nd.v[5];
+      gp[1] += w * nd.v[6];
+      gp[2] += w * nd.v[7];
     }
   }
 };
 
 // ---------------------------------------------------------------- drag, integration, binning count
-// One thread per cell over its segment (ascending index): pass 1 the
-// pre-estimated drags (Eq. 26) and their cell sums (Eq. 27); pass 2 Eq. 28,
-// the acceleration of Eq. 16, v <- v + a, P <- P + v with the periodic wrap,
-// the record stored in place and counted into its new cell.
+// Two passes, one thread per particle slot (a cell-per-thread form left most
+// lanes idle: about one cell in seven holds a sphere).  Pass 1 interpolates
+// at each particle and stores its pre-estimated drag (Eq. 26) and grad p.
+// Pass 2 sums the pre-drags of the particle's cell over its segment in slot
+// order (ascending index, as the collide kernel left it) for Eq. 27, applies
+// Eq. 28 and the acceleration of Eq. 16, moves the particle with the
+// periodic wrap, stores the record in place and counts it into its new cell.
+// pre holds [6][N]: the pre-drag, then grad p, per axis.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k3c_predrag(Parts3<typename Prec<P>::T> pt, Fields3<typename Prec<P>::T> fl,
+                                                     Consts3<typename Prec<P>::T> k, typename Prec<P>::T *__restrict__ pre) {
+  using T = typename Prec<P>::T;
+  const int s = blockIdx.x * BLOCK + threadIdx.x;
+  if (s >= k.npart) return;
+  const size_t N = (size_t)k.npart;
+  int cc[3];
+  cell3_xyz(k, pt.key[s], cc[0], cc[1], cc[2]);
+  const T o[3] = {pt.px[s], pt.py[s], pt.pz[s]}, v[3] = {pt.vx[s], pt.vy[s], pt.vz[s]};
+  Interp3<P> I;
+  I.at(k, fl, cc, o);
+  const T cf = dv<P>(k.vp * I.beta, I.es);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    pre[q * N + s] = cf * (I.u[q] - v[q]);
+    pre[(3 + q) * N + s] = I.gp[q];
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k3c_drag(Parts3<typename Prec<P>::T> pt, Fields3<typename Prec<P>::T> fl,
                                                   const int32_t *__restrict__ cs, Consts3<typename Prec<P>::T> k,
+                                                  const typename Prec<P>::T *__restrict__ pre,
                                                   int32_t *__restrict__ count, int32_t *__restrict__ rank,
                                                   typename Prec<P>::T *dg_fd, typename Prec<P>::T *dg_acc) {
   using T = typename Prec<P>::T;
-  const int c = blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= k.C) return;
+  const int s = blockIdx.x * BLOCK + threadIdx.x;
+  if (s >= k.npart) return;
+  const size_t N = (size_t)k.npart;
+  const int c = pt.key[s];
   const int a0 = cs[c], a1 = cs[c + 1], n = a1 - a0;
-  if (n == 0) return;
+  T S[3] = {(T)0, (T)0, (T)0};
+  for (int t = a0; t < a1; ++t)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) S[q] += pre[q * N + t];
   int cc[3];
   cell3_xyz(k, c, cc[0], cc[1], cc[2]);
-  T S[3] = {(T)0, (T)0, (T)0};
-  for (int s = a0; s < a1; ++s) {
-    const T o[3] = {pt.px[s], pt.py[s], pt.pz[s]}, v[3] = {pt.vx[s], pt.vy[s], pt.vz[s]};
-    Interp3<P> I;
-    I.at(k, fl, cc, o);
-    const T cf = dv<P>(k.vp * I.beta, I.es);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) S[q] += cf * (I.u[q] - v[q]);
-  }
   const T fg[3] = {fl.fpx[c], fl.fpy[c], fl.fpz[c]};
   const int nn[3] = {k.nx, k.ny, k.nz};
-  for (int s = a0; s < a1; ++s) {
-    T o[3] = {pt.px[s], pt.py[s], pt.pz[s]}, v[3] = {pt.vx[s], pt.vy[s], pt.vz[s]};
-    Interp3<P> I;
-    I.at(k, fl, cc, o);
-    const T cf = dv<P>(k.vp * I.beta, I.es);
-    int nc[3];
-    T fd[3], acc[3];
+  T o[3] = {pt.px[s], pt.py[s], pt.pz[s]}, v[3] = {pt.vx[s], pt.vy[s], pt.vz[s]};
+  int nc[3];
+  T fd[3], acc[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const T pr = pre[q * N + s];
+    fd[q] = S[q] == (T)0 ? dv<P>(-fg[q], (T)n) : dv<P>(-fg[q] * pr, S[q]);
+    acc[q] = k.geff[q] + dv<P>(fd[q] + k.fp * pre[(3 + q) * N + s], k.m);
+    v[q] = v[q] + acc[q];
+    nc[q] = Pos3<P>::move_axis(cc[q], o[q], v[q], nn[q]);
+  }
+  const int id = pt.pid[s];
+  if (dg_fd) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      const T pre = cf * (I.u[q] - v[q]);
-      fd[q] = S[q] == (T)0 ? dv<P>(-fg[q], (T)n) : dv<P>(-fg[q] * pre, S[q]);
-      acc[q] = k.geff[q] + dv<P>(fd[q] + k.fp * I.gp[q], k.m);
-      v[q] = v[q] + acc[q];
-      nc[q] = Pos3<P>::move_axis(cc[q], o[q], v[q], nn[q]);
+      dg_fd[3 * (size_t)id + q] = fd[q];
+      dg_acc[3 * (size_t)id + q] = acc[q];
     }
-    const int id = pt.pid[s];
-    if (dg_fd) {
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        dg_fd[3 * (size_t)id + q] = fd[q];
-        dg_acc[3 * (size_t)id + q] = acc[q];
-      }
-    }
-    int nk = (nc[2] * k.ny + nc[1]) * k.nx + nc[0];
-    if (nc[0] < 0 || nc[1] < 0 || nc[2] < 0) {  // not a position in the box: reported, counted in its old cell
-      atomicOr(&k.flags[FLAG_DOMAIN], 1);
-      nk = c;
-    }
-    pt.key[s] = nk;
-    pt.px[s] = o[0];
-    pt.py[s] = o[1];
-    pt.pz[s] = o[2];
-    pt.vx[s] = v[0];
-    pt.vy[s] = v[1];
-    pt.vz[s] = v[2];
-    rank[s] = atomicAdd(&count[nk], 1);
   }
+  int nk = (nc[2] * k.ny + nc[1]) * k.nx + nc[0];
+  if (nc[0] < 0 || nc[1] < 0 || nc[2] < 0) {  // not a position in the box: reported, counted in its old cell
+    atomicOr(&k.flags[FLAG_DOMAIN], 1);
+    nk = c;
+  }
+  pt.key[s] = nk;
+  pt.px[s] = o[0];
+  pt.py[s] = o[1];
+  pt.pz[s] = o[2];
+  pt.vx[s] = v[0];
+  pt.vy[s] = v[1];
+  pt.vz[s] = v[2];
+  rank[s] = atomicAdd(&count[nk], 1);
 }
 
 // ---------------------------------------------------------------- contacts
@@ -482,12 +515,18 @@ __global__ __launch_bounds__(BLOCK) void k3c_contacts(Parts3<typename Prec<P>::T
                                                       Consts3<typename Prec<P>::T> k, Adj adj,
                                                       int32_t *__restrict__ deg, int32_t *__restrict__ done,
                                                       int32_t *ticket, int32_t *__restrict__ chunk_busy,
-                                                      long long *pair_part) {
+                                                      long long *pair_part, int32_t *need_sweep,
+                                                      long long *__restrict__ roots, int32_t *__restrict__ rcount) {
   using T = typename Prec<P>::T;
   __shared__ long long sh[BLOCK / 64];
+  __shared__ int shi[BLOCK / 64];
   const int s = blockIdx.x * BLOCK + threadIdx.x;
-  if (s == 0) *ticket = 0;
+  if (s == 0) {
+    *ticket = 0;
+    *need_sweep = 0;
+  }
   long long fwd = 0;
+  bool cand = false;  // has contacts, all with higher indices: a possible cluster root
   if (s < k.npart) {
     const int key = pt.key[s], id = pt.pid[s];
     const T a[3] = {pt.px[s], pt.py[s], pt.pz[s]};
@@ -541,10 +580,150 @@ __global__ __launch_bounds__(BLOCK) void k3c_contacts(Parts3<typename Prec<P>::T
     if (over) atomicOr(&k.flags[FLAG_CAPACITY], 1);
     deg[s] = cnt;
     done[s] = 0;
-    if (cnt > 0) chunk_busy[id / RES_CHUNK] = 1;
+    if (cnt > 0) {
+      chunk_busy[id / RES_CHUNK] = 1;
+      cand = (int)(row[0] >> 32) > id;
+    }
   }
+  // candidate roots of this workgroup, compacted to the front of its segment
+  int nc;
+  const int off = block_excl_scan(cand ? 1 : 0, shi, nc);
+  if (cand) roots[(size_t)blockIdx.x * BLOCK + off] = ((long long)pt.pid[s] << 32) | (unsigned)s;
   const long long t = block_sum_ll(fwd, sh);
-  if (threadIdx.x == 0) pair_part[blockIdx.x] = t;
+  if (threadIdx.x == 0) {
+    pair_part[blockIdx.x] = t;
+    rcount[blockIdx.x] = nc;
+  }
+}
+
+// ---------------------------------------------------------------- contact clusters
+// As in 2-D: a lane takes a candidate root, gathers its cluster (the contact
+// kernel's rows, up to CL_LDS members, giving up at a lower index), orders the
+// members by index and applies the cluster's pairs in lexicographic order,
+// which is the sequential sweep's result bit for bit (clusters touch disjoint
+// particles).  A member loads its record and up to NB3 higher neighbours' in
+// one round.  A cluster of more members is left to the ordered sweep.
+template <int P, class Row>
+__device__ __forceinline__ void resolve_cluster3(Row q, int m, unsigned long long A,
+                                                 const Consts3<typename Prec<P>::T> &k,
+                                                 Parts3<typename Prec<P>::T> &pt, int32_t *done, long long &ncoll) {
+  using T = typename Prec<P>::T;
+  constexpr int NB3 = 2;
+  for (int i = 1; i < m; ++i) {
+    const long long e = q[i];
+    int j = i - 1;
+    while (j >= 0 && q[j] > e) {
+      q[j + 1] = q[j];
+      --j;
+    }
+    q[j + 1] = e;
+  }
+  for (int i = 0; i < m; ++i) {
+    const long long qi = q[i];
+    const int u = (int)(qi & 0x1fffffffll);
+    const unsigned nbr = (unsigned)(A >> (8 * (int)((qi >> 29) & 7))) & 0xffu;  // places of u's neighbours
+    const int ku = ldu(pt.key, u);
+    const T a[3] = {ldu(pt.px, u), ldu(pt.py, u), ldu(pt.pz, u)};
+    T vu[3] = {ldu(pt.vx, u), ldu(pt.vy, u), ldu(pt.vz, u)};
+    int j = i + 1;  // next member (in index order) to look at
+    while (true) {
+      int w[NB3], kw[NB3];
+      T b[NB3][3], vw[NB3][3];
+      int nw = 0;
+      for (; j < m && nw < NB3; ++j) {
+        const long long qj = q[j];
+        if (nbr >> (int)((qj >> 29) & 7) & 1u) {
+#pragma unroll
+          for (int c = 0; c < NB3; ++c)
+            if (c == nw) w[c] = (int)(qj & 0x1fffffffll);
+          ++nw;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NB3; ++c)
+        if (c < nw) {
+          kw[c] = ldu(pt.key, w[c]);
+          b[c][0] = ldu(pt.px, w[c]);
+          b[c][1] = ldu(pt.py, w[c]);
+          b[c][2] = ldu(pt.pz, w[c]);
+          vw[c][0] = ldu(pt.vx, w[c]);
+          vw[c][1] = ldu(pt.vy, w[c]);
+          vw[c][2] = ldu(pt.vz, w[c]);
+        }
+#pragma unroll
+      for (int c = 0; c < NB3; ++c)
+        if (c < nw) {
+          T d[3];
+          Pos3<P>::sep(k, ku, a, kw[c], b[c], d);
+          const T dot = (vu[0] - vw[c][0]) * d[0] + (vu[1] - vw[c][1]) * d[1] + (vu[2] - vw[c][2]) * d[2];
+          if (dot < (T)0) {
+            const T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const T q0 = (k.one_e * dot) / r2;
+            const T ci = (q0 * k.m) / k.msum;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+              vu[e] = vu[e] - ci * d[e];
+              vw[c][e] = vw[c][e] + ci * d[e];
+            }
+            pt.vx[w[c]] = vw[c][0];
+            pt.vy[w[c]] = vw[c][1];
+            pt.vz[w[c]] = vw[c][2];
+            ++ncoll;
+          }
+        }
+      if (j >= m) break;
+    }
+    pt.vx[u] = vu[0];
+    pt.vy[u] = vu[1];
+    pt.vz[u] = vu[2];
+    done[u] = __builtin_popcount(nbr) | DONE_WHOLE;  // its contacts, all inside the cluster
+  }
+}
+
+constexpr int RC3_LISTS = 4;  // candidate lists per cluster workgroup
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k3c_clusters(Parts3<typename Prec<P>::T> pt, Adj adj,
+                                                      const int32_t *__restrict__ deg, int32_t *done,
+                                                      Consts3<typename Prec<P>::T> k, int32_t *need_sweep,
+                                                      long long *coll_part, const long long *__restrict__ roots,
+                                                      const int32_t *__restrict__ rcount, int nlists) {
+  __shared__ long long sh[BLOCK / 64];
+  __shared__ int shi[BLOCK / 64];
+  __shared__ int pre[BLOCK + 1];
+  __shared__ long long qs[CL_LDS * BLOCK];
+  const int bidx = blockIdx.x, gdim = gridDim.x;
+  const int per = (nlists + gdim - 1) / gdim;  // <= BLOCK (host grid choice)
+  const int b0 = bidx * per;
+  const int nb = max(0, min(nlists - b0, per));
+  // a contact row over its capacity leaves the contact graph incomplete
+  const bool overflow = __hip_atomic_load(&k.flags[FLAG_CAPACITY], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  const int c = (!overflow && (int)threadIdx.x < nb) ? rcount[b0 + threadIdx.x] : 0;
+  int tot;
+  const int o = block_excl_scan(c, shi, tot);
+  long long ncoll = 0;
+  if (tot > 0) {  // uniform
+    if ((int)threadIdx.x < nb) pre[threadIdx.x] = o;
+    if (threadIdx.x == 0) pre[nb] = tot;
+    __syncthreads();
+    const LdsColumn ql{qs + threadIdx.x};
+    for (int f = threadIdx.x; f < tot; f += BLOCK) {
+      int lo = 0, hi = nb;  // list j with pre[j] <= f < pre[j + 1]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= f) lo = mid;
+        else hi = mid;
+      }
+      const long long r = roots[(size_t)(b0 + lo) * BLOCK + (f - pre[lo])];
+      const int s = (int)(r & 0xffffffffll), g = (int)(r >> 32);
+      unsigned long long A;
+      const int m = gather_cluster(ql, CL_LDS, s, g, adj, deg, A);
+      if (m > 0) resolve_cluster3<P>(ql, m, A, k, pt, done, ncoll);
+      else if (m < 0) atomicOr(need_sweep, 1);  // too large: the ordered sweep takes it
+    }
+  }
+  const long long tc = block_sum_ll(ncoll, sh);
+  if (threadIdx.x == 0) coll_part[bidx] = tc;
 }
 
 // ---------------------------------------------------------------- collision resolution (Eqs. 17-18)
@@ -588,13 +767,16 @@ template <int P>
 __global__ __launch_bounds__(BLOCK) void k3c_resolve(Parts3<typename Prec<P>::T> pt, const int32_t *__restrict__ slot,
                                                      Adj adj, const int32_t *__restrict__ deg, int32_t *done,
                                                      int32_t *ticket, Consts3<typename Prec<P>::T> k,
-                                                     long long *coll_part, int32_t *__restrict__ chunk_busy) {
+                                                     long long *coll_part, int32_t *__restrict__ chunk_busy,
+                                                     const int32_t *need_sweep) {
   __shared__ int s_ticket;
   __shared__ long long sh[BLOCK / 64];
   long long ncoll = 0;
   unsigned spins = 0;
   const int nchunks = (k.npart + RES_CHUNK - 1) / RES_CHUNK;
-  if (__hip_atomic_load(&k.flags[FLAG_CAPACITY], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+  // every cluster was resolved whole, or a contact row overflowed (the
+  // resolution is skipped): only clear the chunk marks
+  if (!*need_sweep || __hip_atomic_load(&k.flags[FLAG_CAPACITY], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < nchunks; i += gridDim.x * BLOCK) chunk_busy[i] = 0;
     if (threadIdx.x == 0) coll_part[blockIdx.x] = 0;
     return;
@@ -626,7 +808,7 @@ __global__ __launch_bounds__(BLOCK) void k3c_resolve(Parts3<typename Prec<P>::T>
         }
         s = slot[g];
         dg = deg[s];
-        if (dg == 0) continue;  // no contacts (fully periodic: no wall pass)
+        if (dg == 0 || done[s] >= DONE_WHOLE) continue;  // no contacts (fully periodic: no wall pass), or resolved whole
         row = adj.row(s);
         a = 0;
         while (a < dg && (int)(row[a] >> 32) < g) ++a;

@@ -1905,13 +1905,16 @@ struct lbdps3_ctx {
   long long step = 0;
   double dtau = 0, dd = 0, dmu = 0, dvp = 0, dm = 0, done_e = 0, dfp = 0, dgeff[3]{}, dhalfG[3]{}, dsrc[Q3]{};
   void *f[2]{};
-  void *fld[12]{};  // rho, ugx, ugy, ugz, beta, es, fpx, fpy, fpz, gpx, gpy, gpz
+  void *fld[10]{};  // rho, ugx, ugy, ugz, beta, es, fpx, fpy, fpz, the packed interpolation nodes [C][8]
   int32_t *key[2]{}, *pid[2]{};
   void *pos[2][3]{}, *vel[2][3]{};
   int32_t *count = nullptr, *cs = nullptr, *rank = nullptr, *slot = nullptr, *deg = nullptr, *done = nullptr;
   long long *adj_in = nullptr, *adj_ov = nullptr;
   int32_t *ticket = nullptr, *flags = nullptr, *chunk_busy = nullptr, *spart = nullptr, *pcnt = nullptr;
-  long long *pair_part = nullptr, *coll_part = nullptr;
+  long long *pair_part = nullptr, *coll_part = nullptr, *collc_part = nullptr;
+  long long *roots = nullptr;  // candidate cluster roots, BLOCK per contact workgroup
+  void *pre = nullptr;         // per particle: pre-estimated drag and grad p, [6][N]
+  int32_t *rcount = nullptr, *need_sweep = nullptr;
   void *lut = nullptr;
   int32_t *dg_n = nullptr;
   void *dg_fd = nullptr, *dg_acc = nullptr;
@@ -1962,8 +1965,9 @@ size_t carve3(const lbdps3_params &p, long long nmax, char *base, lbdps3_ctx *x)
   const size_t C = (size_t)p.nx * p.ny * p.nz, N = (size_t)std::max(nmax, 1ll);
   auto raw = [&](size_t bytes) { return cv.take<char>(bytes); };
   char *f0 = raw(Q3 * C * sS), *f1 = raw(Q3 * C * sS);
-  char *fl[12];
-  for (auto &q : fl) q = raw(C * sT);
+  char *fl[10];
+  for (int i = 0; i < 9; ++i) fl[i] = raw(C * sT);
+  fl[9] = raw(8 * C * sT);  // packed interpolation nodes
   int32_t *key[2], *pid[2];
   char *pos[2][3], *vel[2][3];
   for (int b = 0; b < 2; ++b) {
@@ -1981,6 +1985,11 @@ size_t carve3(const lbdps3_params &p, long long nmax, char *base, lbdps3_ctx *x)
   int32_t *spart = cv.take<int32_t>(tiles), *pcnt = cv.take<int32_t>(N + 1);
   const size_t nb = (size_t)nblocks((long long)std::max(C, N)) + 1;
   long long *pair_part = cv.take<long long>(nb), *coll_part = cv.take<long long>(nb);
+  long long *collc_part = cv.take<long long>(nb);
+  const size_t nbN3 = (size_t)nblocks((long long)N);
+  long long *roots = cv.take<long long>(nbN3 * BLOCK);
+  int32_t *rcount = cv.take<int32_t>(nbN3), *need_sweep = cv.take<int32_t>(4);
+  char *pre = raw(6 * N * sT);
   char *lut = raw((size_t)lut3_rows(p.d_p) * L3_W * sT);
   int32_t *dg_n = nullptr;
   char *dg_fd = nullptr, *dg_acc = nullptr;
@@ -1992,7 +2001,7 @@ size_t carve3(const lbdps3_params &p, long long nmax, char *base, lbdps3_ctx *x)
   if (x) {
     x->f[0] = f0;
     x->f[1] = f1;
-    for (int i = 0; i < 12; ++i) x->fld[i] = fl[i];
+    for (int i = 0; i < 10; ++i) x->fld[i] = fl[i];
     for (int b = 0; b < 2; ++b) {
       x->key[b] = key[b];
       x->pid[b] = pid[b];
@@ -2016,6 +2025,11 @@ size_t carve3(const lbdps3_params &p, long long nmax, char *base, lbdps3_ctx *x)
     x->pcnt = pcnt;
     x->pair_part = pair_part;
     x->coll_part = coll_part;
+    x->collc_part = collc_part;
+    x->roots = roots;
+    x->rcount = rcount;
+    x->need_sweep = need_sweep;
+    x->pre = pre;
     x->lut = lut;
     x->dg_n = dg_n;
     x->dg_fd = dg_fd;
@@ -2059,9 +2073,9 @@ template <int P> struct Impl3 {
                      (T *)x->vel[b][0], (T *)x->vel[b][1], (T *)x->vel[b][2]};
   }
   static Fields3<T> fields(const lbdps3_ctx *x) {
-    T *q[12];
-    for (int i = 0; i < 12; ++i) q[i] = (T *)x->fld[i];
-    return Fields3<T>{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10], q[11]};
+    T *q[10];
+    for (int i = 0; i < 10; ++i) q[i] = (T *)x->fld[i];
+    return Fields3<T>{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9]};
   }
   static void scan(lbdps3_ctx *x, int32_t *in, long long n, int32_t *out, int zero_in) {
     const int tiles = (int)((n + SCAN_TILE - 1) / SCAN_TILE) + (n == 0);
@@ -2087,10 +2101,14 @@ template <int P> struct Impl3 {
     if (N == 0) return;
     const Consts3<T> k = consts(x);
     hipLaunchKernelGGL(k3c_contacts<P>, dim3(nblocks(N)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
-                       (const int32_t *)x->cs, k, x->adj(), x->deg, x->done, x->ticket, x->chunk_busy, x->pair_part);
+                       (const int32_t *)x->cs, k, x->adj(), x->deg, x->done, x->ticket, x->chunk_busy, x->pair_part,
+                       x->need_sweep, x->roots, x->rcount);
+    hipLaunchKernelGGL(k3c_clusters<P>, dim3(cluster_blocks(N, RC3_LISTS)), dim3(BLOCK), 0, x->stream,
+                       parts(x, x->cp), x->adj(), (const int32_t *)x->deg, x->done, k, x->need_sweep, x->collc_part,
+                       (const long long *)x->roots, (const int32_t *)x->rcount, nblocks(N));
     hipLaunchKernelGGL(k3c_resolve<P>, dim3(std::min(nblocks(N), 2048)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
                        (const int32_t *)x->slot, x->adj(), (const int32_t *)x->deg, x->done, x->ticket, k,
-                       x->coll_part, x->chunk_busy);
+                       x->coll_part, x->chunk_busy, (const int32_t *)x->need_sweep);
   }
   static lbdps_status step(lbdps3_ctx *x, int nsteps) {
     const bool dg = x->p.diagnostics != 0;
@@ -2102,9 +2120,11 @@ template <int P> struct Impl3 {
                          k, dg ? x->dg_n : nullptr);
       if (x->n > 0) {
         hipLaunchKernelGGL(k3c_gradp<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, fields(x), k);
-        hipLaunchKernelGGL(k3c_drag<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x),
-                           (const int32_t *)x->cs, k, x->count, x->rank, dg ? (T *)x->dg_fd : nullptr,
-                           dg ? (T *)x->dg_acc : nullptr);
+        hipLaunchKernelGGL(k3c_predrag<P>, dim3(nblocks(x->n)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
+                           fields(x), k, (T *)x->pre);
+        hipLaunchKernelGGL(k3c_drag<P>, dim3(nblocks(x->n)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x),
+                           (const int32_t *)x->cs, k, (const T *)x->pre, x->count, x->rank,
+                           dg ? (T *)x->dg_fd : nullptr, dg ? (T *)x->dg_acc : nullptr);
         sort(x, true);
         hard_spheres(x);
       }
@@ -2365,6 +2385,10 @@ lbdps_status lbdps3_counters(lbdps3_ctx *x, int64_t h_out[2]) {
   st = check_hip(hipMemcpy(buf.data(), x->coll_part, (size_t)nr * 8, hipMemcpyDeviceToHost), "lbdps3_counters");
   if (st != LBDPS_OK) return st;
   for (int b = 0; b < nr; ++b) h_out[1] += buf[b];
+  const int ncl = cluster_blocks(x->n, RC3_LISTS);
+  st = check_hip(hipMemcpy(buf.data(), x->collc_part, (size_t)ncl * 8, hipMemcpyDeviceToHost), "lbdps3_counters");
+  if (st != LBDPS_OK) return st;
+  for (int b = 0; b < ncl; ++b) h_out[1] += buf[b];
   return LBDPS_OK;
 }
 
