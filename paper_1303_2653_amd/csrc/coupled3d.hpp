@@ -546,33 +546,56 @@ __global__ __launch_bounds__(BLOCK) void k3c_contacts(Parts3<typename Prec<P>::T
     const AdjRow row = adj.row(s);
     int cnt = 0;
     bool over = false;
-    for (int oz = -1; oz <= 1; ++oz) {
-      if (!use[2][oz + 1]) continue;
-      for (int oy = -1; oy <= 1; ++oy) {
-        if (!use[1][oy + 1]) continue;
-        for (int ox = -1; ox <= 1; ++ox) {
-          if (!use[0][ox + 1]) continue;
-          const int nb = (wrap_p(cc[2] + oz, nn[2]) * k.ny + wrap_p(cc[1] + oy, nn[1])) * k.nx + wrap_p(cc[0] + ox, nn[0]);
-          for (int t = cs[nb]; t < cs[nb + 1]; ++t) {
-            if (t == s) continue;
-            const T b[3] = {pt.px[t], pt.py[t], pt.pz[t]};
-            T d[3];
-            Pos3<P>::sep(k, key, a, pt.key[t], b, d);
-            if (!(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] <= k.dd)) continue;
-            const int tid = pt.pid[t];
-            if (tid > id) ++fwd;
-            if (cnt == KMAX) {
-              over = true;
-              continue;
-            }
-            const long long e = ((long long)tid << 32) | (unsigned)t;
-            int j = cnt;
-            while (j > 0 && row[j - 1] > e) {
-              row[j] = row[j - 1];
-              --j;
-            }
-            row[j] = e;
-            ++cnt;
+    auto test = [&](int t) {
+      if (t == s) return;
+      const T b[3] = {pt.px[t], pt.py[t], pt.pz[t]};
+      T d[3];
+      Pos3<P>::sep(k, key, a, pt.key[t], b, d);
+      if (!(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] <= k.dd)) return;
+      const int tid = pt.pid[t];
+      if (tid > id) ++fwd;
+      if (cnt == KMAX) {
+        over = true;
+        return;
+      }
+      const long long e = ((long long)tid << 32) | (unsigned)t;
+      int j = cnt;
+      while (j > 0 && row[j - 1] > e) {
+        row[j] = row[j - 1];
+        --j;
+      }
+      row[j] = e;
+      ++cnt;
+    };
+    // The cells of one (y, z) row next to each other in x are one slot range:
+    // away from the x seam, the bounds of all (at most nine) ranges are read
+    // together, then their candidates tested.
+    const bool xin = (!use[0][0] || cc[0] >= 1) && (!use[0][2] || cc[0] <= k.nx - 2);
+    if (xin) {
+      int lo[9], hi[9];
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        const int oz = r / 3 - 1, oy = r % 3 - 1;
+        lo[r] = hi[r] = 0;
+        if (use[2][oz + 1] && use[1][oy + 1]) {
+          const int base = (wrap_p(cc[2] + oz, nn[2]) * k.ny + wrap_p(cc[1] + oy, nn[1])) * k.nx;
+          lo[r] = cs[base + cc[0] - (use[0][0] ? 1 : 0)];
+          hi[r] = cs[base + cc[0] + 1 + (use[0][2] ? 1 : 0)];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 9; ++r)
+        for (int t = lo[r]; t < hi[r]; ++t) test(t);
+    } else {
+      for (int oz = -1; oz <= 1; ++oz) {
+        if (!use[2][oz + 1]) continue;
+        for (int oy = -1; oy <= 1; ++oy) {
+          if (!use[1][oy + 1]) continue;
+          for (int ox = -1; ox <= 1; ++ox) {
+            if (!use[0][ox + 1]) continue;
+            const int nb =
+                (wrap_p(cc[2] + oz, nn[2]) * k.ny + wrap_p(cc[1] + oy, nn[1])) * k.nx + wrap_p(cc[0] + ox, nn[0]);
+            for (int t = cs[nb]; t < cs[nb + 1]; ++t) test(t);
           }
         }
       }
