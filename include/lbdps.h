@@ -114,6 +114,12 @@ typedef struct {
                                    at the opposite one, with no particle wall there (the
                                    circulating loop of the riser, Sec. 3.2); the gas keeps its
                                    faces.  0 (default): particles follow the gas faces */
+  int32_t diag_every;        /* > 0: after every diag_every-th step lbdps_step also enqueues
+                                the FP64 conservation sums (as lbdps_conservation) and
+                                latches a non-finite value in populations or velocities,
+                                reported as LBDPS_E_NONFINITE by the next synchronising
+                                call; lbdps_diag_last returns the latest sums.  0 (default):
+                                off.  Batched beds: LBDPS_E_UNSUPPORTED if > 0 */
 } lbdps_params;
 
 typedef struct lbdps_ctx lbdps_ctx;
@@ -222,6 +228,13 @@ lbdps_status lbdps_conservation(lbdps_ctx *ctx, double h_out[6]);
  * lbdps_conservation does.  Synchronises the stream.
  */
 lbdps_status lbdps_conservation_noalloc(lbdps_ctx *ctx, double h_out[6]);
+
+/*
+ * The sums of the latest periodic check (lbdps_params.diag_every > 0), in
+ * lbdps_conservation's layout, and the step after which it ran (*h_step; -1
+ * and zeros if none ran yet).  Synchronises the stream.
+ */
+lbdps_status lbdps_diag_last(lbdps_ctx *ctx, double h_out[6], int64_t *h_step);
 
 /*
  * Event counts of the most recent hard-sphere stage: h_out[0] contact pairs,

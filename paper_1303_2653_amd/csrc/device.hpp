@@ -54,7 +54,7 @@ constexpr int XCD_RUN_COLLIDE = -1, XCD_RUN_DRAG = 8, XCD_RUN_SCAN = -1, XCD_RUN
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INLET = 2, BC_OUTLET = 3 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16DEV = 2, PREC_BF16DEV = 3 };
 // Error flag slots (int32 each).
-enum { FLAG_DOMAIN = 0, FLAG_CAPACITY = 1, FLAG_STALL = 2, FLAG_COUNT = 8 };
+enum { FLAG_DOMAIN = 0, FLAG_CAPACITY = 1, FLAG_STALL = 2, FLAG_NONFINITE = 3, FLAG_COUNT = 8 };
 // Columns of the per-count table (built on the host in FP64).
 enum {
   L_ES3 = 0,  // 3-D solid fraction eps_s,3d (Eq. 11)

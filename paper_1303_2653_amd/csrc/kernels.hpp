@@ -2673,6 +2673,12 @@ __global__ __launch_bounds__(BLOCK) void k_voidage_count(const long long *__rest
   if (threadIdx.x == 0) *out = t;
 }
 
+// The periodic check: a non-finite value found by the conservation sums
+// (out[5] != 0) is latched in the context's flags.
+__global__ void k_flag_nonfinite(const double *__restrict__ out, int32_t *flags) {
+  if (threadIdx.x == 0 && out[5] != 0.0) atomicOr(&flags[FLAG_NONFINITE], 1);
+}
+
 __global__ void k_fill_i32(int32_t *p, long long n, int32_t v) {
   const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
   if (i < n) p[i] = v;

@@ -248,6 +248,9 @@ struct lbdps_ctx {
   long long *tile_part = nullptr;  // the tile kernel's pairs, collisions, wall hits and particles left, per tile
   int ntiles = 0;
   double *cons_pc = nullptr, *cons_pp = nullptr, *cons_out = nullptr;
+  double *diag_pc = nullptr, *diag_pp = nullptr, *diag_out = nullptr;  // the periodic check's own sums
+  int32_t *diag_flag = nullptr;
+  long long diag_step = -1;  // step after which the latest periodic check ran
   double *eg_tab = nullptr;        // FP64 gas voidage per particle count (Eq. 11), for lbdps_voidage
   long long *obs_part = nullptr;   // per-workgroup partial counts of lbdps_voidage
   int32_t *dg_n = nullptr;
@@ -326,6 +329,8 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   }
   long long *tile_part = cv.take<long long>(4 * nst);
   double *pc = cv.take<double>(NB_CONS * 3), *pp = cv.take<double>(NB_CONS * 2), *co = cv.take<double>(8);
+  double *dpc = cv.take<double>(NB_CONS * 3), *dpp = cv.take<double>(NB_CONS * 2), *dco = cv.take<double>(8);
+  int32_t *dfl = cv.take<int32_t>(4);
   double *egt = cv.take<double>((size_t)lut_rows(p.d_p));
   long long *obs = cv.take<long long>((size_t)nblocks(p.nx) + 1);
   unsigned long long *cross = cv.take<unsigned long long>(1);
@@ -389,6 +394,10 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->cons_pc = pc;
     x->cons_pp = pp;
     x->cons_out = co;
+    x->diag_pc = dpc;
+    x->diag_pp = dpp;
+    x->diag_out = dco;
+    x->diag_flag = dfl;
     x->eg_tab = egt;
     x->obs_part = obs;
     x->cross = cross;
@@ -644,6 +653,12 @@ template <int P> struct Impl {
       }
       x->cf = 1 - x->cf;
       x->step += 1;
+      if (x->p.diag_every > 0 && x->step % x->p.diag_every == 0) {  // the periodic FP64 check
+        conservation(x, x->diag_pc, x->diag_pp, x->diag_out, x->diag_flag);
+        hipLaunchKernelGGL(k_flag_nonfinite, dim3(1), dim3(64), 0, x->stream, (const double *)x->diag_out,
+                           x->flags);
+        x->diag_step = x->step;
+      }
     }
     return launch_status("lbdps_step");
   }
@@ -759,6 +774,8 @@ lbdps_status sync_and_check(lbdps_ctx *x, const char *what) {
   if (had[FLAG_CAPACITY])
     return fail(LBDPS_E_CAPACITY, std::string(what) + ": a particle had more than LBDPS_MAX_CONTACTS contacts");
   if (had[FLAG_STALL]) return fail(LBDPS_E_STALL, std::string(what) + ": collision resolution exceeded its wait bound");
+  if (had[FLAG_NONFINITE])
+    return fail(LBDPS_E_NONFINITE, std::string(what) + ": the periodic check found a non-finite population or velocity");
   return fail(LBDPS_E_DEVICE, std::string(what) + ": unknown device flag");
 }
 
@@ -810,6 +827,7 @@ lbdps_status lbdps_validate_params(const lbdps_params *p, int64_t max_particles)
   if (!is_fin(p->cs_smag) || p->cs_smag < 0) return fail(LBDPS_E_INVALID, "cs_smag must be >= 0");
   if (p->particles_periodic_y < 0 || p->particles_periodic_y > 1)
     return fail(LBDPS_E_INVALID, "particles_periodic_y must be 0 or 1");
+  if (p->diag_every < 0) return fail(LBDPS_E_INVALID, "diag_every must be >= 0");
   if (p->n_sub < 0 || p->n_sub > LBDPS_MAX_SUBSTEPS)
     return fail(LBDPS_E_INVALID, "n_sub must be in [0, " + std::to_string(LBDPS_MAX_SUBSTEPS) + "]");
   if (p->precision < 0 || p->precision > 3) return fail(LBDPS_E_INVALID, "precision must be 0..3");
@@ -1133,6 +1151,16 @@ lbdps_status conservation_with(lbdps_ctx *x, double *pc, double *pp, double *out
 lbdps_status lbdps_conservation(lbdps_ctx *x, double h_out[6]) {
   if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
   return conservation_with(x, x->cons_pc, x->cons_pp, x->cons_out, x->nonfinite, h_out, "lbdps_conservation");
+}
+
+lbdps_status lbdps_diag_last(lbdps_ctx *x, double h_out[6], int64_t *h_step) {
+  if (!x || !h_out || !h_step) return fail(LBDPS_E_INVALID, "ctx, out or step is NULL");
+  lbdps_status st = sync_and_check(x, "lbdps_diag_last");
+  if (st != LBDPS_OK) return st;
+  *h_step = x->diag_step;
+  for (int i = 0; i < 6; ++i) h_out[i] = 0.0;
+  if (x->diag_step < 0) return LBDPS_OK;
+  return check_hip(hipMemcpy(h_out, x->diag_out, 6 * sizeof(double), hipMemcpyDeviceToHost), "lbdps_diag_last");
 }
 
 lbdps_status lbdps_conservation_noalloc(lbdps_ctx *x, double h_out[6]) {
@@ -1657,6 +1685,7 @@ lbdps_status batch_layout(const lbdps_params *beds, int32_t nbeds, const int64_t
     if (beds[b].precision != prec) return fail(LBDPS_E_INVALID, "all beds of a batch share one precision");
     if (beds[b].diagnostics) return fail(LBDPS_E_UNSUPPORTED, "batched beds do not record diagnostics");
     if (n_sub_of(beds[b]) > 1) return fail(LBDPS_E_UNSUPPORTED, "batched beds take one particle sub-step");
+    if (beds[b].diag_every > 0) return fail(LBDPS_E_UNSUPPORTED, "batched beds take no periodic check");
   }
   size_t tb = 0;
   lbdps_status st = dispatch_batch(prec, [&](auto impl) {

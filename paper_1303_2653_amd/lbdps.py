@@ -45,6 +45,7 @@ class lbdps_params(ctypes.Structure):
         ("drag_ratio_mode", c_i32), ("u_gas_porosity", c_i32), ("omega_mode", c_i32),
         ("pressure_force_sign", c_i32), ("omega_dense", c_dbl), ("cs_smag", c_dbl),
         ("precision", c_i32), ("diagnostics", c_i32), ("n_sub", c_i32), ("particles_periodic_y", c_i32),
+        ("diag_every", c_i32),
     ]
 
 
@@ -83,6 +84,7 @@ _SIGS = {
     "lbdps_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64)]),
     "lbdps_conservation": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
     "lbdps_conservation_noalloc": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
+    "lbdps_diag_last": (c_i32, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
     "lbdps_counters": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
     "lbdps_outlet_crossings": (c_i32, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
     "lbdps_tile_stats": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
@@ -170,6 +172,7 @@ def make_params(cfg: dict, precision=None, diagnostics: bool = False) -> lbdps_p
     p.diagnostics = int(bool(diagnostics))
     p.n_sub = int(cfg.get("n_sub", 1))
     p.particles_periodic_y = int(cfg.get("particles_periodic_y", 0))
+    p.diag_every = int(cfg.get("diag_every", 0))
     return p
 
 
@@ -331,6 +334,13 @@ class Sim:
         out = (c_dbl * 6)()
         check(lbdps_conservation_noalloc(self.ctx, out), "lbdps_conservation_noalloc")
         return np.array(out[:])
+
+    def diag_last(self):
+        """lbdps_diag_last: the latest periodic check's sums and the step after
+        which it ran (-1 if none has)."""
+        out, step = (c_dbl * 6)(), c_i64(0)
+        check(lbdps_diag_last(self.ctx, out, ctypes.byref(step)), "lbdps_diag_last")
+        return np.array(out[:]), step.value
 
     def counters(self):
         out = (c_i64 * 4)()

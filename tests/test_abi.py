@@ -27,7 +27,8 @@ def test_struct_layout_matches_header():
     assert L.lbdps_params.precision.offset == 136
     assert L.lbdps_params.n_sub.offset == 144
     assert L.lbdps_params.particles_periodic_y.offset == 148
-    assert ctypes.sizeof(L.lbdps_params) == 152
+    assert L.lbdps_params.diag_every.offset == 152
+    assert ctypes.sizeof(L.lbdps_params) == 160
 
 
 def _status(p, nmax=10):
@@ -48,6 +49,7 @@ def test_validation_accepts_workloads():
     ("cs_smag", -0.1, L.LBDPS_E_INVALID), ("cs_smag", float("inf"), L.LBDPS_E_INVALID),
     ("drag_ratio_mode", 3, L.LBDPS_E_INVALID), ("n_sub", -1, L.LBDPS_E_INVALID),
     ("n_sub", L.LBDPS_MAX_SUBSTEPS + 1, L.LBDPS_E_INVALID), ("particles_periodic_y", 2, L.LBDPS_E_INVALID),
+    ("diag_every", -1, L.LBDPS_E_INVALID),
 ])
 def test_validation_rejects(field, value, code):
     p = L.make_params(synth.bubble_small())
@@ -137,6 +139,9 @@ def test_batch_rejects_mixed_precision_and_diagnostics():
     assert L.lbdps_batch_workspace_bytes(params, 2, nmax, ctypes.byref(out)) == L.LBDPS_E_UNSUPPORTED
     params[1].n_sub = 1
     assert L.lbdps_batch_workspace_bytes(params, 2, nmax, ctypes.byref(out)) == L.LBDPS_OK
+    params[0].diag_every = 10  # batched beds take no periodic check
+    assert L.lbdps_batch_workspace_bytes(params, 2, nmax, ctypes.byref(out)) == L.LBDPS_E_UNSUPPORTED
+    params[0].diag_every = 0
     params, nmax = _batch(cfgs, "fp32")
     assert L.lbdps_batch_workspace_bytes(params, 0, nmax, ctypes.byref(out)) == L.LBDPS_E_SHAPE
     params[1].tau = 0.4

@@ -1,0 +1,70 @@
+"""The periodic FP64 check inside lbdps_step (lbdps_params.diag_every): it
+runs after every diag_every-th step, gives the sums lbdps_conservation gives
+on the same state, leaves the state untouched, and latches a non-finite
+population so that the next synchronising call reports LBDPS_E_NONFINITE."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+L = pytest.importorskip("paper_1303_2653_amd.lbdps")
+
+
+def walled_bed(**kw):
+    return synth.tiny(nx=40, ny=30, n=400, seed=12, bc=("wall", "wall", "periodic", "periodic"), vel_scale=1e-2,
+                      G=(0.0, 1e-5), **kw)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_periodic_check_equals_conservation(prec):
+    sim = L.Sim(walled_bed(diag_every=3), precision=prec)
+    sums, step = sim.diag_last()
+    assert step == -1 and not sums.any()
+    sim.step(2)
+    assert sim.diag_last()[1] == -1
+    sim.step(1)
+    s3, step = sim.diag_last()
+    print(prec, "step 3", s3, flush=True)
+    assert step == 3 and np.array_equal(s3, sim.conservation()) and s3[5] == 0.0
+    sim.step(2)  # steps 4 and 5: no check ran, the latest sums stay
+    s, step = sim.diag_last()
+    assert step == 3 and np.array_equal(s, s3)
+    sim.step(1)
+    s6, step = sim.diag_last()
+    assert step == 6 and np.array_equal(s6, sim.conservation())
+    # the check reads the state and changes nothing
+    plain = L.Sim(walled_bed(), precision=prec)
+    plain.step(6)
+    for a, b in zip(sim.state()[:3], plain.state()[:3]):
+        assert np.array_equal(a, b)
+    assert sim.counters() == plain.counters()
+    sim.close()
+    plain.close()
+
+
+def test_periodic_check_reports_a_non_finite_population():
+    """A particle-free periodic bed with one NaN population: off, the steps
+    report nothing; with diag_every = 1 the next synchronising call reports
+    LBDPS_E_NONFINITE once, and the sums then carry the non-finite mark."""
+    for every in (0, 1):
+        cfg = synth.tiny(nx=16, ny=24, n=0, seed=4, bc=("periodic",) * 4, g=(0.0, 0.0), diag_every=every)
+        sim = L.Sim(cfg, precision="fp64")
+        f = sim.state()[0]
+        f[4, 10, 7] = np.nan
+        sim.set_state(f, np.zeros((0, 2)), np.zeros((0, 2)))
+        sim.step(2)
+        print("diag_every", every, flush=True)
+        if every == 0:
+            assert sim.diag_last()[1] == -1
+        else:
+            with pytest.raises(L.LbdpsError) as e:
+                sim.diag_last()
+            assert e.value.status == L.LBDPS_E_NONFINITE
+            sums, step = sim.diag_last()  # reported once; the flag is cleared
+            assert step == 2 and sums[5] != 0.0
+        sim.close()
