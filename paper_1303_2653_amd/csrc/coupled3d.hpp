@@ -632,15 +632,7 @@ __device__ __forceinline__ void resolve_cluster3(Row q, int m, unsigned long lon
                                                  Parts3<typename Prec<P>::T> &pt, int32_t *done, long long &ncoll) {
   using T = typename Prec<P>::T;
   constexpr int NB3 = 2;
-  for (int i = 1; i < m; ++i) {
-    const long long e = q[i];
-    int j = i - 1;
-    while (j >= 0 && q[j] > e) {
-      q[j + 1] = q[j];
-      --j;
-    }
-    q[j + 1] = e;
-  }
+  sort_members(q, m);
   for (int i = 0; i < m; ++i) {
     const long long qi = q[i];
     const int u = (int)(qi & 0x1fffffffll);

@@ -1714,20 +1714,23 @@ struct LdsColumn {  // entry i of a lane's column of a [CL_LDS][BLOCK] LDS array
 // contacts are kept as an 8 x 8 bit matrix over those places (bit 8 a + b:
 // places a and b touch); every contact of a member is inside the cluster, so
 // the matrix holds each member's whole neighbour list.
-constexpr long long CL_POS = 7ll << 29;
 static_assert(CL_LDS <= 8, "places of the members fit in three bits");
 __device__ __forceinline__ unsigned long long cl_bit(int a, int b) { return 1ull << (8 * a + b); }
 
 // Gathers the cluster of candidate slot s (index g) into q[0 .. m) and its
 // contacts into A; returns m, 0 if a member has a lower index than g, and -1
-// if the cluster has more than cap members.  Members are expanded two at a
-// time, so the rows of both are loaded together.
+// if the cluster has more than cap (<= CL_LDS) members.  Members are expanded
+// two at a time, so the rows of both are loaded together.  The members' slots
+// are also kept in registers, where the membership test looks them up.
 template <class Row>
 __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, Adj adj,
                                               const int32_t *__restrict__ deg, unsigned long long &A) {
   q[0] = ((long long)g << 32) | (unsigned)s;
   A = 0;
   int m = 1;
+  int sl[CL_LDS];  // slot of the member at each place, -1 past m
+#pragma unroll
+  for (int i = 0; i < CL_LDS; ++i) sl[i] = i == 0 ? s : -1;
   // adds the contacts of the member at place h; false when the candidate gives up
   auto expand = [&](int h, const AdjRow &ru, int du, const Dense4 &e4, int &res) {
     for (int a = 0; a < du; ++a) {
@@ -1736,9 +1739,11 @@ __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, Adj 
         res = 0;
         return false;
       }
+      const int es = (int)(e & 0x1fffffffll);
       int p = -1;
-      for (int i = 0; i < m; ++i)
-        if ((q[i] & ~CL_POS) == e) p = i;
+#pragma unroll
+      for (int i = 0; i < CL_LDS; ++i)
+        if (sl[i] == es) p = i;
       if (p < 0) {
         if (m == cap) {
           res = -1;
@@ -1746,6 +1751,9 @@ __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, Adj 
         }
         p = m;
         q[m] = e | ((long long)m << 29);
+#pragma unroll
+        for (int i = 1; i < CL_LDS; ++i)
+          if (i == m) sl[i] = es;
         ++m;
       }
       A |= cl_bit(h, p) | cl_bit(p, h);
@@ -1754,8 +1762,13 @@ __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, Adj 
   };
   for (int head = 0; head < m;) {
     const bool two = head + 1 < m;
-    const int u0 = (int)(q[head] & 0x1fffffffll);
-    const int u1 = two ? (int)(q[head + 1] & 0x1fffffffll) : u0;
+    int u0 = s, u1 = s;
+#pragma unroll
+    for (int i = 1; i < CL_LDS; ++i) {
+      if (i == head) u0 = sl[i];
+      if (i == head + 1) u1 = sl[i];
+    }
+    if (!two) u1 = u0;
     const AdjRow r0 = adj.row(u0), r1 = adj.row(u1);
     const int d0 = min(ldu(deg, u0), KMAX), d1 = two ? min(ldu(deg, u1), KMAX) : 0;
     // the dense parts of both rows
@@ -1766,6 +1779,22 @@ __device__ __forceinline__ int gather_cluster(Row q, int cap, int s, int g, Adj 
     head += two ? 2 : 1;
   }
   return m;
+}
+
+// Orders the m gathered entries by index: all are read at once and each is
+// written to its rank among them (the indices are distinct), so no chain of
+// dependent LDS accesses as an insertion sort would make.
+template <class Row> __device__ __forceinline__ void sort_members(Row q, int m) {
+  long long e[CL_LDS];
+#pragma unroll
+  for (int i = 0; i < CL_LDS; ++i) e[i] = i < m ? q[i] : 0x7fffffffffffffffll;
+#pragma unroll
+  for (int i = 0; i < CL_LDS; ++i) {
+    int r = 0;
+#pragma unroll
+    for (int j = 0; j < CL_LDS; ++j) r += e[j] < e[i];
+    if (i < m) q[r] = e[i];
+  }
 }
 
 // Orders the gathered members by index and applies the cluster's pairs in
@@ -1782,30 +1811,21 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, unsigned long long
                                                 Parts<typename Prec<P>::T> &pt, int32_t *done, long long &ncoll,
                                                 long long &nwall) {
   using T = typename Prec<P>::T;
-  for (int i = 1; i < m; ++i) {
-    const long long e = q[i];
-    int j = i - 1;
-    while (j >= 0 && q[j] > e) {
-      q[j + 1] = q[j];
-      --j;
-    }
-    q[j + 1] = e;
-  }
-  int us[CL_LDS], pl[CL_LDS], kk[CL_LDS];
+  sort_members(q, m);
+  int pl[CL_LDS], kk[CL_LDS];
   T xx[CL_LDS], yy[CL_LDS], vx[CL_LDS], vy[CL_LDS];
 #pragma unroll
   for (int i = 0; i < CL_LDS; ++i) {
-    us[i] = 0;
     pl[i] = 0;
     if (i < m) {
       const long long qi = q[i];
-      us[i] = (int)(qi & 0x1fffffffll);
+      const int u = (int)(qi & 0x1fffffffll);
       pl[i] = (int)((qi >> 29) & 7);
-      kk[i] = ldu(pt.key, us[i]);
-      xx[i] = ldu(pt.px, us[i]);
-      yy[i] = ldu(pt.py, us[i]);
-      vx[i] = ldu(pt.vx, us[i]);
-      vy[i] = ldu(pt.vy, us[i]);
+      kk[i] = ldu(pt.key, u);
+      xx[i] = ldu(pt.px, u);
+      yy[i] = ldu(pt.py, u);
+      vx[i] = ldu(pt.vx, u);
+      vy[i] = ldu(pt.vy, u);
     }
   }
 #pragma unroll
@@ -1821,9 +1841,10 @@ __device__ __forceinline__ void resolve_cluster(Row q, int m, unsigned long long
         }
       }
       nwall += Pos<P>::walls_key(k, kk[i], xx[i], yy[i], vx[i], vy[i]);
-      pt.vx[us[i]] = vx[i];
-      pt.vy[us[i]] = vy[i];
-      done[us[i]] = __builtin_popcount(nbr) | DONE_WHOLE;  // its contacts, all inside the cluster
+      const int u = (int)(q[i] & 0x1fffffffll);  // the slot again from LDS rather than held
+      pt.vx[u] = vx[i];
+      pt.vy[u] = vy[i];
+      done[u] = __builtin_popcount(nbr) | DONE_WHOLE;  // its contacts, all inside the cluster
     }
   }
 }
@@ -2066,9 +2087,11 @@ __device__ __forceinline__ void resolve_clusters_body(const int bidx, const int 
   const bool overflow = __hip_atomic_load(&k.flags[FLAG_CAPACITY], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
   // list j holds rcount[j] candidates, or, with one compact list of *nroots
   // (the tile kernel's), its j-th run of BLOCK
+  // (the counts are loaded alongside the flag, not after it)
   int c = 0;
-  if (!overflow && (int)threadIdx.x < nb)
+  if ((int)threadIdx.x < nb)
     c = nroots ? min(max(*nroots - (b0 + (int)threadIdx.x) * BLOCK, 0), BLOCK) : rcount[b0 + threadIdx.x];
+  if (overflow) c = 0;
   const int o = block_excl_scan(c, shi, tot);
   if (tot == 0) {  // no candidate roots in these lists (uniform: the scan's total)
     if (threadIdx.x == 0) {
