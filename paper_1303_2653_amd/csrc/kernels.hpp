@@ -2374,32 +2374,61 @@ __global__ __launch_bounds__(BLOCK) void k_scan_cells(int32_t *__restrict__ coun
   scan_cells_body(xcd_block<XCD_RUN_SCAN>(blockIdx.x, gridDim.x), gridDim.x, count, n, ts, out, stay);
 }
 
+// Generic three-pass scan of n counts (reduce, top, apply), for scans whose
+// tile sums nobody counted beforehand.  A full run of SCAN_ITEMS counts moves
+// as two 16-byte vectors (the arrays are 256-byte aligned).
+__device__ __forceinline__ bool scan_load8(const int32_t *__restrict__ in, long long e0, long long n, int v[8]) {
+  if (e0 + SCAN_ITEMS <= n) {
+    const int4 a = *(const int4 *)(in + e0), b = *(const int4 *)(in + e0 + 4);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+    v[4] = b.x;
+    v[5] = b.y;
+    v[6] = b.z;
+    v[7] = b.w;
+    return true;
+  }
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) v[j] = e0 + j < n ? in[e0 + j] : 0;
+  return false;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int32_t *__restrict__ in, long long n,
                                                        int32_t *__restrict__ part) {
+  static_assert(SCAN_ITEMS == 8, "two 16-byte vectors per thread");
   __shared__ int sh[BLOCK / 64];
   const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  int vals[SCAN_ITEMS];
+  scan_load8(in, base, n, vals);
   int v = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j)
-    if (base + j < n) v += in[base + j];
+  for (int j = 0; j < SCAN_ITEMS; ++j) v += vals[j];
   int total;
   block_excl_scan(v, sh, total);
   if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
-// Single workgroup: exclusive scan of the tile totals; writes the grand total to *total_out.
+// Single workgroup: exclusive scan of the tile totals; writes the grand total
+// to *total_out.  Each thread takes a contiguous run of the totals, so there
+// is one workgroup scan whatever their number.
 __global__ __launch_bounds__(BLOCK) void k_scan_top(int32_t *__restrict__ part, int ntiles, int32_t *total_out) {
   __shared__ int sh[BLOCK / 64];
-  int carry = 0;
-  for (int base = 0; base < ntiles; base += BLOCK) {
-    const int i = base + threadIdx.x;
-    const int v = i < ntiles ? part[i] : 0;
-    int total;
-    const int ex = block_excl_scan(v, sh, total);
-    if (i < ntiles) part[i] = carry + ex;
-    carry += total;
+  const int per = (ntiles + BLOCK - 1) / BLOCK;
+  const int i0 = min((int)threadIdx.x * per, ntiles), i1 = min(i0 + per, ntiles);
+  int sum = 0;
+#pragma unroll 16
+  for (int i = i0; i < i1; ++i) sum += part[i];
+  int total;
+  int run = block_excl_scan(sum, sh, total);
+#pragma unroll 16
+  for (int i = i0; i < i1; ++i) {
+    const int v = part[i];
+    part[i] = run;
+    run += v;
   }
-  if (threadIdx.x == 0) *total_out = carry;
+  if (threadIdx.x == 0) *total_out = total;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_apply(int32_t *__restrict__ in, long long n,
@@ -2408,21 +2437,33 @@ __global__ __launch_bounds__(BLOCK) void k_scan_apply(int32_t *__restrict__ in, 
   __shared__ int sh[BLOCK / 64];
   const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
+  const bool full = scan_load8(in, base, n, v);
   int sum = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j) {
-    v[j] = base + j < n ? in[base + j] : 0;
-    sum += v[j];
-  }
+  for (int j = 0; j < SCAN_ITEMS; ++j) sum += v[j];
   int total;
   int run = part[blockIdx.x] + block_excl_scan(sum, sh, total);
+  int o[SCAN_ITEMS];
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j)
-    if (base + j < n) {
-      out[base + j] = run;
-      run += v[j];
-      if (zero_in) in[base + j] = 0;
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    o[j] = run;
+    run += v[j];
+  }
+  if (full) {
+    *(int4 *)(out + base) = make_int4(o[0], o[1], o[2], o[3]);
+    *(int4 *)(out + base + 4) = make_int4(o[4], o[5], o[6], o[7]);
+    if (zero_in) {
+      *(int4 *)(in + base) = make_int4(0, 0, 0, 0);
+      *(int4 *)(in + base + 4) = make_int4(0, 0, 0, 0);
     }
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j)
+      if (base + j < n) {
+        out[base + j] = o[j];
+        if (zero_in) in[base + j] = 0;
+      }
+  }
 }
 
 // ------------------------------------------------------------------ FP64 conservation sums (fixed-order reductions)
