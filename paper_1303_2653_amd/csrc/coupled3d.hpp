@@ -423,50 +423,65 @@ template <int P> struct Interp3 {
 };
 
 // ---------------------------------------------------------------- drag, integration, binning count
-// Two passes, one thread per particle slot (a cell-per-thread form left most
-// lanes idle: about one cell in seven holds a sphere).  Pass 1 interpolates
-// at each particle and stores its pre-estimated drag (Eq. 26) and grad p.
-// Pass 2 sums the pre-drags of the particle's cell over its segment in slot
-// order (ascending index, as the collide kernel left it) for Eq. 27, applies
-// Eq. 28 and the acceleration of Eq. 16, moves the particle with the
-// periodic wrap, stores the record in place and counts it into its new cell.
-// pre holds [6][N]: the pre-drag, then grad p, per axis.
-template <int P>
-__global__ __launch_bounds__(BLOCK) void k3c_predrag(Parts3<typename Prec<P>::T> pt, Fields3<typename Prec<P>::T> fl,
-                                                     Consts3<typename Prec<P>::T> k, typename Prec<P>::T *__restrict__ pre) {
+// One thread per particle slot (a cell-per-thread form left most lanes idle:
+// about one cell in seven holds a sphere).  Each thread interpolates at its
+// particle and keeps its pre-estimated drag (Eq. 26) in LDS; then it sums the
+// pre-drags of its cell's segment in slot order (ascending index, as the
+// collide kernel left it) for Eq. 27, taking members outside the workgroup's
+// slots (only the first and last cell of a workgroup can have them) from the
+// same interpolation done again, applies Eq. 28 and the acceleration of
+// Eq. 16, moves the particle with the periodic wrap and counts it into its
+// new cell.  The moved record goes to the same slot of the other record set
+// (out), so the records every workgroup reads stay as they were.
+template <int P> struct PreDrag3 {
   using T = typename Prec<P>::T;
-  const int s = blockIdx.x * BLOCK + threadIdx.x;
-  if (s >= k.npart) return;
-  const size_t N = (size_t)k.npart;
-  int cc[3];
-  cell3_xyz(k, pt.key[s], cc[0], cc[1], cc[2]);
-  const T o[3] = {pt.px[s], pt.py[s], pt.pz[s]}, v[3] = {pt.vx[s], pt.vy[s], pt.vz[s]};
+  T pd[3];  // cf (u_gas - v), Eq. 26 before the per-cell correction
   Interp3<P> I;
-  I.at(k, fl, cc, o);
-  const T cf = dv<P>(k.vp * I.beta, I.es);
+  __device__ void at(const Parts3<T> &pt, const Fields3<T> &fl, const Consts3<T> &k, int t) {
+    int cc[3];
+    cell3_xyz(k, pt.key[t], cc[0], cc[1], cc[2]);
+    const T o[3] = {pt.px[t], pt.py[t], pt.pz[t]}, v[3] = {pt.vx[t], pt.vy[t], pt.vz[t]};
+    I.at(k, fl, cc, o);
+    const T cf = dv<P>(k.vp * I.beta, I.es);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    pre[q * N + s] = cf * (I.u[q] - v[q]);
-    pre[(3 + q) * N + s] = I.gp[q];
+    for (int q = 0; q < 3; ++q) pd[q] = cf * (I.u[q] - v[q]);
   }
-}
+};
 
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k3c_drag(Parts3<typename Prec<P>::T> pt, Fields3<typename Prec<P>::T> fl,
-                                                  const int32_t *__restrict__ cs, Consts3<typename Prec<P>::T> k,
-                                                  const typename Prec<P>::T *__restrict__ pre,
-                                                  int32_t *__restrict__ count, int32_t *__restrict__ rank,
-                                                  typename Prec<P>::T *dg_fd, typename Prec<P>::T *dg_acc) {
+__global__ __launch_bounds__(BLOCK) void k3c_drag(Parts3<typename Prec<P>::T> pt, Parts3<typename Prec<P>::T> out,
+                                                  Fields3<typename Prec<P>::T> fl, const int32_t *__restrict__ cs,
+                                                  Consts3<typename Prec<P>::T> k, int32_t *__restrict__ count,
+                                                  int32_t *__restrict__ rank, typename Prec<P>::T *dg_fd,
+                                                  typename Prec<P>::T *dg_acc) {
   using T = typename Prec<P>::T;
-  const int s = blockIdx.x * BLOCK + threadIdx.x;
+  __shared__ T spd[3][BLOCK];
+  const int s0 = blockIdx.x * BLOCK, s = s0 + threadIdx.x, s1 = min(s0 + BLOCK, k.npart);
+  PreDrag3<P> me;
+  if (s < k.npart) {
+    me.at(pt, fl, k, s);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) spd[q][threadIdx.x] = me.pd[q];
+  }
+  __syncthreads();
   if (s >= k.npart) return;
-  const size_t N = (size_t)k.npart;
   const int c = pt.key[s];
   const int a0 = cs[c], a1 = cs[c + 1], n = a1 - a0;
   T S[3] = {(T)0, (T)0, (T)0};
-  for (int t = a0; t < a1; ++t)
+  for (int t = a0; t < a1; ++t) {
+    T pd[3];
+    if (t >= s0 && t < s1) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) S[q] += pre[q * N + t];
+      for (int q = 0; q < 3; ++q) pd[q] = spd[q][t - s0];
+    } else {  // a member held by the neighbouring workgroup
+      PreDrag3<P> o;
+      o.at(pt, fl, k, t);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) pd[q] = o.pd[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) S[q] += pd[q];
+  }
   int cc[3];
   cell3_xyz(k, c, cc[0], cc[1], cc[2]);
   const T fg[3] = {fl.fpx[c], fl.fpy[c], fl.fpz[c]};
@@ -476,9 +491,9 @@ __global__ __launch_bounds__(BLOCK) void k3c_drag(Parts3<typename Prec<P>::T> pt
   T fd[3], acc[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const T pr = pre[q * N + s];
+    const T pr = me.pd[q];
     fd[q] = S[q] == (T)0 ? dv<P>(-fg[q], (T)n) : dv<P>(-fg[q] * pr, S[q]);
-    acc[q] = k.geff[q] + dv<P>(fd[q] + k.fp * pre[(3 + q) * N + s], k.m);
+    acc[q] = k.geff[q] + dv<P>(fd[q] + k.fp * me.I.gp[q], k.m);
     v[q] = v[q] + acc[q];
     nc[q] = Pos3<P>::move_axis(cc[q], o[q], v[q], nn[q]);
   }
@@ -495,13 +510,14 @@ __global__ __launch_bounds__(BLOCK) void k3c_drag(Parts3<typename Prec<P>::T> pt
     atomicOr(&k.flags[FLAG_DOMAIN], 1);
     nk = c;
   }
-  pt.key[s] = nk;
-  pt.px[s] = o[0];
-  pt.py[s] = o[1];
-  pt.pz[s] = o[2];
-  pt.vx[s] = v[0];
-  pt.vy[s] = v[1];
-  pt.vz[s] = v[2];
+  out.key[s] = nk;
+  out.pid[s] = id;
+  out.px[s] = o[0];
+  out.py[s] = o[1];
+  out.pz[s] = o[2];
+  out.vx[s] = v[0];
+  out.vy[s] = v[1];
+  out.vz[s] = v[2];
   rank[s] = atomicAdd(&count[nk], 1);
 }
 

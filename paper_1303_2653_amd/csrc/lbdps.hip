@@ -1942,7 +1942,6 @@ struct lbdps3_ctx {
   int32_t *ticket = nullptr, *flags = nullptr, *chunk_busy = nullptr, *spart = nullptr, *pcnt = nullptr;
   long long *pair_part = nullptr, *coll_part = nullptr, *collc_part = nullptr;
   long long *roots = nullptr;  // candidate cluster roots, BLOCK per contact workgroup
-  void *pre = nullptr;         // per particle: pre-estimated drag and grad p, [6][N]
   int32_t *rcount = nullptr, *need_sweep = nullptr;
   void *lut = nullptr;
   int32_t *dg_n = nullptr;
@@ -2018,7 +2017,6 @@ size_t carve3(const lbdps3_params &p, long long nmax, char *base, lbdps3_ctx *x)
   const size_t nbN3 = (size_t)nblocks((long long)N);
   long long *roots = cv.take<long long>(nbN3 * BLOCK);
   int32_t *rcount = cv.take<int32_t>(nbN3), *need_sweep = cv.take<int32_t>(4);
-  char *pre = raw(6 * N * sT);
   char *lut = raw((size_t)lut3_rows(p.d_p) * L3_W * sT);
   int32_t *dg_n = nullptr;
   char *dg_fd = nullptr, *dg_acc = nullptr;
@@ -2058,7 +2056,6 @@ size_t carve3(const lbdps3_params &p, long long nmax, char *base, lbdps3_ctx *x)
     x->roots = roots;
     x->rcount = rcount;
     x->need_sweep = need_sweep;
-    x->pre = pre;
     x->lut = lut;
     x->dg_n = dg_n;
     x->dg_fd = dg_fd;
@@ -2149,11 +2146,11 @@ template <int P> struct Impl3 {
                          k, dg ? x->dg_n : nullptr);
       if (x->n > 0) {
         hipLaunchKernelGGL(k3c_gradp<P>, dim3(nblocks(x->C)), dim3(BLOCK), 0, x->stream, fields(x), k);
-        hipLaunchKernelGGL(k3c_predrag<P>, dim3(nblocks(x->n)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
-                           fields(x), k, (T *)x->pre);
-        hipLaunchKernelGGL(k3c_drag<P>, dim3(nblocks(x->n)), dim3(BLOCK), 0, x->stream, parts(x, x->cp), fields(x),
-                           (const int32_t *)x->cs, k, (const T *)x->pre, x->count, x->rank,
+        // the moved records go to the other set, which then holds the current state
+        hipLaunchKernelGGL(k3c_drag<P>, dim3(nblocks(x->n)), dim3(BLOCK), 0, x->stream, parts(x, x->cp),
+                           parts(x, 1 - x->cp), fields(x), (const int32_t *)x->cs, k, x->count, x->rank,
                            dg ? (T *)x->dg_fd : nullptr, dg ? (T *)x->dg_acc : nullptr);
+        x->cp = 1 - x->cp;
         sort(x, true);
         hard_spheres(x);
       }
