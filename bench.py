@@ -161,8 +161,9 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None, tuning=None):
     kt = sim.kernel_times()[dominant]
     sim.time_kernels([])
     counters = sim.counters()
+    sums, dstep = sim.diag_last()  # the periodic FP64 check (raises if it found a non-finite value)
     out = dict(ms=ms, breakdown_us=breakdown, dominant=dominant, dom_ms=kt[0], dom_launches=kt[1],
-               pairs=counters["pairs"], tuning=sim.tuning())
+               pairs=counters["pairs"], tuning=sim.tuning(), diag=(sums, dstep))
     sim.close()
     return out
 
@@ -588,6 +589,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=sorted(SIZES))
     ap.add_argument("--n-sub", type=int, default=1, help="particle sub-steps per lattice step")
     ap.add_argument("--cs-smag", type=float, default=None, help="Smagorinsky constant (sub-grid model on)")
+    ap.add_argument("--diag-every", type=int, default=100,
+                    help="steps between the FP64 conservation checks inside lbdps_step (0: off)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="seconds of each oracle leg")
     ap.add_argument("--tuning", default=None, metavar="LISTS,GROUPS[,DRAG[,SPHERE]]",
                     help="fixed launch shapes instead of the autotuner (profiling runs): cluster lists and "
@@ -638,6 +641,7 @@ def main():
         cfg["n_sub"] = args.n_sub
     if args.cs_smag is not None:
         cfg["cs_smag"] = args.cs_smag
+    cfg["diag_every"] = args.diag_every  # the FP64 conservation check inside the timed steps
     C, N = cfg["nx"] * cfg["ny"], len(cfg["pos"])
     fixed = None
     if args.tuning:
@@ -683,11 +687,16 @@ def main():
                    + (f"-les{args.cs_smag:g}" if args.cs_smag is not None else ""), "nx": cfg["nx"], "ny": cfg["ny"],
                    "particles": N,
                    "precision": args.precision, "d_p": cfg["d"], "tau": cfg["tau"],
-                   "n_sub": cfg.get("n_sub", 1), "cs_smag": cfg.get("cs_smag", 0.0)},
+                   "n_sub": cfg.get("n_sub", 1), "cs_smag": cfg.get("cs_smag", 0.0),
+                   "diag_every": args.diag_every},
         "particle_updates_per_s": float(f"{pups:.4e}"),
         "model_bytes_per_step": int(model),
         "model_bw_frac": round(model * args.steps / s / 1e9 / HBM_PEAK_GBS, 4),
         "contact_pairs": r["pairs"],
+        "conservation": {"last_check_step": r["diag"][1], "mass": float(r["diag"][0][0]),
+                         "gas_momentum": [float(v) for v in r["diag"][0][1:3]],
+                         "particle_momentum": [float(v) for v in r["diag"][0][3:5]],
+                         "nonfinite": int(r["diag"][0][5])},
         "autotune": [r["tuning"][f] for f in ("cluster_lists", "cluster_groups_max", "drag_tile", "sphere_tile")],
         "kernel_us": {k: round(v, 2) for k, v in r["breakdown_us"].items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
