@@ -396,6 +396,13 @@ lbdps_status lbdps3_get_pairs(lbdps3_ctx *ctx, int32_t *d_pairs, int64_t cap, in
  * step.  Synchronises. */
 lbdps_status lbdps3_counters(lbdps3_ctx *ctx, int64_t h_out[2]);
 /* Release the host context (the workspace stays the caller's). */
+/* FP64 conservation sums over the current state, fixed-order reductions (the
+ * invariants of the collision and coupling, Eqs. 7, 17-18, 25, 28-29):
+ * h_out[0] = sum of f (mass), h_out[1..3] = sum c_i f_i (gas momentum),
+ * h_out[4..6] = sum m v (particle momentum, m = rho_s pi d_p^3 / 6), h_out[7]
+ * = 1 if any value is not finite, else 0; returns LBDPS_E_NONFINITE then.
+ * Synchronises. */
+lbdps_status lbdps3_conservation(lbdps3_ctx *ctx, double h_out[8]);
 lbdps_status lbdps3_destroy(lbdps3_ctx *ctx);
 
 /* Kernels of one step, for per-kernel timing. */

@@ -922,6 +922,81 @@ __global__ __launch_bounds__(BLOCK) void k3_get_f(const typename Prec<P>::S *__r
   else out[e] = w3<double>((int)(e / C)) + (double)load_v<P>(f, (size_t)e);
 }
 
+// ---------------------------------------------------------------- FP64 conservation sums (fixed-order reductions)
+// Per workgroup over a fixed stride of cells: the mass and gas momentum of the
+// canonical populations (the weights plus the deviations in the reduced
+// storages), part[4 b + j]; a non-finite value sets *nonfinite.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k3_cons_cells(const typename Prec<P>::S *__restrict__ f, long long C,
+                                                       double *__restrict__ part, int32_t *nonfinite) {
+  __shared__ double sh[BLOCK / 64];
+  double m = 0.0, q[3] = {0.0, 0.0, 0.0};
+  int bad = 0;
+  for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < C; c += (long long)gridDim.x * BLOCK) {
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      double v;
+      if constexpr (P == PREC_FP64) v = f[(size_t)i * C + c];
+      else v = w3<double>(i) + (double)load_v<P>(f, (size_t)i * C + c);
+      bad |= !isfinite(v);
+      m += v;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) q[a] += (double)c3(i, a) * v;
+    }
+  }
+  if (bad) atomicOr(nonfinite, 1);
+  const double t0 = block_sum_d(m, sh), t1 = block_sum_d(q[0], sh), t2 = block_sum_d(q[1], sh),
+               t3 = block_sum_d(q[2], sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 4 + 0] = t0;
+    part[blockIdx.x * 4 + 1] = t1;
+    part[blockIdx.x * 4 + 2] = t2;
+    part[blockIdx.x * 4 + 3] = t3;
+  }
+}
+
+// The particles' momentum m v per workgroup, part[3 b + a].
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k3_cons_parts(Parts3<T> pt, int n, double mass, double *__restrict__ part,
+                                                       int32_t *nonfinite) {
+  __shared__ double sh[BLOCK / 64];
+  double q[3] = {0.0, 0.0, 0.0};
+  int bad = 0;
+  for (int s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
+    const double v[3] = {(double)pt.vx[s], (double)pt.vy[s], (double)pt.vz[s]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      bad |= !isfinite(v[a]);
+      q[a] += mass * v[a];
+    }
+  }
+  if (bad) atomicOr(nonfinite, 1);
+  const double t0 = block_sum_d(q[0], sh), t1 = block_sum_d(q[1], sh), t2 = block_sum_d(q[2], sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 3 + 0] = t0;
+    part[blockIdx.x * 3 + 1] = t1;
+    part[blockIdx.x * 3 + 2] = t2;
+  }
+}
+
+// out[0] mass, out[1..3] gas momentum, out[4..6] particle momentum, out[7]
+// 1 if a value was not finite: the workgroup partials summed in a fixed order.
+__global__ __launch_bounds__(BLOCK) void k3_cons_final(const double *__restrict__ pc, int nbc,
+                                                       const double *__restrict__ pp, int nbp,
+                                                       const int32_t *nonfinite, double *out) {
+  __shared__ double sh[BLOCK / 64];
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nbc; b += BLOCK)
+    for (int j = 0; j < 4; ++j) v[j] += pc[b * 4 + j];
+  for (int b = threadIdx.x; b < nbp; b += BLOCK)
+    for (int j = 0; j < 3; ++j) v[4 + j] += pp[b * 3 + j];
+  for (int j = 0; j < 7; ++j) {
+    const double t = block_sum_d(v[j], sh);
+    if (threadIdx.x == 0) out[j] = t;
+  }
+  if (threadIdx.x == 0) out[7] = *nonfinite ? 1.0 : 0.0;
+}
+
 // A field to FP64: one plane (out[i] = add + a[i]) or three interleaved
 // (out[3 i + q] = plane q).
 template <class T>

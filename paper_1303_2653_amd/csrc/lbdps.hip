@@ -1941,6 +1941,8 @@ struct lbdps3_ctx {
   long long *adj_in = nullptr, *adj_ov = nullptr;
   int32_t *ticket = nullptr, *flags = nullptr, *chunk_busy = nullptr, *spart = nullptr, *pcnt = nullptr;
   long long *pair_part = nullptr, *coll_part = nullptr, *collc_part = nullptr;
+  double *cons_pc = nullptr, *cons_pp = nullptr, *cons_out = nullptr;  // conservation scratch
+  int32_t *cons_flag = nullptr;
   long long *roots = nullptr;  // candidate cluster roots, BLOCK per contact workgroup
   int32_t *rcount = nullptr, *need_sweep = nullptr;
   void *lut = nullptr;
@@ -2014,6 +2016,8 @@ size_t carve3(const lbdps3_params &p, long long nmax, char *base, lbdps3_ctx *x)
   const size_t nb = (size_t)nblocks((long long)std::max(C, N)) + 1;
   long long *pair_part = cv.take<long long>(nb), *coll_part = cv.take<long long>(nb);
   long long *collc_part = cv.take<long long>(nb);
+  double *cpc = cv.take<double>(NB_CONS * 4), *cpp = cv.take<double>(NB_CONS * 3), *cout = cv.take<double>(8);
+  int32_t *cflag = cv.take<int32_t>(4);
   const size_t nbN3 = (size_t)nblocks((long long)N);
   long long *roots = cv.take<long long>(nbN3 * BLOCK);
   int32_t *rcount = cv.take<int32_t>(nbN3), *need_sweep = cv.take<int32_t>(4);
@@ -2053,6 +2057,10 @@ size_t carve3(const lbdps3_params &p, long long nmax, char *base, lbdps3_ctx *x)
     x->pair_part = pair_part;
     x->coll_part = coll_part;
     x->collc_part = collc_part;
+    x->cons_pc = cpc;
+    x->cons_pp = cpp;
+    x->cons_out = cout;
+    x->cons_flag = cflag;
     x->roots = roots;
     x->rcount = rcount;
     x->need_sweep = need_sweep;
@@ -2067,6 +2075,7 @@ size_t carve3(const lbdps3_params &p, long long nmax, char *base, lbdps3_ctx *x)
 template <int P> struct Impl3 {
   using T = typename Prec<P>::T;
   using S = typename Prec<P>::S;
+  static constexpr int kP = P;
 
   static Consts3<T> consts(const lbdps3_ctx *x) {
     Consts3<T> k{};
@@ -2415,6 +2424,32 @@ lbdps_status lbdps3_counters(lbdps3_ctx *x, int64_t h_out[2]) {
   st = check_hip(hipMemcpy(buf.data(), x->collc_part, (size_t)ncl * 8, hipMemcpyDeviceToHost), "lbdps3_counters");
   if (st != LBDPS_OK) return st;
   for (int b = 0; b < ncl; ++b) h_out[1] += buf[b];
+  return LBDPS_OK;
+}
+
+lbdps_status lbdps3_conservation(lbdps3_ctx *x, double h_out[8]) {
+  if (!x || !h_out) return fail(LBDPS_E_INVALID, "ctx or out is NULL");
+  lbdps_status st = dispatch3(x, [&](auto impl) {
+    using I = decltype(impl);
+    using T = typename I::T;
+    using S = typename I::S;
+    const double mass = x->p.rho_s * kPi * x->p.d_p * x->p.d_p * x->p.d_p / 6.0;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, x->cons_flag, 1ll, 0);
+    hipLaunchKernelGGL(k3_cons_cells<decltype(impl)::kP>, dim3(NB_CONS), dim3(BLOCK), 0, x->stream,
+                       (const S *)x->f[x->cf], (long long)x->C, x->cons_pc, x->cons_flag);
+    hipLaunchKernelGGL(k3_cons_parts<T>, dim3(NB_CONS), dim3(BLOCK), 0, x->stream, I::parts(x, x->cp), (int)x->n,
+                       mass, x->cons_pp, x->cons_flag);
+    hipLaunchKernelGGL(k3_cons_final, dim3(1), dim3(BLOCK), 0, x->stream, (const double *)x->cons_pc, NB_CONS,
+                       (const double *)x->cons_pp, NB_CONS, (const int32_t *)x->cons_flag, x->cons_out);
+    return launch_status("lbdps3_conservation");
+  });
+  if (st != LBDPS_OK) return st;
+  st = check_hip(hipMemcpyAsync(h_out, x->cons_out, 8 * sizeof(double), hipMemcpyDeviceToHost, x->stream),
+                 "lbdps3_conservation");
+  if (st != LBDPS_OK) return st;
+  st = sync3(x, "lbdps3_conservation");
+  if (st != LBDPS_OK) return st;
+  if (h_out[7] != 0.0) return fail(LBDPS_E_NONFINITE, "non-finite value in populations or velocities");
   return LBDPS_OK;
 }
 

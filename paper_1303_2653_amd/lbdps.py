@@ -74,6 +74,7 @@ _SIGS = {
     "lbdps_step": (c_i32, [c_vp, c_i32]),
     "lbdps_collide_particles": (c_i32, [c_vp]),
     "lbdps_set_inlet": (c_i32, [c_vp, c_vp]),
+    "lbdps3_conservation": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
     "lbdps3_bgk_step": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_dbl, c_i32, c_vp]),
     "lbdps3_psm_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_dbl, c_dbl, c_i32, c_vp]),
     "lbdps_voidage": (c_i32, [c_vp, c_i32, c_i32, c_dbl, c_vp, c_vp, c_vp]),
@@ -591,6 +592,13 @@ class Sim3:
         out = (c_i64 * 2)()
         check(lbdps3_counters(self.ctx, out), "lbdps3_counters")
         return dict(pairs=out[0], collisions=out[1])
+
+    def conservation(self):
+        """lbdps3_conservation: mass, gas momentum (3), particle momentum (3),
+        non-finite flag."""
+        out = (c_dbl * 8)()
+        check(lbdps3_conservation(self.ctx, out), "lbdps3_conservation")
+        return np.array(out[:])
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -202,3 +202,41 @@ def test_riser3d_full_size_one_step():
     bad = {a: v for a, v in errs.items() if a != "pos" and not v <= 5e-7}
     assert not bad, bad
     assert abs(c["pairs"] - len(o.pairs)) <= 1e-4 * len(o.pairs) and len(o.pairs) > 100_000
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
+def test_conservation_sums_3d(prec):
+    """lbdps3_conservation against the same sums written out with numpy over
+    the library's own canonical state after five steps of the moving box
+    (mass = sum f, gas momentum = sum c_i f_i, particle momentum = m sum v),
+    within the rounding of another summation order; in FP64 also against the
+    oracle's state.  The periodic box has no inflow, so the mass stays C to
+    rounding.  A NaN velocity makes the call return LBDPS_E_NONFINITE."""
+    cfg = synth.tiny3d(**CASES["moving"])
+    c, _ = oracle.lattice3()
+    mass = cfg["rho_s"] * np.pi * cfg["d"] ** 3 / 6
+    gpu = L.Sim3(cfg, precision=prec)
+    gpu.step(5)
+    s = gpu.conservation()
+    f, pos, vel = gpu.state()
+    fq = np.asarray(f, np.float64).reshape(19, -1)
+    want = np.concatenate([[fq.sum()], c.T.astype(np.float64) @ fq.sum(axis=1), mass * vel.sum(axis=0), [0.0]])
+    say(prec, "sums", s)
+    C = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    assert abs(s[0] - want[0]) <= 1e-12 * C and abs(s[0] - C) <= 1e-6 * C
+    scale = np.abs(want[1:7]).max()
+    assert np.abs(s[1:7] - want[1:7]).max() <= 1e-12 * max(scale, 1.0) and s[7] == 0.0
+    if prec == "fp64":
+        ref = oracle.Sim3(cfg)
+        for _ in range(5):
+            ref.step()
+        rq = ref.f.reshape(19, -1)
+        ow = np.concatenate([[rq.sum()], c.T.astype(np.float64) @ rq.sum(axis=1), mass * ref.vel.sum(axis=0)])
+        assert np.abs(s[:7] - ow).max() <= 1e-12 * max(np.abs(ow).max(), 1.0)
+    bad = np.array(vel)
+    bad[3, 1] = np.nan
+    gpu.set_state(None, pos, bad)
+    with pytest.raises(L.LbdpsError) as e:
+        gpu.conservation()
+    assert e.value.status == L.LBDPS_E_NONFINITE
+    gpu.close()
