@@ -162,8 +162,9 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None, tuning=None):
     sim.time_kernels([])
     counters = sim.counters()
     sums, dstep = sim.diag_last()  # the periodic FP64 check (raises if it found a non-finite value)
+    hist = sim.count_histogram(8)
     out = dict(ms=ms, breakdown_us=breakdown, dominant=dominant, dom_ms=kt[0], dom_launches=kt[1],
-               pairs=counters["pairs"], tuning=sim.tuning(), diag=(sums, dstep))
+               pairs=counters["pairs"], tuning=sim.tuning(), diag=(sums, dstep), hist=hist)
     sim.close()
     return out
 
@@ -697,6 +698,7 @@ def main():
                          "gas_momentum": [float(v) for v in r["diag"][0][1:3]],
                          "particle_momentum": [float(v) for v in r["diag"][0][3:5]],
                          "nonfinite": int(r["diag"][0][5])},
+        "cells_by_particle_count": [int(v) for v in r["hist"]],  # 0, 1, ... 6, 7 or more
         "autotune": [r["tuning"][f] for f in ("cluster_lists", "cluster_groups_max", "drag_tile", "sphere_tile")],
         "kernel_us": {k: round(v, 2) for k, v in r["breakdown_us"].items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

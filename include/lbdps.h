@@ -286,6 +286,16 @@ lbdps_status lbdps_voidage(lbdps_ctx *ctx, int32_t y0, int32_t y1, double thresh
                            double *d_col_sum, int64_t *d_count);
 
 /*
+ * Histogram of particles per cell at the current positions (metrics of the
+ * deposition: the count at which the solid fraction of Eq. 10 reaches its
+ * clamp, and the one from which eps_g <= 0.74 selects the dense branch of
+ * Eq. 19, follow from d_p).  h_hist[b], b < nbins - 1: cells holding exactly
+ * b particles; h_hist[nbins - 1]: cells holding nbins - 1 or more.
+ * nbins in [2, 256], else LBDPS_E_INVALID.  Synchronises.
+ */
+lbdps_status lbdps_count_histogram(lbdps_ctx *ctx, int64_t *h_hist, int32_t nbins);
+
+/*
  * The 3-D gas lattice, first piece of the 3-D extension (the paper names 3-D
  * as future work): one BGK collide-stream step (the 3-D form of Eqs. 2-3, no
  * particles) of the D3Q19 lattice on a periodic nx x ny x nz box.  D3Q19: the

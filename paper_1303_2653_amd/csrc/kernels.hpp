@@ -2466,6 +2466,23 @@ __global__ __launch_bounds__(BLOCK) void k_scan_apply(int32_t *__restrict__ in, 
   }
 }
 
+// ------------------------------------------------------------------ particles per cell histogram
+// hist[b] (b < nbins - 1): cells holding exactly b particles; hist[nbins - 1]:
+// cells holding nbins - 1 or more, from the cell starts.  Counted per
+// workgroup in LDS, then added to hist (cleared by the caller).
+constexpr int HIST_BINS_MAX = 256;
+__global__ __launch_bounds__(BLOCK) void k_count_hist(const int32_t *__restrict__ cs, int C, int nbins,
+                                                      unsigned long long *hist) {
+  __shared__ unsigned int h[HIST_BINS_MAX];
+  for (int b = threadIdx.x; b < nbins; b += BLOCK) h[b] = 0;
+  __syncthreads();
+  for (int c = blockIdx.x * BLOCK + threadIdx.x; c < C; c += gridDim.x * BLOCK)
+    atomicAdd(&h[min(cs[c + 1] - cs[c], nbins - 1)], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += BLOCK)
+    if (h[b]) atomicAdd(&hist[b], (unsigned long long)h[b]);
+}
+
 // ------------------------------------------------------------------ FP64 conservation sums (fixed-order reductions)
 __device__ __forceinline__ double block_sum_d(double v, double *sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

@@ -214,6 +214,7 @@ struct lbdps_ctx {
   long long nmax = 0, n = 0;
   hipStream_t stream = nullptr;
   unsigned long long *cross = nullptr;  // device: running net count of outlet crossings
+  unsigned long long *hist = nullptr;   // device: particles-per-cell histogram
   unsigned long long cross_seen = 0;    // its value at the previous lbdps_outlet_crossings
   long long cross_step0 = 0;            // the step counter then
   int device = 0;           // the HIP device current at creation
@@ -334,6 +335,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
   double *egt = cv.take<double>((size_t)lut_rows(p.d_p));
   long long *obs = cv.take<long long>((size_t)nblocks(p.nx) + 1);
   unsigned long long *cross = cv.take<unsigned long long>(1);
+  unsigned long long *hist = cv.take<unsigned long long>(HIST_BINS_MAX);
   int32_t *dg_n = nullptr;
   char *dvx = nullptr, *dvy = nullptr, *dfx = nullptr, *dfy = nullptr;
   if (p.diagnostics) {
@@ -401,6 +403,7 @@ size_t carve(const lbdps_params &p, long long nmax, char *base, lbdps_ctx *x) {
     x->eg_tab = egt;
     x->obs_part = obs;
     x->cross = cross;
+    x->hist = hist;
     x->dg_n = dg_n;
     x->dg_vsx = dvx;
     x->dg_vsy = dvy;
@@ -673,6 +676,14 @@ template <int P> struct Impl {
       hipLaunchKernelGGL(k_voidage_count, dim3(1), dim3(BLOCK), 0, x->stream, (const long long *)x->obs_part, ncb,
                          (long long *)count);
     return launch_status("lbdps_voidage");
+  }
+
+  static lbdps_status count_histogram(lbdps_ctx *x, int nbins) {
+    if (!x->bins_valid) rebin(x);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, (int32_t *)x->hist, 2ll * nbins, 0);
+    hipLaunchKernelGGL(k_count_hist, dim3(std::min(nblocks(x->C), 1024)), dim3(BLOCK), 0, x->stream,
+                       (const int32_t *)x->cs, (int)x->C, nbins, x->hist);
+    return launch_status("lbdps_count_histogram");
   }
 
   static lbdps_status collide_particles(lbdps_ctx *x) {
@@ -1041,6 +1052,18 @@ lbdps_status lbdps_voidage(lbdps_ctx *x, int32_t y0, int32_t y1, double threshol
   if (!is_fin(threshold)) return fail(LBDPS_E_INVALID, "threshold must be finite");
   return dispatch(x, [&](auto impl) { return decltype(impl)::voidage(x, y0, y1, threshold, d_row_sum, d_col_sum,
                                                                      d_count); });
+}
+
+lbdps_status lbdps_count_histogram(lbdps_ctx *x, int64_t *h_hist, int32_t nbins) {
+  if (!x || !h_hist) return fail(LBDPS_E_INVALID, "ctx or hist is NULL");
+  if (nbins < 2 || nbins > HIST_BINS_MAX)
+    return fail(LBDPS_E_INVALID, "nbins must be in [2, " + std::to_string(HIST_BINS_MAX) + "]");
+  lbdps_status st = dispatch(x, [&](auto impl) { return decltype(impl)::count_histogram(x, nbins); });
+  if (st != LBDPS_OK) return st;
+  st = check_hip(hipMemcpyAsync(h_hist, x->hist, (size_t)nbins * 8, hipMemcpyDeviceToHost, x->stream),
+                 "lbdps_count_histogram");
+  if (st != LBDPS_OK) return st;
+  return sync_and_check(x, "lbdps_count_histogram");
 }
 
 lbdps_status lbdps_get_fields(lbdps_ctx *x, double *d_rho, double *d_ugas, double *d_fpg, double *d_beta,

@@ -84,6 +84,7 @@ _SIGS = {
     "lbdps_get_accel": (c_i32, [c_vp, c_vp]),
     "lbdps_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64)]),
     "lbdps_conservation": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
+    "lbdps_count_histogram": (c_i32, [c_vp, ctypes.POINTER(c_i64), c_i32]),
     "lbdps_conservation_noalloc": (c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
     "lbdps_diag_last": (c_i32, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64)]),
     "lbdps_counters": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
@@ -334,6 +335,13 @@ class Sim:
         static device array."""
         out = (c_dbl * 6)()
         check(lbdps_conservation_noalloc(self.ctx, out), "lbdps_conservation_noalloc")
+        return np.array(out[:])
+
+    def count_histogram(self, nbins: int = 16):
+        """lbdps_count_histogram: cells holding 0, 1, ... nbins - 2 particles,
+        and nbins - 1 or more."""
+        out = (c_i64 * nbins)()
+        check(lbdps_count_histogram(self.ctx, out, int(nbins)), "lbdps_count_histogram")
         return np.array(out[:])
 
     def diag_last(self):

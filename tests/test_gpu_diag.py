@@ -68,3 +68,27 @@ def test_periodic_check_reports_a_non_finite_population():
             sums, step = sim.diag_last()  # reported once; the flag is cleared
             assert step == 2 and sums[5] != 0.0
         sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_count_histogram_matches_positions(prec):
+    """lbdps_count_histogram against the histogram of the cells of the
+    positions the library returns (floor of each coordinate), after three
+    steps of a crowded bed, with the last bin collecting the crowded cells;
+    nbins outside [2, 256] is rejected."""
+    cfg = synth.tiny(nx=40, ny=30, n=2400, seed=13, bc=("wall", "wall", "periodic", "periodic"), vel_scale=1e-2)
+    sim = L.Sim(cfg, precision=prec)
+    sim.step(3)
+    pos = sim.particles()["pos"]
+    key = np.floor(pos[:, 1]).astype(np.int64) * cfg["nx"] + np.floor(pos[:, 0]).astype(np.int64)
+    n = np.bincount(key, minlength=cfg["nx"] * cfg["ny"])
+    for nbins in (2, 5, 16):
+        want = np.bincount(np.minimum(n, nbins - 1), minlength=nbins)
+        got = sim.count_histogram(nbins)
+        print(prec, nbins, got, flush=True)
+        assert np.array_equal(got, want) and got.sum() == cfg["nx"] * cfg["ny"]
+    for bad in (1, 257):
+        with pytest.raises(L.LbdpsError) as e:
+            sim.count_histogram(bad)
+        assert e.value.status == L.LBDPS_E_INVALID
+    sim.close()
