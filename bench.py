@@ -428,6 +428,7 @@ def run_riser3d(args, torch, L):
     sim.step(args.warmup)
     ms = time_region(torch, st, lambda: sim.step(args.steps))
     pairs = sim.counters()["pairs"]
+    cons = sim.conservation()  # FP64 sums after the timed steps (raises on a non-finite value)
     sim.close()
     del sim
     s = ms / 1e3
@@ -461,6 +462,8 @@ def run_riser3d(args, torch, L):
                                     sample=f"a 64 x 64 x 64 box at the same density ({len(sub['pos'])} spheres), "
                                            f"{k} coupled steps from rest, FP64, per-cell loops on OpenMP threads "
                                            f"({dt:.1f} s)")
+    line["conservation"] = {"mass": float(cons[0]), "gas_momentum": [float(v) for v in cons[1:4]],
+                            "particle_momentum": [float(v) for v in cons[4:7]], "nonfinite": int(cons[7])}
     return line
 
 
