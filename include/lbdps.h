@@ -232,7 +232,8 @@ lbdps_status lbdps_conservation_noalloc(lbdps_ctx *ctx, double h_out[6]);
 /*
  * The sums of the latest periodic check (lbdps_params.diag_every > 0), in
  * lbdps_conservation's layout, and the step after which it ran (*h_step; -1
- * and zeros if none ran yet).  Synchronises the stream.
+ * and zeros if none ran since the context was created or its state was last
+ * set).  Synchronises the stream.
  */
 lbdps_status lbdps_diag_last(lbdps_ctx *ctx, double h_out[6], int64_t *h_step);
 

@@ -715,6 +715,7 @@ template <int P> struct Impl {
                          parts(x, x->cp), x->slot, k, x->flags);
     x->bins_valid = false;
     x->step = 0;
+    x->diag_step = -1;  // no periodic check has run on this state
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLOCK), 0, x->stream, (int32_t *)x->cross, 2ll, 0);
     x->cross_seen = 0;
     x->cross_step0 = 0;

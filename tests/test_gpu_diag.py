@@ -43,6 +43,10 @@ def test_periodic_check_equals_conservation(prec):
     for a, b in zip(sim.state()[:3], plain.state()[:3]):
         assert np.array_equal(a, b)
     assert sim.counters() == plain.counters()
+    # a new state: no check has run on it yet
+    f, pos, vel, _ = sim.state()
+    sim.set_state(f, pos, vel)
+    assert sim.diag_last()[1] == -1
     sim.close()
     plain.close()
 
