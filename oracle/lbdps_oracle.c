@@ -35,6 +35,9 @@
 #include <omp.h>
 #endif
 
+/* R49: the cancellation bound of the regularised Eq. 28 (drag_ratio_mode 2) */
+#define ORC_CANCEL_MAX 100.0
+
 #define ORC_PERIODIC 0
 #define ORC_WALL 1
 #define ORC_INLET 2  /* equilibrium incoming populations (R21) */
@@ -70,7 +73,8 @@ typedef struct {
   double e_pp, e_pw;
   double g[2];   /* gravity acting on particles, before the (1 - rho_g/rho_s) factor */
   double G[2];   /* body force on the gas per cell (R29) */
-  int32_t drag_ratio_mode; /* 0 signed (R15), 1 literal absolute values */
+  int32_t drag_ratio_mode; /* 0 signed (R15), 1 literal absolute values, 2 signed with
+                              the equal split where the pre-drags cancel (R49) */
   int32_t u_gas_porosity;  /* 0 divide by eps_2d, 1 by eps_g (3-D), 2 none (R6) */
   int32_t omega_mode;      /* 0 EMMS Eq. 20, 1 omega == 1 everywhere (Eq. 6) */
   int32_t pressure_sign;   /* -1 physical (R17), 0 off, +1 as printed in Eq. 16 */
@@ -947,6 +951,7 @@ int orc_step(const orc_params *p, const double *inlet_uy, double *f, int64_t np,
   double *gpk = (double *)malloc(NP * 2 * sizeof(double));
   double *fd = (double *)malloc(NP * 2 * sizeof(double));
   double *fcell = (double *)calloc((size_t)(2 * C), sizeof(double));
+  double *acell = (double *)calloc((size_t)(2 * C), sizeof(double)); /* sum of |F_pre| */
   for (int64_t k = 0; k < np; ++k) {
     double px = pos[2 * k], py = pos[2 * k + 1];
     double uk_x = orc_interp(p, ugx, px, py);
@@ -965,12 +970,19 @@ int orc_step(const orc_params *p, const double *inlet_uy, double *f, int64_t np,
     /* Eq. 27, summed in ascending particle index */
     fcell[2 * cell[k]] += fpre[2 * k];
     fcell[2 * cell[k] + 1] += fpre[2 * k + 1];
+    acell[2 * cell[k]] += fabs(fpre[2 * k]);
+    acell[2 * cell[k] + 1] += fabs(fpre[2 * k + 1]);
   }
+  /* R49 (mode 2): where the cell's pre-drags cancel, sum |F_pre| beyond
+   * ORC_CANCEL_MAX times |sum F_pre|, the denominator is taken as zero. */
+  if (p->drag_ratio_mode == 2)
+    for (int64_t c = 0; c < 2 * C; ++c)
+      if (acell[c] > ORC_CANCEL_MAX * fabs(fcell[c])) fcell[c] = 0.0;
   int64_t nzero = 0;
   for (int64_t c = 0; c < C; ++c)
     for (int a = 0; a < 2; ++a)
       if (ncell[c] > 0 && fcell[2 * c + a] == 0.0) ++nzero;
-  /* Eq. 28: signed ratio (R15) or literal absolute values; an exactly zero
+  /* Eq. 28: signed ratio (R15) or literal absolute values; a zero
    * denominator splits F_p->g equally (R16). */
   for (int64_t k = 0; k < np; ++k) {
     int32_t c = cell[k];
@@ -1043,6 +1055,7 @@ int orc_step(const orc_params *p, const double *inlet_uy, double *f, int64_t np,
   free(fpre);
   free(gpk);
   free(fd);
+  free(acell);
   free(fcell);
   return rc;
 }

@@ -517,3 +517,63 @@ def test_f32_stage_follows_the_fp64_sweep(orc):
     v64, nw64 = orc.walls(p, pos32, v64)
     assert nc == nc64 and nw == nw64 and nc > 1000 and nw > 10
     assert np.abs(out - v64).max() <= 1e-5 * np.abs(v64).max()
+
+
+def _cancelling_bed(mode):
+    """A crowded periodic bed with fast random velocities (the regime where a
+    cell's pre-drags can nearly cancel), after one step to develop a flow."""
+    return synth.tiny(nx=8, ny=8, n=400, seed=31, bc=("periodic",) * 4, vel_scale=2e-2, g=(0.0, 0.0),
+                      drag_ratio_mode=mode)
+
+
+def test_regularised_drag_splits_cancelling_cells(orc):
+    """R49 (drag_ratio_mode 2): in a cell whose pre-drags cancel, sum |F_pre|
+    above 100 |sum F_pre| (sums in index order), every particle takes
+    -F_p->g / n, the split of an exactly zero sum (R16); in every other cell
+    the signed ratio of Eq. 28, -F_p->g F_pre,k / sum F_pre.  Both classes
+    occur on this bed, and the drags still sum to -F_p->g per cell."""
+    cfg = _cancelling_bed(2)
+    sim = orc.Sim(cfg)
+    sim.step()
+    pos0 = sim.pos.copy()
+    o = sim.step(record=True)
+    nx = cfg["nx"]
+    cell = (np.floor(pos0[:, 1]) * nx + np.floor(pos0[:, 0])).astype(int)
+    C = nx * cfg["ny"]
+    S = np.zeros((C, 2))
+    A = np.zeros((C, 2))
+    np.add.at(S, cell, o.fpre)
+    np.add.at(A, cell, np.abs(o.fpre))
+    n = np.bincount(cell, minlength=C)
+    fpg = o.fpg.reshape(-1, 2)
+    split = A > 100.0 * np.abs(S)
+    nsplit = 0
+    for k in range(len(pos0)):
+        c = cell[k]
+        for a in range(2):
+            if split[c, a]:
+                want = -fpg[c, a] / n[c]
+                nsplit += 1
+            else:
+                want = -fpg[c, a] * o.fpre[k, a] / S[c, a]
+            assert o.fd[k, a] == want, (k, a, split[c, a])
+    assert nsplit > 0 and nsplit < 2 * len(pos0)
+    tot = np.zeros((C, 2))
+    np.add.at(tot, cell, o.fd)
+    occ = n > 0
+    assert np.abs(tot[occ] + fpg[occ]).max() < 1e-12 * np.abs(fpg).max()
+
+
+def test_regularised_drag_equals_signed_without_cancellation(orc):
+    """R49: on a dilute bed where no cell's pre-drags cancel, drag_ratio_mode 2
+    steps exactly as the signed Eq. 28 (mode 0)."""
+    runs = []
+    for mode in (0, 2):
+        cfg = synth.tiny(nx=16, ny=24, n=60, seed=7, vel_scale=1e-3, drag_ratio_mode=mode)
+        sim = orc.Sim(cfg)
+        for _ in range(10):
+            o = sim.step(record=True)
+        runs.append((sim.f.copy(), sim.pos.copy(), sim.vel.copy(), o))
+    assert (runs[1][3].ncell > 1).any()  # cells where the ratio of Eq. 28 applies
+    for a, b in zip(runs[0][:3], runs[1][:3]):
+        assert np.array_equal(a, b)
