@@ -92,7 +92,10 @@ typedef struct {
                                 Sec. 3 is applied by the library                       */
   double body_force[2];      /* force per cell on the gas (drives periodic beds)      */
   int32_t drag_ratio_mode;   /* Eq. 28: 0 signed ratio F_pg/F_pre (default), 1 ratio of
-                                absolute values as printed                              */
+                                absolute values as printed, 2 signed ratio with F_pg
+                                split equally among the cell's particles where their
+                                pre-drags cancel (sum |F_pre| > 100 |sum F_pre|; not in
+                                the paper: keeps dense beds stable over long runs)     */
   int32_t u_gas_porosity;    /* superficial -> actual gas velocity (after Eq. 24):
                                 0 divide by eps_2d (default), 1 by the 3-D voidage, 2 none */
   int32_t omega_mode;        /* 0 EMMS correction of Eq. 20 (default), 1 omega = 1 (Eq. 6) */

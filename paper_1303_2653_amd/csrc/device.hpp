@@ -160,6 +160,7 @@ template <class T> struct Consts {
   int per_x, per_y, bc_ylo, bc_yhi;  // per_y: the particles' periodicity along y
   int gas_per_y;                     // the lattice's periodicity along y
   int drag_abs;
+  int drag_reg;  // Eq. 28 with the equal split where a cell's pre-drags cancel
   int npart;
   T tau, d, mu, vp, m, msum, one_e, e_pw, r;
   int les;  // Smagorinsky sub-grid model on (Eqs. 12-15)

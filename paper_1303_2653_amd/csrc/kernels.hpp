@@ -724,6 +724,16 @@ template <int TX> struct TileDims {
 };
 constexpr int HIST_MAX = 32;
 
+// Eq. 28's denominator as used: the cell's sum S of pre-drags (Eq. 27), or
+// zero, so that F_p->g is split equally as for an exactly zero sum, where the
+// regularised mode finds the pre-drags cancelling: sum |F_pre| above
+// DRAG_CANCEL_MAX |S|, where the ratio of Eq. 28 would turn a small gas force
+// into large opposite kicks.
+constexpr float DRAG_CANCEL_MAX = 100.0f;
+template <class T> __device__ __forceinline__ T drag_den(const Consts<T> &k, T S, T A) {
+  return (k.drag_reg && A > (T)DRAG_CANCEL_MAX * fabs(S)) ? (T)0 : S;
+}
+
 template <int P, int TX> struct DragTile {
   using T = typename Prec<P>::T;
   static constexpr int DTX = TX, DTY = TileDims<TX>::TY, DSX = TileDims<TX>::SX, DSN = TileDims<TX>::SN;
@@ -910,7 +920,7 @@ __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, 
         T *x = px, *y = py, *vx = pvx, *vy = pvy;
         T prx[SEG_REG], pry[SEG_REG], gpx[SEG_REG], gpy[SEG_REG];
         int nk[SEG_REG];
-        T Sx = (T)0, Sy = (T)0;
+        T Sx = (T)0, Sy = (T)0, Ax = (T)0, Ay = (T)0;
 #pragma unroll
         for (int u = 0; u < SEG_REG; ++u)
           if (u < n) {
@@ -922,7 +932,11 @@ __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, 
             gpy[u] = I.gpy;
             Sx += prx[u];
             Sy += pry[u];
+            Ax += fabs(prx[u]);
+            Ay += fabs(pry[u]);
           }
+        Sx = drag_den(k, Sx, Ax);
+        Sy = drag_den(k, Sy, Ay);
         nzero = (Sx == (T)0) + (Sy == (T)0);
 #pragma unroll
         for (int u = 0; u < SEG_REG; ++u)
@@ -931,13 +945,19 @@ __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, 
         for (int u = 0; u < SEG_REG; ++u)
           if (u < n) count_new(a0 + u, nk[u]);
       } else {
-        T Sx = (T)0, Sy = (T)0;
+        T Sx = (T)0, Sy = (T)0, Ax = (T)0, Ay = (T)0;
         for (int s = a0; s < a1; ++s) {
           Interp<P> I;
           I.at(k, D, tx0, ty0, cx, cy, pt.px[s], pt.py[s]);
-          Sx += dv<P>(k.vp * I.beta, I.es) * (I.ux - pt.vx[s]);
-          Sy += dv<P>(k.vp * I.beta, I.es) * (I.uy - pt.vy[s]);
+          const T qx = dv<P>(k.vp * I.beta, I.es) * (I.ux - pt.vx[s]);
+          const T qy = dv<P>(k.vp * I.beta, I.es) * (I.uy - pt.vy[s]);
+          Sx += qx;
+          Sy += qy;
+          Ax += fabs(qx);
+          Ay += fabs(qy);
         }
+        Sx = drag_den(k, Sx, Ax);
+        Sy = drag_den(k, Sy, Ay);
         nzero = (Sx == (T)0) + (Sy == (T)0);
         for (int s = a0; s < a1; ++s) {
           Interp<P> I;
@@ -1088,11 +1108,15 @@ __device__ __forceinline__ void drag_body_flat(const int bidx, const int gdim, P
     __syncthreads();
     // Eq. 27: the cell's sums in segment order, left at its first flat index
     if (n > 0) {
-      T Sx = (T)0, Sy = (T)0;
+      T Sx = (T)0, Sy = (T)0, Ax = (T)0, Ay = (T)0;
       for (int u = 0; u < n; ++u) {
         Sx += f_px[off + u];
         Sy += f_py[off + u];
+        Ax += fabs(f_px[off + u]);
+        Ay += fabs(f_py[off + u]);
       }
+      Sx = drag_den(k, Sx, Ax);
+      Sy = drag_den(k, Sy, Ay);
       nzero = (Sx == (T)0) + (Sy == (T)0);
       f_px[off] = Sx;
       f_py[off] = Sy;
@@ -1134,13 +1158,19 @@ __device__ __forceinline__ void drag_body_flat(const int bidx, const int gdim, P
     if (inside) {
       if (n > 0) {
         const T fgx = fl.fpgx[c], fgy = fl.fpgy[c];
-        T Sx = (T)0, Sy = (T)0;
+        T Sx = (T)0, Sy = (T)0, Ax = (T)0, Ay = (T)0;
         for (int s = a0; s < a1; ++s) {
           Interp<P> I;
           I.at(k, D, tx0, ty0, cx, cy, pt.px[s], pt.py[s]);
-          Sx += dv<P>(k.vp * I.beta, I.es) * (I.ux - pt.vx[s]);
-          Sy += dv<P>(k.vp * I.beta, I.es) * (I.uy - pt.vy[s]);
+          const T qx = dv<P>(k.vp * I.beta, I.es) * (I.ux - pt.vx[s]);
+          const T qy = dv<P>(k.vp * I.beta, I.es) * (I.uy - pt.vy[s]);
+          Sx += qx;
+          Sy += qy;
+          Ax += fabs(qx);
+          Ay += fabs(qy);
         }
+        Sx = drag_den(k, Sx, Ax);
+        Sy = drag_den(k, Sy, Ay);
         nzero = (Sx == (T)0) + (Sy == (T)0);
         for (int s = a0; s < a1; ++s) {
           Interp<P> I;

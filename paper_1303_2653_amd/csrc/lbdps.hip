@@ -490,6 +490,7 @@ template <int P> struct Impl {
     k.bc_ylo = x->p.bc[2];
     k.bc_yhi = x->p.bc[3];
     k.drag_abs = x->p.drag_ratio_mode == 1;
+    k.drag_reg = x->p.drag_ratio_mode == 2;
     k.npart = (int)x->n;
     k.tau = (T)d.tau;
     k.d = (T)d.d;
@@ -830,7 +831,8 @@ lbdps_status lbdps_validate_params(const lbdps_params *p, int64_t max_particles)
   if (!(p->e_pw >= 0 && p->e_pw <= 1)) return fail(LBDPS_E_INVALID, "e_pw must be in [0, 1]");
   for (int a = 0; a < 2; ++a)
     if (!is_fin(p->g[a]) || !is_fin(p->body_force[a])) return fail(LBDPS_E_INVALID, "g and body_force must be finite");
-  if (p->drag_ratio_mode < 0 || p->drag_ratio_mode > 1) return fail(LBDPS_E_INVALID, "drag_ratio_mode must be 0 or 1");
+  if (p->drag_ratio_mode < 0 || p->drag_ratio_mode > 2)
+    return fail(LBDPS_E_INVALID, "drag_ratio_mode must be 0, 1 or 2");
   if (p->u_gas_porosity < 0 || p->u_gas_porosity > 2) return fail(LBDPS_E_INVALID, "u_gas_porosity must be 0..2");
   if (p->omega_mode < 0 || p->omega_mode > 1) return fail(LBDPS_E_INVALID, "omega_mode must be 0 or 1");
   if (p->pressure_force_sign < -1 || p->pressure_force_sign > 1)
