@@ -29,8 +29,9 @@ def say(*a):
 
 
 def uneven_beds(prec):
-    """Eight beds of different shapes, faces and loads, one without particles,
-    one with the Smagorinsky model and one whose particles circulate in y."""
+    """Nine beds of different shapes, faces and loads, one without particles,
+    one with the Smagorinsky model, one whose particles circulate in y and one
+    under the regularised Eq. 28."""
     beds = [
         synth.tiny(nx=16, ny=24, n=60, seed=1),
         synth.tiny(nx=37, ny=20, n=300, seed=2, bc=("wall", "wall", "periodic", "periodic"), G=(0.0, 2e-5),
@@ -44,6 +45,9 @@ def uneven_beds(prec):
                    g=(0.0, -2e-5), vel_scale=2e-3, cs_smag=1.5),
         synth.tiny(nx=21, ny=26, n=220, seed=8, bc=("wall", "wall", "inlet", "outlet"), band=26.0,
                    particles_periodic_y=1, vel_scale=2e-2),
+        # crowded, fast: cells whose pre-drags cancel, under the regularised Eq. 28
+        synth.tiny(nx=8, ny=8, n=400, seed=31, bc=("periodic",) * 4, vel_scale=2e-2, g=(0.0, 0.0),
+                   drag_ratio_mode=2),
     ]
     for b in beds:
         b["precision"] = prec
