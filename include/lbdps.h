@@ -28,10 +28,13 @@
  *  - D2Q9 numbering: 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1)
  *    6:(-1,1) 7:(-1,-1) 8:(1,-1); weights 4/9, 1/9 (1-4), 1/36 (5-8).
  *  - Work is enqueued on the stream given to lbdps_create (a hipStream_t passed
- *    as void*).  lbdps_step returns without waiting.  The lbdps_get_*,
- *    lbdps_conservation and lbdps_counters calls enqueue their copies on the
- *    same stream and wait for it; device-side errors latched since the last
- *    such call are returned by them.
+ *    as void*).  lbdps_step returns without waiting.  The calls documented
+ *    as synchronising (lbdps_get_*, lbdps_conservation, lbdps_counters,
+ *    lbdps_diag_last, lbdps_count_histogram, lbdps_outlet_crossings, ...)
+ *    enqueue their copies on the same stream and wait for it; device-side
+ *    errors latched since the last such call (a particle outside the domain,
+ *    a contact row over its capacity, a stalled sweep, a non-finite value
+ *    found by the periodic check) are returned by them.
  *  - A context is not thread-safe; separate contexts are independent.
  */
 #ifndef LBDPS_H
