@@ -920,7 +920,7 @@ __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, 
         T *x = px, *y = py, *vx = pvx, *vy = pvy;
         T prx[SEG_REG], pry[SEG_REG], gpx[SEG_REG], gpy[SEG_REG];
         int nk[SEG_REG];
-        T Sx = (T)0, Sy = (T)0, Ax = (T)0, Ay = (T)0;
+        T Sx = (T)0, Sy = (T)0;
 #pragma unroll
         for (int u = 0; u < SEG_REG; ++u)
           if (u < n) {
@@ -932,11 +932,18 @@ __device__ __forceinline__ void drag_body_cells(const int bidx, const int gdim, 
             gpy[u] = I.gpy;
             Sx += prx[u];
             Sy += pry[u];
-            Ax += fabs(prx[u]);
-            Ay += fabs(pry[u]);
           }
-        Sx = drag_den(k, Sx, Ax);
-        Sy = drag_den(k, Sy, Ay);
+        if (k.drag_reg) {  // the sums of |F_pre|, in the same order, after the interpolations
+          T Ax = (T)0, Ay = (T)0;
+#pragma unroll
+          for (int u = 0; u < SEG_REG; ++u)
+            if (u < n) {
+              Ax += fabs(prx[u]);
+              Ay += fabs(pry[u]);
+            }
+          Sx = drag_den(k, Sx, Ax);
+          Sy = drag_den(k, Sy, Ay);
+        }
         nzero = (Sx == (T)0) + (Sy == (T)0);
 #pragma unroll
         for (int u = 0; u < SEG_REG; ++u)
