@@ -52,7 +52,7 @@ typedef enum {
   LBDPS_E_INVALID = -1,     /* a parameter or input value is out of range      */
   LBDPS_E_SHAPE = -2,       /* a size does not match the context or workspace   */
   LBDPS_E_DEVICE = -3,      /* a HIP runtime call failed                        */
-  LBDPS_E_UNSUPPORTED = -4, /* valid for the method, not supported by this build */
+  LBDPS_E_UNSUPPORTED = -4, /* valid for the method, not supported by this library */
   LBDPS_E_NONFINITE = -5,   /* a NaN or infinity appeared in the state           */
   LBDPS_E_CAPACITY = -6,    /* a particle has more contacts than LBDPS_MAX_CONTACTS */
   LBDPS_E_STALL = -7        /* collision resolution exceeded its bounded wait    */
