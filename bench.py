@@ -169,21 +169,26 @@ def run_gpu(cfg, prec, steps, warmup, torch, L, dominant=None, tuning=None):
     return out
 
 
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_2653_amd", "csrc", f)
-                  for f in ("kernels.hpp", "device.hpp", "lattice3d.hpp", "spheres_tile.hpp")]
+CSRC = os.path.join(ROOT, "paper_1303_2653_amd", "csrc")
+KERNEL_SOURCES = ("kernels.hpp", "device.hpp", "lattice3d.hpp", "spheres_tile.hpp")
+# the 3-D coupled step's kernels also live in coupled3d.hpp
+KERNEL_SOURCES_3D = KERNEL_SOURCES + ("coupled3d.hpp",)
 # the kernels of each phase (either form of a kernel, and every launch of the
 # phase: the collision stage's tile kernel with the contact kernel on what it
 # left, the cluster kernel with the ordered sweep)
 KERNEL_KEYS = {"collide": ("k_collide",), "drag": ("k_drag", "k_drag_flat"), "scan": ("k_scan_cells",),
                "scatter": ("k_scatter",), "contacts": ("k_spheres_tile", "k_contacts", "k_contacts_small"),
-               "resolve": ("k_resolve_clusters", "k_resolve"), "k3_bgk": ("k3_bgk",), "k3_psm": ("k3_psm", "k3_psm_pairs")}
+               "resolve": ("k_resolve_clusters", "k_resolve"), "k3_bgk": ("k3_bgk", "k3_bgk_pairs"), "k3_psm": ("k3_psm", "k3_psm_pairs")}
+# the whole 3-D coupled step: every kernel it launches once per step
+STEP3D_KEYS = {"step3d": ("k3c_collide", "k3c_gradp", "k3c_drag", "k_scan_reduce", "k_scan_top", "k_scan_apply",
+                          "k3c_scatter", "k3c_contacts", "k3c_clusters", "k3c_resolve")}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
+    for f in sources:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -196,7 +201,7 @@ def measured_traffic(workload: str, kernel: str):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if t.get("kernel_source_hash") != kernel_source_hash(tuple(t.get("kernel_sources", KERNEL_SOURCES))):
         return None
     v = t.get("bytes_per_launch", {}).get(kernel)
     return None if v is None else int(v)
@@ -242,7 +247,8 @@ def summarize(args):
         lines += ["", f"HBM-side bytes per launch: FETCH_SIZE x {f_scale:.3f} + WRITE_SIZE x {w_scale:.3f}; the factors "
                   f"make a plain {args.copy_bytes} byte copy ({copy_name}) read and write exactly its size.", "",
                   "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes per launch |", "|---|---:|---:|---:|"]
-        for key, knames in KERNEL_KEYS.items():
+        keys = STEP3D_KEYS if args.workload == "riser3d" else KERNEL_KEYS
+        for key, knames in keys.items():
             names = [n for n in knames if n in fetch and n in write]
             if names:
                 b = 0.0
@@ -259,7 +265,9 @@ def summarize(args):
         fh.write("\n".join(lines) + "\n")
     if traffic:
         with open(os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json"), "w") as fh:
-            json.dump({"workload": args.workload, "kernel_source_hash": kernel_source_hash(),
+            srcs = KERNEL_SOURCES_3D if args.workload == "riser3d" else KERNEL_SOURCES
+            json.dump({"workload": args.workload, "kernel_sources": list(srcs),
+                       "kernel_source_hash": kernel_source_hash(srcs),
                        "bytes_per_launch": traffic, "fetch_scale": f_scale, "write_scale": w_scale}, fh, indent=1)
     print("\n".join(lines))
 
@@ -446,7 +454,8 @@ def run_riser3d(args, torch, L):
             "model_bytes_per_step": int(model), "model_bw_frac": round(bw / HBM_PEAK_GBS, 4),
             "contact_pairs": int(pairs),
             "roofline": {"bound": "hbm", "kernel": "step", "achieved": round(bw, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(bw / HBM_PEAK_GBS, 4), "traffic": None,
+                         "unit": "GB/s", "frac": round(bw / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic("riser3d", "step3d") if prec == "fp16" else None,
                          "bytes_per_launch": int(model), "us_per_launch": round(ms / args.steps * 1e3, 3)}}
     if not args.no_cpu_baseline:
         import oracle

@@ -99,10 +99,26 @@ def test_traffic_is_dropped_when_the_kernels_changed(tmp_path, monkeypatch):
     with open(tmp_path / "profiles" / "traffic_wl.json", "w") as fh:
         json.dump({"kernel_source_hash": "abc", "bytes_per_launch": {"contacts": 123}}, fh)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abc")
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda *a: "abc")
     assert bench.measured_traffic("wl", "contacts") == 123
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "def")
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda *a: "def")
     assert bench.measured_traffic("wl", "contacts") is None
+
+
+def test_traffic_is_checked_against_the_sources_it_lists(tmp_path, monkeypatch):
+    """A counter summary that names its kernel sources (the 3-D step's adds
+    coupled3d.hpp) is valid only while the hash over exactly those files
+    matches; one that names none is checked against the default list."""
+    os.makedirs(tmp_path / "profiles")
+    with open(tmp_path / "profiles" / "traffic_wl.json", "w") as fh:
+        json.dump({"kernel_sources": ["a.hpp", "b.hpp"], "kernel_source_hash": "ab",
+                   "bytes_per_launch": {"step3d": 7}}, fh)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda s=bench.KERNEL_SOURCES: "ab" if tuple(s) == ("a.hpp", "b.hpp") else "x")
+    assert bench.measured_traffic("wl", "step3d") == 7
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda s=bench.KERNEL_SOURCES: "x")
+    assert bench.measured_traffic("wl", "step3d") is None
+    assert set(bench.KERNEL_SOURCES) < set(bench.KERNEL_SOURCES_3D) and "coupled3d.hpp" in bench.KERNEL_SOURCES_3D
 
 
 def test_more_than_one_gpu_is_refused():
